@@ -1,0 +1,252 @@
+"""MPS time stepper for eq. FP2 -- oracle (test infrastructure).
+
+The scheme of the "Matrix product state algorithm" section: every vector of
+eq. FP2 (the PDF f, the velocity components <U_i>, the mean compositions
+<Phi_a>) is an MPS, every matrix (the CFD2 derivatives, diagonal
+multiplications) an MPO, and the explicit Runge-Kutta update is carried out
+in MPS arithmetic with the bond dimension of f limited to chi by singular
+value truncation after every operator application and every stage
+combination.
+
+Schedule of one RK4 step (RK2 is the Heun analogue):
+
+    L(g)  = Round_chi( A(g) g ),   A(g) = A_fixed - Omega sum_a D1g^(phi_a) diag(m~_a(g))
+    k1 = L(f); k2 = L(f + dt/2 k1); k3 = L(f + dt/2 k2); k4 = L(f + dt k3)
+    f+ = Round_chi( f + dt/6 k1 + dt/3 k2 + dt/3 k3 + dt/6 k4 )
+
+where the stage inputs f + c k are exact (block-diagonal) sums, m~_a(g) is
+the raw mean composition of g rounded to chi_mean, and Round is the
+randomized range finder followed by simultaneous SVD truncation
+(``oracle.tt.round_sketch``) with the Gaussian sketch given as input.
+
+The operator MPOs are TT-SVDs of the dense 1-D matrices of ``oracle.dense``,
+tensored over dimensions; nothing here is shared with the product path.
+
+Pins: tests/test_oracle_stepper.py -- with chi >= 2^(N/2) (no truncation)
+the stepper reproduces the full-grid solver of ``oracle.dense`` (itself
+pinned to the paper's invariants and to closed forms) to 1e-12.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import workloads
+from . import dense
+from . import tt
+
+
+class MPSStepper:
+    def __init__(self, w):
+        self.w = w
+        self.order = workloads.site_order(w)
+        self.N = len(self.order)
+        self.nd = w.ndims
+        self.M = w.M
+        self.h = 1.0 / w.M
+        self.n_phi = 2 * w.bits
+        if w.ndims == 5 and w.ordering != "serial":
+            raise ValueError("5-D problems use the serial ordering")
+        M = self.M
+        phi = dense.phi_nodes(M)
+        self.ops = {
+            "D1g": tt.operator_qtt(dense.d1_ghost(M)),
+            "D2g": tt.operator_qtt(dense.d2_ghost(M)),
+            "D1p": tt.operator_qtt(dense.d1_periodic(M)),
+            "D2p": tt.operator_qtt(dense.d2_periodic(M)),
+            "D1g_phi": tt.operator_qtt(dense.d1_ghost(M) @ np.diag(phi)),
+            "phi": tt.operator_qtt(np.diag(phi)),
+        }
+        self.Z = workloads.sketch_cores(w)
+        self.ell = workloads.sketch_ranks(w)
+        self.Zm = workloads.mean_sketch_cores(w)
+        self.ell_m = workloads.mean_sketch_ranks(w)
+        self.U = self._velocity() if w.ndims == 5 else None
+        self.fixed = self._fixed_terms()
+        self._weights = {}
+
+    # ------------------------------------------------------------------ inputs
+    def _x_order(self):
+        return [(d - 2, b) for (d, b) in self.order if d >= 2]
+
+    def _phi_order(self):
+        return [(d, b) for (d, b) in self.order if d < 2]
+
+    def _separable(self, terms, order, ndims):
+        parts = []
+        for c, vecs in terms:
+            per = [None if v is None else tt.vector_qtt(v) for v in vecs]
+            parts.append((c, tt.mps_product(per, order, ndims)))
+        return tt.mps_sum(parts)
+
+    def _velocity(self):
+        out = []
+        for comp in workloads.velocity_terms(self.w):
+            x = self._separable(comp, self._x_order(), 3)
+            x, _ = tt.round_det(x, self.w.vel_rank, self.w.rel_tol)
+            out.append(x)
+        return out
+
+    def initial_state(self):
+        f = self._separable(workloads.ic_terms(self.w), self.order, self.nd)
+        f, _ = tt.round_det(f, self.w.chi, self.w.rel_tol)
+        return f
+
+    # ---------------------------------------------------------------- operator
+    def _mpo(self, per):
+        return tt.mpo_product(per, self.order, self.nd)
+
+    def _fixed_terms(self):
+        w, o = self.w, self.ops
+        nd = self.nd
+        terms = []
+        for a in (0, 1):
+            per = [None] * nd
+            per[a] = o["D1g_phi"]
+            terms.append((w.omega, self._mpo(per)))
+            per = [None] * nd
+            per[a] = o["D2g"]
+            terms.append((w.nu_phi, self._mpo(per)))
+            if w.k_react != 0.0:
+                per = [None] * nd
+                per[a] = o["D1g_phi"]
+                per[1 - a] = o["phi"]
+                terms.append((w.k_react, self._mpo(per)))
+        if nd == 5:
+            for i in range(3):
+                if w.gamma != 0.0:
+                    per = [None] * nd
+                    per[2 + i] = o["D2p"]
+                    terms.append((w.gamma, self._mpo(per)))
+                per = [None] * nd
+                per[2 + i] = o["D1p"]
+                D1 = self._mpo(per)
+                diagU = tt.identity_mpo(self.n_phi) + tt.mpo_diag(self.U[i])
+                terms.append((-1.0, tt.mpo_compose(diagU, D1)))
+        return terms
+
+    def _phi_weight(self, a):
+        """Weight MPS over the phi sites for h^2 sum phi_a f (a = None: h^2 sum f)."""
+        if a in self._weights:
+            return self._weights[a]
+        M = self.M
+        vec = [np.full(M, self.h), np.full(M, self.h)]
+        if a is not None:
+            vec[a] = self.h * dense.phi_nodes(M)
+        per = [tt.vector_qtt(v) for v in vec]
+        W = tt.mps_product(per, self._phi_order(), 2)
+        self._weights[a] = W
+        return W
+
+    def mean_field_raw(self, g, a):
+        """<Phi_a>(x) of g: x-MPS (5-D) or scalar (2-D), unrounded."""
+        W = self._phi_weight(a)
+        v = np.ones((1, 1))
+        for n in range(self.n_phi):
+            v = np.einsum("wr,wsW,rsR->WR", v, W[n], g[n], optimize=True)
+        if self.nd == 2:
+            return float(v[0, 0])
+        first = np.einsum("r,rsR->sR", v[0], g[self.n_phi])[None]
+        return [first] + [G.copy() for G in g[self.n_phi + 1:]]
+
+    def mean_field(self, g, a):
+        m = self.mean_field_raw(g, a)
+        if self.nd == 2:
+            return m, None
+        m, info = tt.round_sketch([(1.0, None, m)], self.Zm, self.ell_m,
+                                  self.w.chi_mean, self.w.rel_tol)
+        return m, info
+
+    def operator_terms(self, g):
+        w = self.w
+        terms = list(self.fixed)
+        for a in (0, 1):
+            per = [None] * 2
+            per[a] = self.ops["D1g"]
+            phi_part = tt.mpo_product(per, self._phi_order(), 2)
+            m, _ = self.mean_field(g, a)
+            if self.nd == 2:
+                terms.append((-w.omega * m, phi_part))
+            else:
+                terms.append((-w.omega, phi_part + tt.mpo_diag(m)))
+        return terms
+
+    def apply_exact(self, g):
+        """A(g) g as an explicit (unrounded) MPS -- for small tests."""
+        parts = [(c, tt.mpo_apply(W, g)) for c, W in self.operator_terms(g)]
+        return tt.mps_sum(parts)
+
+    def L(self, g):
+        terms = [(c, W, g) for c, W in self.operator_terms(g)]
+        out, info = tt.round_sketch(terms, self.Z, self.ell, self.w.chi, self.w.rel_tol)
+        return out, info
+
+    # -------------------------------------------------------------------- step
+    def step(self, f):
+        w = self.w
+        dt = w.dt
+        infos = []
+
+        def L(g):
+            out, info = self.L(g)
+            infos.append(info)
+            return out
+
+        if w.integrator == "rk4":
+            k1 = L(f)
+            k2 = L(tt.mps_sum([(1.0, f), (0.5 * dt, k1)]))
+            k3 = L(tt.mps_sum([(1.0, f), (0.5 * dt, k2)]))
+            k4 = L(tt.mps_sum([(1.0, f), (dt, k3)]))
+            comb = [(1.0, None, f), (dt / 6, None, k1), (dt / 3, None, k2),
+                    (dt / 3, None, k3), (dt / 6, None, k4)]
+        elif w.integrator == "rk2":
+            k1 = L(f)
+            k2 = L(tt.mps_sum([(1.0, f), (dt, k1)]))
+            comb = [(1.0, None, f), (0.5 * dt, None, k1), (0.5 * dt, None, k2)]
+        else:
+            raise ValueError(w.integrator)
+        fn, info = tt.round_sketch(comb, self.Z, self.ell, w.chi, w.rel_tol)
+        infos.append(info)
+        return fn, infos
+
+    # ------------------------------------------------------------- observables
+    def _weight_full(self, vecs):
+        per = [tt.vector_qtt(v) for v in vecs]
+        return tt.mps_product(per, self.order, self.nd)
+
+    def observables(self, f):
+        """Space-averaged statistics (eq. spaceAvg, eq. RACov, eq. SGSCov)."""
+        M, h, nd = self.M, self.h, self.nd
+        one = np.full(M, h)
+        phi = h * dense.phi_nodes(M)
+        xs = [one] * (nd - 2)
+        mass = tt.inner(self._weight_full([one, one] + xs), f)
+        m1 = tt.inner(self._weight_full([phi, one] + xs), f)
+        m2 = tt.inner(self._weight_full([one, phi] + xs), f)
+        m12 = tt.inner(self._weight_full([phi, dense.phi_nodes(M) * one] + xs), f)
+        if nd == 2:
+            avg_m1m2 = m1 * m2
+        else:
+            f1 = self.mean_field_raw(f, 0)
+            f2 = self.mean_field_raw(f, 1)
+            avg_m1m2 = h ** (nd - 2) * tt.inner(f1, f2)
+        return {
+            "mass": mass, "mean1": m1, "mean2": m2, "mean12": m12,
+            "R12": avg_m1m2 - m1 * m2, "Y12": m12 - avg_m1m2,
+            "product": mass - m1 - m2,
+        }
+
+    # ---------------------------------------------------------------- helpers
+    def to_dense(self, f):
+        return tt.sites_to_dense(tt.tt_full(f), self.order, self.w.bits, self.nd)
+
+    def velocity_dense(self):
+        """Densified velocity MPSs as (M, M, M) arrays (x1, x2, x3)."""
+        if self.U is None:
+            return None
+        xo = self._x_order()
+        return [tt.sites_to_dense(tt.tt_full(u), xo, self.w.bits, 3) for u in self.U]
+
+    def dense_problem(self):
+        w = self.w
+        return dense.DenseProblem(w.ndims, w.M, w.omega, w.k_react, w.nu_phi,
+                                  w.gamma if w.ndims == 5 else 0.0, self.velocity_dense())

@@ -1,0 +1,106 @@
+"""Problem sizes and physical parameters of the synthetic workloads.
+
+Units follow the paper's flow case with l0 = u0 = T0 = 1, so the Peclet number
+Pe = 1e3 gives the molecular diffusivity gamma = 1e-3, the Damkohler number is
+the reaction rate k_react, and the artificial composition-space dissipation is
+nu_phi = C_Omega * mu with mu = 4e-3 (Materials and Methods, "Flow case
+definition" and "Finite-difference discretisation", eq. FP2).
+
+Dimension order is always phi1, phi2, then x1, x2, x3 (section "Matrix product
+state encoding").  ``ordering`` selects how the bits of the dimensions are laid
+out along the chain: "serial" puts all bits of phi1 first, then phi2, ... (the
+paper's choice); "interleaved" alternates bit b of every dimension.
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    ndims: int                 # 2 (phi1, phi2) or 5 (phi1, phi2, x1, x2, x3)
+    bits: int                  # M = 2**bits grid points per dimension
+    ordering: str              # "serial" | "interleaved"
+    chi: int                   # maximum MPS bond dimension
+    oversample: int = 16       # sketch rank ell = chi + oversample
+    chi_mean: int = 16         # bond cap of the mean-composition x-field
+    oversample_mean: int = 8
+    vel_rank: int = 8          # bond cap of each velocity component
+    omega: float = 1.0         # Omega_mix (constant)
+    k_react: float = 0.0       # reaction rate C_r (= Da in these units)
+    nu_phi: float = 4e-3       # C_Omega * mu
+    gamma: float = 1e-3        # gamma = 1/Pe (constant diffusivity)
+    integrator: str = "rk4"    # "rk4" | "rk2" (Heun)
+    dt: float = 1e-4
+    steps: int = 100
+    seed: int = 0
+    ic: str = "seeded"         # "seeded" | "paper" (exact eq. initPDF / eq. velField)
+    rel_tol: float = 0.0       # > 0: also drop singular values below rel_tol * sigma_1
+
+    @property
+    def M(self) -> int:
+        return 1 << self.bits
+
+    @property
+    def n_sites(self) -> int:
+        return self.ndims * self.bits
+
+    @property
+    def n_phi_sites(self) -> int:
+        return 2 * self.bits
+
+    @property
+    def n_x_sites(self) -> int:
+        return (self.ndims - 2) * self.bits
+
+    @property
+    def ell(self) -> int:
+        return self.chi + self.oversample
+
+    @property
+    def ell_mean(self) -> int:
+        return self.chi_mean + self.oversample_mean
+
+    def replace(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+_W = [
+    # 2-D composition PDF, M = 64, 12 interleaved cores, chi <= 16, RK4 dt = 1e-4, 100 steps.
+    Workload("c1_2d_M64", ndims=2, bits=6, ordering="interleaved", chi=16, oversample=16,
+             omega=1.0, k_react=0.0, nu_phi=4e-3, gamma=0.0, integrator="rk4",
+             dt=1e-4, steps=100, seed=0),
+    # Same, untruncated (chi = 2**6 covers every bond of a 12-core chain).
+    Workload("c1_2d_M64_exact", ndims=2, bits=6, ordering="interleaved", chi=64, oversample=0,
+             omega=1.0, k_react=0.0, nu_phi=4e-3, gamma=0.0, integrator="rk4",
+             dt=1e-4, steps=100, seed=0),
+    # 5-D PDF, M = 128, 35 serial cores, chi = 64, 200 RK4 steps.
+    Workload("c2_5d_M128_chi64", ndims=5, bits=7, ordering="serial", chi=64, oversample=16,
+             omega=1.0, k_react=0.0, dt=1e-3, steps=200, seed=1),
+    # 5-D PDF, M = 1024, 50 serial cores, chi = 128 / 256, reaction k = 10.
+    Workload("c3_5d_M1024_chi128", ndims=5, bits=10, ordering="serial", chi=128, oversample=16,
+             omega=1.0, k_react=10.0, dt=3e-5, steps=50, seed=2),
+    Workload("c3_5d_M1024_chi256", ndims=5, bits=10, ordering="serial", chi=256, oversample=32,
+             omega=1.0, k_react=10.0, dt=3e-5, steps=50, seed=2),
+    # Small 5-D cases that a dense full-grid solver can follow (tests).
+    Workload("t_5d_M8_exact", ndims=5, bits=3, ordering="serial", chi=128, oversample=0,
+             chi_mean=64, oversample_mean=0, vel_rank=64,
+             omega=1.0, k_react=10.0, dt=2e-3, steps=10, seed=3),
+    Workload("t_5d_M8_chi16", ndims=5, bits=3, ordering="serial", chi=16, oversample=8,
+             chi_mean=8, oversample_mean=8, vel_rank=8,
+             omega=1.0, k_react=10.0, dt=2e-3, steps=10, seed=3),
+    Workload("t_5d_M16_chi32", ndims=5, bits=4, ordering="serial", chi=32, oversample=16,
+             chi_mean=16, oversample_mean=8,
+             omega=1.0, k_react=10.0, dt=1e-3, steps=4, seed=4),
+    Workload("t_2d_M64_serial", ndims=2, bits=6, ordering="serial", chi=8, oversample=8,
+             omega=1.0, k_react=5.0, nu_phi=4e-3, gamma=0.0, dt=1e-4, steps=20, seed=5),
+]
+
+WORKLOADS = {w.name: w for w in _W}
+
+
+def get_workload(name: str, **overrides) -> Workload:
+    w = WORKLOADS[name]
+    return w.replace(**overrides) if overrides else w
