@@ -1,0 +1,256 @@
+/*
+ * qttpdf.h -- C ABI of the MI355X quantics tensor-train Fokker-Planck stepper.
+ *
+ * The library time-steps the joint PDF f(phi1, phi2; x, t) of two reacting
+ * scalars (Gourianov, Givi, Jaksch, Pope, "Tensor networks enable the
+ * calculation of turbulence probability distributions"): f lives on an
+ * M^d grid (M = 2^bits, d = 2 or 5) and is stored as a quantics matrix
+ * product state (MPS, section "Matrix product state encoding"); the
+ * finite-difference operators of eq. FP2 are matrix product operators (MPOs,
+ * section "Matrix product state algorithm"); after every operator
+ * application and every Runge-Kutta stage combination the bond dimension is
+ * cut back to chi by singular value truncation.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Status: every call returns tt_status; TT_OK == 0.  Nothing throws across
+ *    the ABI.  tt_last_error() returns a thread-local description of the last
+ *    failure.  Argument errors are reported synchronously; faults of device
+ *    work enqueued earlier surface at the next call that synchronises
+ *    (tt_ctx_synchronize, tt_get_cores, tt_observable, tt_l2_diff, ...).
+ *  - Memory: all tensor data lives in device memory owned by the library
+ *    (hipMalloc).  Host pointers passed in are only read during the call.
+ *    The caller owns every handle it receives and frees it with the matching
+ *    *_free / *_destroy call.  Handles of one context must not be used with
+ *    another context.
+ *  - Streams: a context enqueues all device work on the HIP stream given at
+ *    creation (or set later); pass PyTorch's current stream to interleave
+ *    with torch work.  A context is not thread safe.
+ *  - Layout: an MPS with N sites has bond capacities c_0..c_N (c_0 = c_N = 1)
+ *    and core n stored row-major as [c_n][2][c_{n+1}] (left bond, binary
+ *    digit, right bond), cores packed back to back in site order.  An MPO
+ *    core is [D_n][2 out][2 in][D_{n+1}].  Bonds smaller than the capacity
+ *    are zero padded.  Site order: the bits of dimension phi1 (most
+ *    significant first), then phi2, x1, x2, x3 ("serial"), or bit b of every
+ *    dimension before bit b+1 ("interleaved", 2-D only).
+ *  - Precision: master data are FP64.  tt_dtype selects the precision of
+ *    the contraction kernels (FP64, or FP32 / BF16 inputs on MFMA with FP32
+ *    accumulation); QR, eigen-decompositions and all normalisation-class
+ *    quantities stay FP64.
+ */
+#ifndef QTTPDF_H
+#define QTTPDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TT_OK = 0,
+  TT_ERR_INVALID_ARG = 1, /* bad handle, size, shape or parameter            */
+  TT_ERR_OOM = 2,         /* device or host allocation failed                */
+  TT_ERR_HIP = 3,         /* a HIP runtime call failed                       */
+  TT_ERR_NONFINITE = 4,   /* NaN / Inf detected in a result                  */
+  TT_ERR_UNSUPPORTED = 5, /* valid request outside the implemented envelope  */
+  TT_ERR_STATE = 6        /* call sequence error (e.g. no GPU device)        */
+} tt_status;
+
+typedef enum { TT_F64 = 0, TT_F32 = 1, TT_BF16 = 2 } tt_dtype;
+typedef enum { TT_RK4 = 0, TT_RK2_HEUN = 1 } tt_integrator;
+typedef enum { TT_SERIAL = 0, TT_INTERLEAVED = 1 } tt_ordering;
+typedef enum { TT_MPS = 0, TT_MPO = 1 } tt_kind;
+
+/* Scalar statistics (x-averages over [0,1)^3, eq. spaceAvg; for d = 2 the
+ * plain composition-space integrals):
+ *   MASS    avg <1>                    MEAN1 / MEAN2  avg <Phi_a>
+ *   MEAN12  avg <Phi1 Phi2>            PRODUCT avg <1 - Phi1 - Phi2>
+ *   R12     Reynolds-averaged covariance, eq. RACov
+ *   Y12     SGS covariance, eq. SGSCov                                       */
+typedef enum {
+  TT_OBS_MASS = 0,
+  TT_OBS_MEAN1 = 1,
+  TT_OBS_MEAN2 = 2,
+  TT_OBS_MEAN12 = 3,
+  TT_OBS_R12 = 4,
+  TT_OBS_Y12 = 5,
+  TT_OBS_PRODUCT = 6
+} tt_obs;
+
+typedef struct tt_ctx tt_ctx;
+typedef struct tt_tt tt_tt; /* an MPS or an MPO in device memory */
+typedef struct tt_problem tt_problem;
+
+/* ------------------------------------------------------------------------
+ * Context
+ * ------------------------------------------------------------------------ */
+/* Creates a context on HIP device `device`; `hip_stream` is a hipStream_t
+ * (NULL = the null stream).  Fails with TT_ERR_STATE if there is no device. */
+tt_status tt_ctx_create(int device, void* hip_stream, tt_ctx** out);
+tt_status tt_ctx_destroy(tt_ctx* ctx);
+tt_status tt_ctx_set_stream(tt_ctx* ctx, void* hip_stream);
+/* Waits for all work of the context's stream; reports device faults. */
+tt_status tt_ctx_synchronize(tt_ctx* ctx);
+const char* tt_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Tensor-train storage (the state f, fields, operators, sketches)
+ * ------------------------------------------------------------------------ */
+/* Allocates a zero-filled MPS (kind TT_MPS) or MPO (TT_MPO) with `n_sites`
+ * cores and bond capacities bond_caps[0..n_sites] (bond_caps[0] and
+ * bond_caps[n_sites] must be 1). */
+tt_status tt_alloc(tt_ctx* ctx, tt_kind kind, int n_sites, const int32_t* bond_caps, tt_tt** out);
+tt_status tt_free(tt_tt* t);
+/* Shape query; bond_caps (n_sites + 1 entries) may be NULL.  n_elems is the
+ * number of FP64 values of the packed cores. */
+tt_status tt_info(const tt_tt* t, int* kind, int* n_sites, int32_t* bond_caps, int64_t* n_elems);
+/* Copies packed FP64 cores (layout above, n_elems values) host -> device and
+ * device -> host.  tt_get_cores synchronises the context's stream. */
+tt_status tt_set_cores(tt_tt* t, const double* host_packed);
+tt_status tt_get_cores(const tt_tt* t, double* host_packed);
+
+/* Builds the MPS of a sum of separable functions on a grid of `ndims`
+ * dimensions with M = 2^bits points each, f = sum_t coeffs[t] *
+ * prod_d v[t*ndims + d], each v a host array of M values (NULL = all ones),
+ * and rounds it to bond `chi` (QR sweeps + SVD truncation).  Used for the
+ * initial PDF (eq. initPDF, smoothed in x) and the velocity field
+ * (eq. velField) of the "Flow case definition".  `ordering` is a tt_ordering. */
+tt_status tt_from_separable(tt_ctx* ctx, int ndims, int bits, int ordering, int n_terms,
+                            const double* coeffs, const double* const* v, int chi, tt_tt** out);
+
+/* ------------------------------------------------------------------------
+ * Operator assembly (a1): mpo_build
+ * ------------------------------------------------------------------------ */
+/* One-dimensional CFD2 operators on M = 2^bits points, h = 1/M
+ * ("Finite-difference discretisation"):
+ *   D1G / D2G  first / second central difference with the composition-space
+ *              ghost points of eq. compBCs (f_{-1} = -f_0, f_M = -f_{M-1} for
+ *              first derivatives; f_{-1} = f_0, f_M = f_{M-1} for second)
+ *   D1P / D2P  the same differences with periodic wrap (x directions)
+ *   PHI        diag(phi_i), phi_i = (i + 1/2) h (cell-centred nodes)
+ *   D1G_PHI    D1G * diag(phi)                                              */
+typedef enum {
+  TT_OP_ID = 0,
+  TT_OP_D1G = 1,
+  TT_OP_D2G = 2,
+  TT_OP_D1P = 3,
+  TT_OP_D2P = 4,
+  TT_OP_PHI = 5,
+  TT_OP_D1G_PHI = 6
+} tt_op1d;
+
+/* A term coeff * diag(field) * (op[0] (x) op[1] (x) ... ), op[d] acting on
+ * dimension d.  field < 0: no field; otherwise index into the `fields`
+ * array of mpo_build: an MPS over the last `field_ndims` dimensions (the x
+ * directions), applied as a diagonal. */
+typedef struct {
+  double coeff;
+  int32_t op[8];
+  int32_t field;
+} tt_term;
+
+/* Sums the terms into one MPO, compresses it by SVD truncation at relative
+ * tolerance rel_tol (0: exact), and uploads it (new handle in *out).
+ * max_bond receives the largest MPO bond (nullable).  All construction is
+ * FP64 on the host; the fields are read back from the device. */
+tt_status mpo_build(tt_ctx* ctx, int ndims, int bits, int ordering, const tt_term* terms,
+                    int n_terms, const tt_tt* const* fields, int n_fields, int field_ndims,
+                    double rel_tol, tt_tt** out, int* max_bond);
+
+/* ------------------------------------------------------------------------
+ * MPS arithmetic (a3, a4, a5)
+ * ------------------------------------------------------------------------ */
+/* Exact MPO x MPS product (matrix-vector multiplication in MPS form,
+ * "Computational complexity"): out core n = sum_s W[a,t,s,b] x[c,s,d] with
+ * bond capacities c_n * D_n (new handle). */
+tt_status mps_apply_mpo(tt_ctx* ctx, const tt_tt* mpo, const tt_tt* x, tt_tt** out);
+
+/* Exact linear combination sum_j coeffs[j] * xs[j] by block-diagonal core
+ * concatenation (MPS addition); bond capacities add up (new handle). */
+tt_status mps_axpby(tt_ctx* ctx, int n_terms, const double* coeffs, const tt_tt* const* xs,
+                    tt_tt** out);
+
+/* Deterministic rounding (bond truncation by SVD): an LQ sweep and a QR
+ * sweep (Householder, FP64) bring x to left-orthogonal form, then every bond
+ * n is cut to min(chi, 2^n, 2^(N-n)) leading left singular vectors, obtained
+ * from the eigen-decomposition of its right Gram matrix (FP64).  The result
+ * satisfies ||x - out|| <= sum_n eps_n with eps_n the discarded singular
+ * weight of bond n.  New handle. */
+tt_status mps_round(tt_ctx* ctx, const tt_tt* x, int chi, tt_tt** out);
+
+/* Rounding of Y = sum_j coeffs[j] * W_j x_j (W_j an MPO or NULL = identity)
+ * without forming Y: randomized range finding with the Gaussian sketch TT
+ * `sketch` (ranks ell_n; right partial sketches, then a left-to-right
+ * Householder QR sweep of the sketched unfoldings), followed by the same
+ * bond truncation as mps_round.  Contractions run in precision `dtype`.
+ * New handle with bond caps min(chi, 2^n, 2^(N-n)). */
+tt_status mps_round_sketch(tt_ctx* ctx, int n_terms, const double* coeffs,
+                           const tt_tt* const* mpos, const tt_tt* const* xs,
+                           const tt_tt* sketch, int chi, int dtype, tt_tt** out);
+
+/* ||a - b|| / ||b|| computed from the difference MPS brought to
+ * left-orthogonal form (no cancellation of large inner products). */
+tt_status tt_l2_diff(tt_ctx* ctx, const tt_tt* a, const tt_tt* b, double* rel_err);
+/* <a, b> (FP64 environment contraction). */
+tt_status tt_inner(tt_ctx* ctx, const tt_tt* a, const tt_tt* b, double* out);
+
+/* ------------------------------------------------------------------------
+ * The time step (a2, a6, a7, a8)
+ * ------------------------------------------------------------------------ */
+/* Parameters of eq. FP2 in units l0 = u0 = T0 = 1 ("Flow case definition"):
+ *   omega    Omega_mix (constant LMSE mixing frequency)
+ *   k_react  reaction rate C_r of S_1 = S_2 = -C_r phi1 phi2
+ *   nu_phi   artificial composition-space dissipation C_Omega * mu
+ *   gamma    constant diffusivity in x (1 / Pe); ignored for ndims == 2
+ *   chi      bond cap of f; ell sketch rank (>= chi)
+ *   chi_mean / ell_mean  bond cap and sketch rank of the mean composition
+ *            fields <Phi_a>(x) that enter the LMSE drift (5-D only)
+ *   dt       time step; integrator a tt_integrator; dtype a tt_dtype.     */
+typedef struct {
+  int32_t ndims, bits, ordering;
+  int32_t chi, ell, chi_mean, ell_mean;
+  int32_t integrator, dtype;
+  double omega, k_react, nu_phi, gamma, dt;
+} tt_params;
+
+/* Creates a problem: builds the fixed stage operator (mpo_build of the
+ * drift, dissipation, reaction, convection and diffusion terms of eq. FP2)
+ * and all workspaces.  velocity: three x-MPSs (ndims == 5) or NULL;
+ * sketch: Gaussian TT with ranks min(ell, 2^n, 2^(N-n)); sketch_mean: the
+ * same over the x sites with ell_mean (ndims == 5) or NULL.  The inputs are
+ * copied; the caller keeps ownership. */
+tt_status tt_problem_create(tt_ctx* ctx, const tt_params* p, const tt_tt* const* velocity,
+                            const tt_tt* sketch, const tt_tt* sketch_mean, tt_problem** out);
+tt_status tt_problem_destroy(tt_problem* prob);
+/* Bond dimensions of the fixed stage MPO (n_sites + 1 entries, nullable). */
+tt_status tt_problem_info(const tt_problem* prob, int* n_sites, int32_t* mpo_bonds, int* max_mpo_bond);
+/* Allocates a state with the problem's bond caps min(chi, 2^n, 2^(N-n)). */
+tt_status tt_problem_state(tt_problem* prob, tt_tt** f);
+
+/* Advances f in place by n_steps explicit Runge-Kutta steps of eq. FP2
+ * (RK4, or RK2 in Heun form), each stage L(g) = Round(A(g) g) with the LMSE
+ * mean <Phi_a>(g) recomputed at every stage, and the stage combination
+ * rounded as well.  The first call records the step as a HIP graph that
+ * later calls replay.  f must come from tt_problem_state (or have its caps). */
+tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps);
+
+/* Per-bond discarded singular weight (sum of dropped sigma^2, n_sites + 1
+ * entries) of the last rounding of the last step, and the squared norm of
+ * its result.  Synchronises. */
+tt_status tt_step_info(tt_problem* prob, double* discarded, double* norm2);
+
+/* Scalar statistic of f (see tt_obs), FP64.  Synchronises. */
+tt_status tt_observable(tt_ctx* ctx, tt_problem* prob, const tt_tt* f, int which, double* out);
+
+/* The mean composition <Phi_a>(x) (a = 0, 1) of f as an x-MPS before its
+ * rounding (5-D: new handle over the x sites; 2-D: *out = NULL and the value
+ * is written to *scalar). */
+tt_status tt_mean_field(tt_ctx* ctx, tt_problem* prob, const tt_tt* f, int a, tt_tt** out,
+                        double* scalar);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QTTPDF_H */

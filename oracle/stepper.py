@@ -86,10 +86,10 @@ class MPSStepper:
             out.append(x)
         return out
 
-    def initial_state(self):
+    def initial_state(self, with_info=False):
         f = self._separable(workloads.ic_terms(self.w), self.order, self.nd)
-        f, _ = tt.round_det(f, self.w.chi, self.w.rel_tol)
-        return f
+        f, info = tt.round_det(f, self.w.chi, self.w.rel_tol)
+        return (f, info) if with_info else f
 
     # ---------------------------------------------------------------- operator
     def _mpo(self, per):

@@ -305,20 +305,23 @@ def trunc_gram(X, chi, rel_tol=0.0):
     P_{n-1}^T X_n P_n.  When cap_n >= ell_n nothing is dropped and P_n is a
     full orthogonal matrix, so the rounding is exact whatever the accuracy of
     the small eigenvalues.
-    Returns (cores, info) with info = {"ranks", "discarded", "norm2"}.
+    Returns (cores, info) with info = {"ranks", "discarded", "norm2", "lams"}
+    (lams[n]: eigenvalues of Gamma_n in descending order).
     """
     N = len(X)
     caps = chain_caps(N, chi)
     if N == 1:
         return [X[0].copy()], {"ranks": [1, 1], "discarded": [0.0, 0.0],
-                               "norm2": float(np.sum(X[0] ** 2))}
+                               "norm2": float(np.sum(X[0] ** 2)), "lams": [None, None]}
     G = right_grams(X)
     P = [None] * (N + 1)
     ranks_out = [1] * (N + 1)
     disc = [0.0] * (N + 1)
+    lams = [None] * (N + 1)
     for n in range(1, N):
         lam, V = np.linalg.eigh(G[n])
         lam, V = lam[::-1], V[:, ::-1]
+        lams[n] = lam
         k = lam.size
         if rel_tol > 0 and lam[0] > 0:
             k = int(np.sum(lam > rel_tol * rel_tol * lam[0]))
@@ -335,7 +338,7 @@ def trunc_gram(X, chi, rel_tol=0.0):
             A = np.tensordot(A, P[n + 1], axes=(2, 0))
         out.append(A)
     norm2 = float(np.trace(G[1]))
-    return out, {"ranks": ranks_out, "discarded": disc, "norm2": norm2}
+    return out, {"ranks": ranks_out, "discarded": disc, "norm2": norm2, "lams": lams}
 
 
 def right_orthogonalize(cores):

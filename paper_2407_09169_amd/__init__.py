@@ -1,0 +1,381 @@
+"""Python binding of libqttpdf (MI355X quantics tensor-train Fokker-Planck stepper).
+
+Thin ctypes marshalling over the C ABI declared in include/qttpdf.h; every
+step of the method runs in the HIP library.  PyTorch is only used to pass its
+current HIP stream (optional).  Importing the package does not load the
+library; ``lib()`` does, and raises if libqttpdf.so is missing or no GPU is
+present -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqttpdf.so")
+
+TT_MPS, TT_MPO = 0, 1
+TT_F64, TT_F32, TT_BF16 = 0, 1, 2
+TT_RK4, TT_RK2_HEUN = 0, 1
+TT_SERIAL, TT_INTERLEAVED = 0, 1
+OBS = {"mass": 0, "mean1": 1, "mean2": 2, "mean12": 3, "R12": 4, "Y12": 5, "product": 6}
+OP = {"ID": 0, "D1G": 1, "D2G": 2, "D1P": 3, "D2P": 4, "PHI": 5, "D1G_PHI": 6}
+DTYPES = {"f64": TT_F64, "f32": TT_F32, "bf16": TT_BF16}
+
+# every entry point of include/qttpdf.h
+EXPORTS = [
+    "tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_stream", "tt_ctx_synchronize", "tt_last_error",
+    "tt_alloc", "tt_free", "tt_info", "tt_set_cores", "tt_get_cores", "tt_from_separable",
+    "mpo_build", "mps_apply_mpo", "mps_axpby", "mps_round", "mps_round_sketch", "tt_l2_diff",
+    "tt_inner", "tt_problem_create", "tt_problem_destroy", "tt_problem_info", "tt_problem_state",
+    "tt_step", "tt_step_info", "tt_observable", "tt_mean_field",
+]
+
+
+class TTParams(C.Structure):
+    _fields_ = [
+        ("ndims", C.c_int32), ("bits", C.c_int32), ("ordering", C.c_int32),
+        ("chi", C.c_int32), ("ell", C.c_int32), ("chi_mean", C.c_int32), ("ell_mean", C.c_int32),
+        ("integrator", C.c_int32), ("dtype", C.c_int32),
+        ("omega", C.c_double), ("k_react", C.c_double), ("nu_phi", C.c_double),
+        ("gamma", C.c_double), ("dt", C.c_double),
+    ]
+
+
+class TTTerm(C.Structure):
+    _fields_ = [("coeff", C.c_double), ("op", C.c_int32 * 8), ("field", C.c_int32)]
+
+
+class QttError(RuntimeError):
+    pass
+
+
+_LIB = None
+
+
+def lib_path() -> str:
+    return LIB_PATH
+
+
+def lib():
+    """Loads libqttpdf.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise QttError(f"{LIB_PATH} not built: run `python -m paper_2407_09169_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, dbl = C.c_void_p, C.c_int, C.c_double
+    P = C.POINTER
+    sig = {
+        "tt_ctx_create": [i32, vp, P(vp)],
+        "tt_ctx_destroy": [vp],
+        "tt_ctx_set_stream": [vp, vp],
+        "tt_ctx_synchronize": [vp],
+        "tt_alloc": [vp, i32, i32, P(C.c_int32), P(vp)],
+        "tt_free": [vp],
+        "tt_info": [vp, P(i32), P(i32), P(C.c_int32), P(C.c_int64)],
+        "tt_set_cores": [vp, P(dbl)],
+        "tt_get_cores": [vp, P(dbl)],
+        "tt_from_separable": [vp, i32, i32, i32, i32, P(dbl), P(P(dbl)), i32, P(vp)],
+        "mpo_build": [vp, i32, i32, i32, P(TTTerm), i32, P(vp), i32, i32, dbl, P(vp), P(i32)],
+        "mps_apply_mpo": [vp, vp, vp, P(vp)],
+        "mps_axpby": [vp, i32, P(dbl), P(vp), P(vp)],
+        "mps_round": [vp, vp, i32, P(vp)],
+        "mps_round_sketch": [vp, i32, P(dbl), P(vp), P(vp), vp, i32, i32, P(vp)],
+        "tt_l2_diff": [vp, vp, vp, P(dbl)],
+        "tt_inner": [vp, vp, vp, P(dbl)],
+        "tt_problem_create": [vp, P(TTParams), P(vp), vp, vp, P(vp)],
+        "tt_problem_destroy": [vp],
+        "tt_problem_info": [vp, P(i32), P(C.c_int32), P(i32)],
+        "tt_problem_state": [vp, P(vp)],
+        "tt_step": [vp, vp, vp, i32],
+        "tt_step_info": [vp, P(dbl), P(dbl)],
+        "tt_observable": [vp, vp, vp, i32, P(dbl)],
+        "tt_mean_field": [vp, vp, vp, i32, P(vp), P(dbl)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.tt_last_error.argtypes = []
+    L.tt_last_error.restype = C.c_char_p
+    _LIB = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        msg = lib().tt_last_error().decode(errors="replace")
+        raise QttError(f"qttpdf status {status}: {msg}")
+
+
+def _torch_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:  # noqa: BLE001 - torch is optional plumbing
+        pass
+    return C.c_void_p(None)
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        self.h = C.c_void_p()
+        s = _torch_stream() if stream is None else C.c_void_p(stream)
+        _check(lib().tt_ctx_create(device, s, C.byref(self.h)))
+
+    def synchronize(self):
+        _check(lib().tt_ctx_synchronize(self.h))
+
+    def close(self):
+        if self.h:
+            lib().tt_ctx_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+class TT:
+    """An MPS or MPO in device memory (owned)."""
+
+    def __init__(self, ctx: Context, handle: C.c_void_p):
+        self.ctx = ctx
+        self.h = handle
+
+    @classmethod
+    def alloc(cls, ctx, caps, kind=TT_MPS):
+        caps = np.ascontiguousarray(caps, dtype=np.int32)
+        h = C.c_void_p()
+        _check(lib().tt_alloc(ctx.h, kind, len(caps) - 1, caps.ctypes.data_as(C.POINTER(C.c_int32)),
+                              C.byref(h)))
+        return cls(ctx, h)
+
+    @classmethod
+    def from_cores(cls, ctx, cores, kind=TT_MPS):
+        """Uploads cores (list of arrays (rl, 2, rr) or (rl, 2, 2, rr))."""
+        caps = [1] + [int(G.shape[-1]) for G in cores]
+        t = cls.alloc(ctx, caps, kind)
+        t.set_cores(cores)
+        return t
+
+    def info(self):
+        kind, n = C.c_int(), C.c_int()
+        _check(lib().tt_info(self.h, C.byref(kind), C.byref(n), None, None))
+        caps = np.zeros(n.value + 1, dtype=np.int32)
+        ne = C.c_int64()
+        _check(lib().tt_info(self.h, None, None, caps.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(ne)))
+        return kind.value, n.value, caps, ne.value
+
+    @property
+    def caps(self):
+        return self.info()[2]
+
+    def set_cores(self, cores):
+        kind, n, caps, ne = self.info()
+        p = 4 if kind == TT_MPO else 2
+        buf = np.zeros(ne, dtype=np.float64)
+        off = 0
+        for k in range(n):
+            G = np.asarray(cores[k], dtype=np.float64)
+            shape = (caps[k], 2, caps[k + 1]) if p == 2 else (caps[k], 2, 2, caps[k + 1])
+            full = np.zeros(shape)
+            sl = tuple(slice(0, s) for s in G.shape)
+            full[sl] = G
+            sz = full.size
+            buf[off:off + sz] = full.ravel()
+            off += sz
+        _check(lib().tt_set_cores(self.h, buf.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def cores(self):
+        kind, n, caps, ne = self.info()
+        buf = np.zeros(ne, dtype=np.float64)
+        _check(lib().tt_get_cores(self.h, buf.ctypes.data_as(C.POINTER(C.c_double))))
+        out, off = [], 0
+        for k in range(n):
+            shape = (caps[k], 2, caps[k + 1]) if kind == TT_MPS else (caps[k], 2, 2, caps[k + 1])
+            sz = int(np.prod(shape))
+            out.append(buf[off:off + sz].reshape(shape))
+            off += sz
+        return out
+
+    def free(self):
+        if self.h:
+            lib().tt_free(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+def _handles(ts):
+    arr = (C.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = t.h if t is not None else None
+    return arr
+
+
+def from_separable(ctx, ndims, bits, ordering, terms, chi):
+    """MPS of sum_t c_t prod_d v_t[d] rounded to chi (terms: [(c, [vec or None]*ndims)])."""
+    n = len(terms)
+    coeffs = (C.c_double * n)(*[float(c) for c, _ in terms])
+    keep = []
+    ptrs = (C.POINTER(C.c_double) * (n * ndims))()
+    for t, (_, vecs) in enumerate(terms):
+        for d in range(ndims):
+            v = vecs[d]
+            if v is None:
+                ptrs[t * ndims + d] = C.POINTER(C.c_double)()
+            else:
+                a = np.ascontiguousarray(v, dtype=np.float64)
+                keep.append(a)
+                ptrs[t * ndims + d] = a.ctypes.data_as(C.POINTER(C.c_double))
+    h = C.c_void_p()
+    _check(lib().tt_from_separable(ctx.h, ndims, bits, ordering, n, coeffs, ptrs, chi, C.byref(h)))
+    return TT(ctx, h)
+
+
+def mpo_build(ctx, ndims, bits, ordering, terms, fields=(), field_ndims=0, rel_tol=0.0):
+    """terms: [(coeff, {dim: op_name}, field_index or -1)]."""
+    arr = (TTTerm * len(terms))()
+    for i, (c, ops, fld) in enumerate(terms):
+        arr[i].coeff = c
+        for d in range(8):
+            arr[i].op[d] = OP[ops.get(d, "ID")] if isinstance(ops, dict) else OP["ID"]
+        arr[i].field = fld
+    h = C.c_void_p()
+    mb = C.c_int()
+    _check(lib().mpo_build(ctx.h, ndims, bits, ordering, arr, len(terms), _handles(list(fields)),
+                           len(fields), field_ndims, rel_tol, C.byref(h), C.byref(mb)))
+    return TT(ctx, h), mb.value
+
+
+def apply_mpo(ctx, W, x):
+    h = C.c_void_p()
+    _check(lib().mps_apply_mpo(ctx.h, W.h, x.h, C.byref(h)))
+    return TT(ctx, h)
+
+
+def axpby(ctx, coeffs, xs):
+    c = (C.c_double * len(xs))(*coeffs)
+    h = C.c_void_p()
+    _check(lib().mps_axpby(ctx.h, len(xs), c, _handles(xs), C.byref(h)))
+    return TT(ctx, h)
+
+
+def round_det(ctx, x, chi):
+    h = C.c_void_p()
+    _check(lib().mps_round(ctx.h, x.h, chi, C.byref(h)))
+    return TT(ctx, h)
+
+
+def round_sketch(ctx, coeffs, mpos, xs, sketch, chi, dtype="f64"):
+    c = (C.c_double * len(xs))(*coeffs)
+    h = C.c_void_p()
+    _check(lib().mps_round_sketch(ctx.h, len(xs), c, _handles(mpos), _handles(xs), sketch.h, chi,
+                                  DTYPES[dtype], C.byref(h)))
+    return TT(ctx, h)
+
+
+def l2_diff(ctx, a, b):
+    r = C.c_double()
+    _check(lib().tt_l2_diff(ctx.h, a.h, b.h, C.byref(r)))
+    return r.value
+
+
+def inner(ctx, a, b):
+    r = C.c_double()
+    _check(lib().tt_inner(ctx.h, a.h, b.h, C.byref(r)))
+    return r.value
+
+
+class Problem:
+    """One eq. FP2 problem: fixed operator, sketches and the recorded step."""
+
+    def __init__(self, ctx, params: TTParams, velocity=None, sketch=None, sketch_mean=None):
+        self.ctx = ctx
+        self.params = params
+        self._keep = (velocity, sketch, sketch_mean)
+        h = C.c_void_p()
+        vel = _handles(velocity) if velocity else None
+        _check(lib().tt_problem_create(ctx.h, C.byref(params), vel, sketch.h,
+                                       sketch_mean.h if sketch_mean is not None else None, C.byref(h)))
+        self.h = h
+
+    def info(self):
+        n = C.c_int()
+        _check(lib().tt_problem_info(self.h, C.byref(n), None, None))
+        bonds = np.zeros(n.value + 1, dtype=np.int32)
+        mb = C.c_int()
+        _check(lib().tt_problem_info(self.h, None, bonds.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(mb)))
+        return bonds, mb.value
+
+    def state(self):
+        h = C.c_void_p()
+        _check(lib().tt_problem_state(self.h, C.byref(h)))
+        return TT(self.ctx, h)
+
+    def step(self, f, n_steps=1):
+        _check(lib().tt_step(self.ctx.h, self.h, f.h, n_steps))
+
+    def step_info(self):
+        n = int(self.info()[0].size)
+        disc = np.zeros(n, dtype=np.float64)
+        nrm = C.c_double()
+        _check(lib().tt_step_info(self.h, disc.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nrm)))
+        return disc, nrm.value
+
+    def observable(self, f, which):
+        r = C.c_double()
+        _check(lib().tt_observable(self.ctx.h, self.h, f.h, OBS[which], C.byref(r)))
+        return r.value
+
+    def mean_field(self, f, a):
+        h = C.c_void_p()
+        sc = C.c_double()
+        _check(lib().tt_mean_field(self.ctx.h, self.h, f.h, a, C.byref(h), C.byref(sc)))
+        if h.value is None:
+            return sc.value
+        return TT(self.ctx, h)
+
+    def close(self):
+        if self.h:
+            lib().tt_problem_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+def setup_workload(ctx, w, dtype="f64"):
+    """Builds (problem, f0) for a workloads.Workload with the seeded inputs."""
+    import workloads
+
+    ordering = TT_SERIAL if w.ordering == "serial" else TT_INTERLEAVED
+    velocity = None
+    if w.ndims == 5:
+        velocity = [from_separable(ctx, 3, w.bits, TT_SERIAL, comp, w.vel_rank)
+                    for comp in workloads.velocity_terms(w)]
+    sketch = TT.from_cores(ctx, workloads.sketch_cores(w))
+    sketch_mean = TT.from_cores(ctx, workloads.mean_sketch_cores(w)) if w.ndims == 5 else None
+    p = TTParams(ndims=w.ndims, bits=w.bits, ordering=ordering, chi=w.chi, ell=w.ell,
+                 chi_mean=w.chi_mean, ell_mean=w.ell_mean,
+                 integrator=TT_RK4 if w.integrator == "rk4" else TT_RK2_HEUN,
+                 dtype=DTYPES[dtype], omega=w.omega, k_react=w.k_react, nu_phi=w.nu_phi,
+                 gamma=w.gamma, dt=w.dt)
+    prob = Problem(ctx, p, velocity, sketch, sketch_mean)
+    f0 = from_separable(ctx, w.ndims, w.bits, ordering, workloads.ic_terms(w), w.chi)
+    return prob, f0

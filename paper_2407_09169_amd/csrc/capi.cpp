@@ -1,0 +1,1049 @@
+// extern "C" entry points of the qttpdf library (declared in include/qttpdf.h).
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+#include "library.h"
+
+namespace qtt {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+const char* get_error() { return g_err.c_str(); }
+
+StreamScope::StreamScope(tt_ctx* ctx) : c(ctx) {
+  if (rt::dry()) return;
+  QTT_HIP(hipSetDevice(c->device));
+  if (c->user_stream != c->stream) {
+    QTT_HIP(hipEventRecord(c->ev_in, c->user_stream));
+    QTT_HIP(hipStreamWaitEvent(c->stream, c->ev_in, 0));
+  }
+}
+StreamScope::~StreamScope() {
+  if (!rt::dry() && c->user_stream != c->stream) {
+    (void)hipEventRecord(c->ev_out, c->stream);
+    (void)hipStreamWaitEvent(c->user_stream, c->ev_out, 0);
+  }
+}
+
+static Prec prec_of(int dtype) {
+  switch (dtype) {
+    case TT_F64: return Prec::F64;
+    case TT_F32: return Prec::F32;
+    case TT_BF16: return Prec::BF16;
+  }
+  QTT_THROW(TT_ERR_INVALID_ARG, "unknown dtype %d", dtype);
+}
+
+static host::TT download(const tt_tt* t) {
+  std::vector<double> h(t->total());
+  rt::sync(t->ctx->stream);
+  rt::copy(h.data(), t->buf.p, h.size() * sizeof(double));
+  host::TT out;
+  for (int n = 0; n < t->N; ++n) {
+    host::Core G(t->caps[n], t->p, t->caps[n + 1]);
+    std::copy(h.begin() + t->off[n], h.begin() + t->off[n + 1], G.v.begin());
+    out.push_back(std::move(G));
+  }
+  return out;
+}
+
+// host chain -> device chain with the given capacities (zero padded)
+static std::unique_ptr<tt_tt> upload(tt_ctx* ctx, int kind, const host::TT& x,
+                                     const std::vector<int>& caps) {
+  const int N = (int)x.size();
+  auto t = make_tt(ctx, kind, N, caps);
+  std::vector<double> h(t->total(), 0.0);
+  for (int n = 0; n < N; ++n) {
+    const host::Core& G = x[n];
+    QTT_REQUIRE(G.rl <= caps[n] && G.rr <= caps[n + 1], "bond %d exceeds its capacity", n);
+    for (int a = 0; a < G.rl; ++a)
+      for (int s = 0; s < G.p; ++s)
+        for (int b = 0; b < G.rr; ++b)
+          h[t->off[n] + ((int64_t)a * t->p + s) * caps[n + 1] + b] = G.at(a, s, b);
+  }
+  rt::copy(t->buf.p, h.data(), h.size() * sizeof(double));
+  return t;
+}
+
+static std::vector<int> exact_caps(const host::TT& x) {
+  std::vector<int> c(x.size() + 1, 1);
+  for (size_t n = 0; n < x.size(); ++n) c[n + 1] = x[n].rr;
+  c[0] = 1;
+  return c;
+}
+
+static void check_tt(const tt_tt* t, tt_ctx* ctx = nullptr) {
+  QTT_REQUIRE(t != nullptr, "null tensor-train handle");
+  if (ctx) QTT_REQUIRE(t->ctx == ctx, "handle belongs to another context");
+}
+
+// ---------------------------------------------------------------------------
+// operator assembly
+// ---------------------------------------------------------------------------
+static host::TT build_mpo_host(int ndims, int bits, int ordering, const tt_term* terms, int n_terms,
+                               const std::vector<host::TT>& fields, int field_ndims, double rel_tol) {
+  auto order = host::site_order(ndims, bits, ordering);
+  const int N = ndims * bits;
+  std::vector<host::TT> parts;
+  std::vector<host::TT> ops1d(8);
+  std::vector<bool> have(8, false);
+  parts.reserve(n_terms);
+  for (int t = 0; t < n_terms; ++t) {
+    std::vector<host::TT> per(ndims);
+    std::vector<const host::TT*> pp(ndims, nullptr);
+    for (int d = 0; d < ndims; ++d) {
+      int op = terms[t].op[d];
+      QTT_REQUIRE(op >= TT_OP_ID && op <= TT_OP_D1G_PHI, "term %d: bad operator code %d", t, op);
+      if (op == TT_OP_ID) continue;
+      if (!have[op]) {
+        ops1d[op] = host::op1d(op, bits);
+        have[op] = true;
+      }
+      pp[d] = &ops1d[op];
+    }
+    host::TT W = host::kron_dims(pp, order, ndims, 4);
+    if (terms[t].field >= 0) {
+      QTT_REQUIRE(terms[t].field < (int)fields.size(), "term %d: bad field index", t);
+      QTT_REQUIRE(ordering == TT_SERIAL, "fields need the serial ordering");
+      const host::TT& f = fields[terms[t].field];
+      const int nf = field_ndims * bits;
+      QTT_REQUIRE((int)f.size() == nf, "field length %zu != %d", f.size(), nf);
+      host::TT diag = host::mpo_identity(N - nf);
+      host::TT dg = host::mpo_diag(f);
+      diag.insert(diag.end(), dg.begin(), dg.end());
+      W = host::mpo_compose(diag, W);
+    }
+    parts.push_back(std::move(W));
+  }
+  std::vector<std::pair<double, const host::TT*>> sum;
+  for (int t = 0; t < n_terms; ++t) sum.emplace_back(terms[t].coeff, &parts[t]);
+  host::TT A = host::tt_sum(sum);
+  if (rel_tol > 0) A = host::round_svd(A, rel_tol, 1 << 30);
+  return A;
+}
+
+}  // namespace qtt
+
+using namespace qtt;
+
+// ===========================================================================
+// problem
+// ===========================================================================
+struct tt_problem {
+  tt_ctx* ctx = nullptr;
+  tt_params p{};
+  int N = 0, nphi = 0, nx = 0;
+  std::vector<int> fcaps, mcaps;
+  std::unique_ptr<tt_tt> Z, Zm;
+  std::unique_ptr<tt_tt> A;   // combined stage operator: fixed (+) mean-field part
+  std::vector<int> Dfix;      // bonds of the fixed operator
+  std::unique_ptr<tt_tt> Wm;  // mean-field weights over the phi sites (2 output channels)
+  DevBuf mf_first;                  // 2-D: unscaled first-core blocks [1][4][cols_a] of the two
+  std::vector<int> mf_first_off;    //      mean-field terms, block a at a * 4 * mf_first_ld
+  std::vector<int> mf_first_cols;
+  int mf_first_ld = 1;
+  std::unique_ptr<tt_tt> k[4];
+  std::unique_ptr<tt_tt> mt[2];
+  DevBuf Ef, Ek, mff, mfk, scal;
+  int cphi = 1, cphi1 = 1;  // caps of f at the phi|x cut and after the first x site
+  // recorded step
+  std::unique_ptr<Plan> plan;
+  const tt_tt* plan_f = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  RoundTarget last;
+  std::unique_ptr<Plan> obs_plan;
+  ~tt_problem() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+namespace qtt {
+
+// mean-field partial contraction of x over the phi sites: E (2 x cphi), and
+// for 5-D the first x-core of each raw mean field, first[a] = E[a,:] x_{nphi}
+static void plan_mean_raw(Plan& plan, tt_problem* P, const tt_tt* x, double* E, double* first) {
+  ChainView w = view(P->Wm.get());
+  ChainView xs = view_sites(x, 0, P->nphi);
+  plan_partial(plan, w, xs, E);
+  if (P->nx > 0) {
+    const int c = x->caps[P->nphi], c1 = x->caps[P->nphi + 1];
+    TcDesc d = gemm_desc(2, 2 * c1, c, E, c, false, x->core(P->nphi), 2 * c1, false, first, 2 * c1);
+    plan.add([d](hipStream_t s) { tc_launch(d, Prec::F64, s); });
+  }
+}
+
+// raw mean field a of x as an x-chain: first core from `first`, the rest from x
+static ChainView mean_view(tt_problem* P, const tt_tt* x, const double* first, int a) {
+  ChainView v;
+  v.N = P->nx;
+  v.p = 2;
+  v.caps.push_back(1);
+  for (int j = 1; j <= P->nx; ++j) v.caps.push_back(x->caps[P->nphi + j]);
+  v.core.push_back(first + (size_t)a * 2 * x->caps[P->nphi + 1]);
+  for (int j = 1; j < P->nx; ++j) v.core.push_back(x->core(P->nphi + j));
+  return v;
+}
+
+// writes the mean-field blocks of the stage operator A for the state
+// g = f + cg * kprev (kprev may be null)
+static void plan_stage_operator(Plan& plan, tt_problem* P, const tt_tt* f, const tt_tt* kprev,
+                                double cg) {
+  const tt_params& p = P->p;
+  if (P->nx == 0) {
+    // 2-D: scalars s_a = -Omega (m_a(f) + cg m_a(k)); first-core blocks scaled
+    double* sc = P->scal.d();
+    const double* ef = P->Ef.d();
+    const double* ek = kprev ? P->Ek.d() : nullptr;
+    double om = p.omega;
+    plan.add([=](hipStream_t s) { scalar_comb(sc, ef, ek, cg, -om, 2, s); });
+    std::vector<CopyJob> jobs;
+    int64_t maxe = 1;
+    for (int a = 0; a < 2; ++a) {
+      CopyJob j{};
+      j.src = P->mf_first.d() + (size_t)a * 4 * P->mf_first_ld;
+      j.dst = P->A->core(0);
+      j.rl = 1;
+      j.sp = 4;
+      j.rr = P->mf_first_cols[a];
+      j.dp = 4;
+      j.drr = P->A->caps[1];
+      j.ro = 0;
+      j.co = P->Dfix[1] + P->mf_first_off[a];
+      j.diag = 0;
+      j.scale = 1.0;
+      j.dscale = sc + a;
+      jobs.push_back(j);
+      maxe = std::max<int64_t>(maxe, 4 * j.rr);
+    }
+    for (const CopyJob& j : jobs) validate(j);
+    CopyJob* dj = plan.upload(jobs);
+    plan.add([=](hipStream_t s) { copy_jobs(dj, 2, maxe, s); });
+    return;
+  }
+  // 5-D: round the raw mean fields of g over the x sites, write diag blocks
+  Prec pf = Prec::F64;
+  ChainView Zm = view(P->Zm.get());
+  for (int a = 0; a < 2; ++a) {
+    std::vector<SketchTerm> terms;
+    SketchTerm t1;
+    t1.coef = 1.0;
+    t1.x = mean_view(P, f, P->mff.d(), a);
+    terms.push_back(t1);
+    if (kprev) {
+      SketchTerm t2;
+      t2.coef = cg;
+      t2.x = mean_view(P, kprev, P->mfk.d(), a);
+      terms.push_back(t2);
+    }
+    RoundTarget tg;
+    for (int j = 0; j < P->nx; ++j) tg.core.push_back(P->mt[a]->core(j));
+    tg.caps = P->mt[a]->caps;
+    plan_round_sketch(plan, terms, Zm, tg, pf);
+  }
+  std::vector<CopyJob> jobs;
+  int64_t maxe = 1;
+  const int N = P->N, nphi = P->nphi, nx = P->nx;
+  for (int j = 0; j < nx; ++j) {
+    const int n = nphi + j;
+    for (int a = 0; a < 2; ++a) {
+      const tt_tt* m = P->mt[a].get();
+      CopyJob c{};
+      c.src = m->core(j);
+      c.dst = P->A->core(n);
+      c.rl = m->caps[j];
+      c.sp = 2;
+      c.rr = m->caps[j + 1];
+      c.dp = 4;
+      c.drr = P->A->caps[n + 1];
+      int row0 = (n == 0) ? 0 : P->Dfix[n];
+      int col0 = (n == N - 1) ? 0 : P->Dfix[n + 1];
+      c.ro = row0 + ((j == 0) ? a : a * P->mcaps[j]);
+      c.co = col0 + ((j == nx - 1) ? 0 : a * P->mcaps[j + 1]);
+      c.diag = 1;
+      c.scale = 1.0;
+      c.dscale = nullptr;
+      jobs.push_back(c);
+      maxe = std::max<int64_t>(maxe, (int64_t)c.rl * 2 * c.rr);
+    }
+  }
+  for (const CopyJob& j : jobs) validate(j);
+  CopyJob* dj = plan.upload(jobs);
+  int nj = (int)jobs.size();
+  plan.add([=](hipStream_t s) { copy_jobs(dj, nj, maxe, s); });
+}
+
+static void build_step_plan(tt_problem* P, tt_tt* f) {
+  auto plan = std::make_unique<Plan>();
+  const tt_params& p = P->p;
+  const Prec prec = prec_of(p.dtype);
+  ChainView Z = view(P->Z.get());
+  ChainView Av = view(P->A.get());
+  const bool rk4 = (p.integrator == TT_RK4);
+  const int S = rk4 ? 4 : 2;
+  const double dt = p.dt;
+  const double cst[4] = {0.0, rk4 ? 0.5 * dt : dt, 0.5 * dt, dt};
+  plan_mean_raw(*plan, P, f, P->Ef.d(), P->mff.d());
+  for (int i = 0; i < S; ++i) {
+    const tt_tt* kp = (i == 0) ? nullptr : P->k[i - 1].get();
+    const double cg = cst[i];
+    if (kp) plan_mean_raw(*plan, P, kp, P->Ek.d(), P->mfk.d());
+    plan_stage_operator(*plan, P, f, kp, cg);
+    std::vector<SketchTerm> terms;
+    SketchTerm a;
+    a.coef = 1.0;
+    a.mpo = &Av;
+    a.x = view(f);
+    terms.push_back(a);
+    if (kp) {
+      SketchTerm b;
+      b.coef = cg;
+      b.mpo = &Av;
+      b.x = view(kp);
+      terms.push_back(b);
+    }
+    RoundTarget tg;
+    for (int n = 0; n < P->N; ++n) tg.core.push_back(P->k[i]->core(n));
+    tg.caps = P->fcaps;
+    plan_round_sketch(*plan, terms, Z, tg, prec);
+  }
+  std::vector<SketchTerm> comb;
+  auto add = [&](double c, const tt_tt* x) {
+    SketchTerm t;
+    t.coef = c;
+    t.x = view(x);
+    comb.push_back(t);
+  };
+  add(1.0, f);
+  if (rk4) {
+    add(dt / 6, P->k[0].get());
+    add(dt / 3, P->k[1].get());
+    add(dt / 3, P->k[2].get());
+    add(dt / 6, P->k[3].get());
+  } else {
+    add(0.5 * dt, P->k[0].get());
+    add(0.5 * dt, P->k[1].get());
+  }
+  RoundTarget tg;
+  for (int n = 0; n < P->N; ++n) tg.core.push_back(f->core(n));
+  tg.caps = P->fcaps;
+  plan_round_sketch(*plan, comb, Z, tg, prec);
+  P->last = tg;
+  if (P->exec) {
+    (void)hipGraphExecDestroy(P->exec);
+    P->exec = nullptr;
+  }
+  if (P->graph) {
+    (void)hipGraphDestroy(P->graph);
+    P->graph = nullptr;
+  }
+  P->plan = std::move(plan);
+  P->plan_f = f;
+}
+
+static bool use_graph() {
+  const char* e = std::getenv("QTTPDF_NO_GRAPH");
+  return !(e && e[0] == '1');
+}
+
+}  // namespace qtt
+
+// ===========================================================================
+// extern "C"
+// ===========================================================================
+extern "C" {
+
+const char* tt_last_error(void) { return get_error(); }
+
+tt_status tt_ctx_create(int device, void* hip_stream, tt_ctx** out) {
+  return guard([&] {
+    QTT_REQUIRE(out != nullptr, "out is null");
+    auto c = std::make_unique<tt_ctx>();
+    c->device = device;
+    if (rt::dry()) {
+      *out = c.release();
+      return;
+    }
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) QTT_THROW(TT_ERR_STATE, "no HIP device available");
+    QTT_REQUIRE(device >= 0 && device < n, "device %d out of range (%d devices)", device, n);
+    QTT_HIP(hipSetDevice(device));
+    QTT_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    QTT_HIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    QTT_HIP(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    c->user_stream = static_cast<hipStream_t>(hip_stream);
+    *out = c.release();
+  });
+}
+
+tt_status tt_ctx_destroy(tt_ctx* ctx) {
+  return guard([&] {
+    if (!ctx) return;
+    if (!rt::dry()) {
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipEventDestroy(ctx->ev_in);
+      (void)hipEventDestroy(ctx->ev_out);
+      (void)hipStreamDestroy(ctx->stream);
+    }
+    delete ctx;
+  });
+}
+
+tt_status tt_ctx_set_stream(tt_ctx* ctx, void* hip_stream) {
+  return guard([&] {
+    QTT_REQUIRE(ctx, "null context");
+    ctx->user_stream = static_cast<hipStream_t>(hip_stream);
+  });
+}
+
+tt_status tt_ctx_synchronize(tt_ctx* ctx) {
+  return guard([&] {
+    QTT_REQUIRE(ctx, "null context");
+    rt::sync(ctx->stream);
+  });
+}
+
+tt_status tt_alloc(tt_ctx* ctx, tt_kind kind, int n_sites, const int32_t* bond_caps, tt_tt** out) {
+  return guard([&] {
+    QTT_REQUIRE(ctx && out && bond_caps, "null argument");
+    QTT_REQUIRE(kind == TT_MPS || kind == TT_MPO, "bad kind");
+    std::vector<int> caps(bond_caps, bond_caps + n_sites + 1);
+    auto t = make_tt(ctx, kind, n_sites, caps);
+    StreamScope sc(ctx);
+    fill(t->buf.d(), t->total(), 0.0, ctx->stream);
+    *out = t.release();
+  });
+}
+
+tt_status tt_free(tt_tt* t) {
+  return guard([&] {
+    if (!t) return;
+    if (!rt::dry()) (void)hipStreamSynchronize(t->ctx->stream);
+    delete t;
+  });
+}
+
+tt_status tt_info(const tt_tt* t, int* kind, int* n_sites, int32_t* bond_caps, int64_t* n_elems) {
+  return guard([&] {
+    check_tt(t);
+    if (kind) *kind = t->kind;
+    if (n_sites) *n_sites = t->N;
+    if (bond_caps)
+      for (int n = 0; n <= t->N; ++n) bond_caps[n] = t->caps[n];
+    if (n_elems) *n_elems = t->total();
+  });
+}
+
+tt_status tt_set_cores(tt_tt* t, const double* host_packed) {
+  return guard([&] {
+    check_tt(t);
+    QTT_REQUIRE(host_packed, "null host pointer");
+    StreamScope sc(t->ctx);
+    rt::copy_async(t->buf.p, host_packed, t->total() * sizeof(double), t->ctx->stream);
+    rt::sync(t->ctx->stream);
+  });
+}
+
+tt_status tt_get_cores(const tt_tt* t, double* host_packed) {
+  return guard([&] {
+    check_tt(t);
+    QTT_REQUIRE(host_packed, "null host pointer");
+    StreamScope sc(t->ctx);
+    rt::copy_async(host_packed, t->buf.p, t->total() * sizeof(double), t->ctx->stream);
+    rt::sync(t->ctx->stream);
+  });
+}
+
+tt_status tt_from_separable(tt_ctx* ctx, int ndims, int bits, int ordering, int n_terms,
+                            const double* coeffs, const double* const* v, int chi, tt_tt** out) {
+  return guard([&] {
+    QTT_REQUIRE(ctx && out && coeffs && v, "null argument");
+    QTT_REQUIRE(ndims >= 1 && ndims <= 8 && bits >= 1 && bits <= 20 && n_terms >= 1 && chi >= 1,
+                "bad sizes");
+    QTT_REQUIRE(ordering == TT_SERIAL || ordering == TT_INTERLEAVED, "bad ordering");
+    auto order = host::site_order(ndims, bits, ordering);
+    std::vector<host::TT> parts(n_terms);
+    std::vector<std::pair<double, const host::TT*>> sum;
+    for (int t = 0; t < n_terms; ++t) {
+      std::vector<host::TT> per(ndims);
+      std::vector<const host::TT*> pp(ndims, nullptr);
+      for (int d = 0; d < ndims; ++d) {
+        const double* vec = v[(size_t)t * ndims + d];
+        if (vec) {
+          per[d] = host::vector_qtt(vec, bits);
+          pp[d] = &per[d];
+        }
+      }
+      parts[t] = host::kron_dims(pp, order, ndims, 2);
+      sum.emplace_back(coeffs[t], &parts[t]);
+    }
+    host::TT x = host::round_gram(host::tt_sum(sum), chi);
+    const int N = ndims * bits;
+    auto t = upload(ctx, TT_MPS, x, chain_caps(N, chi));
+    *out = t.release();
+  });
+}
+
+tt_status mpo_build(tt_ctx* ctx, int ndims, int bits, int ordering, const tt_term* terms,
+                    int n_terms, const tt_tt* const* fields, int n_fields, int field_ndims,
+                    double rel_tol, tt_tt** out, int* max_bond) {
+  return guard([&] {
+    QTT_REQUIRE(ctx && out && terms && n_terms >= 1, "null argument");
+    QTT_REQUIRE(ndims >= 1 && ndims <= 8 && bits >= 1 && bits <= 20, "bad grid");
+    std::vector<host::TT> fh;
+    for (int i = 0; i < n_fields; ++i) {
+      check_tt(fields[i], ctx);
+      fh.push_back(download(fields[i]));
+    }
+    host::TT A = build_mpo_host(ndims, bits, ordering, terms, n_terms, fh, field_ndims, rel_tol);
+    auto caps = exact_caps(A);
+    if (max_bond) *max_bond = *std::max_element(caps.begin(), caps.end());
+    *out = upload(ctx, TT_MPO, A, caps).release();
+  });
+}
+
+tt_status mps_apply_mpo(tt_ctx* ctx, const tt_tt* mpo, const tt_tt* x, tt_tt** out) {
+  return guard([&] {
+    check_tt(mpo, ctx);
+    check_tt(x, ctx);
+    QTT_REQUIRE(out, "out is null");
+    QTT_REQUIRE(mpo->kind == TT_MPO && x->kind == TT_MPS && mpo->N == x->N, "shape mismatch");
+    const int N = x->N;
+    std::vector<int> caps(N + 1);
+    for (int n = 0; n <= N; ++n) caps[n] = x->caps[n] * mpo->caps[n];
+    auto y = make_tt(ctx, TT_MPS, N, caps);
+    std::vector<ApplyJob> jobs;
+    int64_t maxe = 1;
+    for (int n = 0; n < N; ++n) {
+      ApplyJob j{mpo->core(n), x->core(n), y->core(n), x->caps[n], x->caps[n + 1], mpo->caps[n],
+                 mpo->caps[n + 1]};
+      jobs.push_back(j);
+      maxe = std::max<int64_t>(maxe, (int64_t)caps[n] * 2 * caps[n + 1]);
+    }
+    StreamScope sc(ctx);
+    for (const ApplyJob& j : jobs) validate(j);
+    DevBuf dj(jobs.size() * sizeof(ApplyJob));
+    rt::copy(dj.p, jobs.data(), jobs.size() * sizeof(ApplyJob));
+    apply_jobs(dj.as<ApplyJob>(), N, maxe, ctx->stream);
+    rt::sync(ctx->stream);
+    *out = y.release();
+  });
+}
+
+tt_status mps_axpby(tt_ctx* ctx, int n_terms, const double* coeffs, const tt_tt* const* xs,
+                    tt_tt** out) {
+  return guard([&] {
+    QTT_REQUIRE(ctx && coeffs && xs && out && n_terms >= 1, "null argument");
+    const int N = xs[0]->N;
+    std::vector<int> caps(N + 1, 0);
+    std::vector<std::pair<double, ChainView>> terms;
+    for (int j = 0; j < n_terms; ++j) {
+      check_tt(xs[j], ctx);
+      QTT_REQUIRE(xs[j]->kind == TT_MPS && xs[j]->N == N, "axpby: operands differ");
+      for (int n = 0; n <= N; ++n) caps[n] += xs[j]->caps[n];
+      terms.emplace_back(coeffs[j], view(xs[j]));
+    }
+    caps[0] = caps[N] = 1;
+    auto y = make_tt(ctx, TT_MPS, N, caps);
+    Plan plan;
+    plan_axpby(plan, terms, y.get());
+    StreamScope sc(ctx);
+    plan.run(ctx->stream);
+    rt::sync(ctx->stream);
+    *out = y.release();
+  });
+}
+
+tt_status mps_round(tt_ctx* ctx, const tt_tt* x, int chi, tt_tt** out) {
+  return guard([&] {
+    check_tt(x, ctx);
+    QTT_REQUIRE(out && chi >= 1 && x->kind == TT_MPS, "bad argument");
+    auto y = make_tt(ctx, TT_MPS, x->N, chain_caps(x->N, chi));
+    Plan plan;
+    RoundTarget tg;
+    for (int n = 0; n < x->N; ++n) tg.core.push_back(y->core(n));
+    tg.caps = y->caps;
+    plan_round_det(plan, view(x), tg);
+    StreamScope sc(ctx);
+    plan.run(ctx->stream);
+    rt::sync(ctx->stream);
+    *out = y.release();
+  });
+}
+
+tt_status mps_round_sketch(tt_ctx* ctx, int n_terms, const double* coeffs,
+                           const tt_tt* const* mpos, const tt_tt* const* xs, const tt_tt* sketch,
+                           int chi, int dtype, tt_tt** out) {
+  return guard([&] {
+    QTT_REQUIRE(ctx && coeffs && xs && out && n_terms >= 1 && chi >= 1, "null argument");
+    check_tt(sketch, ctx);
+    const int N = sketch->N;
+    std::vector<ChainView> mv(n_terms);
+    std::vector<SketchTerm> terms;
+    for (int j = 0; j < n_terms; ++j) {
+      check_tt(xs[j], ctx);
+      QTT_REQUIRE(xs[j]->N == N && xs[j]->kind == TT_MPS, "term %d shape", j);
+      SketchTerm t;
+      t.coef = coeffs[j];
+      t.x = view(xs[j]);
+      if (mpos && mpos[j]) {
+        check_tt(mpos[j], ctx);
+        QTT_REQUIRE(mpos[j]->N == N && mpos[j]->kind == TT_MPO, "operator %d shape", j);
+        mv[j] = view(mpos[j]);
+        t.mpo = &mv[j];
+      }
+      terms.push_back(t);
+    }
+    auto y = make_tt(ctx, TT_MPS, N, chain_caps(N, chi));
+    Plan plan;
+    RoundTarget tg;
+    for (int n = 0; n < N; ++n) tg.core.push_back(y->core(n));
+    tg.caps = y->caps;
+    plan_round_sketch(plan, terms, view(sketch), tg, prec_of(dtype));
+    StreamScope sc(ctx);
+    plan.run(ctx->stream);
+    rt::sync(ctx->stream);
+    *out = y.release();
+  });
+}
+
+tt_status tt_l2_diff(tt_ctx* ctx, const tt_tt* a, const tt_tt* b, double* rel_err) {
+  return guard([&] {
+    check_tt(a, ctx);
+    check_tt(b, ctx);
+    QTT_REQUIRE(rel_err && a->N == b->N, "bad argument");
+    const int N = a->N;
+    std::vector<int> caps(N + 1);
+    for (int n = 0; n <= N; ++n) caps[n] = a->caps[n] + b->caps[n];
+    caps[0] = caps[N] = 1;
+    auto d = make_tt(ctx, TT_MPS, N, caps);
+    Plan plan;
+    plan_axpby(plan, {{1.0, view(a)}, {-1.0, view(b)}}, d.get());
+    LeftOrth ld = plan_left_orth(plan, view(d.get()));
+    LeftOrth lb = plan_left_orth(plan, view(b));
+    StreamScope sc(ctx);
+    plan.run(ctx->stream);
+    rt::sync(ctx->stream);
+    auto nrm = [&](const LeftOrth& lo) {
+      int n = lo.caps[N - 1] * 2;
+      std::vector<double> h(n);
+      rt::copy(h.data(), lo.core[N - 1], n * sizeof(double));
+      double s = 0;
+      for (double v : h) s += v * v;
+      return std::sqrt(s);
+    };
+    double nd = nrm(ld), nb = nrm(lb);
+    *rel_err = (nb > 0) ? nd / nb : nd;
+  });
+}
+
+tt_status tt_inner(tt_ctx* ctx, const tt_tt* a, const tt_tt* b, double* out) {
+  return guard([&] {
+    check_tt(a, ctx);
+    check_tt(b, ctx);
+    QTT_REQUIRE(out && a->N == b->N, "bad argument");
+    Plan plan;
+    double* r = plan.alloc(1);
+    plan_inner(plan, view(a), view(b), r);
+    StreamScope sc(ctx);
+    plan.run(ctx->stream);
+    rt::copy_async(out, r, sizeof(double), ctx->stream);
+    rt::sync(ctx->stream);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// problem
+// ---------------------------------------------------------------------------
+tt_status tt_problem_create(tt_ctx* ctx, const tt_params* pp, const tt_tt* const* velocity,
+                            const tt_tt* sketch, const tt_tt* sketch_mean, tt_problem** out) {
+  return guard([&] {
+    QTT_REQUIRE(ctx && pp && out, "null argument");
+    const tt_params& p = *pp;
+    QTT_REQUIRE(p.ndims == 2 || p.ndims == 5, "ndims must be 2 or 5");
+    QTT_REQUIRE(p.bits >= 1 && p.bits <= 16, "bits out of range");
+    QTT_REQUIRE(p.ordering == TT_SERIAL || (p.ordering == TT_INTERLEAVED && p.ndims == 2),
+                "interleaved ordering is supported for 2-D problems only");
+    QTT_REQUIRE(p.chi >= 1 && p.ell >= p.chi, "need ell >= chi >= 1");
+    QTT_REQUIRE(p.integrator == TT_RK4 || p.integrator == TT_RK2_HEUN, "bad integrator");
+    (void)prec_of(p.dtype);
+    auto P = std::make_unique<tt_problem>();
+    P->ctx = ctx;
+    P->p = p;
+    const int N = p.ndims * p.bits;
+    P->N = N;
+    P->nphi = 2 * p.bits;
+    P->nx = N - P->nphi;
+    if (P->nx > 0) {
+      QTT_REQUIRE(velocity && velocity[0] && velocity[1] && velocity[2], "5-D problem needs velocity");
+      QTT_REQUIRE(sketch_mean, "5-D problem needs the mean-field sketch");
+      QTT_REQUIRE(p.chi_mean >= 1 && p.ell_mean >= p.chi_mean, "need ell_mean >= chi_mean >= 1");
+    }
+    check_tt(sketch, ctx);
+    QTT_REQUIRE(sketch->N == N && sketch->kind == TT_MPS, "sketch length");
+    auto ell = chain_caps(N, p.ell);
+    QTT_REQUIRE(sketch->caps == ell, "sketch ranks must be min(ell, 2^n, 2^(N-n))");
+    P->fcaps = chain_caps(N, p.chi);
+    // copies of the sketches
+    {
+      P->Z = make_tt(ctx, TT_MPS, N, ell);
+      rt::copy(P->Z->buf.p, sketch->buf.p, sketch->total() * sizeof(double));
+    }
+    if (P->nx > 0) {
+      check_tt(sketch_mean, ctx);
+      auto ellm = chain_caps(P->nx, p.ell_mean);
+      QTT_REQUIRE(sketch_mean->N == P->nx && sketch_mean->caps == ellm, "mean-field sketch shape");
+      P->Zm = make_tt(ctx, TT_MPS, P->nx, ellm);
+      rt::copy(P->Zm->buf.p, sketch_mean->buf.p, sketch_mean->total() * sizeof(double));
+      P->mcaps = chain_caps(P->nx, p.chi_mean);
+    }
+    // ---- fixed operator (eq. FP2): drift, dissipation, reaction, convection, diffusion
+    std::vector<tt_term> terms;
+    auto term = [&](double c, std::vector<std::pair<int, int>> ops, int field) {
+      tt_term t{};
+      t.coeff = c;
+      for (int d = 0; d < 8; ++d) t.op[d] = TT_OP_ID;
+      for (auto [d, op] : ops) t.op[d] = op;
+      t.field = field;
+      terms.push_back(t);
+    };
+    for (int a = 0; a < 2; ++a) {
+      term(p.omega, {{a, TT_OP_D1G_PHI}}, -1);
+      term(p.nu_phi, {{a, TT_OP_D2G}}, -1);
+      if (p.k_react != 0.0) term(p.k_react, {{a, TT_OP_D1G_PHI}, {1 - a, TT_OP_PHI}}, -1);
+    }
+    std::vector<host::TT> fields;
+    if (P->nx > 0) {
+      for (int i = 0; i < 3; ++i) {
+        check_tt(velocity[i], ctx);
+        QTT_REQUIRE(velocity[i]->N == P->nx, "velocity component %d length", i);
+        fields.push_back(download(velocity[i]));
+      }
+      for (int i = 0; i < 3; ++i) {
+        if (p.gamma != 0.0) term(p.gamma, {{2 + i, TT_OP_D2P}}, -1);
+        term(-1.0, {{2 + i, TT_OP_D1P}}, i);
+      }
+    }
+    host::TT Fx = build_mpo_host(p.ndims, p.bits, p.ordering, terms.data(), (int)terms.size(),
+                                 fields, 3, 1e-13);
+    P->Dfix = exact_caps(Fx);
+    // ---- mean-field part  -Omega sum_a D1g^(a) diag(<Phi_a>)
+    auto order = host::site_order(p.ndims, p.bits, p.ordering);
+    std::vector<std::pair<int, int>> phi_order(order.begin(), order.begin() + P->nphi);
+    host::TT d1g = host::op1d(TT_OP_D1G, p.bits);
+    host::TT T[2];
+    for (int a = 0; a < 2; ++a) {
+      std::vector<const host::TT*> pp2(2, nullptr);
+      pp2[a] = &d1g;
+      T[a] = host::kron_dims(pp2, phi_order, 2, 4);
+    }
+    // stacked mean-field chain over the phi sites (right bond 2 = channel a for 5-D)
+    host::TT MF;
+    std::vector<int> Dmf(N + 1, 1);
+    {
+      const int nphi = P->nphi;
+      for (int n = 0; n < nphi; ++n) {
+        const host::Core &A0 = T[0][n], &A1 = T[1][n];
+        int rl = (n == 0) ? 1 : A0.rl + A1.rl;
+        int rr = (n == nphi - 1) ? ((P->nx > 0) ? 2 : 1) : A0.rr + A1.rr;
+        host::Core G(rl, 4, rr);
+        for (int a = 0; a < 2; ++a) {
+          const host::Core& B = T[a][n];
+          int ro = (n == 0) ? 0 : (a == 0 ? 0 : A0.rl);
+          int co;
+          if (n == nphi - 1) co = (P->nx > 0) ? a : 0;
+          else co = (a == 0) ? 0 : A0.rr;
+          double sc = (n == 0 && P->nx > 0) ? -p.omega : 1.0;
+          for (int i = 0; i < B.rl; ++i)
+            for (int s = 0; s < 4; ++s)
+              for (int j = 0; j < B.rr; ++j) G.at(ro + i, s, co + j) += sc * B.at(i, s, j);
+        }
+        MF.push_back(std::move(G));
+      }
+      for (int n = 0; n < nphi; ++n) Dmf[n + 1] = MF[n].rr;
+      Dmf[0] = 1;
+      for (int j = 1; j < P->nx; ++j) Dmf[nphi + j] = 2 * P->mcaps[j];
+      Dmf[N] = 1;
+    }
+    std::vector<int> Dc(N + 1, 1);
+    for (int n = 1; n < N; ++n) Dc[n] = P->Dfix[n] + Dmf[n];
+    P->A = make_tt(ctx, TT_MPO, N, Dc);
+    {
+      std::vector<double> h(P->A->total(), 0.0);
+      auto put = [&](int n, const host::Core& B, int ro, int co) {
+        for (int i = 0; i < B.rl; ++i)
+          for (int s = 0; s < 4; ++s)
+            for (int j = 0; j < B.rr; ++j)
+              h[P->A->off[n] + ((int64_t)(ro + i) * 4 + s) * Dc[n + 1] + co + j] = B.at(i, s, j);
+      };
+      for (int n = 0; n < N; ++n) {
+        put(n, Fx[n], 0, 0);
+        if (n < P->nphi) {
+          int ro = (n == 0) ? 0 : P->Dfix[n];
+          int co = (n == N - 1) ? 0 : P->Dfix[n + 1];
+          put(n, MF[n], ro, co);
+        }
+      }
+      rt::copy(P->A->buf.p, h.data(), h.size() * sizeof(double));
+    }
+    if (P->nx == 0) {
+      // first-core blocks of the two mean-field terms, kept unscaled
+      P->mf_first_cols = {T[0][0].rr, T[1][0].rr};
+      P->mf_first_off = {0, T[0][0].rr};
+      P->mf_first_ld = std::max(T[0][0].rr, T[1][0].rr);
+      std::vector<double> h((size_t)2 * 4 * P->mf_first_ld, 0.0);
+      for (int a = 0; a < 2; ++a)
+        for (int s = 0; s < 4; ++s)
+          for (int j = 0; j < T[a][0].rr; ++j)
+            h[(size_t)a * 4 * P->mf_first_ld + (size_t)s * T[a][0].rr + j] = T[a][0].at(0, s, j);
+      P->mf_first.alloc(h.size() * sizeof(double));
+      rt::copy(P->mf_first.p, h.data(), h.size() * sizeof(double));
+    }
+    // ---- mean-field weights: h phi_a on dimension a, h on the other (two channels)
+    {
+      const int M = 1 << p.bits;
+      const double h = 1.0 / M;
+      std::vector<double> wphi(M), wone(M, h);
+      for (int i = 0; i < M; ++i) wphi[i] = h * (i + 0.5) * h;
+      host::TT Wa[2];
+      for (int a = 0; a < 2; ++a) {
+        host::TT q0 = host::vector_qtt(a == 0 ? wphi.data() : wone.data(), p.bits);
+        host::TT q1 = host::vector_qtt(a == 1 ? wphi.data() : wone.data(), p.bits);
+        Wa[a] = host::kron_dims({&q0, &q1}, phi_order, 2, 2);
+      }
+      const int nphi = P->nphi;
+      host::TT W;
+      for (int n = 0; n < nphi; ++n) {
+        const host::Core &A0 = Wa[0][n], &A1 = Wa[1][n];
+        int rl = (n == 0) ? 1 : A0.rl + A1.rl;
+        int rr = (n == nphi - 1) ? 2 : A0.rr + A1.rr;
+        host::Core G(rl, 2, rr);
+        for (int a = 0; a < 2; ++a) {
+          const host::Core& B = Wa[a][n];
+          int ro = (n == 0) ? 0 : (a == 0 ? 0 : A0.rl);
+          int co = (n == nphi - 1) ? a : (a == 0 ? 0 : A0.rr);
+          for (int i = 0; i < B.rl; ++i)
+            for (int s = 0; s < 2; ++s)
+              for (int j = 0; j < B.rr; ++j) G.at(ro + i, s, co + j) += B.at(i, s, j);
+        }
+        W.push_back(std::move(G));
+      }
+      std::vector<int> wc(nphi + 1, 1);
+      for (int n = 0; n < nphi; ++n) wc[n + 1] = W[n].rr;
+      // a chain container needs boundary bonds 1: store the channel bond as the
+      // last capacity through a raw view (planner reads caps from the view)
+      auto t = std::make_unique<tt_tt>();
+      t->ctx = ctx;
+      t->kind = TT_MPS;
+      t->N = nphi;
+      t->p = 2;
+      t->caps = wc;
+      t->off.assign(nphi + 1, 0);
+      for (int n = 0; n < nphi; ++n) t->off[n + 1] = t->off[n] + (int64_t)wc[n] * 2 * wc[n + 1];
+      t->buf.alloc((size_t)t->off[nphi] * sizeof(double));
+      std::vector<double> hv(t->off[nphi], 0.0);
+      for (int n = 0; n < nphi; ++n) std::copy(W[n].v.begin(), W[n].v.end(), hv.begin() + t->off[n]);
+      rt::copy(t->buf.p, hv.data(), hv.size() * sizeof(double));
+      P->Wm = std::move(t);
+    }
+    // ---- per-step buffers
+    const int S = (p.integrator == TT_RK4) ? 4 : 2;
+    for (int i = 0; i < S; ++i) P->k[i] = make_tt(ctx, TT_MPS, N, P->fcaps);
+    P->cphi = P->fcaps[P->nphi];
+    P->cphi1 = (P->nx > 0) ? P->fcaps[P->nphi + 1] : 1;
+    P->Ef.alloc(sizeof(double) * 2 * P->cphi);
+    P->Ek.alloc(sizeof(double) * 2 * P->cphi);
+    P->mff.alloc(sizeof(double) * 2 * 2 * P->cphi1);
+    P->mfk.alloc(sizeof(double) * 2 * 2 * P->cphi1);
+    P->scal.alloc(sizeof(double) * 4);
+    if (P->nx > 0)
+      for (int a = 0; a < 2; ++a) P->mt[a] = make_tt(ctx, TT_MPS, P->nx, P->mcaps);
+    rt::sync(ctx->stream);
+    *out = P.release();
+  });
+}
+
+tt_status tt_problem_destroy(tt_problem* prob) {
+  return guard([&] {
+    if (!prob) return;
+    if (!rt::dry()) (void)hipStreamSynchronize(prob->ctx->stream);
+    delete prob;
+  });
+}
+
+tt_status tt_problem_info(const tt_problem* prob, int* n_sites, int32_t* mpo_bonds, int* max_mpo_bond) {
+  return guard([&] {
+    QTT_REQUIRE(prob, "null problem");
+    if (n_sites) *n_sites = prob->N;
+    if (mpo_bonds)
+      for (int n = 0; n <= prob->N; ++n) mpo_bonds[n] = prob->Dfix[n];
+    if (max_mpo_bond) *max_mpo_bond = *std::max_element(prob->Dfix.begin(), prob->Dfix.end());
+  });
+}
+
+tt_status tt_problem_state(tt_problem* prob, tt_tt** f) {
+  return guard([&] {
+    QTT_REQUIRE(prob && f, "null argument");
+    auto t = make_tt(prob->ctx, TT_MPS, prob->N, prob->fcaps);
+    StreamScope sc(prob->ctx);
+    fill(t->buf.d(), t->total(), 0.0, prob->ctx->stream);
+    *f = t.release();
+  });
+}
+
+tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps) {
+  return guard([&] {
+    QTT_REQUIRE(prob && f && n_steps >= 0, "bad argument");
+    check_tt(f, ctx);
+    QTT_REQUIRE(prob->ctx == ctx, "problem belongs to another context");
+    QTT_REQUIRE(f->caps == prob->fcaps, "state caps differ from the problem's");
+    if (n_steps == 0) return;
+    if (!prob->plan || prob->plan_f != f) build_step_plan(prob, f);
+    StreamScope sc(ctx);
+    if (rt::dry() || !use_graph()) {
+      for (int i = 0; i < n_steps; ++i) prob->plan->run(ctx->stream);
+      return;
+    }
+    if (!prob->exec) {
+      QTT_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+      try {
+        prob->plan->run(ctx->stream);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(ctx->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      QTT_HIP(hipStreamEndCapture(ctx->stream, &prob->graph));
+      QTT_HIP(hipGraphInstantiate(&prob->exec, prob->graph, nullptr, nullptr, 0));
+    }
+    for (int i = 0; i < n_steps; ++i) QTT_HIP(hipGraphLaunch(prob->exec, ctx->stream));
+  });
+}
+
+tt_status tt_step_info(tt_problem* prob, double* discarded, double* norm2) {
+  return guard([&] {
+    QTT_REQUIRE(prob && prob->plan, "no step recorded yet");
+    rt::sync(prob->ctx->stream);
+    const int N = prob->N, ld = prob->last.ldl;
+    std::vector<double> lam((size_t)(N + 1) * ld);
+    rt::copy(lam.data(), prob->last.lam, lam.size() * sizeof(double));
+    auto ell = chain_caps(N, prob->p.ell);
+    for (int n = 0; n <= N; ++n) {
+      double d = 0.0;
+      if (n >= 1 && n < N)
+        for (int i = std::min(ell[n], prob->fcaps[n]); i < ell[n]; ++i) d += std::max(0.0, lam[(size_t)n * ld + i]);
+      if (discarded) discarded[n] = d;
+    }
+    if (norm2) {
+      double s = 0.0;
+      if (N >= 2)
+        for (int i = 0; i < ell[1]; ++i) s += std::max(0.0, lam[(size_t)ld + i]);
+      *norm2 = s;
+    }
+  });
+}
+
+tt_status tt_mean_field(tt_ctx* ctx, tt_problem* prob, const tt_tt* f, int a, tt_tt** out,
+                        double* scalar) {
+  return guard([&] {
+    QTT_REQUIRE(prob && (a == 0 || a == 1), "bad argument");
+    check_tt(f, ctx);
+    QTT_REQUIRE(f->caps == prob->fcaps, "state caps differ from the problem's");
+    Plan plan;
+    double* E = plan.alloc(2 * f->caps[prob->nphi]);
+    double* first = plan.alloc(2 * 2 * std::max(1, prob->nx > 0 ? f->caps[prob->nphi + 1] : 1));
+    plan_mean_raw(plan, prob, f, E, first);
+    StreamScope sc(ctx);
+    plan.run(ctx->stream);
+    rt::sync(ctx->stream);
+    if (prob->nx == 0) {
+      double h[2];
+      rt::copy(h, E, sizeof(h));
+      if (scalar) *scalar = h[a];
+      if (out) *out = nullptr;
+      return;
+    }
+    QTT_REQUIRE(out, "out is null");
+    std::vector<int> caps(prob->nx + 1);
+    caps[0] = 1;
+    for (int j = 1; j <= prob->nx; ++j) caps[j] = f->caps[prob->nphi + j];
+    auto m = make_tt(ctx, TT_MPS, prob->nx, caps);
+    const int c1 = f->caps[prob->nphi + 1];
+    rt::copy(m->core(0), first + (size_t)a * 2 * c1, 2 * c1 * sizeof(double));
+    for (int j = 1; j < prob->nx; ++j)
+      rt::copy(m->core(j), f->core(prob->nphi + j),
+                        (m->off[j + 1] - m->off[j]) * sizeof(double));
+    *out = m.release();
+  });
+}
+
+tt_status tt_observable(tt_ctx* ctx, tt_problem* prob, const tt_tt* f, int which, double* out) {
+  return guard([&] {
+    QTT_REQUIRE(prob && out, "bad argument");
+    check_tt(f, ctx);
+    QTT_REQUIRE(f->caps == prob->fcaps, "state caps differ from the problem's");
+    QTT_REQUIRE(which >= TT_OBS_MASS && which <= TT_OBS_PRODUCT, "unknown observable %d", which);
+    const tt_params& p = prob->p;
+    const int M = 1 << p.bits;
+    const double h = 1.0 / M;
+    auto order = host::site_order(p.ndims, p.bits, p.ordering);
+    std::vector<double> one(M, h), phi(M);
+    for (int i = 0; i < M; ++i) phi[i] = h * (i + 0.5) * h;
+    // weight chain for sum_x,phi w(phi) f h^d
+    auto weight = [&](const std::vector<const std::vector<double>*>& per_phi) {
+      std::vector<host::TT> q(p.ndims);
+      std::vector<const host::TT*> pp(p.ndims);
+      for (int d = 0; d < p.ndims; ++d) {
+        const std::vector<double>* v = (d < 2) ? per_phi[d] : &one;
+        q[d] = host::vector_qtt(v->data(), p.bits);
+        pp[d] = &q[d];
+      }
+      return host::kron_dims(pp, order, p.ndims, 2);
+    };
+    auto contract = [&](const host::TT& w) {
+      auto wt = upload(ctx, TT_MPS, w, exact_caps(w));
+      Plan plan;
+      double* r = plan.alloc(1);
+      plan_inner(plan, view(wt.get()), view(f), r);
+      StreamScope sc(ctx);
+      plan.run(ctx->stream);
+      double v;
+      rt::copy_async(&v, r, sizeof(double), ctx->stream);
+      rt::sync(ctx->stream);
+      return v;
+    };
+    auto mass = [&] { return contract(weight({&one, &one})); };
+    auto mean = [&](int a) { return contract(weight({a == 0 ? &phi : &one, a == 1 ? &phi : &one})); };
+    auto mean12 = [&] { return contract(weight({&phi, &phi})); };
+    auto avg_m1m2 = [&]() -> double {
+      if (prob->nx == 0) return mean(0) * mean(1);
+      tt_tt *m0 = nullptr, *m1 = nullptr;
+      tt_status st = tt_mean_field(ctx, prob, f, 0, &m0, nullptr);
+      if (st != TT_OK) QTT_THROW(st, "%s", get_error());
+      st = tt_mean_field(ctx, prob, f, 1, &m1, nullptr);
+      if (st != TT_OK) QTT_THROW(st, "%s", get_error());
+      std::unique_ptr<tt_tt> u0(m0), u1(m1);
+      double v;
+      st = tt_inner(ctx, m0, m1, &v);
+      if (st != TT_OK) QTT_THROW(st, "%s", get_error());
+      return std::pow(h, prob->nx / p.bits) * v;
+    };
+    double v = 0.0;
+    switch (which) {
+      case TT_OBS_MASS: v = mass(); break;
+      case TT_OBS_MEAN1: v = mean(0); break;
+      case TT_OBS_MEAN2: v = mean(1); break;
+      case TT_OBS_MEAN12: v = mean12(); break;
+      case TT_OBS_PRODUCT: v = mass() - mean(0) - mean(1); break;
+      case TT_OBS_R12: v = avg_m1m2() - mean(0) * mean(1); break;
+      case TT_OBS_Y12: v = mean12() - avg_m1m2(); break;
+    }
+    *out = v;
+  });
+}
+
+}  // extern "C"

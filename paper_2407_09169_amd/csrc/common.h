@@ -1,0 +1,229 @@
+// Shared definitions of the qttpdf HIP library: error state, device
+// allocation, fast integer division and the 2-mode tensor-contraction
+// descriptor used by every contraction kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/qttpdf.h"
+
+namespace qtt {
+
+// ---------------------------------------------------------------------------
+// error state (thread local, read back through tt_last_error)
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+const char* get_error();
+
+struct Error {
+  tt_status code;
+  std::string msg;
+};
+
+#define QTT_THROW(code, ...)                                   \
+  do {                                                         \
+    char _buf[512];                                            \
+    snprintf(_buf, sizeof(_buf), __VA_ARGS__);                 \
+    throw ::qtt::Error{code, std::string(_buf)};               \
+  } while (0)
+
+#define QTT_HIP(call)                                                             \
+  do {                                                                            \
+    hipError_t _e = (call);                                                       \
+    if (_e != hipSuccess)                                                         \
+      QTT_THROW(TT_ERR_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(_e), \
+                __FILE__, __LINE__);                                              \
+  } while (0)
+
+#define QTT_REQUIRE(cond, ...)                         \
+  do {                                                 \
+    if (!(cond)) QTT_THROW(TT_ERR_INVALID_ARG, __VA_ARGS__); \
+  } while (0)
+
+// Runs `body` and converts exceptions into a status code + error message.
+template <class F>
+tt_status guard(F&& body) {
+  try {
+    body();
+    return TT_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return TT_ERR_OOM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return TT_ERR_INVALID_ARG;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// runtime shim: allocation registry (every launch is bounds-checked against
+// it on the host) and a dry-run mode (QTTPDF_DRYRUN=1) in which "device"
+// buffers are host memory and no kernel is launched -- used to validate all
+// launch geometry on machines without a GPU.
+// ---------------------------------------------------------------------------
+namespace rt {
+bool dry();
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+// throws unless [p + lo*esize, p + (hi+1)*esize) lies inside one allocation
+void check_range(const void* p, int64_t lo, int64_t hi, size_t esize, const char* what);
+void copy(void* dst, const void* src, size_t bytes);  // synchronous, any direction
+void copy_async(void* dst, const void* src, size_t bytes, hipStream_t s);
+void sync(hipStream_t s);
+}  // namespace rt
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t n) { alloc(n); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) n = 8;
+    p = rt::dev_alloc(n);
+    bytes = n;
+  }
+  void release() {
+    if (p) rt::dev_free(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  double* d() const { return static_cast<double*>(p); }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ---------------------------------------------------------------------------
+// fast unsigned division by a runtime constant (round-up multiply-shift)
+// valid for dividend < 2^31
+// ---------------------------------------------------------------------------
+struct FastDiv {
+  uint32_t d = 1, m = 0, s = 0;
+  FastDiv() = default;
+  explicit FastDiv(uint32_t div) {
+    d = div;
+    s = 0;
+    while ((1ull << s) < div) ++s;
+    uint64_t one = 1;
+    m = (uint32_t)(((one << 32) * ((one << s) - div)) / div + 1);
+  }
+  __host__ __device__ inline uint32_t div(uint32_t x) const {
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t t = __umulhi(x, m);
+#else
+    uint32_t t = (uint32_t)(((uint64_t)x * m) >> 32);
+#endif
+    return (t + x) >> s;
+  }
+};
+
+// An index i of a contraction dimension that is really two tensor modes:
+// offset(i) = (i / n2) * s1 + (i % n2) * s2.  A single mode has n2 == 0 and
+// offset(i) = i * s2.
+struct Mode2 {
+  FastDiv fd;
+  int32_t n2 = 0;
+  int64_t s1 = 0, s2 = 0;
+  __host__ __device__ inline int64_t off(int32_t i) const {
+    if (n2 == 0) return (int64_t)i * s2;
+    uint32_t q = fd.div((uint32_t)i);
+    uint32_t r = (uint32_t)i - q * (uint32_t)n2;
+    return (int64_t)q * s1 + (int64_t)r * s2;
+  }
+};
+
+// largest offset of indices 0..n-1 (non-negative strides)
+inline int64_t mode_max(const Mode2& m, int32_t n) {
+  if (n <= 0) return 0;
+  if (m.n2 == 0) return (int64_t)(n - 1) * m.s2;
+  int64_t q = (n - 1) / m.n2;
+  int64_t r = std::min<int64_t>(m.n2 - 1, n - 1);
+  return q * m.s1 + r * m.s2;
+}
+
+inline Mode2 mode1(int64_t stride) {
+  Mode2 m;
+  m.n2 = 0;
+  m.s2 = stride;
+  return m;
+}
+inline Mode2 mode2(int32_t n2, int64_t s1, int64_t s2) {
+  Mode2 m;
+  if (n2 <= 1) {  // a single outer mode
+    m.n2 = 0;
+    m.s2 = s1;
+    return m;
+  }
+  m.n2 = n2;
+  m.fd = FastDiv((uint32_t)n2);
+  m.s1 = s1;
+  m.s2 = s2;
+  return m;
+}
+
+// C[b](m,n) = alpha * sum_k A[b](m,k) B[b](k,n) + beta * C[b](m,n)
+struct TcDesc {
+  int32_t M = 0, N = 0, K = 0, batch = 1;
+  Mode2 am, ak, ab;
+  Mode2 bk, bn, bb;
+  Mode2 cm, cn, cb;
+  double alpha = 1.0, beta = 0.0;
+  const double* A = nullptr;
+  const double* B = nullptr;
+  double* C = nullptr;
+};
+
+// precision of the contraction kernels (inputs are rounded to it, accumulation
+// is FP32 for the FP32 / BF16 paths and FP64 otherwise)
+enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
+
+void tc_launch(const TcDesc& d, Prec p, hipStream_t s);
+// host-side bounds check of a contraction against the allocation registry
+void tc_validate(const TcDesc& d);
+
+// plain row-major GEMM helper: C(MxN) = alpha*op(A)*op(B) + beta*C
+TcDesc gemm_desc(int M, int N, int K, const double* A, int64_t lda, bool transA,
+                 const double* B, int64_t ldb, bool transB, double* C, int64_t ldc,
+                 double alpha = 1.0, double beta = 0.0);
+
+// ---------------------------------------------------------------------------
+// factorisations (FP64)
+// ---------------------------------------------------------------------------
+// Householder QR of `count` matrices A_i (m x n, m >= n, element (r,c) at
+// A + i*strideA + r*rs + c*cs).  Writes the thin explicit Q_i (m x n,
+// row-major, ldq = n, at Q + i*strideQ) and, if R != nullptr, R_i (n x n
+// upper triangular, row-major).  `work` must hold count*m*n doubles.
+void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_t rs, int64_t cs,
+               double* Q, int64_t strideQ, double* R, int64_t strideR, double* work,
+               hipStream_t s);
+
+// Eigen-decomposition of `count` symmetric PSD matrices G_i (n_i x n_i,
+// row-major, ld = ldg, at G + i*strideG); n_i = dims[i] (device array).
+// Writes the eigenvectors of the k_i = keep[i] largest eigenvalues as the
+// columns of P_i (n_i x k_i, row-major, ld = ldp, at P + i*strideP) and all
+// eigenvalues in descending order to lam + i*strideL.  `work` holds
+// count * ldg * ldg doubles.
+void eig_launch(int count, const int* dims, const int* keep, const double* G, int64_t strideG,
+                int ldg, double* P, int64_t strideP, int ldp, double* lam, int64_t strideL,
+                double* work, int max_n, hipStream_t s);
+
+}  // namespace qtt

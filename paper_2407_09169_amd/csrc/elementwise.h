@@ -1,0 +1,41 @@
+#pragma once
+#include "common.h"
+
+namespace qtt {
+
+// dst[((ro + a) * dp + s') * drr + co + b] = scale * (*dscale) * src[(a * sp + s) * rr + b]
+// with s' = s, or s' = 2s + s (diag: an MPS core written as a diagonal MPO block)
+struct CopyJob {
+  const double* src;
+  double* dst;
+  int rl, sp, rr;   // source block [rl][sp][rr]
+  int dp, drr;      // destination physical size and right-bond capacity
+  int ro, co;       // block offsets in the destination core
+  int diag;
+  double scale;
+  const double* dscale;  // optional device scalar multiplier
+};
+
+// out[(a*Dl + alpha), t, (b*Dr + beta)] = sum_s W[alpha,t,s,beta] x[a,s,b]
+struct ApplyJob {
+  const double* W;
+  const double* x;
+  double* out;
+  int xl, xr, Dl, Dr;
+};
+
+void fill(double* p, int64_t n, double v, hipStream_t s);
+// dst (cols x rows) = src^T, both row-major
+void transpose(const double* src, int rows, int cols, double* dst, hipStream_t s);
+// dst (m x m) = identity
+void eye(double* dst, int m, hipStream_t s);
+// out[i] = scale * (a[i] + cb * b[i]) for i < n <= 64 (b may be null)
+void scalar_comb(double* out, const double* a, const double* b, double cb, double scale, int n,
+                 hipStream_t s);
+// host-side bounds checks of a job (call before uploading the job table)
+void validate(const CopyJob& j);
+void validate(const ApplyJob& j);
+void copy_jobs(const CopyJob* d_jobs, int njobs, int64_t max_elems, hipStream_t s);
+void apply_jobs(const ApplyJob* d_jobs, int njobs, int64_t max_elems, hipStream_t s);
+
+}  // namespace qtt

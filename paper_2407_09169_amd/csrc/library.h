@@ -1,0 +1,111 @@
+// Internal structures of the qttpdf library: contexts, device tensor trains,
+// launch plans (recorded once, replayed eagerly or as a HIP graph) and the
+// rounding planners.
+#pragma once
+
+#include <functional>
+#include <memory>
+#include <unordered_map>
+
+#include "common.h"
+#include "elementwise.h"
+#include "host_tt.h"
+
+struct tt_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;       // the library's own stream (non-blocking)
+  hipStream_t user_stream = nullptr;  // caller's stream (ordering is kept with events)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+struct tt_tt {
+  tt_ctx* ctx = nullptr;
+  int kind = TT_MPS;  // TT_MPS or TT_MPO
+  int N = 0;
+  int p = 2;  // physical size of a core (2 MPS, 4 MPO)
+  std::vector<int> caps;
+  std::vector<int64_t> off;  // element offset of every core, off[N] = total
+  qtt::DevBuf buf;
+  double* core(int n) const { return buf.d() + off[n]; }
+  int64_t total() const { return off[N]; }
+};
+
+namespace qtt {
+
+// enqueue-on-own-stream scope: orders the library stream after the user's
+// stream on entry and the user's stream after the library stream on exit
+struct StreamScope {
+  tt_ctx* c;
+  explicit StreamScope(tt_ctx* ctx);
+  ~StreamScope();
+};
+
+std::unique_ptr<tt_tt> make_tt(tt_ctx* ctx, int kind, int N, const std::vector<int>& caps);
+std::vector<int> chain_caps(int N, long cap);
+
+// per-site core pointers and bond capacities of a chain
+struct ChainView {
+  int N = 0;
+  int p = 2;
+  std::vector<const double*> core;
+  std::vector<int> caps;  // N + 1
+};
+ChainView view(const tt_tt* t);
+ChainView view_sites(const tt_tt* t, int first, int count);  // sub-chain (bond caps as stored)
+
+// list of enqueue operations with the workspaces they use
+struct Plan {
+  std::vector<std::function<void(hipStream_t)>> ops;
+  std::vector<std::unique_ptr<DevBuf>> bufs;
+  double* alloc(size_t n_doubles) {
+    bufs.emplace_back(new DevBuf(std::max<size_t>(n_doubles, 1) * sizeof(double)));
+    return bufs.back()->d();
+  }
+  template <class T>
+  T* upload(const std::vector<T>& host) {
+    bufs.emplace_back(new DevBuf(std::max<size_t>(host.size(), 1) * sizeof(T)));
+    if (!host.empty()) rt::copy(bufs.back()->p, host.data(), host.size() * sizeof(T));
+    return static_cast<T*>(bufs.back()->p);
+  }
+  void add(std::function<void(hipStream_t)> f) { ops.push_back(std::move(f)); }
+  void run(hipStream_t s) const {
+    for (auto& f : ops) f(s);
+  }
+};
+
+struct SketchTerm {
+  double coef = 1.0;
+  const ChainView* mpo = nullptr;  // nullptr: identity
+  ChainView x;
+};
+
+// Output of a rounding: destination cores (caps chi_n) and, for reporting,
+// the eigenvalues of every bond's Gram matrix.
+struct RoundTarget {
+  std::vector<double*> core;
+  std::vector<int> caps;
+  double* lam = nullptr;  // (N+1) x ldl eigenvalues (optional, filled by the planner)
+  int ldl = 0;
+};
+
+// randomized range finding (right sketches + QR sweep) into an ell-rank
+// left-orthogonal chain, then simultaneous SVD truncation to target.caps
+void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const ChainView& Z,
+                       RoundTarget& target, Prec prec);
+// LQ sweep + QR sweep + simultaneous truncation of an explicit chain
+void plan_round_det(Plan& plan, const ChainView& x, RoundTarget& target);
+// QR sweep only: left-orthogonal copy (returns caps of the result); used for norms
+struct LeftOrth {
+  std::vector<double*> core;
+  std::vector<int> caps;
+};
+LeftOrth plan_left_orth(Plan& plan, const ChainView& x);
+// block-diagonal sum into dst (dst caps must equal the sums of the term caps)
+void plan_axpby(Plan& plan, const std::vector<std::pair<double, ChainView>>& terms, tt_tt* dst);
+// <a, b> environment chain; result in *out_dev (device scalar)
+void plan_inner(Plan& plan, const ChainView& a, const ChainView& b, double* out_dev);
+// contraction of the first sites of x with a weight chain w (right bond = channels);
+// result E (channels x cap of x after the last contracted site) in out_dev
+void plan_partial(Plan& plan, const ChainView& w, const ChainView& x, double* out_dev);
+
+}  // namespace qtt

@@ -1,0 +1,561 @@
+// Launch planners of the MPS arithmetic: randomized range finding with right
+// partial sketches, Householder QR sweeps, simultaneous SVD truncation of all
+// bonds from their Gram matrices, block-diagonal sums, environment chains.
+//
+// Every planner appends enqueue operations to a Plan and allocates the
+// workspaces it needs at planning time, so that a plan can be replayed many
+// times (eagerly or captured as a HIP graph) without allocations.
+#include <algorithm>
+
+#include "library.h"
+
+namespace qtt {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+std::vector<int> chain_caps(int N, long cap) {
+  std::vector<int> c(N + 1);
+  for (int n = 0; n <= N; ++n) {
+    long a = (n < 40) ? (1L << n) : (1L << 40);
+    long b = (N - n < 40) ? (1L << (N - n)) : (1L << 40);
+    c[n] = (int)std::min(cap, std::min(a, b));
+  }
+  return c;
+}
+
+std::unique_ptr<tt_tt> make_tt(tt_ctx* ctx, int kind, int N, const std::vector<int>& caps) {
+  QTT_REQUIRE(N >= 1 && (int)caps.size() == N + 1, "bad chain length");
+  QTT_REQUIRE(caps[0] == 1 && caps[N] == 1, "boundary bonds must be 1");
+  auto t = std::make_unique<tt_tt>();
+  t->ctx = ctx;
+  t->kind = kind;
+  t->N = N;
+  t->p = (kind == TT_MPO) ? 4 : 2;
+  t->caps = caps;
+  t->off.assign(N + 1, 0);
+  for (int n = 0; n < N; ++n) {
+    QTT_REQUIRE(caps[n] >= 1 && caps[n + 1] >= 1, "bond capacities must be >= 1");
+    t->off[n + 1] = t->off[n] + (int64_t)caps[n] * t->p * caps[n + 1];
+  }
+  t->buf.alloc((size_t)t->off[N] * sizeof(double));
+  return t;
+}
+
+ChainView view(const tt_tt* t) {
+  ChainView v;
+  v.N = t->N;
+  v.p = t->p;
+  v.caps = t->caps;
+  for (int n = 0; n < t->N; ++n) v.core.push_back(t->core(n));
+  return v;
+}
+
+ChainView view_sites(const tt_tt* t, int first, int count) {
+  ChainView v;
+  v.N = count;
+  v.p = t->p;
+  for (int n = 0; n < count; ++n) v.core.push_back(t->core(first + n));
+  for (int n = 0; n <= count; ++n) v.caps.push_back(t->caps[first + n]);
+  return v;
+}
+
+static Mode2 M1(int64_t s) { return mode1(s); }
+static Mode2 M2(int n2, int64_t s1, int64_t s2) { return mode2(n2, s1, s2); }
+
+static void add_tc(Plan& plan, TcDesc d, Prec p) {
+  plan.add([d, p](hipStream_t s) { tc_launch(d, p, s); });
+}
+
+static void add_gemm(Plan& plan, int M, int N, int K, const double* A, int64_t lda, bool ta,
+                     const double* B, int64_t ldb, bool tb, double* C, int64_t ldc, double alpha,
+                     double beta, Prec p) {
+  add_tc(plan, gemm_desc(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, alpha, beta), p);
+}
+
+// ---------------------------------------------------------------------------
+// simultaneous truncation of a left-orthogonal chain X (caps ell) to the
+// target caps: right Gram chain, batched eigen-decompositions, P^T X P
+// ---------------------------------------------------------------------------
+static void plan_trunc_gram(Plan& plan, const std::vector<double*>& X, const std::vector<int>& ell,
+                            RoundTarget& tg) {
+  const int N = (int)X.size();
+  QTT_REQUIRE((int)tg.caps.size() == N + 1 && (int)tg.core.size() == N, "truncation target shape");
+  int lmax = 1, cmax = 1;
+  for (int n = 0; n <= N; ++n) {
+    lmax = std::max(lmax, ell[n]);
+    cmax = std::max(cmax, tg.caps[n]);
+  }
+  const int ldg = lmax, ldp = cmax;
+  double* Gam = plan.alloc((size_t)(N + 1) * ldg * ldg);
+  double* P = plan.alloc((size_t)(N + 1) * ldg * ldp);
+  double* lam = plan.alloc((size_t)(N + 1) * ldg);
+  double* ework = plan.alloc((size_t)std::max(1, N - 1) * 2 * ldg * ldg);
+  size_t tsz = 1, vsz = 1;
+  for (int n = 0; n < N; ++n) {
+    tsz = std::max(tsz, (size_t)2 * ell[n] * ell[n + 1]);
+    vsz = std::max(vsz, (size_t)tg.caps[n] * 2 * ell[n + 1]);
+  }
+  double* Tg = plan.alloc(tsz);
+  double* V1 = plan.alloc(vsz);
+  std::vector<int> dims, keep;
+  for (int n = 1; n < N; ++n) {
+    dims.push_back(ell[n]);
+    keep.push_back(std::min(ell[n], tg.caps[n]));
+  }
+  int* d_dims = plan.upload(dims);
+  int* d_keep = plan.upload(keep);
+  tg.lam = lam;
+  tg.ldl = ldg;
+  const size_t psz = (size_t)(N + 1) * ldg * ldp;
+  plan.add([P, psz, lam, N, ldg](hipStream_t s) {
+    fill(P, (int64_t)psz, 0.0, s);
+    fill(lam, (int64_t)(N + 1) * ldg, 0.0, s);
+  });
+  auto G = [&](int n) { return Gam + (size_t)n * ldg * ldg; };
+  auto Pn = [&](int n) { return P + (size_t)n * ldg * ldp; };
+  if (N >= 2) {
+    int l = ell[N - 1];
+    add_gemm(plan, l, l, 2, X[N - 1], 2, false, X[N - 1], 2, true, G(N - 1), ldg, 1.0, 0.0, Prec::F64);
+    for (int n = N - 2; n >= 1; --n) {
+      int a = ell[n], b = ell[n + 1];
+      add_gemm(plan, 2 * a, b, b, X[n], b, false, G(n + 1), ldg, false, Tg, b, 1.0, 0.0, Prec::F64);
+      add_gemm(plan, a, a, 2 * b, Tg, 2 * b, false, X[n], 2 * b, true, G(n), ldg, 1.0, 0.0, Prec::F64);
+    }
+    double* g1 = G(1);
+    double* p1 = Pn(1);
+    double* l1 = lam + ldg;
+    int cnt = N - 1;
+    plan.add([=](hipStream_t s) {
+      eig_launch(cnt, d_dims, d_keep, g1, (int64_t)ldg * ldg, ldg, p1, (int64_t)ldg * ldp, ldp, l1,
+                 ldg, ework, lmax, s);
+    });
+  }
+  // new cores P_n^T X_n P_{n+1}
+  for (int n = 0; n < N; ++n) {
+    int l = ell[n], lr = ell[n + 1], c = tg.caps[n], cr = tg.caps[n + 1];
+    if (N == 1) {
+      double* dst = tg.core[0];
+      const double* src = X[0];
+      plan.add([=](hipStream_t s) {
+        rt::copy_async(dst, src, 2 * sizeof(double), s);
+      });
+    } else if (n == 0) {
+      add_gemm(plan, 2, cr, lr, X[0], lr, false, Pn(1), ldp, false, tg.core[0], cr, 1.0, 0.0, Prec::F64);
+    } else if (n == N - 1) {
+      add_gemm(plan, c, 2, l, Pn(n), ldp, true, X[n], 2, false, tg.core[n], 2, 1.0, 0.0, Prec::F64);
+    } else {
+      add_gemm(plan, c, 2 * lr, l, Pn(n), ldp, true, X[n], 2 * lr, false, V1, 2 * lr, 1.0, 0.0, Prec::F64);
+      add_gemm(plan, 2 * c, cr, lr, V1, lr, false, Pn(n + 1), ldp, false, tg.core[n], cr, 1.0, 0.0,
+               Prec::F64);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// randomized range finding of Y = sum_j c_j W_j x_j (right sketches with the
+// Gaussian TT Z, left-to-right QR sweep of the sketched unfoldings), then
+// simultaneous truncation.
+// ---------------------------------------------------------------------------
+void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const ChainView& Z,
+                       RoundTarget& tg, Prec prec) {
+  const int N = Z.N;
+  const int J = (int)terms.size();
+  QTT_REQUIRE(J >= 1, "rounding needs at least one term");
+  const std::vector<int>& ell = Z.caps;
+  for (int n = 0; n < N; ++n)
+    QTT_REQUIRE(ell[n + 1] <= 2 * ell[n], "sketch ranks must satisfy ell_{n+1} <= 2 ell_n");
+  struct TermShape {
+    std::vector<int> r, D;
+  };
+  std::vector<TermShape> sh(J);
+  for (int j = 0; j < J; ++j) {
+    QTT_REQUIRE(terms[j].x.N == N, "term length differs from the sketch");
+    sh[j].r = terms[j].x.caps;
+    if (terms[j].mpo) {
+      QTT_REQUIRE(terms[j].mpo->N == N, "operator length differs from the sketch");
+      sh[j].D = terms[j].mpo->caps;
+    } else {
+      sh[j].D.assign(N + 1, 1);
+    }
+  }
+  // workspaces
+  size_t t1 = 1, t2 = 1, msz = 1, u1 = 1, csz = 1, ssz = 1;
+  for (int j = 0; j < J; ++j)
+    for (int n = 0; n < N; ++n) {
+      const auto& r = sh[j].r;
+      const auto& D = sh[j].D;
+      t1 = std::max(t1, (size_t)r[n + 1] * D[n + 1] * 2 * ell[n]);
+      t2 = std::max(t2, (size_t)2 * D[n] * r[n + 1] * ell[n]);
+      msz = std::max(msz, (size_t)ell[n] * r[n] * D[n]);
+      u1 = std::max(u1, (size_t)ell[n] * D[n] * 2 * r[n + 1]);
+      csz = std::max(csz, (size_t)ell[n] * 2 * r[n + 1] * D[n + 1]);
+      ssz = std::max(ssz, (size_t)2 * ell[n] * ell[n + 1]);
+    }
+  double* T1 = plan.alloc(t1);
+  double* T2 = plan.alloc(t2);
+  double* U1 = plan.alloc(u1);
+  double* S = plan.alloc(ssz);
+  double* qrw = plan.alloc(ssz);
+  double* one = plan.upload(std::vector<double>{1.0});
+  std::vector<std::vector<double*>> R(J, std::vector<double*>(N + 1, nullptr));
+  std::vector<double*> Ma(J), Mb(J), Cb(J);
+  for (int j = 0; j < J; ++j) {
+    for (int n = 1; n < N; ++n) R[j][n] = plan.alloc((size_t)sh[j].r[n] * sh[j].D[n] * ell[n]);
+    R[j][N] = one;
+    Ma[j] = plan.alloc(msz);
+    Mb[j] = plan.alloc(msz);
+    Cb[j] = plan.alloc(csz);
+  }
+  std::vector<double*> X(N);
+  for (int n = 0; n < N; ++n) X[n] = plan.alloc((size_t)ell[n] * 2 * ell[n + 1]);
+
+  // ---- right partial sketches R_j[n] = Right_n(Y_j) Right_n(Z)^T
+  for (int j = 0; j < J; ++j) {
+    const auto& r = sh[j].r;
+    const auto& D = sh[j].D;
+    const ChainView* W = terms[j].mpo;
+    for (int n = N - 1; n >= 1; --n) {
+      const int l = ell[n], lp = ell[n + 1], rn = r[n], rp = r[n + 1], Dn = D[n], Dp = D[n + 1];
+      {  // T1[(b,beta),(t,z)] = sum_z' R[(b,beta),z'] Z_n[z,t,z']
+        TcDesc d;
+        d.M = rp * Dp;
+        d.N = 2 * l;
+        d.K = lp;
+        d.A = R[j][n + 1];
+        d.am = M1(lp);
+        d.ak = M1(1);
+        d.B = Z.core[n];
+        d.bk = M1(1);
+        d.bn = M2(l, lp, 2 * lp);
+        d.C = T1;
+        d.cm = M1(2 * l);
+        d.cn = M1(1);
+        d.ab = d.bb = d.cb = M1(0);
+        add_tc(plan, d, prec);
+      }
+      if (W) {
+        {  // T2[(alpha,s), b, z] = sum_(beta,t) W[alpha,t,s,beta] T1[(b,beta),(t,z)], batch b
+          TcDesc d;
+          d.batch = rp;
+          d.M = 2 * Dn;
+          d.K = 2 * Dp;
+          d.N = l;
+          d.A = W->core[n];
+          d.am = M2(2, 4 * Dp, Dp);
+          d.ak = M2(2, 1, 2 * Dp);
+          d.ab = M1(0);
+          d.B = T1;
+          d.bk = M2(2, 2 * l, l);
+          d.bn = M1(1);
+          d.bb = M1((int64_t)Dp * 2 * l);
+          d.C = T2;
+          d.cm = M1((int64_t)rp * l);
+          d.cn = M1(1);
+          d.cb = M1(l);
+          add_tc(plan, d, prec);
+        }
+        {  // R[(a,alpha),z] = sum_(s,b) x[a,s,b] T2[alpha,s,b,z], batch alpha
+          TcDesc d;
+          d.batch = Dn;
+          d.M = rn;
+          d.K = 2 * rp;
+          d.N = l;
+          d.A = terms[j].x.core[n];
+          d.am = M1(2 * rp);
+          d.ak = M1(1);
+          d.ab = M1(0);
+          d.B = T2;
+          d.bk = M1(l);
+          d.bn = M1(1);
+          d.bb = M1((int64_t)2 * rp * l);
+          d.C = R[j][n];
+          d.cm = M1((int64_t)Dn * l);
+          d.cn = M1(1);
+          d.cb = M1(l);
+          add_tc(plan, d, prec);
+        }
+      } else {
+        // R[a,z] = sum_(s,b) x[a,s,b] T1[b,(s,z)]
+        TcDesc d;
+        d.M = rn;
+        d.K = 2 * rp;
+        d.N = l;
+        d.A = terms[j].x.core[n];
+        d.am = M1(2 * rp);
+        d.ak = M1(1);
+        d.B = T1;
+        d.bk = M2(rp, l, 2 * l);
+        d.bn = M1(1);
+        d.C = R[j][n];
+        d.cm = M1(l);
+        d.cn = M1(1);
+        d.ab = d.bb = d.cb = M1(0);
+        add_tc(plan, d, prec);
+      }
+    }
+  }
+
+  // ---- left-to-right sweep
+  std::vector<double*> Mcur(J, one), Mnext = Mb;
+  for (int n = 0; n < N; ++n) {
+    const bool last = (n == N - 1);
+    const int l = ell[n], lp = ell[n + 1];
+    for (int j = 0; j < J; ++j) {
+      const auto& r = sh[j].r;
+      const auto& D = sh[j].D;
+      const int rn = r[n], rp = r[n + 1], Dn = D[n], Dp = D[n + 1];
+      const ChainView* W = terms[j].mpo;
+      double* Cdst = last ? X[N - 1] : Cb[j];
+      const double alpha = last ? terms[j].coef : 1.0;
+      const double beta = (last && j > 0) ? 1.0 : 0.0;
+      if (W) {
+        {  // U1[k,alpha,s,b] = sum_a M[k,(a,alpha)] x[a,s,b], batch alpha
+          TcDesc d;
+          d.batch = Dn;
+          d.M = l;
+          d.K = rn;
+          d.N = 2 * rp;
+          d.A = Mcur[j];
+          d.am = M1((int64_t)rn * Dn);
+          d.ak = M1(Dn);
+          d.ab = M1(1);
+          d.B = terms[j].x.core[n];
+          d.bk = M1(2 * rp);
+          d.bn = M1(1);
+          d.bb = M1(0);
+          d.C = U1;
+          d.cm = M1((int64_t)2 * Dn * rp);
+          d.cn = M1(1);
+          d.cb = M1(2 * rp);
+          add_tc(plan, d, prec);
+        }
+        {  // C[k,t,b,beta] = sum_(alpha,s) U1[k,alpha,s,b] W[alpha,t,s,beta]
+          TcDesc d;
+          d.M = l * rp;
+          d.K = 2 * Dn;
+          d.N = 2 * Dp;
+          d.A = U1;
+          d.am = M2(rp, (int64_t)2 * Dn * rp, 1);
+          d.ak = M1(rp);
+          d.B = W->core[n];
+          d.bk = M2(2, 4 * Dp, Dp);
+          d.bn = M2(Dp, 2 * Dp, 1);
+          d.C = Cdst;
+          d.cm = M2(rp, (int64_t)2 * rp * Dp, Dp);
+          d.cn = M2(Dp, (int64_t)rp * Dp, 1);
+          d.ab = d.bb = d.cb = M1(0);
+          d.alpha = alpha;
+          d.beta = beta;
+          add_tc(plan, d, prec);
+        }
+      } else {
+        add_gemm(plan, l, 2 * rp, rn, Mcur[j], rn, false, terms[j].x.core[n], 2 * rp, false, Cdst,
+                 2 * rp, alpha, beta, prec);
+      }
+    }
+    if (last) break;
+    // S = sum_j c_j C_j R_j[n+1]
+    for (int j = 0; j < J; ++j) {
+      const int rp = sh[j].r[n + 1], Dp = sh[j].D[n + 1];
+      add_gemm(plan, 2 * l, lp, rp * Dp, Cb[j], (int64_t)rp * Dp, false, R[j][n + 1], lp, false, S,
+               lp, terms[j].coef, j > 0 ? 1.0 : 0.0, prec);
+    }
+    {
+      double* Xn = X[n];
+      const int m = 2 * l, nc = lp;
+      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, S, 0, nc, 1, Xn, 0, nullptr, 0, qrw, s); });
+    }
+    for (int j = 0; j < J; ++j) {
+      const int rp = sh[j].r[n + 1], Dp = sh[j].D[n + 1];
+      add_gemm(plan, lp, rp * Dp, 2 * l, X[n], lp, true, Cb[j], (int64_t)rp * Dp, false, Mnext[j],
+               (int64_t)rp * Dp, 1.0, 0.0, prec);
+    }
+    for (int j = 0; j < J; ++j) {
+      double* old = Mcur[j];
+      Mcur[j] = Mnext[j];
+      Mnext[j] = (old == one) ? Ma[j] : old;
+    }
+  }
+  plan_trunc_gram(plan, X, ell, tg);
+}
+
+// ---------------------------------------------------------------------------
+// deterministic sweeps
+// ---------------------------------------------------------------------------
+LeftOrth plan_left_orth(Plan& plan, const ChainView& x) {
+  const int N = x.N;
+  LeftOrth out;
+  out.caps.assign(N + 1, 1);
+  out.core.assign(N, nullptr);
+  // cur: the core at site n after absorbing the factor from the left
+  const double* cur = x.core[0];
+  int cl = 1;  // left cap of cur
+  size_t wsz = 1;
+  for (int n = 0; n < N; ++n) wsz = std::max(wsz, (size_t)2 * 2 * x.caps[n] * std::max(x.caps[n + 1], 1));
+  for (int n = 0; n < N; ++n) {
+    const int cr = x.caps[n + 1];
+    if (n == N - 1) {
+      double* dst = plan.alloc((size_t)cl * 2 * cr);
+      const double* src = cur;
+      size_t bytes = (size_t)cl * 2 * cr * sizeof(double);
+      plan.add([=](hipStream_t s) {
+        rt::copy_async(dst, src, bytes, s);
+      });
+      out.core[n] = dst;
+      out.caps[n] = cl;
+      break;
+    }
+    const int m = 2 * cl;
+    const int cnr = x.caps[n + 2];
+    int knew;
+    double* Q;
+    double* next;
+    if (m >= cr) {
+      knew = cr;
+      Q = plan.alloc((size_t)m * cr);
+      double* Rm = plan.alloc((size_t)cr * cr);
+      double* work = plan.alloc((size_t)m * cr);
+      plan.add([=](hipStream_t s) { qr_launch(1, m, cr, cur, 0, cr, 1, Q, 0, Rm, 0, work, s); });
+      next = plan.alloc((size_t)knew * 2 * cnr);
+      add_gemm(plan, knew, 2 * cnr, cr, Rm, cr, false, x.core[n + 1], 2 * cnr, false, next, 2 * cnr,
+               1.0, 0.0, Prec::F64);
+    } else {
+      knew = m;
+      Q = plan.alloc((size_t)m * m);
+      plan.add([=](hipStream_t s) { eye(Q, m, s); });
+      next = plan.alloc((size_t)knew * 2 * cnr);
+      add_gemm(plan, m, 2 * cnr, cr, cur, cr, false, x.core[n + 1], 2 * cnr, false, next, 2 * cnr,
+               1.0, 0.0, Prec::F64);
+    }
+    out.core[n] = Q;
+    out.caps[n] = cl;
+    out.caps[n + 1] = knew;
+    cur = next;
+    cl = knew;
+  }
+  out.caps[N] = 1;
+  (void)wsz;
+  return out;
+}
+
+void plan_round_det(Plan& plan, const ChainView& x, RoundTarget& tg) {
+  const int N = x.N;
+  // LQ sweep right to left -> right-orthogonal chain with caps c'
+  std::vector<double*> rc(N, nullptr);
+  std::vector<int> caps(N + 1, 1);
+  const double* cur = x.core[N - 1];
+  int cr = 1;  // right cap of cur
+  for (int n = N - 1; n >= 1; --n) {
+    const int cl = x.caps[n];
+    const int cols = 2 * cr;
+    const int cll = x.caps[n - 1];
+    double* next = plan.alloc((size_t)cll * 2 * std::min(cl, cols));
+    if (cl <= cols) {
+      // A (cl x cols) = L Q from the QR of A^T (cols x cl)
+      double* Qt = plan.alloc((size_t)cols * cl);
+      double* Rm = plan.alloc((size_t)cl * cl);
+      double* work = plan.alloc((size_t)cols * cl);
+      double* core = plan.alloc((size_t)cl * cols);
+      const double* A = cur;
+      plan.add([=](hipStream_t s) {
+        qr_launch(1, cols, cl, A, 0, 1, cols, Qt, 0, Rm, 0, work, s);
+        transpose(Qt, cols, cl, core, s);
+      });
+      // left neighbour absorbs L = R^T
+      add_gemm(plan, 2 * cll, cl, cl, x.core[n - 1], cl, false, Rm, cl, true, next, cl, 1.0, 0.0,
+               Prec::F64);
+      rc[n] = core;
+      caps[n] = cl;
+    } else {
+      double* core = plan.alloc((size_t)cols * cols);
+      plan.add([=](hipStream_t s) { eye(core, cols, s); });
+      add_gemm(plan, 2 * cll, cols, cl, x.core[n - 1], cl, false, cur, cols, false, next, cols, 1.0,
+               0.0, Prec::F64);
+      rc[n] = core;
+      caps[n] = cols;
+    }
+    cur = next;
+    cr = caps[n];
+  }
+  rc[0] = const_cast<double*>(cur);
+  caps[0] = 1;
+  ChainView rv;
+  rv.N = N;
+  rv.p = 2;
+  rv.caps = caps;
+  for (int n = 0; n < N; ++n) rv.core.push_back(rc[n]);
+  LeftOrth lo = plan_left_orth(plan, rv);
+  plan_trunc_gram(plan, lo.core, lo.caps, tg);
+}
+
+// ---------------------------------------------------------------------------
+// block-diagonal sums and environment chains
+// ---------------------------------------------------------------------------
+void plan_axpby(Plan& plan, const std::vector<std::pair<double, ChainView>>& terms, tt_tt* dst) {
+  const int N = dst->N;
+  std::vector<CopyJob> jobs;
+  std::vector<int> ro(N + 1, 0);
+  int64_t maxe = 1;
+  for (auto& [c, x] : terms) {
+    QTT_REQUIRE(x.N == N, "axpby: chains differ in length");
+    for (int n = 0; n < N; ++n) {
+      CopyJob j{};
+      j.src = x.core[n];
+      j.dst = dst->core(n);
+      j.rl = x.caps[n];
+      j.sp = x.p;
+      j.rr = x.caps[n + 1];
+      j.dp = dst->p;
+      j.drr = dst->caps[n + 1];
+      j.ro = (n == 0) ? 0 : ro[n];
+      j.co = (n == N - 1) ? 0 : ro[n + 1];
+      j.diag = 0;
+      j.scale = (n == 0) ? c : 1.0;
+      j.dscale = nullptr;
+      jobs.push_back(j);
+      maxe = std::max<int64_t>(maxe, (int64_t)j.rl * j.sp * j.rr);
+    }
+    for (int n = 1; n < N; ++n) ro[n] += x.caps[n];
+  }
+  for (int n = 1; n < N; ++n)
+    QTT_REQUIRE(ro[n] <= dst->caps[n], "axpby: destination bond %d too small", n);
+  for (const CopyJob& j : jobs) validate(j);
+  CopyJob* dj = plan.upload(jobs);
+  double* base = dst->buf.d();
+  int64_t tot = dst->total();
+  int nj = (int)jobs.size();
+  plan.add([=](hipStream_t s) {
+    fill(base, tot, 0.0, s);
+    copy_jobs(dj, nj, maxe, s);
+  });
+}
+
+void plan_partial(Plan& plan, const ChainView& w, const ChainView& x, double* out_dev) {
+  const int Nw = w.N;
+  QTT_REQUIRE(x.N >= Nw, "partial contraction longer than the chain");
+  size_t esz = 1, tsz = 1;
+  for (int n = 0; n <= Nw; ++n) esz = std::max(esz, (size_t)w.caps[n] * x.caps[n]);
+  for (int n = 0; n < Nw; ++n) tsz = std::max(tsz, (size_t)w.caps[n] * 2 * x.caps[n + 1]);
+  double* Ea = plan.alloc(esz);
+  double* Eb = plan.alloc(esz);
+  double* T = plan.alloc(tsz);
+  double* one = plan.upload(std::vector<double>{1.0});
+  const double* E = one;
+  for (int n = 0; n < Nw; ++n) {
+    const int wl = w.caps[n], wr = w.caps[n + 1], xl = x.caps[n], xr = x.caps[n + 1];
+    // T[w, (s, R)] = sum_r E[w, r] x[r, s, R]
+    add_gemm(plan, wl, 2 * xr, xl, E, xl, false, x.core[n], 2 * xr, false, T, 2 * xr, 1.0, 0.0, Prec::F64);
+    double* En = (n == Nw - 1) ? out_dev : ((E == Ea) ? Eb : Ea);
+    // E'[W, R] = sum_(w,s) w[(w,s), W] T[(w,s), R]
+    add_gemm(plan, wr, xr, 2 * wl, w.core[n], wr, true, T, xr, false, En, xr, 1.0, 0.0, Prec::F64);
+    E = En;
+  }
+}
+
+void plan_inner(Plan& plan, const ChainView& a, const ChainView& b, double* out_dev) {
+  QTT_REQUIRE(a.N == b.N, "inner: chains differ in length");
+  plan_partial(plan, a, b, out_dev);
+}
+
+}  // namespace qtt

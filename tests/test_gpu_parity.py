@@ -1,0 +1,198 @@
+"""HIP path vs the CPU oracle, element by element on seeded inputs (needs an MI355X).
+
+Tolerances (FP64 path): operator construction and exact arithmetic agree to
+1e-12 relative (rounding only); truncated roundings agree to 1e-9 relative --
+both sides compute the same truncation, but the leading eigenvectors of a
+bond's Gram matrix are only determined to about eps * lambda_1 / gap, which
+for the spectra of these tests stays below 1e-10.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import dense, stepper, tt
+from tests.helpers import full, gaussian_sketch, random_tt, rel, truncation_sensitivity
+
+q = pytest.importorskip("paper_2407_09169_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = q.Context(0)
+    yield c
+    c.close()
+
+
+def _dense_of(st, cores):
+    return st.to_dense([np.asarray(G) for G in cores])
+
+
+# ----------------------------------------------------------------------------- a1
+@pytest.mark.parametrize("bits", [3, 5])
+@pytest.mark.parametrize("op", ["D1G", "D2G", "D1P", "D2P", "PHI", "D1G_PHI"])
+def test_mpo_build_1d_operators(ctx, op, bits):
+    M = 1 << bits
+    ref = {"D1G": dense.d1_ghost(M), "D2G": dense.d2_ghost(M), "D1P": dense.d1_periodic(M),
+           "D2P": dense.d2_periodic(M), "PHI": np.diag(dense.phi_nodes(M)),
+           "D1G_PHI": dense.d1_ghost(M) @ np.diag(dense.phi_nodes(M))}[op]
+    W, mb = q.mpo_build(ctx, 1, bits, q.TT_SERIAL, [(1.0, {0: op}, -1)])
+    A = tt.mpo_full(W.cores())
+    assert np.max(np.abs(A - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert mb <= {"D1G": 5, "D2G": 5, "D1P": 3, "D2P": 3, "PHI": 2, "D1G_PHI": 6}[op]
+
+
+@pytest.mark.parametrize("ordering", ["serial", "interleaved"])
+def test_mpo_build_two_dims(ctx, ordering):
+    bits, M = 3, 8
+    o = q.TT_SERIAL if ordering == "serial" else q.TT_INTERLEAVED
+    W, _ = q.mpo_build(ctx, 2, bits, o, [(0.7, {0: "D1G_PHI"}, -1), (-1.3, {0: "PHI", 1: "D2G"}, -1)])
+    order = ([(d, b) for d in range(2) for b in range(bits)] if o == q.TT_SERIAL
+             else [(d, b) for b in range(bits) for d in range(2)])
+    I = np.eye(M)
+    K = 0.7 * np.kron(dense.d1_ghost(M) @ np.diag(dense.phi_nodes(M)), I) \
+        - 1.3 * np.kron(np.diag(dense.phi_nodes(M)), dense.d2_ghost(M))
+    perm = tt.site_perm(order, bits)
+    N = 2 * bits
+    Kp = K.reshape((2,) * (2 * N)).transpose(perm + [N + p for p in perm]).reshape(1 << N, 1 << N)
+    assert np.max(np.abs(tt.mpo_full(W.cores()) - Kp)) <= 1e-12 * np.max(np.abs(Kp))
+
+
+# ------------------------------------------------------------------- inputs
+@pytest.mark.parametrize("name", ["c1_2d_M64", "t_5d_M8_exact", "t_5d_M8_chi16"])
+def test_from_separable_matches_oracle(ctx, name):
+    w = workloads.get_workload(name)
+    st = stepper.MPSStepper(w)
+    ordering = q.TT_SERIAL if w.ordering == "serial" else q.TT_INTERLEAVED
+    f = q.from_separable(ctx, w.ndims, w.bits, ordering, workloads.ic_terms(w), w.chi)
+    fo, info = st.initial_state(with_info=True)
+    tol = 1e-12 + 100 * truncation_sensitivity([info])
+    assert rel(_dense_of(st, f.cores()), st.to_dense(fo)) < tol
+    if w.ndims == 5:
+        xo = st._x_order()
+        for comp, Uo in zip(workloads.velocity_terms(w), st.U):
+            u = q.from_separable(ctx, 3, w.bits, q.TT_SERIAL, comp, w.vel_rank)
+            du = tt.sites_to_dense(full(u.cores()), xo, w.bits, 3)
+            assert rel(du, tt.sites_to_dense(tt.tt_full(Uo), xo, w.bits, 3)) < 1e-11
+
+
+# ----------------------------------------------------------------- a3, a4
+def _random_mpo(N, D, seed):
+    rng = np.random.default_rng(seed)
+    caps = [1] + [D] * (N - 1) + [1]
+    return [rng.standard_normal((caps[n], 2, 2, caps[n + 1])) for n in range(N)]
+
+
+def test_apply_and_axpby(ctx):
+    Wc = _random_mpo(8, 3, 10)
+    W = q.TT.from_cores(ctx, Wc, kind=q.TT_MPO)
+    xc = random_tt([1, 2, 4, 8, 8, 8, 4, 2, 1], 11)
+    yc = random_tt([1, 2, 3, 5, 6, 5, 3, 2, 1], 12)
+    x = q.TT.from_cores(ctx, xc)
+    y = q.TT.from_cores(ctx, yc)
+    Wx = q.apply_mpo(ctx, W, x)
+    ref = tt.mpo_full(Wc) @ full(xc).reshape(-1)
+    assert rel(full(Wx.cores()).reshape(-1), ref) < 1e-13
+    s = q.axpby(ctx, [0.3, -2.0], [x, y])
+    assert rel(full(s.cores()), 0.3 * full(xc) - 2.0 * full(yc)) < 1e-14
+    ip = float(np.sum(full(xc) * full(yc)))
+    assert abs(q.inner(ctx, x, y) - ip) < 1e-12 * np.linalg.norm(full(xc)) * np.linalg.norm(full(yc))
+
+
+# --------------------------------------------------------------------- a5
+@pytest.mark.parametrize("chi", [3, 6, 64])
+def test_round_det_matches_oracle(ctx, chi):
+    xc = random_tt([1, 2, 4, 8, 16, 16, 8, 4, 2, 1], 21, decay=0.5)
+    x = q.TT.from_cores(ctx, xc)
+    r = q.round_det(ctx, x, chi)
+    ref, _ = tt.round_det(xc, chi)
+    assert rel(full(r.cores()), full(ref)) < 1e-10
+    if chi >= 16:
+        assert rel(full(r.cores()), full(xc)) < 1e-13
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-4), ("bf16", 3e-2)])
+def test_round_sketch_matches_oracle(ctx, dtype, tol):
+    N = 10
+    Wc = _random_mpo(N, 3, 30)
+    xc = random_tt([1, 2, 4, 8, 16, 24, 16, 8, 4, 2, 1], 31, decay=0.7)
+    yc = random_tt([1, 2, 4, 8, 12, 12, 12, 8, 4, 2, 1], 32, decay=0.7)
+    Z, ell = gaussian_sketch(N, 20, 33)
+    chi = 12
+    ref, _ = tt.round_sketch([(1.0, Wc, xc), (-0.25, Wc, yc), (3.0, None, xc)], Z, ell, chi)
+    W = q.TT.from_cores(ctx, Wc, kind=q.TT_MPO)
+    x, y = q.TT.from_cores(ctx, xc), q.TT.from_cores(ctx, yc)
+    sk = q.TT.from_cores(ctx, Z)
+    out = q.round_sketch(ctx, [1.0, -0.25, 3.0], [W, W, None], [x, y, x], sk, chi, dtype)
+    assert rel(full(out.cores()), full(ref)) < tol
+
+
+# --------------------------------------------------------------- a6 step
+@pytest.mark.parametrize("name,integrator", [("t_5d_M8_exact", "rk4"), ("c1_2d_M64_exact", "rk2")])
+def test_step_untruncated_equals_dense(ctx, name, integrator):
+    w = workloads.get_workload(name, integrator=integrator)
+    st = stepper.MPSStepper(w)
+    prob, f = q.setup_workload(ctx, w, "f64")
+    P = st.dense_problem()
+    fd = dense.dense_from_terms(workloads.ic_terms(w), w.ndims, w.M)
+    for _ in range(3):
+        prob.step(f, 1)
+        fd = P.step(fd, w.dt, integrator)
+        assert rel(_dense_of(st, f.cores()), fd) < 1e-11
+
+
+@pytest.mark.parametrize("name,integrator", [("t_5d_M8_chi16", "rk4"), ("c1_2d_M64", "rk4"),
+                                             ("t_2d_M64_serial", "rk2")])
+def test_step_truncated_matches_oracle(ctx, name, integrator):
+    w = workloads.get_workload(name, integrator=integrator)
+    st = stepper.MPSStepper(w)
+    prob, f = q.setup_workload(ctx, w, "f64")
+    fo = st.initial_state()
+    for _ in range(3):
+        prob.step(f, 1)
+        fo, _ = st.step(fo)
+        assert rel(_dense_of(st, f.cores()), st.to_dense(fo)) < 1e-9
+    obs_o = st.observables(fo)
+    for k, v in obs_o.items():
+        assert abs(prob.observable(f, k) - v) <= 1e-9 * max(1.0, abs(v)), k
+
+
+def test_step_graph_replay_is_deterministic(ctx):
+    """Replays of the recorded step graph give bitwise identical results to an
+    eager run of the same plan (several replays, eager work in between)."""
+    import os
+    w = workloads.get_workload("t_5d_M8_chi16")
+    prob, f = q.setup_workload(ctx, w, "f64")
+    prob2, g = q.setup_workload(ctx, w, "f64")
+    for i in range(3):
+        prob.step(f, 1)
+        os.environ["QTTPDF_NO_GRAPH"] = "1"
+        try:
+            prob2.step(g, 1)
+        finally:
+            del os.environ["QTTPDF_NO_GRAPH"]
+        assert np.array_equal(np.concatenate([c.ravel() for c in f.cores()]),
+                              np.concatenate([c.ravel() for c in g.cores()]))
+
+
+def test_l2_diff(ctx):
+    xc = random_tt([1, 2, 4, 8, 4, 2, 1], 41)
+    yc = [c.copy() for c in xc]
+    yc[3] = yc[3] * (1 + 1e-9)
+    x, y = q.TT.from_cores(ctx, xc), q.TT.from_cores(ctx, yc)
+    ref = rel(full(xc), full(yc))
+    assert abs(q.l2_diff(ctx, x, y) - ref) <= 1e-6 * ref
+
+
+def test_mean_field_matches_oracle(ctx):
+    w = workloads.get_workload("t_5d_M8_exact")
+    st = stepper.MPSStepper(w)
+    prob, f = q.setup_workload(ctx, w, "f64")
+    fo = st.initial_state()
+    xo = st._x_order()
+    for a in (0, 1):
+        m = prob.mean_field(f, a)
+        md = tt.sites_to_dense(full(m.cores()), xo, w.bits, 3)
+        mo = tt.sites_to_dense(tt.tt_full(st.mean_field_raw(fo, a)), xo, w.bits, 3)
+        assert rel(md, mo) < 1e-13

@@ -81,9 +81,9 @@ _W = [
              omega=1.0, k_react=0.0, dt=1e-3, steps=200, seed=1),
     # 5-D PDF, M = 1024, 50 serial cores, chi = 128 / 256, reaction k = 10.
     Workload("c3_5d_M1024_chi128", ndims=5, bits=10, ordering="serial", chi=128, oversample=16,
-             omega=1.0, k_react=10.0, dt=3e-5, steps=50, seed=2),
+             chi_mean=8, omega=1.0, k_react=10.0, dt=3e-5, steps=50, seed=2),
     Workload("c3_5d_M1024_chi256", ndims=5, bits=10, ordering="serial", chi=256, oversample=32,
-             omega=1.0, k_react=10.0, dt=3e-5, steps=50, seed=2),
+             chi_mean=8, omega=1.0, k_react=10.0, dt=3e-5, steps=50, seed=2),
     # Small 5-D cases that a dense full-grid solver can follow (tests).
     Workload("t_5d_M8_exact", ndims=5, bits=3, ordering="serial", chi=128, oversample=0,
              chi_mean=64, oversample_mean=0, vel_rank=64,
