@@ -1,0 +1,174 @@
+"""QTT Fokker-Planck time steps per second on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype bf16|f32|f64]
+                    [--workload c3_5d_M1024_chi128] [--no-cpu-baseline]
+
+A step is one full RK4 step (4 stage evaluations with their mean-field
+updates and roundings, plus the rounded stage combination) of the 5-D PDF on
+the 1024^5 grid (50 quantics cores) at chi = 128, with synthetic seeded
+inputs (workloads.c3_5d_M1024_chi128).  Inputs are resident in HBM before the
+timed region.  The MFMA path (BF16 by default) and the plain FP64 path run the
+same schedule from the same initial state; the line reports the MFMA path's
+steps/s as `value`, the FP64 path's steps/s and the L2 distance between the
+two states after the run.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "QTT time steps/sec, 5D PDF chi=128 (MFMA FP32/BF16 vs FP64 plain) at L2 err"
+PEAKS_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f64": 78.6}
+HBM_GBS = 8000.0
+
+
+def _time_steps(torch, prob, f, K):
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    prob.step(f, K)
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1)
+
+
+def _roofline(prob, f, dtype):
+    """Per-kernel-class event timing of one eager step; roofline of the class
+    with the most time."""
+    rows = {}
+    for k in ("contract", "qr", "eig", "stream"):
+        ms, n, fl, by = prob.profile(f, 1, k)
+        rows[k] = {"ms": ms, "launches": n, "flops": fl, "bytes": by}
+    dom = max(rows, key=lambda k: rows[k]["ms"])
+    r = rows[dom]
+    sec = r["ms"] / 1e3 if r["ms"] > 0 else float("nan")
+    if dom == "contract":
+        achieved = r["flops"] / sec / 1e12
+        peak = PEAKS_TFLOPS[dtype]
+        roof = {"bound": "mfma" if dtype != "f64" else "alu", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s"}
+    elif dom == "stream":
+        achieved = r["bytes"] / sec / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s"}
+    else:
+        achieved = r["flops"] / sec / 1e12 if r["flops"] > 0 else 0.0
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAKS_TFLOPS["f64"], "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["launches_per_step"] = r["launches"]
+    roof["avg_launch_us"] = 1e3 * r["ms"] / max(1, r["launches"])
+    return roof, rows
+
+
+def _cpu_baseline(w):
+    """The CPU oracle (numpy / LAPACK, FP64) on a bounded sample: one RK4 step
+    of the same workload from the same initial state."""
+    import numpy as np  # noqa: F401
+    from oracle import stepper
+    st = stepper.MPSStepper(w)
+    f = st.initial_state()
+    t0 = time.perf_counter()
+    st.step(f)
+    el = time.perf_counter() - t0
+    cores = os.cpu_count() or 1
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([i.get("num_threads", 1) for i in info] + [1])
+    except Exception:  # noqa: BLE001
+        pass
+    return {"value": 1.0 / el, "unit": "steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 RK4 step of {w.name} from the seeded initial state ({el:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dtype", default="bf16", choices=["bf16", "f32", "f64"])
+    ap.add_argument("--workload", default="c3_5d_M1024_chi128")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2407_09169_amd as q
+    import workloads
+
+    w = workloads.get_workload(args.workload)
+    ctx = q.Context(0)
+    K, W = args.steps, args.warmup
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    prob, f = q.setup_workload(ctx, w, args.dtype)
+    log(f"{w.name} {args.dtype}: set up; warmup {W}")
+    prob.step(f, W)
+    ms = _time_steps(torch, prob, f, K)
+    value = K / (ms / 1e3)
+    log(f"{args.dtype}: {K} steps in {ms:.1f} ms ({value:.2f} steps/s)")
+
+    plain = None
+    l2 = None
+    if not args.no_plain and args.dtype != "f64":
+        prob64, f64 = q.setup_workload(ctx, w, "f64")
+        prob64.step(f64, W)
+        ms64 = _time_steps(torch, prob64, f64, K)
+        plain = K / (ms64 / 1e3)
+        l2 = q.l2_diff(ctx, f, f64)
+        log(f"f64: {K} steps in {ms64:.1f} ms ({plain:.2f} steps/s); L2 vs f64 {l2:.3e}")
+    mass = prob.observable(f, "mass")
+    disc, norm2 = prob.step_info()
+
+    roof, rows = _roofline(prob, f, args.dtype)
+    log(f"kernel classes: {rows}")
+    cpu = None if args.no_cpu_baseline else _cpu_baseline(w)
+    if cpu:
+        log(f"cpu baseline: {cpu}")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": f"{w.M}^{w.ndims}", "n_cores": w.n_sites,
+                   "chi": w.chi, "ell": w.ell, "chi_mean": w.chi_mean, "integrator": w.integrator,
+                   "dt": w.dt, "omega": w.omega, "k_react": w.k_react},
+        "plain_f64_steps_per_s": plain,
+        "speedup_vs_f64": (value / plain) if plain else None,
+        "l2_err_vs_f64": l2,
+        "mass_after": mass,
+        "discarded_weight_last_rounding": float(sum(disc)),
+        "roofline": roof,
+        "kernel_classes": rows,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

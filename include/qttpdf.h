@@ -236,6 +236,15 @@ tt_status tt_problem_state(tt_problem* prob, tt_tt** f);
  * later calls replay.  f must come from tt_problem_state (or have its caps). */
 tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps);
 
+/* Measurement: runs n_steps steps of the recorded step eagerly (no graph)
+ * with a pair of HIP events around every launch of one kernel class --
+ * 0 contractions (tensor-contraction kernels), 1 Householder QR, 2 batched
+ * eigen-decompositions, 3 streaming block copies -- and returns the summed
+ * event time in ms, the number of such launches, and their algorithmic flops
+ * and bytes (operands read once, results written once).  f is advanced. */
+tt_status tt_profile(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps, int kernel, double* ms,
+                     int64_t* launches, double* flops, double* bytes);
+
 /* Per-bond discarded singular weight (sum of dropped sigma^2, n_sites + 1
  * entries) of the last rounding of the last step, and the squared norm of
  * its result.  Synchronises. */

@@ -30,8 +30,9 @@ EXPORTS = [
     "tt_alloc", "tt_free", "tt_info", "tt_set_cores", "tt_get_cores", "tt_from_separable",
     "mpo_build", "mps_apply_mpo", "mps_axpby", "mps_round", "mps_round_sketch", "tt_l2_diff",
     "tt_inner", "tt_problem_create", "tt_problem_destroy", "tt_problem_info", "tt_problem_state",
-    "tt_step", "tt_step_info", "tt_observable", "tt_mean_field",
+    "tt_step", "tt_profile", "tt_step_info", "tt_observable", "tt_mean_field",
 ]
+KERNELS = {"contract": 0, "qr": 1, "eig": 2, "stream": 3}
 
 
 class TTParams(C.Structure):
@@ -93,6 +94,7 @@ def lib():
         "tt_problem_state": [vp, P(vp)],
         "tt_step": [vp, vp, vp, i32],
         "tt_step_info": [vp, P(dbl), P(dbl)],
+        "tt_profile": [vp, vp, vp, i32, i32, P(dbl), P(C.c_int64), P(dbl), P(dbl)],
         "tt_observable": [vp, vp, vp, i32, P(dbl)],
         "tt_mean_field": [vp, vp, vp, i32, P(vp), P(dbl)],
     }
@@ -327,6 +329,13 @@ class Problem:
 
     def step(self, f, n_steps=1):
         _check(lib().tt_step(self.ctx.h, self.h, f.h, n_steps))
+
+    def profile(self, f, n_steps, kernel):
+        """(ms, launches, flops, bytes) of one kernel class over n_steps eager steps."""
+        ms, n, fl, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+        _check(lib().tt_profile(self.ctx.h, self.h, f.h, n_steps, KERNELS[kernel], C.byref(ms),
+                                C.byref(n), C.byref(fl), C.byref(by)))
+        return ms.value, n.value, fl.value, by.value
 
     def step_info(self):
         n = int(self.info()[0].size)

@@ -421,7 +421,7 @@ tt_status tt_alloc(tt_ctx* ctx, tt_kind kind, int n_sites, const int32_t* bond_c
 tt_status tt_free(tt_tt* t) {
   return guard([&] {
     if (!t) return;
-    if (!rt::dry()) (void)hipStreamSynchronize(t->ctx->stream);
+    if (!rt::dry()) (void)hipDeviceSynchronize();
     delete t;
   });
 }
@@ -869,7 +869,7 @@ tt_status tt_problem_create(tt_ctx* ctx, const tt_params* pp, const tt_tt* const
 tt_status tt_problem_destroy(tt_problem* prob) {
   return guard([&] {
     if (!prob) return;
-    if (!rt::dry()) (void)hipStreamSynchronize(prob->ctx->stream);
+    if (!rt::dry()) (void)hipDeviceSynchronize();
     delete prob;
   });
 }
@@ -921,6 +921,25 @@ tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps) {
       QTT_HIP(hipGraphInstantiate(&prob->exec, prob->graph, nullptr, nullptr, 0));
     }
     for (int i = 0; i < n_steps; ++i) QTT_HIP(hipGraphLaunch(prob->exec, ctx->stream));
+  });
+}
+
+tt_status tt_profile(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps, int kernel, double* ms,
+                     int64_t* launches, double* flops, double* bytes) {
+  return guard([&] {
+    QTT_REQUIRE(prob && f && n_steps >= 1, "bad argument");
+    check_tt(f, ctx);
+    QTT_REQUIRE(f->caps == prob->fcaps, "state caps differ from the problem's");
+    QTT_REQUIRE(kernel >= 0 && kernel <= 3, "unknown kernel class %d", kernel);
+    if (!prob->plan || prob->plan_f != f) build_step_plan(prob, f);
+    StreamScope sc(ctx);
+    double t = 0, fl = 0, by = 0;
+    int64_t n = 0;
+    for (int i = 0; i < n_steps; ++i) prob->plan->run_profiled(ctx->stream, kernel, t, n, fl, by);
+    if (ms) *ms = t;
+    if (launches) *launches = n;
+    if (flops) *flops = fl;
+    if (bytes) *bytes = by;
   });
 }
 

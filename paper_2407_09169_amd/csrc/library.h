@@ -53,9 +53,18 @@ struct ChainView {
 ChainView view(const tt_tt* t);
 ChainView view_sites(const tt_tt* t, int first, int count);  // sub-chain (bond caps as stored)
 
+// kernel classes of a plan (for per-class timing)
+enum OpKind { OP_OTHER = -1, OP_CONTRACT = 0, OP_QR = 1, OP_EIG = 2, OP_STREAM = 3 };
+struct OpInfo {
+  int kind = OP_OTHER;
+  double flops = 0.0;  // algorithmic flops of the launch
+  double bytes = 0.0;  // algorithmic bytes (operands read once, results written once)
+};
+
 // list of enqueue operations with the workspaces they use
 struct Plan {
   std::vector<std::function<void(hipStream_t)>> ops;
+  std::vector<OpInfo> info;
   std::vector<std::unique_ptr<DevBuf>> bufs;
   double* alloc(size_t n_doubles) {
     bufs.emplace_back(new DevBuf(std::max<size_t>(n_doubles, 1) * sizeof(double)));
@@ -67,10 +76,17 @@ struct Plan {
     if (!host.empty()) rt::copy(bufs.back()->p, host.data(), host.size() * sizeof(T));
     return static_cast<T*>(bufs.back()->p);
   }
-  void add(std::function<void(hipStream_t)> f) { ops.push_back(std::move(f)); }
+  void add(std::function<void(hipStream_t)> f, OpInfo oi = OpInfo{}) {
+    ops.push_back(std::move(f));
+    info.push_back(oi);
+  }
   void run(hipStream_t s) const {
     for (auto& f : ops) f(s);
   }
+  // eager run with a pair of events around every op of class `kind`; adds the
+  // event time (ms), the number of such ops and their flops / bytes
+  void run_profiled(hipStream_t s, int kind, double& ms, int64_t& count, double& flops,
+                    double& bytes) const;
 };
 
 struct SketchTerm {

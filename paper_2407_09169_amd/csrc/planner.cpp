@@ -64,7 +64,55 @@ static Mode2 M1(int64_t s) { return mode1(s); }
 static Mode2 M2(int n2, int64_t s1, int64_t s2) { return mode2(n2, s1, s2); }
 
 static void add_tc(Plan& plan, TcDesc d, Prec p) {
-  plan.add([d, p](hipStream_t s) { tc_launch(d, p, s); });
+  tc_validate(d);
+  OpInfo oi;
+  oi.kind = OP_CONTRACT;
+  oi.flops = 2.0 * d.M * (double)d.N * d.K * d.batch;
+  double na = (mode_max(d.ab, d.batch) == 0) ? 1.0 : d.batch;
+  double nb = (mode_max(d.bb, d.batch) == 0) ? 1.0 : d.batch;
+  oi.bytes = 8.0 * (na * d.M * (double)d.K + nb * d.K * (double)d.N +
+                    (d.beta != 0.0 ? 2.0 : 1.0) * d.batch * d.M * (double)d.N);
+  plan.add([d, p](hipStream_t s) { tc_launch(d, p, s); }, oi);
+}
+
+static OpInfo qr_info(int m, int n) {
+  OpInfo oi;
+  oi.kind = OP_QR;
+  oi.flops = 2.0 * (2.0 * m * (double)n * n - 2.0 * n * (double)n * n / 3.0);
+  oi.bytes = 8.0 * 2.0 * m * (double)n;
+  return oi;
+}
+
+void Plan::run_profiled(hipStream_t s, int kind, double& ms, int64_t& count, double& flops,
+                        double& bytes) const {
+  std::vector<size_t> idx;
+  for (size_t i = 0; i < ops.size(); ++i)
+    if (info[i].kind == kind) idx.push_back(i);
+  std::vector<hipEvent_t> ev(2 * idx.size(), nullptr);
+  if (!rt::dry())
+    for (auto& e : ev) QTT_HIP(hipEventCreate(&e));
+  size_t j = 0;
+  for (size_t i = 0; i < ops.size(); ++i) {
+    bool tim = (j < idx.size() && idx[j] == i);
+    if (tim && !rt::dry()) QTT_HIP(hipEventRecord(ev[2 * j], s));
+    ops[i](s);
+    if (tim) {
+      if (!rt::dry()) QTT_HIP(hipEventRecord(ev[2 * j + 1], s));
+      flops += info[i].flops;
+      bytes += info[i].bytes;
+      ++count;
+      ++j;
+    }
+  }
+  rt::sync(s);
+  if (!rt::dry()) {
+    for (size_t k = 0; k < idx.size(); ++k) {
+      float t = 0.f;
+      QTT_HIP(hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]));
+      ms += t;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  }
 }
 
 static void add_gemm(Plan& plan, int M, int N, int K, const double* A, int64_t lda, bool ta,
@@ -126,10 +174,13 @@ static void plan_trunc_gram(Plan& plan, const std::vector<double*>& X, const std
     double* p1 = Pn(1);
     double* l1 = lam + ldg;
     int cnt = N - 1;
+    OpInfo oi;
+    oi.kind = OP_EIG;
+    for (int n = 1; n < N; ++n) oi.bytes += 8.0 * ((double)ell[n] * ell[n] + (double)ell[n] * tg.caps[n]);
     plan.add([=](hipStream_t s) {
       eig_launch(cnt, d_dims, d_keep, g1, (int64_t)ldg * ldg, ldg, p1, (int64_t)ldg * ldp, ldp, l1,
                  ldg, ework, lmax, s);
-    });
+    }, oi);
   }
   // new cores P_n^T X_n P_{n+1}
   for (int n = 0; n < N; ++n) {
@@ -364,7 +415,8 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
     {
       double* Xn = X[n];
       const int m = 2 * l, nc = lp;
-      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, S, 0, nc, 1, Xn, 0, nullptr, 0, qrw, s); });
+      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, S, 0, nc, 1, Xn, 0, nullptr, 0, qrw, s); },
+               qr_info(m, nc));
     }
     for (int j = 0; j < J; ++j) {
       const int rp = sh[j].r[n + 1], Dp = sh[j].D[n + 1];
@@ -416,7 +468,8 @@ LeftOrth plan_left_orth(Plan& plan, const ChainView& x) {
       Q = plan.alloc((size_t)m * cr);
       double* Rm = plan.alloc((size_t)cr * cr);
       double* work = plan.alloc((size_t)m * cr);
-      plan.add([=](hipStream_t s) { qr_launch(1, m, cr, cur, 0, cr, 1, Q, 0, Rm, 0, work, s); });
+      plan.add([=](hipStream_t s) { qr_launch(1, m, cr, cur, 0, cr, 1, Q, 0, Rm, 0, work, s); },
+               qr_info(m, cr));
       next = plan.alloc((size_t)knew * 2 * cnr);
       add_gemm(plan, knew, 2 * cnr, cr, Rm, cr, false, x.core[n + 1], 2 * cnr, false, next, 2 * cnr,
                1.0, 0.0, Prec::F64);
@@ -525,10 +578,14 @@ void plan_axpby(Plan& plan, const std::vector<std::pair<double, ChainView>>& ter
   double* base = dst->buf.d();
   int64_t tot = dst->total();
   int nj = (int)jobs.size();
+  OpInfo oi;
+  oi.kind = OP_STREAM;
+  for (const CopyJob& j : jobs) oi.bytes += 16.0 * j.rl * j.sp * j.rr;
+  oi.bytes += 8.0 * tot;
   plan.add([=](hipStream_t s) {
     fill(base, tot, 0.0, s);
     copy_jobs(dj, nj, maxe, s);
-  });
+  }, oi);
 }
 
 void plan_partial(Plan& plan, const ChainView& w, const ChainView& x, double* out_dev) {
