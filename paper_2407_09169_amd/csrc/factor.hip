@@ -130,6 +130,184 @@ __global__ __launch_bounds__(FT) void qr_kernel(int m, int n, const double* __re
 }
 
 // ---------------------------------------------------------------------------
+// Register-resident Householder QR for m <= 64*RS, n <= 16*CPW: 16 wavefronts,
+// column c lives in wavefront c % 16 (slot c / 16), row r in lane r % 64
+// (slot r / 64).  Step k: the owner of column k builds the reflector with one
+// wavefront reduction and publishes v (double-buffered LDS); one barrier;
+// every wavefront applies it to its columns with interleaved wavefront
+// reductions.  Q is formed in place by backward accumulation.
+// ---------------------------------------------------------------------------
+constexpr int QR_CHUNK = 3;
+
+// a[:, j] -= t (v^T a[:, j]) v for the columns c = wave + QW*j with k < c < n;
+// the wavefront reductions of QR_CHUNK columns are interleaved.
+template <int RS, int CPW, int QW>
+__device__ inline void apply_reflector(double (&a)[RS][CPW], const double (&v)[RS], double t, int k,
+                                       int n, int wave) {
+#pragma unroll
+  for (int j0 = 0; j0 < CPW; j0 += QR_CHUNK) {
+    double d[QR_CHUNK];
+#pragma unroll
+    for (int jj = 0; jj < QR_CHUNK; ++jj) {
+      double p = 0.0;
+      if (j0 + jj < CPW) {
+#pragma unroll
+        for (int i = 0; i < RS; ++i) p += v[i] * a[i][(j0 + jj < CPW) ? j0 + jj : 0];
+      }
+      d[jj] = p;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int jj = 0; jj < QR_CHUNK; ++jj) d[jj] += __shfl_xor(d[jj], off, 64);
+#pragma unroll
+    for (int jj = 0; jj < QR_CHUNK; ++jj) {
+      const int j = j0 + jj;
+      if (j < CPW) {
+        const int c = wave + QW * j;
+        if (c > k && c < n) {
+          const double w = t * d[jj];
+#pragma unroll
+          for (int i = 0; i < RS; ++i) a[i][j < CPW ? j : 0] -= w * v[i];
+        }
+      }
+    }
+  }
+}
+
+template <int RS, int CPW, int QW>
+__global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const double* __restrict__ A0,
+                                                      int64_t strideA, int64_t rs, int64_t cs,
+                                                      double* __restrict__ Q0, int64_t strideQ,
+                                                      double* __restrict__ R0, int64_t strideR) {
+  __shared__ double vbuf[2][64 * RS];
+  __shared__ double taus[QW * CPW];
+  __shared__ double betas[QW * CPW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t bi = blockIdx.x;
+  const double* A = A0 + bi * strideA;
+  double a[RS][CPW];
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) {
+    const int c = wave + QW * j;
+#pragma unroll
+    for (int i = 0; i < RS; ++i) {
+      const int r = lane + 64 * i;
+      a[i][j] = (r < m && c < n) ? A[r * rs + c * cs] : 0.0;
+    }
+  }
+  for (int k = 0; k < n; ++k) {
+    const int owner = k % QW, jk = k / QW, buf = k & 1;
+    if (wave == owner) {
+      double col[RS];
+#pragma unroll
+      for (int i = 0; i < RS; ++i) {
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) v = (j == jk) ? a[i][j] : v;
+        col[i] = v;
+      }
+      double part = 0.0, xk = 0.0;
+#pragma unroll
+      for (int i = 0; i < RS; ++i) {
+        const int r = lane + 64 * i;
+        if (r > k) part += col[i] * col[i];
+        if (r == k) xk = col[i];
+      }
+      const double sig = wave_sum(part);
+      const double x0 = wave_sum(xk);
+      double tau = 0.0, beta = x0, scale = 0.0;
+      if (sig != 0.0) {
+        const double nrm = sqrt(x0 * x0 + sig);
+        beta = x0 >= 0.0 ? -nrm : nrm;
+        tau = (beta - x0) / beta;
+        scale = 1.0 / (x0 - beta);
+      }
+#pragma unroll
+      for (int i = 0; i < RS; ++i) {
+        const int r = lane + 64 * i;
+        const double v = (r > k) ? col[i] * scale : (r == k ? 1.0 : 0.0);
+        vbuf[buf][r] = v;
+        if (r > k) {
+#pragma unroll
+          for (int j = 0; j < CPW; ++j)
+            if (j == jk) a[i][j] = v;
+        }
+      }
+      if (lane == 0) {
+        taus[k] = tau;
+        betas[k] = beta;
+      }
+    }
+    __syncthreads();
+    const double t = taus[k];
+    if (t != 0.0) {
+      double v[RS];
+#pragma unroll
+      for (int i = 0; i < RS; ++i) v[i] = vbuf[buf][lane + 64 * i];
+      apply_reflector<RS, CPW, QW>(a, v, t, k, n, wave);
+    }
+  }
+  __syncthreads();
+  if (R0 != nullptr) {
+    double* R = R0 + bi * strideR;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      const int c = wave + QW * j;
+      if (c >= n) continue;
+#pragma unroll
+      for (int i = 0; i < RS; ++i) {
+        const int r = lane + 64 * i;
+        if (r >= n) continue;
+        R[(int64_t)r * n + c] = (r < c) ? a[i][j] : (r == c ? betas[c] : 0.0);
+      }
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const int owner = k % QW, jk = k / QW, buf = k & 1;
+    if (wave == owner) {
+#pragma unroll
+      for (int i = 0; i < RS; ++i) {
+        const int r = lane + 64 * i;
+        double v = 0.0;
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) v = (j == jk) ? a[i][j] : v;
+        vbuf[buf][r] = (r > k) ? v : (r == k ? 1.0 : 0.0);
+      }
+    }
+    __syncthreads();
+    const double t = taus[k];
+    double v[RS];
+#pragma unroll
+    for (int i = 0; i < RS; ++i) v[i] = vbuf[buf][lane + 64 * i];
+    if (t != 0.0) {
+      apply_reflector<RS, CPW, QW>(a, v, t, k, n, wave);
+    }
+    if (wave == owner) {
+#pragma unroll
+      for (int i = 0; i < RS; ++i) {
+        const int r = lane + 64 * i;
+        const double q = (r < k) ? 0.0 : (r == k ? 1.0 - t : -t * v[i]);
+#pragma unroll
+        for (int j = 0; j < CPW; ++j)
+          if (j == jk) a[i][j] = q;
+      }
+    }
+  }
+  double* Q = Q0 + bi * strideQ;
+#pragma unroll
+  for (int j = 0; j < CPW; ++j) {
+    const int c = wave + QW * j;
+    if (c >= n) continue;
+#pragma unroll
+    for (int i = 0; i < RS; ++i) {
+      const int r = lane + 64 * i;
+      if (r < m) Q[(int64_t)r * n + c] = a[i][j];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Symmetric PSD eigen-decomposition by one-sided (Hestenes) Jacobi on G:
 // G J = U S with J accumulated; for PSD G the columns of J are eigenvectors
 // and the column norms of G J the eigenvalues.  Round-robin pair ordering,
@@ -223,6 +401,246 @@ __global__ __launch_bounds__(FT) void eig_kernel(const int* dims, const int* kee
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident one-sided Jacobi for PSD G (n <= 2*NW*PPW, n <= 64*RS):
+// the n columns of W = G J and of V = J are held as NP = ceil(n/2) column
+// pairs ("slots"), PPW slots per wavefront, rows across lanes.  Each round
+// rotates every pair (three interleaved wavefront reductions per pair), then
+// the columns move one slot around the round-robin circle (slot 0 top fixed):
+// within a wavefront by register moves, across wavefronts through a
+// double-buffered LDS hand-off, one barrier per round.  n - 1 rounds make a
+// sweep in which every pair of columns meets once.
+// ---------------------------------------------------------------------------
+template <int RS, int PPW, int NW, int CH>
+__global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const int* keep,
+                                                          const double* __restrict__ G0,
+                                                          int64_t strideG, int ldg,
+                                                          double* __restrict__ P0, int64_t strideP,
+                                                          int ldp, double* __restrict__ L0,
+                                                          int64_t strideL) {
+  __shared__ double xT[2][NW][2][64 * RS];  // outgoing last top column (W, V) per wave
+  __shared__ double xB[2][NW][2][64 * RS];  // outgoing first bottom column (W, V) per wave
+  __shared__ int xTid[2][NW], xBid[2][NW];
+  __shared__ int rot_any;
+  __shared__ double lam_s[2 * NW * PPW + 2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t bi = blockIdx.x;
+  const int n = dims[bi];
+  const int kk = keep[bi];
+  if (n <= 0) return;
+  const double* G = G0 + bi * strideG;
+  double* P = P0 + bi * strideP;
+  double* L = L0 + bi * strideL;
+  const int NP = (n + 1) / 2;
+  const int p0 = w * PPW;
+  double wt[PPW][RS], wb[PPW][RS], vt[PPW][RS], vb[PPW][RS];
+  int it[PPW], ib[PPW];
+  // initial circle: pair p = (p, 2NP - 1 - p); id n (odd n) is a zero column
+#pragma unroll
+  for (int j = 0; j < PPW; ++j) {
+    const int p = p0 + j;
+    it[j] = p;
+    ib[j] = 2 * NP - 1 - p;
+#pragma unroll
+    for (int i = 0; i < RS; ++i) {
+      const int r = lane + 64 * i;
+      const bool okr = r < n;
+      wt[j][i] = (okr && p < NP && it[j] < n) ? G[(int64_t)r * ldg + it[j]] : 0.0;
+      wb[j][i] = (okr && p < NP && ib[j] < n) ? G[(int64_t)r * ldg + ib[j]] : 0.0;
+      vt[j][i] = (r == it[j]) ? 1.0 : 0.0;
+      vb[j][i] = (r == ib[j]) ? 1.0 : 0.0;
+    }
+  }
+  const int rounds = 2 * NP - 1;
+  int parity = 0;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (threadIdx.x == 0) rot_any = 0;
+    __syncthreads();
+    int rotated = 0;
+    for (int rd = 0; rd < rounds; ++rd) {
+      // ---- rotate every active pair (reductions interleaved CH pairs at a time)
+#pragma unroll
+      for (int j0 = 0; j0 < PPW; j0 += CH) {
+        double A_[CH], B_[CH], C_[CH];
+#pragma unroll
+        for (int jj = 0; jj < CH; ++jj) {
+          const int j = (j0 + jj < PPW) ? j0 + jj : PPW - 1;
+          double a = 0.0, b = 0.0, g = 0.0;
+#pragma unroll
+          for (int i = 0; i < RS; ++i) {
+            a += wt[j][i] * wt[j][i];
+            b += wb[j][i] * wb[j][i];
+            g += wt[j][i] * wb[j][i];
+          }
+          A_[jj] = a;
+          B_[jj] = b;
+          C_[jj] = g;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+          for (int jj = 0; jj < CH; ++jj) {
+            A_[jj] += __shfl_xor(A_[jj], off, 64);
+            B_[jj] += __shfl_xor(B_[jj], off, 64);
+            C_[jj] += __shfl_xor(C_[jj], off, 64);
+          }
+#pragma unroll
+        for (int jj = 0; jj < CH; ++jj) {
+          if (j0 + jj >= PPW) continue;
+          const int j = (j0 + jj < PPW) ? j0 + jj : PPW - 1;
+          const int p = p0 + j;
+          const double a = A_[jj], b = B_[jj], g = C_[jj];
+          if (p < NP && g != 0.0 && fabs(g) > 1e-15 * sqrt(a * b)) {
+            const double zeta = (b - a) / (2.0 * g);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+#pragma unroll
+            for (int i = 0; i < RS; ++i) {
+              const double x = wt[j][i], y = wb[j][i];
+              wt[j][i] = c * x - s * y;
+              wb[j][i] = s * x + c * y;
+              const double u = vt[j][i], z = vb[j][i];
+              vt[j][i] = c * u - s * z;
+              vb[j][i] = s * u + c * z;
+            }
+            rotated = 1;
+          }
+        }
+      }
+      // ---- move one slot around the circle
+#pragma unroll
+      for (int i = 0; i < RS; ++i) {
+        xT[parity][w][0][lane + 64 * i] = wt[PPW - 1][i];
+        xT[parity][w][1][lane + 64 * i] = vt[PPW - 1][i];
+        xB[parity][w][0][lane + 64 * i] = wb[0][i];
+        xB[parity][w][1][lane + 64 * i] = vb[0][i];
+      }
+      if (lane == 0) {
+        xTid[parity][w] = it[PPW - 1];
+        xBid[parity][w] = ib[0];
+      }
+      __syncthreads();
+      const int wl = (w > 0) ? w - 1 : 0, wr = (w < NW - 1) ? w + 1 : w;
+      // bottoms move left: slot p takes the bottom of p+1; the last slot its own top
+#pragma unroll
+      for (int j = 0; j < PPW; ++j) {
+        const int p = p0 + j;
+        if (p >= NP) continue;
+        if (p == NP - 1) {
+#pragma unroll
+          for (int i = 0; i < RS; ++i) {
+            wb[j][i] = wt[j][i];
+            vb[j][i] = vt[j][i];
+          }
+          ib[j] = it[j];
+        } else if (j + 1 < PPW) {
+          const int jn = (j + 1 < PPW) ? j + 1 : j;
+#pragma unroll
+          for (int i = 0; i < RS; ++i) {
+            wb[j][i] = wb[jn][i];
+            vb[j][i] = vb[jn][i];
+          }
+          ib[j] = ib[jn];
+        } else {
+#pragma unroll
+          for (int i = 0; i < RS; ++i) {
+            wb[j][i] = xB[parity][wr][0][lane + 64 * i];
+            vb[j][i] = xB[parity][wr][1][lane + 64 * i];
+          }
+          ib[j] = __builtin_amdgcn_readfirstlane(xBid[parity][wr]);
+        }
+      }
+      // tops move right: slot 0 fixed, slot 1 takes the old bottom of slot 0
+#pragma unroll
+      for (int j = PPW - 1; j >= 0; --j) {
+        const int p = p0 + j;
+        if (p >= NP || p == 0) continue;
+        if (p == 1) {
+#pragma unroll
+          for (int i = 0; i < RS; ++i) {
+            wt[j][i] = xB[parity][0][0][lane + 64 * i];
+            vt[j][i] = xB[parity][0][1][lane + 64 * i];
+          }
+          it[j] = __builtin_amdgcn_readfirstlane(xBid[parity][0]);
+        } else if (j >= 1) {
+          const int jp = (j >= 1) ? j - 1 : 0;
+#pragma unroll
+          for (int i = 0; i < RS; ++i) {
+            wt[j][i] = wt[jp][i];
+            vt[j][i] = vt[jp][i];
+          }
+          it[j] = it[jp];
+        } else {
+#pragma unroll
+          for (int i = 0; i < RS; ++i) {
+            wt[j][i] = xT[parity][wl][0][lane + 64 * i];
+            vt[j][i] = xT[parity][wl][1][lane + 64 * i];
+          }
+          it[j] = __builtin_amdgcn_readfirstlane(xTid[parity][wl]);
+        }
+      }
+      parity ^= 1;
+    }
+    if (rotated && lane == 0) rot_any = 1;
+    __syncthreads();
+    const int any = rot_any;
+    __syncthreads();
+    if (!any) break;
+  }
+  // eigenvalues: column norms of W (PSD: |G v| = lambda)
+  double nt_[PPW], nb_[PPW];
+#pragma unroll
+  for (int j = 0; j < PPW; ++j) {
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int i = 0; i < RS; ++i) {
+      a += wt[j][i] * wt[j][i];
+      b += wb[j][i] * wb[j][i];
+    }
+    nt_[j] = a;
+    nb_[j] = b;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int j = 0; j < PPW; ++j) {
+      nt_[j] += __shfl_xor(nt_[j], off, 64);
+      nb_[j] += __shfl_xor(nb_[j], off, 64);
+    }
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < PPW; ++j) {
+      if (p0 + j >= NP) continue;
+      lam_s[it[j]] = sqrt(nt_[j]);
+      lam_s[ib[j]] = sqrt(nb_[j]);
+    }
+  }
+  __syncthreads();
+  // rank by descending eigenvalue (ties by index); dummy column n excluded
+#pragma unroll
+  for (int j = 0; j < PPW; ++j) {
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      if (p0 + j >= NP) continue;
+      const int id = half ? ib[j] : it[j];
+      if (id >= n) continue;
+      const double v = lam_s[id];
+      int cnt = 0;
+      for (int o = lane; o < n; o += 64) cnt += (lam_s[o] > v) || (lam_s[o] == v && o < id);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+      if (lane == 0) L[cnt] = v;
+      if (cnt < kk) {
+#pragma unroll
+        for (int i = 0; i < RS; ++i) {
+          const int r = lane + 64 * i;
+          if (r < n) P[(int64_t)r * ldp + cnt] = half ? vb[j][i] : vt[j][i];
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_t rs, int64_t cs,
@@ -236,6 +654,22 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
   if (R) rt::check_range(R, 0, (int64_t)(count - 1) * strideR + (int64_t)n * n - 1, sizeof(double), "qr R");
   rt::check_range(work, 0, (int64_t)count * m * n - 1, sizeof(double), "qr workspace");
   if (rt::dry()) return;
+#define QTT_QR_REG(RS_, CPW_, NW_)                                                                \
+  if (m <= 64 * RS_ && n <= NW_ * CPW_) {                                                         \
+    hipLaunchKernelGGL((qr_reg_kernel<RS_, CPW_, NW_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
+                       strideA, rs, cs, Q, strideQ, R, strideR);                                 \
+    QTT_HIP(hipGetLastError());                                                                  \
+    return;                                                                                      \
+  }
+  QTT_QR_REG(1, 1, 16)
+  QTT_QR_REG(1, 2, 16)
+  QTT_QR_REG(2, 2, 16)
+  QTT_QR_REG(2, 4, 16)
+  QTT_QR_REG(3, 6, 16)
+  QTT_QR_REG(4, 8, 16)
+  QTT_QR_REG(5, 9, 16)
+  QTT_QR_REG(5, 10, 16)
+#undef QTT_QR_REG
   hipLaunchKernelGGL(qr_kernel, dim3(count), dim3(FT), 0, s, m, n, A, strideA, rs, cs, Q, strideQ,
                      R, strideR, work);
   QTT_HIP(hipGetLastError());
@@ -255,6 +689,20 @@ void eig_launch(int count, const int* dims, const int* keep, const double* G, in
   rt::check_range(lam, 0, (int64_t)(count - 1) * strideL + max_n - 1, sizeof(double), "eig values");
   rt::check_range(work, 0, (int64_t)count * 2 * ldg * ldg - 1, sizeof(double), "eig workspace");
   if (rt::dry()) return;
+#define QTT_EIG_REG(RS_, PPW_, NW_, CH_)                                                          \
+  if (max_n <= 64 * RS_ && max_n <= 2 * NW_ * PPW_) {                                            \
+    hipLaunchKernelGGL((eig_reg_kernel<RS_, PPW_, NW_, CH_>), dim3(count), dim3(NW_ * 64), 0, s,  \
+                       dims, keep, G, strideG, ldg, P, strideP, ldp, lam, strideL);              \
+    QTT_HIP(hipGetLastError());                                                                  \
+    return;                                                                                      \
+  }
+  QTT_EIG_REG(1, 1, 4, 1)
+  QTT_EIG_REG(1, 2, 8, 2)
+  QTT_EIG_REG(1, 4, 8, 3)
+  QTT_EIG_REG(2, 4, 8, 3)
+  QTT_EIG_REG(2, 8, 8, 2)
+  QTT_EIG_REG(3, 9, 8, 1)
+#undef QTT_EIG_REG
   hipLaunchKernelGGL(eig_kernel, dim3(count), dim3(FT), 0, s, dims, keep, G, strideG, ldg, P,
                      strideP, ldp, lam, strideL, work);
   QTT_HIP(hipGetLastError());

@@ -139,6 +139,24 @@ def test_round_sketch_matches_oracle(ctx, dtype, tol):
     assert err < tol, (dtype, err)
 
 
+@pytest.mark.parametrize("ell,chi", [(144, 128), (80, 64), (40, 32)])
+def test_round_sketch_large_bonds(ctx, ell, chi):
+    """Bond sizes of the 5-D chi = 128 workload (QR of 288 x 144 sketches,
+    eigen-decompositions of 144 x 144 Gram matrices) on a 16-core chain."""
+    N = 16
+    caps = [min(2 ** n, 2 ** (N - n), 160) for n in range(N + 1)]
+    xc = random_tt(caps, 51, decay=0.97)
+    Wc = _random_mpo(N, 2, 52)
+    Z, ellr = gaussian_sketch(N, ell, 53)
+    ref, _ = tt.round_sketch([(1.0, Wc, xc), (0.5, None, xc)], Z, ellr, chi)
+    W = q.TT.from_cores(ctx, Wc, kind=q.TT_MPO)
+    x = q.TT.from_cores(ctx, xc)
+    sk = q.TT.from_cores(ctx, Z)
+    out = q.round_sketch(ctx, [1.0, 0.5], [W, None], [x, x], sk, chi, "f64")
+    err = rel(full(out.cores()), full(ref))
+    assert err < TRUNC_TOL, err
+
+
 # --------------------------------------------------------------- a6 step
 @pytest.mark.parametrize("name,integrator", [("t_5d_M8_exact", "rk4"), ("c1_2d_M64_exact", "rk2")])
 def test_step_untruncated_equals_dense(ctx, name, integrator):
