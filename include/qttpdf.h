@@ -259,6 +259,21 @@ tt_status tt_observable(tt_ctx* ctx, tt_problem* prob, const tt_tt* f, int which
 tt_status tt_mean_field(tt_ctx* ctx, tt_problem* prob, const tt_tt* f, int a, tt_tt** out,
                         double* scalar);
 
+/* ------------------------------------------------------------------------
+ * The FP64 factorisation kernels on their own (unit tests, diagnostics)
+ * ------------------------------------------------------------------------ */
+/* Householder QR of `count` row-major m x n matrices (m >= n, n <= 1024)
+ * given in host memory (A: count*m*n values).  Writes the thin Q (count*m*n)
+ * and, if R != NULL, the upper-triangular R (count*n*n) to host memory. */
+tt_status tt_linalg_qr(tt_ctx* ctx, int count, int m, int n, const double* A, double* Q, double* R);
+/* Eigen-decomposition of `count` symmetric positive semi-definite row-major
+ * n x n matrices (host G: count*n*n values) by one-sided Jacobi: writes the
+ * eigenvectors of the `keep` largest eigenvalues as the columns of row-major
+ * n x keep matrices (host P: count*n*keep) and all n eigenvalues in
+ * descending order (host lam: count*n). */
+tt_status tt_linalg_eigh(tt_ctx* ctx, int count, int n, int keep, const double* G, double* P,
+                         double* lam);
+
 #ifdef __cplusplus
 }
 #endif

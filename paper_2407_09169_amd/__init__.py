@@ -31,6 +31,7 @@ EXPORTS = [
     "mpo_build", "mps_apply_mpo", "mps_axpby", "mps_round", "mps_round_sketch", "tt_l2_diff",
     "tt_inner", "tt_problem_create", "tt_problem_destroy", "tt_problem_info", "tt_problem_state",
     "tt_step", "tt_profile", "tt_step_info", "tt_observable", "tt_mean_field",
+    "tt_linalg_qr", "tt_linalg_eigh",
 ]
 KERNELS = {"contract": 0, "qr": 1, "eig": 2, "stream": 3}
 
@@ -97,6 +98,8 @@ def lib():
         "tt_profile": [vp, vp, vp, i32, i32, P(dbl), P(C.c_int64), P(dbl), P(dbl)],
         "tt_observable": [vp, vp, vp, i32, P(dbl)],
         "tt_mean_field": [vp, vp, vp, i32, P(vp), P(dbl)],
+        "tt_linalg_qr": [vp, i32, i32, i32, P(dbl), P(dbl), P(dbl)],
+        "tt_linalg_eigh": [vp, i32, i32, i32, P(dbl), P(dbl), P(dbl)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -299,6 +302,30 @@ def inner(ctx, a, b):
     r = C.c_double()
     _check(lib().tt_inner(ctx.h, a.h, b.h, C.byref(r)))
     return r.value
+
+
+def linalg_qr(ctx, A, with_r=True):
+    """Householder QR of a stack of matrices A (count, m, n) on the device."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    cnt, m, n = A.shape
+    Q = np.zeros((cnt, m, n))
+    R = np.zeros((cnt, n, n)) if with_r else None
+    dp = C.POINTER(C.c_double)
+    _check(lib().tt_linalg_qr(ctx.h, cnt, m, n, A.ctypes.data_as(dp), Q.ctypes.data_as(dp),
+                              R.ctypes.data_as(dp) if with_r else None))
+    return Q, R
+
+
+def linalg_eigh(ctx, G, keep):
+    """Leading eigenpairs of a stack of PSD matrices G (count, n, n) on the device."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    cnt, n, _ = G.shape
+    P = np.zeros((cnt, n, keep))
+    lam = np.zeros((cnt, n))
+    dp = C.POINTER(C.c_double)
+    _check(lib().tt_linalg_eigh(ctx.h, cnt, n, keep, G.ctypes.data_as(dp), P.ctypes.data_as(dp),
+                                lam.ctypes.data_as(dp)))
+    return P, lam
 
 
 class Problem:

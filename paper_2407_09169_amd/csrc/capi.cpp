@@ -1065,4 +1065,41 @@ tt_status tt_observable(tt_ctx* ctx, tt_problem* prob, const tt_tt* f, int which
   });
 }
 
+tt_status tt_linalg_qr(tt_ctx* ctx, int count, int m, int n, const double* A, double* Q, double* R) {
+  return guard([&] {
+    QTT_REQUIRE(ctx && A && Q && count >= 1 && n >= 1 && m >= n && n <= 1024, "bad argument");
+    const size_t mn = (size_t)m * n, nn = (size_t)n * n;
+    DevBuf dA(count * mn * 8), dQ(count * mn * 8), dR(count * nn * 8), dW(count * mn * 8);
+    StreamScope sc(ctx);
+    rt::copy(dA.p, A, count * mn * 8);
+    qr_launch(count, m, n, dA.d(), (int64_t)mn, n, 1, dQ.d(), (int64_t)mn, R ? dR.d() : nullptr,
+              (int64_t)nn, dW.d(), ctx->stream);
+    rt::sync(ctx->stream);
+    rt::copy(Q, dQ.p, count * mn * 8);
+    if (R) rt::copy(R, dR.p, count * nn * 8);
+  });
+}
+
+tt_status tt_linalg_eigh(tt_ctx* ctx, int count, int n, int keep, const double* G, double* P,
+                         double* lam) {
+  return guard([&] {
+    QTT_REQUIRE(ctx && G && P && lam && count >= 1 && n >= 1 && n <= 1024 && keep >= 1 && keep <= n,
+                "bad argument");
+    const size_t nn = (size_t)n * n;
+    DevBuf dG(count * nn * 8), dP(count * (size_t)n * keep * 8), dL(count * (size_t)n * 8),
+        dW(count * 2 * nn * 8), dd(count * sizeof(int)), dk(count * sizeof(int));
+    std::vector<int> dims(count, n), kp(count, keep);
+    StreamScope sc(ctx);
+    rt::copy(dG.p, G, count * nn * 8);
+    rt::copy(dd.p, dims.data(), count * sizeof(int));
+    rt::copy(dk.p, kp.data(), count * sizeof(int));
+    fill(dP.d(), (int64_t)count * n * keep, 0.0, ctx->stream);
+    eig_launch(count, dd.as<int>(), dk.as<int>(), dG.d(), (int64_t)nn, n, dP.d(), (int64_t)n * keep,
+               keep, dL.d(), n, dW.d(), n, ctx->stream);
+    rt::sync(ctx->stream);
+    rt::copy(P, dP.p, count * (size_t)n * keep * 8);
+    rt::copy(lam, dL.p, count * (size_t)n * 8);
+  });
+}
+
 }  // extern "C"

@@ -521,6 +521,10 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
       }
       __syncthreads();
       const int wl = (w > 0) ? w - 1 : 0, wr = (w < NW - 1) ? w + 1 : w;
+      if (NP == 1) {  // a single pair never moves
+        parity ^= 1;
+        continue;
+      }
       // bottoms move left: slot p takes the bottom of p+1; the last slot its own top
 #pragma unroll
       for (int j = 0; j < PPW; ++j) {

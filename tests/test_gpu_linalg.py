@@ -1,0 +1,45 @@
+"""FP64 factorisation kernels against LAPACK (needs an MI355X)."""
+import numpy as np
+import pytest
+
+q = pytest.importorskip("paper_2407_09169_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = q.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("m,n", [(2, 1), (4, 4), (8, 5), (32, 16), (64, 64), (128, 64), (96, 90),
+                                 (288, 144), (320, 160), (512, 256)])
+def test_qr(ctx, m, n):
+    rng = np.random.default_rng(m * 1000 + n)
+    A = rng.standard_normal((3, m, n))
+    A[1, :, n // 2:] = 0.0  # rank deficient
+    A[2] *= np.logspace(0, -12, n)[None, :]  # graded columns
+    Q, R = q.linalg_qr(ctx, A)
+    for b in range(3):
+        assert np.max(np.abs(Q[b].T @ Q[b] - np.eye(n))) < 50 * n * 2.2e-16, b
+        assert np.max(np.abs(Q[b] @ R[b] - A[b])) <= 50 * n * 2.2e-16 * np.abs(A[b]).max(), b
+        assert np.max(np.abs(np.tril(R[b], -1))) == 0.0
+
+
+@pytest.mark.parametrize("n,keep", [(1, 1), (2, 1), (2, 2), (3, 2), (5, 3), (16, 16), (33, 20), (64, 48), (100, 100),
+                                    (128, 120), (144, 128)])
+def test_eigh(ctx, n, keep):
+    rng = np.random.default_rng(n * 7 + keep)
+    X = rng.standard_normal((3, n, n + 4)) * np.logspace(0, -6, n + 4)[None, None, :]
+    G = X @ np.transpose(X, (0, 2, 1))
+    G[1] = X[1][:, : max(1, n // 3)] @ X[1][:, : max(1, n // 3)].T  # rank deficient
+    P, lam = q.linalg_eigh(ctx, G, keep)
+    for b in range(3):
+        ref = np.linalg.eigvalsh(G[b])[::-1]
+        l1 = ref[0]
+        assert np.max(np.abs(lam[b] - ref)) < 100 * n * 2.2e-16 * l1, b
+        assert np.max(np.abs(P[b].T @ P[b] - np.eye(keep))) < 100 * n * 2.2e-16, b
+        resid = G[b] @ P[b] - P[b] * lam[b][:keep][None, :]
+        assert np.max(np.abs(resid)) < 100 * n * 2.2e-16 * l1, b
