@@ -96,10 +96,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--dtype", default="bf16", choices=["bf16", "f32", "f64"])
+    ap.add_argument("--dtype", default="f32", choices=["bf16", "f32", "f64"])
     ap.add_argument("--workload", default="c3_5d_M1024_chi128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the extra BF16-MFMA measurement made next to an FP32 run")
+    ap.add_argument("--op-log", default=None,
+                    help="also time every launch of one eager step and write one line per launch here")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}); "
@@ -133,9 +137,22 @@ def main():
         plain = K / (ms64 / 1e3)
         l2 = q.l2_diff(ctx, f, f64)
         log(f"f64: {K} steps in {ms64:.1f} ms ({plain:.2f} steps/s); L2 vs f64 {l2:.3e}")
+    extra = {}
+    if args.dtype == "f32" and not args.no_bf16:
+        prob16, f16 = q.setup_workload(ctx, w, "bf16")
+        prob16.step(f16, W)
+        ms16 = _time_steps(torch, prob16, f16, K)
+        extra["bf16_steps_per_s"] = K / (ms16 / 1e3)
+        extra["bf16_l2_err_vs_f64"] = q.l2_diff(ctx, f16, f64) if plain else None
+        extra["bf16_mass_after"] = prob16.observable(f16, "mass")
+        log(f"bf16: {K} steps in {ms16:.1f} ms; L2 vs f64 {extra['bf16_l2_err_vs_f64']}")
     mass = prob.observable(f, "mass")
     disc, norm2 = prob.step_info()
 
+    if args.op_log:
+        os.environ["QTTPDF_PROFILE_LOG"] = os.path.abspath(args.op_log)
+        prob.profile(f, 1, "all")
+        del os.environ["QTTPDF_PROFILE_LOG"]
     roof, rows = _roofline(prob, f, args.dtype)
     log(f"kernel classes: {rows}")
     cpu = None if args.no_cpu_baseline else _cpu_baseline(w)
@@ -163,6 +180,7 @@ def main():
         "l2_err_vs_f64": l2,
         "mass_after": mass,
         "discarded_weight_last_rounding": float(sum(disc)),
+        **extra,
         "roofline": roof,
         "kernel_classes": rows,
         "cpu_baseline": cpu,

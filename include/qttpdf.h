@@ -239,9 +239,12 @@ tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps);
 /* Measurement: runs n_steps steps of the recorded step eagerly (no graph)
  * with a pair of HIP events around every launch of one kernel class --
  * 0 contractions (tensor-contraction kernels), 1 Householder QR, 2 batched
- * eigen-decompositions, 3 streaming block copies -- and returns the summed
- * event time in ms, the number of such launches, and their algorithmic flops
- * and bytes (operands read once, results written once).  f is advanced. */
+ * eigen-decompositions, 3 streaming block copies, 4 every launch -- and
+ * returns the summed event time in ms, the number of such launches, and
+ * their algorithmic flops and bytes (operands read once, results written
+ * once).  With the environment variable QTTPDF_PROFILE_LOG naming a file,
+ * one line per timed launch (plan index, class, ms, flops, shape) is
+ * appended to it.  f is advanced. */
 tt_status tt_profile(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps, int kernel, double* ms,
                      int64_t* launches, double* flops, double* bytes);
 

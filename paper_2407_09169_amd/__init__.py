@@ -33,7 +33,7 @@ EXPORTS = [
     "tt_step", "tt_profile", "tt_step_info", "tt_observable", "tt_mean_field",
     "tt_linalg_qr", "tt_linalg_eigh",
 ]
-KERNELS = {"contract": 0, "qr": 1, "eig": 2, "stream": 3}
+KERNELS = {"contract": 0, "qr": 1, "eig": 2, "stream": 3, "all": 4}
 
 
 class TTParams(C.Structure):

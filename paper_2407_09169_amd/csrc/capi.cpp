@@ -930,7 +930,7 @@ tt_status tt_profile(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps, int k
     QTT_REQUIRE(prob && f && n_steps >= 1, "bad argument");
     check_tt(f, ctx);
     QTT_REQUIRE(f->caps == prob->fcaps, "state caps differ from the problem's");
-    QTT_REQUIRE(kernel >= 0 && kernel <= 3, "unknown kernel class %d", kernel);
+    QTT_REQUIRE(kernel >= 0 && kernel <= 4, "unknown kernel class %d", kernel);
     if (!prob->plan || prob->plan_f != f) build_step_plan(prob, f);
     StreamScope sc(ctx);
     double t = 0, fl = 0, by = 0;

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <functional>
+#include <string>
 #include <memory>
 #include <unordered_map>
 
@@ -54,11 +55,12 @@ ChainView view(const tt_tt* t);
 ChainView view_sites(const tt_tt* t, int first, int count);  // sub-chain (bond caps as stored)
 
 // kernel classes of a plan (for per-class timing)
-enum OpKind { OP_OTHER = -1, OP_CONTRACT = 0, OP_QR = 1, OP_EIG = 2, OP_STREAM = 3 };
+enum OpKind { OP_OTHER = -1, OP_CONTRACT = 0, OP_QR = 1, OP_EIG = 2, OP_STREAM = 3, OP_ALL = 4 };
 struct OpInfo {
   int kind = OP_OTHER;
   double flops = 0.0;  // algorithmic flops of the launch
   double bytes = 0.0;  // algorithmic bytes (operands read once, results written once)
+  std::string what;    // shape description for per-op timing logs
 };
 
 // list of enqueue operations with the workspaces they use
@@ -83,8 +85,10 @@ struct Plan {
   void run(hipStream_t s) const {
     for (auto& f : ops) f(s);
   }
-  // eager run with a pair of events around every op of class `kind`; adds the
-  // event time (ms), the number of such ops and their flops / bytes
+  // eager run with a pair of events around every op of class `kind` (OP_ALL:
+  // every op); adds the event time (ms), the number of such ops and their
+  // flops / bytes.  With QTTPDF_PROFILE_LOG=<file> set, one line per timed op
+  // (index, class, ms, flops, shape) is appended to that file.
   void run_profiled(hipStream_t s, int kind, double& ms, int64_t& count, double& flops,
                     double& bytes) const;
 };

@@ -6,6 +6,9 @@
 // workspaces it needs at planning time, so that a plan can be replayed many
 // times (eagerly or captured as a HIP graph) without allocations.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
 
 #include "library.h"
 
@@ -72,6 +75,10 @@ static void add_tc(Plan& plan, TcDesc d, Prec p) {
   double nb = (mode_max(d.bb, d.batch) == 0) ? 1.0 : d.batch;
   oi.bytes = 8.0 * (na * d.M * (double)d.K + nb * d.K * (double)d.N +
                     (d.beta != 0.0 ? 2.0 : 1.0) * d.batch * d.M * (double)d.N);
+  char w[96];
+  snprintf(w, sizeof w, "tc %s b%d m%d n%d k%d", p == Prec::F64 ? "f64" : (p == Prec::F32 ? "f32" : "bf16"),
+           d.batch, d.M, d.N, d.K);
+  oi.what = w;
   plan.add([d, p](hipStream_t s) { tc_launch(d, p, s); }, oi);
 }
 
@@ -80,6 +87,7 @@ static OpInfo qr_info(int m, int n) {
   oi.kind = OP_QR;
   oi.flops = 2.0 * (2.0 * m * (double)n * n - 2.0 * n * (double)n * n / 3.0);
   oi.bytes = 8.0 * 2.0 * m * (double)n;
+  oi.what = "qr m" + std::to_string(m) + " n" + std::to_string(n);
   return oi;
 }
 
@@ -87,7 +95,7 @@ void Plan::run_profiled(hipStream_t s, int kind, double& ms, int64_t& count, dou
                         double& bytes) const {
   std::vector<size_t> idx;
   for (size_t i = 0; i < ops.size(); ++i)
-    if (info[i].kind == kind) idx.push_back(i);
+    if (kind == OP_ALL || info[i].kind == kind) idx.push_back(i);
   std::vector<hipEvent_t> ev(2 * idx.size(), nullptr);
   if (!rt::dry())
     for (auto& e : ev) QTT_HIP(hipEventCreate(&e));
@@ -105,14 +113,20 @@ void Plan::run_profiled(hipStream_t s, int kind, double& ms, int64_t& count, dou
     }
   }
   rt::sync(s);
-  if (!rt::dry()) {
-    for (size_t k = 0; k < idx.size(); ++k) {
-      float t = 0.f;
-      QTT_HIP(hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]));
-      ms += t;
-    }
-    for (auto& e : ev) (void)hipEventDestroy(e);
+  const char* logp = std::getenv("QTTPDF_PROFILE_LOG");
+  FILE* log = logp ? std::fopen(logp, "a") : nullptr;
+  for (size_t k = 0; k < idx.size(); ++k) {
+    float t = 0.f;
+    if (!rt::dry()) QTT_HIP(hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]));
+    ms += t;
+    const OpInfo& oi = info[idx[k]];
+    if (log)
+      std::fprintf(log, "%zu %d %.6f %.6g %s\n", idx[k], oi.kind, (double)t, oi.flops,
+                   oi.what.empty() ? "-" : oi.what.c_str());
   }
+  if (log) std::fclose(log);
+  if (!rt::dry())
+    for (auto& e : ev) (void)hipEventDestroy(e);
 }
 
 static void add_gemm(Plan& plan, int M, int N, int K, const double* A, int64_t lda, bool ta,
@@ -176,6 +190,7 @@ static void plan_trunc_gram(Plan& plan, const std::vector<double*>& X, const std
     int cnt = N - 1;
     OpInfo oi;
     oi.kind = OP_EIG;
+    oi.what = "eig count" + std::to_string(cnt) + " nmax" + std::to_string(lmax);
     for (int n = 1; n < N; ++n) oi.bytes += 8.0 * ((double)ell[n] * ell[n] + (double)ell[n] * tg.caps[n]);
     plan.add([=](hipStream_t s) {
       eig_launch(cnt, d_dims, d_keep, g1, (int64_t)ldg * ldg, ldg, p1, (int64_t)ldg * ldp, ldp, l1,
