@@ -181,6 +181,9 @@ inline Mode2 mode2(int32_t n2, int64_t s1, int64_t s2) {
 }
 
 // C[b](m,n) = alpha * sum_k A[b](m,k) B[b](k,n) + beta * C[b](m,n)
+// With ksplit > 1 the K range is cut into ksplit chunks whose raw partial
+// sums go to part ([batch][ksplit][M][N], dense) and a second kernel adds
+// them in a fixed order into C.
 struct TcDesc {
   int32_t M = 0, N = 0, K = 0, batch = 1;
   Mode2 am, ak, ab;
@@ -190,6 +193,8 @@ struct TcDesc {
   const double* A = nullptr;
   const double* B = nullptr;
   double* C = nullptr;
+  int32_t ksplit = 1;
+  double* part = nullptr;
 };
 
 // precision of the contraction kernels (inputs are rounded to it, accumulation
@@ -197,6 +202,9 @@ struct TcDesc {
 enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
 
 void tc_launch(const TcDesc& d, Prec p, hipStream_t s);
+// number of K chunks worth splitting a contraction into (1: no split); the
+// caller provides the partial-sum buffer of batch * ksplit * M * N doubles
+int tc_choose_ksplit(const TcDesc& d, Prec p);
 // host-side bounds check of a contraction against the allocation registry
 void tc_validate(const TcDesc& d);
 

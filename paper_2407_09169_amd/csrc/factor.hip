@@ -14,10 +14,63 @@ namespace {
 constexpr int FT = 256;  // threads per factorisation workgroup
 constexpr int FW = FT / 64;
 
-__device__ inline double wave_sum(double v) {
+// Wavefront reductions of doubles without LDS traffic: four DPP steps sum
+// the 16 lanes of every row (quad xor 1, quad xor 2, half-row mirror, row
+// mirror; each leaves the partial sum in every lane of its group), then
+// row_bcast:15 adds row 0 into row 1 and row 2 into row 3, row_bcast:31 adds
+// rows 0+1 into rows 2 and 3, and lane 63, which now holds the total, is read
+// into scalar registers, so every lane gets the same value.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ inline double read_lane(double x, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+struct OpAdd {
+  __device__ static double f(double a, double b) { return a + b; }
+};
+struct OpMax {
+  __device__ static double f(double a, double b) { return fmax(a, b); }
+};
+
+template <class Op, int K>
+__device__ inline void wave_reduce_n(double (&v)[K]) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  for (int k = 0; k < K; ++k) v[k] = Op::f(v[k], dpp_move<0xB1, 0xF>(v[k]));  // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = Op::f(v[k], dpp_move<0x4E, 0xF>(v[k]));  // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = Op::f(v[k], dpp_move<0x141, 0xF>(v[k]));  // row_half_mirror
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = Op::f(v[k], dpp_move<0x140, 0xF>(v[k]));  // row_mirror
+  // rows outside the row mask receive 0, the identity of both operations here
+  // (the max is only taken over non-negative values)
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = Op::f(v[k], dpp_move<0x142, 0xA>(v[k]));  // row_bcast:15 into rows 1, 3
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = Op::f(v[k], dpp_move<0x143, 0xC>(v[k]));  // row_bcast:31 into rows 2, 3
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = read_lane(v[k], 63);
+}
+
+template <int K>
+__device__ inline void wave_sum_n(double (&v)[K]) {
+  wave_reduce_n<OpAdd, K>(v);
+}
+
+__device__ inline double wave_sum(double v) {
+  double a[1] = {v};
+  wave_sum_n<1>(a);
+  return a[0];
 }
 
 __device__ inline double block_sum(double v, double* red) {
@@ -130,52 +183,49 @@ __global__ __launch_bounds__(FT) void qr_kernel(int m, int n, const double* __re
 }
 
 // ---------------------------------------------------------------------------
-// Register-resident Householder QR for m <= 64*RS, n <= 16*CPW: 16 wavefronts,
-// column c lives in wavefront c % 16 (slot c / 16), row r in lane r % 64
+// Register-resident Householder QR for m <= 64*RS, n <= QW*CPW: QW wavefronts,
+// column c lives in wavefront c % QW (slot c / QW), row r in lane r % 64
 // (slot r / 64).  Step k: the owner of column k builds the reflector with one
 // wavefront reduction and publishes v (double-buffered LDS); one barrier;
-// every wavefront applies it to its columns with interleaved wavefront
-// reductions.  Q is formed in place by backward accumulation.
+// every wavefront applies it to its columns c > k, CH column reductions at a
+// time, skipping the row slots above k where v vanishes.  Q is formed in
+// place by backward accumulation.
 // ---------------------------------------------------------------------------
-constexpr int QR_CHUNK = 3;
-
-// a[:, j] -= t (v^T a[:, j]) v for the columns c = wave + QW*j with k < c < n;
-// the wavefront reductions of QR_CHUNK columns are interleaved.
-template <int RS, int CPW, int QW>
+template <int RS, int CPW, int QW, int CH>
 __device__ inline void apply_reflector(double (&a)[RS][CPW], const double (&v)[RS], double t, int k,
-                                       int n, int wave) {
+                                       int n, int wave, int i0) {
 #pragma unroll
-  for (int j0 = 0; j0 < CPW; j0 += QR_CHUNK) {
-    double d[QR_CHUNK];
+  for (int j0 = 0; j0 < CPW; j0 += CH) {
+    const int jl = (j0 + CH - 1 < CPW) ? j0 + CH - 1 : CPW - 1;
+    if (wave + QW * jl <= k) continue;  // every column of the chunk is done
+    if (wave + QW * j0 >= n) break;     // past the last column
+    double d[CH];
 #pragma unroll
-    for (int jj = 0; jj < QR_CHUNK; ++jj) {
+    for (int jj = 0; jj < CH; ++jj) {
+      const int j = (j0 + jj < CPW) ? j0 + jj : CPW - 1;
       double p = 0.0;
-      if (j0 + jj < CPW) {
 #pragma unroll
-        for (int i = 0; i < RS; ++i) p += v[i] * a[i][(j0 + jj < CPW) ? j0 + jj : 0];
-      }
+      for (int i = 0; i < RS; ++i)
+        if (i >= i0) p += v[i] * a[i][j];
       d[jj] = p;
     }
+    wave_sum_n<CH>(d);
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
+    for (int jj = 0; jj < CH; ++jj) {
+      if (j0 + jj >= CPW) continue;
+      const int j = (j0 + jj < CPW) ? j0 + jj : CPW - 1;
+      const int c = wave + QW * j;
+      if (c > k && c < n) {
+        const double w = t * d[jj];
 #pragma unroll
-      for (int jj = 0; jj < QR_CHUNK; ++jj) d[jj] += __shfl_xor(d[jj], off, 64);
-#pragma unroll
-    for (int jj = 0; jj < QR_CHUNK; ++jj) {
-      const int j = j0 + jj;
-      if (j < CPW) {
-        const int c = wave + QW * j;
-        if (c > k && c < n) {
-          const double w = t * d[jj];
-#pragma unroll
-          for (int i = 0; i < RS; ++i) a[i][j < CPW ? j : 0] -= w * v[i];
-        }
+        for (int i = 0; i < RS; ++i)
+          if (i >= i0) a[i][j] -= w * v[i];
       }
     }
   }
 }
 
-template <int RS, int CPW, int QW>
+template <int RS, int CPW, int QW, int CH>
 __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const double* __restrict__ A0,
                                                       int64_t strideA, int64_t rs, int64_t cs,
                                                       double* __restrict__ Q0, int64_t strideQ,
@@ -183,7 +233,8 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
   __shared__ double vbuf[2][64 * RS];
   __shared__ double taus[QW * CPW];
   __shared__ double betas[QW * CPW];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t bi = blockIdx.x;
   const double* A = A0 + bi * strideA;
   double a[RS][CPW];
@@ -197,7 +248,7 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
     }
   }
   for (int k = 0; k < n; ++k) {
-    const int owner = k % QW, jk = k / QW, buf = k & 1;
+    const int owner = k % QW, jk = k / QW, buf = k & 1, i0 = k >> 6;
     if (wave == owner) {
       double col[RS];
 #pragma unroll
@@ -212,10 +263,10 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
       for (int i = 0; i < RS; ++i) {
         const int r = lane + 64 * i;
         if (r > k) part += col[i] * col[i];
-        if (r == k) xk = col[i];
+        if (i == i0) xk = col[i];
       }
       const double sig = wave_sum(part);
-      const double x0 = wave_sum(xk);
+      const double x0 = read_lane(xk, k & 63);
       double tau = 0.0, beta = x0, scale = 0.0;
       if (sig != 0.0) {
         const double nrm = sqrt(x0 * x0 + sig);
@@ -244,8 +295,8 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
     if (t != 0.0) {
       double v[RS];
 #pragma unroll
-      for (int i = 0; i < RS; ++i) v[i] = vbuf[buf][lane + 64 * i];
-      apply_reflector<RS, CPW, QW>(a, v, t, k, n, wave);
+      for (int i = 0; i < RS; ++i) v[i] = (i >= i0) ? vbuf[buf][lane + 64 * i] : 0.0;
+      apply_reflector<RS, CPW, QW, CH>(a, v, t, k, n, wave, i0);
     }
   }
   __syncthreads();
@@ -264,7 +315,7 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
     }
   }
   for (int k = n - 1; k >= 0; --k) {
-    const int owner = k % QW, jk = k / QW, buf = k & 1;
+    const int owner = k % QW, jk = k / QW, buf = k & 1, i0 = k >> 6;
     if (wave == owner) {
 #pragma unroll
       for (int i = 0; i < RS; ++i) {
@@ -279,10 +330,8 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
     const double t = taus[k];
     double v[RS];
 #pragma unroll
-    for (int i = 0; i < RS; ++i) v[i] = vbuf[buf][lane + 64 * i];
-    if (t != 0.0) {
-      apply_reflector<RS, CPW, QW>(a, v, t, k, n, wave);
-    }
+    for (int i = 0; i < RS; ++i) v[i] = (i >= i0) ? vbuf[buf][lane + 64 * i] : 0.0;
+    if (t != 0.0) apply_reflector<RS, CPW, QW, CH>(a, v, t, k, n, wave, i0);
     if (wave == owner) {
 #pragma unroll
       for (int i = 0; i < RS; ++i) {
@@ -405,11 +454,15 @@ __global__ __launch_bounds__(FT) void eig_kernel(const int* dims, const int* kee
 // Register-resident one-sided Jacobi for PSD G (n <= 2*NW*PPW, n <= 64*RS):
 // the n columns of W = G J and of V = J are held as NP = ceil(n/2) column
 // pairs ("slots"), PPW slots per wavefront, rows across lanes.  Each round
-// rotates every pair (three interleaved wavefront reductions per pair), then
+// rotates every pair: one wavefront reduction per pair for the cross product
+// g = w_p . w_q (all PPW of a wavefront reduced together); the squared column
+// norms are kept in LDS by column id, measured at the start of every sweep
+// and updated exactly by each rotation (a' = a - t g, b' = b + t g).  Then
 // the columns move one slot around the round-robin circle (slot 0 top fixed):
 // within a wavefront by register moves, across wavefronts through a
-// double-buffered LDS hand-off, one barrier per round.  n - 1 rounds make a
-// sweep in which every pair of columns meets once.
+// double-buffered LDS hand-off, one barrier per round.  2 NP - 1 rounds make
+// a sweep in which every pair of columns meets once; sweeps repeat until no
+// pair needs a rotation.
 // ---------------------------------------------------------------------------
 template <int RS, int PPW, int NW, int CH>
 __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const int* keep,
@@ -422,8 +475,9 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
   __shared__ double xB[2][NW][2][64 * RS];  // outgoing first bottom column (W, V) per wave
   __shared__ int xTid[2][NW], xBid[2][NW];
   __shared__ int rot_any;
-  __shared__ double lam_s[2 * NW * PPW + 2];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ double cn[2 * NW * PPW + 2];  // squared column norms (later eigenvalues) by id
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t bi = blockIdx.x;
   const int n = dims[bi];
   const int kk = keep[bi];
@@ -454,44 +508,67 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
   const int rounds = 2 * NP - 1;
   int parity = 0;
   for (int sweep = 0; sweep < 40; ++sweep) {
+    // exact squared norms of every column
+#pragma unroll
+    for (int j0 = 0; j0 < PPW; j0 += CH) {
+      double nn[2 * CH];
+#pragma unroll
+      for (int jj = 0; jj < CH; ++jj) {
+        const int j = (j0 + jj < PPW) ? j0 + jj : PPW - 1;
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int i = 0; i < RS; ++i) {
+          a += wt[j][i] * wt[j][i];
+          b += wb[j][i] * wb[j][i];
+        }
+        nn[2 * jj] = a;
+        nn[2 * jj + 1] = b;
+      }
+      wave_sum_n<2 * CH>(nn);
+      if (lane == 0) {
+#pragma unroll
+        for (int jj = 0; jj < CH; ++jj) {
+          const int j = (j0 + jj < PPW) ? j0 + jj : PPW - 1;
+          if (j0 + jj >= PPW || p0 + j >= NP) continue;
+          cn[it[j]] = nn[2 * jj];
+          cn[ib[j]] = nn[2 * jj + 1];
+        }
+      }
+    }
     if (threadIdx.x == 0) rot_any = 0;
     __syncthreads();
+    // a rotation is skipped when the cross product is below the rounding
+    // noise of the columns, eps * lambda_max * max(|w_p|, |w_q|)
+    double gfloor;
+    {
+      double mx[1] = {0.0};
+      for (int o = lane; o < 2 * NP; o += 64) mx[0] = fmax(mx[0], cn[o]);
+      wave_reduce_n<OpMax, 1>(mx);
+      gfloor = 2.220446049250313e-16 * sqrt(mx[0]);
+    }
     int rotated = 0;
     for (int rd = 0; rd < rounds; ++rd) {
-      // ---- rotate every active pair (reductions interleaved CH pairs at a time)
+      // ---- rotate every active pair, CH cross products reduced together
 #pragma unroll
       for (int j0 = 0; j0 < PPW; j0 += CH) {
-        double A_[CH], B_[CH], C_[CH];
+        double g[CH];
 #pragma unroll
         for (int jj = 0; jj < CH; ++jj) {
           const int j = (j0 + jj < PPW) ? j0 + jj : PPW - 1;
-          double a = 0.0, b = 0.0, g = 0.0;
+          double x = 0.0;
 #pragma unroll
-          for (int i = 0; i < RS; ++i) {
-            a += wt[j][i] * wt[j][i];
-            b += wb[j][i] * wb[j][i];
-            g += wt[j][i] * wb[j][i];
-          }
-          A_[jj] = a;
-          B_[jj] = b;
-          C_[jj] = g;
+          for (int i = 0; i < RS; ++i) x += wt[j][i] * wb[j][i];
+          g[jj] = x;
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-          for (int jj = 0; jj < CH; ++jj) {
-            A_[jj] += __shfl_xor(A_[jj], off, 64);
-            B_[jj] += __shfl_xor(B_[jj], off, 64);
-            C_[jj] += __shfl_xor(C_[jj], off, 64);
-          }
+        wave_sum_n<CH>(g);
 #pragma unroll
         for (int jj = 0; jj < CH; ++jj) {
-          if (j0 + jj >= PPW) continue;
           const int j = (j0 + jj < PPW) ? j0 + jj : PPW - 1;
           const int p = p0 + j;
-          const double a = A_[jj], b = B_[jj], g = C_[jj];
-          if (p < NP && g != 0.0 && fabs(g) > 1e-15 * sqrt(a * b)) {
-            const double zeta = (b - a) / (2.0 * g);
+          if (j0 + jj >= PPW || p >= NP) continue;
+          const double a = cn[it[j]], b = cn[ib[j]], gg = g[jj];
+          if (fabs(gg) > 1e-15 * sqrt(a * b) && fabs(gg) > gfloor * sqrt(fmax(a, b))) {
+            const double zeta = (b - a) / (2.0 * gg);
             const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
 #pragma unroll
@@ -503,10 +580,15 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
               vt[j][i] = c * u - s * z;
               vb[j][i] = s * u + c * z;
             }
+            if (lane == 0) {
+              cn[it[j]] = fmax(a - t * gg, 0.0);
+              cn[ib[j]] = fmax(b + t * gg, 0.0);
+            }
             rotated = 1;
           }
         }
       }
+      if (NP == 1) continue;  // a single pair never moves
       // ---- move one slot around the circle
 #pragma unroll
       for (int i = 0; i < RS; ++i) {
@@ -521,10 +603,6 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
       }
       __syncthreads();
       const int wl = (w > 0) ? w - 1 : 0, wr = (w < NW - 1) ? w + 1 : w;
-      if (NP == 1) {  // a single pair never moves
-        parity ^= 1;
-        continue;
-      }
       // bottoms move left: slot p takes the bottom of p+1; the last slot its own top
 #pragma unroll
       for (int j = 0; j < PPW; ++j) {
@@ -592,31 +670,30 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
     if (!any) break;
   }
   // eigenvalues: column norms of W (PSD: |G v| = lambda)
-  double nt_[PPW], nb_[PPW];
 #pragma unroll
-  for (int j = 0; j < PPW; ++j) {
-    double a = 0.0, b = 0.0;
+  for (int j0 = 0; j0 < PPW; j0 += CH) {
+    double nn[2 * CH];
 #pragma unroll
-    for (int i = 0; i < RS; ++i) {
-      a += wt[j][i] * wt[j][i];
-      b += wb[j][i] * wb[j][i];
+    for (int jj = 0; jj < CH; ++jj) {
+      const int j = (j0 + jj < PPW) ? j0 + jj : PPW - 1;
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int i = 0; i < RS; ++i) {
+        a += wt[j][i] * wt[j][i];
+        b += wb[j][i] * wb[j][i];
+      }
+      nn[2 * jj] = a;
+      nn[2 * jj + 1] = b;
     }
-    nt_[j] = a;
-    nb_[j] = b;
-  }
+    wave_sum_n<2 * CH>(nn);
+    if (lane == 0) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int j = 0; j < PPW; ++j) {
-      nt_[j] += __shfl_xor(nt_[j], off, 64);
-      nb_[j] += __shfl_xor(nb_[j], off, 64);
-    }
-  if (lane == 0) {
-#pragma unroll
-    for (int j = 0; j < PPW; ++j) {
-      if (p0 + j >= NP) continue;
-      lam_s[it[j]] = sqrt(nt_[j]);
-      lam_s[ib[j]] = sqrt(nb_[j]);
+      for (int jj = 0; jj < CH; ++jj) {
+        const int j = (j0 + jj < PPW) ? j0 + jj : PPW - 1;
+        if (j0 + jj >= PPW || p0 + j >= NP) continue;
+        cn[it[j]] = sqrt(nn[2 * jj]);
+        cn[ib[j]] = sqrt(nn[2 * jj + 1]);
+      }
     }
   }
   __syncthreads();
@@ -628,11 +705,12 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
       if (p0 + j >= NP) continue;
       const int id = half ? ib[j] : it[j];
       if (id >= n) continue;
-      const double v = lam_s[id];
+      const double v = cn[id];
       int cnt = 0;
-      for (int o = lane; o < n; o += 64) cnt += (lam_s[o] > v) || (lam_s[o] == v && o < id);
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+      for (int o = lane; o < n; o += 64) cnt += (cn[o] > v) || (cn[o] == v && o < id);
+      double cd[1] = {(double)cnt};
+      wave_sum_n<1>(cd);
+      cnt = (int)cd[0];
       if (lane == 0) L[cnt] = v;
       if (cnt < kk) {
 #pragma unroll
@@ -658,21 +736,21 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
   if (R) rt::check_range(R, 0, (int64_t)(count - 1) * strideR + (int64_t)n * n - 1, sizeof(double), "qr R");
   rt::check_range(work, 0, (int64_t)count * m * n - 1, sizeof(double), "qr workspace");
   if (rt::dry()) return;
-#define QTT_QR_REG(RS_, CPW_, NW_)                                                                \
+#define QTT_QR_REG(RS_, CPW_, NW_, CH_)                                                           \
   if (m <= 64 * RS_ && n <= NW_ * CPW_) {                                                         \
-    hipLaunchKernelGGL((qr_reg_kernel<RS_, CPW_, NW_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
+    hipLaunchKernelGGL((qr_reg_kernel<RS_, CPW_, NW_, CH_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
                        strideA, rs, cs, Q, strideQ, R, strideR);                                 \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }
-  QTT_QR_REG(1, 1, 16)
-  QTT_QR_REG(1, 2, 16)
-  QTT_QR_REG(2, 2, 16)
-  QTT_QR_REG(2, 4, 16)
-  QTT_QR_REG(3, 6, 16)
-  QTT_QR_REG(4, 8, 16)
-  QTT_QR_REG(5, 9, 16)
-  QTT_QR_REG(5, 10, 16)
+  QTT_QR_REG(1, 1, 16, 1)
+  QTT_QR_REG(1, 2, 16, 2)
+  QTT_QR_REG(2, 2, 16, 2)
+  QTT_QR_REG(2, 4, 16, 4)
+  QTT_QR_REG(3, 6, 16, 3)
+  QTT_QR_REG(4, 8, 16, 4)
+  QTT_QR_REG(5, 9, 16, 3)
+  QTT_QR_REG(5, 10, 16, 2)
 #undef QTT_QR_REG
   hipLaunchKernelGGL(qr_kernel, dim3(count), dim3(FT), 0, s, m, n, A, strideA, rs, cs, Q, strideQ,
                      R, strideR, work);
@@ -702,10 +780,10 @@ void eig_launch(int count, const int* dims, const int* keep, const double* G, in
   }
   QTT_EIG_REG(1, 1, 4, 1)
   QTT_EIG_REG(1, 2, 8, 2)
-  QTT_EIG_REG(1, 4, 8, 3)
-  QTT_EIG_REG(2, 4, 8, 3)
-  QTT_EIG_REG(2, 8, 8, 2)
-  QTT_EIG_REG(3, 9, 8, 1)
+  QTT_EIG_REG(1, 4, 8, 4)
+  QTT_EIG_REG(2, 4, 8, 4)
+  QTT_EIG_REG(2, 8, 8, 4)
+  QTT_EIG_REG(3, 6, 12, 2)
 #undef QTT_EIG_REG
   hipLaunchKernelGGL(eig_kernel, dim3(count), dim3(FT), 0, s, dims, keep, G, strideG, ldg, P,
                      strideP, ldp, lam, strideL, work);

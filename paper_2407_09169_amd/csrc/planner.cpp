@@ -67,6 +67,8 @@ static Mode2 M1(int64_t s) { return mode1(s); }
 static Mode2 M2(int n2, int64_t s1, int64_t s2) { return mode2(n2, s1, s2); }
 
 static void add_tc(Plan& plan, TcDesc d, Prec p) {
+  d.ksplit = tc_choose_ksplit(d, p);
+  if (d.ksplit > 1) d.part = plan.alloc((size_t)d.batch * d.ksplit * d.M * d.N);
   tc_validate(d);
   OpInfo oi;
   oi.kind = OP_CONTRACT;
@@ -75,9 +77,9 @@ static void add_tc(Plan& plan, TcDesc d, Prec p) {
   double nb = (mode_max(d.bb, d.batch) == 0) ? 1.0 : d.batch;
   oi.bytes = 8.0 * (na * d.M * (double)d.K + nb * d.K * (double)d.N +
                     (d.beta != 0.0 ? 2.0 : 1.0) * d.batch * d.M * (double)d.N);
-  char w[96];
-  snprintf(w, sizeof w, "tc %s b%d m%d n%d k%d", p == Prec::F64 ? "f64" : (p == Prec::F32 ? "f32" : "bf16"),
-           d.batch, d.M, d.N, d.K);
+  char w[112];
+  snprintf(w, sizeof w, "tc %s b%d m%d n%d k%d s%d", p == Prec::F64 ? "f64" : (p == Prec::F32 ? "f32" : "bf16"),
+           d.batch, d.M, d.N, d.K, d.ksplit);
   oi.what = w;
   plan.add([d, p](hipStream_t s) { tc_launch(d, p, s); }, oi);
 }

@@ -10,7 +10,10 @@
 //   * FP32: v_mfma_f32_16x16x4f32, FP32 accumulation;
 //   * BF16: v_mfma_f32_16x16x32_bf16 (CDNA4), FP32 accumulation.
 // The MFMA kernels read the FP64 operands, round them to FP32 / BF16 while
-// staging the tiles in LDS, and write FP64 results.
+// staging the tiles in LDS, and write FP64 results.  All kernels load the
+// next K tile into registers while the current one is being multiplied.
+// Contractions with few output tiles and a long K are split along K
+// (TcDesc::ksplit); their partial sums are added by tc_splitk_reduce.
 #include "common.h"
 
 namespace qtt {
@@ -19,42 +22,70 @@ namespace {
 
 constexpr int BK64 = 16;
 
+struct KRange {
+  int z, beg, end;
+};
+
+template <int BK>
+__device__ inline KRange k_range(const TcDesc& d) {
+  const int ks = (int)(blockIdx.z % (unsigned)d.ksplit);
+  const int z = (int)(blockIdx.z / (unsigned)d.ksplit);
+  const int chunk = ((d.K + d.ksplit - 1) / d.ksplit + BK - 1) / BK * BK;
+  const int beg = ks * chunk;
+  const int end = min(d.K, beg + chunk);
+  return {z, beg, end};
+}
+
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void tc_f64_kernel(TcDesc d, int a_kfast, int b_nfast) {
   constexpr int TM = BM / 16, TN = BN / 16;
+  constexpr int NA = BM * BK64 / 256, NB = BN * BK64 / 256;
   __shared__ double As[BK64][BM + 1];
   __shared__ double Bs[BK64][BN + 1];
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int z = blockIdx.z;
-  const double* A = d.A + d.ab.off(z);
-  const double* B = d.B + d.bb.off(z);
-  double* C = d.C + d.cb.off(z);
+  const KRange kr = k_range<BK64>(d);
+  const double* A = d.A + d.ab.off(kr.z);
+  const double* B = d.B + d.bb.off(kr.z);
   double acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = 0.0;
-
-  for (int k0 = 0; k0 < d.K; k0 += BK64) {
-    for (int e = tid; e < BM * BK64; e += 256) {
-      int mm, kk;
-      if (a_kfast) { kk = e % BK64; mm = e / BK64; } else { mm = e % BM; kk = e / BM; }
-      int m = m0 + mm, k = k0 + kk;
-      double v = 0.0;
-      if (m < d.M && k < d.K) v = A[d.am.off(m) + d.ak.off(k)];
-      As[kk][mm] = v;
+  double ra[NA], rb[NB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      const int mm = a_kfast ? e / BK64 : e % BM, kk = a_kfast ? e % BK64 : e / BM;
+      const int m = m0 + mm, k = k0 + kk;
+      ra[q] = (m < d.M && k < kr.end) ? A[d.am.off(m) + d.ak.off(k)] : 0.0;
     }
-    for (int e = tid; e < BN * BK64; e += 256) {
-      int nn, kk;
-      if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % BK64; nn = e / BK64; }
-      int n = n0 + nn, k = k0 + kk;
-      double v = 0.0;
-      if (n < d.N && k < d.K) v = B[d.bk.off(k) + d.bn.off(n)];
-      Bs[kk][nn] = v;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      const int nn = b_nfast ? e % BN : e / BK64, kk = b_nfast ? e / BN : e % BK64;
+      const int n = n0 + nn, k = k0 + kk;
+      rb[q] = (n < d.N && k < kr.end) ? B[d.bk.off(k) + d.bn.off(n)] : 0.0;
+    }
+  };
+  if (kr.beg < kr.end) load(kr.beg);
+  for (int k0 = kr.beg; k0 < kr.end; k0 += BK64) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      const int mm = a_kfast ? e / BK64 : e % BM, kk = a_kfast ? e % BK64 : e / BM;
+      As[kk][mm] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      const int nn = b_nfast ? e % BN : e / BK64, kk = b_nfast ? e / BN : e % BK64;
+      Bs[kk][nn] = rb[q];
     }
     __syncthreads();
+    if (k0 + BK64 < kr.end) load(k0 + BK64);
 #pragma unroll 4
     for (int kk = 0; kk < BK64; ++kk) {
       double a[TM], b[TN];
@@ -69,14 +100,29 @@ __global__ __launch_bounds__(256) void tc_f64_kernel(TcDesc d, int a_kfast, int 
     }
     __syncthreads();
   }
+  if (d.ksplit > 1) {
+    double* Pp = d.part + (int64_t)blockIdx.z * d.M * d.N;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int m = m0 + ty + 16 * i;
+      if (m >= d.M) continue;
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = n0 + tx + 16 * j;
+        if (n < d.N) Pp[(int64_t)m * d.N + n] = acc[i][j];
+      }
+    }
+    return;
+  }
+  double* C = d.C + d.cb.off(kr.z);
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
-    int m = m0 + ty + 16 * i;
+    const int m = m0 + ty + 16 * i;
     if (m >= d.M) continue;
-    int64_t rowoff = d.cm.off(m);
+    const int64_t rowoff = d.cm.off(m);
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
-      int n = n0 + tx + 16 * j;
+      const int n = n0 + tx + 16 * j;
       if (n >= d.N) continue;
       double* p = C + rowoff + d.cn.off(n);
       double v = d.alpha * acc[i][j];
@@ -95,6 +141,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 template <bool BF16>
 __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d, int a_kfast, int b_nfast) {
   constexpr int BM = 64, BN = 64, BK = 32;
+  constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
   using TIn = typename std::conditional<BF16, __bf16, float>::type;
   constexpr int PAD = BF16 ? 8 : 4;
   __shared__ TIn As[BM][BK + PAD];
@@ -103,35 +150,48 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d, int a_kfast, int
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const int z = blockIdx.z;
-  const double* A = d.A + d.ab.off(z);
-  const double* B = d.B + d.bb.off(z);
-  double* C = d.C + d.cb.off(z);
+  const KRange kr = k_range<BK>(d);
+  const double* A = d.A + d.ab.off(kr.z);
+  const double* B = d.B + d.bb.off(kr.z);
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int li = lane & 15, lq = lane >> 4;
-
-  for (int k0 = 0; k0 < d.K; k0 += BK) {
-    for (int e = tid; e < BM * BK; e += 256) {
-      int mm, kk;
-      if (a_kfast) { kk = e % BK; mm = e / BK; } else { mm = e % BM; kk = e / BM; }
-      int m = m0 + mm, k = k0 + kk;
-      double v = 0.0;
-      if (m < d.M && k < d.K) v = A[d.am.off(m) + d.ak.off(k)];
-      As[mm][kk] = (TIn)(float)v;
+  double ra[NA], rb[NB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      const int mm = a_kfast ? e / BK : e % BM, kk = a_kfast ? e % BK : e / BM;
+      const int m = m0 + mm, k = k0 + kk;
+      ra[q] = (m < d.M && k < kr.end) ? A[d.am.off(m) + d.ak.off(k)] : 0.0;
     }
-    for (int e = tid; e < BN * BK; e += 256) {
-      int nn, kk;
-      if (b_nfast) { nn = e % BN; kk = e / BN; } else { kk = e % BK; nn = e / BK; }
-      int n = n0 + nn, k = k0 + kk;
-      double v = 0.0;
-      if (n < d.N && k < d.K) v = B[d.bk.off(k) + d.bn.off(n)];
-      Bs[nn][kk] = (TIn)(float)v;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      const int nn = b_nfast ? e % BN : e / BK, kk = b_nfast ? e / BN : e % BK;
+      const int n = n0 + nn, k = k0 + kk;
+      rb[q] = (n < d.N && k < kr.end) ? B[d.bk.off(k) + d.bn.off(n)] : 0.0;
+    }
+  };
+  if (kr.beg < kr.end) load(kr.beg);
+  for (int k0 = kr.beg; k0 < kr.end; k0 += BK) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      const int mm = a_kfast ? e / BK : e % BM, kk = a_kfast ? e % BK : e / BM;
+      As[mm][kk] = (TIn)(float)ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      const int nn = b_nfast ? e % BN : e / BK, kk = b_nfast ? e / BN : e % BK;
+      Bs[nn][kk] = (TIn)(float)rb[q];
     }
     __syncthreads();
+    if (k0 + BK < kr.end) load(k0 + BK);
     if constexpr (BF16) {
       bf16x8 a[2], b[2];
 #pragma unroll
@@ -165,14 +225,29 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d, int a_kfast, int
     __syncthreads();
   }
   // accumulator layout: lane holds rows 4*(lane/16)+r, column lane%16 of each block
+  if (d.ksplit > 1) {
+    double* Pp = d.part + (int64_t)blockIdx.z * d.M * d.N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm + 16 * i + 4 * lq + r;
+          const int n = n0 + wn + 16 * j + li;
+          if (m < d.M && n < d.N) Pp[(int64_t)m * d.N + n] = (double)acc[i][j][r];
+        }
+    return;
+  }
+  double* C = d.C + d.cb.off(kr.z);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int m = m0 + wm + 16 * i + 4 * lq + r;
-        int n = n0 + wn + 16 * j + li;
+        const int m = m0 + wm + 16 * i + 4 * lq + r;
+        const int n = n0 + wn + 16 * j + li;
         if (m < d.M && n < d.N) {
           double* p = C + d.cm.off(m) + d.cn.off(n);
           double v = d.alpha * (double)acc[i][j][r];
@@ -182,13 +257,51 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d, int a_kfast, int
       }
 }
 
-inline bool unit(const Mode2& m) { return m.n2 == 0 ? (m.s2 == 1) : (m.s2 == 1); }
+// C = alpha * sum_s part[b][s] + beta * C, one thread per output element,
+// chunks added in increasing order
+__global__ __launch_bounds__(256) void tc_splitk_reduce(TcDesc d) {
+  const int64_t mn = (int64_t)d.M * d.N;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= mn * d.batch) return;
+  const int z = (int)(idx / mn);
+  const int64_t rem = idx - (int64_t)z * mn;
+  const int m = (int)(rem / d.N), n = (int)(rem - (int64_t)m * d.N);
+  const double* Pp = d.part + (int64_t)z * d.ksplit * mn + rem;
+  double s = 0.0;
+  for (int k = 0; k < d.ksplit; ++k) s += Pp[(int64_t)k * mn];
+  double* p = d.C + d.cb.off(z) + d.cm.off(m) + d.cn.off(n);
+  double v = d.alpha * s;
+  if (d.beta != 0.0) v += d.beta * *p;
+  *p = v;
+}
+
+inline bool unit(const Mode2& m) { return m.s2 == 1; }
+
+struct Tile {
+  int bm, bn;
+};
+inline Tile tile_of(const TcDesc& d, Prec p) {
+  if (p != Prec::F64) return {64, 64};
+  return {d.M >= 48 ? 64 : 32, d.N >= 48 ? 64 : 32};
+}
 
 }  // namespace
+
+int tc_choose_ksplit(const TcDesc& d, Prec p) {
+  if (d.M <= 0 || d.N <= 0 || d.batch <= 0 || d.K < 256) return 1;
+  const Tile t = tile_of(d, p);
+  const int64_t tiles = (int64_t)((d.M + t.bm - 1) / t.bm) * ((d.N + t.bn - 1) / t.bn) * d.batch;
+  if (tiles >= 128) return 1;
+  // aim at ~256 workgroups with at least 128 K values each
+  int ks = (int)std::min<int64_t>(d.K / 128, (256 + tiles - 1) / tiles);
+  ks = std::min(ks, 64);
+  return ks >= 2 ? ks : 1;
+}
 
 void tc_validate(const TcDesc& d) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
   QTT_REQUIRE(d.M < (1 << 30) && d.N < (1 << 30) && d.K < (1 << 30), "contraction extent too large");
+  QTT_REQUIRE(d.ksplit >= 1, "bad K split");
   if (d.K > 0) {
     rt::check_range(d.A, 0, mode_max(d.ab, d.batch) + mode_max(d.am, d.M) + mode_max(d.ak, d.K),
                     sizeof(double), "contraction operand A");
@@ -197,38 +310,41 @@ void tc_validate(const TcDesc& d) {
   }
   rt::check_range(d.C, 0, mode_max(d.cb, d.batch) + mode_max(d.cm, d.M) + mode_max(d.cn, d.N),
                   sizeof(double), "contraction result C");
+  if (d.ksplit > 1)
+    rt::check_range(d.part, 0, (int64_t)d.batch * d.ksplit * d.M * d.N - 1, sizeof(double),
+                    "contraction partial sums");
 }
 
 void tc_launch(const TcDesc& d, Prec p, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
   tc_validate(d);
   if (rt::dry()) return;
-  QTT_REQUIRE(d.batch <= 65535 && (d.M + 31) / 32 <= 65535, "contraction too large (M=%d batch=%d)",
-              d.M, d.batch);
-  int a_kfast = unit(d.ak) ? 1 : 0;
-  int b_nfast = unit(d.bn) ? 1 : 0;
+  QTT_REQUIRE((int64_t)d.batch * d.ksplit <= 65535 && (d.M + 31) / 32 <= 65535,
+              "contraction too large (M=%d batch=%d split=%d)", d.M, d.batch, d.ksplit);
+  const int a_kfast = unit(d.ak) ? 1 : 0;
+  const int b_nfast = unit(d.bn) ? 1 : 0;
+  const Tile t = tile_of(d, p);
+  const dim3 grid((d.N + t.bn - 1) / t.bn, (d.M + t.bm - 1) / t.bm, d.batch * d.ksplit);
   if (p == Prec::F64) {
-    if (d.M >= 48 && d.N >= 48) {
-      dim3 grid((d.N + 63) / 64, (d.M + 63) / 64, d.batch);
+    if (t.bm == 64 && t.bn == 64)
       hipLaunchKernelGGL((tc_f64_kernel<64, 64>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
-    } else if (d.M >= 48) {
-      dim3 grid((d.N + 31) / 32, (d.M + 63) / 64, d.batch);
+    else if (t.bm == 64)
       hipLaunchKernelGGL((tc_f64_kernel<64, 32>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
-    } else if (d.N >= 48) {
-      dim3 grid((d.N + 63) / 64, (d.M + 31) / 32, d.batch);
+    else if (t.bn == 64)
       hipLaunchKernelGGL((tc_f64_kernel<32, 64>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
-    } else {
-      dim3 grid((d.N + 31) / 32, (d.M + 31) / 32, d.batch);
-      hipLaunchKernelGGL((tc_f64_kernel<32, 32>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
-    }
-  } else {
-    dim3 grid((d.N + 63) / 64, (d.M + 63) / 64, d.batch);
-    if (p == Prec::BF16)
-      hipLaunchKernelGGL((tc_mfma_kernel<true>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
     else
-      hipLaunchKernelGGL((tc_mfma_kernel<false>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
+      hipLaunchKernelGGL((tc_f64_kernel<32, 32>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
+  } else if (p == Prec::BF16) {
+    hipLaunchKernelGGL((tc_mfma_kernel<true>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
+  } else {
+    hipLaunchKernelGGL((tc_mfma_kernel<false>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
   }
   QTT_HIP(hipGetLastError());
+  if (d.ksplit > 1) {
+    const int64_t tot = (int64_t)d.M * d.N * d.batch;
+    hipLaunchKernelGGL(tc_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, d);
+    QTT_HIP(hipGetLastError());
+  }
 }
 
 TcDesc gemm_desc(int M, int N, int K, const double* A, int64_t lda, bool transA, const double* B,
