@@ -34,9 +34,11 @@ def gaussian_sketch(N, ell, seed):
 def truncation_sensitivity(infos, eps=2.2e-16):
     """First-order size of the change of a simultaneous SVD truncation under
     rounding noise, relative to the norm: at bond n the kept subspace of the
-    Gram matrix moves by ~ m eps lambda_1 / (lambda_k - lambda_{k+1}); the
-    tensor moves by that angle times sigma_k.  Summed over bonds and
-    roundings.  Bonds with nothing discarded contribute nothing."""
+    Gram matrix moves by an angle ~ m eps lambda_1 / (lambda_k - lambda_{k+1})
+    (Davis-Kahan), at most 1 (a cut among eigenvalues at the noise level can
+    turn the kept vectors by any angle); the tensor moves by that angle times
+    sigma_k.  Summed over bonds and roundings.  Bonds with nothing discarded
+    contribute nothing."""
     total = 0.0
     for info in infos:
         lams, ranks = info["lams"], info["ranks"]
@@ -49,5 +51,5 @@ def truncation_sensitivity(infos, eps=2.2e-16):
             l1 = max(lam[0], 1e-300)
             gap = max(lam[k - 1] - lam[k], 1e-300 * l1)
             sk = np.sqrt(max(lam[k - 1], 0.0))
-            total += lam.size * eps * l1 / gap * sk / np.sqrt(l1)
+            total += min(1.0, lam.size * eps * l1 / gap) * sk / np.sqrt(l1)
     return total

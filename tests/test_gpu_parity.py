@@ -175,19 +175,25 @@ def test_step_untruncated_equals_dense(ctx, name, integrator):
 @pytest.mark.parametrize("name,integrator", [("t_5d_M8_chi16", "rk4"), ("c1_2d_M64", "rk4"),
                                              ("t_2d_M64_serial", "rk2")])
 def test_step_truncated_matches_oracle(ctx, name, integrator):
+    """Truncated FP64 steps agree with the oracle up to what rounding noise can
+    move a simultaneous SVD truncation: 10x the first-order sensitivity of the
+    oracle's own cuts (accumulated over the steps), plus 1e-10."""
     w = workloads.get_workload(name, integrator=integrator)
     st = stepper.MPSStepper(w)
     prob, f = q.setup_workload(ctx, w, "f64")
     fo = st.initial_state()
+    sens = 0.0
     for i in range(3):
         prob.step(f, 1)
-        fo, _ = st.step(fo)
+        fo, infos = st.step(fo)
+        sens += truncation_sensitivity(infos)
+        tol = 1e-10 + 10 * sens
         err = rel(_dense_of(st, f.cores()), st.to_dense(fo))
-        assert err < TRUNC_TOL, (name, i, err)
+        assert err < tol, (name, i, err, tol)
     obs_o = st.observables(fo)
     for k, v in obs_o.items():
         g = prob.observable(f, k)
-        assert abs(g - v) <= TRUNC_TOL * max(1.0, abs(v)), (k, g, v)
+        assert abs(g - v) <= tol * max(1.0, abs(v)), (k, g, v)
 
 
 def test_step_graph_replay_is_deterministic(ctx):
