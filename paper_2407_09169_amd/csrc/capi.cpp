@@ -1095,7 +1095,7 @@ tt_status tt_linalg_eigh(tt_ctx* ctx, int count, int n, int keep, const double* 
     rt::copy(dk.p, kp.data(), count * sizeof(int));
     fill(dP.d(), (int64_t)count * n * keep, 0.0, ctx->stream);
     eig_launch(count, dd.as<int>(), dk.as<int>(), dG.d(), (int64_t)nn, n, dP.d(), (int64_t)n * keep,
-               keep, dL.d(), n, dW.d(), n, ctx->stream);
+               keep, dL.d(), n, dW.d(), n, machine_eps(Prec::F64), ctx->stream);
     rt::sync(ctx->stream);
     rt::copy(P, dP.p, count * (size_t)n * keep * 8);
     rt::copy(lam, dL.p, count * (size_t)n * 8);

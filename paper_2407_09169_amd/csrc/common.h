@@ -229,9 +229,15 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
 // Writes the eigenvectors of the k_i = keep[i] largest eigenvalues as the
 // columns of P_i (n_i x k_i, row-major, ld = ldp, at P + i*strideP) and all
 // eigenvalues in descending order to lam + i*strideL.  `work` holds
-// count * ldg * ldg doubles.
+// count * ldg * ldg doubles.  `unoise` is the relative noise of the entries
+// of G (the machine epsilon of the arithmetic that produced it): couplings
+// below unoise * lambda_max times the column norm are not resolved.
 void eig_launch(int count, const int* dims, const int* keep, const double* G, int64_t strideG,
                 int ldg, double* P, int64_t strideP, int ldp, double* lam, int64_t strideL,
-                double* work, int max_n, hipStream_t s);
+                double* work, int max_n, double unoise, hipStream_t s);
+// machine epsilon of a contraction precision
+inline double machine_eps(Prec p) {
+  return p == Prec::F64 ? 2.220446049250313e-16 : (p == Prec::F32 ? 1.1920928955078125e-07 : 7.8125e-03);
+}
 
 }  // namespace qtt

@@ -470,7 +470,7 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
                                                           int64_t strideG, int ldg,
                                                           double* __restrict__ P0, int64_t strideP,
                                                           int ldp, double* __restrict__ L0,
-                                                          int64_t strideL) {
+                                                          int64_t strideL, double unoise) {
   __shared__ double xT[2][NW][2][64 * RS];  // outgoing last top column (W, V) per wave
   __shared__ double xB[2][NW][2][64 * RS];  // outgoing first bottom column (W, V) per wave
   __shared__ int xTid[2][NW], xBid[2][NW];
@@ -537,56 +537,77 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
     }
     if (threadIdx.x == 0) rot_any = 0;
     __syncthreads();
-    // a rotation is skipped when the cross product is below the rounding
-    // noise of the columns, eps * lambda_max * max(|w_p|, |w_q|)
-    double gfloor;
+    // a rotation is skipped when the cross product is below the noise of the
+    // columns, u * lambda_max * max(|w_p|, |w_q|) with u the relative noise of
+    // G (its precision), or below 1e-15 |w_p| |w_q|; compared in squares
+    double gf2;
     {
       double mx[1] = {0.0};
       for (int o = lane; o < 2 * NP; o += 64) mx[0] = fmax(mx[0], cn[o]);
       wave_reduce_n<OpMax, 1>(mx);
-      gfloor = 2.220446049250313e-16 * sqrt(mx[0]);
+      gf2 = unoise * unoise * mx[0];
     }
     int rotated = 0;
     for (int rd = 0; rd < rounds; ++rd) {
-      // ---- rotate every active pair, CH cross products reduced together
+      // ---- cross products of every pair of this wavefront (wave-uniform)
+      double g[PPW];
 #pragma unroll
       for (int j0 = 0; j0 < PPW; j0 += CH) {
-        double g[CH];
+        double gc[CH];
 #pragma unroll
         for (int jj = 0; jj < CH; ++jj) {
           const int j = (j0 + jj < PPW) ? j0 + jj : PPW - 1;
           double x = 0.0;
 #pragma unroll
           for (int i = 0; i < RS; ++i) x += wt[j][i] * wb[j][i];
-          g[jj] = x;
+          gc[jj] = x;
         }
-        wave_sum_n<CH>(g);
+        wave_sum_n<CH>(gc);
 #pragma unroll
-        for (int jj = 0; jj < CH; ++jj) {
-          const int j = (j0 + jj < PPW) ? j0 + jj : PPW - 1;
-          const int p = p0 + j;
-          if (j0 + jj >= PPW || p >= NP) continue;
-          const double a = cn[it[j]], b = cn[ib[j]], gg = g[jj];
-          if (fabs(gg) > 1e-15 * sqrt(a * b) && fabs(gg) > gfloor * sqrt(fmax(a, b))) {
-            const double zeta = (b - a) / (2.0 * gg);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        for (int jj = 0; jj < CH; ++jj)
+          if (j0 + jj < PPW) g[j0 + jj] = gc[jj];
+      }
+      // ---- rotation of pair j computed by lane j (t = tan of the angle that
+      // makes the pair orthogonal, the root of smaller modulus), then broadcast
+      double rc = 1.0, rs = 0.0;
+      {
+        int idt = 0, idb = 0;
+        double gg = 0.0;
 #pragma unroll
-            for (int i = 0; i < RS; ++i) {
-              const double x = wt[j][i], y = wb[j][i];
-              wt[j][i] = c * x - s * y;
-              wb[j][i] = s * x + c * y;
-              const double u = vt[j][i], z = vb[j][i];
-              vt[j][i] = c * u - s * z;
-              vb[j][i] = s * u + c * z;
-            }
-            if (lane == 0) {
-              cn[it[j]] = fmax(a - t * gg, 0.0);
-              cn[ib[j]] = fmax(b + t * gg, 0.0);
-            }
-            rotated = 1;
+        for (int j = 0; j < PPW; ++j)
+          if (lane == j) {
+            idt = it[j];
+            idb = ib[j];
+            gg = g[j];
+          }
+        if (lane < PPW && p0 + lane < NP) {
+          const double a = cn[idt], b = cn[idb];
+          const double g2 = gg * gg;
+          if (g2 > 1e-30 * a * b && g2 > gf2 * fmax(a, b)) {
+            const double dd = b - a;
+            const double r = sqrt(dd * dd + 4.0 * g2);
+            const double t = (dd >= 0.0 ? 2.0 * gg : -2.0 * gg) / (fabs(dd) + r);
+            rc = 1.0 / sqrt(1.0 + t * t);
+            rs = rc * t;
+            cn[idt] = fmax(a - t * gg, 0.0);
+            cn[idb] = fmax(b + t * gg, 0.0);
           }
         }
+      }
+#pragma unroll
+      for (int j = 0; j < PPW; ++j) {
+        const double c = read_lane(rc, j), s = read_lane(rs, j);
+        if (s == 0.0) continue;
+#pragma unroll
+        for (int i = 0; i < RS; ++i) {
+          const double x = wt[j][i], y = wb[j][i];
+          wt[j][i] = c * x - s * y;
+          wb[j][i] = s * x + c * y;
+          const double u = vt[j][i], z = vb[j][i];
+          vt[j][i] = c * u - s * z;
+          vb[j][i] = s * u + c * z;
+        }
+        rotated = 1;
       }
       if (NP == 1) continue;  // a single pair never moves
       // ---- move one slot around the circle
@@ -759,7 +780,7 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
 
 void eig_launch(int count, const int* dims, const int* keep, const double* G, int64_t strideG,
                 int ldg, double* P, int64_t strideP, int ldp, double* lam, int64_t strideL,
-                double* work, int max_n, hipStream_t s) {
+                double* work, int max_n, double unoise, hipStream_t s) {
   if (count <= 0) return;
   QTT_REQUIRE(max_n <= 1024 && max_n <= ldg, "eig: n <= 1024 and n <= ldg");
   rt::check_range(dims, 0, count - 1, sizeof(int), "eig dims");
@@ -774,7 +795,7 @@ void eig_launch(int count, const int* dims, const int* keep, const double* G, in
 #define QTT_EIG_REG(RS_, PPW_, NW_, CH_)                                                          \
   if (max_n <= 64 * RS_ && max_n <= 2 * NW_ * PPW_) {                                            \
     hipLaunchKernelGGL((eig_reg_kernel<RS_, PPW_, NW_, CH_>), dim3(count), dim3(NW_ * 64), 0, s,  \
-                       dims, keep, G, strideG, ldg, P, strideP, ldp, lam, strideL);              \
+                       dims, keep, G, strideG, ldg, P, strideP, ldp, lam, strideL, unoise);      \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }

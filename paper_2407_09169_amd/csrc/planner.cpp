@@ -142,7 +142,10 @@ static void add_gemm(Plan& plan, int M, int N, int K, const double* A, int64_t l
 // target caps: right Gram chain, batched eigen-decompositions, P^T X P
 // ---------------------------------------------------------------------------
 static void plan_trunc_gram(Plan& plan, const std::vector<double*>& X, const std::vector<int>& ell,
-                            RoundTarget& tg) {
+                            RoundTarget& tg, Prec prec) {
+  // the Gram matrices are FP64, but X carries the noise of the contractions
+  // that produced it: eigenvectors are resolved down to that level only
+  const double unoise = machine_eps(prec);
   const int N = (int)X.size();
   QTT_REQUIRE((int)tg.caps.size() == N + 1 && (int)tg.core.size() == N, "truncation target shape");
   int lmax = 1, cmax = 1;
@@ -196,7 +199,7 @@ static void plan_trunc_gram(Plan& plan, const std::vector<double*>& X, const std
     for (int n = 1; n < N; ++n) oi.bytes += 8.0 * ((double)ell[n] * ell[n] + (double)ell[n] * tg.caps[n]);
     plan.add([=](hipStream_t s) {
       eig_launch(cnt, d_dims, d_keep, g1, (int64_t)ldg * ldg, ldg, p1, (int64_t)ldg * ldp, ldp, l1,
-                 ldg, ework, lmax, s);
+                 ldg, ework, lmax, unoise, s);
     }, oi);
   }
   // new cores P_n^T X_n P_{n+1}
@@ -446,7 +449,7 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
       Mnext[j] = (old == one) ? Ma[j] : old;
     }
   }
-  plan_trunc_gram(plan, X, ell, tg);
+  plan_trunc_gram(plan, X, ell, tg, prec);
 }
 
 // ---------------------------------------------------------------------------
@@ -556,7 +559,7 @@ void plan_round_det(Plan& plan, const ChainView& x, RoundTarget& tg) {
   rv.caps = caps;
   for (int n = 0; n < N; ++n) rv.core.push_back(rc[n]);
   LeftOrth lo = plan_left_orth(plan, rv);
-  plan_trunc_gram(plan, lo.core, lo.caps, tg);
+  plan_trunc_gram(plan, lo.core, lo.caps, tg, Prec::F64);
 }
 
 // ---------------------------------------------------------------------------
