@@ -41,33 +41,112 @@ def _time_steps(torch, prob, f, K):
     return t0.elapsed_time(t1)
 
 
-def _roofline(prob, f, dtype):
-    """Per-kernel-class event timing of one eager step; roofline of the class
-    with the most time."""
-    rows = {}
-    for k in ("contract", "qr", "eig", "stream"):
-        ms, n, fl, by = prob.profile(f, 1, k)
-        rows[k] = {"ms": ms, "launches": n, "flops": fl, "bytes": by}
-    dom = max(rows, key=lambda k: rows[k]["ms"])
-    r = rows[dom]
-    sec = r["ms"] / 1e3 if r["ms"] > 0 else float("nan")
-    if dom == "contract":
-        achieved = r["flops"] / sec / 1e12
-        peak = PEAKS_TFLOPS[dtype]
-        roof = {"bound": "mfma" if dtype != "f64" else "alu", "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s"}
-    elif dom == "stream":
-        achieved = r["bytes"] / sec / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s"}
+KERNEL_SOURCES = {"qr_": "factor.hip", "eig_": "factor.hip", "tc_": "tc_gemm.hip"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
+
+
+def _source_hash(kernel):
+    """sha1 (first 12 hex digits) of the source file that holds `kernel`."""
+    import hashlib
+    for prefix, src in KERNEL_SOURCES.items():
+        if kernel.startswith(prefix):
+            path = os.path.join(ROOT, "paper_2407_09169_amd", "csrc", src)
+            return hashlib.sha1(open(path, "rb").read()).hexdigest()[:12]
+    return None
+
+
+def _traffic(kernel, shape):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy
+    calibration) recorded in profiles/traffic.txt for this kernel and shape,
+    or None when absent or taken on a different version of its source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    h = _source_hash(kernel)
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("#") or not line.strip():
+            continue
+        parts = line.rstrip("\n").split("\t")
+        if len(parts) >= 5 and parts[0] == kernel and parts[1] == shape and parts[4] == h:
+            return float(parts[2]) + float(parts[3])
+    return None
+
+
+def _op_log(prob, f):
+    """One eager step with a pair of HIP events around every launch, on the
+    library's stream; returns [(index, class, ms, flops, bytes, description)]."""
+    import tempfile
+    fd, path = tempfile.mkstemp(suffix=".txt")
+    os.close(fd)
+    os.environ["QTTPDF_PROFILE_LOG"] = path
+    try:
+        prob.profile(f, 1, "all")
+    finally:
+        del os.environ["QTTPDF_PROFILE_LOG"]
+    rows = []
+    for line in open(path):
+        i, k, ms, fl, by, what = line.rstrip("\n").split("\t")
+        rows.append((int(i), int(k), float(ms), float(fl), float(by), what))
+    os.unlink(path)
+    return rows
+
+
+def _roofline(rows):
+    """Roofline of the dominant kernel: the (kernel, shape) group with the
+    most event time in one step; achieved = its algorithmic flops (bytes) per
+    launch / its average launch duration."""
+    groups = {}
+    for _, k, ms, fl, by, what in rows:
+        g = groups.setdefault(what, [0, 0.0, 0.0, 0.0])
+        g[0] += 1
+        g[1] += ms
+        g[2] += fl
+        g[3] += by
+    what = max(groups, key=lambda w: groups[w][1])
+    n, ms, fl, by = groups[what]
+    kernel, shape = what.split("|", 1) if "|" in what else (what, "")
+    avg_s = ms / n / 1e3
+    if kernel.startswith("tc_mfma_kernel<false>"):
+        roof = {"bound": "mfma", "achieved": fl / n / avg_s / 1e12, "peak": PEAKS_TFLOPS["f32"], "unit": "TFLOP/s"}
+    elif kernel.startswith("tc_mfma_kernel<true>"):
+        roof = {"bound": "mfma", "achieved": fl / n / avg_s / 1e12, "peak": PEAKS_TFLOPS["bf16"], "unit": "TFLOP/s"}
+    elif fl > 0:
+        roof = {"bound": "alu", "achieved": fl / n / avg_s / 1e12, "peak": PEAKS_TFLOPS["f64"], "unit": "TFLOP/s"}
     else:
-        achieved = r["flops"] / sec / 1e12 if r["flops"] > 0 else 0.0
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAKS_TFLOPS["f64"], "unit": "TFLOP/s"}
+        roof = {"bound": "hbm", "achieved": by / n / avg_s / 1e9, "peak": HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = dom
-    roof["launches_per_step"] = r["launches"]
-    roof["avg_launch_us"] = 1e3 * r["ms"] / max(1, r["launches"])
-    return roof, rows
+    roof["traffic"] = _traffic(kernel, shape)
+    roof["kernel"] = kernel
+    roof["shape"] = shape
+    roof["launches_per_step"] = n
+    roof["avg_launch_us"] = 1e6 * avg_s
+    roof["algorithmic_per_launch"] = (fl / n) if fl > 0 else (by / n)
+    roof["share_of_step_kernel_time"] = ms / sum(r[2] for r in rows)
+    return roof
+
+
+def _classes(rows):
+    names = {0: "contract", 1: "qr", 2: "eig", 3: "stream", -1: "other"}
+    out = {}
+    for _, k, ms, fl, by, _w in rows:
+        c = out.setdefault(names.get(k, "other"), {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
+        c["ms"] += ms
+        c["launches"] += 1
+        c["flops"] += fl
+        c["bytes"] += by
+    return out
+
+
+def _copy_probe(nbytes):
+    """A plain device copy of known size (torch's copy kernel), for scaling
+    the HBM counters of rocprofv3 runs."""
+    import torch
+    n = nbytes // 8
+    a = torch.rand(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": 8 * n, "dispatches": 5}))
 
 
 def _cpu_baseline(w):
@@ -103,8 +182,13 @@ def main():
     ap.add_argument("--no-bf16", action="store_true",
                     help="skip the extra BF16-MFMA measurement made next to an FP32 run")
     ap.add_argument("--op-log", default=None,
-                    help="also time every launch of one eager step and write one line per launch here")
+                    help="also write the per-launch event times of one eager step to this file")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        _copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}); "
               "run with --gpus 1", file=sys.stderr)
@@ -149,12 +233,15 @@ def main():
     mass = prob.observable(f, "mass")
     disc, norm2 = prob.step_info()
 
+    oplog = _op_log(prob, f)
     if args.op_log:
-        os.environ["QTTPDF_PROFILE_LOG"] = os.path.abspath(args.op_log)
-        prob.profile(f, 1, "all")
-        del os.environ["QTTPDF_PROFILE_LOG"]
-    roof, rows = _roofline(prob, f, args.dtype)
+        with open(args.op_log, "w") as fh:
+            for r in oplog:
+                fh.write("\t".join(str(x) for x in r) + "\n")
+    roof = _roofline(oplog)
+    rows = _classes(oplog)
     log(f"kernel classes: {rows}")
+    log(f"dominant kernel: {roof}")
     cpu = None if args.no_cpu_baseline else _cpu_baseline(w)
     if cpu:
         log(f"cpu baseline: {cpu}")

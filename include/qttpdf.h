@@ -243,8 +243,8 @@ tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps);
  * returns the summed event time in ms, the number of such launches, and
  * their algorithmic flops and bytes (operands read once, results written
  * once).  With the environment variable QTTPDF_PROFILE_LOG naming a file,
- * one line per timed launch (plan index, class, ms, flops, shape) is
- * appended to it.  f is advanced. */
+ * one line per timed launch (plan index, class, ms, flops, bytes,
+ * kernel|shape; tab separated) is appended to it.  f is advanced. */
 tt_status tt_profile(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps, int kernel, double* ms,
                      int64_t* launches, double* flops, double* bytes);
 

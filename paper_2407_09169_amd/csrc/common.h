@@ -205,6 +205,10 @@ void tc_launch(const TcDesc& d, Prec p, hipStream_t s);
 // number of K chunks worth splitting a contraction into (1: no split); the
 // caller provides the partial-sum buffer of batch * ksplit * M * N doubles
 int tc_choose_ksplit(const TcDesc& d, Prec p);
+// name of the kernel (template instantiation) a launch uses
+std::string tc_kernel_name(const TcDesc& d, Prec p);
+std::string qr_kernel_name(int m, int n);
+std::string eig_kernel_name(int max_n);
 // host-side bounds check of a contraction against the allocation registry
 void tc_validate(const TcDesc& d);
 

@@ -5,6 +5,9 @@
 // workspace (L2 resident for the sizes used here) so that each Householder
 // reflector or Jacobi rotation touches contiguous columns.  Reductions over
 // a column use wavefront shuffles, then one LDS slot per wavefront.
+#include <cstdio>
+#include <string>
+
 #include "common.h"
 
 namespace qtt {
@@ -746,6 +749,38 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
 
 }  // namespace
 
+// register-resident configurations, tried in order: (rows per lane, columns
+// per wave, waves, reduction chunk) and (rows per lane, pairs per wave,
+// waves, reduction chunk); larger problems use the global-memory kernels
+#define QTT_QR_CONFIGS(X) \
+  X(1, 1, 16, 1) X(1, 2, 16, 2) X(2, 2, 16, 2) X(2, 4, 16, 4) X(3, 6, 16, 3) X(4, 8, 16, 4) X(5, 9, 16, 3) X(5, 10, 16, 2)
+#define QTT_EIG_CONFIGS(X) \
+  X(1, 1, 4, 1) X(1, 2, 8, 2) X(1, 4, 8, 4) X(2, 4, 8, 4) X(2, 8, 8, 4) X(3, 6, 12, 2)
+
+std::string qr_kernel_name(int m, int n) {
+  char b[64];
+#define QTT_QR_NAME(RS_, CPW_, NW_, CH_)                                              \
+  if (m <= 64 * RS_ && n <= NW_ * CPW_) {                                             \
+    snprintf(b, sizeof b, "qr_reg_kernel<%d, %d, %d, %d>", RS_, CPW_, NW_, CH_); \
+    return b;                                                                         \
+  }
+  QTT_QR_CONFIGS(QTT_QR_NAME)
+#undef QTT_QR_NAME
+  return "qr_kernel";
+}
+
+std::string eig_kernel_name(int max_n) {
+  char b[64];
+#define QTT_EIG_NAME(RS_, PPW_, NW_, CH_)                                               \
+  if (max_n <= 64 * RS_ && max_n <= 2 * NW_ * PPW_) {                                   \
+    snprintf(b, sizeof b, "eig_reg_kernel<%d, %d, %d, %d>", RS_, PPW_, NW_, CH_); \
+    return b;                                                                           \
+  }
+  QTT_EIG_CONFIGS(QTT_EIG_NAME)
+#undef QTT_EIG_NAME
+  return "eig_kernel";
+}
+
 void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_t rs, int64_t cs,
                double* Q, int64_t strideQ, double* R, int64_t strideR, double* work,
                hipStream_t s) {
@@ -764,14 +799,7 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }
-  QTT_QR_REG(1, 1, 16, 1)
-  QTT_QR_REG(1, 2, 16, 2)
-  QTT_QR_REG(2, 2, 16, 2)
-  QTT_QR_REG(2, 4, 16, 4)
-  QTT_QR_REG(3, 6, 16, 3)
-  QTT_QR_REG(4, 8, 16, 4)
-  QTT_QR_REG(5, 9, 16, 3)
-  QTT_QR_REG(5, 10, 16, 2)
+  QTT_QR_CONFIGS(QTT_QR_REG)
 #undef QTT_QR_REG
   hipLaunchKernelGGL(qr_kernel, dim3(count), dim3(FT), 0, s, m, n, A, strideA, rs, cs, Q, strideQ,
                      R, strideR, work);
@@ -799,12 +827,7 @@ void eig_launch(int count, const int* dims, const int* keep, const double* G, in
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }
-  QTT_EIG_REG(1, 1, 4, 1)
-  QTT_EIG_REG(1, 2, 8, 2)
-  QTT_EIG_REG(1, 4, 8, 4)
-  QTT_EIG_REG(2, 4, 8, 4)
-  QTT_EIG_REG(2, 8, 8, 4)
-  QTT_EIG_REG(3, 6, 12, 2)
+  QTT_EIG_CONFIGS(QTT_EIG_REG)
 #undef QTT_EIG_REG
   hipLaunchKernelGGL(eig_kernel, dim3(count), dim3(FT), 0, s, dims, keep, G, strideG, ldg, P,
                      strideP, ldp, lam, strideL, work);

@@ -88,7 +88,8 @@ struct Plan {
   // eager run with a pair of events around every op of class `kind` (OP_ALL:
   // every op); adds the event time (ms), the number of such ops and their
   // flops / bytes.  With QTTPDF_PROFILE_LOG=<file> set, one line per timed op
-  // (index, class, ms, flops, shape) is appended to that file.
+  // (index, class, ms, flops, bytes, kernel|shape) is appended to that
+  // file.
   void run_profiled(hipStream_t s, int kind, double& ms, int64_t& count, double& flops,
                     double& bytes) const;
 };

@@ -78,9 +78,8 @@ static void add_tc(Plan& plan, TcDesc d, Prec p) {
   oi.bytes = 8.0 * (na * d.M * (double)d.K + nb * d.K * (double)d.N +
                     (d.beta != 0.0 ? 2.0 : 1.0) * d.batch * d.M * (double)d.N);
   char w[112];
-  snprintf(w, sizeof w, "tc %s b%d m%d n%d k%d s%d", p == Prec::F64 ? "f64" : (p == Prec::F32 ? "f32" : "bf16"),
-           d.batch, d.M, d.N, d.K, d.ksplit);
-  oi.what = w;
+  snprintf(w, sizeof w, "|b%d m%d n%d k%d s%d", d.batch, d.M, d.N, d.K, d.ksplit);
+  oi.what = tc_kernel_name(d, p) + w;
   plan.add([d, p](hipStream_t s) { tc_launch(d, p, s); }, oi);
 }
 
@@ -89,7 +88,7 @@ static OpInfo qr_info(int m, int n) {
   oi.kind = OP_QR;
   oi.flops = 2.0 * (2.0 * m * (double)n * n - 2.0 * n * (double)n * n / 3.0);
   oi.bytes = 8.0 * 2.0 * m * (double)n;
-  oi.what = "qr m" + std::to_string(m) + " n" + std::to_string(n);
+  oi.what = qr_kernel_name(m, n) + "|m" + std::to_string(m) + " n" + std::to_string(n);
   return oi;
 }
 
@@ -123,8 +122,8 @@ void Plan::run_profiled(hipStream_t s, int kind, double& ms, int64_t& count, dou
     ms += t;
     const OpInfo& oi = info[idx[k]];
     if (log)
-      std::fprintf(log, "%zu %d %.6f %.6g %s\n", idx[k], oi.kind, (double)t, oi.flops,
-                   oi.what.empty() ? "-" : oi.what.c_str());
+      std::fprintf(log, "%zu\t%d\t%.6f\t%.6g\t%.6g\t%s\n", idx[k], oi.kind, (double)t, oi.flops,
+                   oi.bytes, oi.what.empty() ? "-" : oi.what.c_str());
   }
   if (log) std::fclose(log);
   if (!rt::dry())
@@ -143,9 +142,13 @@ static void add_gemm(Plan& plan, int M, int N, int K, const double* A, int64_t l
 // ---------------------------------------------------------------------------
 static void plan_trunc_gram(Plan& plan, const std::vector<double*>& X, const std::vector<int>& ell,
                             RoundTarget& tg, Prec prec) {
-  // the Gram matrices are FP64, but X carries the noise of the contractions
-  // that produced it: eigenvectors are resolved down to that level only
-  const double unoise = machine_eps(prec);
+  // The Gram matrices are FP64, but X carries the relative noise u of the
+  // contractions that produced it.  An eigen-residual r turns the direction
+  // of singular value sigma_i by ~ r / sigma_i^2 and moves the tensor by
+  // ~ r / sigma_i; keeping that below the u * sigma_1 the contractions already
+  // cause, for every sigma_i >= u * sigma_1, needs r <= u^2 lambda_1.
+  const double u = machine_eps(prec);
+  const double unoise = std::max(machine_eps(Prec::F64), u * u);
   const int N = (int)X.size();
   QTT_REQUIRE((int)tg.caps.size() == N + 1 && (int)tg.core.size() == N, "truncation target shape");
   int lmax = 1, cmax = 1;
@@ -195,8 +198,13 @@ static void plan_trunc_gram(Plan& plan, const std::vector<double*>& X, const std
     int cnt = N - 1;
     OpInfo oi;
     oi.kind = OP_EIG;
-    oi.what = "eig count" + std::to_string(cnt) + " nmax" + std::to_string(lmax);
-    for (int n = 1; n < N; ++n) oi.bytes += 8.0 * ((double)ell[n] * ell[n] + (double)ell[n] * tg.caps[n]);
+    oi.what = eig_kernel_name(lmax) + "|count" + std::to_string(cnt) + " nmax" + std::to_string(lmax);
+    // algorithmic flops: 9 n^3 per matrix, the count of a dense symmetric
+    // eigen-decomposition with vectors (tridiagonal reduction + implicit QL)
+    for (int n = 1; n < N; ++n) {
+      oi.bytes += 8.0 * ((double)ell[n] * ell[n] + (double)ell[n] * tg.caps[n]);
+      oi.flops += 9.0 * (double)ell[n] * ell[n] * ell[n];
+    }
     plan.add([=](hipStream_t s) {
       eig_launch(cnt, d_dims, d_keep, g1, (int64_t)ldg * ldg, ldg, p1, (int64_t)ldg * ldp, ldp, l1,
                  ldg, ework, lmax, unoise, s);

@@ -14,6 +14,8 @@
 // next K tile into registers while the current one is being multiplied.
 // Contractions with few output tiles and a long K are split along K
 // (TcDesc::ksplit); their partial sums are added by tc_splitk_reduce.
+#include <string>
+
 #include "common.h"
 
 namespace qtt {
@@ -286,6 +288,13 @@ inline Tile tile_of(const TcDesc& d, Prec p) {
 }
 
 }  // namespace
+
+std::string tc_kernel_name(const TcDesc& d, Prec p) {
+  if (p == Prec::BF16) return "tc_mfma_kernel<true>";
+  if (p == Prec::F32) return "tc_mfma_kernel<false>";
+  const Tile t = tile_of(d, p);
+  return "tc_f64_kernel<" + std::to_string(t.bm) + ", " + std::to_string(t.bn) + ">";
+}
 
 int tc_choose_ksplit(const TcDesc& d, Prec p) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0 || d.K < 256) return 1;
