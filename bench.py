@@ -136,6 +136,21 @@ def _classes(rows):
     return out
 
 
+def _kernel_probe(spec):
+    """The QR kernel alone, on the shape the step uses (counter runs)."""
+    import numpy as np
+    import paper_2407_09169_amd as q
+    kind, shape = spec.split(":")
+    if kind != "qr":
+        raise SystemExit(f"unknown kernel probe {kind}")
+    m, n = (int(v) for v in shape.lower().split("x"))
+    A = np.random.default_rng(0).standard_normal((1, m, n))
+    ctx = q.Context(0)
+    for _ in range(5):
+        q.linalg_qr(ctx, A, with_r=False)
+    print(json.dumps({"kernel_probe": spec, "dispatches": 5}))
+
+
 def _copy_probe(nbytes):
     """A plain device copy of known size (torch's copy kernel), for scaling
     the HBM counters of rocprofv3 runs."""
@@ -185,9 +200,15 @@ def main():
                     help="also write the per-launch event times of one eager step to this file")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--kernel-probe", default=None, metavar="qr:MxN",
+                    help="only run the FP64 Householder QR kernel on one seeded M x N matrix "
+                         "five times (counter runs of the dominant kernel)")
     args = ap.parse_args()
     if args.copy_probe:
         _copy_probe(args.copy_probe)
+        return
+    if args.kernel_probe:
+        _kernel_probe(args.kernel_probe)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}); "
