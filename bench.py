@@ -151,6 +151,57 @@ def _kernel_probe(spec):
     print(json.dumps({"kernel_probe": spec, "dispatches": 5}))
 
 
+def _bench_batched(args, log):
+    """The batched ensemble (64 uneven 5-D problems, FP32-MFMA contractions):
+    instance-steps/s of one graph launch per step for all instances, next to
+    the same instances stepped one after another."""
+    import torch
+    import paper_2407_09169_amd as q
+    import workloads
+    ws = workloads.batch_workloads(count=64)
+    ctx = q.Context(0)
+    t0 = time.perf_counter()
+    inst = [q.setup_workload(ctx, w, args.dtype) for w in ws]
+    b = q.Batch(ctx, [p for p, _ in inst], [f for _, f in inst])
+    log(f"batch of {len(ws)} set up in {time.perf_counter() - t0:.1f} s; warmup {args.warmup}")
+    b.step(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    value = len(ws) * args.steps / (ms / 1e3)
+    log(f"batched: {args.steps} steps of {len(ws)} instances in {ms:.1f} ms ({value:.1f} instance-steps/s)")
+    for p, f in inst:  # records each instance's own graph
+        p.step(f, 1)
+    torch.cuda.synchronize()
+    e0.record()
+    for p, f in inst:
+        p.step(f, 1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms1 = e0.elapsed_time(e1)
+    seq = len(ws) / (ms1 / 1e3)
+    log(f"one after another: {seq:.1f} instance-steps/s")
+    masses = [p.observable(f, "mass") for p, f in inst]
+    out = {
+        "metric": "instance-steps/s, 64 uneven 5-D QTT PDF problems in one graph launch per step",
+        "value": value, "unit": "instance-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "batch64", "instances": len(ws),
+                   "grid_levels": sorted({w.M for w in ws}), "chis": sorted({w.chi for w in ws}),
+                   "total_cores": sum(w.n_sites for w in ws), "integrator": "rk4"},
+        "sequential_instance_steps_per_s": seq,
+        "batching_speedup": value / seq,
+        "mass_range": [min(masses), max(masses)],
+    }
+    b.close()
+    print(json.dumps(out))
+
+
 def _copy_probe(nbytes):
     """A plain device copy of known size (torch's copy kernel), for scaling
     the HBM counters of rocprofv3 runs."""
@@ -219,12 +270,15 @@ def main():
     import paper_2407_09169_amd as q
     import workloads
 
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.workload == "batch64":
+        _bench_batched(args, log)
+        return
     w = workloads.get_workload(args.workload)
     ctx = q.Context(0)
     K, W = args.steps, args.warmup
-
-    def log(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     prob, f = q.setup_workload(ctx, w, args.dtype)
     log(f"{w.name} {args.dtype}: set up; warmup {W}")

@@ -82,6 +82,7 @@ typedef enum {
 typedef struct tt_ctx tt_ctx;
 typedef struct tt_tt tt_tt; /* an MPS or an MPO in device memory */
 typedef struct tt_problem tt_problem;
+typedef struct tt_batch tt_batch;
 
 /* ------------------------------------------------------------------------
  * Context
@@ -235,6 +236,25 @@ tt_status tt_problem_state(tt_problem* prob, tt_tt** f);
  * rounded as well.  The first call records the step as a HIP graph that
  * later calls replay.  f must come from tt_problem_state (or have its caps). */
 tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps);
+
+/* ------------------------------------------------------------------------
+ * Batching: many independent problems advanced by one graph launch.
+ * (Not a passage of the paper: the step of section "Matrix product state
+ * algorithm" applied to an ensemble of problems with different grids,
+ * bond caps and parameters.)
+ * ------------------------------------------------------------------------ */
+/* Records one step of `count` problems, each with its own state
+ * (states[i] from tt_problem_state(probs[i]); problems and states must be
+ * distinct), as a single HIP graph in which every instance is an independent
+ * branch.  The handles stay owned by the caller and must outlive the batch;
+ * an instance must not be stepped by other calls while the batch is in use.
+ * Results are bitwise those of tt_step on each instance alone. */
+tt_status tt_batch_create(tt_ctx* ctx, int count, tt_problem* const* probs, tt_tt* const* states,
+                          tt_batch** out);
+/* Advances every instance of the batch by n_steps steps (n_steps graph
+ * launches on the context's stream; asynchronous). */
+tt_status tt_step_batched(tt_batch* batch, int n_steps);
+tt_status tt_batch_destroy(tt_batch* batch);
 
 /* Measurement: runs n_steps steps of the recorded step eagerly (no graph)
  * with a pair of HIP events around every launch of one kernel class --

@@ -31,7 +31,7 @@ EXPORTS = [
     "mpo_build", "mps_apply_mpo", "mps_axpby", "mps_round", "mps_round_sketch", "tt_l2_diff",
     "tt_inner", "tt_problem_create", "tt_problem_destroy", "tt_problem_info", "tt_problem_state",
     "tt_step", "tt_profile", "tt_step_info", "tt_observable", "tt_mean_field",
-    "tt_linalg_qr", "tt_linalg_eigh",
+    "tt_linalg_qr", "tt_linalg_eigh", "tt_batch_create", "tt_step_batched", "tt_batch_destroy",
 ]
 KERNELS = {"contract": 0, "qr": 1, "eig": 2, "stream": 3, "all": 4}
 
@@ -100,6 +100,9 @@ def lib():
         "tt_mean_field": [vp, vp, vp, i32, P(vp), P(dbl)],
         "tt_linalg_qr": [vp, i32, i32, i32, P(dbl), P(dbl), P(dbl)],
         "tt_linalg_eigh": [vp, i32, i32, i32, P(dbl), P(dbl), P(dbl)],
+        "tt_batch_create": [vp, i32, P(vp), P(vp), P(vp)],
+        "tt_step_batched": [vp, i32],
+        "tt_batch_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -388,6 +391,35 @@ class Problem:
         if self.h:
             lib().tt_problem_destroy(self.h)
             self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+class Batch:
+    """Many (problem, state) instances advanced together by one graph launch
+    per step (tt_batch_create / tt_step_batched)."""
+
+    def __init__(self, ctx, problems, states):
+        self.ctx = ctx
+        self._keep = (list(problems), list(states))
+        n = len(problems)
+        P = (C.c_void_p * n)(*[p.h for p in problems])
+        S = (C.c_void_p * n)(*[f.h for f in states])
+        h = C.c_void_p()
+        _check(lib().tt_batch_create(ctx.h, n, P, S, C.byref(h)))
+        self.h = h
+
+    def step(self, n_steps=1):
+        _check(lib().tt_step_batched(self.h, n_steps))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().tt_batch_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

@@ -924,6 +924,97 @@ tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps) {
   });
 }
 
+// ---------------------------------------------------------------------------
+// batching
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct tt_batch {
+  tt_ctx* ctx = nullptr;
+  std::vector<tt_problem*> probs;
+  std::vector<tt_tt*> states;
+  std::vector<hipStream_t> streams;  // one per instance (capture only)
+  std::vector<hipEvent_t> events;    // fork + one join per instance
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~tt_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto e : events) (void)hipEventDestroy(e);
+    for (auto st : streams) (void)hipStreamDestroy(st);
+  }
+};
+
+extern "C" {
+
+tt_status tt_batch_create(tt_ctx* ctx, int count, tt_problem* const* probs, tt_tt* const* states,
+                          tt_batch** out) {
+  return guard([&] {
+    QTT_REQUIRE(ctx && out && probs && states && count >= 1, "bad argument");
+    auto b = std::make_unique<tt_batch>();
+    b->ctx = ctx;
+    for (int i = 0; i < count; ++i) {
+      tt_problem* P = probs[i];
+      tt_tt* f = states[i];
+      QTT_REQUIRE(P && f, "instance %d: null handle", i);
+      QTT_REQUIRE(P->ctx == ctx, "instance %d: problem belongs to another context", i);
+      check_tt(f, ctx);
+      QTT_REQUIRE(f->caps == P->fcaps, "instance %d: state caps differ from the problem's", i);
+      for (int j = 0; j < i; ++j)
+        QTT_REQUIRE(probs[j] != P && states[j] != f, "instance %d repeats a problem or a state", i);
+      if (!P->plan || P->plan_f != f) build_step_plan(P, f);
+      b->probs.push_back(P);
+      b->states.push_back(f);
+    }
+    if (!rt::dry()) {
+      b->streams.resize(count, nullptr);
+      for (auto& st : b->streams) QTT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      b->events.resize(count + 1, nullptr);
+      for (auto& e : b->events) QTT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      hipStream_t s0 = ctx->stream;
+      QTT_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+      try {
+        QTT_HIP(hipEventRecord(b->events[0], s0));
+        for (int i = 0; i < count; ++i) {
+          QTT_HIP(hipStreamWaitEvent(b->streams[i], b->events[0], 0));
+          b->probs[i]->plan->run(b->streams[i]);
+          QTT_HIP(hipEventRecord(b->events[i + 1], b->streams[i]));
+          QTT_HIP(hipStreamWaitEvent(s0, b->events[i + 1], 0));
+        }
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(s0, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      QTT_HIP(hipStreamEndCapture(s0, &b->graph));
+      QTT_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    *out = b.release();
+  });
+}
+
+tt_status tt_step_batched(tt_batch* b, int n_steps) {
+  return guard([&] {
+    QTT_REQUIRE(b && n_steps >= 0, "bad argument");
+    StreamScope sc(b->ctx);
+    if (rt::dry()) {
+      for (int i = 0; i < n_steps; ++i)
+        for (auto* P : b->probs) P->plan->run(b->ctx->stream);
+      return;
+    }
+    for (int i = 0; i < n_steps; ++i) QTT_HIP(hipGraphLaunch(b->exec, b->ctx->stream));
+  });
+}
+
+tt_status tt_batch_destroy(tt_batch* b) {
+  return guard([&] {
+    if (!b) return;
+    if (!rt::dry()) (void)hipStreamSynchronize(b->ctx->stream);
+    delete b;
+  });
+}
+
 tt_status tt_profile(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps, int kernel, double* ms,
                      int64_t* launches, double* flops, double* bytes) {
   return guard([&] {

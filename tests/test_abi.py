@@ -67,6 +67,31 @@ print("ok")
     assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
 
 
+def test_dry_run_batch_planning_is_in_bounds():
+    """The batched step over uneven problems plans every launch in bounds, and
+    a batch that repeats a problem is refused."""
+    code = r"""
+import os, sys
+os.environ["QTTPDF_DRYRUN"] = "1"
+sys.path.insert(0, %r)
+import paper_2407_09169_amd as q, workloads
+ctx = q.Context(0, stream=0)
+ws = workloads.batch_workloads(count=4, seed=7, bits=(3, 4, 6), chis=(8, 16, 64))
+inst = [q.setup_workload(ctx, w, "f32") for w in ws]
+b = q.Batch(ctx, [p for p, _ in inst], [f for _, f in inst])
+b.step(1)
+try:
+    q.Batch(ctx, [inst[0][0], inst[0][0]], [inst[0][1], inst[0][1]])
+except q.QttError as e:
+    assert "repeats" in str(e), e
+else:
+    raise SystemExit("no error for a repeated problem")
+print("ok")
+""" % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
+
+
 def test_errors_are_reported_not_thrown():
     code = r"""
 import os, sys

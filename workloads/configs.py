@@ -104,3 +104,43 @@ WORKLOADS = {w.name: w for w in _W}
 def get_workload(name: str, **overrides) -> Workload:
     w = WORKLOADS[name]
     return w.replace(**overrides) if overrides else w
+
+
+# Upper bound of |<U_i>| for the seeded velocity family (a1, a2 in [0.5, 1.5],
+# a3 = -(a1 + a2), unit jet): |U1| <= 2.5, |U2| <= 1.5, |U3| <= 3.
+U_MAX = 3.0
+
+
+def stable_dt(ndims: int, bits: int, omega: float, k_react: float, nu_phi: float = 4e-3,
+              gamma: float = 1e-3, safety: float = 0.5) -> float:
+    """Explicit RK4 step from a Gershgorin bound of the spectral radius of the
+    discrete operator: rho = sum over the two composition axes of
+    (4 nu_phi / h^2 + (Omega + k) / h) plus, in 5-D, sum over the three
+    physical axes of (4 Gamma / h^2 + U_max / h); dt = safety * 2.78 / rho
+    (2.78 is where RK4's stability region meets the negative real axis)."""
+    h = 1.0 / (1 << bits)
+    rho = 2 * (4.0 * nu_phi / h ** 2 + (omega + k_react) / h)
+    if ndims == 5:
+        rho += 3 * (4.0 * gamma / h ** 2 + U_MAX / h)
+    return safety * 2.78 / rho
+
+
+def batch_workloads(count: int = 64, seed: int = 4, bits=(6, 7, 8, 9), chis=(16, 32, 64, 128),
+                    omega=(0.5, 4.0), k_react=(1.0, 50.0)) -> list:
+    """The batched ensemble of 5-D problems: instance i draws its grid level
+    (bits), bond cap chi, Omega and k from the seeded generator [seed, i] and
+    uses seed 1000 + i for its own initial PDF, velocity and sketches; dt
+    follows stable_dt."""
+    import numpy as np
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng([seed, i])
+        b = int(rng.choice(bits))
+        chi = int(rng.choice(chis))
+        om = float(rng.uniform(*omega))
+        k = float(rng.uniform(*k_react))
+        out.append(Workload(f"batch{i:02d}_M{1 << b}_chi{chi}", ndims=5, bits=b, ordering="serial",
+                            chi=chi, oversample=16, chi_mean=min(16, chi), oversample_mean=8,
+                            omega=om, k_react=k, dt=stable_dt(5, b, om, k), steps=20,
+                            seed=1000 + i))
+    return out
