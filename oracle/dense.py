@@ -133,6 +133,61 @@ class DenseProblem:
                 out += self.gamma * apply_axis(self.D2p, f, 2 + i)
         return out
 
+    def rhs_tangent(self, f, df, param=None):
+        """Directional derivative of rhs at (f, theta) along (df, e_param):
+        the right-hand side linearised in f (the mean composition m_a depends
+        on f, so d(m_a f) = m_a df + m_a(df) f) applied to df, plus the partial
+        derivative with respect to the parameter "omega" or "k_react" (None:
+        no parameter direction)."""
+        out = np.zeros_like(f)
+        p1, p2 = self.phi
+        for a in (0, 1):
+            m = self.mean_field(f, a)
+            dm = self.mean_field(df, a)
+            dflux = self.omega * ((self.phi[a] - m) * df - dm * f) + self.k_react * p1 * p2 * df
+            if param == "omega":
+                dflux = dflux + (self.phi[a] - m) * f
+            elif param == "k_react":
+                dflux = dflux + p1 * p2 * f
+            elif param is not None:
+                raise ValueError(param)
+            out += apply_axis(self.D1g, dflux, a)
+            out += self.nu_phi * apply_axis(self.D2g, df, a)
+        if self.ndims == 5:
+            for i in range(3):
+                Ui = self.U[i][None, None]
+                out -= Ui * apply_axis(self.D1p, df, 2 + i)
+                out += self.gamma * apply_axis(self.D2p, df, 2 + i)
+        return out
+
+    def step_tangent(self, f, df, dt, param=None, integrator="rk4"):
+        """One step and its derivative: returns (f+, df+) with df+ the
+        derivative of the explicit Runge-Kutta map along (df, e_param), stage
+        by stage in the order of the step."""
+        L, dL = self.rhs, self.rhs_tangent
+        if integrator == "rk4":
+            k1, d1 = L(f), dL(f, df, param)
+            g, dg = f + 0.5 * dt * k1, df + 0.5 * dt * d1
+            k2, d2 = L(g), dL(g, dg, param)
+            g, dg = f + 0.5 * dt * k2, df + 0.5 * dt * d2
+            k3, d3 = L(g), dL(g, dg, param)
+            g, dg = f + dt * k3, df + dt * d3
+            k4, d4 = L(g), dL(g, dg, param)
+            return (f + dt / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4),
+                    df + dt / 6.0 * (d1 + 2 * d2 + 2 * d3 + d4))
+        if integrator == "rk2":
+            k1, d1 = L(f), dL(f, df, param)
+            g, dg = f + dt * k1, df + dt * d1
+            k2, d2 = L(g), dL(g, dg, param)
+            return f + 0.5 * dt * (k1 + k2), df + 0.5 * dt * (d1 + d2)
+        raise ValueError(integrator)
+
+    def with_params(self, **kw):
+        """Copy with some of omega / k_react / nu_phi / gamma replaced."""
+        q = DenseProblem(self.ndims, self.M, kw.get("omega", self.omega), kw.get("k_react", self.k_react),
+                         kw.get("nu_phi", self.nu_phi), kw.get("gamma", self.gamma), self.U)
+        return q
+
     def step(self, f, dt, integrator="rk4"):
         L = self.rhs
         if integrator == "rk4":
