@@ -256,6 +256,26 @@ tt_status tt_batch_create(tt_ctx* ctx, int count, tt_problem* const* probs, tt_t
 tt_status tt_step_batched(tt_batch* batch, int n_steps);
 tt_status tt_batch_destroy(tt_batch* batch);
 
+/* ------------------------------------------------------------------------
+ * Parameter derivatives (forward mode).  Not a passage of the paper: the
+ * derivative of the explicit Runge-Kutta map of eq. FP2 with respect to
+ * Omega_mix (eq. FP0's LMSE rate) and the reaction rate C_r, for gradients
+ * of final-time statistics.
+ * ------------------------------------------------------------------------ */
+typedef enum { TT_PARAM_OMEGA = 0, TT_PARAM_K = 1 } tt_param;
+/* Advances f by n_steps steps exactly as tt_step does and, with it, the
+ * derivatives dfs[j] = d f / d theta_j for the n_params (1 or 2) distinct
+ * parameters params[j] (tt_param).  Each tangent is a state of the problem's
+ * caps (tt_problem_state), zero for an initial condition that does not
+ * depend on the parameter.  Stage by stage the linearised right-hand side,
+ * with the dependence of the LMSE mean <Phi_a> on f, is applied to the
+ * tangent and rounded to chi like the state itself; with chi at the exact
+ * ranks the result is the exact derivative of the discrete map.  5-D
+ * problems only.  The first call records the combined step as a HIP graph;
+ * it and tt_step keep separate recordings. */
+tt_status tt_step_tangent(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_params, const int* params,
+                          tt_tt* const* dfs, int n_steps);
+
 /* Measurement: runs n_steps steps of the recorded step eagerly (no graph)
  * with a pair of HIP events around every launch of one kernel class --
  * 0 contractions (tensor-contraction kernels), 1 Householder QR, 2 batched

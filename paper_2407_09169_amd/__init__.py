@@ -23,6 +23,9 @@ TT_SERIAL, TT_INTERLEAVED = 0, 1
 OBS = {"mass": 0, "mean1": 1, "mean2": 2, "mean12": 3, "R12": 4, "Y12": 5, "product": 6}
 OP = {"ID": 0, "D1G": 1, "D2G": 2, "D1P": 3, "D2P": 4, "PHI": 5, "D1G_PHI": 6}
 DTYPES = {"f64": TT_F64, "f32": TT_F32, "bf16": TT_BF16}
+PARAMS = {"omega": 0, "k_react": 1}
+# statistics that are linear in f: their derivative is the statistic of df
+LINEAR_OBS = ("mass", "mean1", "mean2", "mean12", "product")
 
 # every entry point of include/qttpdf.h
 EXPORTS = [
@@ -32,6 +35,7 @@ EXPORTS = [
     "tt_inner", "tt_problem_create", "tt_problem_destroy", "tt_problem_info", "tt_problem_state",
     "tt_step", "tt_profile", "tt_step_info", "tt_observable", "tt_mean_field",
     "tt_linalg_qr", "tt_linalg_eigh", "tt_batch_create", "tt_step_batched", "tt_batch_destroy",
+    "tt_step_tangent",
 ]
 KERNELS = {"contract": 0, "qr": 1, "eig": 2, "stream": 3, "all": 4}
 
@@ -103,6 +107,7 @@ def lib():
         "tt_batch_create": [vp, i32, P(vp), P(vp), P(vp)],
         "tt_step_batched": [vp, i32],
         "tt_batch_destroy": [vp],
+        "tt_step_tangent": [vp, vp, vp, i32, P(i32), P(vp), i32],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -374,6 +379,15 @@ class Problem:
         _check(lib().tt_step_info(self.h, disc.ctypes.data_as(C.POINTER(C.c_double)), C.byref(nrm)))
         return disc, nrm.value
 
+    def step_tangent(self, f, tangents, n_steps=1):
+        """Advances f and the parameter derivatives tangents = {"omega": df,
+        "k_react": dk} (states of this problem) by n_steps steps."""
+        names = list(tangents)
+        n = len(names)
+        params = (C.c_int * n)(*[PARAMS[k] for k in names])
+        dfs = (C.c_void_p * n)(*[tangents[k].h for k in names])
+        _check(lib().tt_step_tangent(self.ctx.h, self.h, f.h, n, params, dfs, n_steps))
+
     def observable(self, f, which):
         r = C.c_double()
         _check(lib().tt_observable(self.ctx.h, self.h, f.h, OBS[which], C.byref(r)))
@@ -426,6 +440,25 @@ class Batch:
             self.close()
         except Exception:  # noqa: BLE001
             pass
+
+
+def statistic_and_gradient(ctx, w, n_steps, statistic="product", dtype="f64",
+                           params=("omega", "k_react")):
+    """J = statistic(f(T)) after n_steps steps of workload w from its initial
+    PDF, and dJ/dtheta for theta in params (forward-mode tangents carried
+    along the step).  statistic must be linear in f."""
+    if statistic not in LINEAR_OBS:
+        raise ValueError(f"derivatives are provided for the linear statistics {LINEAR_OBS}")
+    prob, f = setup_workload(ctx, w, dtype)
+    tans = {p: prob.state() for p in params}
+    prob.step_tangent(f, tans, n_steps)
+    J = prob.observable(f, statistic)
+    grads = {p: prob.observable(tans[p], statistic) for p in params}
+    for t in tans.values():
+        t.free()
+    f.free()
+    prob.close()
+    return J, grads
 
 
 def setup_workload(ctx, w, dtype="f64"):

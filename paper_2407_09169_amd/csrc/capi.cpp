@@ -152,15 +152,63 @@ struct tt_problem {
   const tt_tt* plan_f = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  RoundTarget last;
+  RoundTarget last;              // final rounding of the recording that ran last
+  RoundTarget last_plain, last_tan;  // ... of the plain and of the tangent recording
   std::unique_ptr<Plan> obs_plan;
+  // host copy of the mean-field chain over the phi sites (unscaled) and the
+  // mean-field bonds, for assembling further stage-shaped operators
+  host::TT MFh;
+  std::vector<int> Dmf;
+  // forward-mode derivatives with respect to parameter q (0 Omega, 1 k):
+  // operator B_q = dA_fix/dq - sum_a D1g^(phi_a) diag(.), its fixed bonds,
+  // tangent stage slopes, rounded tangent mean fields, raw partial sums
+  std::unique_ptr<tt_tt> Bt[2];
+  std::vector<int> Dfix_t[2];
+  std::unique_ptr<tt_tt> dk[2][4];
+  std::unique_ptr<tt_tt> mtt[2][2];
+  DevBuf Edf[2], Edk[2], mfdf[2], mfdk[2];
+  std::unique_ptr<Plan> tplan;
+  std::vector<const void*> tplan_key;
+  hipGraph_t tgraph = nullptr;
+  hipGraphExec_t texec = nullptr;
   ~tt_problem() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (texec) (void)hipGraphExecDestroy(texec);
+    if (tgraph) (void)hipGraphDestroy(tgraph);
   }
 };
 
 namespace qtt {
+
+// A stage-shaped MPO: the fixed part F stacked with the mean-field chain over
+// the phi sites (its first core scaled by mf_scale) whose x-site blocks,
+// diag(<Phi_a>) of a rounded mean field, are written when a step runs.
+static std::unique_ptr<tt_tt> assemble_stage_mpo(tt_problem* P, const host::TT& F, double mf_scale,
+                                                 std::vector<int>& Dfix) {
+  const int N = P->N;
+  Dfix = exact_caps(F);
+  std::vector<int> Dc(N + 1, 1);
+  for (int n = 1; n < N; ++n) Dc[n] = Dfix[n] + P->Dmf[n];
+  auto A = make_tt(P->ctx, TT_MPO, N, Dc);
+  std::vector<double> h(A->total(), 0.0);
+  auto put = [&](int n, const host::Core& B, int ro, int co, double sc) {
+    for (int i = 0; i < B.rl; ++i)
+      for (int s = 0; s < 4; ++s)
+        for (int j = 0; j < B.rr; ++j)
+          h[A->off[n] + ((int64_t)(ro + i) * 4 + s) * Dc[n + 1] + co + j] = sc * B.at(i, s, j);
+  };
+  for (int n = 0; n < N; ++n) {
+    put(n, F[n], 0, 0, 1.0);
+    if (n < P->nphi) {
+      const int ro = (n == 0) ? 0 : Dfix[n];
+      const int co = (n == N - 1) ? 0 : Dfix[n + 1];
+      put(n, P->MFh[n], ro, co, n == 0 ? mf_scale : 1.0);
+    }
+  }
+  rt::copy(A->buf.p, h.data(), h.size() * sizeof(double));
+  return A;
+}
 
 // mean-field partial contraction of x over the phi sites: E (2 x cphi), and
 // for 5-D the first x-core of each raw mean field, first[a] = E[a,:] x_{nphi}
@@ -185,6 +233,68 @@ static ChainView mean_view(tt_problem* P, const tt_tt* x, const double* first, i
   v.core.push_back(first + (size_t)a * 2 * x->caps[P->nphi + 1]);
   for (int j = 1; j < P->nx; ++j) v.core.push_back(x->core(P->nphi + j));
   return v;
+}
+
+// one term c * <Phi_a>(x) of a raw mean field (first x-core in `first`)
+struct MeanTerm {
+  double c;
+  const tt_tt* x;
+  const double* first;
+};
+
+// 5-D: rounds sum_j c_j <Phi_a>(x_j) to chi_mean into mt[a], a = 0, 1
+static void plan_mean_round(Plan& plan, tt_problem* P, const std::vector<MeanTerm>& terms,
+                            tt_tt* const mt[2]) {
+  ChainView Zm = view(P->Zm.get());
+  for (int a = 0; a < 2; ++a) {
+    std::vector<SketchTerm> st;
+    for (const MeanTerm& m : terms) {
+      SketchTerm t;
+      t.coef = m.c;
+      t.x = mean_view(P, m.x, m.first, a);
+      st.push_back(t);
+    }
+    RoundTarget tg;
+    for (int j = 0; j < P->nx; ++j) tg.core.push_back(mt[a]->core(j));
+    tg.caps = mt[a]->caps;
+    plan_round_sketch(plan, st, Zm, tg, Prec::F64);
+  }
+}
+
+// 5-D: writes diag(mt[a]) into the x-site mean-field blocks of a stage-shaped
+// MPO whose fixed part has bonds Dfix
+static void plan_mf_blocks(Plan& plan, tt_problem* P, tt_tt* mpo, const std::vector<int>& Dfix,
+                           tt_tt* const mt[2]) {
+  std::vector<CopyJob> jobs;
+  int64_t maxe = 1;
+  const int N = P->N, nphi = P->nphi, nx = P->nx;
+  for (int j = 0; j < nx; ++j) {
+    const int n = nphi + j;
+    for (int a = 0; a < 2; ++a) {
+      const tt_tt* m = mt[a];
+      CopyJob c{};
+      c.src = m->core(j);
+      c.dst = mpo->core(n);
+      c.rl = m->caps[j];
+      c.sp = 2;
+      c.rr = m->caps[j + 1];
+      c.dp = 4;
+      c.drr = mpo->caps[n + 1];
+      const int row0 = (n == 0) ? 0 : Dfix[n];
+      const int col0 = (n == N - 1) ? 0 : Dfix[n + 1];
+      c.ro = row0 + ((j == 0) ? a : a * P->mcaps[j]);
+      c.co = col0 + ((j == nx - 1) ? 0 : a * P->mcaps[j + 1]);
+      c.diag = 1;
+      c.scale = 1.0;
+      c.dscale = nullptr;
+      jobs.push_back(c);
+      maxe = std::max<int64_t>(maxe, (int64_t)c.rl * 2 * c.rr);
+    }
+  }
+  for (const CopyJob& j : jobs) validate(j);
+  CopyJob* dj = plan.upload(jobs);
+  const int nj = (int)jobs.size();
+  plan.add([=](hipStream_t s) { copy_jobs(dj, nj, maxe, s); });
 }
 
 // writes the mean-field blocks of the stage operator A for the state
@@ -224,58 +334,27 @@ static void plan_stage_operator(Plan& plan, tt_problem* P, const tt_tt* f, const
     return;
   }
   // 5-D: round the raw mean fields of g over the x sites, write diag blocks
-  Prec pf = Prec::F64;
-  ChainView Zm = view(P->Zm.get());
-  for (int a = 0; a < 2; ++a) {
-    std::vector<SketchTerm> terms;
-    SketchTerm t1;
-    t1.coef = 1.0;
-    t1.x = mean_view(P, f, P->mff.d(), a);
-    terms.push_back(t1);
-    if (kprev) {
-      SketchTerm t2;
-      t2.coef = cg;
-      t2.x = mean_view(P, kprev, P->mfk.d(), a);
-      terms.push_back(t2);
-    }
-    RoundTarget tg;
-    for (int j = 0; j < P->nx; ++j) tg.core.push_back(P->mt[a]->core(j));
-    tg.caps = P->mt[a]->caps;
-    plan_round_sketch(plan, terms, Zm, tg, pf);
-  }
-  std::vector<CopyJob> jobs;
-  int64_t maxe = 1;
-  const int N = P->N, nphi = P->nphi, nx = P->nx;
-  for (int j = 0; j < nx; ++j) {
-    const int n = nphi + j;
-    for (int a = 0; a < 2; ++a) {
-      const tt_tt* m = P->mt[a].get();
-      CopyJob c{};
-      c.src = m->core(j);
-      c.dst = P->A->core(n);
-      c.rl = m->caps[j];
-      c.sp = 2;
-      c.rr = m->caps[j + 1];
-      c.dp = 4;
-      c.drr = P->A->caps[n + 1];
-      int row0 = (n == 0) ? 0 : P->Dfix[n];
-      int col0 = (n == N - 1) ? 0 : P->Dfix[n + 1];
-      c.ro = row0 + ((j == 0) ? a : a * P->mcaps[j]);
-      c.co = col0 + ((j == nx - 1) ? 0 : a * P->mcaps[j + 1]);
-      c.diag = 1;
-      c.scale = 1.0;
-      c.dscale = nullptr;
-      jobs.push_back(c);
-      maxe = std::max<int64_t>(maxe, (int64_t)c.rl * 2 * c.rr);
-    }
-  }
-  for (const CopyJob& j : jobs) validate(j);
-  CopyJob* dj = plan.upload(jobs);
-  int nj = (int)jobs.size();
-  plan.add([=](hipStream_t s) { copy_jobs(dj, nj, maxe, s); });
+  std::vector<MeanTerm> terms{{1.0, f, P->mff.d()}};
+  if (kprev) terms.push_back({cg, kprev, P->mfk.d()});
+  tt_tt* mt[2] = {P->mt[0].get(), P->mt[1].get()};
+  plan_mean_round(plan, P, terms, mt);
+  plan_mf_blocks(plan, P, P->A.get(), P->Dfix, mt);
 }
 
-static void build_step_plan(tt_problem* P, tt_tt* f) {
+// forward-mode derivative carried along a step: parameter q and its tangent df
+struct Tangent {
+  int q;
+  tt_tt* df;
+};
+
+// Records one step of f; with tangents, also the derivative of the step
+// with respect to each parameter (forward mode, stage by stage): with
+// g_i = f + c_i k_(i-1) and dg_i = df + c_i dk_(i-1),
+//   dk_i = Round( A(g_i) dg_i + B_q(g_i, dg_i) g_i ),
+//   B_q = dA_fix/dq - sum_a D1g^(phi_a) diag(alpha_q <Phi_a>(g_i) + Omega <Phi_a>(dg_i)),
+// alpha_Omega = 1, alpha_k = 0 (the mean field enters A through -Omega m_a(g)),
+// and df+ = Round(df + sum_i b_i dk_i) beside f+ = Round(f + sum_i b_i k_i).
+static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vector<Tangent>& tan) {
   auto plan = std::make_unique<Plan>();
   const tt_params& p = P->p;
   const Prec prec = prec_of(p.dtype);
@@ -285,52 +364,74 @@ static void build_step_plan(tt_problem* P, tt_tt* f) {
   const int S = rk4 ? 4 : 2;
   const double dt = p.dt;
   const double cst[4] = {0.0, rk4 ? 0.5 * dt : dt, 0.5 * dt, dt};
+  std::vector<ChainView> Bv;
+  for (const Tangent& t : tan) Bv.push_back(view(P->Bt[t.q].get()));
+  auto sterm = [](double c, const ChainView* W, const tt_tt* x) {
+    SketchTerm t;
+    t.coef = c;
+    t.mpo = W;
+    t.x = view(x);
+    return t;
+  };
+  auto target = [&](const tt_tt* x) {
+    RoundTarget tg;
+    for (int n = 0; n < P->N; ++n) tg.core.push_back(x->core(n));
+    tg.caps = P->fcaps;
+    return tg;
+  };
   plan_mean_raw(*plan, P, f, P->Ef.d(), P->mff.d());
+  for (const Tangent& t : tan) plan_mean_raw(*plan, P, t.df, P->Edf[t.q].d(), P->mfdf[t.q].d());
   for (int i = 0; i < S; ++i) {
     const tt_tt* kp = (i == 0) ? nullptr : P->k[i - 1].get();
     const double cg = cst[i];
     if (kp) plan_mean_raw(*plan, P, kp, P->Ek.d(), P->mfk.d());
     plan_stage_operator(*plan, P, f, kp, cg);
-    std::vector<SketchTerm> terms;
-    SketchTerm a;
-    a.coef = 1.0;
-    a.mpo = &Av;
-    a.x = view(f);
-    terms.push_back(a);
-    if (kp) {
-      SketchTerm b;
-      b.coef = cg;
-      b.mpo = &Av;
-      b.x = view(kp);
-      terms.push_back(b);
+    {
+      std::vector<SketchTerm> terms{sterm(1.0, &Av, f)};
+      if (kp) terms.push_back(sterm(cg, &Av, kp));
+      RoundTarget tg = target(P->k[i].get());
+      plan_round_sketch(*plan, terms, Z, tg, prec);
     }
-    RoundTarget tg;
-    for (int n = 0; n < P->N; ++n) tg.core.push_back(P->k[i]->core(n));
-    tg.caps = P->fcaps;
-    plan_round_sketch(*plan, terms, Z, tg, prec);
+    for (size_t j = 0; j < tan.size(); ++j) {
+      const int q = tan[j].q;
+      const tt_tt* df = tan[j].df;
+      const tt_tt* dkp = (i == 0) ? nullptr : P->dk[q][i - 1].get();
+      if (dkp) plan_mean_raw(*plan, P, dkp, P->Edk[q].d(), P->mfdk[q].d());
+      std::vector<MeanTerm> mterms;
+      if (q == 0) {
+        mterms.push_back({1.0, f, P->mff.d()});
+        if (kp) mterms.push_back({cg, kp, P->mfk.d()});
+      }
+      mterms.push_back({p.omega, df, P->mfdf[q].d()});
+      if (dkp) mterms.push_back({p.omega * cg, dkp, P->mfdk[q].d()});
+      tt_tt* mt[2] = {P->mtt[q][0].get(), P->mtt[q][1].get()};
+      plan_mean_round(*plan, P, mterms, mt);
+      plan_mf_blocks(*plan, P, P->Bt[q].get(), P->Dfix_t[q], mt);
+      std::vector<SketchTerm> terms{sterm(1.0, &Av, df), sterm(1.0, &Bv[j], f)};
+      if (kp) {
+        terms.push_back(sterm(cg, &Av, dkp));
+        terms.push_back(sterm(cg, &Bv[j], kp));
+      }
+      RoundTarget tg = target(P->dk[q][i].get());
+      plan_round_sketch(*plan, terms, Z, tg, prec);
+    }
   }
-  std::vector<SketchTerm> comb;
-  auto add = [&](double c, const tt_tt* x) {
-    SketchTerm t;
-    t.coef = c;
-    t.x = view(x);
-    comb.push_back(t);
+  const double b4[4] = {dt / 6, dt / 3, dt / 3, dt / 6}, b2[2] = {0.5 * dt, 0.5 * dt};
+  const double* b = rk4 ? b4 : b2;
+  auto combine = [&](tt_tt* x, std::unique_ptr<tt_tt>* ks) {
+    std::vector<SketchTerm> comb{sterm(1.0, nullptr, x)};
+    for (int i = 0; i < S; ++i) comb.push_back(sterm(b[i], nullptr, ks[i].get()));
+    RoundTarget tg = target(x);
+    plan_round_sketch(*plan, comb, Z, tg, prec);
+    return tg;
   };
-  add(1.0, f);
-  if (rk4) {
-    add(dt / 6, P->k[0].get());
-    add(dt / 3, P->k[1].get());
-    add(dt / 3, P->k[2].get());
-    add(dt / 6, P->k[3].get());
-  } else {
-    add(0.5 * dt, P->k[0].get());
-    add(0.5 * dt, P->k[1].get());
-  }
-  RoundTarget tg;
-  for (int n = 0; n < P->N; ++n) tg.core.push_back(f->core(n));
-  tg.caps = P->fcaps;
-  plan_round_sketch(*plan, comb, Z, tg, prec);
-  P->last = tg;
+  P->last = combine(f, P->k);
+  for (const Tangent& t : tan) combine(t.df, P->dk[t.q]);
+  return plan;
+}
+
+static void build_step_plan(tt_problem* P, tt_tt* f) {
+  auto plan = record_step(P, f, {});
   if (P->exec) {
     (void)hipGraphExecDestroy(P->exec);
     P->exec = nullptr;
@@ -341,6 +442,36 @@ static void build_step_plan(tt_problem* P, tt_tt* f) {
   }
   P->plan = std::move(plan);
   P->plan_f = f;
+  P->last_plain = P->last;
+}
+
+// operator and buffers of the derivative with respect to parameter q
+static void ensure_tangent(tt_problem* P, int q) {
+  if (P->Bt[q]) return;
+  QTT_REQUIRE(P->nx > 0, "parameter derivatives are available for 5-D problems");
+  const tt_params& p = P->p;
+  std::vector<tt_term> terms;
+  for (int a = 0; a < 2; ++a) {
+    tt_term t{};
+    t.coeff = 1.0;
+    for (int d = 0; d < 8; ++d) t.op[d] = TT_OP_ID;
+    t.op[a] = TT_OP_D1G_PHI;  // d/dOmega of Omega D1g diag(phi_a)
+    if (q == 1) t.op[1 - a] = TT_OP_PHI;  // d/dk of k D1g diag(phi1 phi2)
+    t.field = -1;
+    terms.push_back(t);
+  }
+  host::TT F = build_mpo_host(p.ndims, p.bits, p.ordering, terms.data(), (int)terms.size(), {}, 3, 1e-13);
+  P->Bt[q] = assemble_stage_mpo(P, F, -1.0, P->Dfix_t[q]);
+  const int S = (p.integrator == TT_RK4) ? 4 : 2;
+  for (int i = 0; i < S; ++i) {
+    P->dk[q][i] = make_tt(P->ctx, TT_MPS, P->N, P->fcaps);
+    fill(P->dk[q][i]->buf.d(), P->dk[q][i]->total(), 0.0, P->ctx->stream);
+  }
+  for (int a = 0; a < 2; ++a) P->mtt[q][a] = make_tt(P->ctx, TT_MPS, P->nx, P->mcaps);
+  P->Edf[q].alloc(sizeof(double) * 2 * P->cphi);
+  P->Edk[q].alloc(sizeof(double) * 2 * P->cphi);
+  P->mfdf[q].alloc(sizeof(double) * 2 * 2 * P->cphi1);
+  P->mfdk[q].alloc(sizeof(double) * 2 * 2 * P->cphi1);
 }
 
 static bool use_graph() {
@@ -729,7 +860,6 @@ tt_status tt_problem_create(tt_ctx* ctx, const tt_params* pp, const tt_tt* const
     }
     host::TT Fx = build_mpo_host(p.ndims, p.bits, p.ordering, terms.data(), (int)terms.size(),
                                  fields, 3, 1e-13);
-    P->Dfix = exact_caps(Fx);
     // ---- mean-field part  -Omega sum_a D1g^(a) diag(<Phi_a>)
     auto order = host::site_order(p.ndims, p.bits, p.ordering);
     std::vector<std::pair<int, int>> phi_order(order.begin(), order.begin() + P->nphi);
@@ -756,10 +886,9 @@ tt_status tt_problem_create(tt_ctx* ctx, const tt_params* pp, const tt_tt* const
           int co;
           if (n == nphi - 1) co = (P->nx > 0) ? a : 0;
           else co = (a == 0) ? 0 : A0.rr;
-          double sc = (n == 0 && P->nx > 0) ? -p.omega : 1.0;
           for (int i = 0; i < B.rl; ++i)
             for (int s = 0; s < 4; ++s)
-              for (int j = 0; j < B.rr; ++j) G.at(ro + i, s, co + j) += sc * B.at(i, s, j);
+              for (int j = 0; j < B.rr; ++j) G.at(ro + i, s, co + j) += B.at(i, s, j);
         }
         MF.push_back(std::move(G));
       }
@@ -768,27 +897,11 @@ tt_status tt_problem_create(tt_ctx* ctx, const tt_params* pp, const tt_tt* const
       for (int j = 1; j < P->nx; ++j) Dmf[nphi + j] = 2 * P->mcaps[j];
       Dmf[N] = 1;
     }
-    std::vector<int> Dc(N + 1, 1);
-    for (int n = 1; n < N; ++n) Dc[n] = P->Dfix[n] + Dmf[n];
-    P->A = make_tt(ctx, TT_MPO, N, Dc);
-    {
-      std::vector<double> h(P->A->total(), 0.0);
-      auto put = [&](int n, const host::Core& B, int ro, int co) {
-        for (int i = 0; i < B.rl; ++i)
-          for (int s = 0; s < 4; ++s)
-            for (int j = 0; j < B.rr; ++j)
-              h[P->A->off[n] + ((int64_t)(ro + i) * 4 + s) * Dc[n + 1] + co + j] = B.at(i, s, j);
-      };
-      for (int n = 0; n < N; ++n) {
-        put(n, Fx[n], 0, 0);
-        if (n < P->nphi) {
-          int ro = (n == 0) ? 0 : P->Dfix[n];
-          int co = (n == N - 1) ? 0 : P->Dfix[n + 1];
-          put(n, MF[n], ro, co);
-        }
-      }
-      rt::copy(P->A->buf.p, h.data(), h.size() * sizeof(double));
-    }
+    P->MFh = MF;
+    P->Dmf = Dmf;
+    // 5-D: the mean-field block carries -Omega in its first core; 2-D: the
+    // first-core blocks are rescaled by -Omega <Phi_a> at every stage
+    P->A = assemble_stage_mpo(P.get(), Fx, P->nx > 0 ? -p.omega : 1.0, P->Dfix);
     if (P->nx == 0) {
       // first-core blocks of the two mean-field terms, kept unscaled
       P->mf_first_cols = {T[0][0].rr, T[1][0].rr};
@@ -902,6 +1015,7 @@ tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps) {
     QTT_REQUIRE(f->caps == prob->fcaps, "state caps differ from the problem's");
     if (n_steps == 0) return;
     if (!prob->plan || prob->plan_f != f) build_step_plan(prob, f);
+    prob->last = prob->last_plain;
     StreamScope sc(ctx);
     if (rt::dry() || !use_graph()) {
       for (int i = 0; i < n_steps; ++i) prob->plan->run(ctx->stream);
@@ -1012,6 +1126,62 @@ tt_status tt_batch_destroy(tt_batch* b) {
     if (!b) return;
     if (!rt::dry()) (void)hipStreamSynchronize(b->ctx->stream);
     delete b;
+  });
+}
+
+tt_status tt_step_tangent(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_params, const int* params,
+                          tt_tt* const* dfs, int n_steps) {
+  return guard([&] {
+    QTT_REQUIRE(prob && f && n_steps >= 0 && n_params >= 1 && n_params <= 2 && params && dfs,
+                "bad argument");
+    check_tt(f, ctx);
+    QTT_REQUIRE(prob->ctx == ctx, "problem belongs to another context");
+    QTT_REQUIRE(f->caps == prob->fcaps, "state caps differ from the problem's");
+    std::vector<Tangent> tan;
+    std::vector<const void*> key{f};
+    for (int j = 0; j < n_params; ++j) {
+      QTT_REQUIRE(params[j] == TT_PARAM_OMEGA || params[j] == TT_PARAM_K, "unknown parameter %d", params[j]);
+      for (int i = 0; i < j; ++i) QTT_REQUIRE(params[i] != params[j], "parameter listed twice");
+      check_tt(dfs[j], ctx);
+      QTT_REQUIRE(dfs[j]->caps == prob->fcaps, "tangent caps differ from the problem's");
+      QTT_REQUIRE(dfs[j] != f, "tangent aliases the state");
+      for (int i = 0; i < j; ++i) QTT_REQUIRE(dfs[i] != dfs[j], "two parameters share a tangent");
+      ensure_tangent(prob, params[j]);
+      tan.push_back({params[j], dfs[j]});
+      key.push_back(dfs[j]);
+      key.push_back(reinterpret_cast<const void*>((intptr_t)params[j]));
+    }
+    if (n_steps == 0) return;
+    if (!prob->tplan || prob->tplan_key != key) {
+      prob->tplan = record_step(prob, f, tan);
+      prob->tplan_key = key;
+      if (prob->texec) (void)hipGraphExecDestroy(prob->texec);
+      if (prob->tgraph) (void)hipGraphDestroy(prob->tgraph);
+      prob->texec = nullptr;
+      prob->tgraph = nullptr;
+      prob->last_tan = prob->last;
+      prob->last = prob->last_plain;
+    }
+    prob->last = prob->last_tan;
+    StreamScope sc(ctx);
+    if (rt::dry() || !use_graph()) {
+      for (int i = 0; i < n_steps; ++i) prob->tplan->run(ctx->stream);
+      return;
+    }
+    if (!prob->texec) {
+      QTT_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+      try {
+        prob->tplan->run(ctx->stream);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(ctx->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      QTT_HIP(hipStreamEndCapture(ctx->stream, &prob->tgraph));
+      QTT_HIP(hipGraphInstantiate(&prob->texec, prob->tgraph, nullptr, nullptr, 0));
+    }
+    for (int i = 0; i < n_steps; ++i) QTT_HIP(hipGraphLaunch(prob->texec, ctx->stream));
   });
 }
 

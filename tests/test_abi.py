@@ -92,6 +92,33 @@ print("ok")
     assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
 
 
+def test_dry_run_tangent_planning_is_in_bounds():
+    """The step with its two parameter derivatives plans every launch in
+    bounds (5-D M = 16 and the M = 256, chi = 64 gradient size)."""
+    code = r"""
+import os, sys
+os.environ["QTTPDF_DRYRUN"] = "1"
+sys.path.insert(0, %r)
+import paper_2407_09169_amd as q, workloads
+ctx = q.Context(0, stream=0)
+for w in [workloads.get_workload("t_5d_M16_chi32"),
+          workloads.get_workload("c2_5d_M128_chi64").replace(bits=8, k_react=10.0, dt=2e-4)]:
+    prob, f = q.setup_workload(ctx, w, "f32")
+    tans = {"omega": prob.state(), "k_react": prob.state()}
+    prob.step_tangent(f, tans, 1)
+    prob.step(f, 1)
+try:
+    prob.step_tangent(f, {"omega": f}, 1)
+except q.QttError as e:
+    assert "aliases" in str(e), e
+else:
+    raise SystemExit("no error for a tangent that aliases the state")
+print("ok")
+""" % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
+
+
 def test_errors_are_reported_not_thrown():
     code = r"""
 import os, sys
