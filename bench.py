@@ -202,6 +202,43 @@ def _bench_batched(args, log):
     print(json.dumps(out))
 
 
+def _bench_gradient(args, log):
+    """Steps of the gradient workload carrying d f / d Omega and d f / d k
+    (tt_step_tangent): gradient-steps/s and the final dJ/dtheta of the
+    product mean."""
+    import torch
+    import paper_2407_09169_amd as q
+    import workloads
+    name = args.workload if args.workload != "c3_5d_M1024_chi128" else "c5_5d_M256_chi64"
+    w = workloads.get_workload(name)
+    ctx = q.Context(0)
+    prob, f = q.setup_workload(ctx, w, args.dtype)
+    tans = {"omega": prob.state(), "k_react": prob.state()}
+    n = w.steps
+    log(f"{w.name} {args.dtype}: {n} steps with two tangents")
+    prob.step_tangent(f, tans, 1)  # records the graph
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    prob.step_tangent(f, tans, n - 1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    J = prob.observable(f, "product")
+    g = {p: prob.observable(t, "product") for p, t in tans.items()}
+    log(f"{n - 1} steps in {ms:.1f} ms; J = {J:.6e}, dJ/dOmega = {g['omega']:.6e}, dJ/dk = {g['k_react']:.6e}")
+    out = {
+        "metric": "RK4 steps/s carrying dJ/dOmega and dJ/dk (forward-mode tangents), 5-D chi=64",
+        "value": (n - 1) / (ms / 1e3), "unit": "steps/s", "n_gpus": 1, "steps": n - 1, "warmup": 1,
+        "ms_per_step": ms / (n - 1), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": w.name, "grid": f"{w.M}^{w.ndims}", "n_cores": w.n_sites, "chi": w.chi,
+                   "statistic": "product mean", "steps_total": n},
+        "J": J, "dJ_dOmega": g["omega"], "dJ_dk": g["k_react"],
+    }
+    print(json.dumps(out))
+
+
 def _copy_probe(nbytes):
     """A plain device copy of known size (torch's copy kernel), for scaling
     the HBM counters of rocprofv3 runs."""
@@ -251,6 +288,9 @@ def main():
                     help="also write the per-launch event times of one eager step to this file")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--gradient", action="store_true",
+                    help="time steps that also carry the derivatives with respect to Omega and k "
+                         "(default workload for this mode: c5_5d_M256_chi64, all its steps)")
     ap.add_argument("--kernel-probe", default=None, metavar="qr:MxN",
                     help="only run the FP64 Householder QR kernel on one seeded M x N matrix "
                          "five times (counter runs of the dominant kernel)")
@@ -275,6 +315,9 @@ def main():
 
     if args.workload == "batch64":
         _bench_batched(args, log)
+        return
+    if args.gradient:
+        _bench_gradient(args, log)
         return
     w = workloads.get_workload(args.workload)
     ctx = q.Context(0)

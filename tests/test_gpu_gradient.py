@@ -44,20 +44,23 @@ def test_tangent_untruncated_equals_dense(ctx):
         assert abs(g - gd) <= 1e-9 * max(abs(gd), 1e-12), (p, g, gd)
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", 1e-3), ("f32", 1e-3)])
-def test_gradient_matches_central_differences(ctx, dtype, tol):
-    """Truncated 5-D M = 16, chi = 32: dJ/dtheta from the tangents against
-    central differences (h = 1e-4 relative) of the GPU step itself."""
-    w = workloads.get_workload("t_5d_M16_chi32")
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gradient_matches_central_differences(ctx, dtype):
+    """Truncated 5-D M = 16 at chi = 64: dJ/dtheta from the tangents against
+    central differences (h = 1e-4 relative) of the FP64 GPU step, to 1e-3
+    (rounding the tangent stands in for the derivative of the rounding; the
+    gap shrinks with the discarded weight).  FP32 is compared with the FP64
+    differences: its own differences drown in FP32 noise at this h."""
+    w = workloads.get_workload("t_5d_M16_chi32").replace(chi=64)
     n = 3
     J, g = q.statistic_and_gradient(ctx, w, n, "product", dtype)
     for p in ("omega", "k_react"):
         th = getattr(w, p)
         h = 1e-4 * max(1.0, abs(th))
-        Jp, _ = q.statistic_and_gradient(ctx, w.replace(**{p: th + h}), n, "product", dtype, params=(p,))
-        Jm, _ = q.statistic_and_gradient(ctx, w.replace(**{p: th - h}), n, "product", dtype, params=(p,))
+        Jp, _ = q.statistic_and_gradient(ctx, w.replace(**{p: th + h}), n, "product", "f64", params=(p,))
+        Jm, _ = q.statistic_and_gradient(ctx, w.replace(**{p: th - h}), n, "product", "f64", params=(p,))
         fdv = (Jp - Jm) / (2 * h)
-        assert abs(g[p] - fdv) <= tol * abs(fdv) + 1e-10, (p, g[p], fdv)
+        assert abs(g[p] - fdv) <= 1e-3 * abs(fdv), (p, g[p], fdv)
 
 
 def test_autograd_function(ctx):

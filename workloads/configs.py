@@ -84,6 +84,10 @@ _W = [
              chi_mean=8, omega=1.0, k_react=10.0, dt=3e-5, steps=50, seed=2),
     Workload("c3_5d_M1024_chi256", ndims=5, bits=10, ordering="serial", chi=256, oversample=32,
              chi_mean=8, omega=1.0, k_react=10.0, dt=3e-5, steps=50, seed=2),
+    # 5-D PDF, M = 256, 40 serial cores, chi = 64: gradients of the final product mean
+    # with respect to Omega and k over 200 RK4 steps.
+    Workload("c5_5d_M256_chi64", ndims=5, bits=8, ordering="serial", chi=64, oversample=16,
+             chi_mean=16, omega=1.0, k_react=10.0, dt=2e-4, steps=200, seed=5),
     # Small 5-D cases that a dense full-grid solver can follow (tests).
     Workload("t_5d_M8_exact", ndims=5, bits=3, ordering="serial", chi=128, oversample=0,
              chi_mean=64, oversample_mean=0, vel_rank=64,
