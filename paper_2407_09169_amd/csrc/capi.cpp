@@ -246,7 +246,9 @@ struct MeanTerm {
 static void plan_mean_round(Plan& plan, tt_problem* P, const std::vector<MeanTerm>& terms,
                             tt_tt* const mt[2]) {
   ChainView Zm = view(P->Zm.get());
+  plan.fork(2);  // the two mean fields on two lanes
   for (int a = 0; a < 2; ++a) {
+    plan.on(a);
     std::vector<SketchTerm> st;
     for (const MeanTerm& m : terms) {
       SketchTerm t;
@@ -257,8 +259,9 @@ static void plan_mean_round(Plan& plan, tt_problem* P, const std::vector<MeanTer
     RoundTarget tg;
     for (int j = 0; j < P->nx; ++j) tg.core.push_back(mt[a]->core(j));
     tg.caps = mt[a]->caps;
-    plan_round_sketch(plan, st, Zm, tg, Prec::F64);
+    plan_round_sketch(plan, st, Zm, tg, Prec::F64, 1);
   }
+  plan.join(2);
 }
 
 // 5-D: writes diag(mt[a]) into the x-site mean-field blocks of a stage-shaped

@@ -360,6 +360,189 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
 }
 
 // ---------------------------------------------------------------------------
+// Householder QR with one column per 16-lane group (a DPP row): for
+// m <= 16*RPL, n <= 4*NW*CS.  Lane li of group g of wavefront w holds rows
+// li + 16 r (r < RPL) of the columns c = 32 j + 4 w + g ... more precisely
+// c = (4 NW) j + 4 w + g for slots j < CS.  A column dot product is a sum over
+// the 16 lanes of a group: four row-local DPP steps reduce the four columns
+// of a wavefront at once and leave each sum in every lane of its group.
+// Step k: the owner group builds the reflector, publishes v (double-buffered
+// LDS); one barrier; every group applies it to its columns c > k.  Q is
+// formed in place by backward accumulation.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ inline double dpp_row(double x) {  // every row lane valid: no old value
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(b & 0xffffffffull), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// sum over the 16 lanes of every row, left in every lane of the row
+__device__ inline double row_sum(double v) {
+  v += dpp_row<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_row<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_row<0x141>(v);  // row_half_mirror
+  v += dpp_row<0x140>(v);  // row_mirror
+  return v;
+}
+
+// a[:, c] -= t (v^T a[:, c]) v for this lane's columns c with k < c < n
+template <int RPL, int CS, int NW>
+__device__ inline void grp_apply(double (&a)[CS][RPL], const double (&v)[RPL], double t, int k, int n,
+                                 int w, int g) {
+  constexpr int CL = 4 * NW;
+#pragma unroll
+  for (int j = 0; j < CS; ++j) {
+    if (CL * j + 4 * w + 3 <= k) continue;  // no column of this slot is past k (wave-uniform)
+    if (CL * j + 4 * w >= n) break;
+    double d = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) d = fma(v[r], a[j][r], d);
+    d = row_sum(d);
+    const int c = CL * j + 4 * w + g;
+    const double wgt = (c > k && c < n) ? t * d : 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) a[j][r] = fma(-wgt, v[r], a[j][r]);
+  }
+}
+
+template <int RPL, int CS, int NW>
+__global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const double* __restrict__ A0,
+                                                       int64_t strideA, int64_t rs, int64_t cs,
+                                                       double* __restrict__ Q0, int64_t strideQ,
+                                                       double* __restrict__ R0, int64_t strideR) {
+  constexpr int CL = 4 * NW;
+  __shared__ double vbuf[2][16 * RPL];
+  __shared__ double taus[CL * CS];
+  __shared__ double betas[CL * CS];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t bi = blockIdx.x;
+  const double* A = A0 + bi * strideA;
+  double a[CS][RPL];
+#pragma unroll
+  for (int j = 0; j < CS; ++j) {
+    const int c = CL * j + 4 * w + g;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int row = li + 16 * r;
+      a[j][r] = (row < m && c < n) ? A[row * rs + c * cs] : 0.0;
+    }
+  }
+  double v[RPL];
+  for (int k = 0; k < n; ++k) {
+    const int wo = (k % CL) >> 2, go = k & 3, jo = k / CL, buf = k & 1;
+    if (w == wo) {
+      // owner wavefront: column jo of every group; only group go's is used
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        double x = 0.0;
+#pragma unroll
+        for (int j = 0; j < CS; ++j) x = (j == jo) ? a[j][r] : x;
+        v[r] = x;
+      }
+      double part = 0.0, xk = 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int row = li + 16 * r;
+        if (row > k) part = fma(v[r], v[r], part);
+        if (r == (k >> 4)) xk = v[r];
+      }
+      part = row_sum(part);
+      const double sig = read_lane(part, 16 * go);
+      const double x0 = read_lane(xk, 16 * go + (k & 15));
+      double tau = 0.0, beta = x0, scale = 0.0;
+      if (sig != 0.0) {
+        const double nrm = sqrt(x0 * x0 + sig);
+        beta = x0 >= 0.0 ? -nrm : nrm;
+        tau = (beta - x0) / beta;
+        scale = 1.0 / (x0 - beta);
+      }
+      if (g == go) {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          const int row = li + 16 * r;
+          const double vv = (row > k) ? v[r] * scale : (row == k ? 1.0 : 0.0);
+          vbuf[buf][row] = vv;
+          if (row > k) {
+#pragma unroll
+            for (int j = 0; j < CS; ++j)
+              if (j == jo) a[j][r] = vv;
+          }
+        }
+        if (li == 0) {
+          taus[k] = tau;
+          betas[k] = beta;
+        }
+      }
+    }
+    __syncthreads();
+    const double t = taus[k];
+    if (t != 0.0) {
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) v[r] = vbuf[buf][li + 16 * r];
+      grp_apply<RPL, CS, NW>(a, v, t, k, n, w, g);
+    }
+  }
+  __syncthreads();
+  if (R0 != nullptr) {
+    double* R = R0 + bi * strideR;
+#pragma unroll
+    for (int j = 0; j < CS; ++j) {
+      const int c = CL * j + 4 * w + g;
+      if (c >= n) continue;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int row = li + 16 * r;
+        if (row >= n) continue;
+        R[(int64_t)row * n + c] = (row < c) ? a[j][r] : (row == c ? betas[c] : 0.0);
+      }
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const int wo = (k % CL) >> 2, go = k & 3, jo = k / CL, buf = k & 1;
+    if (w == wo && g == go) {
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int row = li + 16 * r;
+        double x = 0.0;
+#pragma unroll
+        for (int j = 0; j < CS; ++j) x = (j == jo) ? a[j][r] : x;
+        vbuf[buf][row] = (row > k) ? x : (row == k ? 1.0 : 0.0);
+      }
+    }
+    __syncthreads();
+    const double t = taus[k];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) v[r] = vbuf[buf][li + 16 * r];
+    if (t != 0.0) grp_apply<RPL, CS, NW>(a, v, t, k, n, w, g);
+    if (w == wo && g == go) {
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int row = li + 16 * r;
+        const double qv = (row < k) ? 0.0 : (row == k ? 1.0 - t : -t * v[r]);
+#pragma unroll
+        for (int j = 0; j < CS; ++j)
+          if (j == jo) a[j][r] = qv;
+      }
+    }
+  }
+  double* Q = Q0 + bi * strideQ;
+#pragma unroll
+  for (int j = 0; j < CS; ++j) {
+    const int c = CL * j + 4 * w + g;
+    if (c >= n) continue;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int row = li + 16 * r;
+      if (row < m) Q[(int64_t)row * n + c] = a[j][r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Symmetric PSD eigen-decomposition by one-sided (Hestenes) Jacobi on G:
 // G J = U S with J accumulated; for PSD G the columns of J are eigenvectors
 // and the column norms of G J the eigenvalues.  Round-robin pair ordering,
@@ -752,8 +935,11 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
 // register-resident configurations, tried in order: (rows per lane, columns
 // per wave, waves, reduction chunk) and (rows per lane, pairs per wave,
 // waves, reduction chunk); larger problems use the global-memory kernels
-#define QTT_QR_CONFIGS(X) \
-  X(1, 1, 16, 1) X(1, 2, 16, 2) X(2, 2, 16, 2) X(2, 4, 16, 4) X(3, 6, 16, 3) X(4, 8, 16, 4) X(5, 9, 16, 3) X(5, 10, 16, 2)
+#define QTT_QR_CONFIGS(X) X(1, 1, 16, 1) X(1, 2, 16, 2) X(2, 2, 16, 2) X(2, 4, 16, 4)
+// one column per 16-lane group: (rows per lane, column slots, waves)
+#define QTT_QRG_CONFIGS(X) X(12, 3, 8) X(16, 4, 8) X(18, 3, 12)
+// larger than the group configurations
+#define QTT_QR_CONFIGS_LARGE(X) X(5, 10, 16, 2)
 #define QTT_EIG_CONFIGS(X) \
   X(1, 1, 4, 1) X(1, 2, 8, 2) X(1, 4, 8, 4) X(2, 4, 8, 4) X(2, 8, 8, 4) X(3, 6, 12, 2)
 
@@ -765,6 +951,20 @@ std::string qr_kernel_name(int m, int n) {
     return b;                                                                         \
   }
   QTT_QR_CONFIGS(QTT_QR_NAME)
+#undef QTT_QR_NAME
+#define QTT_QRG_NAME(RPL_, CS_, NW_)                                                \
+  if (m <= 16 * RPL_ && n <= 4 * NW_ * CS_) {                                       \
+    snprintf(b, sizeof b, "qr_grp_kernel<%d, %d, %d>", RPL_, CS_, NW_);             \
+    return b;                                                                       \
+  }
+  QTT_QRG_CONFIGS(QTT_QRG_NAME)
+#undef QTT_QRG_NAME
+#define QTT_QR_NAME(RS_, CPW_, NW_, CH_)                                              \
+  if (m <= 64 * RS_ && n <= NW_ * CPW_) {                                             \
+    snprintf(b, sizeof b, "qr_reg_kernel<%d, %d, %d, %d>", RS_, CPW_, NW_, CH_); \
+    return b;                                                                         \
+  }
+  QTT_QR_CONFIGS_LARGE(QTT_QR_NAME)
 #undef QTT_QR_NAME
   return "qr_kernel";
 }
@@ -800,6 +1000,24 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
     return;                                                                                      \
   }
   QTT_QR_CONFIGS(QTT_QR_REG)
+#undef QTT_QR_REG
+#define QTT_QR_GRP(RPL_, CS_, NW_)                                                                \
+  if (m <= 16 * RPL_ && n <= 4 * NW_ * CS_) {                                                     \
+    hipLaunchKernelGGL((qr_grp_kernel<RPL_, CS_, NW_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
+                       strideA, rs, cs, Q, strideQ, R, strideR);                                 \
+    QTT_HIP(hipGetLastError());                                                                  \
+    return;                                                                                      \
+  }
+  QTT_QRG_CONFIGS(QTT_QR_GRP)
+#undef QTT_QR_GRP
+#define QTT_QR_REG(RS_, CPW_, NW_, CH_)                                                           \
+  if (m <= 64 * RS_ && n <= NW_ * CPW_) {                                                         \
+    hipLaunchKernelGGL((qr_reg_kernel<RS_, CPW_, NW_, CH_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
+                       strideA, rs, cs, Q, strideQ, R, strideR);                                 \
+    QTT_HIP(hipGetLastError());                                                                  \
+    return;                                                                                      \
+  }
+  QTT_QR_CONFIGS_LARGE(QTT_QR_REG)
 #undef QTT_QR_REG
   hipLaunchKernelGGL(qr_kernel, dim3(count), dim3(FT), 0, s, m, n, A, strideA, rs, cs, Q, strideQ,
                      R, strideR, work);

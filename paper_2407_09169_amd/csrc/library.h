@@ -63,11 +63,24 @@ struct OpInfo {
   std::string what;    // shape description for per-op timing logs
 };
 
-// list of enqueue operations with the workspaces they use
+// List of enqueue operations with the workspaces they use.  Operations go to
+// lanes: lane 0 is the stream the plan runs on, lanes 1.. are streams the
+// plan owns (default priority).  fork(n) makes lanes 1..n-1 wait for what
+// lane 0 has enqueued so far; join(n) makes lane 0 wait for lanes 1..n-1.
+// A plan ends joined, so a replay (eager or captured into a HIP graph) is
+// ordered with the caller's stream at both ends.
 struct Plan {
   std::vector<std::function<void(hipStream_t)>> ops;
   std::vector<OpInfo> info;
+  std::vector<int> lane;  // lane of every op
   std::vector<std::unique_ptr<DevBuf>> bufs;
+  std::vector<hipStream_t> streams;  // lanes 1..
+  std::vector<hipEvent_t> events;
+  int cur = 0;
+  Plan() = default;
+  Plan(const Plan&) = delete;
+  Plan& operator=(const Plan&) = delete;
+  ~Plan();
   double* alloc(size_t n_doubles) {
     bufs.emplace_back(new DevBuf(std::max<size_t>(n_doubles, 1) * sizeof(double)));
     return bufs.back()->d();
@@ -81,9 +94,14 @@ struct Plan {
   void add(std::function<void(hipStream_t)> f, OpInfo oi = OpInfo{}) {
     ops.push_back(std::move(f));
     info.push_back(oi);
+    lane.push_back(cur);
   }
+  void fork(int n);
+  void on(int l) { cur = l; }
+  void join(int n);
+  hipStream_t stream_of(int l, hipStream_t s0) const { return l == 0 ? s0 : streams[l - 1]; }
   void run(hipStream_t s) const {
-    for (auto& f : ops) f(s);
+    for (size_t i = 0; i < ops.size(); ++i) ops[i](stream_of(lane[i], s));
   }
   // eager run with a pair of events around every op of class `kind` (OP_ALL:
   // every op); adds the event time (ms), the number of such ops and their
@@ -92,6 +110,10 @@ struct Plan {
   // file.
   void run_profiled(hipStream_t s, int kind, double& ms, int64_t& count, double& flops,
                     double& bytes) const;
+
+ private:
+  hipEvent_t new_event();
+  void ensure_lanes(int n);
 };
 
 struct SketchTerm {
@@ -111,8 +133,9 @@ struct RoundTarget {
 
 // randomized range finding (right sketches + QR sweep) into an ell-rank
 // left-orthogonal chain, then simultaneous SVD truncation to target.caps
+// (the terms' independent chains use up to `lanes` lanes when called on lane 0)
 void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const ChainView& Z,
-                       RoundTarget& target, Prec prec);
+                       RoundTarget& target, Prec prec, int lanes = 4);
 // LQ sweep + QR sweep + simultaneous truncation of an explicit chain
 void plan_round_det(Plan& plan, const ChainView& x, RoundTarget& target);
 // QR sweep only: left-orthogonal copy (returns caps of the result); used for norms

@@ -92,6 +92,62 @@ static OpInfo qr_info(int m, int n) {
   return oi;
 }
 
+Plan::~Plan() {
+  for (auto e : events)
+    if (e) (void)hipEventDestroy(e);
+  for (auto st : streams)
+    if (st) (void)hipStreamDestroy(st);
+}
+
+hipEvent_t Plan::new_event() {
+  hipEvent_t e = nullptr;
+  if (!rt::dry()) QTT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  events.push_back(e);
+  return e;
+}
+
+void Plan::ensure_lanes(int n) {
+  while ((int)streams.size() < n - 1) {
+    hipStream_t st = nullptr;
+    if (!rt::dry()) QTT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    streams.push_back(st);
+  }
+}
+
+void Plan::fork(int n) {
+  if (n <= 1) return;  // single lane: nothing to order
+  QTT_REQUIRE(cur == 0, "fork from lane 0 only");
+  ensure_lanes(n);
+  hipEvent_t e = new_event();
+  add([e](hipStream_t s) {
+    if (!rt::dry()) QTT_HIP(hipEventRecord(e, s));
+  });
+  for (int l = 1; l < n; ++l) {
+    cur = l;
+    add([e](hipStream_t s) {
+      if (!rt::dry()) QTT_HIP(hipStreamWaitEvent(s, e, 0));
+    });
+  }
+  cur = 0;
+}
+
+void Plan::join(int n) {
+  if (n <= 1) return;
+  QTT_REQUIRE(cur < n, "join of lanes that were not forked");
+  for (int l = 1; l < n; ++l) {
+    hipEvent_t e = new_event();
+    cur = l;
+    add([e](hipStream_t s) {
+      if (!rt::dry()) QTT_HIP(hipEventRecord(e, s));
+    });
+    cur = 0;
+    add([e](hipStream_t s) {
+      if (!rt::dry()) QTT_HIP(hipStreamWaitEvent(s, e, 0));
+    });
+  }
+  cur = 0;
+}
+
 void Plan::run_profiled(hipStream_t s, int kind, double& ms, int64_t& count, double& flops,
                         double& bytes) const {
   std::vector<size_t> idx;
@@ -103,10 +159,11 @@ void Plan::run_profiled(hipStream_t s, int kind, double& ms, int64_t& count, dou
   size_t j = 0;
   for (size_t i = 0; i < ops.size(); ++i) {
     bool tim = (j < idx.size() && idx[j] == i);
-    if (tim && !rt::dry()) QTT_HIP(hipEventRecord(ev[2 * j], s));
-    ops[i](s);
+    hipStream_t si = stream_of(lane[i], s);
+    if (tim && !rt::dry()) QTT_HIP(hipEventRecord(ev[2 * j], si));
+    ops[i](si);
     if (tim) {
-      if (!rt::dry()) QTT_HIP(hipEventRecord(ev[2 * j + 1], s));
+      if (!rt::dry()) QTT_HIP(hipEventRecord(ev[2 * j + 1], si));
       flops += info[i].flops;
       bytes += info[i].bytes;
       ++count;
@@ -237,9 +294,11 @@ static void plan_trunc_gram(Plan& plan, const std::vector<double*>& X, const std
 // simultaneous truncation.
 // ---------------------------------------------------------------------------
 void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const ChainView& Z,
-                       RoundTarget& tg, Prec prec) {
+                       RoundTarget& tg, Prec prec, int lanes) {
   const int N = Z.N;
   const int J = (int)terms.size();
+  // the terms' independent contraction chains are spread over L lanes
+  const int L = (plan.cur == 0) ? std::max(1, std::min(lanes, J)) : 1;
   QTT_REQUIRE(J >= 1, "rounding needs at least one term");
   const std::vector<int>& ell = Z.caps;
   for (int n = 0; n < N; ++n)
@@ -271,9 +330,12 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
       csz = std::max(csz, (size_t)ell[n] * 2 * r[n + 1] * D[n + 1]);
       ssz = std::max(ssz, (size_t)2 * ell[n] * ell[n + 1]);
     }
-  double* T1 = plan.alloc(t1);
-  double* T2 = plan.alloc(t2);
-  double* U1 = plan.alloc(u1);
+  std::vector<double*> T1s(L), T2s(L), U1s(L);
+  for (int l = 0; l < L; ++l) {
+    T1s[l] = plan.alloc(t1);
+    T2s[l] = plan.alloc(t2);
+    U1s[l] = plan.alloc(u1);
+  }
   double* S = plan.alloc(ssz);
   double* qrw = plan.alloc(ssz);
   double* one = plan.upload(std::vector<double>{1.0});
@@ -289,11 +351,15 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
   std::vector<double*> X(N);
   for (int n = 0; n < N; ++n) X[n] = plan.alloc((size_t)ell[n] * 2 * ell[n + 1]);
 
-  // ---- right partial sketches R_j[n] = Right_n(Y_j) Right_n(Z)^T
+  // ---- right partial sketches R_j[n] = Right_n(Y_j) Right_n(Z)^T, term j on lane j % L
+  plan.fork(L);
   for (int j = 0; j < J; ++j) {
     const auto& r = sh[j].r;
     const auto& D = sh[j].D;
     const ChainView* W = terms[j].mpo;
+    if (L > 1) plan.on(j % L);
+    double* T1 = T1s[j % L];
+    double* T2 = T2s[j % L];
     for (int n = N - 1; n >= 1; --n) {
       const int l = ell[n], lp = ell[n + 1], rn = r[n], rp = r[n + 1], Dn = D[n], Dp = D[n + 1];
       {  // T1[(b,beta),(t,z)] = sum_z' R[(b,beta),z'] Z_n[z,t,z']
@@ -375,16 +441,23 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
     }
   }
 
-  // ---- left-to-right sweep
+  plan.join(L);
+
+  // ---- left-to-right sweep; per bond the terms' contractions run on lanes
+  // (the last bond accumulates all terms into one core, in order, on lane 0)
   std::vector<double*> Mcur(J, one), Mnext = Mb;
   for (int n = 0; n < N; ++n) {
     const bool last = (n == N - 1);
     const int l = ell[n], lp = ell[n + 1];
+    const int Lb = last ? 1 : L;
+    plan.fork(Lb);
     for (int j = 0; j < J; ++j) {
       const auto& r = sh[j].r;
       const auto& D = sh[j].D;
       const int rn = r[n], rp = r[n + 1], Dn = D[n], Dp = D[n + 1];
       const ChainView* W = terms[j].mpo;
+      if (Lb > 1) plan.on(j % Lb);
+      double* U1 = U1s[j % L];
       double* Cdst = last ? X[N - 1] : Cb[j];
       const double alpha = last ? terms[j].coef : 1.0;
       const double beta = (last && j > 0) ? 1.0 : 0.0;
@@ -433,6 +506,7 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
                  2 * rp, alpha, beta, prec);
       }
     }
+    plan.join(Lb);
     if (last) break;
     // S = sum_j c_j C_j R_j[n+1]
     for (int j = 0; j < J; ++j) {
@@ -446,11 +520,14 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
       plan.add([=](hipStream_t s) { qr_launch(1, m, nc, S, 0, nc, 1, Xn, 0, nullptr, 0, qrw, s); },
                qr_info(m, nc));
     }
+    plan.fork(L);
     for (int j = 0; j < J; ++j) {
       const int rp = sh[j].r[n + 1], Dp = sh[j].D[n + 1];
+      if (L > 1) plan.on(j % L);
       add_gemm(plan, lp, rp * Dp, 2 * l, X[n], lp, true, Cb[j], (int64_t)rp * Dp, false, Mnext[j],
                (int64_t)rp * Dp, 1.0, 0.0, prec);
     }
+    plan.join(L);
     for (int j = 0; j < J; ++j) {
       double* old = Mcur[j];
       Mcur[j] = Mnext[j];

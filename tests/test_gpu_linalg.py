@@ -15,7 +15,8 @@ def ctx():
 
 
 @pytest.mark.parametrize("m,n", [(2, 1), (4, 4), (8, 5), (32, 16), (64, 64), (128, 64), (96, 90),
-                                 (288, 144), (320, 160), (512, 256)])
+                                 (192, 96), (200, 100), (256, 128), (257, 129), (288, 144), (290, 140),
+                                 (320, 160), (512, 256)])
 def test_qr(ctx, m, n):
     rng = np.random.default_rng(m * 1000 + n)
     A = rng.standard_normal((3, m, n))
