@@ -1094,7 +1094,7 @@ tt_status tt_batch_create(tt_ctx* ctx, int count, tt_problem* const* probs, tt_t
         QTT_HIP(hipEventRecord(b->events[0], s0));
         for (int i = 0; i < count; ++i) {
           QTT_HIP(hipStreamWaitEvent(b->streams[i], b->events[0], 0));
-          b->probs[i]->plan->run(b->streams[i]);
+          b->probs[i]->plan->run_serial(b->streams[i]);
           QTT_HIP(hipEventRecord(b->events[i + 1], b->streams[i]));
           QTT_HIP(hipStreamWaitEvent(s0, b->events[i + 1], 0));
         }
@@ -1117,7 +1117,7 @@ tt_status tt_step_batched(tt_batch* b, int n_steps) {
     StreamScope sc(b->ctx);
     if (rt::dry()) {
       for (int i = 0; i < n_steps; ++i)
-        for (auto* P : b->probs) P->plan->run(b->ctx->stream);
+        for (auto* P : b->probs) P->plan->run_serial(b->ctx->stream);
       return;
     }
     for (int i = 0; i < n_steps; ++i) QTT_HIP(hipGraphLaunch(b->exec, b->ctx->stream));

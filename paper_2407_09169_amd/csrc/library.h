@@ -99,9 +99,20 @@ struct Plan {
   void fork(int n);
   void on(int l) { cur = l; }
   void join(int n);
-  hipStream_t stream_of(int l, hipStream_t s0) const { return l == 0 ? s0 : streams[l - 1]; }
+  hipStream_t stream_of(int l, hipStream_t s0) const {
+    if (l == 0) return s0;
+    QTT_REQUIRE(l >= 1 && l - 1 < (int)streams.size(), "plan lane %d has no stream", l);
+    return streams[l - 1];
+  }
   void run(hipStream_t s) const {
     for (size_t i = 0; i < ops.size(); ++i) ops[i](stream_of(lane[i], s));
+  }
+  // every op on s (the fork / join ops then order s with itself): used where
+  // the plan is captured from a stream that itself joined a capture, since
+  // streams joining through such a stream (two levels) are not supported by
+  // the runtime's capture
+  void run_serial(hipStream_t s) const {
+    for (size_t i = 0; i < ops.size(); ++i) ops[i](s);
   }
   // eager run with a pair of events around every op of class `kind` (OP_ALL:
   // every op); adds the event time (ms), the number of such ops and their
