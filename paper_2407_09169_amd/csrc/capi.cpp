@@ -169,6 +169,9 @@ struct tt_problem {
   DevBuf Edf[2], Edk[2], mfdf[2], mfdk[2];
   std::unique_ptr<Plan> tplan;
   std::vector<const void*> tplan_key;
+  // the step recorded without lanes, for batched replays
+  std::unique_ptr<Plan> bplan;
+  const tt_tt* bplan_f = nullptr;
   hipGraph_t tgraph = nullptr;
   hipGraphExec_t texec = nullptr;
   ~tt_problem() {
@@ -248,7 +251,7 @@ static void plan_mean_round(Plan& plan, tt_problem* P, const std::vector<MeanTer
   ChainView Zm = view(P->Zm.get());
   plan.fork(2);  // the two mean fields on two lanes
   for (int a = 0; a < 2; ++a) {
-    plan.on(a);
+    if (!plan.no_lanes) plan.on(a);
     std::vector<SketchTerm> st;
     for (const MeanTerm& m : terms) {
       SketchTerm t;
@@ -357,8 +360,10 @@ struct Tangent {
 //   B_q = dA_fix/dq - sum_a D1g^(phi_a) diag(alpha_q <Phi_a>(g_i) + Omega <Phi_a>(dg_i)),
 // alpha_Omega = 1, alpha_k = 0 (the mean field enters A through -Omega m_a(g)),
 // and df+ = Round(df + sum_i b_i dk_i) beside f+ = Round(f + sum_i b_i k_i).
-static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vector<Tangent>& tan) {
+static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vector<Tangent>& tan,
+                                         bool lanes = true) {
   auto plan = std::make_unique<Plan>();
+  plan->no_lanes = !lanes;
   const tt_params& p = P->p;
   const Prec prec = prec_of(p.dtype);
   ChainView Z = view(P->Z.get());
@@ -1079,7 +1084,12 @@ tt_status tt_batch_create(tt_ctx* ctx, int count, tt_problem* const* probs, tt_t
       QTT_REQUIRE(f->caps == P->fcaps, "instance %d: state caps differ from the problem's", i);
       for (int j = 0; j < i; ++j)
         QTT_REQUIRE(probs[j] != P && states[j] != f, "instance %d repeats a problem or a state", i);
-      if (!P->plan || P->plan_f != f) build_step_plan(P, f);
+      if (!P->bplan || P->bplan_f != f) {
+        P->bplan = record_step(P, f, {}, false);
+        P->bplan_f = f;
+      }
+      QTT_REQUIRE(P->bplan->events.empty() && P->bplan->streams.empty(),
+                  "instance %d: batched plan must not carry lanes", i);
       b->probs.push_back(P);
       b->states.push_back(f);
     }
@@ -1094,7 +1104,7 @@ tt_status tt_batch_create(tt_ctx* ctx, int count, tt_problem* const* probs, tt_t
         QTT_HIP(hipEventRecord(b->events[0], s0));
         for (int i = 0; i < count; ++i) {
           QTT_HIP(hipStreamWaitEvent(b->streams[i], b->events[0], 0));
-          b->probs[i]->plan->run_serial(b->streams[i]);
+          b->probs[i]->bplan->run(b->streams[i]);
           QTT_HIP(hipEventRecord(b->events[i + 1], b->streams[i]));
           QTT_HIP(hipStreamWaitEvent(s0, b->events[i + 1], 0));
         }
@@ -1117,7 +1127,7 @@ tt_status tt_step_batched(tt_batch* b, int n_steps) {
     StreamScope sc(b->ctx);
     if (rt::dry()) {
       for (int i = 0; i < n_steps; ++i)
-        for (auto* P : b->probs) P->plan->run_serial(b->ctx->stream);
+        for (auto* P : b->probs) P->bplan->run(b->ctx->stream);
       return;
     }
     for (int i = 0; i < n_steps; ++i) QTT_HIP(hipGraphLaunch(b->exec, b->ctx->stream));

@@ -77,6 +77,7 @@ struct Plan {
   std::vector<hipStream_t> streams;  // lanes 1..
   std::vector<hipEvent_t> events;
   int cur = 0;
+  bool no_lanes = false;  // record every op on lane 0 (fork / join record nothing)
   Plan() = default;
   Plan(const Plan&) = delete;
   Plan& operator=(const Plan&) = delete;
@@ -107,13 +108,7 @@ struct Plan {
   void run(hipStream_t s) const {
     for (size_t i = 0; i < ops.size(); ++i) ops[i](stream_of(lane[i], s));
   }
-  // every op on s (the fork / join ops then order s with itself): used where
-  // the plan is captured from a stream that itself joined a capture, since
-  // streams joining through such a stream (two levels) are not supported by
-  // the runtime's capture
-  void run_serial(hipStream_t s) const {
-    for (size_t i = 0; i < ops.size(); ++i) ops[i](s);
-  }
+
   // eager run with a pair of events around every op of class `kind` (OP_ALL:
   // every op); adds the event time (ms), the number of such ops and their
   // flops / bytes.  With QTTPDF_PROFILE_LOG=<file> set, one line per timed op

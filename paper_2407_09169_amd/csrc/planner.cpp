@@ -107,6 +107,7 @@ hipEvent_t Plan::new_event() {
 }
 
 void Plan::ensure_lanes(int n) {
+  QTT_REQUIRE(!no_lanes || n <= 1, "plan recorded without lanes");
   while ((int)streams.size() < n - 1) {
     hipStream_t st = nullptr;
     if (!rt::dry()) QTT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -115,7 +116,7 @@ void Plan::ensure_lanes(int n) {
 }
 
 void Plan::fork(int n) {
-  if (n <= 1) return;  // single lane: nothing to order
+  if (n <= 1 || no_lanes) return;  // single lane: nothing to order
   QTT_REQUIRE(cur == 0, "fork from lane 0 only");
   ensure_lanes(n);
   hipEvent_t e = new_event();
@@ -132,7 +133,7 @@ void Plan::fork(int n) {
 }
 
 void Plan::join(int n) {
-  if (n <= 1) return;
+  if (n <= 1 || no_lanes) return;
   QTT_REQUIRE(cur < n, "join of lanes that were not forked");
   for (int l = 1; l < n; ++l) {
     hipEvent_t e = new_event();
@@ -298,7 +299,7 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
   const int N = Z.N;
   const int J = (int)terms.size();
   // the terms' independent contraction chains are spread over L lanes
-  const int L = (plan.cur == 0) ? std::max(1, std::min(lanes, J)) : 1;
+  const int L = (plan.cur == 0 && !plan.no_lanes) ? std::max(1, std::min(lanes, J)) : 1;
   QTT_REQUIRE(J >= 1, "rounding needs at least one term");
   const std::vector<int>& ell = Z.caps;
   for (int n = 0; n < N; ++n)
