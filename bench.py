@@ -96,6 +96,8 @@ def _roofline(rows):
     launch / its average launch duration."""
     groups = {}
     for _, k, ms, fl, by, what in rows:
+        if k < 0:  # copies, fills and lane events are not kernels of the method
+            continue
         g = groups.setdefault(what, [0, 0.0, 0.0, 0.0])
         g[0] += 1
         g[1] += ms

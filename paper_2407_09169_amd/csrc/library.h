@@ -55,7 +55,7 @@ ChainView view(const tt_tt* t);
 ChainView view_sites(const tt_tt* t, int first, int count);  // sub-chain (bond caps as stored)
 
 // kernel classes of a plan (for per-class timing)
-enum OpKind { OP_OTHER = -1, OP_CONTRACT = 0, OP_QR = 1, OP_EIG = 2, OP_STREAM = 3, OP_ALL = 4 };
+enum OpKind { OP_SYNC = -2, OP_OTHER = -1, OP_CONTRACT = 0, OP_QR = 1, OP_EIG = 2, OP_STREAM = 3, OP_ALL = 4 };
 struct OpInfo {
   int kind = OP_OTHER;
   double flops = 0.0;  // algorithmic flops of the launch

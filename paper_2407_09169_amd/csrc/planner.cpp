@@ -119,15 +119,18 @@ void Plan::fork(int n) {
   if (n <= 1 || no_lanes) return;  // single lane: nothing to order
   QTT_REQUIRE(cur == 0, "fork from lane 0 only");
   ensure_lanes(n);
+  OpInfo sync;
+  sync.kind = OP_SYNC;
+  sync.what = "lane fork";
   hipEvent_t e = new_event();
   add([e](hipStream_t s) {
     if (!rt::dry()) QTT_HIP(hipEventRecord(e, s));
-  });
+  }, sync);
   for (int l = 1; l < n; ++l) {
     cur = l;
     add([e](hipStream_t s) {
       if (!rt::dry()) QTT_HIP(hipStreamWaitEvent(s, e, 0));
-    });
+    }, sync);
   }
   cur = 0;
 }
@@ -135,16 +138,19 @@ void Plan::fork(int n) {
 void Plan::join(int n) {
   if (n <= 1 || no_lanes) return;
   QTT_REQUIRE(cur < n, "join of lanes that were not forked");
+  OpInfo sync;
+  sync.kind = OP_SYNC;
+  sync.what = "lane join";
   for (int l = 1; l < n; ++l) {
     hipEvent_t e = new_event();
     cur = l;
     add([e](hipStream_t s) {
       if (!rt::dry()) QTT_HIP(hipEventRecord(e, s));
-    });
+    }, sync);
     cur = 0;
     add([e](hipStream_t s) {
       if (!rt::dry()) QTT_HIP(hipStreamWaitEvent(s, e, 0));
-    });
+    }, sync);
   }
   cur = 0;
 }
@@ -153,7 +159,7 @@ void Plan::run_profiled(hipStream_t s, int kind, double& ms, int64_t& count, dou
                         double& bytes) const {
   std::vector<size_t> idx;
   for (size_t i = 0; i < ops.size(); ++i)
-    if (kind == OP_ALL || info[i].kind == kind) idx.push_back(i);
+    if ((kind == OP_ALL && info[i].kind != OP_SYNC) || info[i].kind == kind) idx.push_back(i);
   std::vector<hipEvent_t> ev(2 * idx.size(), nullptr);
   if (!rt::dry())
     for (auto& e : ev) QTT_HIP(hipEventCreate(&e));
