@@ -17,7 +17,9 @@ Schedule of one RK4 step (RK2 is the Heun analogue):
 where the stage inputs f + c k are exact (block-diagonal) sums, m~_a(g) is
 the raw mean composition of g rounded to chi_mean, and Round is the
 randomized range finder followed by simultaneous SVD truncation
-(``oracle.tt.round_sketch``) with the Gaussian sketch given as input.
+(``oracle.tt.round_sketch_two_sided``: the chain is orthogonalised from both
+ends towards its middle site, then truncated simultaneously) with the
+Gaussian sketches given as input.
 
 The operator MPOs are TT-SVDs of the dense 1-D matrices of ``oracle.dense``,
 tensored over dimensions; nothing here is shared with the product path.
@@ -57,8 +59,10 @@ class MPSStepper:
             "phi": tt.operator_qtt(np.diag(phi)),
         }
         self.Z = workloads.sketch_cores(w)
+        self.Zl = workloads.left_sketch_cores(w)
         self.ell = workloads.sketch_ranks(w)
         self.Zm = workloads.mean_sketch_cores(w)
+        self.Zml = workloads.left_mean_sketch_cores(w)
         self.ell_m = workloads.mean_sketch_ranks(w)
         self.U = self._velocity() if w.ndims == 5 else None
         self.fixed = self._fixed_terms()
@@ -152,8 +156,8 @@ class MPSStepper:
         m = self.mean_field_raw(g, a)
         if self.nd == 2:
             return m, None
-        m, info = tt.round_sketch([(1.0, None, m)], self.Zm, self.ell_m,
-                                  self.w.chi_mean, self.w.rel_tol)
+        m, info = tt.round_sketch_two_sided([(1.0, None, m)], self.Zm, self.Zml,
+                                            self.w.chi_mean, self.w.rel_tol)
         return m, info
 
     def operator_terms(self, g):
@@ -177,7 +181,7 @@ class MPSStepper:
 
     def L(self, g):
         terms = [(c, W, g) for c, W in self.operator_terms(g)]
-        out, info = tt.round_sketch(terms, self.Z, self.ell, self.w.chi, self.w.rel_tol)
+        out, info = tt.round_sketch_two_sided(terms, self.Z, self.Zl, self.w.chi, self.w.rel_tol)
         return out, info
 
     # -------------------------------------------------------------------- step
@@ -204,7 +208,7 @@ class MPSStepper:
             comb = [(1.0, None, f), (0.5 * dt, None, k1), (0.5 * dt, None, k2)]
         else:
             raise ValueError(w.integrator)
-        fn, info = tt.round_sketch(comb, self.Z, self.ell, w.chi, w.rel_tol)
+        fn, info = tt.round_sketch_two_sided(comb, self.Z, self.Zl, w.chi, w.rel_tol)
         infos.append(info)
         return fn, infos
 

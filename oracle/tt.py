@@ -419,6 +419,136 @@ def round_sketch(terms, Z, ell, chi, rel_tol=0.0):
     return trunc_gram(rand_orth(terms, Z, ell), chi, rel_tol)
 
 
+def rand_orth_two_sided(terms, Zr, Zl, c=None):
+    """Two-sided randomized range finding for Y = sum_j c_j W_j x_j.
+
+    The chain is orthogonalised from both ends towards a centre site c
+    (default N // 2): bonds 1..c get left-orthogonal cores X_0..X_(c-1) from
+    the right sketches Right_n(Y) Right_n(Zr)^T (the one-sided sweep of
+    rand_orth stopped at c); bonds c+1..N-1 get right-orthogonal cores
+    V_(c+1)..V_(N-1) from the left sketches Left_n(Zl)^T Left_n(Y), sweeping
+    from the right end.  The centre core is X_(<c)^T Y V_(>c)^T.  Returns
+    (cores, c): a mixed canonical TT with ranks ell (those of the sketches).
+    """
+    terms = [_as_term(t) for t in terms]
+    N = len(Zr)
+    if c is None:
+        c = N // 2
+    # right partial sketches R[j][n] (r_n, D_n, ell_n), bond left of site n
+    R = []
+    for (_, W, x) in terms:
+        Rj = [None] * (N + 1)
+        Rj[N] = np.ones((1, 1, 1))
+        for n in range(N - 1, 0, -1):
+            T1 = _ein("bBy,zty->bBtz", Rj[n + 1], Zr[n])
+            T2 = _ein("AtsB,bBtz->bAsz", W[n], T1)
+            Rj[n] = _ein("asb,bAsz->aAz", x[n], T2)
+        R.append(Rj)
+    # left partial sketches L[j][n] (ell_n, r_n, D_n), bond left of site n
+    Lk = []
+    for (_, W, x) in terms:
+        Lj = [None] * (N + 1)
+        Lj[0] = np.ones((1, 1, 1))
+        for n in range(N - 1):
+            T1 = _ein("yaA,ytz->aAtz", Lj[n], Zl[n])
+            T2 = _ein("AtsB,aAtz->aBsz", W[n], T1)
+            Lj[n + 1] = _ein("asb,aBsz->zbB", x[n], T2)
+        Lk.append(Lj)
+    # left sweep over sites 0..c-1
+    X = []
+    Mj = [np.ones((1, 1, 1)) for _ in terms]  # (ell_n, r_n, D_n)
+    for n in range(c):
+        Cs = []
+        S = 0.0
+        for j, (cj, W, x) in enumerate(terms):
+            C = _ein("kAsb,AtsB->ktbB", _ein("kaA,asb->kAsb", Mj[j], x[n]), W[n])
+            Cs.append(C)
+            S = S + cj * _ein("ktbB,bBz->ktz", C, R[j][n + 1])
+        lp = S.shape[0]
+        Q, _ = np.linalg.qr(S.reshape(lp * 2, -1))
+        Q3 = Q.reshape(lp, 2, Q.shape[1])
+        X.append(Q3)
+        Mj = [_ein("ktz,ktbB->zbB", Q3, C) for C in Cs]
+    # right sweep over sites N-1..c+1
+    V = [None] * N
+    Mr = [np.ones((1, 1, 1)) for _ in terms]  # (r_n, D_n, ell_n) right of bond n
+    for n in range(N - 1, c, -1):
+        Cs = []
+        S = 0.0
+        for j, (cj, W, x) in enumerate(terms):
+            C = _ein("AtsB,asBz->aAtz", W[n], _ein("asb,bBz->asBz", x[n], Mr[j]))
+            Cs.append(C)
+            S = S + cj * _ein("yaA,aAtz->ytz", Lk[j][n], C)
+        ln = S.shape[0]
+        rr = S.shape[2]
+        Q, _ = np.linalg.qr(S.reshape(ln, 2 * rr).T)  # S = (Q R)^T: rows of Q^T orthonormal
+        V3 = Q.T.reshape(Q.shape[1], 2, rr)
+        V[n] = V3
+        Mr = [_ein("aAtz,ytz->aAy", C, V3) for C in Cs]
+    # centre core
+    G = 0.0
+    for j, (cj, W, x) in enumerate(terms):
+        C = _ein("kAsb,AtsB->ktbB", _ein("kaA,asb->kAsb", Mj[j], x[c]), W[c])
+        G = G + cj * _ein("ktbB,bBz->ktz", C, Mr[j])
+    return X + [G] + V[c + 1:], c
+
+
+def trunc_gram_mixed(cores, c, chi, rel_tol=0.0):
+    """Simultaneous SVD truncation of a mixed canonical TT (cores 0..c-1 left
+    orthogonal, c+1..N-1 right orthogonal).  At a bond n <= c the left part is
+    orthonormal, so the kept subspace is that of the right Gram matrix
+    Gamma_n = Right_n Right_n^T (Gamma_c from the centre core, then the chain
+    through X_(c-1)..X_n); at a bond n > c the right part is orthonormal and
+    the left Gram matrix Lambda_n = Left_n^T Left_n decides (Lambda_(c+1) from
+    the centre core, then the chain through V_(c+1)..).  With P_n the leading
+    min(cap_n, ell_n) eigenvectors, the cores become P_n^T A_n P_(n+1).
+    Returns (cores, info) as trunc_gram."""
+    N = len(cores)
+    caps = chain_caps(N, chi)
+    if N == 1:
+        return [cores[0].copy()], {"ranks": [1, 1], "discarded": [0.0, 0.0],
+                                   "norm2": float(np.sum(cores[0] ** 2)), "lams": [None, None]}
+    G = [None] * (N + 1)
+    if c >= 1:
+        G[c] = _ein("ktz,Ktz->kK", cores[c], cores[c])
+        for n in range(c - 1, 0, -1):
+            G[n] = _ein("asb,bc,dsc->ad", cores[n], G[n + 1], cores[n])
+    if c + 1 <= N - 1:
+        G[c + 1] = _ein("ktz,ktZ->zZ", cores[c], cores[c])
+        for n in range(c + 1, N - 1):
+            G[n + 1] = _ein("ysz,yY,YsZ->zZ", cores[n], G[n], cores[n])
+    P = [None] * (N + 1)
+    ranks_out = [1] * (N + 1)
+    disc = [0.0] * (N + 1)
+    lams = [None] * (N + 1)
+    for n in range(1, N):
+        lam, U = np.linalg.eigh(G[n])
+        lam, U = lam[::-1], U[:, ::-1]
+        lams[n] = lam
+        k = lam.size
+        if rel_tol > 0 and lam[0] > 0:
+            k = int(np.sum(lam > rel_tol * rel_tol * lam[0]))
+        k = max(1, min(k, caps[n]))
+        P[n] = U[:, :k]
+        ranks_out[n] = k
+        disc[n] = float(np.sum(np.clip(lam[k:], 0.0, None)))
+    out = []
+    for n in range(N):
+        A = cores[n]
+        if n > 0:
+            A = np.tensordot(P[n].T, A, axes=(1, 0))
+        if n < N - 1:
+            A = np.tensordot(A, P[n + 1], axes=(2, 0))
+        out.append(A)
+    norm2 = float(np.trace(G[1]))
+    return out, {"ranks": ranks_out, "discarded": disc, "norm2": norm2, "lams": lams}
+
+
+def round_sketch_two_sided(terms, Zr, Zl, chi, rel_tol=0.0, c=None):
+    cores, c = rand_orth_two_sided(terms, Zr, Zl, c)
+    return trunc_gram_mixed(cores, c, chi, rel_tol)
+
+
 # ----------------------------------------------------------------------------
 # eq. MPSdofs
 # ----------------------------------------------------------------------------

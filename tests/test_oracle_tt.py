@@ -130,6 +130,52 @@ def test_round_sketch_quasi_optimal():
     assert max(tt.ranks(out)) <= chi
 
 
+@pytest.mark.parametrize("c", [0, 1, 4, 7])
+def test_round_sketch_two_sided_exact_when_ell_covers_rank(c):
+    """Two-sided range finding with the centre at any site: exact when both
+    sketches have the chain's maximal ranks; the range-finder output is
+    left-orthogonal left of the centre and right-orthogonal right of it."""
+    N = 8
+    x = _random_tt([1, 2, 4, 8, 8, 8, 4, 2, 1], 6)
+    W = tt.mpo_product([tt.operator_qtt(dense.d1_ghost(16)), tt.operator_qtt(dense.d2_ghost(16))],
+                       [(0, b) for b in range(4)] + [(1, b) for b in range(4)], 2)
+    Zr, _ = _gaussian_sketch(N, 16, 7)
+    Zl, _ = _gaussian_sketch(N, 16, 8)
+    terms = [(0.7, W, x), (-1.5, None, x)]
+    ref = 0.7 * tt.tt_full(tt.mpo_apply(W, x)) - 1.5 * tt.tt_full(x)
+    mid, cc = tt.rand_orth_two_sided(terms, Zr, Zl, c)
+    assert cc == c
+    for n in range(c):
+        A = mid[n].reshape(-1, mid[n].shape[2])
+        assert np.allclose(A.T @ A, np.eye(A.shape[1]), atol=1e-12)
+    for n in range(c + 1, N):
+        A = mid[n].reshape(mid[n].shape[0], -1)
+        assert np.allclose(A @ A.T, np.eye(A.shape[0]), atol=1e-12)
+    assert np.allclose(tt.tt_full(mid), ref, atol=1e-11 * np.abs(ref).max())
+    out, _ = tt.round_sketch_two_sided(terms, Zr, Zl, 16, c=c)
+    assert np.allclose(tt.tt_full(out), ref, atol=1e-11 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("c", [1, 5, 9])
+def test_round_sketch_two_sided_truncation_bound(c):
+    """With the ranges captured exactly, the simultaneous truncation of the
+    mixed canonical form errs by at most the discarded Gram eigenvalues,
+    summed over the bonds (a wrong choice of Gram matrix on either side of
+    the centre breaks this), and it is within a small factor of TT-SVD."""
+    x = _random_tt([1, 2, 4, 8, 16, 32, 16, 8, 4, 2, 1], 8, decay=0.7)
+    N = 10
+    Zr, _ = _gaussian_sketch(N, 32, 21)
+    Zl, _ = _gaussian_sketch(N, 32, 22)
+    T = tt.tt_full(x)
+    for chi in (3, 6, 12):
+        out, info = tt.round_sketch_two_sided([(1.0, None, x)], Zr, Zl, chi, c=c)
+        e2 = np.linalg.norm(tt.tt_full(out) - T) ** 2
+        assert e2 <= sum(info["discarded"]) * (1 + 1e-9) + 1e-24
+        ref, _ = tt.round_ttsvd(x, chi)
+        assert np.sqrt(e2) <= 3.0 * np.linalg.norm(tt.tt_full(ref) - T) + 1e-14
+        assert max(tt.ranks(out)) <= chi
+
+
 def test_nvpp_paper_claims():
     """eq. MPSdofs against the reductions the paper states for the 128^5 grid
     (N = 35): O(10^6) fewer parameters at chi = 32 (Abstract, Discussion),

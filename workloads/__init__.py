@@ -10,5 +10,5 @@ own tensor-train representation from these numbers.
 from .configs import WORKLOADS, Workload, batch_workloads, get_workload, stable_dt  # noqa: F401
 from .generate import (  # noqa: F401
     phi_points, x_points, ic_terms, velocity_terms, sketch_ranks, sketch_cores,
-    mean_sketch_ranks, mean_sketch_cores, site_order,
+    mean_sketch_ranks, mean_sketch_cores, left_sketch_cores, left_mean_sketch_cores, site_order,
 )

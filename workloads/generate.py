@@ -16,9 +16,11 @@ algebra, no time stepping).  The functions return plain float64 arrays:
   a3 S1 S2 C3 with a1 + a2 + a3 = 0, hence divergence free) minus the
   Gaussian jet of eq. velField along x1.  ``ic="paper"`` gives a = (1, 1, -2)
   and zero phases, i.e. eq. velField itself.
-* ``sketch_cores`` / ``mean_sketch_cores``: i.i.d. Gaussian tensor-train
-  cores used as the random sketch of the randomized rounding.  They are
-  inputs: both sides of a comparison receive the same numbers.
+* ``sketch_cores`` / ``mean_sketch_cores`` (read from the right end) and
+  ``left_sketch_cores`` / ``left_mean_sketch_cores`` (read from the left end):
+  i.i.d. Gaussian tensor-train cores used as the random sketches of the
+  randomized rounding.  They are inputs: both sides of a comparison receive
+  the same numbers.
 """
 from __future__ import annotations
 
@@ -157,3 +159,16 @@ def mean_sketch_cores(w: Workload) -> list[np.ndarray]:
     if w.n_x_sites == 0:
         return []
     return _gaussian_tt(mean_sketch_ranks(w), [w.seed, 4])
+
+
+def left_sketch_cores(w: Workload) -> list[np.ndarray]:
+    """Second, independent Gaussian sketch (same ranks as sketch_cores), read
+    from the left end by the two-sided rounding."""
+    return _gaussian_tt(sketch_ranks(w), [w.seed, 5])
+
+
+def left_mean_sketch_cores(w: Workload) -> list[np.ndarray]:
+    """Second Gaussian sketch for the mean-composition fields."""
+    if w.n_x_sites == 0:
+        return []
+    return _gaussian_tt(mean_sketch_ranks(w), [w.seed, 6])
