@@ -218,12 +218,16 @@ typedef struct {
 
 /* Creates a problem: builds the fixed stage operator (mpo_build of the
  * drift, dissipation, reaction, convection and diffusion terms of eq. FP2)
- * and all workspaces.  velocity: three x-MPSs (ndims == 5) or NULL;
- * sketch: Gaussian TT with ranks min(ell, 2^n, 2^(N-n)); sketch_mean: the
- * same over the x sites with ell_mean (ndims == 5) or NULL.  The inputs are
+ * and all workspaces.  velocity: three x-MPSs (ndims == 5) or NULL.
+ * Every rounding of the step is two-sided (the chain is orthogonalised from
+ * both ends towards its middle site): sketch and sketch_left are two
+ * independent Gaussian TTs with ranks min(ell, 2^n, 2^(N-n)), read from the
+ * right and from the left end; sketch_mean / sketch_mean_left are the same
+ * over the x sites with ell_mean (ndims == 5) or NULL.  The inputs are
  * copied; the caller keeps ownership. */
 tt_status tt_problem_create(tt_ctx* ctx, const tt_params* p, const tt_tt* const* velocity,
-                            const tt_tt* sketch, const tt_tt* sketch_mean, tt_problem** out);
+                            const tt_tt* sketch, const tt_tt* sketch_left, const tt_tt* sketch_mean,
+                            const tt_tt* sketch_mean_left, tt_problem** out);
 tt_status tt_problem_destroy(tt_problem* prob);
 /* Bond dimensions of the fixed stage MPO (n_sites + 1 entries, nullable). */
 tt_status tt_problem_info(const tt_problem* prob, int* n_sites, int32_t* mpo_bonds, int* max_mpo_bond);

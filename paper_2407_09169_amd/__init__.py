@@ -93,7 +93,7 @@ def lib():
         "mps_round_sketch": [vp, i32, P(dbl), P(vp), P(vp), vp, i32, i32, P(vp)],
         "tt_l2_diff": [vp, vp, vp, P(dbl)],
         "tt_inner": [vp, vp, vp, P(dbl)],
-        "tt_problem_create": [vp, P(TTParams), P(vp), vp, vp, P(vp)],
+        "tt_problem_create": [vp, P(TTParams), P(vp), vp, vp, vp, vp, P(vp)],
         "tt_problem_destroy": [vp],
         "tt_problem_info": [vp, P(i32), P(C.c_int32), P(i32)],
         "tt_problem_state": [vp, P(vp)],
@@ -339,14 +339,16 @@ def linalg_eigh(ctx, G, keep):
 class Problem:
     """One eq. FP2 problem: fixed operator, sketches and the recorded step."""
 
-    def __init__(self, ctx, params: TTParams, velocity=None, sketch=None, sketch_mean=None):
+    def __init__(self, ctx, params: TTParams, velocity=None, sketch=None, sketch_left=None,
+                 sketch_mean=None, sketch_mean_left=None):
         self.ctx = ctx
         self.params = params
-        self._keep = (velocity, sketch, sketch_mean)
+        self._keep = (velocity, sketch, sketch_left, sketch_mean, sketch_mean_left)
         h = C.c_void_p()
         vel = _handles(velocity) if velocity else None
-        _check(lib().tt_problem_create(ctx.h, C.byref(params), vel, sketch.h,
-                                       sketch_mean.h if sketch_mean is not None else None, C.byref(h)))
+        opt = lambda t: t.h if t is not None else None  # noqa: E731
+        _check(lib().tt_problem_create(ctx.h, C.byref(params), vel, sketch.h, sketch_left.h,
+                                       opt(sketch_mean), opt(sketch_mean_left), C.byref(h)))
         self.h = h
 
     def info(self):
@@ -471,12 +473,14 @@ def setup_workload(ctx, w, dtype="f64"):
         velocity = [from_separable(ctx, 3, w.bits, TT_SERIAL, comp, w.vel_rank)
                     for comp in workloads.velocity_terms(w)]
     sketch = TT.from_cores(ctx, workloads.sketch_cores(w))
+    sketch_left = TT.from_cores(ctx, workloads.left_sketch_cores(w))
     sketch_mean = TT.from_cores(ctx, workloads.mean_sketch_cores(w)) if w.ndims == 5 else None
+    sketch_mean_left = TT.from_cores(ctx, workloads.left_mean_sketch_cores(w)) if w.ndims == 5 else None
     p = TTParams(ndims=w.ndims, bits=w.bits, ordering=ordering, chi=w.chi, ell=w.ell,
                  chi_mean=w.chi_mean, ell_mean=w.ell_mean,
                  integrator=TT_RK4 if w.integrator == "rk4" else TT_RK2_HEUN,
                  dtype=DTYPES[dtype], omega=w.omega, k_react=w.k_react, nu_phi=w.nu_phi,
                  gamma=w.gamma, dt=w.dt)
-    prob = Problem(ctx, p, velocity, sketch, sketch_mean)
+    prob = Problem(ctx, p, velocity, sketch, sketch_left, sketch_mean, sketch_mean_left)
     f0 = from_separable(ctx, w.ndims, w.bits, ordering, workloads.ic_terms(w), w.chi)
     return prob, f0

@@ -19,8 +19,8 @@ OUT = os.path.join(HERE, "libqttpdf.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("QTTPDF_ARCH", "gfx950")
 
-SOURCES = ["tc_gemm.hip", "factor.hip", "elementwise.hip", "planner.cpp", "capi.cpp", "host_tt.cpp",
-           "runtime.cpp"]
+SOURCES = ["tc_gemm.hip", "factor.hip", "elementwise.hip", "planner.cpp", "planner_two_sided.cpp",
+           "capi.cpp", "host_tt.cpp", "runtime.cpp"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -135,7 +135,8 @@ struct tt_problem {
   tt_params p{};
   int N = 0, nphi = 0, nx = 0;
   std::vector<int> fcaps, mcaps;
-  std::unique_ptr<tt_tt> Z, Zm;
+  std::unique_ptr<tt_tt> Z, Zm;    // sketches read from the right end
+  std::unique_ptr<tt_tt> Zl, Zml;  // sketches read from the left end (two-sided rounding)
   std::unique_ptr<tt_tt> A;   // combined stage operator: fixed (+) mean-field part
   std::vector<int> Dfix;      // bonds of the fixed operator
   std::unique_ptr<tt_tt> Wm;  // mean-field weights over the phi sites (2 output channels)
@@ -249,6 +250,7 @@ struct MeanTerm {
 static void plan_mean_round(Plan& plan, tt_problem* P, const std::vector<MeanTerm>& terms,
                             tt_tt* const mt[2]) {
   ChainView Zm = view(P->Zm.get());
+  ChainView Zml = view(P->Zml.get());
   plan.fork(2);  // the two mean fields on two lanes
   for (int a = 0; a < 2; ++a) {
     if (!plan.no_lanes) plan.on(a);
@@ -262,7 +264,7 @@ static void plan_mean_round(Plan& plan, tt_problem* P, const std::vector<MeanTer
     RoundTarget tg;
     for (int j = 0; j < P->nx; ++j) tg.core.push_back(mt[a]->core(j));
     tg.caps = mt[a]->caps;
-    plan_round_sketch(plan, st, Zm, tg, Prec::F64, 1);
+    plan_round_sketch_two_sided(plan, st, Zm, Zml, tg, Prec::F64, 1);
   }
   plan.join(2);
 }
@@ -367,6 +369,7 @@ static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vec
   const tt_params& p = P->p;
   const Prec prec = prec_of(p.dtype);
   ChainView Z = view(P->Z.get());
+  ChainView Zl = view(P->Zl.get());
   ChainView Av = view(P->A.get());
   const bool rk4 = (p.integrator == TT_RK4);
   const int S = rk4 ? 4 : 2;
@@ -398,7 +401,7 @@ static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vec
       std::vector<SketchTerm> terms{sterm(1.0, &Av, f)};
       if (kp) terms.push_back(sterm(cg, &Av, kp));
       RoundTarget tg = target(P->k[i].get());
-      plan_round_sketch(*plan, terms, Z, tg, prec);
+      plan_round_sketch_two_sided(*plan, terms, Z, Zl, tg, prec);
     }
     for (size_t j = 0; j < tan.size(); ++j) {
       const int q = tan[j].q;
@@ -421,7 +424,7 @@ static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vec
         terms.push_back(sterm(cg, &Bv[j], kp));
       }
       RoundTarget tg = target(P->dk[q][i].get());
-      plan_round_sketch(*plan, terms, Z, tg, prec);
+      plan_round_sketch_two_sided(*plan, terms, Z, Zl, tg, prec);
     }
   }
   const double b4[4] = {dt / 6, dt / 3, dt / 3, dt / 6}, b2[2] = {0.5 * dt, 0.5 * dt};
@@ -430,7 +433,7 @@ static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vec
     std::vector<SketchTerm> comb{sterm(1.0, nullptr, x)};
     for (int i = 0; i < S; ++i) comb.push_back(sterm(b[i], nullptr, ks[i].get()));
     RoundTarget tg = target(x);
-    plan_round_sketch(*plan, comb, Z, tg, prec);
+    plan_round_sketch_two_sided(*plan, comb, Z, Zl, tg, prec);
     return tg;
   };
   P->last = combine(f, P->k);
@@ -798,7 +801,8 @@ tt_status tt_inner(tt_ctx* ctx, const tt_tt* a, const tt_tt* b, double* out) {
 // problem
 // ---------------------------------------------------------------------------
 tt_status tt_problem_create(tt_ctx* ctx, const tt_params* pp, const tt_tt* const* velocity,
-                            const tt_tt* sketch, const tt_tt* sketch_mean, tt_problem** out) {
+                            const tt_tt* sketch, const tt_tt* sketch_left, const tt_tt* sketch_mean,
+                            const tt_tt* sketch_mean_left, tt_problem** out) {
   return guard([&] {
     QTT_REQUIRE(ctx && pp && out, "null argument");
     const tt_params& p = *pp;
@@ -818,7 +822,7 @@ tt_status tt_problem_create(tt_ctx* ctx, const tt_params* pp, const tt_tt* const
     P->nx = N - P->nphi;
     if (P->nx > 0) {
       QTT_REQUIRE(velocity && velocity[0] && velocity[1] && velocity[2], "5-D problem needs velocity");
-      QTT_REQUIRE(sketch_mean, "5-D problem needs the mean-field sketch");
+      QTT_REQUIRE(sketch_mean && sketch_mean_left, "5-D problem needs the two mean-field sketches");
       QTT_REQUIRE(p.chi_mean >= 1 && p.ell_mean >= p.chi_mean, "need ell_mean >= chi_mean >= 1");
     }
     check_tt(sketch, ctx);
@@ -826,10 +830,15 @@ tt_status tt_problem_create(tt_ctx* ctx, const tt_params* pp, const tt_tt* const
     auto ell = chain_caps(N, p.ell);
     QTT_REQUIRE(sketch->caps == ell, "sketch ranks must be min(ell, 2^n, 2^(N-n))");
     P->fcaps = chain_caps(N, p.chi);
+    check_tt(sketch_left, ctx);
+    QTT_REQUIRE(sketch_left->N == N && sketch_left->kind == TT_MPS && sketch_left->caps == ell,
+                "the left sketch must have the ranks of the sketch");
     // copies of the sketches
     {
       P->Z = make_tt(ctx, TT_MPS, N, ell);
       rt::copy(P->Z->buf.p, sketch->buf.p, sketch->total() * sizeof(double));
+      P->Zl = make_tt(ctx, TT_MPS, N, ell);
+      rt::copy(P->Zl->buf.p, sketch_left->buf.p, sketch_left->total() * sizeof(double));
     }
     if (P->nx > 0) {
       check_tt(sketch_mean, ctx);
@@ -837,6 +846,10 @@ tt_status tt_problem_create(tt_ctx* ctx, const tt_params* pp, const tt_tt* const
       QTT_REQUIRE(sketch_mean->N == P->nx && sketch_mean->caps == ellm, "mean-field sketch shape");
       P->Zm = make_tt(ctx, TT_MPS, P->nx, ellm);
       rt::copy(P->Zm->buf.p, sketch_mean->buf.p, sketch_mean->total() * sizeof(double));
+      check_tt(sketch_mean_left, ctx);
+      QTT_REQUIRE(sketch_mean_left->N == P->nx && sketch_mean_left->caps == ellm, "left mean-field sketch shape");
+      P->Zml = make_tt(ctx, TT_MPS, P->nx, ellm);
+      rt::copy(P->Zml->buf.p, sketch_mean_left->buf.p, sketch_mean_left->total() * sizeof(double));
       P->mcaps = chain_caps(P->nx, p.chi_mean);
     }
     // ---- fixed operator (eq. FP2): drift, dissipation, reaction, convection, diffusion

@@ -142,6 +142,16 @@ struct RoundTarget {
 // (the terms' independent chains use up to `lanes` lanes when called on lane 0)
 void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const ChainView& Z,
                        RoundTarget& target, Prec prec, int lanes = 4);
+// randomized range finding from both ends towards the middle site (right
+// sketches with Zr for the left sweep, left sketches with Zl for the right
+// sweep), then simultaneous truncation of the mixed canonical form
+void plan_round_sketch_two_sided(Plan& plan, const std::vector<SketchTerm>& terms, const ChainView& Zr,
+                                 const ChainView& Zl, RoundTarget& target, Prec prec, int lanes = 4);
+// planner building blocks shared by the rounding planners
+void add_tc(Plan& plan, TcDesc d, Prec p);
+void add_gemm(Plan& plan, int M, int N, int K, const double* A, int64_t lda, bool ta, const double* B,
+              int64_t ldb, bool tb, double* C, int64_t ldc, double alpha, double beta, Prec p);
+OpInfo qr_info(int m, int n);
 // LQ sweep + QR sweep + simultaneous truncation of an explicit chain
 void plan_round_det(Plan& plan, const ChainView& x, RoundTarget& target);
 // QR sweep only: left-orthogonal copy (returns caps of the result); used for norms

@@ -66,7 +66,7 @@ ChainView view_sites(const tt_tt* t, int first, int count) {
 static Mode2 M1(int64_t s) { return mode1(s); }
 static Mode2 M2(int n2, int64_t s1, int64_t s2) { return mode2(n2, s1, s2); }
 
-static void add_tc(Plan& plan, TcDesc d, Prec p) {
+void add_tc(Plan& plan, TcDesc d, Prec p) {
   d.ksplit = tc_choose_ksplit(d, p);
   if (d.ksplit > 1) d.part = plan.alloc((size_t)d.batch * d.ksplit * d.M * d.N);
   tc_validate(d);
@@ -83,7 +83,7 @@ static void add_tc(Plan& plan, TcDesc d, Prec p) {
   plan.add([d, p](hipStream_t s) { tc_launch(d, p, s); }, oi);
 }
 
-static OpInfo qr_info(int m, int n) {
+OpInfo qr_info(int m, int n) {
   OpInfo oi;
   oi.kind = OP_QR;
   oi.flops = 2.0 * (2.0 * m * (double)n * n - 2.0 * n * (double)n * n / 3.0);
@@ -194,9 +194,9 @@ void Plan::run_profiled(hipStream_t s, int kind, double& ms, int64_t& count, dou
     for (auto& e : ev) (void)hipEventDestroy(e);
 }
 
-static void add_gemm(Plan& plan, int M, int N, int K, const double* A, int64_t lda, bool ta,
-                     const double* B, int64_t ldb, bool tb, double* C, int64_t ldc, double alpha,
-                     double beta, Prec p) {
+void add_gemm(Plan& plan, int M, int N, int K, const double* A, int64_t lda, bool ta,
+              const double* B, int64_t ldb, bool tb, double* C, int64_t ldc, double alpha,
+              double beta, Prec p) {
   add_tc(plan, gemm_desc(M, N, K, A, lda, ta, B, ldb, tb, C, ldc, alpha, beta), p);
 }
 

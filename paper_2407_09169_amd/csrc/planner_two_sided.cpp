@@ -1,0 +1,612 @@
+// Two-sided randomized rounding of Y = sum_j c_j W_j x_j.
+//
+// The chain is orthogonalised from both ends towards its middle site c:
+//   * sites 0..c-1 by the left-to-right sweep of the one-sided range finder
+//     (sketched unfoldings S_n = [X_(<n)^T Y]_n Right_(n+1)(Y) Right_(n+1)(Zr)^T,
+//     X_n = Householder Q of S_n), giving left-orthogonal cores;
+//   * sites N-1..c+1 by the mirrored right-to-left sweep with the left
+//     sketches Left_n(Zl)^T Left_n(Y) (V_n = Q of the transposed sketched
+//     unfolding), giving right-orthogonal cores;
+//   * the centre core X_(<c)^T Y V_(>c)^T.
+// The two sweeps and, before them, the two families of partial sketches are
+// independent and run on separate lanes, so the sequential chain of QR
+// factorisations is half as long as in the one-sided sweep.
+//
+// Truncation of the mixed canonical form: at a bond n <= c the left part is
+// orthonormal and the right Gram matrix decides (Gamma_c = G G^T from the
+// centre core G, then the chain through X_(c-1)..X_1); at a bond n > c the
+// right part is orthonormal and the left Gram matrix decides (Lambda_(c+1) =
+// G^T G, then the chain through V_(c+1)..).  One batched eigen-decomposition
+// over all bonds, then the cores P_n^T A_n P_(n+1).
+//
+// Layouts: an MPS core is [r][2][r'] row-major, an MPO core [D][2 out][2 in][D'].
+// Right sketches R[(a,A), z] (r_n D_n x ell_n), left sketches Lk[y, (a,A)]
+// (ell_n x r_n D_n), left-sweep cores C[(k,t), (b,B)], right-sweep cores
+// Cr[(a,A), (t,z)], right-orthogonal cores kept as Vt[(t,z), y] = V[y,t,z]
+// (the Q factor of the transposed sketch, as the QR kernel returns it).
+#include <algorithm>
+
+#include "library.h"
+
+namespace qtt {
+
+namespace {
+
+Mode2 M1(int64_t s) { return mode1(s); }
+Mode2 M2(int n2, int64_t s1, int64_t s2) { return mode2(n2, s1, s2); }
+
+struct Shape {
+  std::vector<int> r, D;  // bonds of the term's MPS and MPO (D = 1: identity)
+};
+
+// R_out[(a,A), z] = sum x[a,s,b] W[A,t,s,B] R_in[(b,B), z'] Z[z,t,z']  (site n)
+void add_rsketch(Plan& plan, const SketchTerm& t, const Shape& sh, const ChainView& Z, int n,
+                 const double* Rin, double* Rout, double* T1, double* T2, Prec prec) {
+  const int l = Z.caps[n], lp = Z.caps[n + 1];
+  const int rn = sh.r[n], rp = sh.r[n + 1], Dn = sh.D[n], Dp = sh.D[n + 1];
+  {  // T1[(b,B),(t,z)] = sum_z' R_in[(b,B),z'] Z[z,t,z']
+    TcDesc d;
+    d.M = rp * Dp;
+    d.N = 2 * l;
+    d.K = lp;
+    d.A = Rin;
+    d.am = M1(lp);
+    d.ak = M1(1);
+    d.B = Z.core[n];
+    d.bk = M1(1);
+    d.bn = M2(l, lp, 2 * lp);
+    d.C = T1;
+    d.cm = M1(2 * l);
+    d.cn = M1(1);
+    d.ab = d.bb = d.cb = M1(0);
+    add_tc(plan, d, prec);
+  }
+  if (t.mpo) {
+    {  // T2[(A,s), b, z] = sum_(B,t) W[A,t,s,B] T1[(b,B),(t,z)], batch b
+      TcDesc d;
+      d.batch = rp;
+      d.M = 2 * Dn;
+      d.K = 2 * Dp;
+      d.N = l;
+      d.A = t.mpo->core[n];
+      d.am = M2(2, 4 * Dp, Dp);
+      d.ak = M2(2, 1, 2 * Dp);
+      d.ab = M1(0);
+      d.B = T1;
+      d.bk = M2(2, 2 * l, l);
+      d.bn = M1(1);
+      d.bb = M1((int64_t)Dp * 2 * l);
+      d.C = T2;
+      d.cm = M1((int64_t)rp * l);
+      d.cn = M1(1);
+      d.cb = M1(l);
+      add_tc(plan, d, prec);
+    }
+    {  // R_out[(a,A),z] = sum_(s,b) x[a,s,b] T2[A,s,b,z], batch A
+      TcDesc d;
+      d.batch = Dn;
+      d.M = rn;
+      d.K = 2 * rp;
+      d.N = l;
+      d.A = t.x.core[n];
+      d.am = M1(2 * rp);
+      d.ak = M1(1);
+      d.ab = M1(0);
+      d.B = T2;
+      d.bk = M1(l);
+      d.bn = M1(1);
+      d.bb = M1((int64_t)2 * rp * l);
+      d.C = Rout;
+      d.cm = M1((int64_t)Dn * l);
+      d.cn = M1(1);
+      d.cb = M1(l);
+      add_tc(plan, d, prec);
+    }
+  } else {  // R_out[a,z] = sum_(s,b) x[a,s,b] T1[b,(s,z)]
+    TcDesc d;
+    d.M = rn;
+    d.K = 2 * rp;
+    d.N = l;
+    d.A = t.x.core[n];
+    d.am = M1(2 * rp);
+    d.ak = M1(1);
+    d.B = T1;
+    d.bk = M2(rp, l, 2 * l);
+    d.bn = M1(1);
+    d.C = Rout;
+    d.cm = M1(l);
+    d.cn = M1(1);
+    d.ab = d.bb = d.cb = M1(0);
+    add_tc(plan, d, prec);
+  }
+}
+
+// L_out[z, (b,B)] = sum Zl[y,t,z] L_in[y,(a,A)] x[a,s,b] W[A,t,s,B]  (site n)
+void add_lsketch(Plan& plan, const SketchTerm& t, const Shape& sh, const ChainView& Zl, int n,
+                 const double* Lin, double* Lout, double* T1, double* T2, Prec prec) {
+  const int l = Zl.caps[n], lp = Zl.caps[n + 1];
+  const int rn = sh.r[n], rp = sh.r[n + 1], Dn = sh.D[n], Dp = sh.D[n + 1];
+  {  // T1[(a,A),(t,z)] = sum_y L_in[y,(a,A)] Zl[y,(t,z)]
+    TcDesc d;
+    d.M = rn * Dn;
+    d.N = 2 * lp;
+    d.K = l;
+    d.A = Lin;
+    d.am = M1(1);
+    d.ak = M1((int64_t)rn * Dn);
+    d.B = Zl.core[n];
+    d.bk = M1(2 * lp);
+    d.bn = M1(1);
+    d.C = T1;
+    d.cm = M1(2 * lp);
+    d.cn = M1(1);
+    d.ab = d.bb = d.cb = M1(0);
+    add_tc(plan, d, prec);
+  }
+  if (t.mpo) {
+    {  // T2[a,(s,B),z] = sum_(A,t) W[A,t,s,B] T1[(a,A),(t,z)], batch a
+      TcDesc d;
+      d.batch = rn;
+      d.M = 2 * Dp;
+      d.K = 2 * Dn;
+      d.N = lp;
+      d.A = t.mpo->core[n];
+      d.am = M1(1);
+      d.ak = M1(2 * Dp);
+      d.ab = M1(0);
+      d.B = T1;
+      d.bk = M1(lp);
+      d.bn = M1(1);
+      d.bb = M1((int64_t)Dn * 2 * lp);
+      d.C = T2;
+      d.cm = M1(lp);
+      d.cn = M1(1);
+      d.cb = M1((int64_t)2 * Dp * lp);
+      add_tc(plan, d, prec);
+    }
+    {  // L_out[z,(b,B)] = sum_(a,s) T2[a,(s,B),z] x[a,s,b], batch B
+      TcDesc d;
+      d.batch = Dp;
+      d.M = lp;
+      d.N = rp;
+      d.K = 2 * rn;
+      d.A = T2;
+      d.am = M1(1);
+      d.ak = M1((int64_t)Dp * lp);
+      d.ab = M1(lp);
+      d.B = t.x.core[n];
+      d.bk = M1(rp);
+      d.bn = M1(1);
+      d.bb = M1(0);
+      d.C = Lout;
+      d.cm = M1((int64_t)rp * Dp);
+      d.cn = M1(Dp);
+      d.cb = M1(1);
+      add_tc(plan, d, prec);
+    }
+  } else {  // L_out[z,b] = sum_(a,s) T1[a,(s,z)] x[a,s,b]
+    TcDesc d;
+    d.M = lp;
+    d.N = rp;
+    d.K = 2 * rn;
+    d.A = T1;
+    d.am = M1(1);
+    d.ak = M1(lp);
+    d.B = t.x.core[n];
+    d.bk = M1(rp);
+    d.bn = M1(1);
+    d.C = Lout;
+    d.cm = M1(rp);
+    d.cn = M1(1);
+    d.ab = d.bb = d.cb = M1(0);
+    add_tc(plan, d, prec);
+  }
+}
+
+// C[(k,t),(b,B)] = alpha * sum M[k,(a,A)] x[a,s,b] W[A,t,s,B] + beta * C  (site n, l rows)
+void add_lcore(Plan& plan, const SketchTerm& t, const Shape& sh, int n, int l, const double* M,
+               double* U1, double* Cdst, double alpha, double beta, Prec prec) {
+  const int rn = sh.r[n], rp = sh.r[n + 1], Dn = sh.D[n], Dp = sh.D[n + 1];
+  if (!t.mpo) {
+    add_gemm(plan, l, 2 * rp, rn, M, rn, false, t.x.core[n], 2 * rp, false, Cdst, 2 * rp, alpha,
+             beta, prec);
+    return;
+  }
+  {  // U1[k,A,s,b] = sum_a M[k,(a,A)] x[a,s,b], batch A
+    TcDesc d;
+    d.batch = Dn;
+    d.M = l;
+    d.K = rn;
+    d.N = 2 * rp;
+    d.A = M;
+    d.am = M1((int64_t)rn * Dn);
+    d.ak = M1(Dn);
+    d.ab = M1(1);
+    d.B = t.x.core[n];
+    d.bk = M1(2 * rp);
+    d.bn = M1(1);
+    d.bb = M1(0);
+    d.C = U1;
+    d.cm = M1((int64_t)2 * Dn * rp);
+    d.cn = M1(1);
+    d.cb = M1(2 * rp);
+    add_tc(plan, d, prec);
+  }
+  {  // C[k,t,b,B] = sum_(A,s) U1[k,A,s,b] W[A,t,s,B]
+    TcDesc d;
+    d.M = l * rp;
+    d.K = 2 * Dn;
+    d.N = 2 * Dp;
+    d.A = U1;
+    d.am = M2(rp, (int64_t)2 * Dn * rp, 1);
+    d.ak = M1(rp);
+    d.B = t.mpo->core[n];
+    d.bk = M2(2, 4 * Dp, Dp);
+    d.bn = M2(Dp, 2 * Dp, 1);
+    d.C = Cdst;
+    d.cm = M2(rp, (int64_t)2 * rp * Dp, Dp);
+    d.cn = M2(Dp, (int64_t)rp * Dp, 1);
+    d.ab = d.bb = d.cb = M1(0);
+    d.alpha = alpha;
+    d.beta = beta;
+    add_tc(plan, d, prec);
+  }
+}
+
+// Cr[(a,A),(t,z)] = sum x[a,s,b] W[A,t,s,B] Mr[(b,B),z]  (site n, lp columns of Mr)
+void add_rcore(Plan& plan, const SketchTerm& t, const Shape& sh, int n, int lp, const double* Mr,
+               double* U1, double* Cdst, Prec prec) {
+  const int rn = sh.r[n], rp = sh.r[n + 1], Dn = sh.D[n], Dp = sh.D[n + 1];
+  if (!t.mpo) {  // Cr[(a,s),z] = sum_b x[a,s,b] Mr[b,z]
+    add_gemm(plan, 2 * rn, lp, rp, t.x.core[n], rp, false, Mr, lp, false, Cdst, lp, 1.0, 0.0, prec);
+    return;
+  }
+  {  // U1[(a,s),B,z] = sum_b x[a,s,b] Mr[(b,B),z], batch B
+    TcDesc d;
+    d.batch = Dp;
+    d.M = 2 * rn;
+    d.K = rp;
+    d.N = lp;
+    d.A = t.x.core[n];
+    d.am = M1(rp);
+    d.ak = M1(1);
+    d.ab = M1(0);
+    d.B = Mr;
+    d.bk = M1((int64_t)Dp * lp);
+    d.bn = M1(1);
+    d.bb = M1(lp);
+    d.C = U1;
+    d.cm = M1((int64_t)Dp * lp);
+    d.cn = M1(1);
+    d.cb = M1(lp);
+    add_tc(plan, d, prec);
+  }
+  {  // Cr[(a,A),(t,z)] = sum_(s,B) W[(A,t),(s,B)] U1[(a,s),B,z]: rows (A,t), columns (a,z)
+    TcDesc d;
+    d.M = 2 * Dn;
+    d.N = rn * lp;
+    d.K = 2 * Dp;
+    d.A = t.mpo->core[n];
+    d.am = M1(2 * Dp);
+    d.ak = M1(1);
+    d.B = U1;
+    d.bk = M2(Dp, (int64_t)Dp * lp, lp);
+    d.bn = M2(lp, (int64_t)2 * Dp * lp, 1);
+    d.C = Cdst;
+    d.cm = M1(lp);
+    d.cn = M2(lp, (int64_t)Dn * 2 * lp, 1);
+    d.ab = d.bb = d.cb = M1(0);
+    add_tc(plan, d, prec);
+  }
+}
+
+}  // namespace
+
+// Simultaneous truncation of the mixed canonical chain: left-orthogonal X_n
+// (n < c, [ell_n][2][ell_(n+1)]), centre G ([ell_c][2][ell_(c+1)]) and
+// right-orthogonal V_n (n > c, kept as Vt[(t,z),y]).
+static void plan_trunc_gram_mixed(Plan& plan, const std::vector<double*>& X, const double* Gc,
+                                  const std::vector<double*>& Vt, int c, const std::vector<int>& ell,
+                                  RoundTarget& tg, Prec prec, int lanes) {
+  // eigenvectors resolved down to the noise the contractions left in the
+  // Gram matrices (see the one-sided truncation)
+  const double u = machine_eps(prec);
+  const double unoise = std::max(machine_eps(Prec::F64), u * u);
+  const int N = (int)ell.size() - 1;
+  QTT_REQUIRE((int)tg.caps.size() == N + 1 && (int)tg.core.size() == N, "truncation target shape");
+  int lmax = 1, cmax = 1;
+  for (int n = 0; n <= N; ++n) {
+    lmax = std::max(lmax, ell[n]);
+    cmax = std::max(cmax, tg.caps[n]);
+  }
+  const int ldg = lmax, ldp = cmax;
+  double* Gam = plan.alloc((size_t)(N + 1) * ldg * ldg);
+  double* P = plan.alloc((size_t)(N + 1) * ldg * ldp);
+  double* lam = plan.alloc((size_t)(N + 1) * ldg);
+  double* ework = plan.alloc((size_t)std::max(1, N - 1) * 2 * ldg * ldg);
+  size_t tsz = 1, vsz = 1;
+  for (int n = 0; n < N; ++n) {
+    tsz = std::max(tsz, (size_t)2 * ell[n] * ell[n + 1]);
+    vsz = std::max(vsz, (size_t)tg.caps[n] * 2 * ell[n + 1]);
+  }
+  double* TgL = plan.alloc(tsz);
+  double* TgR = plan.alloc(tsz);
+  double* V1 = plan.alloc(vsz);
+  std::vector<int> dims, keep;
+  for (int n = 1; n < N; ++n) {
+    dims.push_back(ell[n]);
+    keep.push_back(std::min(ell[n], tg.caps[n]));
+  }
+  int* d_dims = plan.upload(dims);
+  int* d_keep = plan.upload(keep);
+  tg.lam = lam;
+  tg.ldl = ldg;
+  const size_t psz = (size_t)(N + 1) * ldg * ldp;
+  plan.add([P, psz, lam, N, ldg](hipStream_t s) {
+    fill(P, (int64_t)psz, 0.0, s);
+    fill(lam, (int64_t)(N + 1) * ldg, 0.0, s);
+  });
+  auto G = [&](int n) { return Gam + (size_t)n * ldg * ldg; };
+  auto Pn = [&](int n) { return P + (size_t)n * ldg * ldp; };
+  const int L = (plan.cur == 0 && !plan.no_lanes && lanes > 1) ? 2 : 1;
+  plan.fork(L);
+  // right Gram chain, bonds c..1 (left of the centre)
+  if (c >= 1) {
+    const int a = ell[c], b = ell[c + 1];
+    add_gemm(plan, a, a, 2 * b, Gc, 2 * b, false, Gc, 2 * b, true, G(c), ldg, 1.0, 0.0, Prec::F64);
+    for (int n = c - 1; n >= 1; --n) {
+      const int an = ell[n], bn = ell[n + 1];
+      add_gemm(plan, 2 * an, bn, bn, X[n], bn, false, G(n + 1), ldg, false, TgL, bn, 1.0, 0.0, Prec::F64);
+      add_gemm(plan, an, an, 2 * bn, TgL, 2 * bn, false, X[n], 2 * bn, true, G(n), ldg, 1.0, 0.0, Prec::F64);
+    }
+  }
+  // left Gram chain, bonds c+1..N-1 (right of the centre)
+  if (L > 1) plan.on(1);
+  if (c + 1 <= N - 1) {
+    const int a = ell[c], b = ell[c + 1];
+    add_gemm(plan, b, b, 2 * a, Gc, b, true, Gc, b, false, G(c + 1), ldg, 1.0, 0.0, Prec::F64);
+    for (int n = c + 1; n <= N - 2; ++n) {
+      const int l = ell[n], lp = ell[n + 1];
+      // H[(t,z),y'] = sum_y Vt[(t,z),y] Lambda_n[y,y']
+      add_gemm(plan, 2 * lp, l, l, Vt[n], l, false, G(n), ldg, false, TgR, l, 1.0, 0.0, Prec::F64);
+      // Lambda_(n+1)[z,z'] = sum_(t,y') H[(t,z),y'] Vt[(t,z'),y']
+      TcDesc d;
+      d.M = lp;
+      d.N = lp;
+      d.K = 2 * l;
+      d.A = TgR;
+      d.am = M1(l);
+      d.ak = M2(l, (int64_t)lp * l, 1);
+      d.B = Vt[n];
+      d.bk = M2(l, (int64_t)lp * l, 1);
+      d.bn = M1(l);
+      d.C = G(n + 1);
+      d.cm = M1(ldg);
+      d.cn = M1(1);
+      d.ab = d.bb = d.cb = M1(0);
+      add_tc(plan, d, Prec::F64);
+    }
+  }
+  plan.join(L);
+  if (N >= 2) {
+    const double* g1 = G(1);
+    double* p1 = Pn(1);
+    double* l1 = lam + ldg;
+    const int cnt = N - 1;
+    OpInfo oi;
+    oi.kind = OP_EIG;
+    oi.what = eig_kernel_name(lmax) + "|count" + std::to_string(cnt) + " nmax" + std::to_string(lmax);
+    for (int n = 1; n < N; ++n) {
+      oi.bytes += 8.0 * ((double)ell[n] * ell[n] + (double)ell[n] * tg.caps[n]);
+      oi.flops += 9.0 * (double)ell[n] * ell[n] * ell[n];
+    }
+    plan.add([=](hipStream_t s) {
+      eig_launch(cnt, d_dims, d_keep, g1, (int64_t)ldg * ldg, ldg, p1, (int64_t)ldg * ldp, ldp, l1, ldg,
+                 ework, lmax, unoise, s);
+    }, oi);
+  }
+  // new cores P_n^T A_n P_(n+1)
+  for (int n = 0; n < N; ++n) {
+    const int l = ell[n], lp = ell[n + 1], cl = tg.caps[n], cr = tg.caps[n + 1];
+    if (n <= c) {
+      const double* A = (n == c) ? Gc : X[n];  // [l][2][lp]
+      if (n == 0 && N == 1) {
+        double* dst = tg.core[0];
+        plan.add([=](hipStream_t s) { rt::copy_async(dst, A, 2 * sizeof(double), s); });
+      } else if (n == 0) {
+        add_gemm(plan, 2, cr, lp, A, lp, false, Pn(1), ldp, false, tg.core[0], cr, 1.0, 0.0, Prec::F64);
+      } else if (n == N - 1) {
+        add_gemm(plan, cl, 2, l, Pn(n), ldp, true, A, 2, false, tg.core[n], 2, 1.0, 0.0, Prec::F64);
+      } else {
+        add_gemm(plan, cl, 2 * lp, l, Pn(n), ldp, true, A, 2 * lp, false, V1, 2 * lp, 1.0, 0.0, Prec::F64);
+        add_gemm(plan, 2 * cl, cr, lp, V1, lp, false, Pn(n + 1), ldp, false, tg.core[n], cr, 1.0, 0.0,
+                 Prec::F64);
+      }
+    } else {
+      // V1[k,(t,z)] = sum_y P_n[y,k] V[y,t,z] = sum_y P_n[y,k] Vt[(t,z),y]
+      const bool lastsite = (n == N - 1);
+      TcDesc d;
+      d.M = cl;
+      d.N = 2 * lp;
+      d.K = l;
+      d.A = Pn(n);
+      d.am = M1(1);
+      d.ak = M1(ldp);
+      d.B = Vt[n];
+      d.bk = M1(1);
+      d.bn = M1(l);
+      d.C = lastsite ? tg.core[n] : V1;
+      d.cm = M1(2 * lp);
+      d.cn = M1(1);
+      d.ab = d.bb = d.cb = M1(0);
+      add_tc(plan, d, Prec::F64);
+      if (!lastsite)
+        add_gemm(plan, 2 * cl, cr, lp, V1, lp, false, Pn(n + 1), ldp, false, tg.core[n], cr, 1.0, 0.0,
+                 Prec::F64);
+    }
+  }
+}
+
+void plan_round_sketch_two_sided(Plan& plan, const std::vector<SketchTerm>& terms, const ChainView& Zr,
+                                 const ChainView& Zl, RoundTarget& tg, Prec prec, int lanes) {
+  const int N = Zr.N;
+  const int J = (int)terms.size();
+  QTT_REQUIRE(J >= 1, "rounding needs at least one term");
+  QTT_REQUIRE(Zl.N == N && Zl.caps == Zr.caps, "the two sketches must have the same ranks");
+  if (N < 2) {
+    plan_round_sketch(plan, terms, Zr, tg, prec, lanes);
+    return;
+  }
+  const std::vector<int>& ell = Zr.caps;
+  for (int n = 0; n < N; ++n)
+    QTT_REQUIRE(ell[n + 1] <= 2 * ell[n] && ell[n] <= 2 * ell[n + 1],
+                "sketch ranks must satisfy ell_(n+1) <= 2 ell_n and ell_n <= 2 ell_(n+1)");
+  const int c = N / 2;
+  const bool lanes_ok = (plan.cur == 0 && !plan.no_lanes);
+  std::vector<Shape> sh(J);
+  for (int j = 0; j < J; ++j) {
+    QTT_REQUIRE(terms[j].x.N == N, "term length differs from the sketch");
+    sh[j].r = terms[j].x.caps;
+    if (terms[j].mpo) {
+      QTT_REQUIRE(terms[j].mpo->N == N, "operator length differs from the sketch");
+      sh[j].D = terms[j].mpo->caps;
+    } else {
+      sh[j].D.assign(N + 1, 1);
+    }
+  }
+  // workspace sizes
+  size_t t1 = 1, t2 = 1, msz = 1, u1 = 1, csz = 1, crsz = 1, ssz = 1;
+  for (int j = 0; j < J; ++j)
+    for (int n = 0; n < N; ++n) {
+      const auto& r = sh[j].r;
+      const auto& D = sh[j].D;
+      const size_t rn = r[n], rp = r[n + 1], Dn = D[n], Dp = D[n + 1], l = ell[n], lp = ell[n + 1];
+      t1 = std::max({t1, rp * Dp * 2 * l, rn * Dn * 2 * lp});
+      t2 = std::max({t2, 2 * Dn * rp * l, rn * 2 * Dp * lp});
+      msz = std::max({msz, l * rn * Dn, rp * Dp * lp});
+      u1 = std::max({u1, l * Dn * 2 * rp, 2 * rn * Dp * lp});
+      csz = std::max(csz, l * 2 * rp * Dp);
+      crsz = std::max(crsz, rn * Dn * 2 * lp);
+      ssz = std::max(ssz, 2 * l * lp);
+    }
+  const int Ls = lanes_ok ? std::max(1, std::min(lanes, 2 * J)) : 1;
+  std::vector<double*> T1s(Ls), T2s(Ls);
+  for (int l = 0; l < Ls; ++l) {
+    T1s[l] = plan.alloc(t1);
+    T2s[l] = plan.alloc(t2);
+  }
+  double* one = plan.upload(std::vector<double>{1.0});
+  std::vector<std::vector<double*>> R(J, std::vector<double*>(N + 1, nullptr));
+  std::vector<std::vector<double*>> Lk(J, std::vector<double*>(N + 1, nullptr));
+  std::vector<double*> Ma(J), Mb(J), Cb(J), Mra(J), Mrb(J), Crb(J);
+  for (int j = 0; j < J; ++j) {
+    for (int n = 1; n < N; ++n) {
+      R[j][n] = plan.alloc((size_t)sh[j].r[n] * sh[j].D[n] * ell[n]);
+      Lk[j][n] = plan.alloc((size_t)ell[n] * sh[j].r[n] * sh[j].D[n]);
+    }
+    R[j][N] = one;
+    Lk[j][0] = one;
+    Ma[j] = plan.alloc(msz);
+    Mb[j] = plan.alloc(msz);
+    Cb[j] = plan.alloc(csz);
+    Mra[j] = plan.alloc(msz);
+    Mrb[j] = plan.alloc(msz);
+    Crb[j] = plan.alloc(crsz);
+  }
+  double* U1L = plan.alloc(u1);
+  double* U1R = plan.alloc(u1);
+  double* SL = plan.alloc(ssz);
+  double* SR = plan.alloc(ssz);
+  double* qwL = plan.alloc(ssz);
+  double* qwR = plan.alloc(ssz);
+  std::vector<double*> X(N, nullptr), Vt(N, nullptr);
+  for (int n = 0; n < c; ++n) X[n] = plan.alloc((size_t)ell[n] * 2 * ell[n + 1]);
+  for (int n = c + 1; n < N; ++n) Vt[n] = plan.alloc((size_t)2 * ell[n + 1] * ell[n]);
+  double* Gc = plan.alloc((size_t)ell[c] * 2 * ell[c + 1]);
+
+  // ---- partial sketches: right (sites N-1..1) and left (sites 0..N-2), chain q on lane q % Ls
+  plan.fork(Ls);
+  for (int q = 0; q < 2 * J; ++q) {
+    const int j = q / 2;
+    if (Ls > 1) plan.on(q % Ls);
+    double* T1 = T1s[q % Ls];
+    double* T2 = T2s[q % Ls];
+    if (q % 2 == 0) {
+      for (int n = N - 1; n >= 1; --n) add_rsketch(plan, terms[j], sh[j], Zr, n, R[j][n + 1], R[j][n], T1, T2, prec);
+    } else {
+      for (int n = 0; n <= N - 2; ++n) add_lsketch(plan, terms[j], sh[j], Zl, n, Lk[j][n], Lk[j][n + 1], T1, T2, prec);
+    }
+  }
+  plan.join(Ls);
+
+  // ---- the two sweeps, on two lanes
+  const int Lw = lanes_ok ? 2 : 1;
+  plan.fork(Lw);
+  std::vector<double*> Mcur(J, one), Mnext = Mb;
+  for (int n = 0; n < c; ++n) {  // left sweep, sites 0..c-1
+    const int l = ell[n], lp = ell[n + 1];
+    for (int j = 0; j < J; ++j) add_lcore(plan, terms[j], sh[j], n, l, Mcur[j], U1L, Cb[j], 1.0, 0.0, prec);
+    for (int j = 0; j < J; ++j) {
+      const int rp = sh[j].r[n + 1], Dp = sh[j].D[n + 1];
+      add_gemm(plan, 2 * l, lp, rp * Dp, Cb[j], (int64_t)rp * Dp, false, R[j][n + 1], lp, false, SL, lp,
+               terms[j].coef, j > 0 ? 1.0 : 0.0, prec);
+    }
+    {
+      double* Xn = X[n];
+      const int m = 2 * l, nc = lp;
+      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, SL, 0, nc, 1, Xn, 0, nullptr, 0, qwL, s); },
+               qr_info(m, nc));
+    }
+    for (int j = 0; j < J; ++j) {
+      const int rp = sh[j].r[n + 1], Dp = sh[j].D[n + 1];
+      add_gemm(plan, lp, rp * Dp, 2 * l, X[n], lp, true, Cb[j], (int64_t)rp * Dp, false, Mnext[j],
+               (int64_t)rp * Dp, 1.0, 0.0, prec);
+    }
+    for (int j = 0; j < J; ++j) {
+      double* old = Mcur[j];
+      Mcur[j] = Mnext[j];
+      Mnext[j] = (old == one) ? Ma[j] : old;
+    }
+  }
+  if (Lw > 1) plan.on(1);
+  std::vector<double*> Mrcur(J, one), Mrnext = Mrb;
+  for (int n = N - 1; n > c; --n) {  // right sweep, sites N-1..c+1
+    const int l = ell[n], lp = ell[n + 1];
+    for (int j = 0; j < J; ++j) add_rcore(plan, terms[j], sh[j], n, lp, Mrcur[j], U1R, Crb[j], prec);
+    for (int j = 0; j < J; ++j) {  // SR[y,(t,z)] = sum_j c_j Lk_j[y,(a,A)] Cr_j[(a,A),(t,z)]
+      const int rD = sh[j].r[n] * sh[j].D[n];
+      add_gemm(plan, l, 2 * lp, rD, Lk[j][n], rD, false, Crb[j], 2 * lp, false, SR, 2 * lp, terms[j].coef,
+               j > 0 ? 1.0 : 0.0, prec);
+    }
+    {  // Q of SR^T (2 lp x l): the rows of V_n = Q^T are orthonormal
+      double* Vn = Vt[n];
+      const int m = 2 * lp, nc = l;
+      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, SR, 0, 1, m, Vn, 0, nullptr, 0, qwR, s); },
+               qr_info(m, nc));
+    }
+    for (int j = 0; j < J; ++j) {  // Mr_j[(a,A),y] = sum_(t,z) Cr_j[(a,A),(t,z)] Vt[(t,z),y]
+      const int rD = sh[j].r[n] * sh[j].D[n];
+      add_gemm(plan, rD, l, 2 * lp, Crb[j], 2 * lp, false, Vt[n], l, false, Mrnext[j], l, 1.0, 0.0, prec);
+    }
+    for (int j = 0; j < J; ++j) {
+      double* old = Mrcur[j];
+      Mrcur[j] = Mrnext[j];
+      Mrnext[j] = (old == one) ? Mra[j] : old;
+    }
+  }
+  plan.join(Lw);
+
+  // ---- centre core G = sum_j c_j [X_(<c)^T Y_j V_(>c)^T]_c
+  {
+    const int l = ell[c], lp = ell[c + 1];
+    for (int j = 0; j < J; ++j) {
+      add_lcore(plan, terms[j], sh[j], c, l, Mcur[j], U1L, Cb[j], 1.0, 0.0, prec);
+      const int rD = sh[j].r[c + 1] * sh[j].D[c + 1];
+      add_gemm(plan, 2 * l, lp, rD, Cb[j], rD, false, Mrcur[j], lp, false, Gc, lp, terms[j].coef,
+               j > 0 ? 1.0 : 0.0, prec);
+    }
+  }
+  plan_trunc_gram_mixed(plan, X, Gc, Vt, c, ell, tg, prec, lanes);
+}
+
+}  // namespace qtt
