@@ -195,7 +195,7 @@ __global__ __launch_bounds__(FT) void qr_kernel(int m, int n, const double* __re
 // place by backward accumulation.
 // ---------------------------------------------------------------------------
 template <int RS, int CPW, int QW, int CH>
-__device__ inline void apply_reflector(double (&a)[RS][CPW], const double (&v)[RS], double t, int k,
+__device__ __forceinline__ void apply_reflector(double (&a)[RS][CPW], const double (&v)[RS], double t, int k,
                                        int n, int wave, int i0) {
 #pragma unroll
   for (int j0 = 0; j0 < CPW; j0 += CH) {
@@ -387,23 +387,95 @@ __device__ inline double row_sum(double v) {
   return v;
 }
 
-// a[:, c] -= t (v^T a[:, c]) v for this lane's columns c with k < c < n
-template <int RPL, int CS, int NW>
-__device__ inline void grp_apply(double (&a)[CS][RPL], const double (&v)[RPL], double t, int k, int n,
-                                 int w, int g) {
+// a[:, c] -= t (v^T a[:, c]) v for this lane's columns c with k < c < n, in
+// the slots J0 <= j < CS with (ONLY < 0 || j == ONLY) && j != SKIP.  Slots
+// below J0 hold only columns <= k.
+template <int RPL, int CS, int NW, int J0, int ONLY = -1, int SKIP = -1>
+__device__ __forceinline__ void grp_apply(double (&a)[CS][RPL], const double (&v)[RPL], double t, int k,
+                                          int n, int w, int g) {
   constexpr int CL = 4 * NW;
 #pragma unroll
-  for (int j = 0; j < CS; ++j) {
-    if (CL * j + 4 * w + 3 <= k) continue;  // no column of this slot is past k (wave-uniform)
+  for (int j = J0; j < CS; ++j) {
+    if ((ONLY >= 0 && j != ONLY) || j == SKIP) continue;
+    if (CL * j + 4 * w + 3 <= k) continue;  // no column of this slot is past k
     if (CL * j + 4 * w >= n) break;
-    double d = 0.0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // four short chains instead of one long one
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) d = fma(v[r], a[j][r], d);
-    d = row_sum(d);
+    for (int r = 0; r < RPL; ++r) acc[r & 3] = fma(v[r], a[j][r], acc[r & 3]);
+    const double d = row_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
     const int c = CL * j + 4 * w + g;
     const double wgt = (c > k && c < n) ? t * d : 0.0;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) a[j][r] = fma(-wgt, v[r], a[j][r]);
+  }
+}
+
+// Owner wavefront of column k (slot JO, group go): builds the reflector
+// H_k = I - tau v v^T from the column in place, stores v below the diagonal,
+// publishes v (vb) and tau / beta.  Called by the whole wavefront.
+template <int RPL, int CS, int JO>
+__device__ __forceinline__ void grp_reflector(double (&a)[CS][RPL], int k, int go, int g, int li, double* vb,
+                                              double* taus, double* betas) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0}, xk = 0.0;
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int row = li + 16 * r;
+    const double x = row > k ? a[JO][r] : 0.0;
+    acc[r & 3] = fma(x, x, acc[r & 3]);
+    if (r == (k >> 4)) xk = a[JO][r];
+  }
+  const double part = row_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
+  const double sig = read_lane(part, 16 * go);
+  const double x0 = read_lane(xk, 16 * go + (k & 15));
+  double tau = 0.0, beta = x0, scale = 0.0;
+  if (sig != 0.0) {
+    // beta = -sign(x0) ||x||, u = x0 - beta (no cancellation), v = x / u with
+    // v_k = 1, tau = -u / beta; one division for both
+    const double nrm = sqrt(x0 * x0 + sig);
+    beta = x0 >= 0.0 ? -nrm : nrm;
+    const double u = x0 - beta;
+    const double q = 1.0 / (u * beta);
+    scale = beta * q;
+    tau = -(u * u) * q;
+  }
+  if (g == go) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int row = li + 16 * r;
+      const double vv = (row > k) ? a[JO][r] * scale : (row == k ? 1.0 : 0.0);
+      vb[row] = vv;
+      if (row > k) a[JO][r] = vv;
+    }
+    if (li == 0) {
+      taus[k] = tau;
+      betas[k] = beta;
+    }
+  }
+}
+
+// Owner of column k (slot JO) in the backward pass: publishes the stored v_k.
+template <int RPL, int CS, int JO>
+__device__ __forceinline__ void grp_publish(const double (&a)[CS][RPL], int k, int li, double* vb) {
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int row = li + 16 * r;
+    vb[row] = (row > k) ? a[JO][r] : (row == k ? 1.0 : 0.0);
+  }
+}
+
+// Calls f(std::integral_constant<int, I>) for I = B, B+1, ..., E-1 (or, with
+// DOWN, for I = E-1, ..., B): the slot index becomes a compile-time constant,
+// so the register array is never indexed at run time.
+template <int B, int E, bool DOWN = false, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    if constexpr (DOWN) {
+      f(std::integral_constant<int, E - 1>{});
+      static_for<B, E - 1, true>(f);
+    } else {
+      f(std::integral_constant<int, B>{});
+      static_for<B + 1, E, false>(f);
+    }
   }
 }
 
@@ -431,61 +503,40 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
       a[j][r] = (row < m && c < n) ? A[row * rs + c * cs] : 0.0;
     }
   }
+  auto wo_of = [](int k) { return (k % CL) >> 2; };
   double v[RPL];
-  for (int k = 0; k < n; ++k) {
-    const int wo = (k % CL) >> 2, go = k & 3, jo = k / CL, buf = k & 1;
-    if (w == wo) {
-      // owner wavefront: column jo of every group; only group go's is used
+  // ---- factorisation, one phase per slot (columns JO*CL .. JO*CL+CL-1), with
+  // look-ahead: the owner of column k+1 applies H_k to that column first and
+  // publishes v_(k+1) before updating its other columns
+  if (w == 0) grp_reflector<RPL, CS, 0>(a, 0, 0, g, li, vbuf[0], taus, betas);
+  static_for<0, CS>([&](auto J) {
+    constexpr int JO = decltype(J)::value;
+    const int kend = min(n, CL * (JO + 1));
+    for (int k = CL * JO; k < kend; ++k) {
+      __syncthreads();  // v_k, tau_k visible
+      const double t = taus[k];
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        double x = 0.0;
-#pragma unroll
-        for (int j = 0; j < CS; ++j) x = (j == jo) ? a[j][r] : x;
-        v[r] = x;
+      for (int r = 0; r < RPL; ++r) v[r] = vbuf[k & 1][li + 16 * r];
+      const int k1 = k + 1;
+      const bool own = k1 < n && w == wo_of(k1);  // wave-uniform
+      // the owner's chain up to publishing v_(k+1) gates the next step: it
+      // runs at raised wave priority
+      if (own) __builtin_amdgcn_s_setprio(2);
+      if (t != 0.0) grp_apply<RPL, CS, NW, JO, JO>(a, v, t, k, n, w, g);
+      if (own && k1 < CL * (JO + 1)) {
+        grp_reflector<RPL, CS, JO>(a, k1, k1 & 3, g, li, vbuf[k1 & 1], taus, betas);
+        __builtin_amdgcn_s_setprio(0);
       }
-      double part = 0.0, xk = 0.0;
-#pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int row = li + 16 * r;
-        if (row > k) part = fma(v[r], v[r], part);
-        if (r == (k >> 4)) xk = v[r];
-      }
-      part = row_sum(part);
-      const double sig = read_lane(part, 16 * go);
-      const double x0 = read_lane(xk, 16 * go + (k & 15));
-      double tau = 0.0, beta = x0, scale = 0.0;
-      if (sig != 0.0) {
-        const double nrm = sqrt(x0 * x0 + sig);
-        beta = x0 >= 0.0 ? -nrm : nrm;
-        tau = (beta - x0) / beta;
-        scale = 1.0 / (x0 - beta);
-      }
-      if (g == go) {
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-          const int row = li + 16 * r;
-          const double vv = (row > k) ? v[r] * scale : (row == k ? 1.0 : 0.0);
-          vbuf[buf][row] = vv;
-          if (row > k) {
-#pragma unroll
-            for (int j = 0; j < CS; ++j)
-              if (j == jo) a[j][r] = vv;
-          }
+      if constexpr (JO + 1 < CS) {
+        if (t != 0.0) grp_apply<RPL, CS, NW, JO + 1, JO + 1>(a, v, t, k, n, w, g);
+        if (own && k1 == CL * (JO + 1)) {
+          grp_reflector<RPL, CS, JO + 1>(a, k1, k1 & 3, g, li, vbuf[k1 & 1], taus, betas);
+          __builtin_amdgcn_s_setprio(0);
         }
-        if (li == 0) {
-          taus[k] = tau;
-          betas[k] = beta;
-        }
+        if (t != 0.0) grp_apply<RPL, CS, NW, JO + 2>(a, v, t, k, n, w, g);
       }
     }
-    __syncthreads();
-    const double t = taus[k];
-    if (t != 0.0) {
-#pragma unroll
-      for (int r = 0; r < RPL; ++r) v[r] = vbuf[buf][li + 16 * r];
-      grp_apply<RPL, CS, NW>(a, v, t, k, n, w, g);
-    }
-  }
+  });
   __syncthreads();
   if (R0 != nullptr) {
     double* R = R0 + bi * strideR;
@@ -501,34 +552,38 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
       }
     }
   }
-  for (int k = n - 1; k >= 0; --k) {
-    const int wo = (k % CL) >> 2, go = k & 3, jo = k / CL, buf = k & 1;
-    if (w == wo && g == go) {
+  // ---- thin Q by backward accumulation, slot phases in reverse; v_(k-1) is
+  // published while H_k is being applied (the stored reflectors no longer
+  // change)
+  static_for<0, CS>([&](auto J) {
+    constexpr int JO = decltype(J)::value;
+    const int kl = n - 1;
+    if (kl / CL == JO && w == wo_of(kl) && g == (kl & 3)) grp_publish<RPL, CS, JO>(a, kl, li, vbuf[kl & 1]);
+  });
+  static_for<0, CS, true>([&](auto J) {
+    constexpr int JO = decltype(J)::value;
+    for (int k = min(n, CL * (JO + 1)) - 1; k >= CL * JO; --k) {
+      __syncthreads();  // v_k visible
+      const double t = taus[k];
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int row = li + 16 * r;
-        double x = 0.0;
+      for (int r = 0; r < RPL; ++r) v[r] = vbuf[k & 1][li + 16 * r];
+      const int km = k - 1;
+      if (km >= 0 && w == wo_of(km) && g == (km & 3)) {
+        if (km >= CL * JO)
+          grp_publish<RPL, CS, JO>(a, km, li, vbuf[km & 1]);
+        else if constexpr (JO > 0)
+          grp_publish<RPL, CS, JO - 1>(a, km, li, vbuf[km & 1]);
+      }
+      if (t != 0.0) grp_apply<RPL, CS, NW, JO>(a, v, t, k, n, w, g);
+      if (w == wo_of(k) && g == (k & 3)) {
 #pragma unroll
-        for (int j = 0; j < CS; ++j) x = (j == jo) ? a[j][r] : x;
-        vbuf[buf][row] = (row > k) ? x : (row == k ? 1.0 : 0.0);
+        for (int r = 0; r < RPL; ++r) {
+          const int row = li + 16 * r;
+          a[JO][r] = (row < k) ? 0.0 : (row == k ? 1.0 - t : -t * v[r]);
+        }
       }
     }
-    __syncthreads();
-    const double t = taus[k];
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) v[r] = vbuf[buf][li + 16 * r];
-    if (t != 0.0) grp_apply<RPL, CS, NW>(a, v, t, k, n, w, g);
-    if (w == wo && g == go) {
-#pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int row = li + 16 * r;
-        const double qv = (row < k) ? 0.0 : (row == k ? 1.0 - t : -t * v[r]);
-#pragma unroll
-        for (int j = 0; j < CS; ++j)
-          if (j == jo) a[j][r] = qv;
-      }
-    }
-  }
+  });
   double* Q = Q0 + bi * strideQ;
 #pragma unroll
   for (int j = 0; j < CS; ++j) {
@@ -937,7 +992,7 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
 // waves, reduction chunk); larger problems use the global-memory kernels
 #define QTT_QR_CONFIGS(X) X(1, 1, 16, 1) X(1, 2, 16, 2) X(2, 2, 16, 2) X(2, 4, 16, 4)
 // one column per 16-lane group: (rows per lane, column slots, waves)
-#define QTT_QRG_CONFIGS(X) X(12, 3, 8) X(16, 4, 8) X(18, 3, 12)
+#define QTT_QRG_CONFIGS(X) X(12, 3, 8) X(16, 4, 8) X(18, 5, 8)
 // larger than the group configurations
 #define QTT_QR_CONFIGS_LARGE(X) X(5, 10, 16, 2)
 #define QTT_EIG_CONFIGS(X) \
