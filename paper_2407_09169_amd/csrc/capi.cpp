@@ -1374,15 +1374,17 @@ tt_status tt_linalg_eigh(tt_ctx* ctx, int count, int n, int keep, const double* 
                 "bad argument");
     const size_t nn = (size_t)n * n;
     DevBuf dG(count * nn * 8), dP(count * (size_t)n * keep * 8), dL(count * (size_t)n * 8),
-        dW(count * 2 * nn * 8), dd(count * sizeof(int)), dk(count * sizeof(int));
+        dW(count * 3 * nn * 8), dd(count * sizeof(int)), dk(count * sizeof(int));
     std::vector<int> dims(count, n), kp(count, keep);
     StreamScope sc(ctx);
     rt::copy(dG.p, G, count * nn * 8);
     rt::copy(dd.p, dims.data(), count * sizeof(int));
     rt::copy(dk.p, kp.data(), count * sizeof(int));
     fill(dP.d(), (int64_t)count * n * keep, 0.0, ctx->stream);
+    const bool pre = eig_uses_precondition(n);
+    if (pre) eig_precondition_launch(count, dd.as<int>(), dG.d(), (int64_t)nn, n, dW.d(), n, ctx->stream);
     eig_launch(count, dd.as<int>(), dk.as<int>(), dG.d(), (int64_t)nn, n, dP.d(), (int64_t)n * keep,
-               keep, dL.d(), n, dW.d(), n, machine_eps(Prec::F64), ctx->stream);
+               keep, dL.d(), n, dW.d(), n, machine_eps(Prec::F64), ctx->stream, pre);
     rt::sync(ctx->stream);
     rt::copy(P, dP.p, count * (size_t)n * keep * 8);
     rt::copy(lam, dL.p, count * (size_t)n * 8);

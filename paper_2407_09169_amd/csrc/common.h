@@ -224,21 +224,38 @@ TcDesc gemm_desc(int M, int N, int K, const double* A, int64_t lda, bool transA,
 // A + i*strideA + r*rs + c*cs).  Writes the thin explicit Q_i (m x n,
 // row-major, ldq = n, at Q + i*strideQ) and, if R != nullptr, R_i (n x n
 // upper triangular, row-major).  `work` must hold count*m*n doubles.
+// With sq != nullptr (m == n required), matrix i is sq[i] x sq[i] (<= m; none
+// when <= 0) and Q_i, R_i have leading dimension sq[i].  `work` is used only
+// when no register configuration fits (qr_kernel_name(m, n) == "qr_kernel").
 void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_t rs, int64_t cs,
                double* Q, int64_t strideQ, double* R, int64_t strideR, double* work,
-               hipStream_t s);
+               hipStream_t s, const int* sq = nullptr);
 
 // Eigen-decomposition of `count` symmetric PSD matrices G_i (n_i x n_i,
 // row-major, ld = ldg, at G + i*strideG); n_i = dims[i] (device array).
 // Writes the eigenvectors of the k_i = keep[i] largest eigenvalues as the
 // columns of P_i (n_i x k_i, row-major, ld = ldp, at P + i*strideP) and all
 // eigenvalues in descending order to lam + i*strideL.  `work` holds
-// count * ldg * ldg doubles.  `unoise` is the relative noise of the entries
+// 3 * count * ldg * ldg doubles.  `unoise` is the relative noise of the entries
 // of G (the machine epsilon of the arithmetic that produced it): couplings
 // below unoise * lambda_max times the column norm are not resolved.
+// With `preconditioned`, `work` must hold what eig_precondition_launch wrote
+// for the same G: the sweeps then start from W = R2^T, V = Q2 instead of
+// W = G, V = I.
 void eig_launch(int count, const int* dims, const int* keep, const double* G, int64_t strideG,
                 int ldg, double* P, int64_t strideP, int ldp, double* lam, int64_t strideL,
-                double* work, int max_n, double unoise, hipStream_t s);
+                double* work, int max_n, double unoise, hipStream_t s, bool preconditioned = false);
+
+// Whether matrices of size <= max_n take the register Jacobi kernel, which can
+// start from a QR factorisation of G.
+bool eig_uses_precondition(int max_n);
+
+// Two QR factorisations, G_i = Q1_i R1_i and R1_i^T = Q2_i R2_i (n_i =
+// dims[i]), into `work` (3 * count * ldg * ldg doubles): Q2_i at
+// work + i*ldg^2, R2_i at work + (2 count + i)*ldg^2, row-major with leading
+// dimension max_n.  Needs eig_uses_precondition(max_n).
+void eig_precondition_launch(int count, const int* dims, const double* G, int64_t strideG, int ldg,
+                             double* work, int max_n, hipStream_t s);
 // machine epsilon of a contraction precision
 inline double machine_eps(Prec p) {
   return p == Prec::F64 ? 2.220446049250313e-16 : (p == Prec::F32 ? 1.1920928955078125e-07 : 7.8125e-03);

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(FT) void qr_kernel(int m, int n, const double* __re
                                                 int64_t strideA, int64_t rs, int64_t cs,
                                                 double* __restrict__ Q0, int64_t strideQ,
                                                 double* __restrict__ R0, int64_t strideR,
-                                                double* __restrict__ work) {
+                                                double* __restrict__ work, const int* __restrict__ sq) {
   __shared__ double red[FW];
   __shared__ double taus[1024];
   __shared__ double betas[1024];
@@ -105,6 +105,11 @@ __global__ __launch_bounds__(FT) void qr_kernel(int m, int n, const double* __re
   const int64_t b = blockIdx.x;
   const double* A = A0 + b * strideA;
   double* W = work + b * (int64_t)m * n;  // column-major, W[c*m + r]
+  const int ldo = n;  // leading dimension of Q and R
+  if (sq != nullptr) {  // per-matrix square size
+    m = n = sq[b];
+    if (n <= 0) return;
+  }
   for (int64_t e = tid; e < (int64_t)m * n; e += FT) {
     int r = (int)(e % m), c = (int)(e / m);
     W[e] = A[r * rs + c * cs];
@@ -153,7 +158,7 @@ __global__ __launch_bounds__(FT) void qr_kernel(int m, int n, const double* __re
       double v = 0.0;
       if (r == c) v = betas[r];
       else if (r < c) v = W[(int64_t)c * m + r];
-      R[e] = v;
+      R[(int64_t)r * ldo + c] = v;
     }
   }
   __syncthreads();
@@ -181,7 +186,7 @@ __global__ __launch_bounds__(FT) void qr_kernel(int m, int n, const double* __re
   double* Q = Q0 + b * strideQ;
   for (int64_t e = tid; e < (int64_t)m * n; e += FT) {
     int r = (int)(e / n), c = (int)(e % n);
-    Q[e] = W[(int64_t)c * m + r];
+    Q[(int64_t)r * ldo + c] = W[(int64_t)c * m + r];
   }
 }
 
@@ -232,7 +237,8 @@ template <int RS, int CPW, int QW, int CH>
 __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const double* __restrict__ A0,
                                                       int64_t strideA, int64_t rs, int64_t cs,
                                                       double* __restrict__ Q0, int64_t strideQ,
-                                                      double* __restrict__ R0, int64_t strideR) {
+                                                      double* __restrict__ R0, int64_t strideR,
+                                                      const int* __restrict__ sq) {
   __shared__ double vbuf[2][64 * RS];
   __shared__ double taus[QW * CPW];
   __shared__ double betas[QW * CPW];
@@ -240,6 +246,11 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t bi = blockIdx.x;
   const double* A = A0 + bi * strideA;
+  const int ldo = n;  // leading dimension of Q and R
+  if (sq != nullptr) {  // per-matrix square size
+    m = n = sq[bi];
+    if (n <= 0) return;
+  }
   double a[RS][CPW];
 #pragma unroll
   for (int j = 0; j < CPW; ++j) {
@@ -313,7 +324,7 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
       for (int i = 0; i < RS; ++i) {
         const int r = lane + 64 * i;
         if (r >= n) continue;
-        R[(int64_t)r * n + c] = (r < c) ? a[i][j] : (r == c ? betas[c] : 0.0);
+        R[(int64_t)r * ldo + c] = (r < c) ? a[i][j] : (r == c ? betas[c] : 0.0);
       }
     }
   }
@@ -354,7 +365,7 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
 #pragma unroll
     for (int i = 0; i < RS; ++i) {
       const int r = lane + 64 * i;
-      if (r < m) Q[(int64_t)r * n + c] = a[i][j];
+      if (r < m) Q[(int64_t)r * ldo + c] = a[i][j];
     }
   }
 }
@@ -430,13 +441,13 @@ __device__ __forceinline__ void grp_reflector(double (&a)[CS][RPL], int k, int g
   double tau = 0.0, beta = x0, scale = 0.0;
   if (sig != 0.0) {
     // beta = -sign(x0) ||x||, u = x0 - beta (no cancellation), v = x / u with
-    // v_k = 1, tau = -u / beta; one division for both
+    // v_k = 1, tau = -u / beta (two divisions: a product u * beta would
+    // leave the range of doubles for columns of norm below ~1e-154)
     const double nrm = sqrt(x0 * x0 + sig);
     beta = x0 >= 0.0 ? -nrm : nrm;
     const double u = x0 - beta;
-    const double q = 1.0 / (u * beta);
-    scale = beta * q;
-    tau = -(u * u) * q;
+    scale = 1.0 / u;
+    tau = -u / beta;
   }
   if (g == go) {
 #pragma unroll
@@ -483,7 +494,8 @@ template <int RPL, int CS, int NW>
 __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const double* __restrict__ A0,
                                                        int64_t strideA, int64_t rs, int64_t cs,
                                                        double* __restrict__ Q0, int64_t strideQ,
-                                                       double* __restrict__ R0, int64_t strideR) {
+                                                       double* __restrict__ R0, int64_t strideR,
+                                                       const int* __restrict__ sq) {
   constexpr int CL = 4 * NW;
   __shared__ double vbuf[2][16 * RPL];
   __shared__ double taus[CL * CS];
@@ -493,6 +505,11 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
   const int g = lane >> 4, li = lane & 15;
   const int64_t bi = blockIdx.x;
   const double* A = A0 + bi * strideA;
+  const int ldo = n;  // leading dimension of Q and R
+  if (sq != nullptr) {  // per-matrix square size
+    m = n = sq[bi];
+    if (n <= 0) return;
+  }
   double a[CS][RPL];
 #pragma unroll
   for (int j = 0; j < CS; ++j) {
@@ -548,7 +565,7 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
       for (int r = 0; r < RPL; ++r) {
         const int row = li + 16 * r;
         if (row >= n) continue;
-        R[(int64_t)row * n + c] = (row < c) ? a[j][r] : (row == c ? betas[c] : 0.0);
+        R[(int64_t)row * ldo + c] = (row < c) ? a[j][r] : (row == c ? betas[c] : 0.0);
       }
     }
   }
@@ -592,7 +609,7 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const int row = li + 16 * r;
-      if (row < m) Q[(int64_t)row * n + c] = a[j][r];
+      if (row < m) Q[(int64_t)row * ldo + c] = a[j][r];
     }
   }
 }
@@ -711,7 +728,10 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
                                                           int64_t strideG, int ldg,
                                                           double* __restrict__ P0, int64_t strideP,
                                                           int ldp, double* __restrict__ L0,
-                                                          int64_t strideL, double unoise) {
+                                                          int64_t strideL, double unoise,
+                                                          const double* __restrict__ Q0,
+                                                          const double* __restrict__ R0,
+                                                          int64_t strideQR, int ldqr) {
   __shared__ double xT[2][NW][2][64 * RS];  // outgoing last top column (W, V) per wave
   __shared__ double xB[2][NW][2][64 * RS];  // outgoing first bottom column (W, V) per wave
   __shared__ int xTid[2][NW], xBid[2][NW];
@@ -730,6 +750,21 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
   const int p0 = w * PPW;
   double wt[PPW][RS], wb[PPW][RS], vt[PPW][RS], vb[PPW][RS];
   int it[PPW], ib[PPW];
+  // Starting point: W = G, V = I; or, given G = Q1 R^T Q^T with Q1, Q
+  // orthogonal and R upper triangular (Q and R passed, n x n, row-major, ld
+  // ldqr), W = R^T and V = Q.  Then W J = U S makes G = (Q1 U) S (Q J)^T an
+  // SVD of G; G being symmetric PSD, the columns of V J = Q J are its
+  // eigenvectors and the column norms of W J its eigenvalues.  The columns
+  // of R^T are graded and far closer to orthogonal than those of G, which
+  // cuts the number of sweeps.
+  const double* Qb = Q0 ? Q0 + bi * strideQR : nullptr;
+  const double* Rb = Q0 ? R0 + bi * strideQR : nullptr;
+  auto w_at = [&](int r, int c) -> double {
+    return Qb ? Rb[(int64_t)c * ldqr + r] : G[(int64_t)r * ldg + c];
+  };
+  auto v_at = [&](int r, int c) -> double {
+    return Qb ? Qb[(int64_t)r * ldqr + c] : (r == c ? 1.0 : 0.0);
+  };
   // initial circle: pair p = (p, 2NP - 1 - p); id n (odd n) is a zero column
 #pragma unroll
   for (int j = 0; j < PPW; ++j) {
@@ -740,10 +775,10 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
     for (int i = 0; i < RS; ++i) {
       const int r = lane + 64 * i;
       const bool okr = r < n;
-      wt[j][i] = (okr && p < NP && it[j] < n) ? G[(int64_t)r * ldg + it[j]] : 0.0;
-      wb[j][i] = (okr && p < NP && ib[j] < n) ? G[(int64_t)r * ldg + ib[j]] : 0.0;
-      vt[j][i] = (r == it[j]) ? 1.0 : 0.0;
-      vb[j][i] = (r == ib[j]) ? 1.0 : 0.0;
+      wt[j][i] = (okr && p < NP && it[j] < n) ? w_at(r, it[j]) : 0.0;
+      wb[j][i] = (okr && p < NP && ib[j] < n) ? w_at(r, ib[j]) : 0.0;
+      vt[j][i] = (okr && p < NP && it[j] < n) ? v_at(r, it[j]) : (r == it[j] ? 1.0 : 0.0);
+      vb[j][i] = (okr && p < NP && ib[j] < n) ? v_at(r, ib[j]) : (r == ib[j] ? 1.0 : 0.0);
     }
   }
   const int rounds = 2 * NP - 1;
@@ -992,7 +1027,7 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
 // waves, reduction chunk); larger problems use the global-memory kernels
 #define QTT_QR_CONFIGS(X) X(1, 1, 16, 1) X(1, 2, 16, 2) X(2, 2, 16, 2) X(2, 4, 16, 4)
 // one column per 16-lane group: (rows per lane, column slots, waves)
-#define QTT_QRG_CONFIGS(X) X(12, 3, 8) X(16, 4, 8) X(18, 5, 8)
+#define QTT_QRG_CONFIGS(X) X(12, 3, 8) X(16, 4, 8) X(9, 5, 8) X(18, 5, 8)
 // larger than the group configurations
 #define QTT_QR_CONFIGS_LARGE(X) X(5, 10, 16, 2)
 #define QTT_EIG_CONFIGS(X) \
@@ -1038,19 +1073,22 @@ std::string eig_kernel_name(int max_n) {
 
 void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_t rs, int64_t cs,
                double* Q, int64_t strideQ, double* R, int64_t strideR, double* work,
-               hipStream_t s) {
+               hipStream_t s, const int* sq) {
   if (count <= 0) return;
   QTT_REQUIRE(m >= n && n >= 1 && n <= 1024, "qr: need m >= n, 1 <= n <= 1024 (m=%d n=%d)", m, n);
+  QTT_REQUIRE(sq == nullptr || m == n, "qr: per-matrix sizes need square matrices");
   rt::check_range(A, 0, (int64_t)(count - 1) * strideA + (int64_t)(m - 1) * rs + (int64_t)(n - 1) * cs,
                   sizeof(double), "qr input");
   rt::check_range(Q, 0, (int64_t)(count - 1) * strideQ + (int64_t)m * n - 1, sizeof(double), "qr Q");
   if (R) rt::check_range(R, 0, (int64_t)(count - 1) * strideR + (int64_t)n * n - 1, sizeof(double), "qr R");
-  rt::check_range(work, 0, (int64_t)count * m * n - 1, sizeof(double), "qr workspace");
+  if (sq) rt::check_range(sq, 0, count - 1, sizeof(int), "qr sizes");
+  const bool generic = qr_kernel_name(m, n) == "qr_kernel";
+  if (generic) rt::check_range(work, 0, (int64_t)count * m * n - 1, sizeof(double), "qr workspace");
   if (rt::dry()) return;
 #define QTT_QR_REG(RS_, CPW_, NW_, CH_)                                                           \
   if (m <= 64 * RS_ && n <= NW_ * CPW_) {                                                         \
     hipLaunchKernelGGL((qr_reg_kernel<RS_, CPW_, NW_, CH_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
-                       strideA, rs, cs, Q, strideQ, R, strideR);                                 \
+                       strideA, rs, cs, Q, strideQ, R, strideR, sq);                             \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }
@@ -1059,7 +1097,7 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
 #define QTT_QR_GRP(RPL_, CS_, NW_)                                                                \
   if (m <= 16 * RPL_ && n <= 4 * NW_ * CS_) {                                                     \
     hipLaunchKernelGGL((qr_grp_kernel<RPL_, CS_, NW_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
-                       strideA, rs, cs, Q, strideQ, R, strideR);                                 \
+                       strideA, rs, cs, Q, strideQ, R, strideR, sq);                             \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }
@@ -1068,20 +1106,45 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
 #define QTT_QR_REG(RS_, CPW_, NW_, CH_)                                                           \
   if (m <= 64 * RS_ && n <= NW_ * CPW_) {                                                         \
     hipLaunchKernelGGL((qr_reg_kernel<RS_, CPW_, NW_, CH_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
-                       strideA, rs, cs, Q, strideQ, R, strideR);                                 \
+                       strideA, rs, cs, Q, strideQ, R, strideR, sq);                             \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }
   QTT_QR_CONFIGS_LARGE(QTT_QR_REG)
 #undef QTT_QR_REG
   hipLaunchKernelGGL(qr_kernel, dim3(count), dim3(FT), 0, s, m, n, A, strideA, rs, cs, Q, strideQ,
-                     R, strideR, work);
+                     R, strideR, work, sq);
   QTT_HIP(hipGetLastError());
+}
+
+bool eig_uses_precondition(int max_n) {
+#define QTT_EIG_FITS(RS_, PPW_, NW_, CH_) \
+  if (max_n <= 64 * RS_ && max_n <= 2 * NW_ * PPW_) return true;
+  QTT_EIG_CONFIGS(QTT_EIG_FITS)
+#undef QTT_EIG_FITS
+  return false;
+}
+
+void eig_precondition_launch(int count, const int* dims, const double* G, int64_t strideG, int ldg,
+                             double* work, int max_n, hipStream_t s) {
+  if (count <= 0) return;
+  QTT_REQUIRE(eig_uses_precondition(max_n), "eig: no preconditioned configuration for n = %d", max_n);
+  QTT_REQUIRE(max_n <= ldg, "eig: n <= ldg");
+  const int64_t st = (int64_t)ldg * ldg;
+  rt::check_range(work, 0, (int64_t)count * 3 * st - 1, sizeof(double), "eig workspace");
+  double* Q = work;
+  double* R1 = work + count * st;
+  double* R2 = work + 2 * count * st;
+  // G = Q1 R1 and R1^T = Q2 R2 give G = Q1 R2^T Q2^T: the sweeps run on
+  // W = R2^T from V = Q2 (Q2 overwrites Q1, which is not needed).  Two
+  // factorisations leave the columns closer to orthogonal than one.
+  qr_launch(count, max_n, max_n, G, strideG, ldg, 1, Q, st, R1, st, nullptr, s, dims);
+  qr_launch(count, max_n, max_n, R1, st, 1, max_n, Q, st, R2, st, nullptr, s, dims);
 }
 
 void eig_launch(int count, const int* dims, const int* keep, const double* G, int64_t strideG,
                 int ldg, double* P, int64_t strideP, int ldp, double* lam, int64_t strideL,
-                double* work, int max_n, double unoise, hipStream_t s) {
+                double* work, int max_n, double unoise, hipStream_t s, bool preconditioned) {
   if (count <= 0) return;
   QTT_REQUIRE(max_n <= 1024 && max_n <= ldg, "eig: n <= 1024 and n <= ldg");
   rt::check_range(dims, 0, count - 1, sizeof(int), "eig dims");
@@ -1091,12 +1154,17 @@ void eig_launch(int count, const int* dims, const int* keep, const double* G, in
   rt::check_range(P, 0, (int64_t)(count - 1) * strideP + (int64_t)(max_n - 1) * ldp + ldp - 1,
                   sizeof(double), "eig vectors");
   rt::check_range(lam, 0, (int64_t)(count - 1) * strideL + max_n - 1, sizeof(double), "eig values");
-  rt::check_range(work, 0, (int64_t)count * 2 * ldg * ldg - 1, sizeof(double), "eig workspace");
+  rt::check_range(work, 0, (int64_t)count * 3 * ldg * ldg - 1, sizeof(double), "eig workspace");
+  QTT_REQUIRE(!preconditioned || eig_uses_precondition(max_n), "eig: no preconditioned configuration");
   if (rt::dry()) return;
+  const int64_t st = (int64_t)ldg * ldg;
+  const double* Qf = preconditioned ? work : nullptr;
+  const double* Rf = preconditioned ? work + 2 * count * st : nullptr;
 #define QTT_EIG_REG(RS_, PPW_, NW_, CH_)                                                          \
   if (max_n <= 64 * RS_ && max_n <= 2 * NW_ * PPW_) {                                            \
     hipLaunchKernelGGL((eig_reg_kernel<RS_, PPW_, NW_, CH_>), dim3(count), dim3(NW_ * 64), 0, s,  \
-                       dims, keep, G, strideG, ldg, P, strideP, ldp, lam, strideL, unoise);      \
+                       dims, keep, G, strideG, ldg, P, strideP, ldp, lam, strideL, unoise, Qf, Rf, \
+                       st, max_n);                                                               \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }

@@ -323,7 +323,7 @@ static void plan_trunc_gram_mixed(Plan& plan, const std::vector<double*>& X, con
   double* Gam = plan.alloc((size_t)(N + 1) * ldg * ldg);
   double* P = plan.alloc((size_t)(N + 1) * ldg * ldp);
   double* lam = plan.alloc((size_t)(N + 1) * ldg);
-  double* ework = plan.alloc((size_t)std::max(1, N - 1) * 2 * ldg * ldg);
+  double* ework = plan.alloc((size_t)std::max(1, N - 1) * 3 * ldg * ldg);
   size_t tsz = 1, vsz = 1;
   for (int n = 0; n < N; ++n) {
     tsz = std::max(tsz, (size_t)2 * ell[n] * ell[n + 1]);
@@ -393,6 +393,22 @@ static void plan_trunc_gram_mixed(Plan& plan, const std::vector<double*>& X, con
     double* p1 = Pn(1);
     double* l1 = lam + ldg;
     const int cnt = N - 1;
+    const bool pre = eig_uses_precondition(lmax);
+    if (pre) {
+      // QR factors of every Gram matrix: the Jacobi sweeps start from R^T
+      OpInfo qi;
+      qi.kind = OP_QR;
+      qi.what = qr_kernel_name(lmax, lmax) + "|eig precondition count" + std::to_string(cnt) + " n" +
+                std::to_string(lmax);
+      for (int n = 1; n < N; ++n) {
+        const OpInfo one = qr_info(ell[n], ell[n]);
+        qi.flops += one.flops;
+        qi.bytes += one.bytes + 8.0 * (double)ell[n] * ell[n];  // G in, Q and R out
+      }
+      plan.add([=](hipStream_t s) {
+        eig_precondition_launch(cnt, d_dims, g1, (int64_t)ldg * ldg, ldg, ework, lmax, s);
+      }, qi);
+    }
     OpInfo oi;
     oi.kind = OP_EIG;
     oi.what = eig_kernel_name(lmax) + "|count" + std::to_string(cnt) + " nmax" + std::to_string(lmax);
@@ -402,7 +418,7 @@ static void plan_trunc_gram_mixed(Plan& plan, const std::vector<double*>& X, con
     }
     plan.add([=](hipStream_t s) {
       eig_launch(cnt, d_dims, d_keep, g1, (int64_t)ldg * ldg, ldg, p1, (int64_t)ldg * ldp, ldp, l1, ldg,
-                 ework, lmax, unoise, s);
+                 ework, lmax, unoise, s, pre);
     }, oi);
   }
   // new cores P_n^T A_n P_(n+1)
