@@ -373,13 +373,17 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
 // ---------------------------------------------------------------------------
 // Householder QR with one column per 16-lane group (a DPP row): for
 // m <= 16*RPL, n <= 4*NW*CS.  Lane li of group g of wavefront w holds rows
-// li + 16 r (r < RPL) of the columns c = 32 j + 4 w + g ... more precisely
-// c = (4 NW) j + 4 w + g for slots j < CS.  A column dot product is a sum over
-// the 16 lanes of a group: four row-local DPP steps reduce the four columns
-// of a wavefront at once and leave each sum in every lane of its group.
-// Step k: the owner group builds the reflector, publishes v (double-buffered
-// LDS); one barrier; every group applies it to its columns c > k.  Q is
-// formed in place by backward accumulation.
+// li + 16 r (r < RPL) of the columns c = (4 NW) j + 4 w + g, slots j < CS.  A
+// column dot product is a sum over the 16 lanes of a group: four row-local
+// DPP steps reduce the four columns of a wavefront at once and leave each
+// sum in every lane of its group.  The columns of slot j form phase j; the
+// slot index is a compile-time constant inside each phase, and the row
+// chunks above the phase's first column (where every reflector vanishes)
+// are skipped.  Factorisation, step k: one barrier, every group applies H_k
+// to its columns c > k, the owner of column k+1 first to that column, then
+// builds and publishes v_(k+1) before its other columns (look-ahead).  Thin
+// Q by backward accumulation, phase by phase: the phase's stored reflectors
+// are published at once and applied with no barrier in between.
 // ---------------------------------------------------------------------------
 template <int CTRL>
 __device__ inline double dpp_row(double x) {  // every row lane valid: no old value
@@ -400,8 +404,8 @@ __device__ inline double row_sum(double v) {
 
 // a[:, c] -= t (v^T a[:, c]) v for this lane's columns c with k < c < n, in
 // the slots J0 <= j < CS with (ONLY < 0 || j == ONLY) && j != SKIP.  Slots
-// below J0 hold only columns <= k.
-template <int RPL, int CS, int NW, int J0, int ONLY = -1, int SKIP = -1>
+// below J0 hold only columns <= k; v vanishes in the row chunks r < R0.
+template <int RPL, int CS, int NW, int R0, int J0, int ONLY = -1, int SKIP = -1>
 __device__ __forceinline__ void grp_apply(double (&a)[CS][RPL], const double (&v)[RPL], double t, int k,
                                           int n, int w, int g) {
   constexpr int CL = 4 * NW;
@@ -412,24 +416,31 @@ __device__ __forceinline__ void grp_apply(double (&a)[CS][RPL], const double (&v
     if (CL * j + 4 * w >= n) break;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};  // four short chains instead of one long one
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) acc[r & 3] = fma(v[r], a[j][r], acc[r & 3]);
+    for (int r = R0; r < RPL; ++r) acc[r & 3] = fma(v[r], a[j][r], acc[r & 3]);
     const double d = row_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
     const int c = CL * j + 4 * w + g;
     const double wgt = (c > k && c < n) ? t * d : 0.0;
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) a[j][r] = fma(-wgt, v[r], a[j][r]);
+    for (int r = R0; r < RPL; ++r) a[j][r] = fma(-wgt, v[r], a[j][r]);
   }
+}
+
+// first row chunk (16 rows) in which a reflector v_k with k >= CL*JO can be
+// nonzero: every row of the chunks below lies above the diagonal
+template <int CL, int JO, int RPL>
+constexpr int grp_r0() {
+  return (CL * JO) / 16 < RPL ? (CL * JO) / 16 : RPL;
 }
 
 // Owner wavefront of column k (slot JO, group go): builds the reflector
 // H_k = I - tau v v^T from the column in place, stores v below the diagonal,
 // publishes v (vb) and tau / beta.  Called by the whole wavefront.
-template <int RPL, int CS, int JO>
+template <int RPL, int CS, int JO, int R0>
 __device__ __forceinline__ void grp_reflector(double (&a)[CS][RPL], int k, int go, int g, int li, double* vb,
                                               double* taus, double* betas) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0}, xk = 0.0;
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) {
+  for (int r = R0; r < RPL; ++r) {
     const int row = li + 16 * r;
     const double x = row > k ? a[JO][r] : 0.0;
     acc[r & 3] = fma(x, x, acc[r & 3]);
@@ -451,7 +462,7 @@ __device__ __forceinline__ void grp_reflector(double (&a)[CS][RPL], int k, int g
   }
   if (g == go) {
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
+    for (int r = R0; r < RPL; ++r) {
       const int row = li + 16 * r;
       const double vv = (row > k) ? a[JO][r] * scale : (row == k ? 1.0 : 0.0);
       vb[row] = vv;
@@ -461,16 +472,6 @@ __device__ __forceinline__ void grp_reflector(double (&a)[CS][RPL], int k, int g
       taus[k] = tau;
       betas[k] = beta;
     }
-  }
-}
-
-// Owner of column k (slot JO) in the backward pass: publishes the stored v_k.
-template <int RPL, int CS, int JO>
-__device__ __forceinline__ void grp_publish(const double (&a)[CS][RPL], int k, int li, double* vb) {
-#pragma unroll
-  for (int r = 0; r < RPL; ++r) {
-    const int row = li + 16 * r;
-    vb[row] = (row > k) ? a[JO][r] : (row == k ? 1.0 : 0.0);
   }
 }
 
@@ -498,6 +499,7 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
                                                        const int* __restrict__ sq) {
   constexpr int CL = 4 * NW;
   __shared__ double vbuf[2][16 * RPL];
+  __shared__ double vall[CL][16 * RPL];
   __shared__ double taus[CL * CS];
   __shared__ double betas[CL * CS];
   const int lane = threadIdx.x & 63;
@@ -525,32 +527,36 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
   // ---- factorisation, one phase per slot (columns JO*CL .. JO*CL+CL-1), with
   // look-ahead: the owner of column k+1 applies H_k to that column first and
   // publishes v_(k+1) before updating its other columns
-  if (w == 0) grp_reflector<RPL, CS, 0>(a, 0, 0, g, li, vbuf[0], taus, betas);
+  if (w == 0) grp_reflector<RPL, CS, 0, 0>(a, 0, 0, g, li, vbuf[0], taus, betas);
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) v[r] = 0.0;
   static_for<0, CS>([&](auto J) {
     constexpr int JO = decltype(J)::value;
+    constexpr int R0 = grp_r0<CL, JO, RPL>();
+    constexpr int R1 = grp_r0<CL, JO + 1, RPL>();
     const int kend = min(n, CL * (JO + 1));
     for (int k = CL * JO; k < kend; ++k) {
       __syncthreads();  // v_k, tau_k visible
       const double t = taus[k];
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) v[r] = vbuf[k & 1][li + 16 * r];
+      for (int r = R0; r < RPL; ++r) v[r] = vbuf[k & 1][li + 16 * r];
       const int k1 = k + 1;
       const bool own = k1 < n && w == wo_of(k1);  // wave-uniform
       // the owner's chain up to publishing v_(k+1) gates the next step: it
       // runs at raised wave priority
       if (own) __builtin_amdgcn_s_setprio(2);
-      if (t != 0.0) grp_apply<RPL, CS, NW, JO, JO>(a, v, t, k, n, w, g);
+      if (t != 0.0) grp_apply<RPL, CS, NW, R0, JO, JO>(a, v, t, k, n, w, g);
       if (own && k1 < CL * (JO + 1)) {
-        grp_reflector<RPL, CS, JO>(a, k1, k1 & 3, g, li, vbuf[k1 & 1], taus, betas);
+        grp_reflector<RPL, CS, JO, R0>(a, k1, k1 & 3, g, li, vbuf[k1 & 1], taus, betas);
         __builtin_amdgcn_s_setprio(0);
       }
       if constexpr (JO + 1 < CS) {
-        if (t != 0.0) grp_apply<RPL, CS, NW, JO + 1, JO + 1>(a, v, t, k, n, w, g);
+        if (t != 0.0) grp_apply<RPL, CS, NW, R0, JO + 1, JO + 1>(a, v, t, k, n, w, g);
         if (own && k1 == CL * (JO + 1)) {
-          grp_reflector<RPL, CS, JO + 1>(a, k1, k1 & 3, g, li, vbuf[k1 & 1], taus, betas);
+          grp_reflector<RPL, CS, JO + 1, R1>(a, k1, k1 & 3, g, li, vbuf[k1 & 1], taus, betas);
           __builtin_amdgcn_s_setprio(0);
         }
-        if (t != 0.0) grp_apply<RPL, CS, NW, JO + 2>(a, v, t, k, n, w, g);
+        if (t != 0.0) grp_apply<RPL, CS, NW, R0, JO + 2>(a, v, t, k, n, w, g);
       }
     }
   });
@@ -569,34 +575,38 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
       }
     }
   }
-  // ---- thin Q by backward accumulation, slot phases in reverse; v_(k-1) is
-  // published while H_k is being applied (the stored reflectors no longer
-  // change)
-  static_for<0, CS>([&](auto J) {
-    constexpr int JO = decltype(J)::value;
-    const int kl = n - 1;
-    if (kl / CL == JO && w == wo_of(kl) && g == (kl & 3)) grp_publish<RPL, CS, JO>(a, kl, li, vbuf[kl & 1]);
-  });
+  // ---- thin Q by backward accumulation, one slot phase at a time (in
+  // reverse): the reflectors of the phase's CL columns are published together,
+  // then every wavefront applies them, last to first, to its own columns with
+  // no barrier in between (the owner of column k resets it to H_k e_k when its
+  // turn comes; nothing else touches it)
   static_for<0, CS, true>([&](auto J) {
     constexpr int JO = decltype(J)::value;
-    for (int k = min(n, CL * (JO + 1)) - 1; k >= CL * JO; --k) {
-      __syncthreads();  // v_k visible
+    constexpr int R0 = grp_r0<CL, JO, RPL>();
+    const int kb = CL * JO, ke = min(n, CL * (JO + 1));
+    if (kb >= ke) return;  // block-uniform
+    __syncthreads();  // the previous phase has finished reading vall
+    {
+      const int k = kb + 4 * w + g;  // this lane's column in slot JO
+      if (k < ke) {
+#pragma unroll
+        for (int r = R0; r < RPL; ++r) {
+          const int row = li + 16 * r;
+          vall[k - kb][row] = (row > k) ? a[JO][r] : (row == k ? 1.0 : 0.0);
+        }
+      }
+    }
+    __syncthreads();
+    for (int k = ke - 1; k >= kb; --k) {
       const double t = taus[k];
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) v[r] = vbuf[k & 1][li + 16 * r];
-      const int km = k - 1;
-      if (km >= 0 && w == wo_of(km) && g == (km & 3)) {
-        if (km >= CL * JO)
-          grp_publish<RPL, CS, JO>(a, km, li, vbuf[km & 1]);
-        else if constexpr (JO > 0)
-          grp_publish<RPL, CS, JO - 1>(a, km, li, vbuf[km & 1]);
-      }
-      if (t != 0.0) grp_apply<RPL, CS, NW, JO>(a, v, t, k, n, w, g);
+      for (int r = R0; r < RPL; ++r) v[r] = vall[k - kb][li + 16 * r];
+      if (t != 0.0) grp_apply<RPL, CS, NW, R0, JO>(a, v, t, k, n, w, g);
       if (w == wo_of(k) && g == (k & 3)) {
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
           const int row = li + 16 * r;
-          a[JO][r] = (row < k) ? 0.0 : (row == k ? 1.0 - t : -t * v[r]);
+          a[JO][r] = (r < R0 || row < k) ? 0.0 : (row == k ? 1.0 - t : -t * v[r]);
         }
       }
     }

@@ -422,8 +422,15 @@ static void plan_trunc_gram_mixed(Plan& plan, const std::vector<double*>& X, con
     }, oi);
   }
   // new cores P_n^T A_n P_(n+1)
+  // the cores are independent: spread over lanes, each with its own V1
+  const int Lc = (plan.cur == 0 && !plan.no_lanes && lanes > 1) ? std::min(4, N) : 1;
+  std::vector<double*> V1s(Lc, V1);
+  for (int q = 1; q < Lc; ++q) V1s[q] = plan.alloc(vsz);
+  plan.fork(Lc);
   for (int n = 0; n < N; ++n) {
     const int l = ell[n], lp = ell[n + 1], cl = tg.caps[n], cr = tg.caps[n + 1];
+    if (Lc > 1) plan.on(n % Lc);
+    double* V1 = V1s[n % Lc];
     if (n <= c) {
       const double* A = (n == c) ? Gc : X[n];  // [l][2][lp]
       if (n == 0 && N == 1) {
@@ -461,6 +468,7 @@ static void plan_trunc_gram_mixed(Plan& plan, const std::vector<double*>& X, con
                  Prec::F64);
     }
   }
+  plan.join(Lc);
 }
 
 void plan_round_sketch_two_sided(Plan& plan, const std::vector<SketchTerm>& terms, const ChainView& Zr,
