@@ -73,7 +73,8 @@ def _traffic(kernel, shape):
 
 def _op_log(prob, f):
     """One eager step with a pair of HIP events around every launch, on the
-    library's stream; returns [(index, class, ms, flops, bytes, description)]."""
+    stream of its lane; returns [(index, class, ms, flops, bytes, description,
+    lane)], lane fork / join events included (class -2, no time)."""
     import tempfile
     fd, path = tempfile.mkstemp(suffix=".txt")
     os.close(fd)
@@ -84,8 +85,8 @@ def _op_log(prob, f):
         del os.environ["QTTPDF_PROFILE_LOG"]
     rows = []
     for line in open(path):
-        i, k, ms, fl, by, what = line.rstrip("\n").split("\t")
-        rows.append((int(i), int(k), float(ms), float(fl), float(by), what))
+        i, k, ms, fl, by, what, lane = line.rstrip("\n").split("\t")
+        rows.append((int(i), int(k), float(ms), float(fl), float(by), what, int(lane)))
     os.unlink(path)
     return rows
 
@@ -95,7 +96,7 @@ def _roofline(rows):
     most event time in one step; achieved = its algorithmic flops (bytes) per
     launch / its average launch duration."""
     groups = {}
-    for _, k, ms, fl, by, what in rows:
+    for _, k, ms, fl, by, what, _lane in rows:
         if k < 0:  # copies, fills and lane events are not kernels of the method
             continue
         g = groups.setdefault(what, [0, 0.0, 0.0, 0.0])
@@ -129,7 +130,9 @@ def _roofline(rows):
 def _classes(rows):
     names = {0: "contract", 1: "qr", 2: "eig", 3: "stream", -1: "other"}
     out = {}
-    for _, k, ms, fl, by, _w in rows:
+    for _, k, ms, fl, by, _w, _lane in rows:
+        if k == -2:  # lane fork / join
+            continue
         c = out.setdefault(names.get(k, "other"), {"ms": 0.0, "launches": 0, "flops": 0.0, "bytes": 0.0})
         c["ms"] += ms
         c["launches"] += 1

@@ -288,7 +288,11 @@ tt_status tt_step_tangent(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_params,
  * their algorithmic flops and bytes (operands read once, results written
  * once).  With the environment variable QTTPDF_PROFILE_LOG naming a file,
  * one line per timed launch (plan index, class, ms, flops, bytes,
- * kernel|shape; tab separated) is appended to it.  f is advanced. */
+ * kernel|shape, lane; tab separated) is appended to it, and one per lane
+ * fork or join event (class -2, ms 0, "lane fork record" on lane 0 then
+ * "lane fork wait" on each forked lane; "lane join record" on a lane then
+ * "lane join wait" on lane 0), in plan order: the lanes' ordering can be
+ * rebuilt from it.  f is advanced. */
 tt_status tt_profile(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps, int kernel, double* ms,
                      int64_t* launches, double* flops, double* bytes);
 

@@ -251,9 +251,10 @@ static void plan_mean_round(Plan& plan, tt_problem* P, const std::vector<MeanTer
                             tt_tt* const mt[2]) {
   ChainView Zm = view(P->Zm.get());
   ChainView Zml = view(P->Zml.get());
-  plan.fork(2);  // the two mean fields on two lanes
+  const int La = lane_budget(plan, 2);
+  plan.fork(La);  // the two mean fields on two lanes
   for (int a = 0; a < 2; ++a) {
-    if (!plan.no_lanes) plan.on(a);
+    if (La > 1) plan.on(a);
     std::vector<SketchTerm> st;
     for (const MeanTerm& m : terms) {
       SketchTerm t;
@@ -266,7 +267,7 @@ static void plan_mean_round(Plan& plan, tt_problem* P, const std::vector<MeanTer
     tg.caps = mt[a]->caps;
     plan_round_sketch_two_sided(plan, st, Zm, Zml, tg, Prec::F64, 1);
   }
-  plan.join(2);
+  plan.join(La);
 }
 
 // 5-D: writes diag(mt[a]) into the x-site mean-field blocks of a stage-shaped

@@ -69,6 +69,11 @@ struct OpInfo {
 // lane 0 has enqueued so far; join(n) makes lane 0 wait for lanes 1..n-1.
 // A plan ends joined, so a replay (eager or captured into a HIP graph) is
 // ordered with the caller's stream at both ends.
+//
+// Every fork starts from lane 0 and every join ends on it: under HIP graph
+// capture, a lane other than the capturing stream may neither record an
+// event that another such lane waits for nor wait for one recorded there
+// (this host runtime fails at capture time on that pattern).
 struct Plan {
   std::vector<std::function<void(hipStream_t)>> ops;
   std::vector<OpInfo> info;
@@ -76,7 +81,7 @@ struct Plan {
   std::vector<std::unique_ptr<DevBuf>> bufs;
   std::vector<hipStream_t> streams;  // lanes 1..
   std::vector<hipEvent_t> events;
-  int cur = 0;
+  int cur = 0;  // lane of the next op
   bool no_lanes = false;  // record every op on lane 0 (fork / join record nothing)
   Plan() = default;
   Plan(const Plan&) = delete;
@@ -121,6 +126,13 @@ struct Plan {
   hipEvent_t new_event();
   void ensure_lanes(int n);
 };
+
+// lanes a planner may fork into (at most `want`): 1 unless it records on
+// lane 0 of a plan with lanes
+inline int lane_budget(const Plan& plan, int want) {
+  if (plan.cur != 0 || plan.no_lanes) return 1;
+  return std::max(1, want);
+}
 
 struct SketchTerm {
   double coef = 1.0;

@@ -119,18 +119,19 @@ void Plan::fork(int n) {
   if (n <= 1 || no_lanes) return;  // single lane: nothing to order
   QTT_REQUIRE(cur == 0, "fork from lane 0 only");
   ensure_lanes(n);
-  OpInfo sync;
-  sync.kind = OP_SYNC;
-  sync.what = "lane fork";
+  OpInfo rec, wait;
+  rec.kind = wait.kind = OP_SYNC;
+  rec.what = "lane fork record";
+  wait.what = "lane fork wait";
   hipEvent_t e = new_event();
   add([e](hipStream_t s) {
     if (!rt::dry()) QTT_HIP(hipEventRecord(e, s));
-  }, sync);
+  }, rec);
   for (int l = 1; l < n; ++l) {
     cur = l;
     add([e](hipStream_t s) {
       if (!rt::dry()) QTT_HIP(hipStreamWaitEvent(s, e, 0));
-    }, sync);
+    }, wait);
   }
   cur = 0;
 }
@@ -138,19 +139,20 @@ void Plan::fork(int n) {
 void Plan::join(int n) {
   if (n <= 1 || no_lanes) return;
   QTT_REQUIRE(cur < n, "join of lanes that were not forked");
-  OpInfo sync;
-  sync.kind = OP_SYNC;
-  sync.what = "lane join";
+  OpInfo rec, wait;
+  rec.kind = wait.kind = OP_SYNC;
+  rec.what = "lane join record";
+  wait.what = "lane join wait";
   for (int l = 1; l < n; ++l) {
     hipEvent_t e = new_event();
     cur = l;
     add([e](hipStream_t s) {
       if (!rt::dry()) QTT_HIP(hipEventRecord(e, s));
-    }, sync);
+    }, rec);
     cur = 0;
     add([e](hipStream_t s) {
       if (!rt::dry()) QTT_HIP(hipStreamWaitEvent(s, e, 0));
-    }, sync);
+    }, wait);
   }
   cur = 0;
 }
@@ -178,16 +180,24 @@ void Plan::run_profiled(hipStream_t s, int kind, double& ms, int64_t& count, dou
     }
   }
   rt::sync(s);
+  // log: one line per operation in plan order (index, class, ms, flops,
+  // bytes, description, lane); lane fork / join events appear with class
+  // OP_SYNC so that the lanes' ordering can be reconstructed
   const char* logp = std::getenv("QTTPDF_PROFILE_LOG");
   FILE* log = logp ? std::fopen(logp, "a") : nullptr;
-  for (size_t k = 0; k < idx.size(); ++k) {
+  size_t k = 0;
+  for (size_t i = 0; i < ops.size(); ++i) {
+    const OpInfo& oi = info[i];
+    const bool tim = (k < idx.size() && idx[k] == i);
     float t = 0.f;
-    if (!rt::dry()) QTT_HIP(hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]));
-    ms += t;
-    const OpInfo& oi = info[idx[k]];
-    if (log)
-      std::fprintf(log, "%zu\t%d\t%.6f\t%.6g\t%.6g\t%s\n", idx[k], oi.kind, (double)t, oi.flops,
-                   oi.bytes, oi.what.empty() ? "-" : oi.what.c_str());
+    if (tim) {
+      if (!rt::dry()) QTT_HIP(hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]));
+      ms += t;
+      ++k;
+    }
+    if (log && (tim || oi.kind == OP_SYNC))
+      std::fprintf(log, "%zu\t%d\t%.6f\t%.6g\t%.6g\t%s\t%d\n", i, oi.kind, (double)t, oi.flops,
+                   oi.bytes, oi.what.empty() ? "-" : oi.what.c_str(), lane[i]);
   }
   if (log) std::fclose(log);
   if (!rt::dry())
@@ -321,7 +331,7 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
   const int N = Z.N;
   const int J = (int)terms.size();
   // the terms' independent contraction chains are spread over L lanes
-  const int L = (plan.cur == 0 && !plan.no_lanes) ? std::max(1, std::min(lanes, J)) : 1;
+  const int L = lane_budget(plan, std::min(lanes, J));
   QTT_REQUIRE(J >= 1, "rounding needs at least one term");
   const std::vector<int>& ell = Z.caps;
   for (int n = 0; n < N; ++n)

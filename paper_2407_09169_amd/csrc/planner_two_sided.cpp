@@ -348,7 +348,7 @@ static void plan_trunc_gram_mixed(Plan& plan, const std::vector<double*>& X, con
   });
   auto G = [&](int n) { return Gam + (size_t)n * ldg * ldg; };
   auto Pn = [&](int n) { return P + (size_t)n * ldg * ldp; };
-  const int L = (plan.cur == 0 && !plan.no_lanes && lanes > 1) ? 2 : 1;
+  const int L = lane_budget(plan, std::min(lanes, 2));
   plan.fork(L);
   // right Gram chain, bonds c..1 (left of the centre)
   if (c >= 1) {
@@ -423,7 +423,7 @@ static void plan_trunc_gram_mixed(Plan& plan, const std::vector<double*>& X, con
   }
   // new cores P_n^T A_n P_(n+1)
   // the cores are independent: spread over lanes, each with its own V1
-  const int Lc = (plan.cur == 0 && !plan.no_lanes && lanes > 1) ? std::min(4, N) : 1;
+  const int Lc = lane_budget(plan, std::min({lanes, 4, N}));
   std::vector<double*> V1s(Lc, V1);
   for (int q = 1; q < Lc; ++q) V1s[q] = plan.alloc(vsz);
   plan.fork(Lc);
@@ -513,7 +513,7 @@ void plan_round_sketch_two_sided(Plan& plan, const std::vector<SketchTerm>& term
       crsz = std::max(crsz, rn * Dn * 2 * lp);
       ssz = std::max(ssz, 2 * l * lp);
     }
-  const int Ls = lanes_ok ? std::max(1, std::min(lanes, 2 * J)) : 1;
+  const int Ls = lanes_ok ? lane_budget(plan, std::min(lanes, 2 * J)) : 1;
   std::vector<double*> T1s(Ls), T2s(Ls);
   for (int l = 0; l < Ls; ++l) {
     T1s[l] = plan.alloc(t1);
@@ -564,7 +564,7 @@ void plan_round_sketch_two_sided(Plan& plan, const std::vector<SketchTerm>& term
   plan.join(Ls);
 
   // ---- the two sweeps, on two lanes
-  const int Lw = lanes_ok ? 2 : 1;
+  const int Lw = lanes_ok ? lane_budget(plan, std::min(lanes, 2)) : 1;
   plan.fork(Lw);
   std::vector<double*> Mcur(J, one), Mnext = Mb;
   for (int n = 0; n < c; ++n) {  // left sweep, sites 0..c-1
