@@ -246,28 +246,27 @@ struct MeanTerm {
   const double* first;
 };
 
-// 5-D: rounds sum_j c_j <Phi_a>(x_j) to chi_mean into mt[a], a = 0, 1
+// 5-D: rounds sum_j c_j <Phi_a>(x_j) to chi_mean into mt[a], a = 0, 1 (the
+// two roundings recorded side by side, sharing the lanes)
 static void plan_mean_round(Plan& plan, tt_problem* P, const std::vector<MeanTerm>& terms,
                             tt_tt* const mt[2]) {
   ChainView Zm = view(P->Zm.get());
   ChainView Zml = view(P->Zml.get());
-  const int La = lane_budget(plan, 2);
-  plan.fork(La);  // the two mean fields on two lanes
+  std::vector<SketchTerm> st[2];
+  RoundTarget tg[2];
+  std::vector<RoundJob> jobs;
   for (int a = 0; a < 2; ++a) {
-    if (La > 1) plan.on(a);
-    std::vector<SketchTerm> st;
     for (const MeanTerm& m : terms) {
       SketchTerm t;
       t.coef = m.c;
       t.x = mean_view(P, m.x, m.first, a);
-      st.push_back(t);
+      st[a].push_back(t);
     }
-    RoundTarget tg;
-    for (int j = 0; j < P->nx; ++j) tg.core.push_back(mt[a]->core(j));
-    tg.caps = mt[a]->caps;
-    plan_round_sketch_two_sided(plan, st, Zm, Zml, tg, Prec::F64, 1);
+    for (int j = 0; j < P->nx; ++j) tg[a].core.push_back(mt[a]->core(j));
+    tg[a].caps = mt[a]->caps;
+    jobs.push_back({&st[a], &tg[a]});
   }
-  plan.join(La);
+  plan_round_two_sided_multi(plan, jobs, Zm, Zml, Prec::F64, 4);
 }
 
 // 5-D: writes diag(mt[a]) into the x-site mean-field blocks of a stage-shaped

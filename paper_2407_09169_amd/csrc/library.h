@@ -159,6 +159,15 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
 // sweep), then simultaneous truncation of the mixed canonical form
 void plan_round_sketch_two_sided(Plan& plan, const std::vector<SketchTerm>& terms, const ChainView& Zr,
                                  const ChainView& Zl, RoundTarget& target, Prec prec, int lanes = 4);
+
+// Several independent two-sided roundings with the same sketches, recorded
+// phase by phase side by side so that their work shares the lanes.
+struct RoundJob {
+  const std::vector<SketchTerm>* terms;
+  RoundTarget* tg;
+};
+void plan_round_two_sided_multi(Plan& plan, const std::vector<RoundJob>& jobs, const ChainView& Zr,
+                                const ChainView& Zl, Prec prec, int lanes = 4);
 // planner building blocks shared by the rounding planners
 void add_tc(Plan& plan, TcDesc d, Prec p);
 void add_gemm(Plan& plan, int M, int N, int K, const double* A, int64_t lda, bool ta, const double* B,

@@ -300,211 +300,61 @@ void add_rcore(Plan& plan, const SketchTerm& t, const Shape& sh, int n, int lp, 
   }
 }
 
-}  // namespace
+// ---------------------------------------------------------------------------
+// One rounding while its phases are recorded.  Several independent roundings
+// (same sketches, e.g. the two mean compositions) are recorded phase by phase
+// side by side, their work items spread over the lanes; every phase forks
+// from lane 0 and joins back to it.
+// ---------------------------------------------------------------------------
+struct TwoSided {
+  const std::vector<SketchTerm>* terms = nullptr;
+  RoundTarget* tg = nullptr;
+  int J = 0, N = 0, c = 0;
+  std::vector<Shape> sh;
+  std::vector<std::vector<double*>> R, Lk;  // partial sketches per term and bond
+  std::vector<double*> Ma, Mb, Cb, Mra, Mrb, Crb;
+  double *U1L = nullptr, *U1R = nullptr, *SL = nullptr, *SR = nullptr, *qwL = nullptr, *qwR = nullptr;
+  std::vector<double*> X, Vt;  // left- / right-orthogonal cores
+  double* Gc = nullptr;        // centre core
+  std::vector<double*> Mcur, Mrcur;  // projections after the sweeps
+  // truncation
+  double *Gam = nullptr, *P = nullptr, *lam = nullptr, *ework = nullptr, *TgL = nullptr, *TgR = nullptr;
+  int ldg = 1, ldp = 1, lmax = 1;
+  int *d_dims = nullptr, *d_keep = nullptr;
+  size_t vsz = 1;
+  double* G(int n) const { return Gam + (size_t)n * ldg * ldg; }
+  double* Pn(int n) const { return P + (size_t)n * ldg * ldp; }
+};
 
-// Simultaneous truncation of the mixed canonical chain: left-orthogonal X_n
-// (n < c, [ell_n][2][ell_(n+1)]), centre G ([ell_c][2][ell_(c+1)]) and
-// right-orthogonal V_n (n > c, kept as Vt[(t,z),y]).
-static void plan_trunc_gram_mixed(Plan& plan, const std::vector<double*>& X, const double* Gc,
-                                  const std::vector<double*>& Vt, int c, const std::vector<int>& ell,
-                                  RoundTarget& tg, Prec prec, int lanes) {
-  // eigenvectors resolved down to the noise the contractions left in the
-  // Gram matrices (see the one-sided truncation)
-  const double u = machine_eps(prec);
-  const double unoise = std::max(machine_eps(Prec::F64), u * u);
+// shapes and buffers of one rounding; t1 / t2 / u1 grow to its scratch sizes
+void ts_setup(Plan& plan, TwoSided& r, const std::vector<SketchTerm>& terms, RoundTarget& tg,
+              const std::vector<int>& ell, double* one, size_t& t1, size_t& t2) {
   const int N = (int)ell.size() - 1;
-  QTT_REQUIRE((int)tg.caps.size() == N + 1 && (int)tg.core.size() == N, "truncation target shape");
-  int lmax = 1, cmax = 1;
-  for (int n = 0; n <= N; ++n) {
-    lmax = std::max(lmax, ell[n]);
-    cmax = std::max(cmax, tg.caps[n]);
-  }
-  const int ldg = lmax, ldp = cmax;
-  double* Gam = plan.alloc((size_t)(N + 1) * ldg * ldg);
-  double* P = plan.alloc((size_t)(N + 1) * ldg * ldp);
-  double* lam = plan.alloc((size_t)(N + 1) * ldg);
-  double* ework = plan.alloc((size_t)std::max(1, N - 1) * 3 * ldg * ldg);
-  size_t tsz = 1, vsz = 1;
-  for (int n = 0; n < N; ++n) {
-    tsz = std::max(tsz, (size_t)2 * ell[n] * ell[n + 1]);
-    vsz = std::max(vsz, (size_t)tg.caps[n] * 2 * ell[n + 1]);
-  }
-  double* TgL = plan.alloc(tsz);
-  double* TgR = plan.alloc(tsz);
-  double* V1 = plan.alloc(vsz);
-  std::vector<int> dims, keep;
-  for (int n = 1; n < N; ++n) {
-    dims.push_back(ell[n]);
-    keep.push_back(std::min(ell[n], tg.caps[n]));
-  }
-  int* d_dims = plan.upload(dims);
-  int* d_keep = plan.upload(keep);
-  tg.lam = lam;
-  tg.ldl = ldg;
-  const size_t psz = (size_t)(N + 1) * ldg * ldp;
-  plan.add([P, psz, lam, N, ldg](hipStream_t s) {
-    fill(P, (int64_t)psz, 0.0, s);
-    fill(lam, (int64_t)(N + 1) * ldg, 0.0, s);
-  });
-  auto G = [&](int n) { return Gam + (size_t)n * ldg * ldg; };
-  auto Pn = [&](int n) { return P + (size_t)n * ldg * ldp; };
-  const int L = lane_budget(plan, std::min(lanes, 2));
-  plan.fork(L);
-  // right Gram chain, bonds c..1 (left of the centre)
-  if (c >= 1) {
-    const int a = ell[c], b = ell[c + 1];
-    add_gemm(plan, a, a, 2 * b, Gc, 2 * b, false, Gc, 2 * b, true, G(c), ldg, 1.0, 0.0, Prec::F64);
-    for (int n = c - 1; n >= 1; --n) {
-      const int an = ell[n], bn = ell[n + 1];
-      add_gemm(plan, 2 * an, bn, bn, X[n], bn, false, G(n + 1), ldg, false, TgL, bn, 1.0, 0.0, Prec::F64);
-      add_gemm(plan, an, an, 2 * bn, TgL, 2 * bn, false, X[n], 2 * bn, true, G(n), ldg, 1.0, 0.0, Prec::F64);
-    }
-  }
-  // left Gram chain, bonds c+1..N-1 (right of the centre)
-  if (L > 1) plan.on(1);
-  if (c + 1 <= N - 1) {
-    const int a = ell[c], b = ell[c + 1];
-    add_gemm(plan, b, b, 2 * a, Gc, b, true, Gc, b, false, G(c + 1), ldg, 1.0, 0.0, Prec::F64);
-    for (int n = c + 1; n <= N - 2; ++n) {
-      const int l = ell[n], lp = ell[n + 1];
-      // H[(t,z),y'] = sum_y Vt[(t,z),y] Lambda_n[y,y']
-      add_gemm(plan, 2 * lp, l, l, Vt[n], l, false, G(n), ldg, false, TgR, l, 1.0, 0.0, Prec::F64);
-      // Lambda_(n+1)[z,z'] = sum_(t,y') H[(t,z),y'] Vt[(t,z'),y']
-      TcDesc d;
-      d.M = lp;
-      d.N = lp;
-      d.K = 2 * l;
-      d.A = TgR;
-      d.am = M1(l);
-      d.ak = M2(l, (int64_t)lp * l, 1);
-      d.B = Vt[n];
-      d.bk = M2(l, (int64_t)lp * l, 1);
-      d.bn = M1(l);
-      d.C = G(n + 1);
-      d.cm = M1(ldg);
-      d.cn = M1(1);
-      d.ab = d.bb = d.cb = M1(0);
-      add_tc(plan, d, Prec::F64);
-    }
-  }
-  plan.join(L);
-  if (N >= 2) {
-    const double* g1 = G(1);
-    double* p1 = Pn(1);
-    double* l1 = lam + ldg;
-    const int cnt = N - 1;
-    const bool pre = eig_uses_precondition(lmax);
-    if (pre) {
-      // QR factors of every Gram matrix: the Jacobi sweeps start from R^T
-      OpInfo qi;
-      qi.kind = OP_QR;
-      qi.what = qr_kernel_name(lmax, lmax) + "|eig precondition count" + std::to_string(cnt) + " n" +
-                std::to_string(lmax);
-      for (int n = 1; n < N; ++n) {
-        const OpInfo one = qr_info(ell[n], ell[n]);
-        qi.flops += one.flops;
-        qi.bytes += one.bytes + 8.0 * (double)ell[n] * ell[n];  // G in, Q and R out
-      }
-      plan.add([=](hipStream_t s) {
-        eig_precondition_launch(cnt, d_dims, g1, (int64_t)ldg * ldg, ldg, ework, lmax, s);
-      }, qi);
-    }
-    OpInfo oi;
-    oi.kind = OP_EIG;
-    oi.what = eig_kernel_name(lmax) + "|count" + std::to_string(cnt) + " nmax" + std::to_string(lmax);
-    for (int n = 1; n < N; ++n) {
-      oi.bytes += 8.0 * ((double)ell[n] * ell[n] + (double)ell[n] * tg.caps[n]);
-      oi.flops += 9.0 * (double)ell[n] * ell[n] * ell[n];
-    }
-    plan.add([=](hipStream_t s) {
-      eig_launch(cnt, d_dims, d_keep, g1, (int64_t)ldg * ldg, ldg, p1, (int64_t)ldg * ldp, ldp, l1, ldg,
-                 ework, lmax, unoise, s, pre);
-    }, oi);
-  }
-  // new cores P_n^T A_n P_(n+1)
-  // the cores are independent: spread over lanes, each with its own V1
-  const int Lc = lane_budget(plan, std::min({lanes, 4, N}));
-  std::vector<double*> V1s(Lc, V1);
-  for (int q = 1; q < Lc; ++q) V1s[q] = plan.alloc(vsz);
-  plan.fork(Lc);
-  for (int n = 0; n < N; ++n) {
-    const int l = ell[n], lp = ell[n + 1], cl = tg.caps[n], cr = tg.caps[n + 1];
-    if (Lc > 1) plan.on(n % Lc);
-    double* V1 = V1s[n % Lc];
-    if (n <= c) {
-      const double* A = (n == c) ? Gc : X[n];  // [l][2][lp]
-      if (n == 0 && N == 1) {
-        double* dst = tg.core[0];
-        plan.add([=](hipStream_t s) { rt::copy_async(dst, A, 2 * sizeof(double), s); });
-      } else if (n == 0) {
-        add_gemm(plan, 2, cr, lp, A, lp, false, Pn(1), ldp, false, tg.core[0], cr, 1.0, 0.0, Prec::F64);
-      } else if (n == N - 1) {
-        add_gemm(plan, cl, 2, l, Pn(n), ldp, true, A, 2, false, tg.core[n], 2, 1.0, 0.0, Prec::F64);
-      } else {
-        add_gemm(plan, cl, 2 * lp, l, Pn(n), ldp, true, A, 2 * lp, false, V1, 2 * lp, 1.0, 0.0, Prec::F64);
-        add_gemm(plan, 2 * cl, cr, lp, V1, lp, false, Pn(n + 1), ldp, false, tg.core[n], cr, 1.0, 0.0,
-                 Prec::F64);
-      }
-    } else {
-      // V1[k,(t,z)] = sum_y P_n[y,k] V[y,t,z] = sum_y P_n[y,k] Vt[(t,z),y]
-      const bool lastsite = (n == N - 1);
-      TcDesc d;
-      d.M = cl;
-      d.N = 2 * lp;
-      d.K = l;
-      d.A = Pn(n);
-      d.am = M1(1);
-      d.ak = M1(ldp);
-      d.B = Vt[n];
-      d.bk = M1(1);
-      d.bn = M1(l);
-      d.C = lastsite ? tg.core[n] : V1;
-      d.cm = M1(2 * lp);
-      d.cn = M1(1);
-      d.ab = d.bb = d.cb = M1(0);
-      add_tc(plan, d, Prec::F64);
-      if (!lastsite)
-        add_gemm(plan, 2 * cl, cr, lp, V1, lp, false, Pn(n + 1), ldp, false, tg.core[n], cr, 1.0, 0.0,
-                 Prec::F64);
-    }
-  }
-  plan.join(Lc);
-}
-
-void plan_round_sketch_two_sided(Plan& plan, const std::vector<SketchTerm>& terms, const ChainView& Zr,
-                                 const ChainView& Zl, RoundTarget& tg, Prec prec, int lanes) {
-  const int N = Zr.N;
-  const int J = (int)terms.size();
+  r.terms = &terms;
+  r.tg = &tg;
+  r.J = (int)terms.size();
+  r.N = N;
+  r.c = N / 2;
+  const int J = r.J;
   QTT_REQUIRE(J >= 1, "rounding needs at least one term");
-  QTT_REQUIRE(Zl.N == N && Zl.caps == Zr.caps, "the two sketches must have the same ranks");
-  if (N < 2) {
-    plan_round_sketch(plan, terms, Zr, tg, prec, lanes);
-    return;
-  }
-  const std::vector<int>& ell = Zr.caps;
-  for (int n = 0; n < N; ++n)
-    QTT_REQUIRE(ell[n + 1] <= 2 * ell[n] && ell[n] <= 2 * ell[n + 1],
-                "sketch ranks must satisfy ell_(n+1) <= 2 ell_n and ell_n <= 2 ell_(n+1)");
-  const int c = N / 2;
-  const bool lanes_ok = (plan.cur == 0 && !plan.no_lanes);
-  std::vector<Shape> sh(J);
+  QTT_REQUIRE((int)tg.caps.size() == N + 1 && (int)tg.core.size() == N, "truncation target shape");
+  r.sh.resize(J);
   for (int j = 0; j < J; ++j) {
     QTT_REQUIRE(terms[j].x.N == N, "term length differs from the sketch");
-    sh[j].r = terms[j].x.caps;
+    r.sh[j].r = terms[j].x.caps;
     if (terms[j].mpo) {
       QTT_REQUIRE(terms[j].mpo->N == N, "operator length differs from the sketch");
-      sh[j].D = terms[j].mpo->caps;
+      r.sh[j].D = terms[j].mpo->caps;
     } else {
-      sh[j].D.assign(N + 1, 1);
+      r.sh[j].D.assign(N + 1, 1);
     }
   }
-  // workspace sizes
-  size_t t1 = 1, t2 = 1, msz = 1, u1 = 1, csz = 1, crsz = 1, ssz = 1;
+  size_t msz = 1, u1 = 1, csz = 1, crsz = 1, ssz = 1;
   for (int j = 0; j < J; ++j)
     for (int n = 0; n < N; ++n) {
-      const auto& r = sh[j].r;
-      const auto& D = sh[j].D;
-      const size_t rn = r[n], rp = r[n + 1], Dn = D[n], Dp = D[n + 1], l = ell[n], lp = ell[n + 1];
+      const auto& rr = r.sh[j].r;
+      const auto& D = r.sh[j].D;
+      const size_t rn = rr[n], rp = rr[n + 1], Dn = D[n], Dp = D[n + 1], l = ell[n], lp = ell[n + 1];
       t1 = std::max({t1, rp * Dp * 2 * l, rn * Dn * 2 * lp});
       t2 = std::max({t2, 2 * Dn * rp * l, rn * 2 * Dp * lp});
       msz = std::max({msz, l * rn * Dn, rp * Dp * lp});
@@ -513,124 +363,412 @@ void plan_round_sketch_two_sided(Plan& plan, const std::vector<SketchTerm>& term
       crsz = std::max(crsz, rn * Dn * 2 * lp);
       ssz = std::max(ssz, 2 * l * lp);
     }
-  const int Ls = lanes_ok ? lane_budget(plan, std::min(lanes, 2 * J)) : 1;
-  std::vector<double*> T1s(Ls), T2s(Ls);
-  for (int l = 0; l < Ls; ++l) {
-    T1s[l] = plan.alloc(t1);
-    T2s[l] = plan.alloc(t2);
-  }
-  double* one = plan.upload(std::vector<double>{1.0});
-  std::vector<std::vector<double*>> R(J, std::vector<double*>(N + 1, nullptr));
-  std::vector<std::vector<double*>> Lk(J, std::vector<double*>(N + 1, nullptr));
-  std::vector<double*> Ma(J), Mb(J), Cb(J), Mra(J), Mrb(J), Crb(J);
+  r.R.assign(J, std::vector<double*>(N + 1, nullptr));
+  r.Lk.assign(J, std::vector<double*>(N + 1, nullptr));
+  r.Ma.resize(J);
+  r.Mb.resize(J);
+  r.Cb.resize(J);
+  r.Mra.resize(J);
+  r.Mrb.resize(J);
+  r.Crb.resize(J);
   for (int j = 0; j < J; ++j) {
     for (int n = 1; n < N; ++n) {
-      R[j][n] = plan.alloc((size_t)sh[j].r[n] * sh[j].D[n] * ell[n]);
-      Lk[j][n] = plan.alloc((size_t)ell[n] * sh[j].r[n] * sh[j].D[n]);
+      r.R[j][n] = plan.alloc((size_t)r.sh[j].r[n] * r.sh[j].D[n] * ell[n]);
+      r.Lk[j][n] = plan.alloc((size_t)ell[n] * r.sh[j].r[n] * r.sh[j].D[n]);
     }
-    R[j][N] = one;
-    Lk[j][0] = one;
-    Ma[j] = plan.alloc(msz);
-    Mb[j] = plan.alloc(msz);
-    Cb[j] = plan.alloc(csz);
-    Mra[j] = plan.alloc(msz);
-    Mrb[j] = plan.alloc(msz);
-    Crb[j] = plan.alloc(crsz);
+    r.R[j][N] = one;
+    r.Lk[j][0] = one;
+    r.Ma[j] = plan.alloc(msz);
+    r.Mb[j] = plan.alloc(msz);
+    r.Cb[j] = plan.alloc(csz);
+    r.Mra[j] = plan.alloc(msz);
+    r.Mrb[j] = plan.alloc(msz);
+    r.Crb[j] = plan.alloc(crsz);
   }
-  double* U1L = plan.alloc(u1);
-  double* U1R = plan.alloc(u1);
-  double* SL = plan.alloc(ssz);
-  double* SR = plan.alloc(ssz);
-  double* qwL = plan.alloc(ssz);
-  double* qwR = plan.alloc(ssz);
-  std::vector<double*> X(N, nullptr), Vt(N, nullptr);
-  for (int n = 0; n < c; ++n) X[n] = plan.alloc((size_t)ell[n] * 2 * ell[n + 1]);
-  for (int n = c + 1; n < N; ++n) Vt[n] = plan.alloc((size_t)2 * ell[n + 1] * ell[n]);
-  double* Gc = plan.alloc((size_t)ell[c] * 2 * ell[c + 1]);
-
-  // ---- partial sketches: right (sites N-1..1) and left (sites 0..N-2), chain q on lane q % Ls
-  plan.fork(Ls);
-  for (int q = 0; q < 2 * J; ++q) {
-    const int j = q / 2;
-    if (Ls > 1) plan.on(q % Ls);
-    double* T1 = T1s[q % Ls];
-    double* T2 = T2s[q % Ls];
-    if (q % 2 == 0) {
-      for (int n = N - 1; n >= 1; --n) add_rsketch(plan, terms[j], sh[j], Zr, n, R[j][n + 1], R[j][n], T1, T2, prec);
-    } else {
-      for (int n = 0; n <= N - 2; ++n) add_lsketch(plan, terms[j], sh[j], Zl, n, Lk[j][n], Lk[j][n + 1], T1, T2, prec);
-    }
+  r.U1L = plan.alloc(u1);
+  r.U1R = plan.alloc(u1);
+  r.SL = plan.alloc(ssz);
+  r.SR = plan.alloc(ssz);
+  r.qwL = plan.alloc(ssz);
+  r.qwR = plan.alloc(ssz);
+  r.X.assign(N, nullptr);
+  r.Vt.assign(N, nullptr);
+  for (int n = 0; n < r.c; ++n) r.X[n] = plan.alloc((size_t)ell[n] * 2 * ell[n + 1]);
+  for (int n = r.c + 1; n < N; ++n) r.Vt[n] = plan.alloc((size_t)2 * ell[n + 1] * ell[n]);
+  r.Gc = plan.alloc((size_t)ell[r.c] * 2 * ell[r.c + 1]);
+  // truncation buffers
+  int lmax = 1, cmax = 1;
+  for (int n = 0; n <= N; ++n) {
+    lmax = std::max(lmax, ell[n]);
+    cmax = std::max(cmax, tg.caps[n]);
   }
-  plan.join(Ls);
+  r.lmax = lmax;
+  r.ldg = lmax;
+  r.ldp = cmax;
+  r.Gam = plan.alloc((size_t)(N + 1) * r.ldg * r.ldg);
+  r.P = plan.alloc((size_t)(N + 1) * r.ldg * r.ldp);
+  r.lam = plan.alloc((size_t)(N + 1) * r.ldg);
+  r.ework = plan.alloc((size_t)std::max(1, N - 1) * 3 * r.ldg * r.ldg);
+  size_t tsz = 1;
+  for (int n = 0; n < N; ++n) {
+    tsz = std::max(tsz, (size_t)2 * ell[n] * ell[n + 1]);
+    r.vsz = std::max(r.vsz, (size_t)tg.caps[n] * 2 * ell[n + 1]);
+  }
+  r.TgL = plan.alloc(tsz);
+  r.TgR = plan.alloc(tsz);
+  std::vector<int> dims, keep;
+  for (int n = 1; n < N; ++n) {
+    dims.push_back(ell[n]);
+    keep.push_back(std::min(ell[n], tg.caps[n]));
+  }
+  r.d_dims = plan.upload(dims);
+  r.d_keep = plan.upload(keep);
+  tg.lam = r.lam;
+  tg.ldl = r.ldg;
+}
 
-  // ---- the two sweeps, on two lanes
-  const int Lw = lanes_ok ? lane_budget(plan, std::min(lanes, 2)) : 1;
-  plan.fork(Lw);
-  std::vector<double*> Mcur(J, one), Mnext = Mb;
-  for (int n = 0; n < c; ++n) {  // left sweep, sites 0..c-1
+// partial sketch chain q of a rounding: right sketches of term q/2 (q even),
+// left sketches (q odd)
+void ts_sketch(Plan& plan, TwoSided& r, int q, const ChainView& Zr, const ChainView& Zl, double* T1,
+               double* T2, Prec prec) {
+  const int j = q / 2, N = r.N;
+  const SketchTerm& t = (*r.terms)[j];
+  if (q % 2 == 0) {
+    for (int n = N - 1; n >= 1; --n) add_rsketch(plan, t, r.sh[j], Zr, n, r.R[j][n + 1], r.R[j][n], T1, T2, prec);
+  } else {
+    for (int n = 0; n <= N - 2; ++n) add_lsketch(plan, t, r.sh[j], Zl, n, r.Lk[j][n], r.Lk[j][n + 1], T1, T2, prec);
+  }
+}
+
+// left-to-right sweep, sites 0..c-1
+void ts_left_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double* one, Prec prec) {
+  const int J = r.J;
+  const auto& terms = *r.terms;
+  std::vector<double*> Mcur(J, one), Mnext = r.Mb;
+  for (int n = 0; n < r.c; ++n) {
     const int l = ell[n], lp = ell[n + 1];
-    for (int j = 0; j < J; ++j) add_lcore(plan, terms[j], sh[j], n, l, Mcur[j], U1L, Cb[j], 1.0, 0.0, prec);
+    for (int j = 0; j < J; ++j) add_lcore(plan, terms[j], r.sh[j], n, l, Mcur[j], r.U1L, r.Cb[j], 1.0, 0.0, prec);
     for (int j = 0; j < J; ++j) {
-      const int rp = sh[j].r[n + 1], Dp = sh[j].D[n + 1];
-      add_gemm(plan, 2 * l, lp, rp * Dp, Cb[j], (int64_t)rp * Dp, false, R[j][n + 1], lp, false, SL, lp,
+      const int rp = r.sh[j].r[n + 1], Dp = r.sh[j].D[n + 1];
+      add_gemm(plan, 2 * l, lp, rp * Dp, r.Cb[j], (int64_t)rp * Dp, false, r.R[j][n + 1], lp, false, r.SL, lp,
                terms[j].coef, j > 0 ? 1.0 : 0.0, prec);
     }
     {
-      double* Xn = X[n];
+      double* Xn = r.X[n];
+      double* SL = r.SL;
+      double* qw = r.qwL;
       const int m = 2 * l, nc = lp;
-      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, SL, 0, nc, 1, Xn, 0, nullptr, 0, qwL, s); },
+      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, SL, 0, nc, 1, Xn, 0, nullptr, 0, qw, s); },
                qr_info(m, nc));
     }
     for (int j = 0; j < J; ++j) {
-      const int rp = sh[j].r[n + 1], Dp = sh[j].D[n + 1];
-      add_gemm(plan, lp, rp * Dp, 2 * l, X[n], lp, true, Cb[j], (int64_t)rp * Dp, false, Mnext[j],
+      const int rp = r.sh[j].r[n + 1], Dp = r.sh[j].D[n + 1];
+      add_gemm(plan, lp, rp * Dp, 2 * l, r.X[n], lp, true, r.Cb[j], (int64_t)rp * Dp, false, Mnext[j],
                (int64_t)rp * Dp, 1.0, 0.0, prec);
     }
     for (int j = 0; j < J; ++j) {
       double* old = Mcur[j];
       Mcur[j] = Mnext[j];
-      Mnext[j] = (old == one) ? Ma[j] : old;
+      Mnext[j] = (old == one) ? r.Ma[j] : old;
     }
   }
-  if (Lw > 1) plan.on(1);
-  std::vector<double*> Mrcur(J, one), Mrnext = Mrb;
-  for (int n = N - 1; n > c; --n) {  // right sweep, sites N-1..c+1
+  r.Mcur = Mcur;
+}
+
+// right-to-left sweep, sites N-1..c+1
+void ts_right_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double* one, Prec prec) {
+  const int J = r.J;
+  const auto& terms = *r.terms;
+  std::vector<double*> Mrcur(J, one), Mrnext = r.Mrb;
+  for (int n = r.N - 1; n > r.c; --n) {
     const int l = ell[n], lp = ell[n + 1];
-    for (int j = 0; j < J; ++j) add_rcore(plan, terms[j], sh[j], n, lp, Mrcur[j], U1R, Crb[j], prec);
+    for (int j = 0; j < J; ++j) add_rcore(plan, terms[j], r.sh[j], n, lp, Mrcur[j], r.U1R, r.Crb[j], prec);
     for (int j = 0; j < J; ++j) {  // SR[y,(t,z)] = sum_j c_j Lk_j[y,(a,A)] Cr_j[(a,A),(t,z)]
-      const int rD = sh[j].r[n] * sh[j].D[n];
-      add_gemm(plan, l, 2 * lp, rD, Lk[j][n], rD, false, Crb[j], 2 * lp, false, SR, 2 * lp, terms[j].coef,
-               j > 0 ? 1.0 : 0.0, prec);
+      const int rD = r.sh[j].r[n] * r.sh[j].D[n];
+      add_gemm(plan, l, 2 * lp, rD, r.Lk[j][n], rD, false, r.Crb[j], 2 * lp, false, r.SR, 2 * lp,
+               terms[j].coef, j > 0 ? 1.0 : 0.0, prec);
     }
     {  // Q of SR^T (2 lp x l): the rows of V_n = Q^T are orthonormal
-      double* Vn = Vt[n];
+      double* Vn = r.Vt[n];
+      double* SR = r.SR;
+      double* qw = r.qwR;
       const int m = 2 * lp, nc = l;
-      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, SR, 0, 1, m, Vn, 0, nullptr, 0, qwR, s); },
+      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, SR, 0, 1, m, Vn, 0, nullptr, 0, qw, s); },
                qr_info(m, nc));
     }
     for (int j = 0; j < J; ++j) {  // Mr_j[(a,A),y] = sum_(t,z) Cr_j[(a,A),(t,z)] Vt[(t,z),y]
-      const int rD = sh[j].r[n] * sh[j].D[n];
-      add_gemm(plan, rD, l, 2 * lp, Crb[j], 2 * lp, false, Vt[n], l, false, Mrnext[j], l, 1.0, 0.0, prec);
+      const int rD = r.sh[j].r[n] * r.sh[j].D[n];
+      add_gemm(plan, rD, l, 2 * lp, r.Crb[j], 2 * lp, false, r.Vt[n], l, false, Mrnext[j], l, 1.0, 0.0, prec);
     }
     for (int j = 0; j < J; ++j) {
       double* old = Mrcur[j];
       Mrcur[j] = Mrnext[j];
-      Mrnext[j] = (old == one) ? Mra[j] : old;
+      Mrnext[j] = (old == one) ? r.Mra[j] : old;
     }
   }
-  plan.join(Lw);
+  r.Mrcur = Mrcur;
+}
 
-  // ---- centre core G = sum_j c_j [X_(<c)^T Y_j V_(>c)^T]_c
-  {
-    const int l = ell[c], lp = ell[c + 1];
-    for (int j = 0; j < J; ++j) {
-      add_lcore(plan, terms[j], sh[j], c, l, Mcur[j], U1L, Cb[j], 1.0, 0.0, prec);
-      const int rD = sh[j].r[c + 1] * sh[j].D[c + 1];
-      add_gemm(plan, 2 * l, lp, rD, Cb[j], rD, false, Mrcur[j], lp, false, Gc, lp, terms[j].coef,
-               j > 0 ? 1.0 : 0.0, prec);
-    }
+// centre core G = sum_j c_j [X_(<c)^T Y_j V_(>c)^T]_c
+void ts_centre(Plan& plan, TwoSided& r, const std::vector<int>& ell, Prec prec) {
+  const int c = r.c, l = ell[c], lp = ell[c + 1];
+  const auto& terms = *r.terms;
+  for (int j = 0; j < r.J; ++j) {
+    add_lcore(plan, terms[j], r.sh[j], c, l, r.Mcur[j], r.U1L, r.Cb[j], 1.0, 0.0, prec);
+    const int rD = r.sh[j].r[c + 1] * r.sh[j].D[c + 1];
+    add_gemm(plan, 2 * l, lp, rD, r.Cb[j], rD, false, r.Mrcur[j], lp, false, r.Gc, lp, terms[j].coef,
+             j > 0 ? 1.0 : 0.0, prec);
   }
-  plan_trunc_gram_mixed(plan, X, Gc, Vt, c, ell, tg, prec, lanes);
+}
+
+// Truncation of the mixed canonical chain (left-orthogonal X_n for n < c,
+// centre G, right-orthogonal V_n for n > c, kept as Vt[(t,z),y]): at a bond
+// n <= c the right Gram matrix decides (Gamma_c = G G^T, then the chain
+// through X_(c-1)..X_1), at n > c the left one (Lambda_(c+1) = G^T G, then
+// the chain through V_(c+1)..)
+void ts_gram_right(Plan& plan, TwoSided& r, const std::vector<int>& ell) {
+  const int c = r.c;
+  if (c < 1) return;
+  const int a = ell[c], b = ell[c + 1];
+  add_gemm(plan, a, a, 2 * b, r.Gc, 2 * b, false, r.Gc, 2 * b, true, r.G(c), r.ldg, 1.0, 0.0, Prec::F64);
+  for (int n = c - 1; n >= 1; --n) {
+    const int an = ell[n], bn = ell[n + 1];
+    add_gemm(plan, 2 * an, bn, bn, r.X[n], bn, false, r.G(n + 1), r.ldg, false, r.TgL, bn, 1.0, 0.0, Prec::F64);
+    add_gemm(plan, an, an, 2 * bn, r.TgL, 2 * bn, false, r.X[n], 2 * bn, true, r.G(n), r.ldg, 1.0, 0.0, Prec::F64);
+  }
+}
+
+void ts_gram_left(Plan& plan, TwoSided& r, const std::vector<int>& ell) {
+  const int c = r.c, N = r.N;
+  if (c + 1 > N - 1) return;
+  const int a = ell[c], b = ell[c + 1];
+  add_gemm(plan, b, b, 2 * a, r.Gc, b, true, r.Gc, b, false, r.G(c + 1), r.ldg, 1.0, 0.0, Prec::F64);
+  for (int n = c + 1; n <= N - 2; ++n) {
+    const int l = ell[n], lp = ell[n + 1];
+    // H[(t,z),y'] = sum_y Vt[(t,z),y] Lambda_n[y,y']
+    add_gemm(plan, 2 * lp, l, l, r.Vt[n], l, false, r.G(n), r.ldg, false, r.TgR, l, 1.0, 0.0, Prec::F64);
+    // Lambda_(n+1)[z,z'] = sum_(t,y') H[(t,z),y'] Vt[(t,z'),y']
+    TcDesc d;
+    d.M = lp;
+    d.N = lp;
+    d.K = 2 * l;
+    d.A = r.TgR;
+    d.am = M1(l);
+    d.ak = M2(l, (int64_t)lp * l, 1);
+    d.B = r.Vt[n];
+    d.bk = M2(l, (int64_t)lp * l, 1);
+    d.bn = M1(l);
+    d.C = r.G(n + 1);
+    d.cm = M1(r.ldg);
+    d.cn = M1(1);
+    d.ab = d.bb = d.cb = M1(0);
+    add_tc(plan, d, Prec::F64);
+  }
+}
+
+// one batched eigen-decomposition over all bonds (after the Gram chains)
+void ts_eig(Plan& plan, TwoSided& r, const std::vector<int>& ell, Prec prec) {
+  const int N = r.N, ldg = r.ldg, ldp = r.ldp, lmax = r.lmax;
+  {
+    double* P = r.P;
+    double* lam = r.lam;
+    const size_t psz = (size_t)(N + 1) * ldg * ldp;
+    plan.add([P, psz, lam, N, ldg](hipStream_t s) {
+      fill(P, (int64_t)psz, 0.0, s);
+      fill(lam, (int64_t)(N + 1) * ldg, 0.0, s);
+    });
+  }
+  if (N < 2) return;
+  // eigenvectors resolved down to the noise the contractions left in the
+  // Gram matrices (see the one-sided truncation)
+  const double u = machine_eps(prec);
+  const double unoise = std::max(machine_eps(Prec::F64), u * u);
+  const double* g1 = r.G(1);
+  double* p1 = r.Pn(1);
+  double* l1 = r.lam + ldg;
+  double* ework = r.ework;
+  const int* d_dims = r.d_dims;
+  const int* d_keep = r.d_keep;
+  const int cnt = N - 1;
+  const bool pre = eig_uses_precondition(lmax);
+  if (pre) {
+    // QR factors of every Gram matrix: the Jacobi sweeps start from R^T
+    OpInfo qi;
+    qi.kind = OP_QR;
+    qi.what = qr_kernel_name(lmax, lmax) + "|eig precondition count" + std::to_string(cnt) + " n" +
+              std::to_string(lmax);
+    for (int n = 1; n < N; ++n) {
+      const OpInfo one = qr_info(ell[n], ell[n]);
+      qi.flops += one.flops;
+      qi.bytes += one.bytes + 8.0 * (double)ell[n] * ell[n];  // G in, Q and R out
+    }
+    plan.add([=](hipStream_t s) {
+      eig_precondition_launch(cnt, d_dims, g1, (int64_t)ldg * ldg, ldg, ework, lmax, s);
+    }, qi);
+  }
+  OpInfo oi;
+  oi.kind = OP_EIG;
+  oi.what = eig_kernel_name(lmax) + "|count" + std::to_string(cnt) + " nmax" + std::to_string(lmax);
+  for (int n = 1; n < N; ++n) {
+    oi.bytes += 8.0 * ((double)ell[n] * ell[n] + (double)ell[n] * r.tg->caps[n]);
+    oi.flops += 9.0 * (double)ell[n] * ell[n] * ell[n];
+  }
+  plan.add([=](hipStream_t s) {
+    eig_launch(cnt, d_dims, d_keep, g1, (int64_t)ldg * ldg, ldg, p1, (int64_t)ldg * ldp, ldp, l1, ldg, ework,
+               lmax, unoise, s, pre);
+  }, oi);
+}
+
+// new core n: P_n^T A_n P_(n+1) (V1: scratch of r.vsz doubles)
+void ts_core(Plan& plan, TwoSided& r, int n, const std::vector<int>& ell, double* V1) {
+  const int N = r.N, c = r.c, ldp = r.ldp;
+  RoundTarget& tg = *r.tg;
+  const int l = ell[n], lp = ell[n + 1], cl = tg.caps[n], cr = tg.caps[n + 1];
+  if (n <= c) {
+    const double* A = (n == c) ? r.Gc : r.X[n];  // [l][2][lp]
+    if (n == 0 && N == 1) {
+      double* dst = tg.core[0];
+      plan.add([=](hipStream_t s) { rt::copy_async(dst, A, 2 * sizeof(double), s); });
+    } else if (n == 0) {
+      add_gemm(plan, 2, cr, lp, A, lp, false, r.Pn(1), ldp, false, tg.core[0], cr, 1.0, 0.0, Prec::F64);
+    } else if (n == N - 1) {
+      add_gemm(plan, cl, 2, l, r.Pn(n), ldp, true, A, 2, false, tg.core[n], 2, 1.0, 0.0, Prec::F64);
+    } else {
+      add_gemm(plan, cl, 2 * lp, l, r.Pn(n), ldp, true, A, 2 * lp, false, V1, 2 * lp, 1.0, 0.0, Prec::F64);
+      add_gemm(plan, 2 * cl, cr, lp, V1, lp, false, r.Pn(n + 1), ldp, false, tg.core[n], cr, 1.0, 0.0,
+               Prec::F64);
+    }
+  } else {
+    // V1[k,(t,z)] = sum_y P_n[y,k] V[y,t,z] = sum_y P_n[y,k] Vt[(t,z),y]
+    const bool lastsite = (n == N - 1);
+    TcDesc d;
+    d.M = cl;
+    d.N = 2 * lp;
+    d.K = l;
+    d.A = r.Pn(n);
+    d.am = M1(1);
+    d.ak = M1(ldp);
+    d.B = r.Vt[n];
+    d.bk = M1(1);
+    d.bn = M1(l);
+    d.C = lastsite ? tg.core[n] : V1;
+    d.cm = M1(2 * lp);
+    d.cn = M1(1);
+    d.ab = d.bb = d.cb = M1(0);
+    add_tc(plan, d, Prec::F64);
+    if (!lastsite)
+      add_gemm(plan, 2 * cl, cr, lp, V1, lp, false, r.Pn(n + 1), ldp, false, tg.core[n], cr, 1.0, 0.0,
+               Prec::F64);
+  }
+}
+
+}  // namespace
+
+void plan_round_two_sided_multi(Plan& plan, const std::vector<RoundJob>& jobs, const ChainView& Zr,
+                                const ChainView& Zl, Prec prec, int lanes) {
+  const int N = Zr.N;
+  const int K = (int)jobs.size();
+  QTT_REQUIRE(K >= 1, "no rounding to record");
+  QTT_REQUIRE(Zl.N == N && Zl.caps == Zr.caps, "the two sketches must have the same ranks");
+  if (N < 2) {
+    for (const RoundJob& jb : jobs) plan_round_sketch(plan, *jb.terms, Zr, *jb.tg, prec, lanes);
+    return;
+  }
+  const std::vector<int>& ell = Zr.caps;
+  for (int n = 0; n < N; ++n)
+    QTT_REQUIRE(ell[n + 1] <= 2 * ell[n] && ell[n] <= 2 * ell[n + 1],
+                "sketch ranks must satisfy ell_(n+1) <= 2 ell_n and ell_n <= 2 ell_(n+1)");
+  const int L = lane_budget(plan, lanes);
+  double* one = plan.upload(std::vector<double>{1.0});
+  std::vector<TwoSided> rs(K);
+  size_t t1 = 1, t2 = 1;
+  for (int k = 0; k < K; ++k) ts_setup(plan, rs[k], *jobs[k].terms, *jobs[k].tg, ell, one, t1, t2);
+
+  // ---- partial sketches: right (sites N-1..1) and left (sites 0..N-2) of
+  // every term of every rounding, chain i on lane i % Ls
+  {
+    int Q = 0;
+    for (const TwoSided& r : rs) Q += 2 * r.J;
+    const int Ls = std::min(L, Q);
+    std::vector<double*> T1s(Ls), T2s(Ls);
+    for (int l = 0; l < Ls; ++l) {
+      T1s[l] = plan.alloc(t1);
+      T2s[l] = plan.alloc(t2);
+    }
+    plan.fork(Ls);
+    int i = 0;
+    for (TwoSided& r : rs)
+      for (int q = 0; q < 2 * r.J; ++q, ++i) {
+        if (Ls > 1) plan.on(i % Ls);
+        ts_sketch(plan, r, q, Zr, Zl, T1s[i % Ls], T2s[i % Ls], prec);
+      }
+    plan.join(Ls);
+  }
+  // ---- the sweeps (two per rounding), sweep i on lane i % Lw
+  {
+    const int Lw = std::min(L, 2 * K);
+    plan.fork(Lw);
+    for (int k = 0; k < K; ++k) {
+      if (Lw > 1) plan.on((2 * k) % Lw);
+      ts_left_sweep(plan, rs[k], ell, one, prec);
+      if (Lw > 1) plan.on((2 * k + 1) % Lw);
+      ts_right_sweep(plan, rs[k], ell, one, prec);
+    }
+    plan.join(Lw);
+  }
+  // ---- centre cores
+  {
+    const int Lk = std::min(L, K);
+    plan.fork(Lk);
+    for (int k = 0; k < K; ++k) {
+      if (Lk > 1) plan.on(k % Lk);
+      ts_centre(plan, rs[k], ell, prec);
+    }
+    plan.join(Lk);
+  }
+  // ---- Gram chains (two per rounding)
+  {
+    const int Lg = std::min(L, 2 * K);
+    plan.fork(Lg);
+    for (int k = 0; k < K; ++k) {
+      if (Lg > 1) plan.on((2 * k) % Lg);
+      ts_gram_right(plan, rs[k], ell);
+      if (Lg > 1) plan.on((2 * k + 1) % Lg);
+      ts_gram_left(plan, rs[k], ell);
+    }
+    plan.join(Lg);
+  }
+  // ---- eigen-decompositions (one batched launch per rounding)
+  {
+    const int Le = std::min(L, K);
+    plan.fork(Le);
+    for (int k = 0; k < K; ++k) {
+      if (Le > 1) plan.on(k % Le);
+      ts_eig(plan, rs[k], ell, prec);
+    }
+    plan.join(Le);
+  }
+  // ---- new cores, independent: item i on lane i % Lc with its own V1
+  {
+    const int Lc = std::min(L, std::max(1, std::min(4, K * N)));
+    size_t vsz = 1;
+    for (const TwoSided& r : rs) vsz = std::max(vsz, r.vsz);
+    std::vector<double*> V1s(Lc);
+    for (int l = 0; l < Lc; ++l) V1s[l] = plan.alloc(vsz);
+    plan.fork(Lc);
+    int i = 0;
+    for (int k = 0; k < K; ++k)
+      for (int n = 0; n < N; ++n, ++i) {
+        if (Lc > 1) plan.on(i % Lc);
+        ts_core(plan, rs[k], n, ell, V1s[i % Lc]);
+      }
+    plan.join(Lc);
+  }
+}
+
+void plan_round_sketch_two_sided(Plan& plan, const std::vector<SketchTerm>& terms, const ChainView& Zr,
+                                 const ChainView& Zl, RoundTarget& tg, Prec prec, int lanes) {
+  plan_round_two_sided_multi(plan, {RoundJob{&terms, &tg}}, Zr, Zl, prec, lanes);
 }
 
 }  // namespace qtt
