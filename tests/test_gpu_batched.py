@@ -9,12 +9,7 @@ import workloads
 from oracle import stepper
 from tests.helpers import rel, truncation_sensitivity
 
-pytestmark = [
-    pytest.mark.gpu,
-    pytest.mark.skip(reason="tt_batch_create crashed the host process (segfault) after step plans gained "
-                            "stream lanes; batch plans are now recorded without lanes (the op sequence that "
-                            "passed before) but that has not been re-run on the GPU yet"),
-]
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
