@@ -182,8 +182,18 @@ inline Mode2 mode2(int32_t n2, int64_t s1, int64_t s2) {
 
 // C[b](m,n) = alpha * sum_k A[b](m,k) B[b](k,n) + beta * C[b](m,n)
 // With ksplit > 1 the K range is cut into ksplit chunks whose raw partial
-// sums go to part ([batch][ksplit][M][N], dense) and a second kernel adds
-// them in a fixed order into C.
+// sums go to part ([batch][ng][ksplit][M][N], dense) and a second kernel adds
+// them in a fixed order into C; summed pointer groups (gsum) take the same
+// route even without a K split.
+// Pointer groups: with ng > 1 the launch covers ng operand sets with the same
+// shapes and strides but their own base pointers gA[g], gB[g], gC[g] (e.g. the
+// terms of a rounding, whose cores live in different allocations).  With
+// gsum = 1 the groups are one more reduction index: C = sum_g A_g B_g (gC
+// unused), added in group order by the partial-sum reduction.  The kernels
+// read the pointers from the device table gdev = [gA[0..ng), gB[0..ng),
+// gC[0..ng)] (the host arrays serve the bounds checks).
+constexpr int TC_MAXG = 6;
+
 struct TcDesc {
   int32_t M = 0, N = 0, K = 0, batch = 1;
   Mode2 am, ak, ab;
@@ -195,6 +205,11 @@ struct TcDesc {
   double* C = nullptr;
   int32_t ksplit = 1;
   double* part = nullptr;
+  int32_t ng = 1, gsum = 0;
+  const double* gA[TC_MAXG] = {};
+  const double* gB[TC_MAXG] = {};
+  double* gC[TC_MAXG] = {};
+  const double* const* gdev = nullptr;
 };
 
 // precision of the contraction kernels (inputs are rounded to it, accumulation
@@ -203,8 +218,11 @@ enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
 
 void tc_launch(const TcDesc& d, Prec p, hipStream_t s);
 // number of K chunks worth splitting a contraction into (1: no split); the
-// caller provides the partial-sum buffer of batch * ksplit * M * N doubles
+// caller provides the partial-sum buffer of tc_part_size(d) doubles when
+// tc_uses_part(d) (set d.ksplit first)
 int tc_choose_ksplit(const TcDesc& d, Prec p);
+inline bool tc_uses_part(const TcDesc& d) { return d.ksplit > 1 || (d.ng > 1 && d.gsum); }
+inline int64_t tc_part_size(const TcDesc& d) { return (int64_t)d.batch * d.ng * d.ksplit * d.M * d.N; }
 // name of the kernel (template instantiation) a launch uses
 std::string tc_kernel_name(const TcDesc& d, Prec p);
 std::string qr_kernel_name(int m, int n);

@@ -68,17 +68,29 @@ static Mode2 M2(int n2, int64_t s1, int64_t s2) { return mode2(n2, s1, s2); }
 
 void add_tc(Plan& plan, TcDesc d, Prec p) {
   d.ksplit = tc_choose_ksplit(d, p);
-  if (d.ksplit > 1) d.part = plan.alloc((size_t)d.batch * d.ksplit * d.M * d.N);
+  if (tc_uses_part(d)) d.part = plan.alloc((size_t)tc_part_size(d));
+  if (d.ng > 1) {
+    std::vector<const double*> table;
+    for (int g = 0; g < d.ng; ++g) table.push_back(d.gA[g]);
+    for (int g = 0; g < d.ng; ++g) table.push_back(d.gB[g]);
+    for (int g = 0; g < d.ng; ++g) table.push_back(d.gsum ? d.C : d.gC[g]);
+    d.gdev = plan.upload(table);
+  }
   tc_validate(d);
   OpInfo oi;
   oi.kind = OP_CONTRACT;
-  oi.flops = 2.0 * d.M * (double)d.N * d.K * d.batch;
+  const double ng = d.ng, nc = d.gsum ? 1.0 : ng;
+  oi.flops = 2.0 * d.M * (double)d.N * d.K * d.batch * ng;
   double na = (mode_max(d.ab, d.batch) == 0) ? 1.0 : d.batch;
   double nb = (mode_max(d.bb, d.batch) == 0) ? 1.0 : d.batch;
-  oi.bytes = 8.0 * (na * d.M * (double)d.K + nb * d.K * (double)d.N +
-                    (d.beta != 0.0 ? 2.0 : 1.0) * d.batch * d.M * (double)d.N);
+  oi.bytes = 8.0 * (ng * na * d.M * (double)d.K + ng * nb * d.K * (double)d.N +
+                    nc * (d.beta != 0.0 ? 2.0 : 1.0) * d.batch * d.M * (double)d.N);
   char w[112];
-  snprintf(w, sizeof w, "|b%d m%d n%d k%d s%d", d.batch, d.M, d.N, d.K, d.ksplit);
+  if (d.ng > 1)
+    snprintf(w, sizeof w, "|b%d m%d n%d k%d s%d g%d%s", d.batch, d.M, d.N, d.K, d.ksplit, d.ng,
+             d.gsum ? "+" : "");
+  else
+    snprintf(w, sizeof w, "|b%d m%d n%d k%d s%d", d.batch, d.M, d.N, d.K, d.ksplit);
   oi.what = tc_kernel_name(d, p) + w;
   plan.add([d, p](hipStream_t s) { tc_launch(d, p, s); }, oi);
 }

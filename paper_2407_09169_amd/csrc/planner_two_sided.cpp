@@ -203,17 +203,16 @@ void add_lsketch(Plan& plan, const SketchTerm& t, const Shape& sh, const ChainVi
   }
 }
 
-// C[(k,t),(b,B)] = alpha * sum M[k,(a,A)] x[a,s,b] W[A,t,s,B] + beta * C  (site n, l rows)
-void add_lcore(Plan& plan, const SketchTerm& t, const Shape& sh, int n, int l, const double* M,
-               double* U1, double* Cdst, double alpha, double beta, Prec prec) {
+// C[(k,t),(b,B)] = alpha * sum M[k,(a,A)] x[a,s,b] W[A,t,s,B] + beta * C  (site n, l rows):
+// the launches of one term, in order
+std::vector<TcDesc> lcore_descs(const SketchTerm& t, const Shape& sh, int n, int l, const double* M, double* U1,
+                                double* Cdst, double alpha, double beta) {
   const int rn = sh.r[n], rp = sh.r[n + 1], Dn = sh.D[n], Dp = sh.D[n + 1];
-  if (!t.mpo) {
-    add_gemm(plan, l, 2 * rp, rn, M, rn, false, t.x.core[n], 2 * rp, false, Cdst, 2 * rp, alpha,
-             beta, prec);
-    return;
-  }
+  if (!t.mpo)
+    return {gemm_desc(l, 2 * rp, rn, M, rn, false, t.x.core[n], 2 * rp, false, Cdst, 2 * rp, alpha, beta)};
+  std::vector<TcDesc> out(2);
   {  // U1[k,A,s,b] = sum_a M[k,(a,A)] x[a,s,b], batch A
-    TcDesc d;
+    TcDesc& d = out[0];
     d.batch = Dn;
     d.M = l;
     d.K = rn;
@@ -230,10 +229,9 @@ void add_lcore(Plan& plan, const SketchTerm& t, const Shape& sh, int n, int l, c
     d.cm = M1((int64_t)2 * Dn * rp);
     d.cn = M1(1);
     d.cb = M1(2 * rp);
-    add_tc(plan, d, prec);
   }
   {  // C[k,t,b,B] = sum_(A,s) U1[k,A,s,b] W[A,t,s,B]
-    TcDesc d;
+    TcDesc& d = out[1];
     d.M = l * rp;
     d.K = 2 * Dn;
     d.N = 2 * Dp;
@@ -249,20 +247,20 @@ void add_lcore(Plan& plan, const SketchTerm& t, const Shape& sh, int n, int l, c
     d.ab = d.bb = d.cb = M1(0);
     d.alpha = alpha;
     d.beta = beta;
-    add_tc(plan, d, prec);
   }
+  return out;
 }
 
-// Cr[(a,A),(t,z)] = sum x[a,s,b] W[A,t,s,B] Mr[(b,B),z]  (site n, lp columns of Mr)
-void add_rcore(Plan& plan, const SketchTerm& t, const Shape& sh, int n, int lp, const double* Mr,
-               double* U1, double* Cdst, Prec prec) {
+// Cr[(a,A),(t,z)] = sum x[a,s,b] W[A,t,s,B] Mr[(b,B),z]  (site n, lp columns of Mr):
+// the launches of one term, in order
+std::vector<TcDesc> rcore_descs(const SketchTerm& t, const Shape& sh, int n, int lp, const double* Mr, double* U1,
+                                double* Cdst) {
   const int rn = sh.r[n], rp = sh.r[n + 1], Dn = sh.D[n], Dp = sh.D[n + 1];
-  if (!t.mpo) {  // Cr[(a,s),z] = sum_b x[a,s,b] Mr[b,z]
-    add_gemm(plan, 2 * rn, lp, rp, t.x.core[n], rp, false, Mr, lp, false, Cdst, lp, 1.0, 0.0, prec);
-    return;
-  }
+  if (!t.mpo)  // Cr[(a,s),z] = sum_b x[a,s,b] Mr[b,z]
+    return {gemm_desc(2 * rn, lp, rp, t.x.core[n], rp, false, Mr, lp, false, Cdst, lp, 1.0, 0.0)};
+  std::vector<TcDesc> out(2);
   {  // U1[(a,s),B,z] = sum_b x[a,s,b] Mr[(b,B),z], batch B
-    TcDesc d;
+    TcDesc& d = out[0];
     d.batch = Dp;
     d.M = 2 * rn;
     d.K = rp;
@@ -279,10 +277,9 @@ void add_rcore(Plan& plan, const SketchTerm& t, const Shape& sh, int n, int lp, 
     d.cm = M1((int64_t)Dp * lp);
     d.cn = M1(1);
     d.cb = M1(lp);
-    add_tc(plan, d, prec);
   }
   {  // Cr[(a,A),(t,z)] = sum_(s,B) W[(A,t),(s,B)] U1[(a,s),B,z]: rows (A,t), columns (a,z)
-    TcDesc d;
+    TcDesc& d = out[1];
     d.M = 2 * Dn;
     d.N = rn * lp;
     d.K = 2 * Dp;
@@ -296,8 +293,31 @@ void add_rcore(Plan& plan, const SketchTerm& t, const Shape& sh, int n, int lp, 
     d.cm = M1(lp);
     d.cn = M2(lp, (int64_t)Dn * 2 * lp, 1);
     d.ab = d.bb = d.cb = M1(0);
-    add_tc(plan, d, prec);
   }
+  return out;
+}
+
+// one launch for the same contraction of several terms (same shapes and
+// strides, own operands): pointer groups, summed into one result with gsum
+void add_grouped(Plan& plan, const std::vector<TcDesc>& ds, bool gsum, Prec prec) {
+  QTT_REQUIRE(!ds.empty() && (int)ds.size() <= TC_MAXG, "bad contraction group");
+  if (ds.size() == 1) {
+    add_tc(plan, ds[0], prec);
+    return;
+  }
+  TcDesc d = ds[0];
+  d.ng = (int)ds.size();
+  d.gsum = gsum ? 1 : 0;
+  for (int g = 0; g < d.ng; ++g) {
+    const TcDesc& e = ds[g];
+    QTT_REQUIRE(e.M == d.M && e.N == d.N && e.K == d.K && e.batch == d.batch && e.alpha == d.alpha &&
+                    e.beta == d.beta && (!gsum || e.C == d.C),
+                "grouped contractions differ in shape");
+    d.gA[g] = e.A;
+    d.gB[g] = e.B;
+    d.gC[g] = e.C;
+  }
+  add_tc(plan, d, prec);
 }
 
 // ---------------------------------------------------------------------------
@@ -312,8 +332,11 @@ struct TwoSided {
   int J = 0, N = 0, c = 0;
   std::vector<Shape> sh;
   std::vector<std::vector<double*>> R, Lk;  // partial sketches per term and bond
-  std::vector<double*> Ma, Mb, Cb, Mra, Mrb, Crb;
-  double *U1L = nullptr, *U1R = nullptr, *SL = nullptr, *SR = nullptr, *qwL = nullptr, *qwR = nullptr;
+  std::vector<double*> Ma, Mb, Cb, Mra, Mrb, Crb, U1L, U1R;
+  double *SL = nullptr, *SR = nullptr, *qwL = nullptr, *qwR = nullptr;
+  // terms with the same operator and bonds, recorded as one launch per
+  // contraction (pointer groups)
+  std::vector<std::vector<int>> groups;
   std::vector<double*> X, Vt;  // left- / right-orthogonal cores
   double* Gc = nullptr;        // centre core
   std::vector<double*> Mcur, Mrcur;  // projections after the sweeps
@@ -328,7 +351,7 @@ struct TwoSided {
 
 // shapes and buffers of one rounding; t1 / t2 / u1 grow to its scratch sizes
 void ts_setup(Plan& plan, TwoSided& r, const std::vector<SketchTerm>& terms, RoundTarget& tg,
-              const std::vector<int>& ell, double* one, size_t& t1, size_t& t2) {
+              const std::vector<int>& ell, size_t& t1, size_t& t2) {
   const int N = (int)ell.size() - 1;
   r.terms = &terms;
   r.tg = &tg;
@@ -371,22 +394,40 @@ void ts_setup(Plan& plan, TwoSided& r, const std::vector<SketchTerm>& terms, Rou
   r.Mra.resize(J);
   r.Mrb.resize(J);
   r.Crb.resize(J);
+  r.U1L.resize(J);
+  r.U1R.resize(J);
   for (int j = 0; j < J; ++j) {
     for (int n = 1; n < N; ++n) {
       r.R[j][n] = plan.alloc((size_t)r.sh[j].r[n] * r.sh[j].D[n] * ell[n]);
       r.Lk[j][n] = plan.alloc((size_t)ell[n] * r.sh[j].r[n] * r.sh[j].D[n]);
     }
-    r.R[j][N] = one;
-    r.Lk[j][0] = one;
+    // the sketch chains start from the term's coefficient instead of 1, so
+    // every partial sketch carries c_j and the sums over terms need none
+    double* cj = plan.upload(std::vector<double>{terms[j].coef});
+    r.R[j][N] = cj;
+    r.Lk[j][0] = cj;
     r.Ma[j] = plan.alloc(msz);
     r.Mb[j] = plan.alloc(msz);
     r.Cb[j] = plan.alloc(csz);
     r.Mra[j] = plan.alloc(msz);
     r.Mrb[j] = plan.alloc(msz);
     r.Crb[j] = plan.alloc(crsz);
+    r.U1L[j] = plan.alloc(u1);
+    r.U1R[j] = plan.alloc(u1);
   }
-  r.U1L = plan.alloc(u1);
-  r.U1R = plan.alloc(u1);
+  for (int j = 0; j < J; ++j) {  // group terms of the same operator and bonds
+    bool placed = false;
+    for (auto& g : r.groups) {
+      const int f = g[0];
+      if ((int)g.size() < TC_MAXG && terms[f].mpo == terms[j].mpo && r.sh[f].r == r.sh[j].r &&
+          r.sh[f].D == r.sh[j].D) {
+        g.push_back(j);
+        placed = true;
+        break;
+      }
+    }
+    if (!placed) r.groups.push_back({j});
+  }
   r.SL = plan.alloc(ssz);
   r.SR = plan.alloc(ssz);
   r.qwL = plan.alloc(ssz);
@@ -447,11 +488,23 @@ void ts_left_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double*
   std::vector<double*> Mcur(J, one), Mnext = r.Mb;
   for (int n = 0; n < r.c; ++n) {
     const int l = ell[n], lp = ell[n + 1];
-    for (int j = 0; j < J; ++j) add_lcore(plan, terms[j], r.sh[j], n, l, Mcur[j], r.U1L, r.Cb[j], 1.0, 0.0, prec);
-    for (int j = 0; j < J; ++j) {
-      const int rp = r.sh[j].r[n + 1], Dp = r.sh[j].D[n + 1];
-      add_gemm(plan, 2 * l, lp, rp * Dp, r.Cb[j], (int64_t)rp * Dp, false, r.R[j][n + 1], lp, false, r.SL, lp,
-               terms[j].coef, j > 0 ? 1.0 : 0.0, prec);
+    for (const auto& g : r.groups) {  // C_j = M_j x_j W
+      std::vector<std::vector<TcDesc>> per;
+      for (int j : g) per.push_back(lcore_descs(terms[j], r.sh[j], n, l, Mcur[j], r.U1L[j], r.Cb[j], 1.0, 0.0));
+      for (size_t q = 0; q < per[0].size(); ++q) {
+        std::vector<TcDesc> ds;
+        for (auto& v : per) ds.push_back(v[q]);
+        add_grouped(plan, ds, false, prec);
+      }
+    }
+    for (size_t gi = 0; gi < r.groups.size(); ++gi) {  // S = sum_j C_j R_j (c_j is in R_j)
+      std::vector<TcDesc> ds;
+      for (int j : r.groups[gi]) {
+        const int rp = r.sh[j].r[n + 1], Dp = r.sh[j].D[n + 1];
+        ds.push_back(gemm_desc(2 * l, lp, rp * Dp, r.Cb[j], (int64_t)rp * Dp, false, r.R[j][n + 1], lp, false,
+                               r.SL, lp, 1.0, gi > 0 ? 1.0 : 0.0));
+      }
+      add_grouped(plan, ds, true, prec);
     }
     {
       double* Xn = r.X[n];
@@ -461,10 +514,14 @@ void ts_left_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double*
       plan.add([=](hipStream_t s) { qr_launch(1, m, nc, SL, 0, nc, 1, Xn, 0, nullptr, 0, qw, s); },
                qr_info(m, nc));
     }
-    for (int j = 0; j < J; ++j) {
-      const int rp = r.sh[j].r[n + 1], Dp = r.sh[j].D[n + 1];
-      add_gemm(plan, lp, rp * Dp, 2 * l, r.X[n], lp, true, r.Cb[j], (int64_t)rp * Dp, false, Mnext[j],
-               (int64_t)rp * Dp, 1.0, 0.0, prec);
+    for (const auto& g : r.groups) {  // M'_j = X_n^T C_j
+      std::vector<TcDesc> ds;
+      for (int j : g) {
+        const int rp = r.sh[j].r[n + 1], Dp = r.sh[j].D[n + 1];
+        ds.push_back(gemm_desc(lp, rp * Dp, 2 * l, r.X[n], lp, true, r.Cb[j], (int64_t)rp * Dp, false, Mnext[j],
+                               (int64_t)rp * Dp, 1.0, 0.0));
+      }
+      add_grouped(plan, ds, false, prec);
     }
     for (int j = 0; j < J; ++j) {
       double* old = Mcur[j];
@@ -482,11 +539,24 @@ void ts_right_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double
   std::vector<double*> Mrcur(J, one), Mrnext = r.Mrb;
   for (int n = r.N - 1; n > r.c; --n) {
     const int l = ell[n], lp = ell[n + 1];
-    for (int j = 0; j < J; ++j) add_rcore(plan, terms[j], r.sh[j], n, lp, Mrcur[j], r.U1R, r.Crb[j], prec);
-    for (int j = 0; j < J; ++j) {  // SR[y,(t,z)] = sum_j c_j Lk_j[y,(a,A)] Cr_j[(a,A),(t,z)]
-      const int rD = r.sh[j].r[n] * r.sh[j].D[n];
-      add_gemm(plan, l, 2 * lp, rD, r.Lk[j][n], rD, false, r.Crb[j], 2 * lp, false, r.SR, 2 * lp,
-               terms[j].coef, j > 0 ? 1.0 : 0.0, prec);
+    for (const auto& g : r.groups) {  // Cr_j = x_j W Mr_j
+      std::vector<std::vector<TcDesc>> per;
+      for (int j : g) per.push_back(rcore_descs(terms[j], r.sh[j], n, lp, Mrcur[j], r.U1R[j], r.Crb[j]));
+      for (size_t q = 0; q < per[0].size(); ++q) {
+        std::vector<TcDesc> ds;
+        for (auto& v : per) ds.push_back(v[q]);
+        add_grouped(plan, ds, false, prec);
+      }
+    }
+    for (size_t gi = 0; gi < r.groups.size(); ++gi) {
+      // SR[y,(t,z)] = sum_j Lk_j[y,(a,A)] Cr_j[(a,A),(t,z)] (c_j is in Lk_j)
+      std::vector<TcDesc> ds;
+      for (int j : r.groups[gi]) {
+        const int rD = r.sh[j].r[n] * r.sh[j].D[n];
+        ds.push_back(gemm_desc(l, 2 * lp, rD, r.Lk[j][n], rD, false, r.Crb[j], 2 * lp, false, r.SR, 2 * lp, 1.0,
+                               gi > 0 ? 1.0 : 0.0));
+      }
+      add_grouped(plan, ds, true, prec);
     }
     {  // Q of SR^T (2 lp x l): the rows of V_n = Q^T are orthonormal
       double* Vn = r.Vt[n];
@@ -496,9 +566,13 @@ void ts_right_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double
       plan.add([=](hipStream_t s) { qr_launch(1, m, nc, SR, 0, 1, m, Vn, 0, nullptr, 0, qw, s); },
                qr_info(m, nc));
     }
-    for (int j = 0; j < J; ++j) {  // Mr_j[(a,A),y] = sum_(t,z) Cr_j[(a,A),(t,z)] Vt[(t,z),y]
-      const int rD = r.sh[j].r[n] * r.sh[j].D[n];
-      add_gemm(plan, rD, l, 2 * lp, r.Crb[j], 2 * lp, false, r.Vt[n], l, false, Mrnext[j], l, 1.0, 0.0, prec);
+    for (const auto& g : r.groups) {  // Mr_j[(a,A),y] = sum_(t,z) Cr_j[(a,A),(t,z)] Vt[(t,z),y]
+      std::vector<TcDesc> ds;
+      for (int j : g) {
+        const int rD = r.sh[j].r[n] * r.sh[j].D[n];
+        ds.push_back(gemm_desc(rD, l, 2 * lp, r.Crb[j], 2 * lp, false, r.Vt[n], l, false, Mrnext[j], l, 1.0, 0.0));
+      }
+      add_grouped(plan, ds, false, prec);
     }
     for (int j = 0; j < J; ++j) {
       double* old = Mrcur[j];
@@ -513,8 +587,16 @@ void ts_right_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double
 void ts_centre(Plan& plan, TwoSided& r, const std::vector<int>& ell, Prec prec) {
   const int c = r.c, l = ell[c], lp = ell[c + 1];
   const auto& terms = *r.terms;
+  for (const auto& g : r.groups) {
+    std::vector<std::vector<TcDesc>> per;
+    for (int j : g) per.push_back(lcore_descs(terms[j], r.sh[j], c, l, r.Mcur[j], r.U1L[j], r.Cb[j], 1.0, 0.0));
+    for (size_t q = 0; q < per[0].size(); ++q) {
+      std::vector<TcDesc> ds;
+      for (auto& v : per) ds.push_back(v[q]);
+      add_grouped(plan, ds, false, prec);
+    }
+  }
   for (int j = 0; j < r.J; ++j) {
-    add_lcore(plan, terms[j], r.sh[j], c, l, r.Mcur[j], r.U1L, r.Cb[j], 1.0, 0.0, prec);
     const int rD = r.sh[j].r[c + 1] * r.sh[j].D[c + 1];
     add_gemm(plan, 2 * l, lp, rD, r.Cb[j], rD, false, r.Mrcur[j], lp, false, r.Gc, lp, terms[j].coef,
              j > 0 ? 1.0 : 0.0, prec);
@@ -682,7 +764,7 @@ void plan_round_two_sided_multi(Plan& plan, const std::vector<RoundJob>& jobs, c
   double* one = plan.upload(std::vector<double>{1.0});
   std::vector<TwoSided> rs(K);
   size_t t1 = 1, t2 = 1;
-  for (int k = 0; k < K; ++k) ts_setup(plan, rs[k], *jobs[k].terms, *jobs[k].tg, ell, one, t1, t2);
+  for (int k = 0; k < K; ++k) ts_setup(plan, rs[k], *jobs[k].terms, *jobs[k].tg, ell, t1, t2);
 
   // ---- partial sketches: right (sites N-1..1) and left (sites 0..N-2) of
   // every term of every rounding, chain i on lane i % Ls

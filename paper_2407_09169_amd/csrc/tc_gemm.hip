@@ -24,19 +24,34 @@ namespace {
 
 constexpr int BK64 = 16;
 
+// blockIdx.z = (batch index * ng + group) * ksplit + K chunk
 struct KRange {
-  int z, beg, end;
+  int z, g, beg, end;
 };
 
 template <int BK>
 __device__ inline KRange k_range(const TcDesc& d) {
   const int ks = (int)(blockIdx.z % (unsigned)d.ksplit);
-  const int z = (int)(blockIdx.z / (unsigned)d.ksplit);
+  const int zg = (int)(blockIdx.z / (unsigned)d.ksplit);
+  const int g = zg % d.ng;
+  const int z = zg / d.ng;
   const int chunk = ((d.K + d.ksplit - 1) / d.ksplit + BK - 1) / BK * BK;
   const int beg = ks * chunk;
   const int end = min(d.K, beg + chunk);
-  return {z, beg, end};
+  return {z, g, beg, end};
 }
+
+// group base pointers from the device table (one scalar load each)
+__device__ inline const double* base_a(const TcDesc& d, const KRange& kr) {
+  return (d.ng > 1 ? d.gdev[kr.g] : d.A) + d.ab.off(kr.z);
+}
+__device__ inline const double* base_b(const TcDesc& d, const KRange& kr) {
+  return (d.ng > 1 ? d.gdev[d.ng + kr.g] : d.B) + d.bb.off(kr.z);
+}
+__device__ inline double* base_c(const TcDesc& d, const KRange& kr) {
+  return (d.ng > 1 ? const_cast<double*>(d.gdev[2 * d.ng + kr.g]) : d.C) + d.cb.off(kr.z);
+}
+__device__ inline bool to_part(const TcDesc& d) { return d.ksplit > 1 || (d.ng > 1 && d.gsum); }
 
 template <int BM, int BN>
 __global__ __launch_bounds__(256) void tc_f64_kernel(TcDesc d, int a_kfast, int b_nfast) {
@@ -48,8 +63,8 @@ __global__ __launch_bounds__(256) void tc_f64_kernel(TcDesc d, int a_kfast, int 
   const int tx = tid & 15, ty = tid >> 4;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const KRange kr = k_range<BK64>(d);
-  const double* A = d.A + d.ab.off(kr.z);
-  const double* B = d.B + d.bb.off(kr.z);
+  const double* A = base_a(d, kr);
+  const double* B = base_b(d, kr);
   double acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -102,7 +117,7 @@ __global__ __launch_bounds__(256) void tc_f64_kernel(TcDesc d, int a_kfast, int 
     }
     __syncthreads();
   }
-  if (d.ksplit > 1) {
+  if (to_part(d)) {
     double* Pp = d.part + (int64_t)blockIdx.z * d.M * d.N;
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
@@ -116,7 +131,7 @@ __global__ __launch_bounds__(256) void tc_f64_kernel(TcDesc d, int a_kfast, int 
     }
     return;
   }
-  double* C = d.C + d.cb.off(kr.z);
+  double* C = base_c(d, kr);
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     const int m = m0 + ty + 16 * i;
@@ -153,8 +168,8 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d, int a_kfast, int
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const KRange kr = k_range<BK>(d);
-  const double* A = d.A + d.ab.off(kr.z);
-  const double* B = d.B + d.bb.off(kr.z);
+  const double* A = base_a(d, kr);
+  const double* B = base_b(d, kr);
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -227,7 +242,7 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d, int a_kfast, int
     __syncthreads();
   }
   // accumulator layout: lane holds rows 4*(lane/16)+r, column lane%16 of each block
-  if (d.ksplit > 1) {
+  if (to_part(d)) {
     double* Pp = d.part + (int64_t)blockIdx.z * d.M * d.N;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -241,7 +256,7 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d, int a_kfast, int
         }
     return;
   }
-  double* C = d.C + d.cb.off(kr.z);
+  double* C = base_c(d, kr);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -259,19 +274,25 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d, int a_kfast, int
       }
 }
 
-// C = alpha * sum_s part[b][s] + beta * C, one thread per output element,
-// chunks added in increasing order
+// C = alpha * sum part + beta * C, one thread per output element.  Outputs
+// are (batch index, group) pairs, or batch indices alone when the groups are
+// summed; the parts of an output (groups, then K chunks) are added in
+// increasing order.
 __global__ __launch_bounds__(256) void tc_splitk_reduce(TcDesc d) {
   const int64_t mn = (int64_t)d.M * d.N;
+  const int gout = d.gsum ? 1 : d.ng;      // outputs per batch index
+  const int nparts = (d.gsum ? d.ng : 1) * d.ksplit;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= mn * d.batch) return;
-  const int z = (int)(idx / mn);
-  const int64_t rem = idx - (int64_t)z * mn;
+  if (idx >= mn * d.batch * gout) return;
+  const int zo = (int)(idx / mn);
+  const int64_t rem = idx - (int64_t)zo * mn;
   const int m = (int)(rem / d.N), n = (int)(rem - (int64_t)m * d.N);
-  const double* Pp = d.part + (int64_t)z * d.ksplit * mn + rem;
+  const int z = zo / gout, g = zo - z * gout;
+  const double* Pp = d.part + ((int64_t)z * d.ng + g) * d.ksplit * mn + rem;
   double s = 0.0;
-  for (int k = 0; k < d.ksplit; ++k) s += Pp[(int64_t)k * mn];
-  double* p = d.C + d.cb.off(z) + d.cm.off(m) + d.cn.off(n);
+  for (int k = 0; k < nparts; ++k) s += Pp[(int64_t)k * mn];
+  double* base = (d.ng > 1 && !d.gsum) ? const_cast<double*>(d.gdev[2 * d.ng + g]) : d.C;
+  double* p = base + d.cb.off(z) + d.cm.off(m) + d.cn.off(n);
   double v = d.alpha * s;
   if (d.beta != 0.0) v += d.beta * *p;
   *p = v;
@@ -299,7 +320,7 @@ std::string tc_kernel_name(const TcDesc& d, Prec p) {
 int tc_choose_ksplit(const TcDesc& d, Prec p) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0 || d.K < 256) return 1;
   const Tile t = tile_of(d, p);
-  const int64_t tiles = (int64_t)((d.M + t.bm - 1) / t.bm) * ((d.N + t.bn - 1) / t.bn) * d.batch;
+  const int64_t tiles = (int64_t)((d.M + t.bm - 1) / t.bm) * ((d.N + t.bn - 1) / t.bn) * d.batch * d.ng;
   if (tiles >= 128) return 1;
   // aim at ~256 workgroups with at least 128 K values each
   int ks = (int)std::min<int64_t>(d.K / 128, (256 + tiles - 1) / tiles);
@@ -311,29 +332,36 @@ void tc_validate(const TcDesc& d) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
   QTT_REQUIRE(d.M < (1 << 30) && d.N < (1 << 30) && d.K < (1 << 30), "contraction extent too large");
   QTT_REQUIRE(d.ksplit >= 1, "bad K split");
-  if (d.K > 0) {
-    rt::check_range(d.A, 0, mode_max(d.ab, d.batch) + mode_max(d.am, d.M) + mode_max(d.ak, d.K),
-                    sizeof(double), "contraction operand A");
-    rt::check_range(d.B, 0, mode_max(d.bb, d.batch) + mode_max(d.bk, d.K) + mode_max(d.bn, d.N),
-                    sizeof(double), "contraction operand B");
+  QTT_REQUIRE(d.ng >= 1 && d.ng <= TC_MAXG, "contraction pointer groups %d outside 1..%d", d.ng, TC_MAXG);
+  if (d.ng > 1) rt::check_range(d.gdev, 0, 3 * d.ng - 1, sizeof(double*), "contraction pointer table");
+  // every pointer group is checked against its own allocation
+  for (int g = 0; g < d.ng; ++g) {
+    const double* A = d.ng > 1 ? d.gA[g] : d.A;
+    const double* B = d.ng > 1 ? d.gB[g] : d.B;
+    double* C = (d.ng > 1 && !d.gsum) ? d.gC[g] : d.C;
+    if (d.K > 0) {
+      rt::check_range(A, 0, mode_max(d.ab, d.batch) + mode_max(d.am, d.M) + mode_max(d.ak, d.K),
+                      sizeof(double), "contraction operand A");
+      rt::check_range(B, 0, mode_max(d.bb, d.batch) + mode_max(d.bk, d.K) + mode_max(d.bn, d.N),
+                      sizeof(double), "contraction operand B");
+    }
+    rt::check_range(C, 0, mode_max(d.cb, d.batch) + mode_max(d.cm, d.M) + mode_max(d.cn, d.N),
+                    sizeof(double), "contraction result C");
   }
-  rt::check_range(d.C, 0, mode_max(d.cb, d.batch) + mode_max(d.cm, d.M) + mode_max(d.cn, d.N),
-                  sizeof(double), "contraction result C");
-  if (d.ksplit > 1)
-    rt::check_range(d.part, 0, (int64_t)d.batch * d.ksplit * d.M * d.N - 1, sizeof(double),
-                    "contraction partial sums");
+  if (tc_uses_part(d))
+    rt::check_range(d.part, 0, tc_part_size(d) - 1, sizeof(double), "contraction partial sums");
 }
 
 void tc_launch(const TcDesc& d, Prec p, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
   tc_validate(d);
   if (rt::dry()) return;
-  QTT_REQUIRE((int64_t)d.batch * d.ksplit <= 65535 && (d.M + 31) / 32 <= 65535,
-              "contraction too large (M=%d batch=%d split=%d)", d.M, d.batch, d.ksplit);
+  QTT_REQUIRE((int64_t)d.batch * d.ng * d.ksplit <= 65535 && (d.M + 31) / 32 <= 65535,
+              "contraction too large (M=%d batch=%d groups=%d split=%d)", d.M, d.batch, d.ng, d.ksplit);
   const int a_kfast = unit(d.ak) ? 1 : 0;
   const int b_nfast = unit(d.bn) ? 1 : 0;
   const Tile t = tile_of(d, p);
-  const dim3 grid((d.N + t.bn - 1) / t.bn, (d.M + t.bm - 1) / t.bm, d.batch * d.ksplit);
+  const dim3 grid((d.N + t.bn - 1) / t.bn, (d.M + t.bm - 1) / t.bm, d.batch * d.ng * d.ksplit);
   if (p == Prec::F64) {
     if (t.bm == 64 && t.bn == 64)
       hipLaunchKernelGGL((tc_f64_kernel<64, 64>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
@@ -349,8 +377,8 @@ void tc_launch(const TcDesc& d, Prec p, hipStream_t s) {
     hipLaunchKernelGGL((tc_mfma_kernel<false>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
   }
   QTT_HIP(hipGetLastError());
-  if (d.ksplit > 1) {
-    const int64_t tot = (int64_t)d.M * d.N * d.batch;
+  if (tc_uses_part(d)) {
+    const int64_t tot = (int64_t)d.M * d.N * d.batch * (d.gsum ? 1 : d.ng);
     hipLaunchKernelGGL(tc_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, d);
     QTT_HIP(hipGetLastError());
   }
