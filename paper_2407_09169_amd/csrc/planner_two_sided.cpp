@@ -39,9 +39,11 @@ struct Shape {
   std::vector<int> r, D;  // bonds of the term's MPS and MPO (D = 1: identity)
 };
 
-// R_out[(a,A), z] = sum x[a,s,b] W[A,t,s,B] R_in[(b,B), z'] Z[z,t,z']  (site n)
-void add_rsketch(Plan& plan, const SketchTerm& t, const Shape& sh, const ChainView& Z, int n,
-                 const double* Rin, double* Rout, double* T1, double* T2, Prec prec) {
+// R_out[(a,A), z] = sum x[a,s,b] W[A,t,s,B] R_in[(b,B), z'] Z[z,t,z']  (site n): the
+// launches of one term, in order
+std::vector<TcDesc> rsketch_descs(const SketchTerm& t, const Shape& sh, const ChainView& Z, int n,
+                                  const double* Rin, double* Rout, double* T1, double* T2) {
+  std::vector<TcDesc> out;
   const int l = Z.caps[n], lp = Z.caps[n + 1];
   const int rn = sh.r[n], rp = sh.r[n + 1], Dn = sh.D[n], Dp = sh.D[n + 1];
   {  // T1[(b,B),(t,z)] = sum_z' R_in[(b,B),z'] Z[z,t,z']
@@ -59,7 +61,7 @@ void add_rsketch(Plan& plan, const SketchTerm& t, const Shape& sh, const ChainVi
     d.cm = M1(2 * l);
     d.cn = M1(1);
     d.ab = d.bb = d.cb = M1(0);
-    add_tc(plan, d, prec);
+    out.push_back(d);
   }
   if (t.mpo) {
     {  // T2[(A,s), b, z] = sum_(B,t) W[A,t,s,B] T1[(b,B),(t,z)], batch b
@@ -80,7 +82,7 @@ void add_rsketch(Plan& plan, const SketchTerm& t, const Shape& sh, const ChainVi
       d.cm = M1((int64_t)rp * l);
       d.cn = M1(1);
       d.cb = M1(l);
-      add_tc(plan, d, prec);
+      out.push_back(d);
     }
     {  // R_out[(a,A),z] = sum_(s,b) x[a,s,b] T2[A,s,b,z], batch A
       TcDesc d;
@@ -100,7 +102,7 @@ void add_rsketch(Plan& plan, const SketchTerm& t, const Shape& sh, const ChainVi
       d.cm = M1((int64_t)Dn * l);
       d.cn = M1(1);
       d.cb = M1(l);
-      add_tc(plan, d, prec);
+      out.push_back(d);
     }
   } else {  // R_out[a,z] = sum_(s,b) x[a,s,b] T1[b,(s,z)]
     TcDesc d;
@@ -117,13 +119,16 @@ void add_rsketch(Plan& plan, const SketchTerm& t, const Shape& sh, const ChainVi
     d.cm = M1(l);
     d.cn = M1(1);
     d.ab = d.bb = d.cb = M1(0);
-    add_tc(plan, d, prec);
+    out.push_back(d);
   }
+  return out;
 }
 
-// L_out[z, (b,B)] = sum Zl[y,t,z] L_in[y,(a,A)] x[a,s,b] W[A,t,s,B]  (site n)
-void add_lsketch(Plan& plan, const SketchTerm& t, const Shape& sh, const ChainView& Zl, int n,
-                 const double* Lin, double* Lout, double* T1, double* T2, Prec prec) {
+// L_out[z, (b,B)] = sum Zl[y,t,z] L_in[y,(a,A)] x[a,s,b] W[A,t,s,B]  (site n): the
+// launches of one term, in order
+std::vector<TcDesc> lsketch_descs(const SketchTerm& t, const Shape& sh, const ChainView& Zl, int n,
+                                  const double* Lin, double* Lout, double* T1, double* T2) {
+  std::vector<TcDesc> out;
   const int l = Zl.caps[n], lp = Zl.caps[n + 1];
   const int rn = sh.r[n], rp = sh.r[n + 1], Dn = sh.D[n], Dp = sh.D[n + 1];
   {  // T1[(a,A),(t,z)] = sum_y L_in[y,(a,A)] Zl[y,(t,z)]
@@ -141,7 +146,7 @@ void add_lsketch(Plan& plan, const SketchTerm& t, const Shape& sh, const ChainVi
     d.cm = M1(2 * lp);
     d.cn = M1(1);
     d.ab = d.bb = d.cb = M1(0);
-    add_tc(plan, d, prec);
+    out.push_back(d);
   }
   if (t.mpo) {
     {  // T2[a,(s,B),z] = sum_(A,t) W[A,t,s,B] T1[(a,A),(t,z)], batch a
@@ -162,7 +167,7 @@ void add_lsketch(Plan& plan, const SketchTerm& t, const Shape& sh, const ChainVi
       d.cm = M1(lp);
       d.cn = M1(1);
       d.cb = M1((int64_t)2 * Dp * lp);
-      add_tc(plan, d, prec);
+      out.push_back(d);
     }
     {  // L_out[z,(b,B)] = sum_(a,s) T2[a,(s,B),z] x[a,s,b], batch B
       TcDesc d;
@@ -182,7 +187,7 @@ void add_lsketch(Plan& plan, const SketchTerm& t, const Shape& sh, const ChainVi
       d.cm = M1((int64_t)rp * Dp);
       d.cn = M1(Dp);
       d.cb = M1(1);
-      add_tc(plan, d, prec);
+      out.push_back(d);
     }
   } else {  // L_out[z,b] = sum_(a,s) T1[a,(s,z)] x[a,s,b]
     TcDesc d;
@@ -199,8 +204,9 @@ void add_lsketch(Plan& plan, const SketchTerm& t, const Shape& sh, const ChainVi
     d.cm = M1(rp);
     d.cn = M1(1);
     d.ab = d.bb = d.cb = M1(0);
-    add_tc(plan, d, prec);
+    out.push_back(d);
   }
+  return out;
 }
 
 // C[(k,t),(b,B)] = alpha * sum M[k,(a,A)] x[a,s,b] W[A,t,s,B] + beta * C  (site n, l rows):
@@ -333,6 +339,7 @@ struct TwoSided {
   std::vector<Shape> sh;
   std::vector<std::vector<double*>> R, Lk;  // partial sketches per term and bond
   std::vector<double*> Ma, Mb, Cb, Mra, Mrb, Crb, U1L, U1R;
+  std::vector<double*> T1, T2, L1, L2;  // sketch-chain scratch per term (right, left)
   double *SL = nullptr, *SR = nullptr, *qwL = nullptr, *qwR = nullptr;
   // terms with the same operator and bonds, recorded as one launch per
   // contraction (pointer groups)
@@ -351,7 +358,7 @@ struct TwoSided {
 
 // shapes and buffers of one rounding; t1 / t2 / u1 grow to its scratch sizes
 void ts_setup(Plan& plan, TwoSided& r, const std::vector<SketchTerm>& terms, RoundTarget& tg,
-              const std::vector<int>& ell, size_t& t1, size_t& t2) {
+              const std::vector<int>& ell) {
   const int N = (int)ell.size() - 1;
   r.terms = &terms;
   r.tg = &tg;
@@ -372,7 +379,7 @@ void ts_setup(Plan& plan, TwoSided& r, const std::vector<SketchTerm>& terms, Rou
       r.sh[j].D.assign(N + 1, 1);
     }
   }
-  size_t msz = 1, u1 = 1, csz = 1, crsz = 1, ssz = 1;
+  size_t t1 = 1, t2 = 1, msz = 1, u1 = 1, csz = 1, crsz = 1, ssz = 1;
   for (int j = 0; j < J; ++j)
     for (int n = 0; n < N; ++n) {
       const auto& rr = r.sh[j].r;
@@ -414,6 +421,10 @@ void ts_setup(Plan& plan, TwoSided& r, const std::vector<SketchTerm>& terms, Rou
     r.Crb[j] = plan.alloc(crsz);
     r.U1L[j] = plan.alloc(u1);
     r.U1R[j] = plan.alloc(u1);
+    r.T1.push_back(plan.alloc(t1));
+    r.T2.push_back(plan.alloc(t2));
+    r.L1.push_back(plan.alloc(t1));
+    r.L2.push_back(plan.alloc(t2));
   }
   for (int j = 0; j < J; ++j) {  // group terms of the same operator and bonds
     bool placed = false;
@@ -468,16 +479,33 @@ void ts_setup(Plan& plan, TwoSided& r, const std::vector<SketchTerm>& terms, Rou
   tg.ldl = r.ldg;
 }
 
-// partial sketch chain q of a rounding: right sketches of term q/2 (q even),
-// left sketches (q odd)
-void ts_sketch(Plan& plan, TwoSided& r, int q, const ChainView& Zr, const ChainView& Zl, double* T1,
-               double* T2, Prec prec) {
-  const int j = q / 2, N = r.N;
-  const SketchTerm& t = (*r.terms)[j];
+// partial sketch chain q of a rounding: right sketches of term group q/2
+// (q even), left sketches (q odd); one launch per contraction for the group
+void ts_sketch(Plan& plan, TwoSided& r, int q, const ChainView& Zr, const ChainView& Zl, Prec prec) {
+  const std::vector<int>& g = r.groups[q / 2];
+  const int N = r.N;
+  const auto& terms = *r.terms;
+  auto record = [&](std::vector<std::vector<TcDesc>>& per) {
+    for (size_t i = 0; i < per[0].size(); ++i) {
+      std::vector<TcDesc> ds;
+      for (auto& v : per) ds.push_back(v[i]);
+      add_grouped(plan, ds, false, prec);
+    }
+  };
   if (q % 2 == 0) {
-    for (int n = N - 1; n >= 1; --n) add_rsketch(plan, t, r.sh[j], Zr, n, r.R[j][n + 1], r.R[j][n], T1, T2, prec);
+    for (int n = N - 1; n >= 1; --n) {
+      std::vector<std::vector<TcDesc>> per;
+      for (int j : g)
+        per.push_back(rsketch_descs(terms[j], r.sh[j], Zr, n, r.R[j][n + 1], r.R[j][n], r.T1[j], r.T2[j]));
+      record(per);
+    }
   } else {
-    for (int n = 0; n <= N - 2; ++n) add_lsketch(plan, t, r.sh[j], Zl, n, r.Lk[j][n], r.Lk[j][n + 1], T1, T2, prec);
+    for (int n = 0; n <= N - 2; ++n) {
+      std::vector<std::vector<TcDesc>> per;
+      for (int j : g)
+        per.push_back(lsketch_descs(terms[j], r.sh[j], Zl, n, r.Lk[j][n], r.Lk[j][n + 1], r.L1[j], r.L2[j]));
+      record(per);
+    }
   }
 }
 
@@ -763,26 +791,20 @@ void plan_round_two_sided_multi(Plan& plan, const std::vector<RoundJob>& jobs, c
   const int L = lane_budget(plan, lanes);
   double* one = plan.upload(std::vector<double>{1.0});
   std::vector<TwoSided> rs(K);
-  size_t t1 = 1, t2 = 1;
-  for (int k = 0; k < K; ++k) ts_setup(plan, rs[k], *jobs[k].terms, *jobs[k].tg, ell, t1, t2);
+  for (int k = 0; k < K; ++k) ts_setup(plan, rs[k], *jobs[k].terms, *jobs[k].tg, ell);
 
   // ---- partial sketches: right (sites N-1..1) and left (sites 0..N-2) of
-  // every term of every rounding, chain i on lane i % Ls
+  // every term group of every rounding, chain i on lane i % Ls
   {
     int Q = 0;
-    for (const TwoSided& r : rs) Q += 2 * r.J;
+    for (const TwoSided& r : rs) Q += 2 * (int)r.groups.size();
     const int Ls = std::min(L, Q);
-    std::vector<double*> T1s(Ls), T2s(Ls);
-    for (int l = 0; l < Ls; ++l) {
-      T1s[l] = plan.alloc(t1);
-      T2s[l] = plan.alloc(t2);
-    }
     plan.fork(Ls);
     int i = 0;
     for (TwoSided& r : rs)
-      for (int q = 0; q < 2 * r.J; ++q, ++i) {
+      for (int q = 0; q < 2 * (int)r.groups.size(); ++q, ++i) {
         if (Ls > 1) plan.on(i % Ls);
-        ts_sketch(plan, r, q, Zr, Zl, T1s[i % Ls], T2s[i % Ls], prec);
+        ts_sketch(plan, r, q, Zr, Zl, prec);
       }
     plan.join(Ls);
   }
