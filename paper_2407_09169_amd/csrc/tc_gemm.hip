@@ -154,9 +154,12 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // 64x64 output tile per workgroup, 4 waves each owning a 32x32 quadrant made
 // of 2x2 16x16 MFMA blocks.  LDS holds A as [m][k] and B as [n][k] so that a
-// lane's MFMA operand is contiguous in k.
-template <bool BF16>
-__global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d, int a_kfast, int b_nfast) {
+// lane's MFMA operand is contiguous in k.  AKF / BNF: A is read along k
+// (row-major operand) / B along n; each thread's tile elements keep their row
+// (column) offsets for the whole K loop, so a K step costs one or NA mode
+// offsets instead of two per element.
+template <bool BF16, bool AKF, bool BNF>
+__global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
   constexpr int BM = 64, BN = 64, BK = 32;
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
   using TIn = typename std::conditional<BF16, __bf16, float>::type;
@@ -176,37 +179,61 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d, int a_kfast, int
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int li = lane & 15, lq = lane >> 4;
+  // element q of this thread: A at (row am_q, column ak_q), B at (ak_q', bn_q)
+  auto a_row = [&](int q) { return AKF ? tid / BK + q * (256 / BK) : tid % BM; };
+  auto a_col = [&](int q) { return AKF ? tid % BK : tid / BM + q * (256 / BM); };
+  auto b_col = [&](int q) { return BNF ? tid % BN : tid / BK + q * (256 / BK); };
+  auto b_row = [&](int q) { return BNF ? tid / BN + q * (256 / BN) : tid % BK; };
+  constexpr int NAR = AKF ? NA : 1, NBC = BNF ? 1 : NB;  // distinct rows of A / columns of B
+  int64_t aoff[NAR], boff[NBC];
+  bool aok[NAR], bok[NBC];
+#pragma unroll
+  for (int q = 0; q < NAR; ++q) {
+    const int m = m0 + a_row(q);
+    aok[q] = m < d.M;
+    aoff[q] = aok[q] ? d.am.off(m) : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < NBC; ++q) {
+    const int n = n0 + b_col(q);
+    bok[q] = n < d.N;
+    boff[q] = bok[q] ? d.bn.off(n) : 0;
+  }
   double ra[NA], rb[NB];
   auto load = [&](int k0) {
+    if (AKF) {
+      const int k = k0 + a_col(0);
+      const bool kok = k < kr.end;
+      const int64_t ko = kok ? d.ak.off(k) : 0;
 #pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int e = tid + 256 * q;
-      const int mm = a_kfast ? e / BK : e % BM, kk = a_kfast ? e % BK : e / BM;
-      const int m = m0 + mm, k = k0 + kk;
-      ra[q] = (m < d.M && k < kr.end) ? A[d.am.off(m) + d.ak.off(k)] : 0.0;
+      for (int q = 0; q < NA; ++q) ra[q] = (aok[q] && kok) ? A[aoff[q] + ko] : 0.0;
+    } else {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const int k = k0 + a_col(q);
+        ra[q] = (aok[0] && k < kr.end) ? A[aoff[0] + d.ak.off(k)] : 0.0;
+      }
     }
+    if (BNF) {
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int e = tid + 256 * q;
-      const int nn = b_nfast ? e % BN : e / BK, kk = b_nfast ? e / BN : e % BK;
-      const int n = n0 + nn, k = k0 + kk;
-      rb[q] = (n < d.N && k < kr.end) ? B[d.bk.off(k) + d.bn.off(n)] : 0.0;
+      for (int q = 0; q < NB; ++q) {
+        const int k = k0 + b_row(q);
+        rb[q] = (bok[0] && k < kr.end) ? B[d.bk.off(k) + boff[0]] : 0.0;
+      }
+    } else {
+      const int k = k0 + b_row(0);
+      const bool kok = k < kr.end;
+      const int64_t ko = kok ? d.bk.off(k) : 0;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) rb[q] = (bok[q] && kok) ? B[ko + boff[q]] : 0.0;
     }
   };
   if (kr.beg < kr.end) load(kr.beg);
   for (int k0 = kr.beg; k0 < kr.end; k0 += BK) {
 #pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int e = tid + 256 * q;
-      const int mm = a_kfast ? e / BK : e % BM, kk = a_kfast ? e % BK : e / BM;
-      As[mm][kk] = (TIn)(float)ra[q];
-    }
+    for (int q = 0; q < NA; ++q) As[a_row(q)][a_col(q)] = (TIn)(float)ra[q];
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int e = tid + 256 * q;
-      const int nn = b_nfast ? e % BN : e / BK, kk = b_nfast ? e / BN : e % BK;
-      Bs[nn][kk] = (TIn)(float)rb[q];
-    }
+    for (int q = 0; q < NB; ++q) Bs[b_col(q)][b_row(q)] = (TIn)(float)rb[q];
     __syncthreads();
     if (k0 + BK < kr.end) load(k0 + BK);
     if constexpr (BF16) {
@@ -311,8 +338,11 @@ inline Tile tile_of(const TcDesc& d, Prec p) {
 }  // namespace
 
 std::string tc_kernel_name(const TcDesc& d, Prec p) {
-  if (p == Prec::BF16) return "tc_mfma_kernel<true>";
-  if (p == Prec::F32) return "tc_mfma_kernel<false>";
+  if (p != Prec::F64) {
+    const char* ak = unit(d.ak) ? "true" : "false";
+    const char* bn = unit(d.bn) ? "true" : "false";
+    return std::string("tc_mfma_kernel<") + (p == Prec::BF16 ? "true" : "false") + ", " + ak + ", " + bn + ">";
+  }
   const Tile t = tile_of(d, p);
   return "tc_f64_kernel<" + std::to_string(t.bm) + ", " + std::to_string(t.bn) + ">";
 }
@@ -371,10 +401,19 @@ void tc_launch(const TcDesc& d, Prec p, hipStream_t s) {
       hipLaunchKernelGGL((tc_f64_kernel<32, 64>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
     else
       hipLaunchKernelGGL((tc_f64_kernel<32, 32>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
-  } else if (p == Prec::BF16) {
-    hipLaunchKernelGGL((tc_mfma_kernel<true>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
   } else {
-    hipLaunchKernelGGL((tc_mfma_kernel<false>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
+#define QTT_TC_MFMA(BF, AK, BN)                                                          \
+  if ((p == Prec::BF16) == BF && (a_kfast != 0) == AK && (b_nfast != 0) == BN)            \
+    hipLaunchKernelGGL((tc_mfma_kernel<BF, AK, BN>), grid, dim3(256), 0, s, d);
+    QTT_TC_MFMA(true, true, true)
+    QTT_TC_MFMA(true, true, false)
+    QTT_TC_MFMA(true, false, true)
+    QTT_TC_MFMA(true, false, false)
+    QTT_TC_MFMA(false, true, true)
+    QTT_TC_MFMA(false, true, false)
+    QTT_TC_MFMA(false, false, true)
+    QTT_TC_MFMA(false, false, false)
+#undef QTT_TC_MFMA
   }
   QTT_HIP(hipGetLastError());
   if (tc_uses_part(d)) {
