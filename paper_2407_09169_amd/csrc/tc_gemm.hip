@@ -348,12 +348,15 @@ std::string tc_kernel_name(const TcDesc& d, Prec p) {
 }
 
 int tc_choose_ksplit(const TcDesc& d, Prec p) {
-  if (d.M <= 0 || d.N <= 0 || d.batch <= 0 || d.K < 256) return 1;
+  if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return 1;
   const Tile t = tile_of(d, p);
   const int64_t tiles = (int64_t)((d.M + t.bm - 1) / t.bm) * ((d.N + t.bn - 1) / t.bn) * d.batch * d.ng;
   if (tiles >= 128) return 1;
-  // aim at ~256 workgroups with at least 128 K values each
-  int ks = (int)std::min<int64_t>(d.K / 128, (256 + tiles - 1) / tiles);
+  // aim at ~256 workgroups.  The FP64 kernel is slow per K step, so it splits
+  // down to one LDS tile (16) per chunk; the MFMA kernels keep >= 128 per chunk.
+  const int minchunk = (p == Prec::F64) ? 16 : 128;
+  if (d.K < 4 * minchunk) return 1;
+  int ks = (int)std::min<int64_t>(d.K / minchunk, (256 + tiles - 1) / tiles);
   ks = std::min(ks, 64);
   return ks >= 2 ? ks : 1;
 }
