@@ -142,17 +142,29 @@ def _classes(rows):
 
 
 def _kernel_probe(spec):
-    """The QR kernel alone, on the shape the step uses (counter runs)."""
+    """One factorisation kernel alone, on the shape the step uses (counter
+    runs): qr:MxN (one matrix, as in the sweeps) or eig:N (a batch of 49
+    Gram-like PSD matrices with eigenvalues over 20 decades, as in a
+    truncation)."""
     import numpy as np
     import paper_2407_09169_amd as q
     kind, shape = spec.split(":")
-    if kind != "qr":
-        raise SystemExit(f"unknown kernel probe {kind}")
-    m, n = (int(v) for v in shape.lower().split("x"))
-    A = np.random.default_rng(0).standard_normal((1, m, n))
     ctx = q.Context(0)
-    for _ in range(5):
-        q.linalg_qr(ctx, A, with_r=False)
+    rng = np.random.default_rng(0)
+    if kind == "qr":
+        m, n = (int(v) for v in shape.lower().split("x"))
+        A = rng.standard_normal((1, m, n))
+        for _ in range(5):
+            q.linalg_qr(ctx, A, with_r=False)
+    elif kind == "eig":
+        n = int(shape)
+        Q, _ = np.linalg.qr(rng.standard_normal((49, n, n)))
+        lam = 10.0 ** (-20.0 * np.arange(n) / (n - 1))
+        G = np.einsum("bij,j,bkj->bik", Q, lam, Q)
+        for _ in range(5):
+            q.linalg_eigh(ctx, G, min(n, 128))
+    else:
+        raise SystemExit(f"unknown kernel probe {kind}")
     print(json.dumps({"kernel_probe": spec, "dispatches": 5}))
 
 
@@ -296,9 +308,10 @@ def main():
     ap.add_argument("--gradient", action="store_true",
                     help="time steps that also carry the derivatives with respect to Omega and k "
                          "(default workload for this mode: c5_5d_M256_chi64, all its steps)")
-    ap.add_argument("--kernel-probe", default=None, metavar="qr:MxN",
-                    help="only run the FP64 Householder QR kernel on one seeded M x N matrix "
-                         "five times (counter runs of the dominant kernel)")
+    ap.add_argument("--kernel-probe", default=None, metavar="qr:MxN|eig:N",
+                    help="only run one FP64 factorisation kernel five times: the Householder QR "
+                         "on one seeded M x N matrix, or the Jacobi eigensolver on a batch of "
+                         "49 seeded N x N PSD matrices (counter runs)")
     args = ap.parse_args()
     if args.copy_probe:
         _copy_probe(args.copy_probe)
