@@ -170,8 +170,9 @@ def _kernel_probe(spec):
 
 def _bench_batched(args, log):
     """The batched ensemble (64 uneven 5-D problems, FP32-MFMA contractions):
-    instance-steps/s of one graph launch per step for all instances, next to
-    the same instances stepped one after another."""
+    instance-steps/s of the instances stepped together (one call per step,
+    their step graphs on parallel branches), next to the same instances
+    stepped one after another."""
     import torch
     import paper_2407_09169_amd as q
     import workloads
@@ -191,20 +192,24 @@ def _bench_batched(args, log):
     ms = e0.elapsed_time(e1)
     value = len(ws) * args.steps / (ms / 1e3)
     log(f"batched: {args.steps} steps of {len(ws)} instances in {ms:.1f} ms ({value:.1f} instance-steps/s)")
-    for p, f in inst:  # records each instance's own graph
-        p.step(f, 1)
-    torch.cuda.synchronize()
-    e0.record()
+    masses = [p.observable(f, "mass") for p, f in inst]
+    b.close()  # releases the batch plan before the instances record their own
+    # one after another: each instance records its own graph, is timed over
+    # one step, and releases its plan (all 64 step plans at once would not fit)
+    ms1 = 0.0
     for p, f in inst:
         p.step(f, 1)
-    e1.record()
-    torch.cuda.synchronize()
-    ms1 = e0.elapsed_time(e1)
+        torch.cuda.synchronize()
+        e0.record()
+        p.step(f, 1)
+        e1.record()
+        torch.cuda.synchronize()
+        ms1 += e0.elapsed_time(e1)
+        p.close()
     seq = len(ws) / (ms1 / 1e3)
     log(f"one after another: {seq:.1f} instance-steps/s")
-    masses = [p.observable(f, "mass") for p, f in inst]
     out = {
-        "metric": "instance-steps/s, 64 uneven 5-D QTT PDF problems in one graph launch per step",
+        "metric": "instance-steps/s, 64 uneven 5-D QTT PDF problems stepped together",
         "value": value, "unit": "instance-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
@@ -215,7 +220,6 @@ def _bench_batched(args, log):
         "batching_speedup": value / seq,
         "mass_range": [min(masses), max(masses)],
     }
-    b.close()
     print(json.dumps(out))
 
 

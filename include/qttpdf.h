@@ -242,21 +242,26 @@ tt_status tt_problem_state(tt_problem* prob, tt_tt** f);
 tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps);
 
 /* ------------------------------------------------------------------------
- * Batching: many independent problems advanced by one graph launch.
+ * Batching: many independent problems advanced by one call per step.
  * (Not a passage of the paper: the step of section "Matrix product state
  * algorithm" applied to an ensemble of problems with different grids,
  * bond caps and parameters.)
  * ------------------------------------------------------------------------ */
-/* Records one step of `count` problems, each with its own state
- * (states[i] from tt_problem_state(probs[i]); problems and states must be
- * distinct), as a single HIP graph in which every instance is an independent
- * branch.  The handles stay owned by the caller and must outlive the batch;
- * an instance must not be stepped by other calls while the batch is in use.
- * Results are bitwise those of tt_step on each instance alone. */
+/* Prepares `count` problems, each with its own state (states[i] from
+ * tt_problem_state(probs[i]); problems and states must be distinct), to be
+ * stepped together.  Every instance keeps its own step graph, recorded as
+ * tt_step records it.  The instances are spread over a few parallel branches
+ * (streams; 8, or the environment variable QTTPDF_BATCH_BRANCHES), each a
+ * chain of whole instance steps: an instance joins the branch with the least
+ * estimated work (sum of cap^3 over its bonds), largest first.  The handles
+ * stay owned by the caller and must outlive the batch; an instance must not
+ * be stepped by other calls while the batch is in use.  Results are bitwise
+ * those of tt_step on each instance alone. */
 tt_status tt_batch_create(tt_ctx* ctx, int count, tt_problem* const* probs, tt_tt* const* states,
                           tt_batch** out);
-/* Advances every instance of the batch by n_steps steps (n_steps graph
- * launches on the context's stream; asynchronous). */
+/* Advances every instance of the batch by n_steps steps: per step, the
+ * branches fork from the context's stream, launch their instances' step
+ * graphs in order, and join back (asynchronous to the host). */
 tt_status tt_step_batched(tt_batch* batch, int n_steps);
 tt_status tt_batch_destroy(tt_batch* batch);
 

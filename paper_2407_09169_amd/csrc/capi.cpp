@@ -170,9 +170,6 @@ struct tt_problem {
   DevBuf Edf[2], Edk[2], mfdf[2], mfdk[2];
   std::unique_ptr<Plan> tplan;
   std::vector<const void*> tplan_key;
-  // the step recorded without lanes, for batched replays
-  std::unique_ptr<Plan> bplan;
-  const tt_tt* bplan_f = nullptr;
   hipGraph_t tgraph = nullptr;
   hipGraphExec_t texec = nullptr;
   ~tt_problem() {
@@ -1028,6 +1025,37 @@ tt_status tt_problem_state(tt_problem* prob, tt_tt** f) {
   });
 }
 
+}  // extern "C"
+
+// The step plan of (problem, state), recorded on first use, and with graphs
+// enabled captured once from the context's stream as a HIP graph.
+static void ensure_step_graph(tt_problem* prob, tt_tt* f) {
+  if (!prob->plan || prob->plan_f != f) build_step_plan(prob, f);
+  if (rt::dry() || !use_graph() || prob->exec) return;
+  StreamScope sc(prob->ctx);
+  hipStream_t s = prob->ctx->stream;
+  QTT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  try {
+    prob->plan->run(s);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(s, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  QTT_HIP(hipStreamEndCapture(s, &prob->graph));
+  QTT_HIP(hipGraphInstantiate(&prob->exec, prob->graph, nullptr, nullptr, 0));
+}
+
+// one step of a problem whose plan (and graph) exist, on stream s
+static void launch_step(tt_problem* prob, hipStream_t s) {
+  prob->last = prob->last_plain;
+  if (rt::dry() || !use_graph()) prob->plan->run(s);
+  else QTT_HIP(hipGraphLaunch(prob->exec, s));
+}
+
+extern "C" {
+
 tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps) {
   return guard([&] {
     QTT_REQUIRE(prob && f && n_steps >= 0, "bad argument");
@@ -1035,27 +1063,9 @@ tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps) {
     QTT_REQUIRE(prob->ctx == ctx, "problem belongs to another context");
     QTT_REQUIRE(f->caps == prob->fcaps, "state caps differ from the problem's");
     if (n_steps == 0) return;
-    if (!prob->plan || prob->plan_f != f) build_step_plan(prob, f);
-    prob->last = prob->last_plain;
+    ensure_step_graph(prob, f);
     StreamScope sc(ctx);
-    if (rt::dry() || !use_graph()) {
-      for (int i = 0; i < n_steps; ++i) prob->plan->run(ctx->stream);
-      return;
-    }
-    if (!prob->exec) {
-      QTT_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-      try {
-        prob->plan->run(ctx->stream);
-      } catch (...) {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(ctx->stream, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
-      }
-      QTT_HIP(hipStreamEndCapture(ctx->stream, &prob->graph));
-      QTT_HIP(hipGraphInstantiate(&prob->exec, prob->graph, nullptr, nullptr, 0));
-    }
-    for (int i = 0; i < n_steps; ++i) QTT_HIP(hipGraphLaunch(prob->exec, ctx->stream));
+    for (int i = 0; i < n_steps; ++i) launch_step(prob, ctx->stream);
   });
 }
 
@@ -1064,17 +1074,21 @@ tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps) {
 // ---------------------------------------------------------------------------
 }  // extern "C"
 
+// parallel branches of a batched step: QTTPDF_BATCH_BRANCHES, default 8
+static int batch_branches() {
+  const char* e = std::getenv("QTTPDF_BATCH_BRANCHES");
+  const int v = e ? std::atoi(e) : 0;
+  return v >= 1 ? v : 8;
+}
+
 struct tt_batch {
   tt_ctx* ctx = nullptr;
   std::vector<tt_problem*> probs;
   std::vector<tt_tt*> states;
-  std::vector<hipStream_t> streams;  // one per instance (capture only)
-  std::vector<hipEvent_t> events;    // fork + one join per instance
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  std::vector<std::vector<int>> chain;  // instances of each branch, in order
+  std::vector<hipStream_t> streams;     // one per branch
+  std::vector<hipEvent_t> events;       // fork + one join per branch
   ~tt_batch() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
     for (auto e : events) (void)hipEventDestroy(e);
     for (auto st : streams) (void)hipStreamDestroy(st);
   }
@@ -1097,38 +1111,35 @@ tt_status tt_batch_create(tt_ctx* ctx, int count, tt_problem* const* probs, tt_t
       QTT_REQUIRE(f->caps == P->fcaps, "instance %d: state caps differ from the problem's", i);
       for (int j = 0; j < i; ++j)
         QTT_REQUIRE(probs[j] != P && states[j] != f, "instance %d repeats a problem or a state", i);
-      if (!P->bplan || P->bplan_f != f) {
-        P->bplan = record_step(P, f, {}, false);
-        P->bplan_f = f;
-      }
-      QTT_REQUIRE(P->bplan->events.empty() && P->bplan->streams.empty(),
-                  "instance %d: batched plan must not carry lanes", i);
       b->probs.push_back(P);
       b->states.push_back(f);
     }
+    // every instance keeps its own step graph (with its lanes), as tt_step
+    // records it
+    for (int i = 0; i < count; ++i) ensure_step_graph(b->probs[i], b->states[i]);
+    // Instances run on a few parallel branches (streams), each a chain of
+    // whole instance steps; an instance joins the branch with the least
+    // estimated work so far, largest first (work ~ sum of cap^3 over the
+    // bonds).
+    const int nb = std::min(count, batch_branches());
+    std::vector<double> cost(count, 0.0);
+    for (int i = 0; i < count; ++i)
+      for (int c : b->probs[i]->fcaps) cost[i] += (double)c * c * c;
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    b->chain.assign(nb, {});
+    std::vector<double> load(nb, 0.0);
+    for (int i : order) {
+      const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      b->chain[k].push_back(i);
+      load[k] += cost[i];
+    }
     if (!rt::dry()) {
-      b->streams.resize(count, nullptr);
+      b->streams.resize(nb, nullptr);
       for (auto& st : b->streams) QTT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-      b->events.resize(count + 1, nullptr);
+      b->events.resize(nb + 1, nullptr);
       for (auto& e : b->events) QTT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      hipStream_t s0 = ctx->stream;
-      QTT_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
-      try {
-        QTT_HIP(hipEventRecord(b->events[0], s0));
-        for (int i = 0; i < count; ++i) {
-          QTT_HIP(hipStreamWaitEvent(b->streams[i], b->events[0], 0));
-          b->probs[i]->bplan->run(b->streams[i]);
-          QTT_HIP(hipEventRecord(b->events[i + 1], b->streams[i]));
-          QTT_HIP(hipStreamWaitEvent(s0, b->events[i + 1], 0));
-        }
-      } catch (...) {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(s0, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
-      }
-      QTT_HIP(hipStreamEndCapture(s0, &b->graph));
-      QTT_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     }
     *out = b.release();
   });
@@ -1138,12 +1149,22 @@ tt_status tt_step_batched(tt_batch* b, int n_steps) {
   return guard([&] {
     QTT_REQUIRE(b && n_steps >= 0, "bad argument");
     StreamScope sc(b->ctx);
-    if (rt::dry()) {
-      for (int i = 0; i < n_steps; ++i)
-        for (auto* P : b->probs) P->bplan->run(b->ctx->stream);
-      return;
+    hipStream_t s0 = b->ctx->stream;
+    for (int step = 0; step < n_steps; ++step) {
+      if (rt::dry()) {
+        for (auto& ch : b->chain)
+          for (int i : ch) launch_step(b->probs[i], s0);
+        continue;
+      }
+      // fork from the context's stream, one chain per branch, join back
+      QTT_HIP(hipEventRecord(b->events[0], s0));
+      for (size_t k = 0; k < b->chain.size(); ++k) {
+        QTT_HIP(hipStreamWaitEvent(b->streams[k], b->events[0], 0));
+        for (int i : b->chain[k]) launch_step(b->probs[i], b->streams[k]);
+        QTT_HIP(hipEventRecord(b->events[k + 1], b->streams[k]));
+        QTT_HIP(hipStreamWaitEvent(s0, b->events[k + 1], 0));
+      }
     }
-    for (int i = 0; i < n_steps; ++i) QTT_HIP(hipGraphLaunch(b->exec, b->ctx->stream));
   });
 }
 
