@@ -190,6 +190,21 @@ tt_status mps_round(tt_ctx* ctx, const tt_tt* x, int chi, tt_tt** out);
 tt_status mps_round_sketch(tt_ctx* ctx, int n_terms, const double* coeffs,
                            const tt_tt* const* mpos, const tt_tt* const* xs,
                            const tt_tt* sketch, int chi, int dtype, tt_tt** out);
+/* The two-sided form of the same rounding, the one the time step uses
+ * (section "Matrix product state algorithm", read as a randomized range
+ * finder orthogonalised from both ends): bonds 1..c (c = N / 2) get
+ * left-orthogonal cores from a left-to-right Householder QR sweep of the
+ * sketched unfoldings (right sketches from `sketch`), bonds c+1..N-1
+ * right-orthogonal cores from a right-to-left sweep (left sketches from
+ * `sketch_left`, same length and ranks as `sketch`); the centre core
+ * joins them, and the mixed canonical chain is truncated simultaneously
+ * from the eigen-decompositions of its bond Gram matrices.  Errors as
+ * mps_round_sketch; TT_ERR_INVALID_ARG if sketch_left is NULL or its
+ * shape differs from the sketch's. */
+tt_status mps_round_sketch_two_sided(tt_ctx* ctx, int n_terms, const double* coeffs,
+                                     const tt_tt* const* mpos, const tt_tt* const* xs,
+                                     const tt_tt* sketch, const tt_tt* sketch_left, int chi,
+                                     int dtype, tt_tt** out);
 
 /* ||a - b|| / ||b|| computed from the difference MPS brought to
  * left-orthogonal form (no cancellation of large inner products). */

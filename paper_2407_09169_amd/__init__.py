@@ -31,7 +31,8 @@ LINEAR_OBS = ("mass", "mean1", "mean2", "mean12", "product")
 EXPORTS = [
     "tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_stream", "tt_ctx_synchronize", "tt_last_error",
     "tt_alloc", "tt_free", "tt_info", "tt_set_cores", "tt_get_cores", "tt_from_separable",
-    "mpo_build", "mps_apply_mpo", "mps_axpby", "mps_round", "mps_round_sketch", "tt_l2_diff",
+    "mpo_build", "mps_apply_mpo", "mps_axpby", "mps_round", "mps_round_sketch",
+    "mps_round_sketch_two_sided", "tt_l2_diff",
     "tt_inner", "tt_problem_create", "tt_problem_destroy", "tt_problem_info", "tt_problem_state",
     "tt_step", "tt_profile", "tt_step_info", "tt_observable", "tt_mean_field",
     "tt_linalg_qr", "tt_linalg_eigh", "tt_batch_create", "tt_step_batched", "tt_batch_destroy",
@@ -91,6 +92,7 @@ def lib():
         "mps_axpby": [vp, i32, P(dbl), P(vp), P(vp)],
         "mps_round": [vp, vp, i32, P(vp)],
         "mps_round_sketch": [vp, i32, P(dbl), P(vp), P(vp), vp, i32, i32, P(vp)],
+        "mps_round_sketch_two_sided": [vp, i32, P(dbl), P(vp), P(vp), vp, vp, i32, i32, P(vp)],
         "tt_l2_diff": [vp, vp, vp, P(dbl)],
         "tt_inner": [vp, vp, vp, P(dbl)],
         "tt_problem_create": [vp, P(TTParams), P(vp), vp, vp, vp, vp, P(vp)],
@@ -292,11 +294,17 @@ def round_det(ctx, x, chi):
     return TT(ctx, h)
 
 
-def round_sketch(ctx, coeffs, mpos, xs, sketch, chi, dtype="f64"):
+def round_sketch(ctx, coeffs, mpos, xs, sketch, chi, dtype="f64", sketch_left=None):
+    """mps_round_sketch, or with a left sketch mps_round_sketch_two_sided."""
     c = (C.c_double * len(xs))(*coeffs)
     h = C.c_void_p()
-    _check(lib().mps_round_sketch(ctx.h, len(xs), c, _handles(mpos), _handles(xs), sketch.h, chi,
-                                  DTYPES[dtype], C.byref(h)))
+    if sketch_left is None:
+        _check(lib().mps_round_sketch(ctx.h, len(xs), c, _handles(mpos), _handles(xs), sketch.h, chi,
+                                      DTYPES[dtype], C.byref(h)))
+    else:
+        _check(lib().mps_round_sketch_two_sided(ctx.h, len(xs), c, _handles(mpos), _handles(xs),
+                                                sketch.h, sketch_left.h, chi, DTYPES[dtype],
+                                                C.byref(h)))
     return TT(ctx, h)
 
 

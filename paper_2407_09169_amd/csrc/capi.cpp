@@ -713,39 +713,71 @@ tt_status mps_round(tt_ctx* ctx, const tt_tt* x, int chi, tt_tt** out) {
   });
 }
 
+}  // extern "C"
+
+// Rounding of sum_j coeffs[j] W_j x_j by the one-sided (no left sketch) or
+// two-sided randomized range finder, then the bond truncation.
+static void round_sketch_common(tt_ctx* ctx, int n_terms, const double* coeffs,
+                                const tt_tt* const* mpos, const tt_tt* const* xs,
+                                const tt_tt* sketch, const tt_tt* sketch_left, int chi, int dtype,
+                                tt_tt** out) {
+  QTT_REQUIRE(ctx && coeffs && xs && out && n_terms >= 1 && chi >= 1, "null argument");
+  check_tt(sketch, ctx);
+  const int N = sketch->N;
+  QTT_REQUIRE(sketch->kind == TT_MPS, "sketch must be an MPS");
+  if (sketch_left) {
+    check_tt(sketch_left, ctx);
+    QTT_REQUIRE(sketch_left->N == N && sketch_left->kind == TT_MPS && sketch_left->caps == sketch->caps,
+                "left sketch must have the sketch's length and ranks");
+  }
+  std::vector<ChainView> mv(n_terms);
+  std::vector<SketchTerm> terms;
+  for (int j = 0; j < n_terms; ++j) {
+    check_tt(xs[j], ctx);
+    QTT_REQUIRE(xs[j]->N == N && xs[j]->kind == TT_MPS, "term %d shape", j);
+    SketchTerm t;
+    t.coef = coeffs[j];
+    t.x = view(xs[j]);
+    if (mpos && mpos[j]) {
+      check_tt(mpos[j], ctx);
+      QTT_REQUIRE(mpos[j]->N == N && mpos[j]->kind == TT_MPO, "operator %d shape", j);
+      mv[j] = view(mpos[j]);
+      t.mpo = &mv[j];
+    }
+    terms.push_back(t);
+  }
+  auto y = make_tt(ctx, TT_MPS, N, chain_caps(N, chi));
+  Plan plan;
+  RoundTarget tg;
+  for (int n = 0; n < N; ++n) tg.core.push_back(y->core(n));
+  tg.caps = y->caps;
+  if (sketch_left)
+    plan_round_sketch_two_sided(plan, terms, view(sketch), view(sketch_left), tg, prec_of(dtype));
+  else
+    plan_round_sketch(plan, terms, view(sketch), tg, prec_of(dtype));
+  StreamScope sc(ctx);
+  plan.run(ctx->stream);
+  rt::sync(ctx->stream);
+  *out = y.release();
+}
+
+extern "C" {
+
 tt_status mps_round_sketch(tt_ctx* ctx, int n_terms, const double* coeffs,
                            const tt_tt* const* mpos, const tt_tt* const* xs, const tt_tt* sketch,
                            int chi, int dtype, tt_tt** out) {
   return guard([&] {
-    QTT_REQUIRE(ctx && coeffs && xs && out && n_terms >= 1 && chi >= 1, "null argument");
-    check_tt(sketch, ctx);
-    const int N = sketch->N;
-    std::vector<ChainView> mv(n_terms);
-    std::vector<SketchTerm> terms;
-    for (int j = 0; j < n_terms; ++j) {
-      check_tt(xs[j], ctx);
-      QTT_REQUIRE(xs[j]->N == N && xs[j]->kind == TT_MPS, "term %d shape", j);
-      SketchTerm t;
-      t.coef = coeffs[j];
-      t.x = view(xs[j]);
-      if (mpos && mpos[j]) {
-        check_tt(mpos[j], ctx);
-        QTT_REQUIRE(mpos[j]->N == N && mpos[j]->kind == TT_MPO, "operator %d shape", j);
-        mv[j] = view(mpos[j]);
-        t.mpo = &mv[j];
-      }
-      terms.push_back(t);
-    }
-    auto y = make_tt(ctx, TT_MPS, N, chain_caps(N, chi));
-    Plan plan;
-    RoundTarget tg;
-    for (int n = 0; n < N; ++n) tg.core.push_back(y->core(n));
-    tg.caps = y->caps;
-    plan_round_sketch(plan, terms, view(sketch), tg, prec_of(dtype));
-    StreamScope sc(ctx);
-    plan.run(ctx->stream);
-    rt::sync(ctx->stream);
-    *out = y.release();
+    round_sketch_common(ctx, n_terms, coeffs, mpos, xs, sketch, nullptr, chi, dtype, out);
+  });
+}
+
+tt_status mps_round_sketch_two_sided(tt_ctx* ctx, int n_terms, const double* coeffs,
+                                     const tt_tt* const* mpos, const tt_tt* const* xs,
+                                     const tt_tt* sketch, const tt_tt* sketch_left, int chi,
+                                     int dtype, tt_tt** out) {
+  return guard([&] {
+    QTT_REQUIRE(sketch_left, "null left sketch");
+    round_sketch_common(ctx, n_terms, coeffs, mpos, xs, sketch, sketch_left, chi, dtype, out);
   });
 }
 

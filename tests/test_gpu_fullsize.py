@@ -1,0 +1,90 @@
+"""One step of the full 5-D workload (grid 1024^5 as 50 quantics cores,
+chi = 128, sketch width 144; the configuration the bench times) on the HIP
+path against the oracle's MPS stepper on the same seeded inputs (needs an
+MI355X; the oracle step takes about 15 s on the host).
+
+The tensors have 2^50 entries, so they are compared as MPSs: the difference
+a - b is written exactly as a block sum (bond 256), left-orthogonalised by
+QR, and its norm read off the last core. No inner products are subtracted,
+so the measured difference carries no cancellation error. The observables
+(integrals of section "Integrated quantities") are compared as well.
+
+Tolerances. Both sides cut every bond from the eigen-decomposition of an
+FP64 Gram matrix B B^T. Its entries carry rounding noise of about
+u sigma_1^2 (u = 2^-52), so singular directions of B below
+sqrt(u) sigma_1 (about 1.5e-8 sigma_1) are not resolved: there the two
+implementations may keep different mixtures, and each rounding may move
+its result by up to about sqrt(u) of its norm. At this size the final
+combination of a step has such a tail. On one (128^5 grid) the HIP side
+returns the exact sum to 4e-12, while the oracle's LAPACK eigensolver leaves
+9e-9. FP64
+tolerance: 3 sqrt(u) + 10 x (first-order sensitivity of the cuts) + 1e-9.
+FP32-MFMA contractions (the bench's path) accumulate in FP32: 3e-5, ten
+times the drift the bench measures against FP64 after twelve steps.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import stepper, tt
+from tests.helpers import truncation_sensitivity
+
+q = pytest.importorskip("paper_2407_09169_amd")
+
+pytestmark = pytest.mark.gpu
+
+NAME = "c3_5d_M1024_chi128"
+
+
+def _diff_norm(a, b):
+    """|| a - b ||_2 of two MPSs on the same sites (bond dimensions may differ)."""
+    N = len(a)
+    cores = []
+    for n, (A, B) in enumerate(zip(a, b)):
+        if n == 0:
+            C = np.concatenate([A, B], axis=2)
+        elif n == N - 1:
+            C = np.concatenate([A, -B], axis=0)
+        else:
+            C = np.zeros((A.shape[0] + B.shape[0], 2, A.shape[2] + B.shape[2]))
+            C[:A.shape[0], :, :A.shape[2]] = A
+            C[A.shape[0]:, :, A.shape[2]:] = B
+        cores.append(C)
+    return float(np.linalg.norm(tt.left_orthogonalize(cores)[-1]))
+
+
+def _norm(a):
+    return float(np.linalg.norm(tt.left_orthogonalize([np.asarray(G) for G in a])[-1]))
+
+
+@pytest.fixture(scope="module")
+def oracle_step():
+    w = workloads.get_workload(NAME)
+    st = stepper.MPSStepper(w)
+    f0 = st.initial_state()
+    f1, infos = st.step(f0)
+    return w, f1, st.observables(f1), truncation_sensitivity(infos)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = q.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("dtype,base_tol", [("f64", 1e-9 + 3 * np.sqrt(2.0 ** -52)), ("f32", 3e-5)])
+def test_full_size_step_matches_oracle(ctx, oracle_step, dtype, base_tol):
+    w, fo, obs_o, sens = oracle_step
+    tol = base_tol + 10 * sens
+    prob, f = q.setup_workload(ctx, w, dtype)
+    prob.step(f, 1)
+    fg = [np.asarray(G, dtype=np.float64) for G in f.cores()]
+    assert len(fg) == len(fo) == w.n_sites
+    err = _diff_norm(fg, fo) / _norm(fo)
+    print(f"{NAME} {dtype}: relative L2 difference {err:.3e} (tol {tol:.1e})", flush=True)
+    assert err < tol, (dtype, err, tol)
+    for k, v in obs_o.items():
+        g = prob.observable(f, k)
+        assert abs(g - v) <= tol * max(1.0, abs(v)), (k, g, v)
+    prob.close()

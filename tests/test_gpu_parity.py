@@ -107,6 +107,40 @@ def test_apply_and_axpby(ctx):
     assert abs(q.inner(ctx, x, y) - ip) < 1e-12 * np.linalg.norm(full(xc)) * np.linalg.norm(full(yc))
 
 
+@pytest.mark.parametrize("bonds", [[1, 1, 1, 3, 3, 1, 1, 1], [2, 1, 3, 1, 2, 1, 4, 1], [5, 5, 1, 1, 1, 1, 1, 1]])
+def test_apply_uneven_mpo_bonds(ctx, bonds):
+    """MPO x MPS with bond-1 stretches and uneven bonds (as an operator acting
+    on one dimension of a chain has) against the dense product."""
+    N = 9
+    rng = np.random.default_rng(13)
+    caps = [1] + bonds + [1]
+    Wc = [rng.standard_normal((caps[n], 2, 2, caps[n + 1])) for n in range(N)]
+    W = q.TT.from_cores(ctx, Wc, kind=q.TT_MPO)
+    xc = random_tt([1, 2, 4, 8, 8, 8, 8, 4, 2, 1], 14)
+    Wx = q.apply_mpo(ctx, W, q.TT.from_cores(ctx, xc))
+    ref = tt.mpo_full(Wc) @ full(xc).reshape(-1)
+    assert rel(full(Wx.cores()).reshape(-1), ref) < 1e-13
+
+
+@pytest.mark.parametrize("dim", [0, 1, 2, 3, 4])
+def test_apply_single_dimension_operator(ctx, dim):
+    """An operator built by mpo_build on one dimension of a 5-D chain, applied
+    with mps_apply_mpo to a random state, against the dense finite-difference
+    matrix along that axis.  (A random state: the seeded initial PDF does not
+    vary along x2 and x3, where the derivative would vanish.)"""
+    w = workloads.get_workload("t_5d_M8_chi16")
+    st = stepper.MPSStepper(w)
+    N, M = w.n_sites, w.M
+    xc = random_tt([min(2 ** n, 2 ** (N - n), 12) for n in range(N + 1)], 15 + dim)
+    op = "D1G" if dim < 2 else "D1P"
+    D = dense.d1_ghost(M) if dim < 2 else dense.d1_periodic(M)
+    F = st.to_dense(xc)
+    ref = np.moveaxis(np.tensordot(D, F, axes=(1, dim)), 0, dim)
+    W, _ = q.mpo_build(ctx, 5, w.bits, q.TT_SERIAL, [(1.0, {dim: op}, -1)])
+    y = q.apply_mpo(ctx, W, q.TT.from_cores(ctx, xc))
+    assert rel(_dense_of(st, y.cores()), ref) < 1e-13
+
+
 # --------------------------------------------------------------------- a5
 @pytest.mark.parametrize("chi", [3, 6, 64])
 def test_round_det_matches_oracle(ctx, chi):
@@ -155,6 +189,30 @@ def test_round_sketch_large_bonds(ctx, ell, chi):
     out = q.round_sketch(ctx, [1.0, 0.5], [W, None], [x, x], sk, chi, "f64")
     err = rel(full(out.cores()), full(ref))
     assert err < TRUNC_TOL, err
+
+
+@pytest.mark.parametrize("N,cap,decay,ell,chi", [(10, 24, 0.7, 20, 12), (12, 64, 0.9, 40, 32),
+                                                 (16, 160, 0.97, 144, 128)])
+def test_round_sketch_two_sided_matches_oracle(ctx, N, cap, decay, ell, chi):
+    """The two-sided rounding (the step's) against the oracle's, on sums of
+    MPO-applied chains whose spectra run well past the sketch width, so the
+    range finder and the truncation both cut real weight."""
+    caps = [min(2 ** n, 2 ** (N - n), cap) for n in range(N + 1)]
+    xc = random_tt(caps, 61, decay=decay)
+    yc = random_tt(caps, 62, decay=decay)
+    Wc = _random_mpo(N, 2, 63)
+    Z, ellr = gaussian_sketch(N, ell, 64)
+    Zl, _ = gaussian_sketch(N, ell, 65)
+    terms = [(1.0, Wc, xc), (-0.25, Wc, yc), (0.5, None, xc)]
+    ref, info = tt.round_sketch_two_sided(terms, Z, Zl, chi)
+    W = q.TT.from_cores(ctx, Wc, kind=q.TT_MPO)
+    x, y = q.TT.from_cores(ctx, xc), q.TT.from_cores(ctx, yc)
+    out = q.round_sketch(ctx, [1.0, -0.25, 0.5], [W, W, None], [x, y, x], q.TT.from_cores(ctx, Z), chi,
+                         "f64", sketch_left=q.TT.from_cores(ctx, Zl))
+    err = rel(full(out.cores()), full(ref))
+    tol = 1e-10 + 10 * truncation_sensitivity([info])
+    print(f"two-sided N={N} ell={ell} chi={chi}: {err:.3e} (tol {tol:.1e})")
+    assert err < tol, (err, tol)
 
 
 # --------------------------------------------------------------- a6 step
