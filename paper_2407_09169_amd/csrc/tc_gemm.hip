@@ -31,6 +31,7 @@ struct KRange {
 
 template <int BK>
 __device__ inline KRange k_range(const TcDesc& d) {
+  if (d.ksplit == 1 && d.ng == 1) return {(int)blockIdx.z, 0, 0, d.K};  // no split, no groups
   const int ks = (int)(blockIdx.z % (unsigned)d.ksplit);
   const int zg = (int)(blockIdx.z / (unsigned)d.ksplit);
   const int g = zg % d.ng;
@@ -132,6 +133,12 @@ __global__ __launch_bounds__(256) void tc_f64_kernel(TcDesc d, int a_kfast, int 
     return;
   }
   double* C = base_c(d, kr);
+  int64_t coff[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int n = n0 + tx + 16 * j;
+    coff[j] = n < d.N ? d.cn.off(n) : 0;
+  }
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     const int m = m0 + ty + 16 * i;
@@ -141,7 +148,7 @@ __global__ __launch_bounds__(256) void tc_f64_kernel(TcDesc d, int a_kfast, int 
     for (int j = 0; j < TN; ++j) {
       const int n = n0 + tx + 16 * j;
       if (n >= d.N) continue;
-      double* p = C + rowoff + d.cn.off(n);
+      double* p = C + rowoff + coff[j];
       double v = d.alpha * acc[i][j];
       if (d.beta != 0.0) v += d.beta * *p;
       *p = v;
@@ -284,21 +291,31 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
     return;
   }
   double* C = base_c(d, kr);
+  // output offsets: 8 distinct rows and 2 distinct columns per thread
+  int64_t coff[2];
+  bool cok[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int n = n0 + wn + 16 * j + li;
+    cok[j] = n < d.N;
+    coff[j] = cok[j] ? d.cn.off(n) : 0;
+  }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm + 16 * i + 4 * lq + r;
+      if (m >= d.M) continue;
+      const int64_t ro = d.cm.off(m);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + 16 * i + 4 * lq + r;
-        const int n = n0 + wn + 16 * j + li;
-        if (m < d.M && n < d.N) {
-          double* p = C + d.cm.off(m) + d.cn.off(n);
-          double v = d.alpha * (double)acc[i][j][r];
-          if (d.beta != 0.0) v += d.beta * *p;
-          *p = v;
-        }
+      for (int j = 0; j < 2; ++j) {
+        if (!cok[j]) continue;
+        double* p = C + ro + coff[j];
+        double v = d.alpha * (double)acc[i][j][r];
+        if (d.beta != 0.0) v += d.beta * *p;
+        *p = v;
       }
+    }
 }
 
 // C = alpha * sum part + beta * C, one thread per output element.  Outputs
