@@ -19,6 +19,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "QTT time steps/sec, 5D PDF chi=128 (MFMA FP32/BF16 vs FP64 plain) at L2 err"
 PEAKS_TFLOPS = {"bf16": 2500.0, "f32": 157.3, "f64": 78.6}
+N_CU = 256  # compute units of an MI355X
 HBM_GBS = 8000.0
 
 
@@ -108,9 +110,9 @@ def _roofline(rows):
     n, ms, fl, by = groups[what]
     kernel, shape = what.split("|", 1) if "|" in what else (what, "")
     avg_s = ms / n / 1e3
-    if kernel.startswith("tc_mfma_kernel<false>"):
+    if kernel.startswith("tc_mfma_kernel<false"):
         roof = {"bound": "mfma", "achieved": fl / n / avg_s / 1e12, "peak": PEAKS_TFLOPS["f32"], "unit": "TFLOP/s"}
-    elif kernel.startswith("tc_mfma_kernel<true>"):
+    elif kernel.startswith("tc_mfma_kernel<true"):
         roof = {"bound": "mfma", "achieved": fl / n / avg_s / 1e12, "peak": PEAKS_TFLOPS["bf16"], "unit": "TFLOP/s"}
     elif fl > 0:
         roof = {"bound": "alu", "achieved": fl / n / avg_s / 1e12, "peak": PEAKS_TFLOPS["f64"], "unit": "TFLOP/s"}
@@ -124,6 +126,13 @@ def _roofline(rows):
     roof["avg_launch_us"] = 1e6 * avg_s
     roof["algorithmic_per_launch"] = (fl / n) if fl > 0 else (by / n)
     roof["share_of_step_kernel_time"] = ms / sum(r[2] for r in rows)
+    if kernel.startswith(("qr_", "eig_")):
+        # one workgroup (one CU) per matrix: the fraction of the peak of the
+        # CUs such a launch occupies
+        m = re.match(r"b(\d+) ", shape)
+        cus = int(m.group(1)) if m else 1
+        roof["cus_per_launch"] = cus
+        roof["frac_of_cus_used"] = roof["achieved"] / (roof["peak"] * cus / N_CU)
     return roof
 
 
