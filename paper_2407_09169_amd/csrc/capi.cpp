@@ -1427,7 +1427,7 @@ tt_status tt_linalg_eigh(tt_ctx* ctx, int count, int n, int keep, const double* 
                 "bad argument");
     const size_t nn = (size_t)n * n;
     DevBuf dG(count * nn * 8), dP(count * (size_t)n * keep * 8), dL(count * (size_t)n * 8),
-        dW(count * 3 * nn * 8), dd(count * sizeof(int)), dk(count * sizeof(int));
+        dW(eig_work_size(count, n) * 8), dd(count * sizeof(int)), dk(count * sizeof(int));
     std::vector<int> dims(count, n), kp(count, keep);
     StreamScope sc(ctx);
     rt::copy(dG.p, G, count * nn * 8);

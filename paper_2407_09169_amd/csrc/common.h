@@ -240,21 +240,22 @@ TcDesc gemm_desc(int M, int N, int K, const double* A, int64_t lda, bool transA,
 // ---------------------------------------------------------------------------
 // Householder QR of `count` matrices A_i (m x n, m >= n, element (r,c) at
 // A + i*strideA + r*rs + c*cs).  Writes the thin explicit Q_i (m x n,
-// row-major, ldq = n, at Q + i*strideQ) and, if R != nullptr, R_i (n x n
-// upper triangular, row-major).  `work` must hold count*m*n doubles.
+// row-major, leading dimension ldq, default n, at Q + i*strideQ) and, if
+// R != nullptr, R_i (n x n upper triangular, row-major, same leading
+// dimension).  `work` must hold count*m*n doubles.
 // With sq != nullptr (m == n required), matrix i is sq[i] x sq[i] (<= m; none
-// when <= 0) and Q_i, R_i have leading dimension sq[i].  `work` is used only
+// when <= 0) in the top-left corner of its m x n layout.  `work` is used only
 // when no register configuration fits (qr_kernel_name(m, n) == "qr_kernel").
 void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_t rs, int64_t cs,
                double* Q, int64_t strideQ, double* R, int64_t strideR, double* work,
-               hipStream_t s, const int* sq = nullptr);
+               hipStream_t s, const int* sq = nullptr, int ldq = 0);
 
 // Eigen-decomposition of `count` symmetric PSD matrices G_i (n_i x n_i,
 // row-major, ld = ldg, at G + i*strideG); n_i = dims[i] (device array).
 // Writes the eigenvectors of the k_i = keep[i] largest eigenvalues as the
 // columns of P_i (n_i x k_i, row-major, ld = ldp, at P + i*strideP) and all
 // eigenvalues in descending order to lam + i*strideL.  `work` holds
-// 3 * count * ldg * ldg doubles.  `unoise` is the relative noise of the entries
+// eig_work_size(count, ldg) doubles.  `unoise` is the relative noise of the entries
 // of G (the machine epsilon of the arithmetic that produced it): couplings
 // below unoise * lambda_max times the column norm are not resolved.
 // With `preconditioned`, `work` must hold what eig_precondition_launch wrote
@@ -264,14 +265,19 @@ void eig_launch(int count, const int* dims, const int* keep, const double* G, in
                 int ldg, double* P, int64_t strideP, int ldp, double* lam, int64_t strideL,
                 double* work, int max_n, double unoise, hipStream_t s, bool preconditioned = false);
 
-// Whether matrices of size <= max_n take the register Jacobi kernel, which can
-// start from a QR factorisation of G.
+// Whether matrices of size <= max_n can start the sweeps from a QR
+// factorisation of G (every size the kernels take).
 bool eig_uses_precondition(int max_n);
 
+// workspace of eig_launch / eig_precondition_launch, in doubles: Q, R1, R2
+// and the workspace of the global-memory QR, count * ldg^2 each
+inline int64_t eig_work_size(int count, int ldg) { return 4 * (int64_t)count * ldg * ldg; }
+
 // Two QR factorisations, G_i = Q1_i R1_i and R1_i^T = Q2_i R2_i (n_i =
-// dims[i]), into `work` (3 * count * ldg * ldg doubles): Q2_i at
-// work + i*ldg^2, R2_i at work + (2 count + i)*ldg^2, row-major with leading
-// dimension max_n.  Needs eig_uses_precondition(max_n).
+// dims[i]), into `work` (eig_work_size(count, ldg) doubles): Q2_i at
+// work + i*ldg^2, R1_i at work + (count + i)*ldg^2, R2_i at
+// work + (2 count + i)*ldg^2, row-major with leading dimension max_n; the
+// last quarter is the workspace of the global-memory QR (max_n > 160).
 void eig_precondition_launch(int count, const int* dims, const double* G, int64_t strideG, int ldg,
                              double* work, int max_n, hipStream_t s);
 // machine epsilon of a contraction precision

@@ -92,25 +92,68 @@ __device__ inline double block_sum(double v, double* red) {
 // Householder QR:  A (m x n, m >= n) = Q R,  H_j = I - tau_j v_j v_j^T,
 // v_j(j) = 1, beta_j = -sign(a_jj) ||a_{j:,j}||.  Q formed in place by
 // backward accumulation (apply H_j to columns j+1.., then set column j).
+// General sizes, matrix in global memory (L2): 16 wavefronts, each applying
+// a reflector to QCB columns at a time (one pass over v for all of them, one
+// wavefront reduction for their QCB dot products).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(FT) void qr_kernel(int m, int n, const double* __restrict__ A0,
-                                                int64_t strideA, int64_t rs, int64_t cs,
-                                                double* __restrict__ Q0, int64_t strideQ,
-                                                double* __restrict__ R0, int64_t strideR,
-                                                double* __restrict__ work, const int* __restrict__ sq) {
-  __shared__ double red[FW];
+constexpr int QFT = 1024, QFW = QFT / 64, QCB = 4;
+
+__device__ inline double block_sum_q(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < QFW; ++w) s += red[w];
+  return s;
+}
+
+// columns c0 .. c0+QCB-1 (those < n) of the column-major W (ld m):
+// a -= tau (v^T a) v with v = column j of W below row j and v_j = 1.
+// Called by a whole wavefront (c0 wave-uniform).
+__device__ inline void qr_apply_cols(double* W, int m, int n, int j, double tau, int c0, int lane) {
+  const double* cj = W + (int64_t)j * m;
+  double p[QCB];
+#pragma unroll
+  for (int b = 0; b < QCB; ++b) p[b] = (lane == 0 && c0 + b < n) ? W[(int64_t)(c0 + b) * m + j] : 0.0;
+  for (int r = j + 1 + lane; r < m; r += 64) {
+    const double vr = cj[r];
+#pragma unroll
+    for (int b = 0; b < QCB; ++b)
+      if (c0 + b < n) p[b] = fma(vr, W[(int64_t)(c0 + b) * m + r], p[b]);
+  }
+  wave_sum_n<QCB>(p);
+#pragma unroll
+  for (int b = 0; b < QCB; ++b) {
+    if (c0 + b >= n) continue;
+    double* cc = W + (int64_t)(c0 + b) * m;
+    const double wgt = p[b] * tau;
+    if (lane == 0) cc[j] -= wgt;
+    for (int r = j + 1 + lane; r < m; r += 64) cc[r] = fma(-wgt, cj[r], cc[r]);
+  }
+}
+
+__global__ __launch_bounds__(QFT) void qr_kernel(int m, int n, const double* __restrict__ A0,
+                                                 int64_t strideA, int64_t rs, int64_t cs,
+                                                 double* __restrict__ Q0, int64_t strideQ,
+                                                 double* __restrict__ R0, int64_t strideR,
+                                                 double* __restrict__ work, const int* __restrict__ sq,
+                                                 int ldq) {
+  __shared__ double red[QFW];
   __shared__ double taus[1024];
   __shared__ double betas[1024];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t b = blockIdx.x;
   const double* A = A0 + b * strideA;
   double* W = work + b * (int64_t)m * n;  // column-major, W[c*m + r]
-  const int ldo = n;  // leading dimension of Q and R
+  const int ldo = ldq > 0 ? ldq : n;  // leading dimension of Q and R (launch n by default)
   if (sq != nullptr) {  // per-matrix square size
     m = n = sq[b];
     if (n <= 0) return;
   }
-  for (int64_t e = tid; e < (int64_t)m * n; e += FT) {
+  for (int64_t e = tid; e < (int64_t)m * n; e += QFT) {
     int r = (int)(e % m), c = (int)(e / m);
     W[e] = A[r * rs + c * cs];
   }
@@ -118,8 +161,8 @@ __global__ __launch_bounds__(FT) void qr_kernel(int m, int n, const double* __re
   for (int j = 0; j < n; ++j) {
     double* cj = W + (int64_t)j * m;
     double part = 0.0;
-    for (int r = j + 1 + tid; r < m; r += FT) part += cj[r] * cj[r];
-    double sig = block_sum(part, red);  // sum of squares below the diagonal
+    for (int r = j + 1 + tid; r < m; r += QFT) part += cj[r] * cj[r];
+    double sig = block_sum_q(part, red);  // sum of squares below the diagonal
     double x0 = cj[j];
     double tau, beta, scale;
     if (sig == 0.0) {
@@ -133,27 +176,19 @@ __global__ __launch_bounds__(FT) void qr_kernel(int m, int n, const double* __re
       scale = 1.0 / (x0 - beta);
     }
     __syncthreads();
-    for (int r = j + 1 + tid; r < m; r += FT) cj[r] *= scale;
+    for (int r = j + 1 + tid; r < m; r += QFT) cj[r] *= scale;
     if (tid == 0) {
       taus[j] = tau;
       betas[j] = beta;
     }
     __syncthreads();
-    if (tau != 0.0) {
-      for (int c = j + 1 + wave; c < n; c += FW) {
-        double* cc = W + (int64_t)c * m;
-        double p = (lane == 0) ? cc[j] : 0.0;
-        for (int r = j + 1 + lane; r < m; r += 64) p += cj[r] * cc[r];
-        double w = wave_sum(p) * tau;
-        if (lane == 0) cc[j] -= w;
-        for (int r = j + 1 + lane; r < m; r += 64) cc[r] -= w * cj[r];
-      }
-    }
+    if (tau != 0.0)
+      for (int c0 = j + 1 + wave * QCB; c0 < n; c0 += QFW * QCB) qr_apply_cols(W, m, n, j, tau, c0, lane);
     __syncthreads();
   }
   if (R0 != nullptr) {
     double* R = R0 + b * strideR;
-    for (int e = tid; e < n * n; e += FT) {
+    for (int e = tid; e < n * n; e += QFT) {
       int r = e / n, c = e % n;
       double v = 0.0;
       if (r == c) v = betas[r];
@@ -165,16 +200,10 @@ __global__ __launch_bounds__(FT) void qr_kernel(int m, int n, const double* __re
   for (int j = n - 1; j >= 0; --j) {
     const double tau = taus[j];
     double* cj = W + (int64_t)j * m;
-    for (int c = j + 1 + wave; c < n; c += FW) {
-      double* cc = W + (int64_t)c * m;
-      double p = (lane == 0) ? cc[j] : 0.0;
-      for (int r = j + 1 + lane; r < m; r += 64) p += cj[r] * cc[r];
-      double w = wave_sum(p) * tau;
-      if (lane == 0) cc[j] -= w;
-      for (int r = j + 1 + lane; r < m; r += 64) cc[r] -= w * cj[r];
-    }
+    if (tau != 0.0)
+      for (int c0 = j + 1 + wave * QCB; c0 < n; c0 += QFW * QCB) qr_apply_cols(W, m, n, j, tau, c0, lane);
     __syncthreads();
-    for (int r = tid; r < m; r += FT) {
+    for (int r = tid; r < m; r += QFT) {
       double v;
       if (r < j) v = 0.0;
       else if (r == j) v = 1.0 - tau;
@@ -184,7 +213,7 @@ __global__ __launch_bounds__(FT) void qr_kernel(int m, int n, const double* __re
     __syncthreads();
   }
   double* Q = Q0 + b * strideQ;
-  for (int64_t e = tid; e < (int64_t)m * n; e += FT) {
+  for (int64_t e = tid; e < (int64_t)m * n; e += QFT) {
     int r = (int)(e / n), c = (int)(e % n);
     Q[(int64_t)r * ldo + c] = W[(int64_t)c * m + r];
   }
@@ -238,7 +267,7 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
                                                       int64_t strideA, int64_t rs, int64_t cs,
                                                       double* __restrict__ Q0, int64_t strideQ,
                                                       double* __restrict__ R0, int64_t strideR,
-                                                      const int* __restrict__ sq) {
+                                                      const int* __restrict__ sq, int ldq) {
   __shared__ double vbuf[2][64 * RS];
   __shared__ double taus[QW * CPW];
   __shared__ double betas[QW * CPW];
@@ -246,7 +275,7 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t bi = blockIdx.x;
   const double* A = A0 + bi * strideA;
-  const int ldo = n;  // leading dimension of Q and R
+  const int ldo = ldq > 0 ? ldq : n;  // leading dimension of Q and R (launch n by default)
   if (sq != nullptr) {  // per-matrix square size
     m = n = sq[bi];
     if (n <= 0) return;
@@ -496,7 +525,7 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
                                                        int64_t strideA, int64_t rs, int64_t cs,
                                                        double* __restrict__ Q0, int64_t strideQ,
                                                        double* __restrict__ R0, int64_t strideR,
-                                                       const int* __restrict__ sq) {
+                                                       const int* __restrict__ sq, int ldq) {
   constexpr int CL = 4 * NW;
   __shared__ double vbuf[2][16 * RPL];
   __shared__ double vall[CL][16 * RPL];
@@ -507,7 +536,7 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
   const int g = lane >> 4, li = lane & 15;
   const int64_t bi = blockIdx.x;
   const double* A = A0 + bi * strideA;
-  const int ldo = n;  // leading dimension of Q and R
+  const int ldo = ldq > 0 ? ldq : n;  // leading dimension of Q and R (launch n by default)
   if (sq != nullptr) {  // per-matrix square size
     m = n = sq[bi];
     if (n <= 0) return;
@@ -625,70 +654,113 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric PSD eigen-decomposition by one-sided (Hestenes) Jacobi on G:
-// G J = U S with J accumulated; for PSD G the columns of J are eigenvectors
-// and the column norms of G J the eigenvalues.  Round-robin pair ordering,
-// sweeps until no pair needs a rotation.
+// Symmetric PSD eigen-decomposition by one-sided (Hestenes) Jacobi, general
+// sizes, columns in global memory (L2), 16 wavefronts.  Either from W = G,
+// V = I, or (preconditioned) from W = R^T, V = Q where G = Q1 R^T Q^T comes
+// from two QR factorisations (Q, R1, R2 as eig_precondition_launch leaves
+// them): W is then R2 itself (its row c is column c of W) and V is written
+// into R1's space, which the second factorisation no longer needs.  Round-
+// robin pair ordering; a pair is left alone when its cross product is below
+// 1e-15 |w_p| |w_q| or below the noise of the columns, u * lambda_max *
+// max(|w_p|, |w_q|) (compared in squares); sweeps until no pair rotates.  For
+// PSD G the columns of V J are eigenvectors and the column norms of W J the
+// eigenvalues.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(FT) void eig_kernel(const int* dims, const int* keep,
-                                                 const double* __restrict__ G0, int64_t strideG,
-                                                 int ldg, double* __restrict__ P0, int64_t strideP,
-                                                 int ldp, double* __restrict__ L0, int64_t strideL,
-                                                 double* __restrict__ work) {
+constexpr int EFT = 1024, EFW = EFT / 64;
+
+__global__ __launch_bounds__(EFT) void eig_kernel(const int* dims, const int* keep,
+                                                  const double* __restrict__ G0, int64_t strideG,
+                                                  int ldg, double* __restrict__ P0, int64_t strideP,
+                                                  int ldp, double* __restrict__ L0, int64_t strideL,
+                                                  double* __restrict__ work, double unoise,
+                                                  const double* __restrict__ Qp, double* __restrict__ R1p,
+                                                  double* __restrict__ R2p, int64_t strideQR, int ldqr) {
   __shared__ int changed;
+  __shared__ double gmax;
   __shared__ double nrm[1024];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t b = blockIdx.x;
   const int n = dims[b];
   const int k = keep[b];
+  if (n <= 0) return;
   const double* G = G0 + b * strideG;
   double* P = P0 + b * strideP;
   double* L = L0 + b * strideL;
-  double* Wm = work + b * (int64_t)ldg * ldg * 2;  // G J, column-major
-  double* V = Wm + (int64_t)ldg * ldg;              // J, column-major
-  if (n <= 0) return;
-  for (int e = tid; e < n * n; e += FT) {
-    int r = e % n, c = e / n;
-    Wm[(int64_t)c * n + r] = G[(int64_t)r * ldg + c];
-    V[(int64_t)c * n + r] = (r == c) ? 1.0 : 0.0;
+  double *Wm, *V;
+  int ld;
+  if (Qp != nullptr) {
+    const double* Q = Qp + b * strideQR;
+    Wm = R2p + b * strideQR;
+    V = R1p + b * strideQR;
+    ld = ldqr;
+    for (int e = tid; e < n * n; e += EFT) {
+      const int r = e % n, c = e / n;
+      V[(int64_t)c * ld + r] = Q[(int64_t)r * ldqr + c];
+    }
+  } else {
+    Wm = work + b * (int64_t)ldg * ldg * 2;  // G J, column-major
+    V = Wm + (int64_t)ldg * ldg;             // J, column-major
+    ld = n;
+    for (int e = tid; e < n * n; e += EFT) {
+      const int r = e % n, c = e / n;
+      Wm[(int64_t)c * ld + r] = G[(int64_t)r * ldg + c];
+      V[(int64_t)c * ld + r] = (r == c) ? 1.0 : 0.0;
+    }
   }
   __syncthreads();
   const int np = n + (n & 1);  // even number of players (a dummy when n is odd)
   const int K = np - 1;
   for (int sweep = 0; sweep < 40 && np > 1; ++sweep) {
+    // largest squared column norm: the noise level of this sweep
+    for (int c = wave; c < n; c += EFW) {
+      double sq = 0.0;
+      for (int r = lane; r < n; r += 64) sq += Wm[(int64_t)c * ld + r] * Wm[(int64_t)c * ld + r];
+      sq = wave_sum(sq);
+      if (lane == 0) nrm[c] = sq;
+    }
     if (tid == 0) changed = 0;
     __syncthreads();
+    if (tid == 0) {
+      double mx = 0.0;
+      for (int c = 0; c < n; ++c) mx = fmax(mx, nrm[c]);
+      gmax = mx;
+    }
+    __syncthreads();
+    const double gf2 = unoise * unoise * gmax;
     for (int rnd = 0; rnd < K; ++rnd) {
-      for (int i = wave; i < np / 2; i += FW) {
+      for (int i = wave; i < np / 2; i += EFW) {
         int p, q;
         if (i == 0) { p = rnd % K; q = K; }
         else { p = (rnd + i) % K; q = (rnd + K - i) % K; }
         if (p >= n || q >= n) continue;
-        double* wp = Wm + (int64_t)p * n;
-        double* wq = Wm + (int64_t)q * n;
-        double a = 0.0, bb = 0.0, g = 0.0;
+        double* wp = Wm + (int64_t)p * ld;
+        double* wq = Wm + (int64_t)q * ld;
+        double s3[3] = {0.0, 0.0, 0.0};
+#pragma unroll 4
         for (int r = lane; r < n; r += 64) {
-          double x = wp[r], y = wq[r];
-          a += x * x;
-          bb += y * y;
-          g += x * y;
+          const double x = wp[r], y = wq[r];
+          s3[0] = fma(x, x, s3[0]);
+          s3[1] = fma(y, y, s3[1]);
+          s3[2] = fma(x, y, s3[2]);
         }
-        a = wave_sum(a);
-        bb = wave_sum(bb);
-        g = wave_sum(g);
-        if (fabs(g) <= 1e-15 * sqrt(a * bb) || g == 0.0) continue;
-        double zeta = (bb - a) / (2.0 * g);
-        double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        wave_sum_n<3>(s3);
+        const double a = s3[0], bb = s3[1], g = s3[2];
+        const double g2 = g * g;
+        if (!(g2 > 1e-30 * a * bb && g2 > gf2 * fmax(a, bb))) continue;
+        const double zeta = (bb - a) / (2.0 * g);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+#pragma unroll 4
         for (int r = lane; r < n; r += 64) {
-          double x = wp[r], y = wq[r];
+          const double x = wp[r], y = wq[r];
           wp[r] = c * x - s * y;
           wq[r] = s * x + c * y;
         }
-        double* vp = V + (int64_t)p * n;
-        double* vq = V + (int64_t)q * n;
+        double* vp = V + (int64_t)p * ld;
+        double* vq = V + (int64_t)q * ld;
+#pragma unroll 4
         for (int r = lane; r < n; r += 64) {
-          double x = vp[r], y = vq[r];
+          const double x = vp[r], y = vq[r];
           vp[r] = c * x - s * y;
           vq[r] = s * x + c * y;
         }
@@ -699,22 +771,22 @@ __global__ __launch_bounds__(FT) void eig_kernel(const int* dims, const int* kee
     if (!changed) break;
     __syncthreads();
   }
-  // eigenvalues = column norms of G J
-  for (int c = wave; c < n; c += FW) {
-    double s = 0.0;
-    for (int r = lane; r < n; r += 64) s += Wm[(int64_t)c * n + r] * Wm[(int64_t)c * n + r];
-    s = wave_sum(s);
-    if (lane == 0) nrm[c] = sqrt(s);
+  // eigenvalues = column norms of W J
+  for (int c = wave; c < n; c += EFW) {
+    double sq = 0.0;
+    for (int r = lane; r < n; r += 64) sq += Wm[(int64_t)c * ld + r] * Wm[(int64_t)c * ld + r];
+    sq = wave_sum(sq);
+    if (lane == 0) nrm[c] = sqrt(sq);
   }
   __syncthreads();
   // rank of each column by descending eigenvalue (ties by index)
-  for (int c = tid; c < n; c += FT) {
-    double v = nrm[c];
+  for (int c = tid; c < n; c += EFT) {
+    const double v = nrm[c];
     int rank = 0;
     for (int o = 0; o < n; ++o) rank += (nrm[o] > v) || (nrm[o] == v && o < c);
     L[rank] = v;
     if (rank < k)
-      for (int r = 0; r < n; ++r) P[(int64_t)r * ldp + rank] = V[(int64_t)c * n + r];
+      for (int r = 0; r < n; ++r) P[(int64_t)r * ldp + rank] = V[(int64_t)c * ld + r];
   }
 }
 
@@ -1037,7 +1109,7 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
 // waves, reduction chunk); larger problems use the global-memory kernels
 #define QTT_QR_CONFIGS(X) X(1, 1, 16, 1) X(1, 2, 16, 2) X(2, 2, 16, 2) X(2, 4, 16, 4)
 // one column per 16-lane group: (rows per lane, column slots, waves)
-#define QTT_QRG_CONFIGS(X) X(12, 3, 8) X(16, 4, 8) X(9, 5, 8) X(18, 5, 8)
+#define QTT_QRG_CONFIGS(X) X(12, 3, 8) X(16, 4, 8) X(9, 5, 8) X(18, 5, 8) X(36, 1, 8)
 // larger than the group configurations
 #define QTT_QR_CONFIGS_LARGE(X) X(5, 10, 16, 2)
 #define QTT_EIG_CONFIGS(X) \
@@ -1083,14 +1155,17 @@ std::string eig_kernel_name(int max_n) {
 
 void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_t rs, int64_t cs,
                double* Q, int64_t strideQ, double* R, int64_t strideR, double* work,
-               hipStream_t s, const int* sq) {
+               hipStream_t s, const int* sq, int ldq) {
   if (count <= 0) return;
   QTT_REQUIRE(m >= n && n >= 1 && n <= 1024, "qr: need m >= n, 1 <= n <= 1024 (m=%d n=%d)", m, n);
   QTT_REQUIRE(sq == nullptr || m == n, "qr: per-matrix sizes need square matrices");
+  QTT_REQUIRE(ldq == 0 || ldq >= n, "qr: ld of Q below n");
+  const int lq = ldq > 0 ? ldq : n;
   rt::check_range(A, 0, (int64_t)(count - 1) * strideA + (int64_t)(m - 1) * rs + (int64_t)(n - 1) * cs,
                   sizeof(double), "qr input");
-  rt::check_range(Q, 0, (int64_t)(count - 1) * strideQ + (int64_t)m * n - 1, sizeof(double), "qr Q");
-  if (R) rt::check_range(R, 0, (int64_t)(count - 1) * strideR + (int64_t)n * n - 1, sizeof(double), "qr R");
+  rt::check_range(Q, 0, (int64_t)(count - 1) * strideQ + (int64_t)(m - 1) * lq + n - 1, sizeof(double), "qr Q");
+  if (R) rt::check_range(R, 0, (int64_t)(count - 1) * strideR + (int64_t)(n - 1) * lq + n - 1, sizeof(double),
+                         "qr R");
   if (sq) rt::check_range(sq, 0, count - 1, sizeof(int), "qr sizes");
   const bool generic = qr_kernel_name(m, n) == "qr_kernel";
   if (generic) rt::check_range(work, 0, (int64_t)count * m * n - 1, sizeof(double), "qr workspace");
@@ -1098,7 +1173,7 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
 #define QTT_QR_REG(RS_, CPW_, NW_, CH_)                                                           \
   if (m <= 64 * RS_ && n <= NW_ * CPW_) {                                                         \
     hipLaunchKernelGGL((qr_reg_kernel<RS_, CPW_, NW_, CH_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
-                       strideA, rs, cs, Q, strideQ, R, strideR, sq);                             \
+                       strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq);                             \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }
@@ -1107,7 +1182,7 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
 #define QTT_QR_GRP(RPL_, CS_, NW_)                                                                \
   if (m <= 16 * RPL_ && n <= 4 * NW_ * CS_) {                                                     \
     hipLaunchKernelGGL((qr_grp_kernel<RPL_, CS_, NW_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
-                       strideA, rs, cs, Q, strideQ, R, strideR, sq);                             \
+                       strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq);                             \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }
@@ -1116,24 +1191,18 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
 #define QTT_QR_REG(RS_, CPW_, NW_, CH_)                                                           \
   if (m <= 64 * RS_ && n <= NW_ * CPW_) {                                                         \
     hipLaunchKernelGGL((qr_reg_kernel<RS_, CPW_, NW_, CH_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
-                       strideA, rs, cs, Q, strideQ, R, strideR, sq);                             \
+                       strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq);                             \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }
   QTT_QR_CONFIGS_LARGE(QTT_QR_REG)
 #undef QTT_QR_REG
-  hipLaunchKernelGGL(qr_kernel, dim3(count), dim3(FT), 0, s, m, n, A, strideA, rs, cs, Q, strideQ,
-                     R, strideR, work, sq);
+  hipLaunchKernelGGL(qr_kernel, dim3(count), dim3(QFT), 0, s, m, n, A, strideA, rs, cs, Q, strideQ,
+                     R, strideR, work, sq, ldq);
   QTT_HIP(hipGetLastError());
 }
 
-bool eig_uses_precondition(int max_n) {
-#define QTT_EIG_FITS(RS_, PPW_, NW_, CH_) \
-  if (max_n <= 64 * RS_ && max_n <= 2 * NW_ * PPW_) return true;
-  QTT_EIG_CONFIGS(QTT_EIG_FITS)
-#undef QTT_EIG_FITS
-  return false;
-}
+bool eig_uses_precondition(int max_n) { return max_n >= 1 && max_n <= 1024; }
 
 void eig_precondition_launch(int count, const int* dims, const double* G, int64_t strideG, int ldg,
                              double* work, int max_n, hipStream_t s) {
@@ -1141,15 +1210,16 @@ void eig_precondition_launch(int count, const int* dims, const double* G, int64_
   QTT_REQUIRE(eig_uses_precondition(max_n), "eig: no preconditioned configuration for n = %d", max_n);
   QTT_REQUIRE(max_n <= ldg, "eig: n <= ldg");
   const int64_t st = (int64_t)ldg * ldg;
-  rt::check_range(work, 0, (int64_t)count * 3 * st - 1, sizeof(double), "eig workspace");
+  rt::check_range(work, 0, eig_work_size(count, ldg) - 1, sizeof(double), "eig workspace");
   double* Q = work;
   double* R1 = work + count * st;
   double* R2 = work + 2 * count * st;
+  double* qw = work + 3 * count * st;  // global-memory QR workspace (count * max_n^2 <= count * st)
   // G = Q1 R1 and R1^T = Q2 R2 give G = Q1 R2^T Q2^T: the sweeps run on
   // W = R2^T from V = Q2 (Q2 overwrites Q1, which is not needed).  Two
   // factorisations leave the columns closer to orthogonal than one.
-  qr_launch(count, max_n, max_n, G, strideG, ldg, 1, Q, st, R1, st, nullptr, s, dims);
-  qr_launch(count, max_n, max_n, R1, st, 1, max_n, Q, st, R2, st, nullptr, s, dims);
+  qr_launch(count, max_n, max_n, G, strideG, ldg, 1, Q, st, R1, st, qw, s, dims);
+  qr_launch(count, max_n, max_n, R1, st, 1, max_n, Q, st, R2, st, qw, s, dims);
 }
 
 void eig_launch(int count, const int* dims, const int* keep, const double* G, int64_t strideG,
@@ -1164,7 +1234,7 @@ void eig_launch(int count, const int* dims, const int* keep, const double* G, in
   rt::check_range(P, 0, (int64_t)(count - 1) * strideP + (int64_t)(max_n - 1) * ldp + ldp - 1,
                   sizeof(double), "eig vectors");
   rt::check_range(lam, 0, (int64_t)(count - 1) * strideL + max_n - 1, sizeof(double), "eig values");
-  rt::check_range(work, 0, (int64_t)count * 3 * ldg * ldg - 1, sizeof(double), "eig workspace");
+  rt::check_range(work, 0, eig_work_size(count, ldg) - 1, sizeof(double), "eig workspace");
   QTT_REQUIRE(!preconditioned || eig_uses_precondition(max_n), "eig: no preconditioned configuration");
   if (rt::dry()) return;
   const int64_t st = (int64_t)ldg * ldg;
@@ -1180,8 +1250,9 @@ void eig_launch(int count, const int* dims, const int* keep, const double* G, in
   }
   QTT_EIG_CONFIGS(QTT_EIG_REG)
 #undef QTT_EIG_REG
-  hipLaunchKernelGGL(eig_kernel, dim3(count), dim3(FT), 0, s, dims, keep, G, strideG, ldg, P,
-                     strideP, ldp, lam, strideL, work);
+  hipLaunchKernelGGL(eig_kernel, dim3(count), dim3(EFT), 0, s, dims, keep, G, strideG, ldg, P,
+                     strideP, ldp, lam, strideL, work, unoise, Qf, preconditioned ? work + count * st : nullptr,
+                     preconditioned ? work + 2 * count * st : nullptr, st, max_n);
   QTT_HIP(hipGetLastError());
 }
 

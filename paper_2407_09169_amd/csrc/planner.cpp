@@ -246,7 +246,7 @@ static void plan_trunc_gram(Plan& plan, const std::vector<double*>& X, const std
   double* Gam = plan.alloc((size_t)(N + 1) * ldg * ldg);
   double* P = plan.alloc((size_t)(N + 1) * ldg * ldp);
   double* lam = plan.alloc((size_t)(N + 1) * ldg);
-  double* ework = plan.alloc((size_t)std::max(1, N - 1) * 3 * ldg * ldg);
+  double* ework = plan.alloc((size_t)eig_work_size(std::max(1, N - 1), ldg));
   size_t tsz = 1, vsz = 1;
   for (int n = 0; n < N; ++n) {
     tsz = std::max(tsz, (size_t)2 * ell[n] * ell[n + 1]);

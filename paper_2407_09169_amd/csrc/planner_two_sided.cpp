@@ -460,7 +460,7 @@ void ts_setup(Plan& plan, TwoSided& r, const std::vector<SketchTerm>& terms, Rou
   r.Gam = plan.alloc((size_t)(N + 1) * r.ldg * r.ldg);
   r.P = plan.alloc((size_t)(N + 1) * r.ldg * r.ldp);
   r.lam = plan.alloc((size_t)(N + 1) * r.ldg);
-  r.ework = plan.alloc((size_t)std::max(1, N - 1) * 3 * r.ldg * r.ldg);
+  r.ework = plan.alloc((size_t)eig_work_size(std::max(1, N - 1), r.ldg));
   size_t tsz = 1;
   for (int n = 0; n < N; ++n) {
     tsz = std::max(tsz, (size_t)2 * ell[n] * ell[n + 1]);

@@ -88,3 +88,27 @@ def test_full_size_step_matches_oracle(ctx, oracle_step, dtype, base_tol):
         g = prob.observable(f, k)
         assert abs(g - v) <= tol * max(1.0, abs(v)), (k, g, v)
     prob.close()
+
+
+def test_chi256_step_properties(ctx):
+    """The chi = 256 case of the same workload (sketch width 288: its QR and
+    eigen problems exceed one CU's registers and run on the global-memory
+    kernels). An oracle step at this size takes over a minute on the host, so
+    one step is checked through properties that hold at any size: FP32 and
+    FP64 paths agree to the FP32 tolerance above, mass is kept to the weight
+    the roundings discard, and every core is finite."""
+    w = workloads.get_workload("c3_5d_M1024_chi256")
+    out = {}
+    for dtype in ("f64", "f32"):
+        prob, f = q.setup_workload(ctx, w, dtype)
+        m0 = prob.observable(f, "mass")
+        prob.step(f, 1)
+        m1 = prob.observable(f, "mass")
+        cores = [np.asarray(G, dtype=np.float64) for G in f.cores()]
+        assert all(np.all(np.isfinite(G)) for G in cores), dtype
+        assert abs(m1 - m0) <= 1e-6 * abs(m0), (dtype, m0, m1)
+        out[dtype] = cores
+        prob.close()
+    err = _diff_norm(out["f32"], out["f64"]) / _norm(out["f64"])
+    print(f"c3_5d_M1024_chi256: FP32 vs FP64 after one step {err:.3e}", flush=True)
+    assert err < 3e-5, err

@@ -16,7 +16,7 @@ def ctx():
 
 @pytest.mark.parametrize("m,n", [(2, 1), (4, 4), (8, 5), (32, 16), (64, 64), (128, 64), (96, 90),
                                  (192, 96), (200, 100), (256, 128), (257, 129), (288, 144), (290, 140),
-                                 (320, 160), (512, 256)])
+                                 (320, 160), (512, 256), (576, 288), (333, 257), (576, 32), (500, 30)])
 def test_qr(ctx, m, n):
     rng = np.random.default_rng(m * 1000 + n)
     A = rng.standard_normal((3, m, n))
@@ -30,7 +30,7 @@ def test_qr(ctx, m, n):
 
 
 @pytest.mark.parametrize("n,keep", [(1, 1), (2, 1), (2, 2), (3, 2), (5, 3), (16, 16), (33, 20), (64, 48), (100, 100),
-                                    (128, 120), (144, 128)])
+                                    (128, 120), (144, 128), (288, 256)])
 def test_eigh(ctx, n, keep):
     rng = np.random.default_rng(n * 7 + keep)
     X = rng.standard_normal((3, n, n + 4)) * np.logspace(0, -6, n + 4)[None, None, :]
