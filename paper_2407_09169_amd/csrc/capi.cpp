@@ -359,10 +359,8 @@ struct Tangent {
 //   B_q = dA_fix/dq - sum_a D1g^(phi_a) diag(alpha_q <Phi_a>(g_i) + Omega <Phi_a>(dg_i)),
 // alpha_Omega = 1, alpha_k = 0 (the mean field enters A through -Omega m_a(g)),
 // and df+ = Round(df + sum_i b_i dk_i) beside f+ = Round(f + sum_i b_i k_i).
-static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vector<Tangent>& tan,
-                                         bool lanes = true) {
+static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vector<Tangent>& tan) {
   auto plan = std::make_unique<Plan>();
-  plan->no_lanes = !lanes;
   const tt_params& p = P->p;
   const Prec prec = prec_of(p.dtype);
   ChainView Z = view(P->Z.get());

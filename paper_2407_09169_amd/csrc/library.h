@@ -82,7 +82,6 @@ struct Plan {
   std::vector<hipStream_t> streams;  // lanes 1..
   std::vector<hipEvent_t> events;
   int cur = 0;  // lane of the next op
-  bool no_lanes = false;  // record every op on lane 0 (fork / join record nothing)
   Plan() = default;
   Plan(const Plan&) = delete;
   Plan& operator=(const Plan&) = delete;
@@ -130,7 +129,7 @@ struct Plan {
 // lanes a planner may fork into (at most `want`): 1 unless it records on
 // lane 0 of a plan with lanes
 inline int lane_budget(const Plan& plan, int want) {
-  if (plan.cur != 0 || plan.no_lanes) return 1;
+  if (plan.cur != 0) return 1;
   return std::max(1, want);
 }
 

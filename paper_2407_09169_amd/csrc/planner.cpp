@@ -119,7 +119,6 @@ hipEvent_t Plan::new_event() {
 }
 
 void Plan::ensure_lanes(int n) {
-  QTT_REQUIRE(!no_lanes || n <= 1, "plan recorded without lanes");
   while ((int)streams.size() < n - 1) {
     hipStream_t st = nullptr;
     if (!rt::dry()) QTT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -128,7 +127,7 @@ void Plan::ensure_lanes(int n) {
 }
 
 void Plan::fork(int n) {
-  if (n <= 1 || no_lanes) return;  // single lane: nothing to order
+  if (n <= 1) return;  // single lane: nothing to order
   QTT_REQUIRE(cur == 0, "fork from lane 0 only");
   ensure_lanes(n);
   OpInfo rec, wait;
@@ -149,7 +148,7 @@ void Plan::fork(int n) {
 }
 
 void Plan::join(int n) {
-  if (n <= 1 || no_lanes) return;
+  if (n <= 1) return;
   QTT_REQUIRE(cur < n, "join of lanes that were not forked");
   OpInfo rec, wait;
   rec.kind = wait.kind = OP_SYNC;
