@@ -126,9 +126,9 @@ def _roofline(rows):
     roof["avg_launch_us"] = 1e6 * avg_s
     roof["algorithmic_per_launch"] = (fl / n) if fl > 0 else (by / n)
     roof["share_of_step_kernel_time"] = ms / sum(r[2] for r in rows)
-    if kernel.startswith(("qr_", "eig_")):
+    if kernel.startswith(("qr_", "eig_")) and kernel != "qr_blocked":
         # one workgroup (one CU) per matrix: the fraction of the peak of the
-        # CUs such a launch occupies
+        # CUs such a launch occupies (the blocked QR spreads over the chip)
         m = re.match(r"b(\d+) ", shape)
         cus = int(m.group(1)) if m else 1
         roof["cus_per_launch"] = cus

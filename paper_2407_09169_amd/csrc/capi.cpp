@@ -1407,11 +1407,12 @@ tt_status tt_linalg_qr(tt_ctx* ctx, int count, int m, int n, const double* A, do
   return guard([&] {
     QTT_REQUIRE(ctx && A && Q && count >= 1 && n >= 1 && m >= n && n <= 1024, "bad argument");
     const size_t mn = (size_t)m * n, nn = (size_t)n * n;
-    DevBuf dA(count * mn * 8), dQ(count * mn * 8), dR(count * nn * 8), dW(count * mn * 8);
+    const int64_t ws = qr_work_size(count, m, n);
+    DevBuf dA(count * mn * 8), dQ(count * mn * 8), dR(count * nn * 8), dW((size_t)ws * 8);
     StreamScope sc(ctx);
     rt::copy(dA.p, A, count * mn * 8);
     qr_launch(count, m, n, dA.d(), (int64_t)mn, n, 1, dQ.d(), (int64_t)mn, R ? dR.d() : nullptr,
-              (int64_t)nn, dW.d(), ctx->stream);
+              (int64_t)nn, dW.d(), ctx->stream, nullptr, 0, ws);
     rt::sync(ctx->stream);
     rt::copy(Q, dQ.p, count * mn * 8);
     if (R) rt::copy(R, dR.p, count * nn * 8);

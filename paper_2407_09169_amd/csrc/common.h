@@ -226,6 +226,9 @@ inline int64_t tc_part_size(const TcDesc& d) { return (int64_t)d.batch * d.ng * 
 // name of the kernel (template instantiation) a launch uses
 std::string tc_kernel_name(const TcDesc& d, Prec p);
 std::string qr_kernel_name(int m, int n);
+// what factorises one m x n matrix given qr_work_size(1, m, n) of workspace:
+// a register kernel's name, "qr_blocked", or "qr_kernel"
+std::string qr_path_name(int m, int n);
 std::string eig_kernel_name(int max_n);
 // host-side bounds check of a contraction against the allocation registry
 void tc_validate(const TcDesc& d);
@@ -245,10 +248,20 @@ TcDesc gemm_desc(int M, int N, int K, const double* A, int64_t lda, bool transA,
 // dimension).  `work` must hold count*m*n doubles.
 // With sq != nullptr (m == n required), matrix i is sq[i] x sq[i] (<= m; none
 // when <= 0) in the top-left corner of its m x n layout.  `work` is used only
-// when no register configuration fits (qr_kernel_name(m, n) == "qr_kernel").
+// when no register configuration fits (qr_kernel_name(m, n) == "qr_kernel");
+// then one matrix with m <= 576 and work_size >= qr_work_size(1, m, n) is
+// factorised by blocked Householder (32-column register panels, compact WY
+// updates on the whole chip) instead of the single-workgroup kernel.
 void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_t rs, int64_t cs,
                double* Q, int64_t strideQ, double* R, int64_t strideR, double* work,
-               hipStream_t s, const int* sq = nullptr, int ldq = 0);
+               hipStream_t s, const int* sq = nullptr, int ldq = 0, int64_t work_size = -1);
+
+// workspace that lets a single matrix beyond the register kernels (m <= 576)
+// take the blocked Householder QR (pass it as work_size); otherwise
+// count * m * n doubles suffice
+inline int64_t qr_work_size(int count, int m, int n) {
+  return (int64_t)count * m * n + (count == 1 ? (int64_t)m * n + 97 * (int64_t)n + 64 * 32 * (int64_t)n : 0);
+}
 
 // Eigen-decomposition of `count` symmetric PSD matrices G_i (n_i x n_i,
 // row-major, ld = ldg, at G + i*strideG); n_i = dims[i] (device array).

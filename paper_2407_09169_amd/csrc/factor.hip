@@ -525,7 +525,8 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
                                                        int64_t strideA, int64_t rs, int64_t cs,
                                                        double* __restrict__ Q0, int64_t strideQ,
                                                        double* __restrict__ R0, int64_t strideR,
-                                                       const int* __restrict__ sq, int ldq) {
+                                                       const int* __restrict__ sq, int ldq,
+                                                       double* __restrict__ Vout, double* __restrict__ tout) {
   constexpr int CL = 4 * NW;
   __shared__ double vbuf[2][16 * RPL];
   __shared__ double vall[CL][16 * RPL];
@@ -603,6 +604,20 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
         R[(int64_t)row * ldo + c] = (row < c) ? a[j][r] : (row == c ? betas[c] : 0.0);
       }
     }
+  }
+  if (Vout != nullptr) {  // panel of a blocked QR: reflectors (m x n, unit diagonal) and taus, no Q
+#pragma unroll
+    for (int j = 0; j < CS; ++j) {
+      const int c = CL * j + 4 * w + g;
+      if (c >= n) continue;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int row = li + 16 * r;
+        if (row < m) Vout[(int64_t)row * n + c] = (row > c) ? a[j][r] : (row == c ? 1.0 : 0.0);
+      }
+    }
+    for (int c = threadIdx.x; c < n; c += NW * 64) tout[c] = taus[c];
+    return;
   }
   // ---- thin Q by backward accumulation, one slot phase at a time (in
   // reverse): the reflectors of the phase's CL columns are published together,
@@ -1153,9 +1168,154 @@ std::string eig_kernel_name(int max_n) {
   return "eig_kernel";
 }
 
+namespace {
+
+// ---------------------------------------------------------------------------
+// Blocked Householder QR of one m x n matrix (m <= 576) too wide for the
+// register kernels: 32-column panels factorised in registers (reflectors
+// and taus written out), the compact WY form Q_p = I - V T V^T of each
+// panel (T upper triangular from V^T V and the taus), the trailing columns
+// updated by Q_p^T with three FP64 contractions across the chip, and the thin
+// Q accumulated backwards from [I; 0] by the same blocks.  R is the factored
+// upper triangle.
+// ---------------------------------------------------------------------------
+constexpr int QB = 32;       // panel width
+constexpr int QB_MAXM = 576; // rows of the register panel kernel (16 * 36)
+
+// dst[r * ldd + c] = src[r * rs + c * cs], r < m, c < n
+__global__ void qrb_copy_kernel(double* __restrict__ dst, int ldd, const double* __restrict__ src, int64_t rs,
+                                int64_t cs, int m, int n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * n) return;
+  const int r = (int)(e / n), c = (int)(e % n);
+  dst[(int64_t)r * ldd + c] = src[r * rs + c * cs];
+}
+
+// Q (m x n, ld ldq) = [I; 0]
+__global__ void qrb_eye_kernel(double* __restrict__ Q, int ldq, int m, int n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)m * n) return;
+  const int r = (int)(e / n), c = (int)(e % n);
+  Q[(int64_t)r * ldq + c] = (r == c) ? 1.0 : 0.0;
+}
+
+// R (n x n, ld ldr) = upper triangle of W (ld n)
+__global__ void qrb_upper_kernel(double* __restrict__ R, int ldr, const double* __restrict__ W, int n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const int r = (int)(e / n), c = (int)(e % n);
+  R[(int64_t)r * ldr + c] = (r <= c) ? W[(int64_t)r * n + c] : 0.0;
+}
+
+// T (w x w, ld w, upper triangular) of the compact WY form of w reflectors
+// V (mr x w, ld w): T_jj = tau_j, T_(0:j, j) = -tau_j T_(0:j, 0:j) V_(:, 0:j)^T v_j.
+__global__ __launch_bounds__(256) void qrb_t_kernel(const double* __restrict__ V, int mr, int w,
+                                                    const double* __restrict__ taus, double* __restrict__ T) {
+  __shared__ double S[QB][QB + 1];
+  __shared__ double Ts[QB][QB + 1];
+  for (int e = threadIdx.x; e < w * w; e += 256) {
+    const int i = e / w, j = e % w;
+    double acc = 0.0;
+    for (int r = 0; r < mr; ++r) acc = fma(V[(int64_t)r * w + i], V[(int64_t)r * w + j], acc);
+    S[i][j] = acc;
+    Ts[i][j] = 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    const double tj = taus[j];
+    if ((int)threadIdx.x < j) {
+      const int i = threadIdx.x;
+      double acc = 0.0;
+      for (int k = i; k < j; ++k) acc = fma(Ts[i][k], S[k][j], acc);
+      Ts[i][j] = -tj * acc;
+    }
+    if (threadIdx.x == 0) Ts[j][j] = tj;
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < w * w; e += 256) T[e] = Ts[e / w][e % w];
+}
+
+// C = alpha op(A) op(B) + beta C in FP64, K split when that helps (partials in `part`)
+void qrb_gemm(TcDesc d, double* part, hipStream_t s) {
+  d.ksplit = tc_choose_ksplit(d, Prec::F64);
+  if (tc_uses_part(d)) d.part = part;
+  tc_launch(d, Prec::F64, s);
+}
+
+void qr_blocked(int m, int n, const double* A, int64_t rs, int64_t cs, double* Q, int ldq, double* R, double* work,
+                hipStream_t s) {
+  double* W = work;                          // m x n, ld n
+  double* Vall = W + (int64_t)m * n;         // panels' reflectors, compact, (m - p0) x w each
+  double* Tall = Vall + (int64_t)m * n;      // QB x QB per panel
+  double* taus = Tall + (int64_t)n * QB;     // n
+  double* W1 = taus + n;                     // QB x n
+  double* W2 = W1 + (int64_t)QB * n;         // QB x n
+  double* part = W2 + (int64_t)QB * n;       // K-split partials, <= 64 * QB * n
+  auto grid = [](int64_t tot) { return dim3((unsigned)((tot + 255) / 256)); };
+  const bool run = !rt::dry();  // dry runs validate the contractions' ranges only
+  if (run) {
+    hipLaunchKernelGGL(qrb_copy_kernel, grid((int64_t)m * n), dim3(256), 0, s, W, n, A, rs, cs, m, n);
+    QTT_HIP(hipGetLastError());
+  }
+  std::vector<int64_t> voff;
+  int64_t vo = 0;
+  for (int p0 = 0; p0 < n; p0 += QB) {
+    const int w = std::min(QB, n - p0), mr = m - p0;
+    double* Vp = Vall + vo;
+    double* Tp = Tall + (int64_t)p0 * QB;
+    voff.push_back(vo);
+    vo += (int64_t)mr * w;
+    double* Wp = W + (int64_t)p0 * n + p0;
+    // panel: reflectors to Vp, taus, its R block (w x w, ld n) to W2, then into W
+    if (run) {
+      hipLaunchKernelGGL((qr_grp_kernel<36, 1, 8>), dim3(1), dim3(512), 0, s, mr, w, (const double*)Wp, (int64_t)0,
+                         (int64_t)n, (int64_t)1, (double*)nullptr, (int64_t)0, W2, (int64_t)0, (const int*)nullptr,
+                         n, Vp, taus + p0);
+      QTT_HIP(hipGetLastError());
+      hipLaunchKernelGGL(qrb_copy_kernel, grid((int64_t)w * w), dim3(256), 0, s, Wp, n, (const double*)W2,
+                         (int64_t)n, (int64_t)1, w, w);
+      QTT_HIP(hipGetLastError());
+      hipLaunchKernelGGL(qrb_t_kernel, dim3(1), dim3(256), 0, s, Vp, mr, w, taus + p0, Tp);
+      QTT_HIP(hipGetLastError());
+    }
+    const int nt = n - p0 - w;
+    if (nt > 0) {  // trailing columns: A_t <- (I - V T^T V^T) A_t
+      double* At = Wp + w;
+      qrb_gemm(gemm_desc(w, nt, mr, Vp, w, true, At, n, false, W1, nt), part, s);
+      qrb_gemm(gemm_desc(w, nt, w, Tp, w, true, W1, nt, false, W2, nt), part, s);
+      qrb_gemm(gemm_desc(mr, nt, w, Vp, w, false, W2, nt, false, At, n, -1.0, 1.0), part, s);
+    }
+  }
+  if (run && R != nullptr) {
+    hipLaunchKernelGGL(qrb_upper_kernel, grid((int64_t)n * n), dim3(256), 0, s, R, ldq, W, n);
+    QTT_HIP(hipGetLastError());
+  }
+  if (run) {
+    hipLaunchKernelGGL(qrb_eye_kernel, grid((int64_t)m * n), dim3(256), 0, s, Q, ldq, m, n);
+    QTT_HIP(hipGetLastError());
+  }
+  int pi = (int)voff.size() - 1;
+  for (int p0 = ((n - 1) / QB) * QB; p0 >= 0; p0 -= QB, --pi) {  // Q[p0:, p0:] <- (I - V T V^T) Q[p0:, p0:]
+    const int w = std::min(QB, n - p0), mr = m - p0, nq = n - p0;
+    const double* Vp = Vall + voff[pi];
+    const double* Tp = Tall + (int64_t)p0 * QB;
+    double* Qs = Q + (int64_t)p0 * ldq + p0;
+    qrb_gemm(gemm_desc(w, nq, mr, Vp, w, true, Qs, ldq, false, W1, nq), part, s);
+    qrb_gemm(gemm_desc(w, nq, w, Tp, w, false, W1, nq, false, W2, nq), part, s);
+    qrb_gemm(gemm_desc(mr, nq, w, Vp, w, false, W2, nq, false, Qs, ldq, -1.0, 1.0), part, s);
+  }
+}
+
+}  // namespace
+
+std::string qr_path_name(int m, int n) {
+  const std::string k = qr_kernel_name(m, n);
+  return (k == "qr_kernel" && m <= QB_MAXM) ? std::string("qr_blocked") : k;
+}
+
 void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_t rs, int64_t cs,
                double* Q, int64_t strideQ, double* R, int64_t strideR, double* work,
-               hipStream_t s, const int* sq, int ldq) {
+               hipStream_t s, const int* sq, int ldq, int64_t work_size) {
   if (count <= 0) return;
   QTT_REQUIRE(m >= n && n >= 1 && n <= 1024, "qr: need m >= n, 1 <= n <= 1024 (m=%d n=%d)", m, n);
   QTT_REQUIRE(sq == nullptr || m == n, "qr: per-matrix sizes need square matrices");
@@ -1169,6 +1329,11 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
   if (sq) rt::check_range(sq, 0, count - 1, sizeof(int), "qr sizes");
   const bool generic = qr_kernel_name(m, n) == "qr_kernel";
   if (generic) rt::check_range(work, 0, (int64_t)count * m * n - 1, sizeof(double), "qr workspace");
+  if (generic && count == 1 && sq == nullptr && m <= QB_MAXM && work_size >= qr_work_size(1, m, n)) {
+    rt::check_range(work, 0, qr_work_size(1, m, n) - 1, sizeof(double), "qr workspace");
+    qr_blocked(m, n, A, rs, cs, Q, lq, R, work, s);
+    return;
+  }
   if (rt::dry()) return;
 #define QTT_QR_REG(RS_, CPW_, NW_, CH_)                                                           \
   if (m <= 64 * RS_ && n <= NW_ * CPW_) {                                                         \
@@ -1182,7 +1347,7 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
 #define QTT_QR_GRP(RPL_, CS_, NW_)                                                                \
   if (m <= 16 * RPL_ && n <= 4 * NW_ * CS_) {                                                     \
     hipLaunchKernelGGL((qr_grp_kernel<RPL_, CS_, NW_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
-                       strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq);                             \
+                       strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq, nullptr, nullptr);         \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }

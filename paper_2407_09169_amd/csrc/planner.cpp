@@ -100,7 +100,7 @@ OpInfo qr_info(int m, int n) {
   oi.kind = OP_QR;
   oi.flops = 2.0 * (2.0 * m * (double)n * n - 2.0 * n * (double)n * n / 3.0);
   oi.bytes = 8.0 * 2.0 * m * (double)n;
-  oi.what = qr_kernel_name(m, n) + "|m" + std::to_string(m) + " n" + std::to_string(n);
+  oi.what = qr_path_name(m, n) + "|m" + std::to_string(m) + " n" + std::to_string(n);
   return oi;
 }
 
@@ -362,7 +362,7 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
     }
   }
   // workspaces
-  size_t t1 = 1, t2 = 1, msz = 1, u1 = 1, csz = 1, ssz = 1;
+  size_t t1 = 1, t2 = 1, msz = 1, u1 = 1, csz = 1, ssz = 1, qsz = 1;
   for (int j = 0; j < J; ++j)
     for (int n = 0; n < N; ++n) {
       const auto& r = sh[j].r;
@@ -373,6 +373,7 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
       u1 = std::max(u1, (size_t)ell[n] * D[n] * 2 * r[n + 1]);
       csz = std::max(csz, (size_t)ell[n] * 2 * r[n + 1] * D[n + 1]);
       ssz = std::max(ssz, (size_t)2 * ell[n] * ell[n + 1]);
+      qsz = std::max(qsz, (size_t)qr_work_size(1, 2 * ell[n], ell[n + 1]));
     }
   std::vector<double*> T1s(L), T2s(L), U1s(L);
   for (int l = 0; l < L; ++l) {
@@ -381,7 +382,8 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
     U1s[l] = plan.alloc(u1);
   }
   double* S = plan.alloc(ssz);
-  double* qrw = plan.alloc(ssz);
+  double* qrw = plan.alloc(qsz);
+  const int64_t qrws = (int64_t)qsz;
   double* one = plan.upload(std::vector<double>{1.0});
   std::vector<std::vector<double*>> R(J, std::vector<double*>(N + 1, nullptr));
   std::vector<double*> Ma(J), Mb(J), Cb(J);
@@ -561,7 +563,7 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
     {
       double* Xn = X[n];
       const int m = 2 * l, nc = lp;
-      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, S, 0, nc, 1, Xn, 0, nullptr, 0, qrw, s); },
+      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, S, 0, nc, 1, Xn, 0, nullptr, 0, qrw, s, nullptr, 0, qrws); },
                qr_info(m, nc));
     }
     plan.fork(L);
@@ -616,8 +618,9 @@ LeftOrth plan_left_orth(Plan& plan, const ChainView& x) {
       knew = cr;
       Q = plan.alloc((size_t)m * cr);
       double* Rm = plan.alloc((size_t)cr * cr);
-      double* work = plan.alloc((size_t)m * cr);
-      plan.add([=](hipStream_t s) { qr_launch(1, m, cr, cur, 0, cr, 1, Q, 0, Rm, 0, work, s); },
+      const int64_t ws = qr_work_size(1, m, cr);
+      double* work = plan.alloc((size_t)ws);
+      plan.add([=](hipStream_t s) { qr_launch(1, m, cr, cur, 0, cr, 1, Q, 0, Rm, 0, work, s, nullptr, 0, ws); },
                qr_info(m, cr));
       next = plan.alloc((size_t)knew * 2 * cnr);
       add_gemm(plan, knew, 2 * cnr, cr, Rm, cr, false, x.core[n + 1], 2 * cnr, false, next, 2 * cnr,
@@ -657,11 +660,12 @@ void plan_round_det(Plan& plan, const ChainView& x, RoundTarget& tg) {
       // A (cl x cols) = L Q from the QR of A^T (cols x cl)
       double* Qt = plan.alloc((size_t)cols * cl);
       double* Rm = plan.alloc((size_t)cl * cl);
-      double* work = plan.alloc((size_t)cols * cl);
+      const int64_t ws = qr_work_size(1, cols, cl);
+      double* work = plan.alloc((size_t)ws);
       double* core = plan.alloc((size_t)cl * cols);
       const double* A = cur;
       plan.add([=](hipStream_t s) {
-        qr_launch(1, cols, cl, A, 0, 1, cols, Qt, 0, Rm, 0, work, s);
+        qr_launch(1, cols, cl, A, 0, 1, cols, Qt, 0, Rm, 0, work, s, nullptr, 0, ws);
         transpose(Qt, cols, cl, core, s);
       });
       // left neighbour absorbs L = R^T

@@ -341,6 +341,7 @@ struct TwoSided {
   std::vector<double*> Ma, Mb, Cb, Mra, Mrb, Crb, U1L, U1R;
   std::vector<double*> T1, T2, L1, L2;  // sketch-chain scratch per term (right, left)
   double *SL = nullptr, *SR = nullptr, *qwL = nullptr, *qwR = nullptr;
+  int64_t qwsz = 0;  // doubles in qwL, qwR
   // terms with the same operator and bonds, recorded as one launch per
   // contraction (pointer groups)
   std::vector<std::vector<int>> groups;
@@ -379,7 +380,7 @@ void ts_setup(Plan& plan, TwoSided& r, const std::vector<SketchTerm>& terms, Rou
       r.sh[j].D.assign(N + 1, 1);
     }
   }
-  size_t t1 = 1, t2 = 1, msz = 1, u1 = 1, csz = 1, crsz = 1, ssz = 1;
+  size_t t1 = 1, t2 = 1, msz = 1, u1 = 1, csz = 1, crsz = 1, ssz = 1, qsz = 1;
   for (int j = 0; j < J; ++j)
     for (int n = 0; n < N; ++n) {
       const auto& rr = r.sh[j].r;
@@ -392,6 +393,7 @@ void ts_setup(Plan& plan, TwoSided& r, const std::vector<SketchTerm>& terms, Rou
       csz = std::max(csz, l * 2 * rp * Dp);
       crsz = std::max(crsz, rn * Dn * 2 * lp);
       ssz = std::max(ssz, 2 * l * lp);
+      qsz = std::max({qsz, (size_t)qr_work_size(1, (int)(2 * l), (int)lp), (size_t)qr_work_size(1, (int)(2 * lp), (int)l)});
     }
   r.R.assign(J, std::vector<double*>(N + 1, nullptr));
   r.Lk.assign(J, std::vector<double*>(N + 1, nullptr));
@@ -441,8 +443,9 @@ void ts_setup(Plan& plan, TwoSided& r, const std::vector<SketchTerm>& terms, Rou
   }
   r.SL = plan.alloc(ssz);
   r.SR = plan.alloc(ssz);
-  r.qwL = plan.alloc(ssz);
-  r.qwR = plan.alloc(ssz);
+  r.qwL = plan.alloc(qsz);
+  r.qwR = plan.alloc(qsz);
+  r.qwsz = (int64_t)qsz;
   r.X.assign(N, nullptr);
   r.Vt.assign(N, nullptr);
   for (int n = 0; n < r.c; ++n) r.X[n] = plan.alloc((size_t)ell[n] * 2 * ell[n + 1]);
@@ -538,8 +541,9 @@ void ts_left_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double*
       double* Xn = r.X[n];
       double* SL = r.SL;
       double* qw = r.qwL;
+      const int64_t qws = r.qwsz;
       const int m = 2 * l, nc = lp;
-      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, SL, 0, nc, 1, Xn, 0, nullptr, 0, qw, s); },
+      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, SL, 0, nc, 1, Xn, 0, nullptr, 0, qw, s, nullptr, 0, qws); },
                qr_info(m, nc));
     }
     for (const auto& g : r.groups) {  // M'_j = X_n^T C_j
@@ -590,8 +594,9 @@ void ts_right_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double
       double* Vn = r.Vt[n];
       double* SR = r.SR;
       double* qw = r.qwR;
+      const int64_t qws = r.qwsz;
       const int m = 2 * lp, nc = l;
-      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, SR, 0, 1, m, Vn, 0, nullptr, 0, qw, s); },
+      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, SR, 0, 1, m, Vn, 0, nullptr, 0, qw, s, nullptr, 0, qws); },
                qr_info(m, nc));
     }
     for (const auto& g : r.groups) {  // Mr_j[(a,A),y] = sum_(t,z) Cr_j[(a,A),(t,z)] Vt[(t,z),y]

@@ -43,7 +43,7 @@ def test_binding_lists_every_declared_symbol():
 
 
 def test_dry_run_planning_is_in_bounds():
-    """Plans every entry point at the full 5-D M=1024 chi=128 shapes with host
+    """Plans every entry point at the full 5-D M=1024 chi=128 and 256 shapes with host
     memory standing in for device memory: every contraction, QR, eigen and
     copy launch is checked against its buffers; no kernel runs."""
     code = r"""
@@ -52,7 +52,7 @@ os.environ["QTTPDF_DRYRUN"] = "1"
 sys.path.insert(0, %r)
 import paper_2407_09169_amd as q, workloads
 ctx = q.Context(0, stream=0)
-for name in ["c1_2d_M64", "t_5d_M8_chi16", "c3_5d_M1024_chi128"]:
+for name in ["c1_2d_M64", "t_5d_M8_chi16", "c3_5d_M1024_chi128", "c3_5d_M1024_chi256"]:
     w = workloads.get_workload(name)
     for dt in ("f64", "bf16"):
         prob, f = q.setup_workload(ctx, w, dt)

@@ -29,6 +29,27 @@ def test_qr(ctx, m, n):
         assert np.max(np.abs(np.tril(R[b], -1))) == 0.0
 
 
+@pytest.mark.parametrize("m,n", [(576, 288), (576, 100), (500, 250), (400, 33), (333, 257)])
+def test_qr_single_blocked(ctx, m, n):
+    """One matrix beyond the register kernels: blocked Householder (register
+    panels, compact WY updates).  Random, exactly rank-deficient and graded
+    matrices; Q orthonormal, Q R = A, R upper triangular."""
+    rng = np.random.default_rng(m * 7 + n)
+    for kind in ("random", "rank deficient", "graded"):
+        A = rng.standard_normal((1, m, n))
+        if kind == "rank deficient":
+            A[0, :, n // 2:] = 0.0
+        if kind == "graded":
+            A[0] *= np.logspace(0, -12, n)[None, :]
+        Q, R = q.linalg_qr(ctx, A)
+        Qb, Rb, Ab = Q[0], R[0], A[0]
+        assert np.max(np.abs(Qb.T @ Qb - np.eye(n))) < 50 * n * 2.2e-16, kind
+        assert np.max(np.abs(Qb @ Rb - Ab)) <= 50 * n * 2.2e-16 * np.abs(Ab).max(), kind
+        assert np.max(np.abs(np.tril(Rb, -1))) == 0.0, kind
+        Q2, _ = q.linalg_qr(ctx, A, with_r=False)
+        assert np.array_equal(Q2, Q), kind
+
+
 @pytest.mark.parametrize("n,keep", [(1, 1), (2, 1), (2, 2), (3, 2), (5, 3), (16, 16), (33, 20), (64, 48), (100, 100),
                                     (128, 120), (144, 128), (288, 256)])
 def test_eigh(ctx, n, keep):
