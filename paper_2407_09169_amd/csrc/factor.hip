@@ -1208,31 +1208,35 @@ __global__ void qrb_upper_kernel(double* __restrict__ R, int ldr, const double* 
 }
 
 // T (w x w, ld w, upper triangular) of the compact WY form of w reflectors
-// V (mr x w, ld w): T_jj = tau_j, T_(0:j, j) = -tau_j T_(0:j, 0:j) V_(:, 0:j)^T v_j.
-__global__ __launch_bounds__(256) void qrb_t_kernel(const double* __restrict__ V, int mr, int w,
-                                                    const double* __restrict__ taus, double* __restrict__ T) {
-  __shared__ double S[QB][QB + 1];
-  __shared__ double Ts[QB][QB + 1];
-  for (int e = threadIdx.x; e < w * w; e += 256) {
-    const int i = e / w, j = e % w;
-    double acc = 0.0;
-    for (int r = 0; r < mr; ++r) acc = fma(V[(int64_t)r * w + i], V[(int64_t)r * w + j], acc);
-    S[i][j] = acc;
-    Ts[i][j] = 0.0;
-  }
+// with Gram matrix S = V^T V (w x w, ld w): T_ii = tau_i and, for j > i,
+// T_ij = -tau_j sum_(i <= k < j) T_ik S_kj.  Row i needs only its own earlier
+// entries, so thread i builds it alone (no barriers).
+__global__ __launch_bounds__(64) void qrb_t_kernel(const double* __restrict__ S, int w,
+                                                   const double* __restrict__ taus, double* __restrict__ T) {
+  __shared__ double Ss[QB][QB + 1];
+  for (int e = threadIdx.x; e < w * w; e += 64) Ss[e / w][e % w] = S[e];
   __syncthreads();
-  for (int j = 0; j < w; ++j) {
-    const double tj = taus[j];
-    if ((int)threadIdx.x < j) {
-      const int i = threadIdx.x;
-      double acc = 0.0;
-      for (int k = i; k < j; ++k) acc = fma(Ts[i][k], S[k][j], acc);
-      Ts[i][j] = -tj * acc;
+  const int i = threadIdx.x;
+  if (i >= w) return;
+  double t[QB];
+#pragma unroll
+  for (int j = 0; j < QB; ++j) t[j] = 0.0;
+#pragma unroll
+  for (int j = 0; j < QB; ++j) {
+    if (j < i || j >= w) continue;
+    if (j == i) {
+      t[j] = taus[j];
+      continue;
     }
-    if (threadIdx.x == 0) Ts[j][j] = tj;
-    __syncthreads();
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < QB; ++k)
+      if (k >= i && k < j) acc = fma(t[k], Ss[k][j], acc);
+    t[j] = -taus[j] * acc;
   }
-  for (int e = threadIdx.x; e < w * w; e += 256) T[e] = Ts[e / w][e % w];
+#pragma unroll
+  for (int j = 0; j < QB; ++j)
+    if (j < w) T[(int64_t)i * w + j] = t[j];
 }
 
 // C = alpha op(A) op(B) + beta C in FP64, K split when that helps (partials in `part`)
@@ -1275,7 +1279,10 @@ void qr_blocked(int m, int n, const double* A, int64_t rs, int64_t cs, double* Q
       hipLaunchKernelGGL(qrb_copy_kernel, grid((int64_t)w * w), dim3(256), 0, s, Wp, n, (const double*)W2,
                          (int64_t)n, (int64_t)1, w, w);
       QTT_HIP(hipGetLastError());
-      hipLaunchKernelGGL(qrb_t_kernel, dim3(1), dim3(256), 0, s, Vp, mr, w, taus + p0, Tp);
+    }
+    qrb_gemm(gemm_desc(w, w, mr, Vp, w, true, Vp, w, false, W1, w), part, s);  // S = V^T V
+    if (run) {
+      hipLaunchKernelGGL(qrb_t_kernel, dim3(1), dim3(64), 0, s, (const double*)W1, w, (const double*)(taus + p0), Tp);
       QTT_HIP(hipGetLastError());
     }
     const int nt = n - p0 - w;
