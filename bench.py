@@ -232,6 +232,68 @@ def _bench_batched(args, log):
     print(json.dumps(out))
 
 
+def _bench_moments(args, log):
+    """The moment equation of the flow case (eq. FPMoms at Da = 0, RK2-CFD2)
+    for both mean compositions on an M^3 grid with the Smagorinsky
+    diffusivity of eq. velField's flow: RK2 steps/s, and the roofline of the
+    stage kernel.  Algorithmic bytes per grid point and step: the first stage
+    reads the two fields, U (3 values) and G and writes two fields (8 values,
+    64 bytes); the second also reads the two base fields (10 values, 80
+    bytes)."""
+    import numpy as np
+    import torch
+    import paper_2407_09169_amd as q
+    import workloads
+    bits = int(round(np.log2(int(args.workload.split("_M")[1]))))
+    M, n = 1 << bits, 1 << (3 * bits)
+    w = workloads.get_workload("t_5d_M8_chi16", bits=bits, ic="paper")
+    ctx = q.Context(0)
+    dev = torch.device("cuda", 0)
+    U = torch.zeros((3, M, M, M), dtype=torch.float64, device=dev)
+    one = torch.ones(M, dtype=torch.float64, device=dev)
+    for i, comp in enumerate(workloads.velocity_terms(w)):
+        for c, vecs in comp:
+            v = [one if x is None else torch.as_tensor(x, device=dev) for x in vecs]
+            U[i] += c * v[0][:, None, None] * v[1][None, :, None] * v[2][None, None, :]
+    G = torch.empty(n, dtype=torch.float64, device=dev)
+    delta = 3.0 / M
+    q.smagorinsky(ctx, bits, U.view(-1), G, 0.11, delta, 1e-3)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(17)
+    m = torch.rand(2 * n, dtype=torch.float64, device=dev, generator=gen)
+    work = torch.empty_like(m)
+    gmax = float(G.max())
+    dt = 0.2 / (M * M * gmax * 6 + M * 4)
+    q.moment_steps(ctx, bits, U.view(-1), G, m, work, dt, args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    q.moment_steps(ctx, bits, U.view(-1), G, m, work, dt, args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    value = args.steps / (ms / 1e3)
+    per_launch_bytes = (64 + 80) / 2 * n
+    avg_us = ms * 1e3 / (2 * args.steps)
+    achieved = per_launch_bytes / (avg_us * 1e-6) / 1e9
+    log(f"moments M={M}: {args.steps} RK2 steps in {ms:.2f} ms ({value:.1f} steps/s, "
+        f"{achieved:.0f} GB/s per stage launch)")
+    out = {
+        "metric": "moment-equation RK2 steps/s (both mean compositions, Smagorinsky diffusivity)",
+        "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "grid": f"{M}^3", "fields": 2, "dt": dt},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_GBS, "traffic": None,
+                     "kernel": "moment_stage_kernel<2>", "avg_launch_us": avg_us,
+                     "algorithmic_bytes_per_launch": per_launch_bytes,
+                     "timing": "events around the timed steps, divided by the launches"},
+        "finite": bool(torch.isfinite(m).all()),
+    }
+    print(json.dumps(out))
+
+
 def _bench_gradient(args, log):
     """Steps of the gradient workload carrying d f / d Omega and d f / d k
     (tt_step_tangent): gradient-steps/s and the final dJ/dtheta of the
@@ -349,6 +411,9 @@ def main():
         return
     if args.gradient:
         _bench_gradient(args, log)
+        return
+    if args.workload.startswith("fpmoms_M"):
+        _bench_moments(args, log)
         return
     w = workloads.get_workload(args.workload)
     ctx = q.Context(0)

@@ -331,6 +331,55 @@ tt_status tt_mean_field(tt_ctx* ctx, tt_problem* prob, const tt_tt* f, int a, tt
                         double* scalar);
 
 /* ------------------------------------------------------------------------
+ * The flow case (section "Materials and Methods"): composition moments of
+ * the PDF as x-fields, dense evaluation, the Smagorinsky diffusivity, the
+ * moment equation (eq. FPMoms) and the error measures (eq. RMSE0, RMSE1).
+ * Dense fields are FP64 device arrays on the periodic M^3 x grid (M =
+ * 2^bits, 3 <= bits <= 10, x_j = j / M) in row-major [x1][x2][x3] order; the
+ * caller allocates them (M^3 doubles per field, fields of a set back to
+ * back) and keeps ownership.  Work is enqueued on the context's stream.
+ * ------------------------------------------------------------------------ */
+/* The composition moment h^2 sum_{i1,i2} w1(phi1_i1) w2(phi2_i2) f(., x) of
+ * a 5-D state as an x-MPS (new handle, bond caps those of f over the x
+ * sites): w1, w2 are host arrays of M weights (NULL = all ones), so
+ * (phi, NULL) gives <Phi_1>(x), (NULL, phi) <Phi_2>(x) and (NULL, NULL) the
+ * local norm <1>(x) of eq. spaceAvg's integrand.  Synchronises. */
+tt_status tt_moment_field(tt_ctx* ctx, tt_problem* prob, const tt_tt* f, const double* w1,
+                          const double* w2, tt_tt** out);
+/* Every entry of an MPS of N <= 30 sites written to the device array out
+ * (2^N doubles, the first site's digit most significant; for an x-MPS of
+ * the serial ordering this is the [x1][x2][x3] layout).  Synchronises. */
+tt_status tt_to_dense(tt_ctx* ctx, const tt_tt* x, double* out);
+/* Total diffusivity G = gamma + gamma_SGS with the Smagorinsky closure of
+ * the paragraph after eq. FP0: gamma_SGS = c_s delta^2 / 2 times the square
+ * root of sum_ij (dU_i/dx_j + dU_j/dx_i)^2, the derivatives taken as
+ * periodic central differences.  U: the three velocity components (3 M^3
+ * doubles); G: M^3 doubles, not overlapping U. */
+tt_status fd_smagorinsky(tt_ctx* ctx, int bits, const double* U, double c_s, double delta,
+                         double gamma, double* G);
+/* n_steps RK2 (Heun) steps of eq. FPMoms with S = 0 (Da = 0) for `count`
+ * (1 or 2) mean-composition fields m (count M^3 doubles, updated in place):
+ * dm/dt = sum_i [-U_i D1_i m + G D2_i m + (D1_i G)(D1_i m)], central
+ * differences, periodic in x (the variable-diffusivity term in expanded
+ * form).  U: 3 M^3 doubles; G: M^3 doubles; work: count M^3 doubles not
+ * overlapping m. */
+tt_status fd_moment_steps(tt_ctx* ctx, int bits, int count, const double* U, const double* G,
+                          double* m, double* work, double dt, int n_steps);
+/* *out (host) = sum_i (a_i - b_i - c)^2 over n >= 1 device values (b may be
+ * NULL), summed in a fixed order.  Synchronises. */
+tt_status fd_sq_diff_sum(tt_ctx* ctx, int64_t n, const double* a, const double* b, double c,
+                         double* out);
+/* The four RMSE measures of eq. RMSE0 from T = n_samples time samples, the
+ * time average of eq. RMSE1 taken as the mean over the samples (host
+ * arrays): mean_bar (2 x T) the space averages of <Phi_1>, <Phi_2>;
+ * sq_mean_x (2 x T, NULL if no exact solution) the grid means of
+ * (<Phi_a>(x) - <Phi_a>_exact(x))^2; sq_norm_x (T) the grid means of
+ * (<1>(x) - 1)^2.  out[0..3] = Error_2b up, Error_2b down (NaN without
+ * sq_mean_x), Error_2c up, Error_2c down. */
+tt_status flow_error_measures(int n_samples, const double* mean_bar, const double* sq_mean_x,
+                              const double* sq_norm_x, double* out);
+
+/* ------------------------------------------------------------------------
  * The FP64 factorisation kernels on their own (unit tests, diagnostics)
  * ------------------------------------------------------------------------ */
 /* Householder QR of `count` row-major m x n matrices (m >= n, n <= 1024)

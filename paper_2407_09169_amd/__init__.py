@@ -36,7 +36,8 @@ EXPORTS = [
     "tt_inner", "tt_problem_create", "tt_problem_destroy", "tt_problem_info", "tt_problem_state",
     "tt_step", "tt_profile", "tt_step_info", "tt_observable", "tt_mean_field",
     "tt_linalg_qr", "tt_linalg_eigh", "tt_batch_create", "tt_step_batched", "tt_batch_destroy",
-    "tt_step_tangent",
+    "tt_step_tangent", "tt_moment_field", "tt_to_dense", "fd_smagorinsky", "fd_moment_steps",
+    "fd_sq_diff_sum", "flow_error_measures",
 ]
 KERNELS = {"contract": 0, "qr": 1, "eig": 2, "stream": 3, "all": 4}
 
@@ -110,6 +111,12 @@ def lib():
         "tt_step_batched": [vp, i32],
         "tt_batch_destroy": [vp],
         "tt_step_tangent": [vp, vp, vp, i32, P(i32), P(vp), i32],
+        "tt_moment_field": [vp, vp, vp, P(dbl), P(dbl), P(vp)],
+        "tt_to_dense": [vp, vp, vp],
+        "fd_smagorinsky": [vp, i32, vp, dbl, dbl, dbl, vp],
+        "fd_moment_steps": [vp, i32, i32, vp, vp, vp, vp, dbl, i32],
+        "fd_sq_diff_sum": [vp, C.c_int64, vp, vp, dbl, P(dbl)],
+        "flow_error_measures": [i32, P(dbl), P(dbl), P(dbl), P(dbl)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -139,6 +146,7 @@ def _torch_stream():
 
 class Context:
     def __init__(self, device: int = 0, stream=None):
+        self.device = device
         self.h = C.c_void_p()
         s = _torch_stream() if stream is None else C.c_void_p(stream)
         _check(lib().tt_ctx_create(device, s, C.byref(self.h)))
@@ -411,6 +419,24 @@ class Problem:
             return sc.value
         return TT(self.ctx, h)
 
+    def moment_field(self, f, w1=None, w2=None):
+        """h^2 sum w1(phi1) w2(phi2) f as an x-MPS (tt_moment_field); w1, w2 are
+        arrays of M weights or None (all ones)."""
+        M = 1 << self.params.bits
+        ws = []
+        for w in (w1, w2):
+            if w is None:
+                ws.append(None)
+                continue
+            a = np.ascontiguousarray(w, dtype=np.float64)
+            if a.shape != (M,):
+                raise ValueError(f"weights must have shape ({M},)")
+            ws.append(a)
+        h = C.c_void_p()
+        ptr = [None if a is None else a.ctypes.data_as(C.POINTER(C.c_double)) for a in ws]
+        _check(lib().tt_moment_field(self.ctx.h, self.h, f.h, ptr[0], ptr[1], C.byref(h)))
+        return TT(self.ctx, h)
+
     def close(self):
         if self.h:
             lib().tt_problem_destroy(self.h)
@@ -492,3 +518,74 @@ def setup_workload(ctx, w, dtype="f64"):
     prob = Problem(ctx, p, velocity, sketch, sketch_left, sketch_mean, sketch_mean_left)
     f0 = from_separable(ctx, w.ndims, w.bits, ordering, workloads.ic_terms(w), w.chi)
     return prob, f0
+
+
+# ---------------------------------------------------------------------------
+# flow case: dense x fields (float64 torch tensors on the GPU, row-major
+# [x1][x2][x3]); the arithmetic runs in the library
+# ---------------------------------------------------------------------------
+def _dense_arg(t, n, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be contiguous with {n} elements (has {t.numel()})")
+    return C.c_void_p(t.data_ptr())
+
+
+def to_dense(ctx, x, out):
+    """Writes every entry of the MPS x (N <= 30 sites) into the tensor out (2^N values)."""
+    _, n_sites, _, _ = x.info()
+    _check(lib().tt_to_dense(ctx.h, x.h, _dense_arg(out, 1 << n_sites, "out")))
+    return out
+
+
+def smagorinsky(ctx, bits, U, G, c_s, delta, gamma):
+    """G = gamma + c_s delta^2 / 2 |S(U)| (fd_smagorinsky); U has 3 M^3 values."""
+    n = 1 << (3 * bits)
+    _check(lib().fd_smagorinsky(ctx.h, bits, _dense_arg(U, 3 * n, "U"), c_s, delta, gamma,
+                                _dense_arg(G, n, "G")))
+    return G
+
+
+def moment_steps(ctx, bits, U, G, m, work, dt, n_steps=1):
+    """n_steps RK2 steps of the moment equation on m (1 or 2 fields) in place."""
+    n = 1 << (3 * bits)
+    count = m.numel() // n
+    if count not in (1, 2):
+        raise ValueError("m must hold one or two fields of M^3 values")
+    _check(lib().fd_moment_steps(ctx.h, bits, count, _dense_arg(U, 3 * n, "U"),
+                                 _dense_arg(G, n, "G"), _dense_arg(m, count * n, "m"),
+                                 _dense_arg(work, count * n, "work"), dt, n_steps))
+    return m
+
+
+def sq_diff_sum(ctx, a, b=None, c=0.0):
+    """sum (a - b - c)^2 over the entries of a (b optional, same size)."""
+    n = a.numel()
+    out = C.c_double()
+    bp = None if b is None else _dense_arg(b, n, "b")
+    _check(lib().fd_sq_diff_sum(ctx.h, n, _dense_arg(a, n, "a"), bp, c, C.byref(out)))
+    return out.value
+
+
+def error_measures(mean_bar, sq_mean_x, sq_norm_x):
+    """(Error_2b up, Error_2b down, Error_2c up, Error_2c down) of eq. RMSE0."""
+    mb = np.ascontiguousarray(mean_bar, dtype=np.float64)
+    T = mb.shape[1]
+    if mb.shape != (2, T):
+        raise ValueError("mean_bar must have shape (2, T)")
+    sn = np.ascontiguousarray(sq_norm_x, dtype=np.float64)
+    if sn.shape != (T,):
+        raise ValueError("sq_norm_x must have shape (T,)")
+    dp = C.POINTER(C.c_double)
+    sm = None
+    if sq_mean_x is not None:
+        sm = np.ascontiguousarray(sq_mean_x, dtype=np.float64)
+        if sm.shape != (2, T):
+            raise ValueError("sq_mean_x must have shape (2, T)")
+    out = np.zeros(4)
+    _check(lib().flow_error_measures(T, mb.ctypes.data_as(dp),
+                                     None if sm is None else sm.ctypes.data_as(dp),
+                                     sn.ctypes.data_as(dp), out.ctypes.data_as(dp)))
+    return tuple(float(v) for v in out)

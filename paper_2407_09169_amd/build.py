@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "libqttpdf.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("QTTPDF_ARCH", "gfx950")
 
-SOURCES = ["tc_gemm.hip", "factor.hip", "elementwise.hip", "planner.cpp", "planner_two_sided.cpp",
+SOURCES = ["tc_gemm.hip", "factor.hip", "elementwise.hip", "moments.hip", "planner.cpp", "planner_two_sided.cpp",
            "capi.cpp", "host_tt.cpp", "runtime.cpp"]
 
 COMMON = [

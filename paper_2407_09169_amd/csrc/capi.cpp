@@ -4,6 +4,7 @@
 #include <cstring>
 
 #include "library.h"
+#include "moments.h"
 
 namespace qtt {
 
@@ -1444,3 +1445,143 @@ tt_status tt_linalg_eigh(tt_ctx* ctx, int count, int n, int keep, const double* 
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// flow case: composition moments as x-fields, dense evaluation, the
+// Smagorinsky field, the moment equation and the error measures
+// ===========================================================================
+tt_status tt_moment_field(tt_ctx* ctx, tt_problem* prob, const tt_tt* f, const double* w1,
+                          const double* w2, tt_tt** out) {
+  return guard([&] {
+    QTT_REQUIRE(prob && out, "bad argument");
+    check_tt(f, ctx);
+    QTT_REQUIRE(prob->nx > 0, "moment fields need a problem with x dimensions");
+    QTT_REQUIRE(f->caps == prob->fcaps, "state caps differ from the problem's");
+    const tt_params& p = prob->p;
+    const int M = 1 << p.bits;
+    const double h = 1.0 / M;
+    std::vector<double> v1(M, h), v2(M, h);
+    for (int i = 0; i < M; ++i) {
+      if (w1) v1[i] = h * w1[i];
+      if (w2) v2[i] = h * w2[i];
+    }
+    auto order = host::site_order(p.ndims, p.bits, p.ordering);
+    std::vector<std::pair<int, int>> phi_order(order.begin(), order.begin() + prob->nphi);
+    host::TT q1 = host::vector_qtt(v1.data(), p.bits), q2 = host::vector_qtt(v2.data(), p.bits);
+    host::TT w = host::kron_dims({&q1, &q2}, phi_order, 2, 2);
+    auto wt = upload(ctx, TT_MPS, w, exact_caps(w));
+    const int c = f->caps[prob->nphi], c1 = f->caps[prob->nphi + 1];
+    std::vector<int> caps(prob->nx + 1);
+    caps[0] = 1;
+    for (int j = 1; j <= prob->nx; ++j) caps[j] = f->caps[prob->nphi + j];
+    auto m = make_tt(ctx, TT_MPS, prob->nx, caps);
+    Plan plan;
+    double* E = plan.alloc(c);
+    plan_partial(plan, view(wt.get()), view_sites(f, 0, prob->nphi), E);
+    TcDesc d = gemm_desc(1, 2 * c1, c, E, c, false, f->core(prob->nphi), 2 * c1, false, m->core(0),
+                         2 * c1);
+    plan.add([d](hipStream_t s) { tc_launch(d, Prec::F64, s); });
+    StreamScope sc(ctx);
+    plan.run(ctx->stream);
+    for (int j = 1; j < prob->nx; ++j)
+      rt::copy_async(m->core(j), f->core(prob->nphi + j),
+                     (m->off[j + 1] - m->off[j]) * sizeof(double), ctx->stream);
+    rt::sync(ctx->stream);
+    *out = m.release();
+  });
+}
+
+tt_status tt_to_dense(tt_ctx* ctx, const tt_tt* x, double* out) {
+  return guard([&] {
+    check_tt(x, ctx);
+    QTT_REQUIRE(out, "out is null");
+    QTT_REQUIRE(x->kind == TT_MPS, "tt_to_dense needs an MPS");
+    const int N = x->N;
+    QTT_REQUIRE(N >= 1 && N <= 30, "tt_to_dense: %d sites outside [1, 30]", N);
+    // T_n (2^n x c_n, row-major) = T_{n-1} (2^(n-1) x c_{n-1}) * core (c_{n-1} x 2 c_n)
+    int64_t maxsz = 2 * (int64_t)x->caps[1];
+    for (int n = 1; n < N; ++n) maxsz = std::max(maxsz, (int64_t(1) << n) * 2 * x->caps[n + 1]);
+    DevBuf A((size_t)maxsz * sizeof(double)), B((size_t)maxsz * sizeof(double));
+    StreamScope sc(ctx);
+    rt::copy_async(A.p, x->core(0), 2 * (size_t)x->caps[1] * sizeof(double), ctx->stream);
+    int64_t rows = 2;
+    constexpr int64_t CHUNK = int64_t(1) << 20;
+    for (int n = 1; n < N; ++n) {
+      const int K = x->caps[n], NC = 2 * x->caps[n + 1];
+      for (int64_t r0 = 0; r0 < rows; r0 += CHUNK) {
+        const int rr = (int)std::min(CHUNK, rows - r0);
+        TcDesc d = gemm_desc(rr, NC, K, A.d() + r0 * K, K, false, x->core(n), NC, false,
+                             B.d() + r0 * NC, NC);
+        tc_launch(d, Prec::F64, ctx->stream);
+      }
+      std::swap(A, B);
+      rows *= 2;
+    }
+    rt::copy_async(out, A.p, (size_t)rows * sizeof(double), ctx->stream);
+    rt::sync(ctx->stream);
+  });
+}
+
+tt_status fd_smagorinsky(tt_ctx* ctx, int bits, const double* U, double c_s, double delta,
+                         double gamma, double* G) {
+  return guard([&] {
+    QTT_REQUIRE(ctx && U && G, "bad argument");
+    QTT_REQUIRE(delta > 0 && c_s >= 0 && gamma >= 0, "bad closure constants");
+    const int64_t n = int64_t(1) << (3 * bits);
+    QTT_REQUIRE(G + n <= U || U + 3 * n <= G, "G overlaps U");
+    StreamScope sc(ctx);
+    smagorinsky(bits, U, c_s * delta * delta / 2.0, gamma, G, ctx->stream);
+  });
+}
+
+tt_status fd_moment_steps(tt_ctx* ctx, int bits, int count, const double* U, const double* G,
+                          double* m, double* work, double dt, int n_steps) {
+  return guard([&] {
+    QTT_REQUIRE(ctx && U && G && m && work, "bad argument");
+    QTT_REQUIRE(count >= 1 && count <= 2, "count %d outside [1, 2]", count);
+    QTT_REQUIRE(n_steps >= 0, "negative step count");
+    const int64_t n = int64_t(1) << (3 * bits);
+    QTT_REQUIRE(m + count * n <= work || work + count * n <= m, "work overlaps m");
+    StreamScope sc(ctx);
+    for (int k = 0; k < n_steps; ++k) {
+      // Heun: m1 = m + dt L(m); m+ = (m + m1) / 2 + dt / 2 L(m1)
+      moment_stage(bits, count, U, G, m, nullptr, 0.0, 1.0, dt, work, ctx->stream);
+      moment_stage(bits, count, U, G, work, m, 0.5, 0.5, 0.5 * dt, m, ctx->stream);
+    }
+  });
+}
+
+tt_status fd_sq_diff_sum(tt_ctx* ctx, int64_t n, const double* a, const double* b, double c,
+                         double* out) {
+  return guard([&] {
+    QTT_REQUIRE(ctx && a && out && n >= 1, "bad argument");
+    DevBuf part((size_t)(sq_diff_partials() + 1) * sizeof(double));
+    StreamScope sc(ctx);
+    sq_diff_sum(n, a, b, c, part.d(), part.d() + sq_diff_partials(), ctx->stream);
+    rt::copy_async(out, part.d() + sq_diff_partials(), sizeof(double), ctx->stream);
+    rt::sync(ctx->stream);
+  });
+}
+
+tt_status flow_error_measures(int n_samples, const double* mean_bar, const double* sq_mean_x,
+                              const double* sq_norm_x, double* out) {
+  return guard([&] {
+    QTT_REQUIRE(n_samples >= 1 && mean_bar && sq_norm_x && out, "bad argument");
+    const int T = n_samples;
+    double up = 0.0, dn = 0.0, cu = 0.0, cd = 0.0;
+    for (int t = 0; t < T; ++t) {
+      for (int a = 0; a < 2; ++a) {
+        const double e = mean_bar[a * T + t] - 0.5;
+        up += e * e;
+        if (sq_mean_x) dn += sq_mean_x[a * T + t];
+      }
+      const double d = mean_bar[t] - mean_bar[T + t];
+      cu += d * d;
+      cd += sq_norm_x[t];
+    }
+    out[0] = std::sqrt(0.5 * up / T);
+    out[1] = sq_mean_x ? std::sqrt(0.5 * dn / T) : std::nan("");
+    out[2] = std::sqrt(cu / T);
+    out[3] = std::sqrt(cd / T);
+  });
+}

@@ -1,0 +1,201 @@
+"""Flow-case kernels and protocol (HIP library through the C ABI) against the
+oracle: the Smagorinsky field, the moment equation, dense evaluation of
+MPSs, composition moments as x-fields, squared-difference sums and the
+error measures of eq. RMSE0, and a short end-to-end run of the protocol.
+
+Tolerances: the dense stencil kernels and reductions are the oracle's
+arithmetic in another summation order, so they agree to 1e-12 relative;
+the end-to-end run inherits the truncated-rounding agreement of the MPS
+steps (about 1e-9 relative on these sizes, see test_gpu_parity), which
+bounds the error measures' difference by about 1e-8 absolute.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import dense as odense, moments, stepper, tt
+from tests.helpers import random_tt
+
+q = pytest.importorskip("paper_2407_09169_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = q.Context(0)
+    yield c
+    c.close()
+
+
+def _cuda(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _paper_velocity(M):
+    """eq. velField on the M^3 grid (x1, x2, x3), from the seeded-input module."""
+    w = workloads.get_workload("t_5d_M8_chi16", bits=int(np.log2(M)), ic="paper")
+    U = []
+    for comp in workloads.velocity_terms(w):
+        u = np.zeros((M, M, M))
+        for c, (v1, v2, v3) in comp:
+            ones = np.ones(M)
+            v1 = ones if v1 is None else v1
+            v2 = ones if v2 is None else v2
+            v3 = ones if v3 is None else v3
+            u += c * np.einsum("i,j,k->ijk", v1, v2, v3)
+        U.append(u)
+    return U
+
+
+def _close(got, want, rtol):
+    scale = max(np.max(np.abs(want)), 1e-300)
+    assert np.max(np.abs(got - want)) <= rtol * scale, np.max(np.abs(got - want)) / scale
+
+
+@pytest.mark.parametrize("bits", [3, 5, 6])
+def test_smagorinsky_matches_oracle(ctx, bits):
+    M = 1 << bits
+    U = _paper_velocity(M)
+    delta = 3.0 / M
+    want = moments.gamma_total(U, 1e-3, 0.11, delta)
+    import torch
+    Ud = _cuda(np.concatenate([u.ravel() for u in U]))
+    G = torch.empty(M ** 3, dtype=torch.float64, device="cuda")
+    q.smagorinsky(ctx, bits, Ud, G, 0.11, delta, 1e-3)
+    _close(G.cpu().numpy().reshape(M, M, M), want, 1e-12)
+
+
+@pytest.mark.parametrize("bits,count,steps", [(3, 1, 3), (4, 2, 5), (5, 2, 8)])
+def test_moment_steps_match_oracle(ctx, bits, count, steps):
+    """Smagorinsky diffusivity (strengthened so that the variable-coefficient
+    term matters), eq. velField, seeded random initial means."""
+    import torch
+    M = 1 << bits
+    U = _paper_velocity(M)
+    delta = 3.0 / M
+    c_s = 2.0
+    G = moments.gamma_total(U, 1e-3, c_s, delta)
+    assert np.max(G) > 3 * np.min(G)
+    rng = np.random.default_rng([bits, count])
+    m0 = rng.random((count, M, M, M))
+    dt = 0.2 / (M * M * np.max(G) * 6 + M * 4)
+    want = m0.copy()
+    for k in range(steps):
+        want = np.stack([moments.step(want[a], U, G, dt) for a in range(count)])
+    Ud = _cuda(np.concatenate([u.ravel() for u in U]))
+    Gd = torch.empty(M ** 3, dtype=torch.float64, device="cuda")
+    q.smagorinsky(ctx, bits, Ud, Gd, c_s, delta, 1e-3)
+    m = _cuda(m0.ravel())
+    work = torch.empty_like(m)
+    q.moment_steps(ctx, bits, Ud, Gd, m, work, dt, steps)
+    _close(m.cpu().numpy().reshape(count, M, M, M), want, 1e-12)
+    # the solution moved away from the start
+    assert np.max(np.abs(want - m0)) > 1e-3
+
+
+@pytest.mark.parametrize("ranks", [[1, 2, 1], [1, 2, 4, 8, 5, 3, 2, 1],
+                                   [1] + [2, 4, 8] + [8] * 9 + [8, 4, 2] + [1],
+                                   [1] + [2, 4, 8, 16] + [16] * 12 + [16, 8, 4, 2] + [1]])
+def test_to_dense_matches_oracle(ctx, ranks):
+    import torch
+    cores = random_tt(ranks, seed=len(ranks))
+    want = tt.tt_full(cores).ravel()
+    x = q.TT.from_cores(ctx, cores)
+    out = torch.empty(want.size, dtype=torch.float64, device="cuda")
+    q.to_dense(ctx, x, out)
+    _close(out.cpu().numpy(), want, 1e-12)
+
+
+def test_moment_field_matches_oracle(ctx):
+    w = workloads.get_workload("t_5d_M8_chi16")
+    st = stepper.MPSStepper(w)
+    f_or = st.initial_state()
+    F = st.to_dense(f_or)  # (phi1, phi2, x1, x2, x3)
+    M = w.M
+    h = 1.0 / M
+    phi = odense.phi_nodes(M)
+    prob, f = q.setup_workload(ctx, w)
+    import torch
+    out = torch.empty(M ** 3, dtype=torch.float64, device="cuda")
+    for w1, w2 in ((phi, None), (None, phi), (None, None), (phi, phi)):
+        a1 = np.ones(M) if w1 is None else w1
+        a2 = np.ones(M) if w2 is None else w2
+        want = h * h * np.einsum("i,j,ijabc->abc", a1, a2, F)
+        x = prob.moment_field(f, w1, w2)
+        q.to_dense(ctx, x, out)
+        x.free()
+        # the two sides build the truncated initial state independently
+        _close(out.cpu().numpy().reshape(M, M, M), want, 1e-8)
+    f.free()
+    prob.close()
+
+
+@pytest.mark.parametrize("n,with_b,c", [(1, False, 0.0), (255, True, 0.0), (12345, True, 0.5),
+                                        (1 << 21, False, 1.0), ((1 << 22) + 77, True, -0.25)])
+def test_sq_diff_sum(ctx, n, with_b, c):
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal(n)
+    b = rng.standard_normal(n) if with_b else None
+    want = float(np.sum((a - (b if with_b else 0.0) - c) ** 2))
+    got = q.sq_diff_sum(ctx, _cuda(a), None if b is None else _cuda(b), c)
+    assert abs(got - want) <= 1e-12 * want
+
+
+def test_error_measures_match_oracle():
+    T = 17
+    rng = np.random.default_rng(11)
+    shape = (4, 4, 4)
+    mean_bar = 0.5 + 0.01 * rng.standard_normal((2, T))
+    ex = rng.random((2, T) + shape)
+    mx = ex + 0.001 * rng.standard_normal((2, T) + shape)
+    nx = 1.0 + 1e-3 * rng.standard_normal((T,) + shape)
+    want = moments.error_measures(mean_bar, mx, ex, nx)
+    sq_mean = np.mean((mx - ex) ** 2, axis=(2, 3, 4))
+    sq_norm = np.mean((nx - 1.0) ** 2, axis=(1, 2, 3))
+    got = q.error_measures(mean_bar, sq_mean, sq_norm)
+    assert np.allclose(got, want, rtol=1e-13, atol=0)
+    got = q.error_measures(mean_bar, None, sq_norm)
+    assert np.isnan(got[1]) and np.allclose([got[0], got[2], got[3]],
+                                            [want[0], want[2], want[3]], rtol=1e-13)
+
+
+def _oracle_flow(w, T, k):
+    st = stepper.MPSStepper(w)
+    f = st.initial_state()
+    M, h = w.M, 1.0 / w.M
+    phi = odense.phi_nodes(M)
+    U = st.velocity_dense()
+    G = np.full((M, M, M), w.gamma)
+    F = st.to_dense(f)
+    m = [h * h * np.einsum("i,iabc->abc", phi, F.sum(axis=1)),
+         h * h * np.einsum("j,jabc->abc", phi, F.sum(axis=0))]
+    bar, mx, ex, nx = np.zeros((2, T)), [[], []], [[], []], []
+    for t in range(T):
+        if t > 0:
+            for _ in range(k):
+                f, _ = st.step(f)
+                m = [moments.step(m[a], U, G, w.dt) for a in range(2)]
+        F = st.to_dense(f)
+        obs = st.observables(f)
+        bar[0, t], bar[1, t] = obs["mean1"], obs["mean2"]
+        nx.append(h * h * F.sum(axis=(0, 1)))
+        mx[0].append(h * h * np.einsum("i,iabc->abc", phi, F.sum(axis=1)))
+        mx[1].append(h * h * np.einsum("j,jabc->abc", phi, F.sum(axis=0)))
+        ex[0].append(m[0])
+        ex[1].append(m[1])
+    return moments.error_measures(bar, np.array(mx), np.array(ex), np.array(nx))
+
+
+def test_flow_protocol_matches_oracle(ctx):
+    """A short run of the protocol at Da = 0 (RK2, 5 samples, 2 steps apart)."""
+    from paper_2407_09169_amd import flow
+    w = workloads.get_workload("t_5d_M8_chi16", k_react=0.0, integrator="rk2")
+    T, k = 5, 2
+    want = _oracle_flow(w, T, k)
+    got = flow.run(ctx, w, n_samples=T, steps_per_sample=k)
+    vals = [got["E2b_up"], got["E2b_down"], got["E2c_up"], got["E2c_down"]]
+    assert all(np.isfinite(vals))
+    assert vals[1] > 0.0
+    assert np.allclose(vals, want, rtol=1e-6, atol=1e-8), (vals, want)
