@@ -97,12 +97,20 @@ def apply_axis(A: np.ndarray, f: np.ndarray, axis: int) -> np.ndarray:
 class DenseProblem:
     """Parameters and operators of eq. FP2 on the full grid."""
 
-    def __init__(self, ndims, M, omega, k_react, nu_phi, gamma=0.0, U=None):
+    def __init__(self, ndims, M, omega, k_react, nu_phi, gamma=0.0, U=None, G=None, Omega=None):
+        """G, Omega: optional (M, M, M) x-fields of the flow case (section
+        "Materials and Methods"): the total diffusivity gamma + gamma_SGS, which
+        replaces the constant gamma in the expanded variable-coefficient form
+        G D2_i f + (D1_i G)(D1_i f), and the LMSE frequency Omega_mix(x), which
+        replaces the constant omega."""
         if ndims not in (2, 5):
             raise ValueError("ndims must be 2 or 5")
         self.ndims, self.M = ndims, M
         self.omega, self.k_react, self.nu_phi, self.gamma = omega, k_react, nu_phi, gamma
         self.U = U  # list of three (M, M, M) arrays or None
+        self.G, self.Omega = G, Omega
+        if (G is not None or Omega is not None) and ndims != 5:
+            raise ValueError("x-fields need a 5-D problem")
         if ndims == 5 and U is None:
             raise ValueError("5-D problem needs a velocity field")
         self.D1g, self.D2g = d1_ghost(M), d2_ghost(M)
@@ -121,19 +129,27 @@ class DenseProblem:
         out = np.zeros_like(f)
         p1, p2 = self.phi
         react = self.k_react * p1 * p2 * f
+        om = self.omega if self.Omega is None else self.Omega[None, None]
         for a in (0, 1):
             m = self.mean_field(f, a)
-            flux = self.omega * (self.phi[a] - m) * f + react
+            flux = om * (self.phi[a] - m) * f + react
             out += apply_axis(self.D1g, flux, a)
             out += self.nu_phi * apply_axis(self.D2g, f, a)
         if self.ndims == 5:
             for i in range(3):
                 Ui = self.U[i][None, None]
-                out -= Ui * apply_axis(self.D1p, f, 2 + i)
-                out += self.gamma * apply_axis(self.D2p, f, 2 + i)
+                d1f = apply_axis(self.D1p, f, 2 + i)
+                out -= Ui * d1f
+                if self.G is None:
+                    out += self.gamma * apply_axis(self.D2p, f, 2 + i)
+                else:
+                    dG = apply_axis(self.D1p, self.G, i)[None, None]
+                    out += self.G[None, None] * apply_axis(self.D2p, f, 2 + i) + dG * d1f
         return out
 
     def rhs_tangent(self, f, df, param=None):
+        if self.G is not None or self.Omega is not None:
+            raise NotImplementedError("derivatives are defined for constant coefficients")
         """Directional derivative of rhs at (f, theta) along (df, e_param):
         the right-hand side linearised in f (the mean composition m_a depends
         on f, so d(m_a f) = m_a df + m_a(df) f) applied to df, plus the partial

@@ -8,6 +8,12 @@ in MPS arithmetic with the bond dimension of f limited to chi by singular
 value truncation after every operator application and every stage
 combination.
 
+With the flow case's x-fields (a total diffusivity G(x) and an LMSE
+frequency Omega_mix(x)), the constant-coefficient terms become
+diag(G) D2p_i + diag(D1p_i G) D1p_i and diag(Omega) D1g diag(phi_a), and the
+mean-field term uses the rounding of diag(Omega) <Phi_a>(x) with Omega = 1
+in front.
+
 Schedule of one RK4 step (RK2 is the Heun analogue):
 
     L(g)  = Round_chi( A(g) g ),   A(g) = A_fixed - Omega sum_a D1g^(phi_a) diag(m~_a(g))
@@ -38,8 +44,13 @@ from . import tt
 
 
 class MPSStepper:
-    def __init__(self, w):
+    def __init__(self, w, fields=None):
+        """fields: optional x-MPS cores of the flow case's variable
+        coefficients, {"G": total diffusivity gamma + gamma_SGS (replaces the
+        constant gamma), "Omega": LMSE frequency Omega_mix(x) (replaces the
+        constant omega)}."""
         self.w = w
+        self.fields = dict(fields or {})
         self.order = workloads.site_order(w)
         self.N = len(self.order)
         self.nd = w.ndims
@@ -65,6 +76,9 @@ class MPSStepper:
         self.Zml = workloads.left_mean_sketch_cores(w)
         self.ell_m = workloads.mean_sketch_ranks(w)
         self.U = self._velocity() if w.ndims == 5 else None
+        if self.fields and w.ndims != 5:
+            raise ValueError("x-fields need a 5-D problem")
+        self.dG = self._gradient(self.fields["G"]) if "G" in self.fields else None
         self.fixed = self._fixed_terms()
         self._weights = {}
 
@@ -90,6 +104,19 @@ class MPSStepper:
             out.append(x)
         return out
 
+    def _gradient(self, G):
+        """D1p_i G for i = 1, 2, 3 as exact x-MPSs (bond 3 times G's)."""
+        out = []
+        for i in range(3):
+            per = [None] * 3
+            per[i] = self.ops["D1p"]
+            out.append(tt.mpo_apply(tt.mpo_product(per, self._x_order(), 3), G))
+        return out
+
+    def _x_diag(self, x):
+        """diag(x) of an x-MPS, as an operator on the whole chain."""
+        return tt.identity_mpo(self.n_phi) + tt.mpo_diag(x)
+
     def initial_state(self, with_info=False):
         f = self._separable(workloads.ic_terms(self.w), self.order, self.nd)
         f, info = tt.round_det(f, self.w.chi, self.w.rel_tol)
@@ -106,7 +133,10 @@ class MPSStepper:
         for a in (0, 1):
             per = [None] * nd
             per[a] = o["D1g_phi"]
-            terms.append((w.omega, self._mpo(per)))
+            if "Omega" in self.fields:
+                terms.append((1.0, tt.mpo_compose(self._x_diag(self.fields["Omega"]), self._mpo(per))))
+            else:
+                terms.append((w.omega, self._mpo(per)))
             per = [None] * nd
             per[a] = o["D2g"]
             terms.append((w.nu_phi, self._mpo(per)))
@@ -117,7 +147,14 @@ class MPSStepper:
                 terms.append((w.k_react, self._mpo(per)))
         if nd == 5:
             for i in range(3):
-                if w.gamma != 0.0:
+                if "G" in self.fields:
+                    per = [None] * nd
+                    per[2 + i] = o["D2p"]
+                    terms.append((1.0, tt.mpo_compose(self._x_diag(self.fields["G"]), self._mpo(per))))
+                    per = [None] * nd
+                    per[2 + i] = o["D1p"]
+                    terms.append((1.0, tt.mpo_compose(self._x_diag(self.dG[i]), self._mpo(per))))
+                elif w.gamma != 0.0:
                     per = [None] * nd
                     per[2 + i] = o["D2p"]
                     terms.append((w.gamma, self._mpo(per)))
@@ -153,10 +190,14 @@ class MPSStepper:
         return [first] + [G.copy() for G in g[self.n_phi + 1:]]
 
     def mean_field(self, g, a):
+        """<Phi_a>(x) of g rounded to chi_mean; with an Omega field, the
+        product Omega_mix(x) <Phi_a>(x) (the field enters the rounding as a
+        diagonal operator)."""
         m = self.mean_field_raw(g, a)
         if self.nd == 2:
             return m, None
-        m, info = tt.round_sketch_two_sided([(1.0, None, m)], self.Zm, self.Zml,
+        W = tt.mpo_diag(self.fields["Omega"]) if "Omega" in self.fields else None
+        m, info = tt.round_sketch_two_sided([(1.0, W, m)], self.Zm, self.Zml,
                                             self.w.chi_mean, self.w.rel_tol)
         return m, info
 
@@ -171,7 +212,8 @@ class MPSStepper:
             if self.nd == 2:
                 terms.append((-w.omega * m, phi_part))
             else:
-                terms.append((-w.omega, phi_part + tt.mpo_diag(m)))
+                om = 1.0 if "Omega" in self.fields else w.omega
+                terms.append((-om, phi_part + tt.mpo_diag(m)))
         return terms
 
     def apply_exact(self, g):
@@ -252,5 +294,8 @@ class MPSStepper:
 
     def dense_problem(self):
         w = self.w
+        xo = self._x_order()
+        fd = {k: tt.sites_to_dense(tt.tt_full(v), xo, w.bits, 3) for k, v in self.fields.items()}
         return dense.DenseProblem(w.ndims, w.M, w.omega, w.k_react, w.nu_phi,
-                                  w.gamma if w.ndims == 5 else 0.0, self.velocity_dense())
+                                  w.gamma if w.ndims == 5 else 0.0, self.velocity_dense(),
+                                  G=fd.get("G"), Omega=fd.get("Omega"))

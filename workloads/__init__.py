@@ -11,4 +11,5 @@ from .configs import WORKLOADS, Workload, batch_workloads, get_workload, stable_
 from .generate import (  # noqa: F401
     phi_points, x_points, ic_terms, velocity_terms, sketch_ranks, sketch_cores,
     mean_sketch_ranks, mean_sketch_cores, left_sketch_cores, left_mean_sketch_cores, site_order,
+    flow_field_terms,
 )

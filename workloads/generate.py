@@ -127,6 +127,23 @@ def velocity_terms(w: Workload):
     ]
 
 
+def flow_field_terms(w: Workload):
+    """Seeded smooth x-fields standing in for the flow case's variable
+    coefficients, as separable terms over (x1, x2, x3):
+    {"G": gamma (1 + a sin(2 pi x1 + t1) cos(2 pi x3 + t3)),
+     "Omega": omega (1 + b cos(2 pi x2 + t2))}, 0 < a, b < 1/2."""
+    x = x_points(w.M)
+    rng = np.random.default_rng([w.seed, 3])
+    t = rng.uniform(0.0, 2.0 * np.pi, 3)
+    a, b = rng.uniform(0.2, 0.5, 2)
+    tp = 2.0 * np.pi
+    return {
+        "G": [(w.gamma, [None, None, None]),
+              (w.gamma * a, [np.sin(tp * x + t[0]), None, np.cos(tp * x + t[2])])],
+        "Omega": [(w.omega, [None, None, None]), (w.omega * b, [None, np.cos(tp * x + t[1]), None])],
+    }
+
+
 def _chain_ranks(n_sites: int, cap: int) -> list[int]:
     return [min(cap, 1 << n, 1 << (n_sites - n)) for n in range(n_sites + 1)]
 
