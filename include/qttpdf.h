@@ -243,6 +243,22 @@ typedef struct {
 tt_status tt_problem_create(tt_ctx* ctx, const tt_params* p, const tt_tt* const* velocity,
                             const tt_tt* sketch, const tt_tt* sketch_left, const tt_tt* sketch_mean,
                             const tt_tt* sketch_mean_left, tt_problem** out);
+/* The same problem with the flow case's variable coefficients (section
+ * "Materials and Methods", the paragraphs after eq. FP0, and eq. FP2): the
+ * x-MPS `diffusivity` (the total gamma + gamma_SGS, replacing the constant
+ * gamma: the diffusion term becomes diag(G) D2P_i + diag(D1P_i G) D1P_i,
+ * the expanded form of D1P_i (G D1P_i f)) and the x-MPS `mixing` (the LMSE
+ * frequency Omega_mix(x), replacing the constant omega in the drift
+ * diag(Omega) D1G diag(phi_a) and in the mean-field term, where the mean
+ * <Phi_a>(x) is rounded to chi_mean together with the factor Omega(x)).
+ * Either may be NULL (constant coefficient); both need ndims == 5 and the
+ * length of the x chain.  The fields are copied.  tt_step_tangent returns
+ * TT_ERR_UNSUPPORTED for such a problem. */
+tt_status tt_problem_create_flow(tt_ctx* ctx, const tt_params* p, const tt_tt* const* velocity,
+                                 const tt_tt* diffusivity, const tt_tt* mixing,
+                                 const tt_tt* sketch, const tt_tt* sketch_left,
+                                 const tt_tt* sketch_mean, const tt_tt* sketch_mean_left,
+                                 tt_problem** out);
 tt_status tt_problem_destroy(tt_problem* prob);
 /* Bond dimensions of the fixed stage MPO (n_sites + 1 entries, nullable). */
 tt_status tt_problem_info(const tt_problem* prob, int* n_sites, int32_t* mpo_bonds, int* max_mpo_bond);

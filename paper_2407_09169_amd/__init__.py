@@ -37,7 +37,7 @@ EXPORTS = [
     "tt_step", "tt_profile", "tt_step_info", "tt_observable", "tt_mean_field",
     "tt_linalg_qr", "tt_linalg_eigh", "tt_batch_create", "tt_step_batched", "tt_batch_destroy",
     "tt_step_tangent", "tt_moment_field", "tt_to_dense", "fd_smagorinsky", "fd_moment_steps",
-    "fd_sq_diff_sum", "flow_error_measures",
+    "fd_sq_diff_sum", "flow_error_measures", "tt_problem_create_flow",
 ]
 KERNELS = {"contract": 0, "qr": 1, "eig": 2, "stream": 3, "all": 4}
 
@@ -117,6 +117,7 @@ def lib():
         "fd_moment_steps": [vp, i32, i32, vp, vp, vp, vp, dbl, i32],
         "fd_sq_diff_sum": [vp, C.c_int64, vp, vp, dbl, P(dbl)],
         "flow_error_measures": [i32, P(dbl), P(dbl), P(dbl), P(dbl)],
+        "tt_problem_create_flow": [vp, P(TTParams), P(vp), vp, vp, vp, vp, vp, vp, P(vp)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -356,15 +357,22 @@ class Problem:
     """One eq. FP2 problem: fixed operator, sketches and the recorded step."""
 
     def __init__(self, ctx, params: TTParams, velocity=None, sketch=None, sketch_left=None,
-                 sketch_mean=None, sketch_mean_left=None):
+                 sketch_mean=None, sketch_mean_left=None, diffusivity=None, mixing=None):
+        """diffusivity / mixing: optional x-MPS fields G(x) and Omega_mix(x)
+        (tt_problem_create_flow)."""
         self.ctx = ctx
         self.params = params
         self._keep = (velocity, sketch, sketch_left, sketch_mean, sketch_mean_left)
         h = C.c_void_p()
         vel = _handles(velocity) if velocity else None
         opt = lambda t: t.h if t is not None else None  # noqa: E731
-        _check(lib().tt_problem_create(ctx.h, C.byref(params), vel, sketch.h, sketch_left.h,
-                                       opt(sketch_mean), opt(sketch_mean_left), C.byref(h)))
+        if diffusivity is None and mixing is None:
+            _check(lib().tt_problem_create(ctx.h, C.byref(params), vel, sketch.h, sketch_left.h,
+                                           opt(sketch_mean), opt(sketch_mean_left), C.byref(h)))
+        else:
+            _check(lib().tt_problem_create_flow(ctx.h, C.byref(params), vel, opt(diffusivity),
+                                                opt(mixing), sketch.h, sketch_left.h,
+                                                opt(sketch_mean), opt(sketch_mean_left), C.byref(h)))
         self.h = h
 
     def info(self):
@@ -497,8 +505,10 @@ def statistic_and_gradient(ctx, w, n_steps, statistic="product", dtype="f64",
     return J, grads
 
 
-def setup_workload(ctx, w, dtype="f64"):
-    """Builds (problem, f0) for a workloads.Workload with the seeded inputs."""
+def setup_workload(ctx, w, dtype="f64", fields=False):
+    """Builds (problem, f0) for a workloads.Workload with the seeded inputs;
+    fields=True adds the seeded x-fields G(x) and Omega(x)
+    (workloads.flow_field_terms, built exactly from their separable terms)."""
     import workloads
 
     ordering = TT_SERIAL if w.ordering == "serial" else TT_INTERLEAVED
@@ -515,7 +525,12 @@ def setup_workload(ctx, w, dtype="f64"):
                  integrator=TT_RK4 if w.integrator == "rk4" else TT_RK2_HEUN,
                  dtype=DTYPES[dtype], omega=w.omega, k_react=w.k_react, nu_phi=w.nu_phi,
                  gamma=w.gamma, dt=w.dt)
-    prob = Problem(ctx, p, velocity, sketch, sketch_left, sketch_mean, sketch_mean_left)
+    fx = {}
+    if fields:
+        for k, terms in workloads.flow_field_terms(w).items():
+            fx[k] = from_separable(ctx, 3, w.bits, TT_SERIAL, terms, 16)
+    prob = Problem(ctx, p, velocity, sketch, sketch_left, sketch_mean, sketch_mean_left,
+                   diffusivity=fx.get("G"), mixing=fx.get("Omega"))
     f0 = from_separable(ctx, w.ndims, w.bits, ordering, workloads.ic_terms(w), w.chi)
     return prob, f0
 

@@ -141,6 +141,11 @@ struct tt_problem {
   std::unique_ptr<tt_tt> A;   // combined stage operator: fixed (+) mean-field part
   std::vector<int> Dfix;      // bonds of the fixed operator
   std::unique_ptr<tt_tt> Wm;  // mean-field weights over the phi sites (2 output channels)
+  // flow-case x-fields: total diffusivity G(x) and LMSE frequency Omega(x);
+  // Wom = diag(Omega) over the x sites (weights the mean-field rounding)
+  bool has_G = false, has_Om = false;
+  std::unique_ptr<tt_tt> Wom;
+  ChainView Womv;
   DevBuf mf_first;                  // 2-D: unscaled first-core blocks [1][4][cols_a] of the two
   std::vector<int> mf_first_off;    //      mean-field terms, block a at a * 4 * mf_first_ld
   std::vector<int> mf_first_cols;
@@ -257,6 +262,7 @@ static void plan_mean_round(Plan& plan, tt_problem* P, const std::vector<MeanTer
     for (const MeanTerm& m : terms) {
       SketchTerm t;
       t.coef = m.c;
+      t.mpo = P->has_Om ? &P->Womv : nullptr;
       t.x = mean_view(P, m.x, m.first, a);
       st[a].push_back(t);
     }
@@ -831,6 +837,15 @@ tt_status tt_inner(tt_ctx* ctx, const tt_tt* a, const tt_tt* b, double* out) {
 tt_status tt_problem_create(tt_ctx* ctx, const tt_params* pp, const tt_tt* const* velocity,
                             const tt_tt* sketch, const tt_tt* sketch_left, const tt_tt* sketch_mean,
                             const tt_tt* sketch_mean_left, tt_problem** out) {
+  return tt_problem_create_flow(ctx, pp, velocity, nullptr, nullptr, sketch, sketch_left,
+                                sketch_mean, sketch_mean_left, out);
+}
+
+tt_status tt_problem_create_flow(tt_ctx* ctx, const tt_params* pp, const tt_tt* const* velocity,
+                                 const tt_tt* diffusivity, const tt_tt* mixing,
+                                 const tt_tt* sketch, const tt_tt* sketch_left,
+                                 const tt_tt* sketch_mean, const tt_tt* sketch_mean_left,
+                                 tt_problem** out) {
   return guard([&] {
     QTT_REQUIRE(ctx && pp && out, "null argument");
     const tt_params& p = *pp;
@@ -890,20 +905,61 @@ tt_status tt_problem_create(tt_ctx* ctx, const tt_params* pp, const tt_tt* const
       t.field = field;
       terms.push_back(t);
     };
-    for (int a = 0; a < 2; ++a) {
-      term(p.omega, {{a, TT_OP_D1G_PHI}}, -1);
-      term(p.nu_phi, {{a, TT_OP_D2G}}, -1);
-      if (p.k_react != 0.0) term(p.k_react, {{a, TT_OP_D1G_PHI}, {1 - a, TT_OP_PHI}}, -1);
-    }
+    // flow-case x-fields (fields 3: G, 4..6: D1p_i G, 7: Omega)
     std::vector<host::TT> fields;
+    if (diffusivity || mixing) QTT_REQUIRE(P->nx > 0, "x-fields need a 5-D problem");
     if (P->nx > 0) {
       for (int i = 0; i < 3; ++i) {
         check_tt(velocity[i], ctx);
         QTT_REQUIRE(velocity[i]->N == P->nx, "velocity component %d length", i);
         fields.push_back(download(velocity[i]));
       }
+      auto x_order = host::site_order(3, p.bits, TT_SERIAL);
+      host::TT Gh, Omh;
+      if (diffusivity) {
+        check_tt(diffusivity, ctx);
+        QTT_REQUIRE(diffusivity->N == P->nx && diffusivity->kind == TT_MPS, "diffusivity field shape");
+        Gh = host::round_svd(download(diffusivity), 1e-14, 1 << 30);  // drops the zero padding
+      }
+      if (mixing) {
+        check_tt(mixing, ctx);
+        QTT_REQUIRE(mixing->N == P->nx && mixing->kind == TT_MPS, "mixing field shape");
+        Omh = host::round_svd(download(mixing), 1e-14, 1 << 30);
+      }
+      fields.push_back(Gh);
+      host::TT d1p = host::op1d(TT_OP_D1P, p.bits);
       for (int i = 0; i < 3; ++i) {
-        if (p.gamma != 0.0) term(p.gamma, {{2 + i, TT_OP_D2P}}, -1);
+        host::TT dG;
+        if (diffusivity) {
+          std::vector<const host::TT*> per(3, nullptr);
+          per[i] = &d1p;
+          dG = host::mpo_apply(host::kron_dims(per, x_order, 3, 4), Gh);
+        }
+        fields.push_back(dG);
+      }
+      fields.push_back(Omh);
+      P->has_G = diffusivity != nullptr;
+      P->has_Om = mixing != nullptr;
+      if (P->has_Om) {
+        host::TT W = host::mpo_diag(Omh);
+        P->Wom = upload(ctx, TT_MPO, W, exact_caps(W));
+        P->Womv = view(P->Wom.get());
+      }
+    }
+    for (int a = 0; a < 2; ++a) {
+      if (P->has_Om) term(1.0, {{a, TT_OP_D1G_PHI}}, 7);
+      else term(p.omega, {{a, TT_OP_D1G_PHI}}, -1);
+      term(p.nu_phi, {{a, TT_OP_D2G}}, -1);
+      if (p.k_react != 0.0) term(p.k_react, {{a, TT_OP_D1G_PHI}, {1 - a, TT_OP_PHI}}, -1);
+    }
+    if (P->nx > 0) {
+      for (int i = 0; i < 3; ++i) {
+        if (P->has_G) {
+          term(1.0, {{2 + i, TT_OP_D2P}}, 3);
+          term(1.0, {{2 + i, TT_OP_D1P}}, 4 + i);
+        } else if (p.gamma != 0.0) {
+          term(p.gamma, {{2 + i, TT_OP_D2P}}, -1);
+        }
         term(-1.0, {{2 + i, TT_OP_D1P}}, i);
       }
     }
@@ -950,7 +1006,7 @@ tt_status tt_problem_create(tt_ctx* ctx, const tt_params* pp, const tt_tt* const
     P->Dmf = Dmf;
     // 5-D: the mean-field block carries -Omega in its first core; 2-D: the
     // first-core blocks are rescaled by -Omega <Phi_a> at every stage
-    P->A = assemble_stage_mpo(P.get(), Fx, P->nx > 0 ? -p.omega : 1.0, P->Dfix);
+    P->A = assemble_stage_mpo(P.get(), Fx, P->nx > 0 ? (P->has_Om ? -1.0 : -p.omega) : 1.0, P->Dfix);
     if (P->nx == 0) {
       // first-core blocks of the two mean-field terms, kept unscaled
       P->mf_first_cols = {T[0][0].rr, T[1][0].rr};
@@ -1214,6 +1270,8 @@ tt_status tt_step_tangent(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_params,
                 "bad argument");
     check_tt(f, ctx);
     QTT_REQUIRE(prob->ctx == ctx, "problem belongs to another context");
+    if (prob->has_G || prob->has_Om)
+      QTT_THROW(TT_ERR_UNSUPPORTED, "parameter derivatives need constant coefficients (no x-fields)");
     QTT_REQUIRE(f->caps == prob->fcaps, "state caps differ from the problem's");
     std::vector<Tangent> tan;
     std::vector<const void*> key{f};

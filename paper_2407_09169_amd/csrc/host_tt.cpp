@@ -406,6 +406,26 @@ TT mpo_compose(const TT& A, const TT& B) {
   return out;
 }
 
+TT mpo_apply(const TT& W, const TT& x) {
+  TT out;
+  for (size_t n = 0; n < x.size(); ++n) {
+    const Core &A = W[n], &B = x[n];
+    // out[(b, alpha), t, (c, beta)] = sum_s A[alpha, t, s, beta] B[b, s, c]
+    Core G(B.rl * A.rl, 2, B.rr * A.rr);
+    for (int b = 0; b < B.rl; ++b)
+      for (int al = 0; al < A.rl; ++al)
+        for (int t = 0; t < 2; ++t)
+          for (int c = 0; c < B.rr; ++c)
+            for (int be = 0; be < A.rr; ++be) {
+              double v = 0.0;
+              for (int s2 = 0; s2 < 2; ++s2) v += A.at(al, t * 2 + s2, be) * B.at(b, s2, c);
+              G.at(b * A.rl + al, t, c * A.rr + be) = v;
+            }
+    out.push_back(std::move(G));
+  }
+  return out;
+}
+
 TT mpo_diag(const TT& x) {
   TT out;
   for (const Core& G : x) {

@@ -47,6 +47,8 @@ TT tt_sum(const std::vector<std::pair<double, const TT*>>& terms);
 TT mpo_compose(const TT& A, const TT& B);
 // diag(x) for an MPS x
 TT mpo_diag(const TT& x);
+// exact MPO x MPS product W x (bonds multiply)
+TT mpo_apply(const TT& W, const TT& x);
 // identity MPO over n sites
 TT mpo_identity(int n);
 

@@ -10,9 +10,9 @@ sums (fd_sq_diff_sum) and the final measures (flow_error_measures).  This
 module only sequences the calls and holds device tensors.
 
 The moment equation sees the same velocity as the MPS problem (its velocity
-MPSs evaluated on the grid) and, as the problem has a constant diffusivity,
-the constant field G = gamma; its initial condition is the first composition
-moment of the initial PDF.  Exact means exist only without reaction (Da =
+MPSs evaluated on the grid) and the same diffusivity (the constant gamma, or
+the problem's x-field G(x) evaluated on the grid); its initial condition is
+the first composition moment of the initial PDF.  Exact means exist only without reaction (Da =
 0); with reaction the measure Error_2b down is NaN.
 """
 from __future__ import annotations
@@ -23,7 +23,7 @@ from . import (TT_SERIAL, from_separable, error_measures, moment_steps, setup_wo
                sq_diff_sum, to_dense)
 
 
-def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None):
+def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None, fields=False):
     """Advances workload w (5-D) for (n_samples - 1) * steps_per_sample steps,
     sampling at every steps_per_sample steps from t = 0.
 
@@ -31,7 +31,9 @@ def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None):
     "E2c_down") and the per-sample series they come from: "mean_bar" (2, T),
     "sq_mean_x" (2, T) and "sq_norm_x" (T) (grid means of the squared
     differences).  exact: None (solve the moment equation when k_react == 0)
-    or False (skip it)."""
+    or False (skip it).  fields=True runs the problem with the seeded x-fields
+    G(x) and Omega(x) (setup_workload), and the moment equation with the
+    same G(x)."""
     import torch
     import workloads
 
@@ -42,7 +44,7 @@ def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None):
     bits, M = w.bits, w.M
     n = M ** 3
     dev = torch.device("cuda", ctx.device)
-    prob, f = setup_workload(ctx, w, dtype)
+    prob, f = setup_workload(ctx, w, dtype, fields=fields)
     phi = (np.arange(M) + 0.5) / M
     dense = torch.empty(n, dtype=torch.float64, device=dev)
     m = work = U = G = None
@@ -53,6 +55,10 @@ def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None):
             to_dense(ctx, v, U[i * n:(i + 1) * n])
             v.free()
         G = torch.full((n,), w.gamma, dtype=torch.float64, device=dev)
+        if fields:
+            g = from_separable(ctx, 3, bits, TT_SERIAL, workloads.flow_field_terms(w)["G"], 16)
+            to_dense(ctx, g, G)
+            g.free()
         m = torch.empty(2 * n, dtype=torch.float64, device=dev)
         work = torch.empty(2 * n, dtype=torch.float64, device=dev)
         for a in range(2):

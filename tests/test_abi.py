@@ -143,3 +143,30 @@ print("ok")
 """ % ROOT
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
+
+
+def test_dry_run_field_problem_planning_is_in_bounds():
+    """A problem with the x-fields G(x) and Omega(x) (5-D M = 8, 16 and the
+    M = 128 flow grid) plans every launch in bounds, and refuses tangents."""
+    code = r"""
+import os, sys
+os.environ["QTTPDF_DRYRUN"] = "1"
+sys.path.insert(0, %r)
+import paper_2407_09169_amd as q, workloads
+ctx = q.Context(0, stream=0)
+for w in [workloads.get_workload("t_5d_M8_chi16"), workloads.get_workload("t_5d_M16_chi32"),
+          workloads.get_workload("c2_5d_M128_chi64")]:
+    for dt in ("f64", "f32"):
+        prob, f = q.setup_workload(ctx, w, dt, fields=True)
+        prob.step(f, 1)
+        prob.observable(f, "mass")
+    try:
+        prob.step_tangent(f, {"omega": prob.state()}, 1)
+    except q.QttError as e:
+        assert "status 5" in str(e), e
+    else:
+        raise SystemExit("tangent accepted for a field problem")
+print("ok")
+""" % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr

@@ -14,7 +14,8 @@ import pytest
 
 import workloads
 from oracle import dense as odense, moments, stepper, tt
-from tests.helpers import random_tt
+from oracle.dense import dense_from_terms
+from tests.helpers import random_tt, truncation_sensitivity
 
 q = pytest.importorskip("paper_2407_09169_amd")
 
@@ -199,3 +200,60 @@ def test_flow_protocol_matches_oracle(ctx):
     assert all(np.isfinite(vals))
     assert vals[1] > 0.0
     assert np.allclose(vals, want, rtol=1e-6, atol=1e-8), (vals, want)
+
+
+def _field_stepper(w):
+    st0 = stepper.MPSStepper(w)
+    xo = st0._x_order()
+    fields = {k: st0._separable(terms, xo, 3) for k, terms in workloads.flow_field_terms(w).items()}
+    return stepper.MPSStepper(w, fields)
+
+
+@pytest.mark.parametrize("integrator", ["rk2", "rk4"])
+def test_field_step_untruncated_equals_dense(ctx, integrator):
+    """Variable G(x) and Omega(x) at exact ranks: the GPU step reproduces the
+    full-grid solver with the same fields."""
+    w = workloads.get_workload("t_5d_M8_exact", integrator=integrator)
+    st = _field_stepper(w)
+    P = st.dense_problem()
+    prob, f = q.setup_workload(ctx, w, "f64", fields=True)
+    fd = dense_from_terms(workloads.ic_terms(w), w.ndims, w.M)
+    for _ in range(3):
+        prob.step(f, 1)
+        fd = P.step(fd, w.dt, integrator)
+        err = np.linalg.norm(st.to_dense(f.cores()) - fd) / np.linalg.norm(fd)
+        assert err < 1e-11, err
+    prob.close()
+
+
+@pytest.mark.parametrize("name,integrator", [("t_5d_M8_chi16", "rk2"), ("t_5d_M16_chi32", "rk4")])
+def test_field_step_truncated_matches_oracle(ctx, name, integrator):
+    """Truncated FP64 steps with the x-fields, to the same bound as the
+    constant-coefficient steps (10x the oracle's first-order truncation
+    sensitivity plus 1e-10)."""
+    w = workloads.get_workload(name, integrator=integrator)
+    st = _field_stepper(w)
+    prob, f = q.setup_workload(ctx, w, "f64", fields=True)
+    fo = st.initial_state()
+    sens = 0.0
+    for i in range(3):
+        prob.step(f, 1)
+        fo, infos = st.step(fo)
+        sens += truncation_sensitivity(infos)
+        tol = 1e-10 + 10 * sens
+        err = np.linalg.norm(st.to_dense(f.cores()) - st.to_dense(fo)) / np.linalg.norm(st.to_dense(fo))
+        assert err < tol, (name, i, err, tol)
+    with pytest.raises(q.QttError):
+        prob.step_tangent(f, {"omega": prob.state()}, 1)
+    prob.close()
+
+
+def test_flow_protocol_with_fields_runs(ctx):
+    """The protocol with G(x) and Omega(x): finite measures, the mass-norm
+    error at the truncation level, and the exact-mean error above zero."""
+    from paper_2407_09169_amd import flow
+    w = workloads.get_workload("t_5d_M16_chi32", k_react=0.0, integrator="rk2")
+    got = flow.run(ctx, w, n_samples=5, steps_per_sample=2, fields=True)
+    vals = [got["E2b_up"], got["E2b_down"], got["E2c_up"], got["E2c_down"]]
+    assert all(np.isfinite(vals)), vals
+    assert 0.0 < vals[1] < 1e-2 and vals[3] < 1e-2, vals
