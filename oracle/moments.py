@@ -81,6 +81,44 @@ def step(m: np.ndarray, U, G, dt: float) -> np.ndarray:
     return m + 0.5 * dt * (k1 + k2)
 
 
+def rhs_at(m: np.ndarray, U, G, pts: np.ndarray) -> np.ndarray:
+    """The right-hand side of ``rhs`` at the grid points pts (k x 3 integer
+    indices), each evaluated on its own from its periodic neighbours: for
+    checks of large grids at sampled points."""
+    M = m.shape[0]
+    h = 1.0 / M
+    pts = np.asarray(pts) % M
+    out = np.zeros(len(pts))
+    for q, (a, b, c) in enumerate(pts):
+        idx = (a, b, c)
+        for i in range(3):
+            p1 = list(idx)
+            m1 = list(idx)
+            p1[i] = (idx[i] + 1) % M
+            m1[i] = (idx[i] - 1) % M
+            p1, m1 = tuple(p1), tuple(m1)
+            d1 = (m[p1] - m[m1]) / (2 * h)
+            d2 = (m[p1] - 2 * m[idx] + m[m1]) / (h * h)
+            dG = (G[p1] - G[m1]) / (2 * h)
+            out[q] += -U[i][idx] * d1 + G[idx] * d2 + dG * d1
+    return out
+
+
+def step_at(m: np.ndarray, U, G, dt: float, pts: np.ndarray) -> np.ndarray:
+    """One Heun step (as ``step``) at the grid points pts only: the first
+    stage is evaluated at the points and their six neighbours."""
+    M = m.shape[0]
+    pts = np.asarray(pts) % M
+    offs = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    nb = np.concatenate([(pts + np.array(o)) % M for o in offs])
+    m1_nb = m[tuple(nb.T)] + dt * rhs_at(m, U, G, nb)
+    m1 = m.copy()  # only the stencil points of m1 are used below
+    m1[tuple(nb.T)] = m1_nb
+    k1 = rhs_at(m, U, G, pts)
+    k2 = rhs_at(m1, U, G, pts)
+    return m[tuple(pts.T)] + 0.5 * dt * (k1 + k2)
+
+
 def time_mean_sq(g, g0) -> float:
     """E_t of eq. RMSE1: the mean over the time samples of (g - g0)^2."""
     g = np.asarray(g, dtype=np.float64)

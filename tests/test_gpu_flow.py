@@ -68,7 +68,7 @@ def test_smagorinsky_matches_oracle(ctx, bits):
     _close(G.cpu().numpy().reshape(M, M, M), want, 1e-12)
 
 
-@pytest.mark.parametrize("bits,count,steps", [(3, 1, 3), (4, 2, 5), (5, 2, 8)])
+@pytest.mark.parametrize("bits,count,steps", [(3, 1, 3), (4, 2, 5), (5, 2, 8), (6, 2, 3), (7, 1, 2)])
 def test_moment_steps_match_oracle(ctx, bits, count, steps):
     """Smagorinsky diffusivity (strengthened so that the variable-coefficient
     term matters), eq. velField, seeded random initial means."""
@@ -257,3 +257,38 @@ def test_flow_protocol_with_fields_runs(ctx):
     vals = [got["E2b_up"], got["E2b_down"], got["E2c_up"], got["E2c_down"]]
     assert all(np.isfinite(vals)), vals
     assert 0.0 < vals[1] < 1e-2 and vals[3] < 1e-2, vals
+
+
+@pytest.mark.parametrize("bits,count", [(8, 1), (8, 2)])
+def test_moment_steps_full_size_sampled(ctx, bits, count):
+    """M = 256, one and two fields, one step in the launch configuration the
+    bench times from M = 256 up (column kernel, 16 planes per workgroup): sampled points
+    against the oracle's point-by-point step, including the tile, chunk and
+    periodic edges."""
+    import torch
+    M = 1 << bits
+    n = M ** 3
+    rng = np.random.default_rng(bits)
+    dev = torch.device("cuda")
+    U = _paper_velocity(M)
+    delta = 3.0 / M
+    Ud = _cuda(np.concatenate([u.ravel() for u in U]))
+    Gd = torch.empty(n, dtype=torch.float64, device=dev)
+    q.smagorinsky(ctx, bits, Ud, Gd, 2.0, delta, 1e-3)
+    G = Gd.cpu().numpy().reshape(M, M, M)  # checked against the oracle below
+    pts = rng.integers(0, M, size=(400, 3))
+    edges = np.array([[0, 0, 0], [M - 1, M - 1, M - 1], [15, 3, 63], [16, 4, 64], [M - 1, 0, 64],
+                      [31, M - 1, 0], [32, 127, 191]])
+    pts = np.concatenate([pts, edges % M])
+    Gor = moments.gamma_total(U, 1e-3, 2.0, delta)
+    want_g = Gor[tuple(pts.T)]
+    assert np.max(np.abs(G[tuple(pts.T)] - want_g)) <= 1e-12 * np.max(np.abs(want_g))
+    m0 = rng.random((count, M, M, M))
+    dt = 0.2 / (M * M * float(G.max()) * 6 + M * 4)
+    m = _cuda(m0.ravel())
+    work = torch.empty_like(m)
+    q.moment_steps(ctx, bits, Ud, Gd, m, work, dt, 1)
+    got = m.cpu().numpy().reshape(count, M, M, M)
+    for a in range(count):
+        want = moments.step_at(m0[a], U, Gor, dt, pts)
+        _close(got[a][tuple(pts.T)], want, 1e-12)

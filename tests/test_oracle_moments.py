@@ -189,3 +189,19 @@ def test_matches_dense_fokker_planck_moment_variable_diffusivity():
             mm = moments.step(mm, U, G, dt)
         got = prob.mean_field(g, a)[0, 0]
         assert np.max(np.abs(got - mm)) < 1e-13 * np.max(np.abs(mm))
+
+
+def test_step_at_points_equals_step():
+    """The point-by-point Heun step reproduces the whole-grid step."""
+    M = 16
+    U, _ = _velocity_case(M)
+    X1, X2, X3 = _grid(M)
+    G = 1e-2 * (1.0 + 0.5 * np.sin(2 * np.pi * X1) * np.cos(2 * np.pi * X3))
+    m = np.random.default_rng(2).random((M, M, M))
+    dt = 1e-4
+    pts = np.random.default_rng(3).integers(0, M, size=(40, 3))
+    pts[0] = (0, 0, 0)
+    pts[1] = (M - 1, M - 1, M - 1)
+    want = moments.step(m, U, G, dt)[tuple(pts.T)]
+    got = moments.step_at(m, U, G, dt, pts)
+    assert np.max(np.abs(got - want)) < 1e-13 * np.max(np.abs(want))
