@@ -43,7 +43,8 @@ def _time_steps(torch, prob, f, K):
     return t0.elapsed_time(t1)
 
 
-KERNEL_SOURCES = {"qr_": "factor.hip", "eig_": "factor.hip", "tc_": "tc_gemm.hip"}
+KERNEL_SOURCES = {"qr_": "factor.hip", "eig_": "factor.hip", "tc_": "tc_gemm.hip",
+                  "moment_": "moments.hip"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.txt")
 
 
@@ -274,6 +275,7 @@ def _bench_moments(args, log):
     ms = e0.elapsed_time(e1)
     value = args.steps / (ms / 1e3)
     per_launch_bytes = (64 + 80) / 2 * n
+    kernel = "moment_stage_col_kernel<2>" if bits >= 8 else "moment_stage_kernel<2>"
     avg_us = ms * 1e3 / (2 * args.steps)
     achieved = per_launch_bytes / (avg_us * 1e-6) / 1e9
     log(f"moments M={M}: {args.steps} RK2 steps in {ms:.2f} ms ({value:.1f} steps/s, "
@@ -285,8 +287,8 @@ def _bench_moments(args, log):
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "grid": f"{M}^3", "fields": 2, "dt": dt},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_GBS, "traffic": None,
-                     "kernel": "moment_stage_kernel<2>", "avg_launch_us": avg_us,
+                     "frac": achieved / HBM_GBS, "traffic": _traffic(kernel, f"M{M}"),
+                     "kernel": kernel, "avg_launch_us": avg_us,
                      "algorithmic_bytes_per_launch": per_launch_bytes,
                      "timing": "events around the timed steps, divided by the launches"},
         "finite": bool(torch.isfinite(m).all()),
