@@ -296,6 +296,43 @@ def _bench_moments(args, log):
     print(json.dumps(out))
 
 
+def _bench_flow(args, log):
+    """The flow case's accuracy protocol on the paper's 128^5 grid: the MPS
+    step (chi = 64, RK2, Da = 0, the seeded x-fields G(x) and Omega(x)) and the
+    moment equation advanced side by side from the printed initial PDF and
+    velocity (eq. initPDF, eq. velField), 17 samples, the four error measures
+    of eq. RMSE0; protocol steps/s over the whole run."""
+    import torch
+    import paper_2407_09169_amd as q
+    from paper_2407_09169_amd import flow
+    import workloads
+    w = workloads.get_workload("c2_5d_M128_chi64", k_react=0.0, integrator="rk2", ic="paper")
+    ctx = q.Context(0)
+    k = max(1, args.steps // 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = flow.run(ctx, w, n_samples=17, steps_per_sample=k, dtype=args.dtype, fields=True)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    steps = 16 * k
+    log(f"flow protocol 128^5 chi=64: {steps} steps and 17 samples in {sec:.2f} s; "
+        f"E2b up {r['E2b_up']:.3e} down {r['E2b_down']:.3e}, E2c up {r['E2c_up']:.3e} down {r['E2c_down']:.3e}")
+    out = {
+        "metric": "flow-protocol steps/s (MPS step + moment equation + 17 samples of the error measures)",
+        "value": steps / sec, "unit": "steps/s", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": 1e3 * sec / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": "flow_c2_5d_M128_chi64", "grid": "128^5", "chi": w.chi,
+                   "integrator": "rk2", "k_react": 0.0, "dt": w.dt, "samples": 17,
+                   "steps_per_sample": k, "fields": "seeded G(x), Omega(x)",
+                   "initial_state": "eq. initPDF, eq. velField"},
+        "errors": {"E2b_up": r["E2b_up"], "E2b_down": r["E2b_down"], "E2c_up": r["E2c_up"],
+                   "E2c_down": r["E2c_down"]},
+        "timing": "wall clock of the whole protocol, set-up and first-step recording included",
+    }
+    print(json.dumps(out))
+
+
 def _bench_gradient(args, log):
     """Steps of the gradient workload carrying d f / d Omega and d f / d k
     (tt_step_tangent): gradient-steps/s and the final dJ/dtheta of the
@@ -416,6 +453,9 @@ def main():
         return
     if args.workload.startswith("fpmoms_M"):
         _bench_moments(args, log)
+        return
+    if args.workload == "flow_c2_5d_M128_chi64":
+        _bench_flow(args, log)
         return
     w = workloads.get_workload(args.workload)
     ctx = q.Context(0)
