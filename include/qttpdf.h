@@ -366,6 +366,17 @@ tt_status tt_moment_field(tt_ctx* ctx, tt_problem* prob, const tt_tt* f, const d
  * (2^N doubles, the first site's digit most significant; for an x-MPS of
  * the serial ordering this is the [x1][x2][x3] layout).  Synchronises. */
 tt_status tt_to_dense(tt_ctx* ctx, const tt_tt* x, double* out);
+/* An MPS of a dense vector of 2^n_sites values (device array; for an x-field
+ * the [x1][x2][x3] layout gives the serial x chain): the truncated TT-SVD
+ * from the left, every bond cut to min(chi, 2^n, 2^(N-n)) leading left
+ * singular vectors taken from the eigen-decomposition of the unfolding's Gram
+ * matrix (FP64; directions below about sqrt(eps) sigma_1 are not resolved).
+ * Used for fields that are not sums of separable terms, such as the
+ * Smagorinsky diffusivity (whose bonds the paper keeps of order ten).
+ * *discarded (nullable) receives the sum of the dropped eigenvalues over the
+ * bonds, the squared 2-norm of the approximation error.  Synchronises. */
+tt_status tt_from_dense(tt_ctx* ctx, int n_sites, const double* values, int chi, tt_tt** out,
+                        double* discarded);
 /* Total diffusivity G = gamma + gamma_SGS with the Smagorinsky closure of
  * the paragraph after eq. FP0: gamma_SGS = c_s delta^2 / 2 times the square
  * root of sum_ij (dU_i/dx_j + dU_j/dx_i)^2, the derivatives taken as

@@ -37,7 +37,7 @@ EXPORTS = [
     "tt_step", "tt_profile", "tt_step_info", "tt_observable", "tt_mean_field",
     "tt_linalg_qr", "tt_linalg_eigh", "tt_batch_create", "tt_step_batched", "tt_batch_destroy",
     "tt_step_tangent", "tt_moment_field", "tt_to_dense", "fd_smagorinsky", "fd_moment_steps",
-    "fd_sq_diff_sum", "flow_error_measures", "tt_problem_create_flow",
+    "fd_sq_diff_sum", "flow_error_measures", "tt_problem_create_flow", "tt_from_dense",
 ]
 KERNELS = {"contract": 0, "qr": 1, "eig": 2, "stream": 3, "all": 4}
 
@@ -118,6 +118,7 @@ def lib():
         "fd_sq_diff_sum": [vp, C.c_int64, vp, vp, dbl, P(dbl)],
         "flow_error_measures": [i32, P(dbl), P(dbl), P(dbl), P(dbl)],
         "tt_problem_create_flow": [vp, P(TTParams), P(vp), vp, vp, vp, vp, vp, vp, P(vp)],
+        "tt_from_dense": [vp, i32, vp, i32, P(vp), P(dbl)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -508,7 +509,8 @@ def statistic_and_gradient(ctx, w, n_steps, statistic="product", dtype="f64",
 def setup_workload(ctx, w, dtype="f64", fields=False):
     """Builds (problem, f0) for a workloads.Workload with the seeded inputs;
     fields=True adds the seeded x-fields G(x) and Omega(x)
-    (workloads.flow_field_terms, built exactly from their separable terms)."""
+    (workloads.flow_field_terms, built exactly from their separable terms); a
+    dict {"G": TT, "Omega": TT} passes given x-MPSs."""
     import workloads
 
     ordering = TT_SERIAL if w.ordering == "serial" else TT_INTERLEAVED
@@ -525,8 +527,8 @@ def setup_workload(ctx, w, dtype="f64", fields=False):
                  integrator=TT_RK4 if w.integrator == "rk4" else TT_RK2_HEUN,
                  dtype=DTYPES[dtype], omega=w.omega, k_react=w.k_react, nu_phi=w.nu_phi,
                  gamma=w.gamma, dt=w.dt)
-    fx = {}
-    if fields:
+    fx = dict(fields) if isinstance(fields, dict) else {}
+    if fields is True:
         for k, terms in workloads.flow_field_terms(w).items():
             fx[k] = from_separable(ctx, 3, w.bits, TT_SERIAL, terms, 16)
     prob = Problem(ctx, p, velocity, sketch, sketch_left, sketch_mean, sketch_mean_left,
@@ -553,6 +555,20 @@ def to_dense(ctx, x, out):
     _, n_sites, _, _ = x.info()
     _check(lib().tt_to_dense(ctx.h, x.h, _dense_arg(out, 1 << n_sites, "out")))
     return out
+
+
+def from_dense(ctx, values, chi):
+    """(MPS, discarded weight) of a dense float64 CUDA tensor of 2^N values
+    (tt_from_dense: truncated TT-SVD, bonds capped at chi)."""
+    n = values.numel()
+    N = n.bit_length() - 1
+    if n != 1 << N:
+        raise ValueError("the number of values must be a power of two")
+    h = C.c_void_p()
+    disc = C.c_double()
+    _check(lib().tt_from_dense(ctx.h, N, _dense_arg(values, n, "values"), chi, C.byref(h),
+                               C.byref(disc)))
+    return TT(ctx, h), disc.value
 
 
 def smagorinsky(ctx, bits, U, G, c_s, delta, gamma):

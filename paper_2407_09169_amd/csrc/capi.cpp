@@ -1643,3 +1643,61 @@ tt_status flow_error_measures(int n_samples, const double* mean_bar, const doubl
     out[3] = std::sqrt(cd / T);
   });
 }
+
+extern "C" {
+
+tt_status tt_from_dense(tt_ctx* ctx, int n_sites, const double* values, int chi, tt_tt** out,
+                        double* discarded) {
+  return guard([&] {
+    QTT_REQUIRE(ctx && values && out, "bad argument");
+    const int N = n_sites;
+    QTT_REQUIRE(N >= 2 && N <= 30, "tt_from_dense: %d sites outside [2, 30]", N);
+    QTT_REQUIRE(chi >= 1 && chi <= 512, "tt_from_dense: chi %d outside [1, 512]", chi);
+    const int64_t total = int64_t(1) << N;
+    auto caps = chain_caps(N, chi);
+    auto x = make_tt(ctx, TT_MPS, N, caps);
+    DevBuf A((size_t)total * 8), B((size_t)total * 8);
+    int gm = 2;
+    for (int n = 0; n < N; ++n) gm = std::max(gm, 2 * caps[n]);
+    DevBuf Gd((size_t)gm * gm * 8), Pd((size_t)gm * gm * 8), Ld((size_t)gm * 8),
+        Wd((size_t)eig_work_size(1, gm) * 8), dd(sizeof(int)), dk(sizeof(int));
+    StreamScope sc(ctx);
+    hipStream_t s = ctx->stream;
+    rt::copy_async(A.p, values, (size_t)total * 8, s);
+    double disc = 0.0;
+    std::vector<double> lam(gm);
+    for (int n = 0; n + 1 < N; ++n) {
+      // C (rows = 2 r, K = 2^(N-n-1) columns) -> Gram C C^T -> leading eigenvectors P
+      const int r = caps[n], rows = 2 * r, k = caps[n + 1];
+      const int64_t K = total >> (n + 1);
+      TcDesc g = gemm_desc(rows, rows, (int)K, A.d(), K, false, A.d(), K, true, Gd.d(), rows);
+      g.ksplit = tc_choose_ksplit(g, Prec::F64);
+      DevBuf part;
+      if (tc_uses_part(g)) {
+        part.alloc((size_t)tc_part_size(g) * 8);
+        g.part = part.d();
+      }
+      tc_launch(g, Prec::F64, s);
+      rt::copy_async(dd.p, &rows, sizeof(int), s);
+      rt::copy_async(dk.p, &k, sizeof(int), s);
+      const bool pre = eig_uses_precondition(rows);
+      if (pre) eig_precondition_launch(1, dd.as<int>(), Gd.d(), (int64_t)rows * rows, rows, Wd.d(), rows, s);
+      eig_launch(1, dd.as<int>(), dk.as<int>(), Gd.d(), (int64_t)rows * rows, rows, Pd.d(),
+                 (int64_t)rows * k, k, Ld.d(), rows, Wd.d(), rows, machine_eps(Prec::F64), s, pre);
+      // core n = P (r x 2 x k, the caps of this chain exactly); next C = P^T C
+      rt::copy_async(x->core(n), Pd.d(), (size_t)rows * k * 8, s);
+      TcDesc c = gemm_desc(k, (int)K, rows, Pd.d(), k, true, A.d(), K, false, B.d(), K);
+      tc_launch(c, Prec::F64, s);
+      rt::copy_async(lam.data(), Ld.d(), (size_t)rows * 8, s);
+      rt::sync(s);  // the part buffer and the host copies of dims, keep and lam
+      for (int i = k; i < rows; ++i) disc += std::max(0.0, lam[i]);
+      std::swap(A, B);
+    }
+    rt::copy_async(x->core(N - 1), A.p, 2 * (size_t)caps[N - 1] * 8, s);
+    rt::sync(s);
+    if (discarded) *discarded = disc;
+    *out = x.release();
+  });
+}
+
+}  // extern "C"

@@ -19,11 +19,39 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (TT_SERIAL, from_separable, error_measures, moment_steps, setup_workload,
-               sq_diff_sum, to_dense)
+from . import (TT_SERIAL, axpby, from_dense, from_separable, error_measures, moment_steps,
+               setup_workload, smagorinsky, sq_diff_sum, to_dense)
+
+C_S = 0.11  # Smagorinsky constant of the flow case
 
 
-def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None, fields=False):
+def smagorinsky_fields(ctx, w, chi_field, c_omega=1.0):
+    """The paper's closure fields as x-MPSs: G = gamma + gamma_SGS from the
+    velocity of w (its velocity MPSs on the grid, Delta = 3 / M) by
+    fd_smagorinsky, cut to chi_field by tt_from_dense, and Omega_mix =
+    C_Omega G / Delta^2.  Returns ({"G": TT, "Omega": TT}, discarded weight
+    of G, the dense G of the cut MPS)."""
+    import torch
+    import workloads
+    bits, M = w.bits, w.M
+    n = M ** 3
+    dev = torch.device("cuda", ctx.device)
+    U = torch.empty(3 * n, dtype=torch.float64, device=dev)
+    for i, comp in enumerate(workloads.velocity_terms(w)):
+        v = from_separable(ctx, 3, bits, TT_SERIAL, comp, w.vel_rank)
+        to_dense(ctx, v, U[i * n:(i + 1) * n])
+        v.free()
+    delta = 3.0 / M
+    G = torch.empty(n, dtype=torch.float64, device=dev)
+    smagorinsky(ctx, bits, U, G, C_S, delta, w.gamma)
+    g, disc = from_dense(ctx, G, chi_field)
+    om = axpby(ctx, [c_omega / (delta * delta)], [g])
+    to_dense(ctx, g, G)
+    return {"G": g, "Omega": om}, disc, G
+
+
+def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None, fields=False,
+        chi_field=16, c_omega=1.0):
     """Advances workload w (5-D) for (n_samples - 1) * steps_per_sample steps,
     sampling at every steps_per_sample steps from t = 0.
 
@@ -32,8 +60,9 @@ def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None, field
     "sq_mean_x" (2, T) and "sq_norm_x" (T) (grid means of the squared
     differences).  exact: None (solve the moment equation when k_react == 0)
     or False (skip it).  fields=True runs the problem with the seeded x-fields
-    G(x) and Omega(x) (setup_workload), and the moment equation with the
-    same G(x)."""
+    G(x) and Omega(x) (setup_workload), fields="smagorinsky" with the paper's
+    closure (smagorinsky_fields, G cut to chi_field, Omega = c_omega G /
+    Delta^2); the moment equation then uses the same G(x)."""
     import torch
     import workloads
 
@@ -44,7 +73,13 @@ def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None, field
     bits, M = w.bits, w.M
     n = M ** 3
     dev = torch.device("cuda", ctx.device)
-    prob, f = setup_workload(ctx, w, dtype, fields=fields)
+    G_closure = None
+    fdisc = None
+    if fields == "smagorinsky":
+        fx, fdisc, G_closure = smagorinsky_fields(ctx, w, chi_field, c_omega)
+        prob, f = setup_workload(ctx, w, dtype, fields=fx)
+    else:
+        prob, f = setup_workload(ctx, w, dtype, fields=fields)
     phi = (np.arange(M) + 0.5) / M
     dense = torch.empty(n, dtype=torch.float64, device=dev)
     m = work = U = G = None
@@ -55,7 +90,9 @@ def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None, field
             to_dense(ctx, v, U[i * n:(i + 1) * n])
             v.free()
         G = torch.full((n,), w.gamma, dtype=torch.float64, device=dev)
-        if fields:
+        if G_closure is not None:
+            G = G_closure
+        elif fields:
             g = from_separable(ctx, 3, bits, TT_SERIAL, workloads.flow_field_terms(w)["G"], 16)
             to_dense(ctx, g, G)
             g.free()
@@ -91,4 +128,4 @@ def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None, field
     prob.close()
     return {"E2b_up": e[0], "E2b_down": e[1], "E2c_up": e[2], "E2c_down": e[3],
             "mean_bar": mean_bar, "sq_mean_x": sq_mean_x if exact else None,
-            "sq_norm_x": sq_norm_x}
+            "sq_norm_x": sq_norm_x, "field_discarded": fdisc}

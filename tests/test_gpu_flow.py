@@ -292,3 +292,38 @@ def test_moment_steps_full_size_sampled(ctx, bits, count):
     for a in range(count):
         want = moments.step_at(m0[a], U, Gor, dt, pts)
         _close(got[a][tuple(pts.T)], want, 1e-12)
+
+
+@pytest.mark.parametrize("bits,chi", [(3, 4), (4, 8), (5, 16)])
+def test_from_dense_matches_oracle(ctx, bits, chi):
+    """The truncated TT-SVD of a smooth non-separable 3-D field: same
+    reconstruction as the oracle's TT-SVD at the same cap, and the discarded
+    weight equals the squared approximation error."""
+    import torch
+    M = 1 << bits
+    X1, X2, X3 = np.meshgrid(*(np.arange(M) / M,) * 3, indexing="ij")
+    F = np.exp(np.sin(2 * np.pi * X1) * np.cos(2 * np.pi * X2) + 0.5 * np.sin(2 * np.pi * (X2 + X3)))
+    F += 0.2 * np.cos(2 * np.pi * (X1 + 2 * X3)) * np.sin(4 * np.pi * X2)
+    cores = tt.tt_svd(F.reshape((2,) * (3 * bits)), rel_tol=0.0, chi=chi)
+    want = tt.tt_full(cores).ravel()
+    x, disc = q.from_dense(ctx, _cuda(F.ravel()), chi)
+    out = torch.empty(M ** 3, dtype=torch.float64, device="cuda")
+    q.to_dense(ctx, x, out)
+    got = out.cpu().numpy()
+    err2 = float(np.sum((F.ravel() - want) ** 2))
+    assert err2 > 1e-12 * np.sum(F ** 2)  # the cap truncates
+    # Gram truncation resolves the kept subspace to about sqrt(eps) sigma_1
+    assert np.max(np.abs(got - want)) <= 1e-7 * np.max(np.abs(F))
+    assert abs(disc - err2) <= 1e-6 * err2 + 1e-9 * np.sum(F ** 2)
+
+
+def test_flow_protocol_smagorinsky_runs(ctx):
+    """The protocol with the paper's closure: the Smagorinsky field from the
+    velocity, cut to a bond cap, and Omega = C_Omega G / Delta^2."""
+    from paper_2407_09169_amd import flow
+    w = workloads.get_workload("t_5d_M16_chi32", k_react=0.0, integrator="rk2", ic="paper")
+    got = flow.run(ctx, w, n_samples=4, steps_per_sample=1, fields="smagorinsky", chi_field=8)
+    vals = [got["E2b_up"], got["E2b_down"], got["E2c_up"], got["E2c_down"]]
+    assert all(np.isfinite(vals)), vals
+    assert got["field_discarded"] >= 0.0
+    assert vals[1] < 1e-2 and vals[3] < 1e-2, vals
