@@ -170,3 +170,24 @@ print("ok")
 """ % ROOT
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
+
+
+def test_flow_error_measures_host_logic():
+    """flow_error_measures is host code of the library: it runs without a GPU
+    and gives the oracle's eq. RMSE0 measures."""
+    import numpy as np
+    from oracle import moments
+    import paper_2407_09169_amd as q
+    T = 17
+    rng = np.random.default_rng(5)
+    shape = (3, 3, 3)
+    mean_bar = 0.5 + 0.02 * rng.standard_normal((2, T))
+    ex = rng.random((2, T) + shape)
+    mx = ex + 0.01 * rng.standard_normal((2, T) + shape)
+    nx = 1.0 + 1e-3 * rng.standard_normal((T,) + shape)
+    want = moments.error_measures(mean_bar, mx, ex, nx)
+    got = q.error_measures(mean_bar, np.mean((mx - ex) ** 2, axis=(2, 3, 4)),
+                           np.mean((nx - 1.0) ** 2, axis=(1, 2, 3)))
+    assert np.allclose(got, want, rtol=1e-13, atol=0)
+    with pytest.raises(ValueError):
+        q.error_measures(mean_bar[:, :3], None, np.zeros(T))
