@@ -327,3 +327,30 @@ def test_flow_protocol_smagorinsky_runs(ctx):
     assert all(np.isfinite(vals)), vals
     assert got["field_discarded"] >= 0.0
     assert vals[1] < 1e-2 and vals[3] < 1e-2, vals
+
+
+@pytest.mark.parametrize("bits", [9, 10])
+def test_from_dense_full_size(ctx, bits):
+    """512^3 and 1024^3 (8 GiB): a sum of two separable smooth terms whose QTT
+    singular values fall to rounding level within the cap chi = 8: sampled
+    entries equal the field's values to the resolution of a Gram-based cut
+    (about sqrt(eps) sigma_1, the floor of reading R9: 3 sqrt(2^-52)), and
+    what is discarded is rounding noise."""
+    import torch
+    M = 1 << bits
+    dev = torch.device("cuda")
+    x = torch.arange(M, dtype=torch.float64, device=dev) / M
+    a = (torch.sin(2 * np.pi * x), torch.cos(4 * np.pi * x) + 2.0, torch.exp(torch.sin(2 * np.pi * x)))
+    b = (1.0 + 0.5 * x, torch.sin(6 * np.pi * x), torch.ones_like(x))
+    F = (a[0][:, None, None] * a[1][None, :, None] * a[2][None, None, :]
+         + b[0][:, None, None] * b[1][None, :, None] * b[2][None, None, :]).reshape(-1)
+    xt, disc = q.from_dense(ctx, F, 8)
+    out = torch.empty_like(F)
+    q.to_dense(ctx, xt, out)
+    idx = torch.as_tensor(np.random.default_rng(bits).integers(0, M ** 3, size=4096), device=dev)
+    err = (out[idx] - F[idx]).abs().max().item()
+    scale = F.abs().max().item()
+    assert err <= 3 * np.sqrt(2.0 ** -52) * scale, err / scale
+    assert disc <= 1e-12 * float((F * F).sum())
+    del F, out
+    torch.cuda.empty_cache()
