@@ -191,3 +191,36 @@ def test_flow_error_measures_host_logic():
     assert np.allclose(got, want, rtol=1e-13, atol=0)
     with pytest.raises(ValueError):
         q.error_measures(mean_bar[:, :3], None, np.zeros(T))
+
+
+def test_dry_run_flow_argument_checks():
+    """The dense-field entry points validate their arguments on the host
+    (grid size, field count, overlapping buffers) before any launch."""
+    code = r"""
+import os, sys, ctypes as C
+os.environ["QTTPDF_DRYRUN"] = "1"
+sys.path.insert(0, %r)
+import numpy as np
+import paper_2407_09169_amd as q
+L = q.lib()
+ctx = q.Context(0, stream=0)
+bits = 3
+n = 1 << (3 * bits)
+U, G, m, w = (np.zeros(k * n) for k in (3, 1, 2, 2))
+p = lambda a, off=0: C.c_void_p(a.ctypes.data + 8 * off)
+assert L.fd_moment_steps(ctx.h, bits, 2, p(U), p(G), p(m), p(w), 1e-3, 1) == 0
+assert L.fd_moment_steps(ctx.h, 2, 1, p(U), p(G), p(m), p(w), 1e-3, 1) == 1   # bits < 3
+assert L.fd_moment_steps(ctx.h, bits, 3, p(U), p(G), p(m), p(w), 1e-3, 1) == 1  # count
+assert L.fd_moment_steps(ctx.h, bits, 2, p(U), p(G), p(m), p(m, n), 1e-3, 1) == 1  # work overlaps m
+assert L.fd_moment_steps(ctx.h, bits, 1, p(U), p(G), p(m), p(w), 1e-3, -1) == 1
+assert L.fd_smagorinsky(ctx.h, bits, p(U), 0.11, 3.0 / 8, 1e-3, p(U, n)) == 1      # G overlaps U
+assert L.fd_smagorinsky(ctx.h, bits, p(U), 0.11, 0.0, 1e-3, p(G)) == 1             # delta
+assert L.fd_smagorinsky(ctx.h, 11, p(U), 0.11, 3.0 / 8, 1e-3, p(G)) == 1           # bits > 10
+h = C.c_void_p(); d = C.c_double()
+assert L.tt_from_dense(ctx.h, 1, p(m), 4, C.byref(h), C.byref(d)) == 1
+assert L.tt_from_dense(ctx.h, 9, p(m), 0, C.byref(h), C.byref(d)) == 1
+assert L.tt_from_dense(ctx.h, 9, p(m), 4, C.byref(h), C.byref(d)) == 0
+print("ok")
+""" % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
