@@ -112,3 +112,24 @@ def test_chi256_step_properties(ctx):
     err = _diff_norm(out["f32"], out["f64"]) / _norm(out["f64"])
     print(f"c3_5d_M1024_chi256: FP32 vs FP64 after one step {err:.3e}", flush=True)
     assert err < 3e-5, err
+
+
+def test_field_step_at_paper_grid_matches_oracle(ctx):
+    """One RK2 step on the paper's 128^5 grid (chi = 64) with the x-fields G(x)
+    and Omega(x), FP64, against the oracle's field stepper on the same seeded
+    inputs; same tolerance rule as the constant-coefficient step."""
+    w = workloads.get_workload("c2_5d_M128_chi64", integrator="rk2", k_react=0.0)
+    st0 = stepper.MPSStepper(w)
+    xo = st0._x_order()
+    fields = {k: st0._separable(t, xo, 3) for k, t in workloads.flow_field_terms(w).items()}
+    st = stepper.MPSStepper(w, fields)
+    fo, infos = st.step(st.initial_state())
+    tol = 1e-9 + 3 * np.sqrt(2.0 ** -52) + 10 * truncation_sensitivity(infos)
+    prob, f = q.setup_workload(ctx, w, "f64", fields=True)
+    prob.step(f, 1)
+    fg = f.cores()
+    err = _diff_norm(fg, fo) / _norm(fo)
+    print(f"field step 128^5 chi=64: rel diff {err:.3e} (tol {tol:.3e})")
+    assert err < tol, (err, tol)
+    f.free()
+    prob.close()
