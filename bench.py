@@ -332,6 +332,7 @@ def _bench_flow(args, log):
         "errors": {"E2b_up": r["E2b_up"], "E2b_down": r["E2b_down"], "E2c_up": r["E2c_up"],
                    "E2c_down": r["E2c_down"]},
         "field_discarded_weight": r["field_discarded"],
+        "max_stage_mpo_bond": r["max_mpo_bond"],
         "timing": "wall clock of the whole protocol, set-up and first-step recording included",
     }
     print(json.dumps(out))

@@ -124,8 +124,9 @@ def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None, field
                 x.free()
                 sq_mean_x[a, t] = sq_diff_sum(ctx, dense, m[a * n:(a + 1) * n]) / n
     e = error_measures(mean_bar, sq_mean_x if exact else None, sq_norm_x)
+    _, max_bond = prob.info()
     f.free()
     prob.close()
     return {"E2b_up": e[0], "E2b_down": e[1], "E2c_up": e[2], "E2c_down": e[3],
             "mean_bar": mean_bar, "sq_mean_x": sq_mean_x if exact else None,
-            "sq_norm_x": sq_norm_x, "field_discarded": fdisc}
+            "sq_norm_x": sq_norm_x, "field_discarded": fdisc, "max_mpo_bond": max_bond}
