@@ -7,10 +7,15 @@ A step is one full RK4 step (4 stage evaluations with their mean-field
 updates and roundings, plus the rounded stage combination) of the 5-D PDF on
 the 1024^5 grid (50 quantics cores) at chi = 128, with synthetic seeded
 inputs (workloads.c3_5d_M1024_chi128).  Inputs are resident in HBM before the
-timed region.  The MFMA path (BF16 by default) and the plain FP64 path run the
+timed region.  The MFMA path (FP32 by default) and the plain FP64 path run the
 same schedule from the same initial state; the line reports the MFMA path's
 steps/s as `value`, the FP64 path's steps/s and the L2 distance between the
 two states after the run.
+
+Other workloads print their own line: batch64 (64 uneven problems stepped
+together), --gradient (steps carrying parameter derivatives), fpmoms_M<M>
+(the moment equation on an M^3 grid) and flow_c2_5d_M128_chi64 (the flow
+case's accuracy protocol on the 128^5 grid).
 
 Prints ONE JSON line.
 """
