@@ -259,12 +259,15 @@ def test_flow_protocol_with_fields_runs(ctx):
     assert 0.0 < vals[1] < 1e-2 and vals[3] < 1e-2, vals
 
 
-@pytest.mark.parametrize("bits,count", [(8, 1), (8, 2)])
-def test_moment_steps_full_size_sampled(ctx, bits, count):
-    """M = 256, one and two fields, one step in the launch configuration the
-    bench times from M = 256 up (column kernel, 16 planes per workgroup): sampled points
-    against the oracle's point-by-point step, including the tile, chunk and
-    periodic edges."""
+@pytest.mark.parametrize("bits,count,closure", [(8, 1, "smagorinsky"), (8, 2, "smagorinsky"),
+                                                 (9, 2, "analytic")])
+def test_moment_steps_full_size_sampled(ctx, bits, count, closure):
+    """M = 256 and 512, one and two fields, one step in the launch
+    configuration the bench times (column kernel, 16 planes per workgroup):
+    sampled points against the oracle's point-by-point
+    step, including the tile, chunk and periodic edges.  At 256^3 the
+    diffusivity is the Smagorinsky field (checked against the oracle's); at
+    512^3 it is a given smooth field passed to both sides."""
     import torch
     M = 1 << bits
     n = M ** 3
@@ -273,18 +276,24 @@ def test_moment_steps_full_size_sampled(ctx, bits, count):
     U = _paper_velocity(M)
     delta = 3.0 / M
     Ud = _cuda(np.concatenate([u.ravel() for u in U]))
-    Gd = torch.empty(n, dtype=torch.float64, device=dev)
-    q.smagorinsky(ctx, bits, Ud, Gd, 2.0, delta, 1e-3)
-    G = Gd.cpu().numpy().reshape(M, M, M)  # checked against the oracle below
     pts = rng.integers(0, M, size=(400, 3))
     edges = np.array([[0, 0, 0], [M - 1, M - 1, M - 1], [15, 3, 63], [16, 4, 64], [M - 1, 0, 64],
-                      [31, M - 1, 0], [32, 127, 191]])
+                      [31, M - 1, 0], [32, 127, 191], [33, 128, 255]])
     pts = np.concatenate([pts, edges % M])
-    Gor = moments.gamma_total(U, 1e-3, 2.0, delta)
-    want_g = Gor[tuple(pts.T)]
-    assert np.max(np.abs(G[tuple(pts.T)] - want_g)) <= 1e-12 * np.max(np.abs(want_g))
+    if closure == "smagorinsky":
+        Gd = torch.empty(n, dtype=torch.float64, device=dev)
+        q.smagorinsky(ctx, bits, Ud, Gd, 2.0, delta, 1e-3)
+        Gor = moments.gamma_total(U, 1e-3, 2.0, delta)
+        want_g = Gor[tuple(pts.T)]
+        got_g = Gd.cpu().numpy().reshape(M, M, M)[tuple(pts.T)]
+        assert np.max(np.abs(got_g - want_g)) <= 1e-12 * np.max(np.abs(want_g))
+    else:
+        x = np.arange(M) / M
+        Gor = 1e-3 * (1.0 + 0.5 * np.sin(2 * np.pi * x)[:, None, None]
+                      * np.cos(2 * np.pi * x)[None, None, :] + 0 * x[None, :, None])
+        Gd = _cuda(Gor.ravel())
     m0 = rng.random((count, M, M, M))
-    dt = 0.2 / (M * M * float(G.max()) * 6 + M * 4)
+    dt = 0.2 / (M * M * float(Gor.max()) * 6 + M * 4)
     m = _cuda(m0.ravel())
     work = torch.empty_like(m)
     q.moment_steps(ctx, bits, Ud, Gd, m, work, dt, 1)
