@@ -25,7 +25,17 @@ the raw mean composition of g rounded to chi_mean, and Round is the
 randomized range finder followed by simultaneous SVD truncation
 (``oracle.tt.round_sketch_two_sided``: the chain is orthogonalised from both
 ends towards its middle site, then truncated simultaneously) with the
-Gaussian sketches given as input.
+Gaussian sketches given as input.  This is ``rounding="sketch"``, the
+schedule the GPU path runs.
+
+``rounding="svd"`` is the paper's plain schedule instead: every operator
+application A(g) g and every stage combination (the stage inputs
+f + c k included) is formed explicitly and rounded by the textbook QR sweep
+plus right-to-left truncated SVDs (``oracle.tt.round_ttsvd``); the mean
+composition likewise.  It needs no random input and anchors the randomized
+schedule: both approximate the same discrete solution, and the tests bound
+the randomized step's distance to the full-grid solver by a small multiple
+of this one's.
 
 The operator MPOs are TT-SVDs of the dense 1-D matrices of ``oracle.dense``,
 tensored over dimensions; nothing here is shared with the product path.
@@ -44,11 +54,16 @@ from . import tt
 
 
 class MPSStepper:
-    def __init__(self, w, fields=None):
+    def __init__(self, w, fields=None, rounding="sketch"):
         """fields: optional x-MPS cores of the flow case's variable
         coefficients, {"G": total diffusivity gamma + gamma_SGS (replaces the
         constant gamma), "Omega": LMSE frequency Omega_mix(x) (replaces the
-        constant omega)}."""
+        constant omega)}.  rounding: "sketch" (randomized two-sided range
+        finder, the GPU path's schedule) or "svd" (the paper's plain
+        schedule of explicit products rounded by QR + truncated SVDs)."""
+        if rounding not in ("sketch", "svd"):
+            raise ValueError(rounding)
+        self.rounding = rounding
         self.w = w
         self.fields = dict(fields or {})
         self.order = workloads.site_order(w)
@@ -197,6 +212,11 @@ class MPSStepper:
         if self.nd == 2:
             return m, None
         W = tt.mpo_diag(self.fields["Omega"]) if "Omega" in self.fields else None
+        if self.rounding == "svd":
+            if W is not None:
+                m = tt.mpo_apply(W, m)
+            m, disc = tt.round_ttsvd(m, self.w.chi_mean, self.w.rel_tol)
+            return m, {"discarded": disc}
         m, info = tt.round_sketch_two_sided([(1.0, W, m)], self.Zm, self.Zml,
                                             self.w.chi_mean, self.w.rel_tol)
         return m, info
@@ -221,10 +241,23 @@ class MPSStepper:
         parts = [(c, tt.mpo_apply(W, g)) for c, W in self.operator_terms(g)]
         return tt.mps_sum(parts)
 
+    def _round_explicit(self, x, chi):
+        out, disc = tt.round_ttsvd(x, chi, self.w.rel_tol)
+        return out, {"discarded": disc}
+
     def L(self, g):
+        if self.rounding == "svd":
+            return self._round_explicit(self.apply_exact(g), self.w.chi)
         terms = [(c, W, g) for c, W in self.operator_terms(g)]
         out, info = tt.round_sketch_two_sided(terms, self.Z, self.Zl, self.w.chi, self.w.rel_tol)
         return out, info
+
+    def _combine(self, comb):
+        """Round sum_j c_j x_j (comb = [(c_j, x_j)]) to chi."""
+        if self.rounding == "svd":
+            return self._round_explicit(tt.mps_sum(comb), self.w.chi)
+        return tt.round_sketch_two_sided([(c, None, x) for c, x in comb], self.Z, self.Zl,
+                                         self.w.chi, self.w.rel_tol)
 
     # -------------------------------------------------------------------- step
     def step(self, f):
@@ -237,20 +270,27 @@ class MPSStepper:
             infos.append(info)
             return out
 
+        def stage_input(c, k):
+            # exact block sum (sketch schedule) or rounded (plain schedule)
+            g = tt.mps_sum([(1.0, f), (c, k)])
+            if self.rounding == "svd":
+                g, info = self._round_explicit(g, w.chi)
+                infos.append(info)
+            return g
+
         if w.integrator == "rk4":
             k1 = L(f)
-            k2 = L(tt.mps_sum([(1.0, f), (0.5 * dt, k1)]))
-            k3 = L(tt.mps_sum([(1.0, f), (0.5 * dt, k2)]))
-            k4 = L(tt.mps_sum([(1.0, f), (dt, k3)]))
-            comb = [(1.0, None, f), (dt / 6, None, k1), (dt / 3, None, k2),
-                    (dt / 3, None, k3), (dt / 6, None, k4)]
+            k2 = L(stage_input(0.5 * dt, k1))
+            k3 = L(stage_input(0.5 * dt, k2))
+            k4 = L(stage_input(dt, k3))
+            comb = [(1.0, f), (dt / 6, k1), (dt / 3, k2), (dt / 3, k3), (dt / 6, k4)]
         elif w.integrator == "rk2":
             k1 = L(f)
-            k2 = L(tt.mps_sum([(1.0, f), (dt, k1)]))
-            comb = [(1.0, None, f), (0.5 * dt, None, k1), (0.5 * dt, None, k2)]
+            k2 = L(stage_input(dt, k1))
+            comb = [(1.0, f), (0.5 * dt, k1), (0.5 * dt, k2)]
         else:
             raise ValueError(w.integrator)
-        fn, info = tt.round_sketch_two_sided(comb, self.Z, self.Zl, w.chi, w.rel_tol)
+        fn, info = self._combine(comb)
         infos.append(info)
         return fn, infos
 

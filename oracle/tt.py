@@ -11,24 +11,30 @@ Conventions
   every bit of phi1 first, then phi2, x1, x2, x3.
 
 Rounding (bond truncation by singular value decompositions, "Matrix product
-state algorithm" section) comes in three forms, all FP64 and plain LAPACK:
+state algorithm" section), all FP64 and plain LAPACK:
 
 * ``round_ttsvd``: the textbook sweep -- QR left-orthogonalisation, then a
-  right-to-left sweep of truncated SVDs (Oseledets 2011).  Used for pins.
-* ``trunc_gram``: on a left-orthogonal TT every bond is truncated to the span
-  of the leading eigenvectors of its right Gram matrix, i.e. to its leading
-  left singular vectors.  All bonds are truncated from the same untruncated
-  tensor (simultaneously), so ||T - T~|| <= sum_n eps_n where eps_n is the
-  discarded singular weight at bond n.
-* ``rand_orth``: randomized range finding for a sum of MPO-applied MPSs
-  (Al Daas et al., "Randomized algorithms for rounding in the tensor-train
-  format", SISC 2023, randomize-then-orthogonalize): right partial sketches
-  with a Gaussian TT, then a left-to-right QR sweep on the sketched
-  unfoldings.  The Gaussian sketch is an input.
+  right-to-left sweep of truncated SVDs (Oseledets 2011).  This is the
+  rounding the paper describes.
+* ``trunc_svd``: on a left-orthogonal TT every bond is truncated to its
+  leading left singular vectors, taken by SVD of the bond's right factor.
+  All bonds are truncated from the same untruncated tensor
+  (simultaneously), so ||T - T~||^2 <= sum_n eps_n^2 where eps_n^2 is the
+  discarded singular weight at bond n.  ``trunc_svd_mixed`` does the same
+  for a mixed canonical TT (orthogonal from both ends towards a centre).
+  No Gram matrix is formed, so singular values down to about eps sigma_1
+  are resolved.
+* ``rand_orth`` / ``rand_orth_two_sided``: randomized range finding for a
+  sum of MPO-applied MPSs (Al Daas et al., "Randomized algorithms for
+  rounding in the tensor-train format", SISC 2023,
+  randomize-then-orthogonalize): partial sketches with Gaussian TTs, then QR
+  sweeps on the sketched unfoldings.  The Gaussian sketches are inputs.
 
-``round_det = trunc_gram o left_orthogonalize`` is the deterministic rounding
-of an explicit MPS; ``round_sketch = trunc_gram o rand_orth`` rounds
-sum_j c_j O_j x_j without forming the bond-(r D) product.
+``round_det = trunc_svd o left_orthogonalize o right_orthogonalize`` is the
+deterministic rounding of an explicit MPS; ``round_sketch = trunc_svd o
+rand_orth`` and ``round_sketch_two_sided = trunc_svd_mixed o
+rand_orth_two_sided`` round sum_j c_j W_j x_j without forming the bond-(r D)
+product.
 
 Pins: tests/test_oracle_tt.py (dense round trip, Kronecker brute force for
 MPOs, rounding error bounds, eq. MPSdofs).
@@ -283,62 +289,102 @@ def round_ttsvd(cores, chi, rel_tol=1e-14):
     return X, disc
 
 
-def right_grams(X):
-    """Gamma_n = Right_n Right_n^T for n = 1..N-1 (index n = bond left of site n)."""
-    N = len(X)
-    G = [None] * N
-    last = X[N - 1][:, :, 0]
-    G[N - 1] = last @ last.T
-    for n in range(N - 2, 0, -1):
-        A = X[n]
-        G[n] = _ein("asb,bc,dsc->ad", A, G[n + 1], A)
-    return G
+def _cut(s, cap, rel_tol):
+    """Number of singular values kept at a bond: at most cap, with rel_tol > 0
+    also only those above rel_tol * sigma_1 (at least one)."""
+    k = s.size
+    if rel_tol > 0 and s.size and s[0] > 0:
+        k = int(np.sum(s > rel_tol * s[0]))
+    return max(1, min(k, cap))
 
 
-def trunc_gram(X, chi, rel_tol=0.0):
-    """Simultaneous SVD truncation of every bond of a left-orthogonal TT.
-
-    At bond n the unfolding is Left_n Right_n with Left_n orthonormal, so its
-    left singular vectors are Left_n V_n with Gamma_n = V_n Lambda_n V_n^T.
-    Keep the k_n = min(cap_n, ell_n) leading vectors P_n (with rel_tol > 0,
-    also at most #{lambda_i > rel_tol^2 lambda_1}) and form the cores
-    P_{n-1}^T X_n P_n.  When cap_n >= ell_n nothing is dropped and P_n is a
-    full orthogonal matrix, so the rounding is exact whatever the accuracy of
-    the small eigenvalues.
-    Returns (cores, info) with info = {"ranks", "discarded", "norm2", "lams"}
-    (lams[n]: eigenvalues of Gamma_n in descending order).
-    """
-    N = len(X)
-    caps = chain_caps(N, chi)
-    if N == 1:
-        return [X[0].copy()], {"ranks": [1, 1], "discarded": [0.0, 0.0],
-                               "norm2": float(np.sum(X[0] ** 2)), "lams": [None, None]}
-    G = right_grams(X)
-    P = [None] * (N + 1)
-    ranks_out = [1] * (N + 1)
-    disc = [0.0] * (N + 1)
-    lams = [None] * (N + 1)
-    for n in range(1, N):
-        lam, V = np.linalg.eigh(G[n])
-        lam, V = lam[::-1], V[:, ::-1]
-        lams[n] = lam
-        k = lam.size
-        if rel_tol > 0 and lam[0] > 0:
-            k = int(np.sum(lam > rel_tol * rel_tol * lam[0]))
-        k = max(1, min(k, caps[n]))
-        P[n] = V[:, :k]
-        ranks_out[n] = k
-        disc[n] = float(np.sum(np.clip(lam[k:], 0.0, None)))
+def _project(cores, P):
+    """Cores P_n^T A_n P_(n+1) (P_0 = P_N = None: no projection)."""
+    N = len(cores)
     out = []
     for n in range(N):
-        A = X[n]
+        A = cores[n]
         if n > 0:
             A = np.tensordot(P[n].T, A, axes=(1, 0))
         if n < N - 1:
             A = np.tensordot(A, P[n + 1], axes=(2, 0))
         out.append(A)
-    norm2 = float(np.trace(G[1]))
-    return out, {"ranks": ranks_out, "discarded": disc, "norm2": norm2, "lams": lams}
+    return out
+
+
+def _right_factors(cores, last, first):
+    """Left singular vectors and singular values of the right factor at bonds
+    last, last-1, ..., first, for a chain whose cores right of `last` are
+    right-orthogonal: at bond `last` the factor is core `last` itself
+    (rows = its left bond); going left, the factor at bond n is core n
+    contracted with U_(n+1) S_(n+1), the factor of bond n+1 up to its
+    orthogonal right part.  SVDs of these factors, never of their Gram
+    matrices, so singular values far below sqrt(eps) sigma_1 are resolved."""
+    U, S = {}, {}
+    C = None
+    for n in range(last, first - 1, -1):
+        A = cores[n]
+        B = A if C is None else np.tensordot(A, C, axes=(2, 0))
+        u, s, _ = np.linalg.svd(B.reshape(B.shape[0], -1), full_matrices=False)
+        U[n], S[n] = u, s
+        C = u * s
+    return U, S
+
+
+def _left_factors(cores, first, last):
+    """Mirror image of _right_factors: right singular vectors and singular
+    values of the left factor at bonds first+1, ..., last+1 for a chain whose
+    cores left of `first` are left-orthogonal (bond n + 1 is right of core n)."""
+    V, S = {}, {}
+    C = None
+    for n in range(first, last + 1):
+        A = cores[n]
+        B = A if C is None else np.tensordot(C, A, axes=(1, 0))
+        _, s, vt = np.linalg.svd(B.reshape(-1, B.shape[2]), full_matrices=False)
+        V[n + 1], S[n + 1] = vt.T, s
+        C = s[:, None] * vt
+    return V, S
+
+
+def _trunc_from_factors(cores, chi, rel_tol, vecs, svals):
+    N = len(cores)
+    caps = chain_caps(N, chi)
+    P = [None] * (N + 1)
+    ranks_out = [1] * (N + 1)
+    disc = [0.0] * (N + 1)
+    sig = [None] * (N + 1)
+    for n in range(1, N):
+        s = svals[n]
+        k = _cut(s, caps[n], rel_tol)
+        P[n] = vecs[n][:, :k]
+        ranks_out[n] = k
+        disc[n] = float(np.sum(s[k:] ** 2))
+        sig[n] = s
+    s1 = svals[1]
+    return _project(cores, P), {"ranks": ranks_out, "discarded": disc,
+                                "norm2": float(np.sum(s1 ** 2)), "sigmas": sig}
+
+
+def trunc_svd(X, chi, rel_tol=0.0):
+    """Simultaneous SVD truncation of every bond of a left-orthogonal TT.
+
+    At bond n the unfolding is Left_n Right_n with Left_n orthonormal, so its
+    singular values and left singular vectors are those of the right factor
+    Right_n, taken by SVD (``_right_factors``).  Keep the k_n = min(cap_n, .)
+    leading left singular vectors P_n (with rel_tol > 0, also only those
+    above rel_tol * sigma_1) and form the cores P_(n-1)^T X_n P_n.  All bonds
+    are cut from the same untruncated tensor, so ||T - T~||^2 <= sum_n of the
+    discarded sigma^2, and when cap_n covers the bond nothing is dropped.
+    Returns (cores, info) with info = {"ranks", "discarded" (sum of dropped
+    sigma^2 per bond), "norm2", "sigmas" (singular values per bond,
+    descending)}.
+    """
+    N = len(X)
+    if N == 1:
+        return [X[0].copy()], {"ranks": [1, 1], "discarded": [0.0, 0.0],
+                               "norm2": float(np.sum(X[0] ** 2)), "sigmas": [None, None]}
+    U, S = _right_factors(X, N - 1, 1)
+    return _trunc_from_factors(X, chi, rel_tol, U, S)
 
 
 def right_orthogonalize(cores):
@@ -355,7 +401,7 @@ def round_det(cores, chi, rel_tol=0.0):
     bond down to at most min(2^n, 2^(N-n), input bond) with a left-orthogonal
     TT; the simultaneous SVD truncation then cuts each bond to chi.
     """
-    return trunc_gram(left_orthogonalize(right_orthogonalize(cores)), chi, rel_tol)
+    return trunc_svd(left_orthogonalize(right_orthogonalize(cores)), chi, rel_tol)
 
 
 def _as_term(t):
@@ -416,7 +462,7 @@ def rand_orth(terms, Z, ell):
 
 
 def round_sketch(terms, Z, ell, chi, rel_tol=0.0):
-    return trunc_gram(rand_orth(terms, Z, ell), chi, rel_tol)
+    return trunc_svd(rand_orth(terms, Z, ell), chi, rel_tol)
 
 
 def rand_orth_two_sided(terms, Zr, Zl, c=None):
@@ -493,60 +539,34 @@ def rand_orth_two_sided(terms, Zr, Zl, c=None):
     return X + [G] + V[c + 1:], c
 
 
-def trunc_gram_mixed(cores, c, chi, rel_tol=0.0):
+def trunc_svd_mixed(cores, c, chi, rel_tol=0.0):
     """Simultaneous SVD truncation of a mixed canonical TT (cores 0..c-1 left
-    orthogonal, c+1..N-1 right orthogonal).  At a bond n <= c the left part is
-    orthonormal, so the kept subspace is that of the right Gram matrix
-    Gamma_n = Right_n Right_n^T (Gamma_c from the centre core, then the chain
-    through X_(c-1)..X_n); at a bond n > c the right part is orthonormal and
-    the left Gram matrix Lambda_n = Left_n^T Left_n decides (Lambda_(c+1) from
-    the centre core, then the chain through V_(c+1)..).  With P_n the leading
-    min(cap_n, ell_n) eigenvectors, the cores become P_n^T A_n P_(n+1).
-    Returns (cores, info) as trunc_gram."""
+    orthogonal, c+1..N-1 right orthogonal).  At a bond n <= c the left part
+    is orthonormal, so the singular structure is that of the right factor:
+    the centre core, then going left through X_(c-1)..X_n (``_right_factors``
+    from the centre); at a bond n > c the right part is orthonormal and the
+    left factor decides: the centre core, then going right through
+    V_(c+1).. (``_left_factors``).  With P_n the leading singular vectors,
+    the cores become P_n^T A_n P_(n+1).  Returns (cores, info) as trunc_svd."""
     N = len(cores)
-    caps = chain_caps(N, chi)
     if N == 1:
         return [cores[0].copy()], {"ranks": [1, 1], "discarded": [0.0, 0.0],
-                                   "norm2": float(np.sum(cores[0] ** 2)), "lams": [None, None]}
-    G = [None] * (N + 1)
+                                   "norm2": float(np.sum(cores[0] ** 2)), "sigmas": [None, None]}
+    vecs, svals = {}, {}
     if c >= 1:
-        G[c] = _ein("ktz,Ktz->kK", cores[c], cores[c])
-        for n in range(c - 1, 0, -1):
-            G[n] = _ein("asb,bc,dsc->ad", cores[n], G[n + 1], cores[n])
+        U, S = _right_factors(cores, c, 1)
+        vecs.update(U)
+        svals.update(S)
     if c + 1 <= N - 1:
-        G[c + 1] = _ein("ktz,ktZ->zZ", cores[c], cores[c])
-        for n in range(c + 1, N - 1):
-            G[n + 1] = _ein("ysz,yY,YsZ->zZ", cores[n], G[n], cores[n])
-    P = [None] * (N + 1)
-    ranks_out = [1] * (N + 1)
-    disc = [0.0] * (N + 1)
-    lams = [None] * (N + 1)
-    for n in range(1, N):
-        lam, U = np.linalg.eigh(G[n])
-        lam, U = lam[::-1], U[:, ::-1]
-        lams[n] = lam
-        k = lam.size
-        if rel_tol > 0 and lam[0] > 0:
-            k = int(np.sum(lam > rel_tol * rel_tol * lam[0]))
-        k = max(1, min(k, caps[n]))
-        P[n] = U[:, :k]
-        ranks_out[n] = k
-        disc[n] = float(np.sum(np.clip(lam[k:], 0.0, None)))
-    out = []
-    for n in range(N):
-        A = cores[n]
-        if n > 0:
-            A = np.tensordot(P[n].T, A, axes=(1, 0))
-        if n < N - 1:
-            A = np.tensordot(A, P[n + 1], axes=(2, 0))
-        out.append(A)
-    norm2 = float(np.trace(G[1]))
-    return out, {"ranks": ranks_out, "discarded": disc, "norm2": norm2, "lams": lams}
+        V, S = _left_factors(cores, c, N - 2)
+        vecs.update(V)
+        svals.update(S)
+    return _trunc_from_factors(cores, chi, rel_tol, vecs, svals)
 
 
 def round_sketch_two_sided(terms, Zr, Zl, chi, rel_tol=0.0, c=None):
     cores, c = rand_orth_two_sided(terms, Zr, Zl, c)
-    return trunc_gram_mixed(cores, c, chi, rel_tol)
+    return trunc_svd_mixed(cores, c, chi, rel_tol)
 
 
 # ----------------------------------------------------------------------------

@@ -15,7 +15,8 @@ import pytest
 import workloads
 from oracle import dense as odense, moments, stepper, tt
 from oracle.dense import dense_from_terms
-from tests.helpers import random_tt, truncation_sensitivity
+from tests import cases
+from tests.helpers import TRUNC_TOL_F64, random_tt
 
 q = pytest.importorskip("paper_2407_09169_amd")
 
@@ -226,21 +227,18 @@ def test_field_step_untruncated_equals_dense(ctx, integrator):
     prob.close()
 
 
-@pytest.mark.parametrize("name,integrator", [("t_5d_M8_chi16", "rk2"), ("t_5d_M16_chi32", "rk4")])
-def test_field_step_truncated_matches_oracle(ctx, name, integrator):
+@pytest.mark.parametrize("name,integrator,steps", [(n, i, k) for n, i, k, fl in cases.STEP_CASES if fl])
+def test_field_step_truncated_matches_oracle(ctx, name, integrator, steps):
     """Truncated FP64 steps with the x-fields, to the same bound as the
-    constant-coefficient steps (10x the oracle's first-order truncation
-    sensitivity plus 1e-10)."""
+    constant-coefficient steps (TRUNC_TOL_F64)."""
     w = workloads.get_workload(name, integrator=integrator)
     st = _field_stepper(w)
     prob, f = q.setup_workload(ctx, w, "f64", fields=True)
     fo = st.initial_state()
-    sens = 0.0
-    for i in range(3):
+    tol = TRUNC_TOL_F64
+    for i in range(steps):
         prob.step(f, 1)
-        fo, infos = st.step(fo)
-        sens += truncation_sensitivity(infos)
-        tol = 1e-10 + 10 * sens
+        fo, _ = st.step(fo)
         err = np.linalg.norm(st.to_dense(f.cores()) - st.to_dense(fo)) / np.linalg.norm(st.to_dense(fo))
         assert err < tol, (name, i, err, tol)
     with pytest.raises(q.QttError):

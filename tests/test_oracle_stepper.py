@@ -101,3 +101,90 @@ def test_constant_fields_reduce_to_constants():
                             G=np.full((M, M, M), w.gamma), Omega=np.full((M, M, M), w.omega))
     f = st.to_dense(st.initial_state())
     assert _rel(Pf.rhs(f), P.rhs(f)) < 1e-14
+
+
+@pytest.mark.parametrize("name,integrator", [("c1_2d_M64_exact", "rk4"), ("t_5d_M8_exact", "rk2")])
+def test_untruncated_svd_schedule_equals_dense(name, integrator):
+    """The paper's plain schedule (explicit products, QR + truncated-SVD
+    rounding of every product and stage combination) is exact when chi covers
+    every bond."""
+    w = workloads.get_workload(name, integrator=integrator)
+    st = stepper.MPSStepper(w, rounding="svd")
+    f = st.initial_state()
+    P = st.dense_problem()
+    fd = st.to_dense(f)
+    for _ in range(3):
+        f, _ = st.step(f)
+        fd = P.step(fd, w.dt, integrator)
+        assert _rel(st.to_dense(f), fd) < 1e-12
+
+
+@pytest.mark.parametrize("name,steps", [("c1_2d_M64", 5), ("t_2d_M64_serial", 5),
+                                        ("t_5d_M8_chi16", 3), ("t_5d_M16_chi32", 1)])
+def test_randomized_schedule_against_plain_svd_schedule(name, steps):
+    """At truncated chi, the randomized two-sided schedule (the one the GPU
+    path runs) and the paper's plain QR + SVD schedule approximate the same
+    discrete solution about equally well: measured from the same (rounded)
+    initial state against the full-grid solver, the randomized step's error
+    is within 5 % of the plain one's, and the two schedules differ from each
+    other by less than 0.3 of that error (measured: 0.006 to 0.19; the
+    schedules differ in where they round, so they need not coincide).  A
+    rounding that dropped or mis-signed a term, or truncated the wrong
+    subspace, fails both."""
+    w = workloads.get_workload(name)
+    sk = stepper.MPSStepper(w)
+    sv = stepper.MPSStepper(w, rounding="svd")
+    f1 = sk.initial_state()
+    f2 = sv.initial_state()
+    P = sk.dense_problem()
+    fd = sk.to_dense(f1)
+    assert _rel(sv.to_dense(f2), fd) < 1e-13
+    for _ in range(steps):
+        f1, _ = sk.step(f1)
+        f2, _ = sv.step(f2)
+        fd = P.step(fd, w.dt, w.integrator)
+    d1, d2 = sk.to_dense(f1), sv.to_dense(f2)
+    e_rand, e_svd = _rel(d1, fd), _rel(d2, fd)
+    assert e_svd > 1e-13  # truncation is active
+    assert e_rand <= 1.05 * e_svd
+    assert _rel(d1, d2) <= 0.3 * e_svd
+    assert max(tt.ranks(f1)) <= w.chi and max(tt.ranks(f2)) <= w.chi
+
+
+def _mixture_moments(M, gA, gB):
+    """Discrete first moments h sum phi g of the four normalised composition
+    Gaussians (A and B, for phi1 and phi2)."""
+    phi = dense.phi_nodes(M)
+    h = 1.0 / M
+    return [h * np.dot(phi, g) for g in (gA[0], gB[0], gA[1], gB[1])]
+
+
+@pytest.mark.parametrize("window", ["constant", "x1"])
+def test_covariances_closed_form(window):
+    """eq. RACov and eq. SGSCov on a mixture f = w(x) G_A(phi) + (1 - w(x))
+    G_B(phi) of two product Gaussians: with a, b the means of Phi_1 under
+    G_A, G_B and c, d those of Phi_2, the local means are
+    <Phi_1>(x) = w a + (1 - w) b and <Phi_2>(x) = w c + (1 - w) d, so
+    R12 = var_x(w) (a - b)(c - d) and Y12 = avg_x(w (1 - w)) (a - b)(c - d).
+    A constant w gives R12 = 0 exactly.  Checked for the MPS and the dense
+    observables (the seeded 5-D initial state has this form, eq. initPDF)."""
+    w = workloads.get_workload("t_5d_M8_exact")
+    M = w.M
+    terms = workloads.ic_terms(w)
+    gA, gB = terms[0][1][:2], terms[1][1][:2]
+    win = terms[0][1][2] if window == "x1" else np.full(M, 0.3)
+    a, b, c, d = _mixture_moments(M, gA, gB)
+    st = stepper.MPSStepper(w)
+    f = st._separable([(1.0, [gA[0], gA[1], win, None, None]),
+                       (1.0, [gB[0], gB[1], 1.0 - win, None, None])], st.order, 5)
+    ob = st.observables(f)
+    obd = st.dense_problem().observables(st.to_dense(f))
+    R12 = (np.mean(win ** 2) - np.mean(win) ** 2) * (a - b) * (c - d)
+    Y12 = np.mean(win * (1.0 - win)) * (a - b) * (c - d)
+    assert abs(Y12) > 1e-5  # the centres differ: a non-trivial covariance
+    for o in (ob, obd):
+        assert abs(o["R12"] - R12) < 1e-14
+        assert abs(o["Y12"] - Y12) < 1e-14
+        assert abs(o["mass"] - 1.0) < 1e-14
+    if window == "constant":
+        assert abs(ob["R12"]) < 1e-15

@@ -198,3 +198,59 @@ def test_nvpp_paper_claims():
     stored = sum(2 * caps[n] * caps[n + 1] for n in range(N))
     gauge = sum(caps[n] ** 2 for n in range(1, N))
     assert tt.nvpp(N, chi) == stored - gauge
+
+
+def _graded_chain(sig, seed):
+    """8-site MPS whose middle bond (bond 4, the only one above 8) has the
+    singular values sig: T = U diag(sig) V^T with orthonormal U, V (16 x 16)."""
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((16, 16)))
+    V, _ = np.linalg.qr(rng.standard_normal((16, 16)))
+    T = (U * sig) @ V.T
+    return tt.tt_svd(T.reshape((2,) * 8), rel_tol=0.0), U, V
+
+
+def test_svd_truncation_resolves_below_sqrt_eps():
+    """Singular values far below sqrt(eps) sigma_1 (1e-10 .. 1e-22) are cut
+    exactly where they should be: the rounded chain equals U_k diag(s_k) V_k^T
+    of the one truncated bond to rounding error (a Gram-matrix eigensolver
+    cannot separate directions whose squared singular values are below
+    eps sigma_1^2, and would err by up to ~1e-8 here).  The deterministic,
+    the one-sided and the two-sided sketched roundings all agree with it."""
+    sig = 10.0 ** (-1.5 * np.arange(16))
+    x, U, V = _graded_chain(sig, 31)
+    k = 8
+    exact = ((U[:, :k] * sig[:k]) @ V[:, :k].T).reshape(-1)
+    N = 8
+    Zr, ell = _gaussian_sketch(N, 16, 32)
+    Zl, _ = _gaussian_sketch(N, 16, 33)
+    outs = {
+        "ttsvd": tt.round_ttsvd(x, k)[0],
+        "det": tt.round_det(x, k)[0],
+        "sketch": tt.round_sketch([(1.0, None, x)], Zr, ell, k)[0],
+        "two_sided": tt.round_sketch_two_sided([(1.0, None, x)], Zr, Zl, k)[0],
+    }
+    for name, r in outs.items():
+        err = np.abs(tt.tt_full(r).reshape(-1) - exact).max()
+        assert err < 1e-15, (name, err)
+    g, info = tt.round_det(x, k)
+    # singular values to absolute accuracy ~ eps sigma_1 (sigma_1 = 1)
+    assert abs(np.sqrt(info["discarded"][4]) - np.sqrt(np.sum(sig[k:] ** 2))) < 1e-14
+    assert np.allclose(info["sigmas"][4], sig, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("c", [2, 4, 6])
+def test_mixed_truncation_matches_ttsvd_at_one_bond(c):
+    """When only one bond is over its cap, simultaneous and sequential
+    truncation coincide: the two-sided rounding with any centre reproduces
+    the textbook rounding and the exact truncated SVD."""
+    sig = 0.6 ** np.arange(16)
+    x, U, V = _graded_chain(sig, 34)
+    N = 8
+    Zr, _ = _gaussian_sketch(N, 16, 35)
+    Zl, _ = _gaussian_sketch(N, 16, 36)
+    for k in (8,):  # chi = 8: every other bond of the 8-site chain is within its cap
+        ref = tt.tt_full(tt.round_ttsvd(x, k)[0])
+        out, info = tt.round_sketch_two_sided([(2.0, None, x)], Zr, Zl, k, c=c)
+        assert np.abs(tt.tt_full(out) - 2.0 * ref).max() < 1e-13
+        assert np.isclose(info["discarded"][4], 4.0 * np.sum(sig[k:] ** 2), rtol=1e-10)
