@@ -212,6 +212,22 @@ tt_status tt_l2_diff(tt_ctx* ctx, const tt_tt* a, const tt_tt* b, double* rel_er
 /* <a, b> (FP64 environment contraction). */
 tt_status tt_inner(tt_ctx* ctx, const tt_tt* a, const tt_tt* b, double* out);
 
+/* <a, b> exactly as tt_inner computes it (same kernels, same order), for
+ * callers that cannot allocate device memory: code recorded under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  It calls
+ * no hipMalloc / hipFree and no allocating library routine and does not
+ * synchronise: the environments and partial sums live in a static device
+ * buffer of 32 MiB per GPU (held from library load until the process ends),
+ * and the result is written to out_dev, one double of device memory owned
+ * by the caller, asynchronously on the context's stream.  Chains whose
+ * contraction needs more scratch than the buffer holds (bond products
+ * cap_a * cap_b beyond roughly 512 * 512) are rejected with
+ * TT_ERR_INVALID_ARG before anything is enqueued.  All calls on one GPU
+ * share its buffer, which keeps the last call's contents (nothing in it
+ * needs clearing: every value is written before it is read): calls that
+ * overlap in time on one GPU (two streams, two threads) race. */
+tt_status tt_inner_noalloc(tt_ctx* ctx, const tt_tt* a, const tt_tt* b, double* out_dev);
+
 /* ------------------------------------------------------------------------
  * The time step (a2, a6, a7, a8)
  * ------------------------------------------------------------------------ */

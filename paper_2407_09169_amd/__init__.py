@@ -33,7 +33,7 @@ EXPORTS = [
     "tt_alloc", "tt_free", "tt_info", "tt_set_cores", "tt_get_cores", "tt_from_separable",
     "mpo_build", "mps_apply_mpo", "mps_axpby", "mps_round", "mps_round_sketch",
     "mps_round_sketch_two_sided", "tt_l2_diff",
-    "tt_inner", "tt_problem_create", "tt_problem_destroy", "tt_problem_info", "tt_problem_state",
+    "tt_inner", "tt_inner_noalloc", "tt_problem_create", "tt_problem_destroy", "tt_problem_info", "tt_problem_state",
     "tt_step", "tt_profile", "tt_step_info", "tt_observable", "tt_mean_field",
     "tt_linalg_qr", "tt_linalg_eigh", "tt_batch_create", "tt_step_batched", "tt_batch_destroy",
     "tt_step_tangent", "tt_moment_field", "tt_to_dense", "fd_smagorinsky", "fd_moment_steps",
@@ -96,6 +96,7 @@ def lib():
         "mps_round_sketch_two_sided": [vp, i32, P(dbl), P(vp), P(vp), vp, vp, i32, i32, P(vp)],
         "tt_l2_diff": [vp, vp, vp, P(dbl)],
         "tt_inner": [vp, vp, vp, P(dbl)],
+        "tt_inner_noalloc": [vp, vp, vp, vp],
         "tt_problem_create": [vp, P(TTParams), P(vp), vp, vp, vp, vp, P(vp)],
         "tt_problem_destroy": [vp],
         "tt_problem_info": [vp, P(i32), P(C.c_int32), P(i32)],
@@ -328,6 +329,14 @@ def inner(ctx, a, b):
     r = C.c_double()
     _check(lib().tt_inner(ctx.h, a.h, b.h, C.byref(r)))
     return r.value
+
+
+def inner_noalloc(ctx, a, b, out):
+    """tt_inner_noalloc: <a, b> written to out (a float64 CUDA tensor owned by
+    the caller; its first element), asynchronously on the context's stream."""
+    if out.dtype.itemsize != 8 or out.numel() < 1 or not out.is_cuda:
+        raise ValueError("out must be a float64 CUDA tensor with at least one element")
+    _check(lib().tt_inner_noalloc(ctx.h, a.h, b.h, C.c_void_p(out.data_ptr())))
 
 
 def linalg_qr(ctx, A, with_r=True):

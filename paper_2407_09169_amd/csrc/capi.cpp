@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "library.h"
 #include "moments.h"
@@ -123,6 +124,57 @@ static host::TT build_mpo_host(int ndims, int bits, int ordering, const tt_term*
   if (rel_tol > 0) A = host::round_svd(A, rel_tol, 1 << 30);
   return A;
 }
+
+// ---------------------------------------------------------------------------
+// Static scratch of the entry points that allocate nothing (tt_inner_noalloc).
+// Every GPU the library runs on holds its own copy of `scratch` until the
+// process ends.  Host code never passes the array's name to a kernel: the
+// device address of each GPU's copy is looked up once per device, with that
+// device current, when the first context on it is created (tt_ctx_create),
+// and kept in g_scratch_dev.  Dry runs use a host buffer in its place.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchDoubles = size_t(4) << 20;  // 32 MiB
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) double scratch[kScratchDoubles];
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[kMaxDevices] = {};
+
+static void scratch_init(int device) {
+  QTT_REQUIRE(device >= 0 && device < kMaxDevices, "device %d beyond the scratch table", device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return;
+  void* p = nullptr;
+  if (rt::dry()) {
+    p = std::calloc(kScratchDoubles, sizeof(double));
+    if (!p) QTT_THROW(TT_ERR_OOM, "host stand-in of the static scratch");
+  } else {
+    QTT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  }
+  rt::register_range(p, kScratchDoubles * sizeof(double));
+  g_scratch_dev[device] = static_cast<double*>(p);
+}
+
+static double* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_scratch_dev[device] : nullptr;
+}
+
+// Enters a caller-owned device range into the bounds-check registry for the
+// lifetime of the scope, unless an allocation of the library already covers it.
+struct CallerRange {
+  const void* p = nullptr;
+  CallerRange(const void* ptr, size_t bytes, const char* what) {
+    try {
+      rt::check_range(ptr, 0, (int64_t)bytes - 1, 1, what);
+    } catch (const Error&) {
+      rt::register_range(ptr, bytes);
+      p = ptr;
+    }
+  }
+  ~CallerRange() {
+    if (p) rt::unregister_range(p);
+  }
+};
 
 }  // namespace qtt
 
@@ -507,6 +559,7 @@ tt_status tt_ctx_create(int device, void* hip_stream, tt_ctx** out) {
     auto c = std::make_unique<tt_ctx>();
     c->device = device;
     if (rt::dry()) {
+      scratch_init(device);
       *out = c.release();
       return;
     }
@@ -515,6 +568,7 @@ tt_status tt_ctx_create(int device, void* hip_stream, tt_ctx** out) {
     if (e != hipSuccess || n <= 0) QTT_THROW(TT_ERR_STATE, "no HIP device available");
     QTT_REQUIRE(device >= 0 && device < n, "device %d out of range (%d devices)", device, n);
     QTT_HIP(hipSetDevice(device));
+    scratch_init(device);
     QTT_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     QTT_HIP(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     QTT_HIP(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
@@ -828,6 +882,24 @@ tt_status tt_inner(tt_ctx* ctx, const tt_tt* a, const tt_tt* b, double* out) {
     plan.run(ctx->stream);
     rt::copy_async(out, r, sizeof(double), ctx->stream);
     rt::sync(ctx->stream);
+  });
+}
+
+tt_status tt_inner_noalloc(tt_ctx* ctx, const tt_tt* a, const tt_tt* b, double* out_dev) {
+  return guard([&] {
+    check_tt(a, ctx);
+    check_tt(b, ctx);
+    QTT_REQUIRE(out_dev, "out_dev is null");
+    QTT_REQUIRE(a->N == b->N && a->kind == TT_MPS && b->kind == TT_MPS, "inner of MPSs of equal length");
+    double* base = scratch_of(ctx->device);
+    QTT_REQUIRE(base, "no static scratch on device %d", ctx->device);
+    CallerRange out(out_dev, sizeof(double), "tt_inner_noalloc output");
+    Plan plan;
+    plan.arena = base;
+    plan.arena_cap = kScratchDoubles;
+    plan_inner(plan, view(a), view(b), out_dev);
+    StreamScope sc(ctx);
+    plan.run(ctx->stream);
   });
 }
 

@@ -76,6 +76,10 @@ void* dev_alloc(size_t bytes);
 void dev_free(void* p);
 // throws unless [p + lo*esize, p + (hi+1)*esize) lies inside one allocation
 void check_range(const void* p, int64_t lo, int64_t hi, size_t esize, const char* what);
+// enters memory the library did not allocate (a static device buffer) into
+// the registry that check_range consults; idempotent
+void register_range(const void* p, size_t bytes);
+void unregister_range(const void* p);
 void copy(void* dst, const void* src, size_t bytes);  // synchronous, any direction
 void copy_async(void* dst, const void* src, size_t bytes, hipStream_t s);
 void sync(hipStream_t s);

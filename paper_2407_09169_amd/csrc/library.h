@@ -86,12 +86,35 @@ struct Plan {
   Plan(const Plan&) = delete;
   Plan& operator=(const Plan&) = delete;
   ~Plan();
+  // With an arena (a device buffer owned by the caller), alloc() carves
+  // 256-byte aligned pieces from its bottom instead of allocating, and
+  // upload() and lanes are refused: recording such a plan allocates no device
+  // memory.  alloc_transient() serves buffers that live for one launch only
+  // (split-K partial sums): with an arena they all share its top, which is
+  // safe because the plan's launches run one after another on one stream.
+  double* arena = nullptr;
+  size_t arena_cap = 0, arena_used = 0, arena_top = 0;  // in doubles
   double* alloc(size_t n_doubles) {
+    if (arena) {
+      const size_t n = (std::max<size_t>(n_doubles, 1) + 31) & ~size_t(31);
+      arena_fits(arena_used + n, arena_top);
+      double* p = arena + arena_used;
+      arena_used += n;
+      return p;
+    }
     bufs.emplace_back(new DevBuf(std::max<size_t>(n_doubles, 1) * sizeof(double)));
     return bufs.back()->d();
   }
+  double* alloc_transient(size_t n_doubles) {
+    if (!arena) return alloc(n_doubles);
+    const size_t n = (std::max<size_t>(n_doubles, 1) + 31) & ~size_t(31);
+    arena_fits(arena_used, std::max(arena_top, n));
+    arena_top = std::max(arena_top, n);
+    return arena + (arena_cap - n);
+  }
   template <class T>
   T* upload(const std::vector<T>& host) {
+    QTT_REQUIRE(arena == nullptr, "a plan on a fixed scratch buffer cannot upload tables");
     bufs.emplace_back(new DevBuf(std::max<size_t>(host.size(), 1) * sizeof(T)));
     if (!host.empty()) rt::copy(bufs.back()->p, host.data(), host.size() * sizeof(T));
     return static_cast<T*>(bufs.back()->p);
@@ -102,6 +125,12 @@ struct Plan {
     lane.push_back(cur);
   }
   void fork(int n);
+  void arena_fits(size_t bottom, size_t top) const {
+    if (bottom + top > arena_cap)
+      QTT_THROW(TT_ERR_INVALID_ARG,
+                "the operation needs %zu bytes of scratch, more than the %zu bytes of the static scratch buffer",
+                (bottom + top) * sizeof(double), arena_cap * sizeof(double));
+  }
   void on(int l) { cur = l; }
   void join(int n);
   hipStream_t stream_of(int l, hipStream_t s0) const {

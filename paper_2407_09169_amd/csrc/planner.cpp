@@ -68,7 +68,7 @@ static Mode2 M2(int n2, int64_t s1, int64_t s2) { return mode2(n2, s1, s2); }
 
 void add_tc(Plan& plan, TcDesc d, Prec p) {
   d.ksplit = tc_choose_ksplit(d, p);
-  if (tc_uses_part(d)) d.part = plan.alloc((size_t)tc_part_size(d));
+  if (tc_uses_part(d)) d.part = plan.alloc_transient((size_t)tc_part_size(d));
   if (d.ng > 1) {
     std::vector<const double*> table;
     for (int g = 0; g < d.ng; ++g) table.push_back(d.gA[g]);
@@ -129,6 +129,7 @@ void Plan::ensure_lanes(int n) {
 void Plan::fork(int n) {
   if (n <= 1) return;  // single lane: nothing to order
   QTT_REQUIRE(cur == 0, "fork from lane 0 only");
+  QTT_REQUIRE(arena == nullptr, "a plan on a fixed scratch buffer runs on one lane");
   ensure_lanes(n);
   OpInfo rec, wait;
   rec.kind = wait.kind = OP_SYNC;
@@ -750,7 +751,13 @@ void plan_partial(Plan& plan, const ChainView& w, const ChainView& x, double* ou
   double* Ea = plan.alloc(esz);
   double* Eb = plan.alloc(esz);
   double* T = plan.alloc(tsz);
-  double* one = plan.upload(std::vector<double>{1.0});
+  double* one;
+  if (plan.arena) {  // no uploads into a fixed scratch buffer: write the 1 when the plan runs
+    one = plan.alloc(1);
+    plan.add([one](hipStream_t s) { fill(one, 1, 1.0, s); });
+  } else {
+    one = plan.upload(std::vector<double>{1.0});
+  }
   const double* E = one;
   for (int n = 0; n < Nw; ++n) {
     const int wl = w.caps[n], wr = w.caps[n + 1], xl = x.caps[n], xr = x.caps[n + 1];

@@ -48,6 +48,16 @@ void dev_free(void* p) {
   else (void)hipFree(p);
 }
 
+void register_range(const void* p, size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  registry()[(uintptr_t)p] = bytes;
+}
+
+void unregister_range(const void* p) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  registry().erase((uintptr_t)p);
+}
+
 void check_range(const void* p, int64_t lo, int64_t hi, size_t esize, const char* what) {
   if (hi < lo) return;  // empty range
   uintptr_t a = (uintptr_t)p + (uintptr_t)(lo * (int64_t)esize);

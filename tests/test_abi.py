@@ -224,3 +224,29 @@ print("ok")
 """ % ROOT
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
+
+
+def test_dry_run_inner_noalloc():
+    """tt_inner_noalloc plans its launches inside the static scratch buffer
+    (host stand-in in a dry run): accepted for chains whose environments fit,
+    refused with TT_ERR_INVALID_ARG for larger ones."""
+    code = r"""
+import os, sys, ctypes as C
+os.environ["QTTPDF_DRYRUN"] = "1"
+sys.path.insert(0, %r)
+import paper_2407_09169_amd as q
+from tests.helpers import random_tt
+ctx = q.Context(0, stream=0)
+out = (C.c_double * 1)()
+def run(N, cap):
+    caps = [min(2 ** n, 2 ** (N - n), cap) for n in range(N + 1)]
+    a = q.TT.from_cores(ctx, random_tt(caps, 1))
+    b = q.TT.from_cores(ctx, random_tt(caps, 2))
+    return q.lib().tt_inner_noalloc(ctx.h, a.h, b.h, C.cast(out, C.c_void_p))
+assert run(24, 160) == 0 and run(12, 24) == 0 and run(20, 512) == 0
+assert run(22, 1024) == 1
+assert b"static scratch" in q.lib().tt_last_error()
+print("ok")
+""" % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
