@@ -393,25 +393,107 @@ def _copy_probe(nbytes):
     print(json.dumps({"copy_probe_bytes": 8 * n, "dispatches": 5}))
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def _cpu_baseline(w):
-    """The CPU oracle (numpy / LAPACK, FP64) on a bounded sample: one RK4 step
-    of the same workload from the same initial state."""
-    import numpy as np  # noqa: F401
+    """The CPU oracle (numpy / LAPACK, FP64) on bounded samples: one RK4 step
+    of the same workload from the same initial state with every BLAS thread
+    (the reported value), and, for a number of the kind the paper quotes for
+    its single-core runs (the longest of the first steps of a run), the first
+    two steps of the 128^5 chi = 64 workload on one thread."""
     from oracle import stepper
+    import workloads
     st = stepper.MPSStepper(w)
     f = st.initial_state()
     t0 = time.perf_counter()
     st.step(f)
     el = time.perf_counter() - t0
     cores = os.cpu_count() or 1
+    single = None
     try:
         import threadpoolctl
         info = threadpoolctl.threadpool_info()
         cores = max([i.get("num_threads", 1) for i in info] + [1])
-    except Exception:  # noqa: BLE001
-        pass
+        w2 = workloads.get_workload("c2_5d_M128_chi64")
+        with threadpoolctl.threadpool_limits(1):
+            st2 = stepper.MPSStepper(w2)
+            g = st2.initial_state()
+            longest = 0.0
+            for _ in range(2):
+                t1 = time.perf_counter()
+                g, _ = st2.step(g)
+                longest = max(longest, time.perf_counter() - t1)
+        single = {"workload": w2.name, "threads": 1, "steps": 2, "longest_step_s": longest}
+    except Exception as e:  # noqa: BLE001
+        single = {"error": str(e)}
     return {"value": 1.0 / el, "unit": "steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 RK4 step of {w.name} from the seeded initial state ({el:.1f} s)"}
+            "cpu_model": _cpu_model(),
+            "sample": f"1 RK4 step of {w.name} from the seeded initial state ({el:.1f} s)",
+            "single_thread": single}
+
+
+def _accuracy_series(q, ctx, w, runs, n):
+    """Every run of `runs` ({name: (problem, state[, workload])}, "f64" among
+    them; a run's own workload, when given, may differ from w in chi or in the
+    sketch seeds) is restarted from the seeded initial state and advanced one
+    step at a time for n steps; after each step the relative L2 distance of
+    each state to the FP64 one (tt_l2_diff) and every run's mass deviation
+    <1> - 1 are recorded."""
+    import workloads
+    ordering = q.TT_SERIAL if w.ordering == "serial" else q.TT_INTERLEAVED
+    for r in runs.values():
+        wr = r[2] if len(r) > 2 else w
+        f0 = q.from_separable(ctx, w.ndims, w.bits, ordering, workloads.ic_terms(w), wr.chi)
+        r[1].set_cores(f0.cores())
+        f0.free()
+    series = {k: {"l2_vs_f64": [], "mass_dev": []} for k in runs}
+    f64 = runs["f64"][1]
+    for _ in range(n):
+        for r in runs.values():
+            r[0].step(r[1], 1)
+        for k, r in runs.items():
+            if k != "f64":
+                series[k]["l2_vs_f64"].append(q.l2_diff(ctx, r[1], f64))
+            series[k]["mass_dev"].append(r[0].observable(r[1], "mass") - 1.0)
+    del series["f64"]["l2_vs_f64"]
+    return series
+
+
+def _bench_drift(args, log):
+    """Precision drift over a long run: the 128^5 chi = 64 workload (200 RK4
+    steps) in FP32 and BF16 next to FP64 from the same initial state, the
+    relative L2 distance to the FP64 state and the mass deviation after every
+    step.  Two FP64 runs give the scale of what truncation alone leaves
+    undetermined: the same schedule at twice the bond cap (the truncation
+    error ||f_chi - f_2chi||), and at the same cap with other Gaussian sketches
+    (another, equally valid truncated trajectory)."""
+    import paper_2407_09169_amd as q
+    import workloads
+    w = workloads.get_workload("c2_5d_M128_chi64")
+    ctx = q.Context(0)
+    runs = {dt: q.setup_workload(ctx, w, dt) for dt in ("f64", "f32", "bf16")}
+    w2 = w.replace(chi=2 * w.chi)
+    runs["f64_2chi"] = (*q.setup_workload(ctx, w2, "f64"), w2)
+    runs["f64_other_sketch"] = (*q.setup_workload(ctx, w, "f64", sketch_seed=w.seed + 100), w)
+    n = args.steps
+    t0 = time.perf_counter()
+    series = _accuracy_series(q, ctx, w, runs, n)
+    log(f"drift over {n} steps in {time.perf_counter() - t0:.1f} s")
+    out = {"metric": "relative L2 distance to the FP64 run, per step", "workload": w.name,
+           "steps": n, "dt": w.dt, "chi": w.chi,
+           "final": {k: {"l2_vs_f64": v["l2_vs_f64"][-1] if "l2_vs_f64" in v else None,
+                         "max_l2_vs_f64": max(v["l2_vs_f64"]) if "l2_vs_f64" in v else None,
+                         "mass_dev": v["mass_dev"][-1]} for k, v in series.items()},
+           "series": series}
+    print(json.dumps(out))
 
 
 def main():
@@ -429,6 +511,9 @@ def main():
                     help="also write the per-launch event times of one eager step to this file")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--drift", action="store_true",
+                    help="precision drift: FP32 and BF16 against FP64 after every step of the 128^5 "
+                         "chi = 64 workload (--steps steps, 200 for the stated target)")
     ap.add_argument("--gradient", action="store_true",
                     help="time steps that also carry the derivatives with respect to Omega and k "
                          "(default workload for this mode: c5_5d_M256_chi64, all its steps)")
@@ -460,6 +545,9 @@ def main():
         return
     if args.gradient:
         _bench_gradient(args, log)
+        return
+    if args.drift:
+        _bench_drift(args, log)
         return
     if args.workload.startswith("fpmoms_M"):
         _bench_moments(args, log)
@@ -498,6 +586,13 @@ def main():
         log(f"bf16: {K} steps in {ms16:.1f} ms; L2 vs f64 {extra['bf16_l2_err_vs_f64']}")
     mass = prob.observable(f, "mass")
     disc, norm2 = prob.step_info()
+    accuracy = None
+    if plain:
+        runs = {"f64": (prob64, f64), args.dtype: (prob, f)}
+        if "bf16_steps_per_s" in extra:
+            runs["bf16"] = (prob16, f16)
+        accuracy = _accuracy_series(q, ctx, w, runs, W + K)
+        log(f"per-step accuracy: { {k: v.get('l2_vs_f64', [None])[-1] for k, v in accuracy.items()} }")
 
     oplog = _op_log(prob, f)
     if args.op_log:
@@ -534,6 +629,7 @@ def main():
         "mass_after": mass,
         "discarded_weight_last_rounding": float(sum(disc)),
         **extra,
+        "per_step_accuracy": accuracy,
         "roofline": roof,
         "kernel_classes": rows,
         "cpu_baseline": cpu,

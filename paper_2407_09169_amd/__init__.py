@@ -515,22 +515,24 @@ def statistic_and_gradient(ctx, w, n_steps, statistic="product", dtype="f64",
     return J, grads
 
 
-def setup_workload(ctx, w, dtype="f64", fields=False):
+def setup_workload(ctx, w, dtype="f64", fields=False, sketch_seed=None):
     """Builds (problem, f0) for a workloads.Workload with the seeded inputs;
     fields=True adds the seeded x-fields G(x) and Omega(x)
     (workloads.flow_field_terms, built exactly from their separable terms); a
-    dict {"G": TT, "Omega": TT} passes given x-MPSs."""
+    dict {"G": TT, "Omega": TT} passes given x-MPSs.  sketch_seed draws the
+    Gaussian sketches from another seed (same initial state and velocity)."""
     import workloads
+    ws = w if sketch_seed is None else w.replace(seed=sketch_seed)
 
     ordering = TT_SERIAL if w.ordering == "serial" else TT_INTERLEAVED
     velocity = None
     if w.ndims == 5:
         velocity = [from_separable(ctx, 3, w.bits, TT_SERIAL, comp, w.vel_rank)
                     for comp in workloads.velocity_terms(w)]
-    sketch = TT.from_cores(ctx, workloads.sketch_cores(w))
-    sketch_left = TT.from_cores(ctx, workloads.left_sketch_cores(w))
-    sketch_mean = TT.from_cores(ctx, workloads.mean_sketch_cores(w)) if w.ndims == 5 else None
-    sketch_mean_left = TT.from_cores(ctx, workloads.left_mean_sketch_cores(w)) if w.ndims == 5 else None
+    sketch = TT.from_cores(ctx, workloads.sketch_cores(ws))
+    sketch_left = TT.from_cores(ctx, workloads.left_sketch_cores(ws))
+    sketch_mean = TT.from_cores(ctx, workloads.mean_sketch_cores(ws)) if w.ndims == 5 else None
+    sketch_mean_left = TT.from_cores(ctx, workloads.left_mean_sketch_cores(ws)) if w.ndims == 5 else None
     p = TTParams(ndims=w.ndims, bits=w.bits, ordering=ordering, chi=w.chi, ell=w.ell,
                  chi_mean=w.chi_mean, ell_mean=w.ell_mean,
                  integrator=TT_RK4 if w.integrator == "rk4" else TT_RK2_HEUN,

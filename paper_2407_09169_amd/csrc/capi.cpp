@@ -483,11 +483,15 @@ static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vec
   }
   const double b4[4] = {dt / 6, dt / 3, dt / 3, dt / 6}, b2[2] = {0.5 * dt, 0.5 * dt};
   const double* b = rk4 ? b4 : b2;
+  // The final combination is dominated by f itself, whose every digit the
+  // next step inherits: its sketches run in the data precision (FP32 when
+  // BF16 is requested), while BF16 serves the sketches of the stage slopes,
+  // whose errors enter f+ weighted by dt.
   auto combine = [&](tt_tt* x, std::unique_ptr<tt_tt>* ks) {
     std::vector<SketchTerm> comb{sterm(1.0, nullptr, x)};
     for (int i = 0; i < S; ++i) comb.push_back(sterm(b[i], nullptr, ks[i].get()));
     RoundTarget tg = target(x);
-    plan_round_sketch_two_sided(*plan, comb, Z, Zl, tg, prec);
+    plan_round_sketch_two_sided(*plan, comb, Z, Zl, tg, data_prec(prec));
     return tg;
   };
   P->last = combine(f, P->k);

@@ -297,9 +297,11 @@ inline int64_t eig_work_size(int count, int ldg) { return 4 * (int64_t)count * l
 // last quarter is the workspace of the global-memory QR (max_n > 160).
 void eig_precondition_launch(int count, const int* dims, const double* G, int64_t strideG, int ldg,
                              double* work, int max_n, hipStream_t s);
-// machine epsilon of a contraction precision
+// relative precision of a contraction precision's products: the machine
+// epsilon of FP64 / FP32, and 2^-16 for BF16 (operands split into high and
+// low BF16 parts, the low-low product dropped)
 inline double machine_eps(Prec p) {
-  return p == Prec::F64 ? 2.220446049250313e-16 : (p == Prec::F32 ? 1.1920928955078125e-07 : 7.8125e-03);
+  return p == Prec::F64 ? 2.220446049250313e-16 : (p == Prec::F32 ? 1.1920928955078125e-07 : 1.52587890625e-05);
 }
 
 }  // namespace qtt

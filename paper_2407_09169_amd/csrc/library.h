@@ -162,6 +162,15 @@ inline int lane_budget(const Plan& plan, int want) {
   return std::max(1, want);
 }
 
+// Precision by role in a sketched rounding.  The sketch chains and the
+// sketched unfoldings only choose the bases that the QR sweeps
+// orthogonalise, so they run in the requested contraction precision; the
+// contractions that carry the data into the result (the projections of the
+// terms onto the bases, the centre core) run in FP32 when BF16 is requested,
+// so the operator's cores (whose column sums vanish, keeping the mass) and
+// the state keep FP32 accuracy.  FP32 and FP64 use one precision throughout.
+inline Prec data_prec(Prec p) { return p == Prec::BF16 ? Prec::F32 : p; }
+
 struct SketchTerm {
   double coef = 1.0;
   const ChainView* mpo = nullptr;  // nullptr: identity

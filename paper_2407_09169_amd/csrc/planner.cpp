@@ -490,6 +490,7 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
 
   plan.join(L);
 
+  const Prec dprec = data_prec(prec);
   // ---- left-to-right sweep; per bond the terms' contractions run on lanes
   // (the last bond accumulates all terms into one core, in order, on lane 0)
   std::vector<double*> Mcur(J, one), Mnext = Mb;
@@ -527,7 +528,7 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
           d.cm = M1((int64_t)2 * Dn * rp);
           d.cn = M1(1);
           d.cb = M1(2 * rp);
-          add_tc(plan, d, prec);
+          add_tc(plan, d, dprec);
         }
         {  // C[k,t,b,beta] = sum_(alpha,s) U1[k,alpha,s,b] W[alpha,t,s,beta]
           TcDesc d;
@@ -546,11 +547,11 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
           d.ab = d.bb = d.cb = M1(0);
           d.alpha = alpha;
           d.beta = beta;
-          add_tc(plan, d, prec);
+          add_tc(plan, d, dprec);
         }
       } else {
         add_gemm(plan, l, 2 * rp, rn, Mcur[j], rn, false, terms[j].x.core[n], 2 * rp, false, Cdst,
-                 2 * rp, alpha, beta, prec);
+                 2 * rp, alpha, beta, dprec);
       }
     }
     plan.join(Lb);
@@ -572,7 +573,7 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
       const int rp = sh[j].r[n + 1], Dp = sh[j].D[n + 1];
       if (L > 1) plan.on(j % L);
       add_gemm(plan, lp, rp * Dp, 2 * l, X[n], lp, true, Cb[j], (int64_t)rp * Dp, false, Mnext[j],
-               (int64_t)rp * Dp, 1.0, 0.0, prec);
+               (int64_t)rp * Dp, 1.0, 0.0, dprec);
     }
     plan.join(L);
     for (int j = 0; j < J; ++j) {
@@ -581,7 +582,7 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
       Mnext[j] = (old == one) ? Ma[j] : old;
     }
   }
-  plan_trunc_gram(plan, X, ell, tg, prec);
+  plan_trunc_gram(plan, X, ell, tg, dprec);
 }
 
 // ---------------------------------------------------------------------------

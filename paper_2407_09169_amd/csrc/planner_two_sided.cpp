@@ -516,6 +516,7 @@ void ts_sketch(Plan& plan, TwoSided& r, int q, const ChainView& Zr, const ChainV
 void ts_left_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double* one, Prec prec) {
   const int J = r.J;
   const auto& terms = *r.terms;
+  const Prec dprec = data_prec(prec);
   std::vector<double*> Mcur(J, one), Mnext = r.Mb;
   for (int n = 0; n < r.c; ++n) {
     const int l = ell[n], lp = ell[n + 1];
@@ -525,7 +526,7 @@ void ts_left_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double*
       for (size_t q = 0; q < per[0].size(); ++q) {
         std::vector<TcDesc> ds;
         for (auto& v : per) ds.push_back(v[q]);
-        add_grouped(plan, ds, false, prec);
+        add_grouped(plan, ds, false, dprec);
       }
     }
     for (size_t gi = 0; gi < r.groups.size(); ++gi) {  // S = sum_j C_j R_j (c_j is in R_j)
@@ -553,7 +554,7 @@ void ts_left_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double*
         ds.push_back(gemm_desc(lp, rp * Dp, 2 * l, r.X[n], lp, true, r.Cb[j], (int64_t)rp * Dp, false, Mnext[j],
                                (int64_t)rp * Dp, 1.0, 0.0));
       }
-      add_grouped(plan, ds, false, prec);
+      add_grouped(plan, ds, false, dprec);
     }
     for (int j = 0; j < J; ++j) {
       double* old = Mcur[j];
@@ -568,6 +569,7 @@ void ts_left_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double*
 void ts_right_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double* one, Prec prec) {
   const int J = r.J;
   const auto& terms = *r.terms;
+  const Prec dprec = data_prec(prec);
   std::vector<double*> Mrcur(J, one), Mrnext = r.Mrb;
   for (int n = r.N - 1; n > r.c; --n) {
     const int l = ell[n], lp = ell[n + 1];
@@ -577,7 +579,7 @@ void ts_right_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double
       for (size_t q = 0; q < per[0].size(); ++q) {
         std::vector<TcDesc> ds;
         for (auto& v : per) ds.push_back(v[q]);
-        add_grouped(plan, ds, false, prec);
+        add_grouped(plan, ds, false, dprec);
       }
     }
     for (size_t gi = 0; gi < r.groups.size(); ++gi) {
@@ -605,7 +607,7 @@ void ts_right_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double
         const int rD = r.sh[j].r[n] * r.sh[j].D[n];
         ds.push_back(gemm_desc(rD, l, 2 * lp, r.Crb[j], 2 * lp, false, r.Vt[n], l, false, Mrnext[j], l, 1.0, 0.0));
       }
-      add_grouped(plan, ds, false, prec);
+      add_grouped(plan, ds, false, dprec);
     }
     for (int j = 0; j < J; ++j) {
       double* old = Mrcur[j];
@@ -620,19 +622,20 @@ void ts_right_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double
 void ts_centre(Plan& plan, TwoSided& r, const std::vector<int>& ell, Prec prec) {
   const int c = r.c, l = ell[c], lp = ell[c + 1];
   const auto& terms = *r.terms;
+  const Prec dprec = data_prec(prec);
   for (const auto& g : r.groups) {
     std::vector<std::vector<TcDesc>> per;
     for (int j : g) per.push_back(lcore_descs(terms[j], r.sh[j], c, l, r.Mcur[j], r.U1L[j], r.Cb[j], 1.0, 0.0));
     for (size_t q = 0; q < per[0].size(); ++q) {
       std::vector<TcDesc> ds;
       for (auto& v : per) ds.push_back(v[q]);
-      add_grouped(plan, ds, false, prec);
+      add_grouped(plan, ds, false, dprec);
     }
   }
   for (int j = 0; j < r.J; ++j) {
     const int rD = r.sh[j].r[c + 1] * r.sh[j].D[c + 1];
     add_gemm(plan, 2 * l, lp, rD, r.Cb[j], rD, false, r.Mrcur[j], lp, false, r.Gc, lp, terms[j].coef,
-             j > 0 ? 1.0 : 0.0, prec);
+             j > 0 ? 1.0 : 0.0, dprec);
   }
 }
 
@@ -696,7 +699,7 @@ void ts_eig(Plan& plan, TwoSided& r, const std::vector<int>& ell, Prec prec) {
   if (N < 2) return;
   // eigenvectors resolved down to the noise the contractions left in the
   // Gram matrices (see the one-sided truncation)
-  const double u = machine_eps(prec);
+  const double u = machine_eps(data_prec(prec));
   const double unoise = std::max(machine_eps(Prec::F64), u * u);
   const double* g1 = r.G(1);
   double* p1 = r.Pn(1);

@@ -8,9 +8,10 @@
 // Three kernels:
 //   * FP64: LDS-tiled SIMT FMA (64x64 or 32x32 tiles, 256 threads);
 //   * FP32: v_mfma_f32_16x16x4f32, FP32 accumulation;
-//   * BF16: v_mfma_f32_16x16x32_bf16 (CDNA4), FP32 accumulation.
-// The MFMA kernels read the FP64 operands, round them to FP32 / BF16 while
-// staging the tiles in LDS, and write FP64 results.  All kernels load the
+//   * BF16: v_mfma_f32_16x16x32_bf16 (CDNA4), FP32 accumulation, each
+//     operand split into a BF16 high and low part (three MFMAs per product).
+// The MFMA kernels read the FP64 operands, round them to FP32 / split them
+// into BF16 pairs while staging the tiles in LDS, and write FP64 results.  All kernels load the
 // next K tile into registers while the current one is being multiplied.
 // Contractions with few output tiles and a long K are split along K
 // (TcDesc::ksplit); their partial sums are added by tc_splitk_reduce.
@@ -165,14 +166,21 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // (row-major operand) / B along n; each thread's tile elements keep their row
 // (column) offsets for the whole K loop, so a K step costs one or NA mode
 // offsets instead of two per element.
+//
+// BF16: every operand x is staged as two BF16 numbers, hi = bf16(x) and
+// lo = bf16(x - hi), and each product is accumulated as hi*hi + hi*lo +
+// lo*hi on v_mfma_f32_16x16x32_bf16 (the dropped lo*lo term and the rounding
+// of lo leave a relative error of about 2^-16 per product instead of the
+// 2^-8 of a single BF16 operand).
 template <bool BF16, bool AKF, bool BNF>
 __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
   constexpr int BM = 64, BN = 64, BK = 32;
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
   using TIn = typename std::conditional<BF16, __bf16, float>::type;
   constexpr int PAD = BF16 ? 8 : 4;
-  __shared__ TIn As[BM][BK + PAD];
-  __shared__ TIn Bs[BN][BK + PAD];
+  constexpr int NH = BF16 ? 2 : 1;  // hi (and lo) parts of each staged operand
+  __shared__ TIn As[NH][BM][BK + PAD];
+  __shared__ TIn Bs[NH][BN][BK + PAD];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -237,35 +245,56 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
   };
   if (kr.beg < kr.end) load(kr.beg);
   for (int k0 = kr.beg; k0 < kr.end; k0 += BK) {
+    if constexpr (BF16) {
 #pragma unroll
-    for (int q = 0; q < NA; ++q) As[a_row(q)][a_col(q)] = (TIn)(float)ra[q];
+      for (int q = 0; q < NA; ++q) {
+        const float x = (float)ra[q];
+        const __bf16 hi = (__bf16)x;
+        As[0][a_row(q)][a_col(q)] = hi;
+        As[1][a_row(q)][a_col(q)] = (__bf16)(x - (float)hi);
+      }
 #pragma unroll
-    for (int q = 0; q < NB; ++q) Bs[b_col(q)][b_row(q)] = (TIn)(float)rb[q];
+      for (int q = 0; q < NB; ++q) {
+        const float x = (float)rb[q];
+        const __bf16 hi = (__bf16)x;
+        Bs[0][b_col(q)][b_row(q)] = hi;
+        Bs[1][b_col(q)][b_row(q)] = (__bf16)(x - (float)hi);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) As[0][a_row(q)][a_col(q)] = (float)ra[q];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) Bs[0][b_col(q)][b_row(q)] = (float)rb[q];
+    }
     __syncthreads();
     if (k0 + BK < kr.end) load(k0 + BK);
     if constexpr (BF16) {
-      bf16x8 a[2], b[2];
+      bf16x8 a[2][2], b[2][2];  // [hi/lo][block]
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            a[h][i][t] = As[h][wm + 16 * i + li][8 * lq + t];
+            b[h][i][t] = Bs[h][wn + 16 * i + li][8 * lq + t];
+          }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int t = 0; t < 8; ++t) a[i][t] = As[wm + 16 * i + li][8 * lq + t];
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int t = 0; t < 8; ++t) b[j][t] = Bs[wn + 16 * j + li][8 * lq + t];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
+        }
     } else {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
         float a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = As[wm + 16 * i + li][kk + lq];
+        for (int i = 0; i < 2; ++i) a[i] = As[0][wm + 16 * i + li][kk + lq];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = Bs[wn + 16 * j + li][kk + lq];
+        for (int j = 0; j < 2; ++j) b[j] = Bs[0][wn + 16 * j + li][kk + lq];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll

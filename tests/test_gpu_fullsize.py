@@ -17,7 +17,10 @@ of the truncation moves these very steps by less than a third of it).
 FP32-MFMA contractions (the bench's path) round their inputs to 2^-24 and
 accumulate K <= 2304 products in FP32: about sqrt(K) 2^-24 = 3e-6 relative
 per rounding, five roundings per RK4 step adding in quadrature to ~7e-6;
-tolerance 3e-5.
+tolerance 3e-5. BF16 (split operands, 2^-16 per product) runs only the
+sketches of the stage slopes, which pick the bases; the projections and the
+stage combination stay FP32. It is held to the BF16 target stated for the
+method before any run, 1e-2 relative L2.
 """
 import numpy as np
 import pytest
@@ -52,7 +55,7 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", TRUNC_TOL_F64), ("f32", 3e-5)])
+@pytest.mark.parametrize("dtype,tol", [("f64", TRUNC_TOL_F64), ("f32", 3e-5), ("bf16", 1e-2)])
 def test_full_size_step_matches_oracle(ctx, oracle_step, dtype, tol):
     w, fo, obs_o = oracle_step
     prob, f = q.setup_workload(ctx, w, dtype)
