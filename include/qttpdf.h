@@ -19,7 +19,8 @@
  *    work enqueued earlier surface at the next call that synchronises
  *    (tt_ctx_synchronize, tt_get_cores, tt_observable, tt_l2_diff, ...).
  *  - Memory: all tensor data lives in device memory owned by the library
- *    (hipMalloc).  Host pointers passed in are only read during the call.
+ *    (hipMalloc, or the allocator given to tt_set_allocator).  Host pointers
+ *    passed in are only read during the call.
  *    The caller owns every handle it receives and frees it with the matching
  *    *_free / *_destroy call.  Handles of one context must not be used with
  *    another context.
@@ -83,6 +84,23 @@ typedef struct tt_ctx tt_ctx;
 typedef struct tt_tt tt_tt; /* an MPS or an MPO in device memory */
 typedef struct tt_problem tt_problem;
 typedef struct tt_batch tt_batch;
+
+/* ------------------------------------------------------------------------
+ * Device memory
+ * ------------------------------------------------------------------------ */
+/* The caller's device allocator: alloc returns `bytes` of device memory on
+ * HIP device `device` (NULL on failure), free takes back a pointer alloc
+ * returned, with the same size and device.  `stream` is always NULL (the
+ * library uses memory on its own streams and frees it only after
+ * hipDeviceSynchronize, so an allocator may recycle a freed block at once). */
+typedef void* (*tt_alloc_fn)(size_t bytes, int device, void* stream, void* user);
+typedef void (*tt_free_fn)(void* ptr, size_t bytes, int device, void* stream, void* user);
+/* Routes every later device allocation of the library (tensor trains,
+ * problems, workspaces) through alloc / free, e.g. PyTorch's caching
+ * allocator (paper_2407_09169_amd.use_torch_allocator); alloc = free = NULL
+ * restores hipMalloc / hipFree.  Process-wide; memory is always returned to
+ * the allocator that produced it, also after a later change. */
+tt_status tt_set_allocator(tt_alloc_fn alloc, tt_free_fn free, void* user);
 
 /* ------------------------------------------------------------------------
  * Context
@@ -164,22 +182,42 @@ tt_status mpo_build(tt_ctx* ctx, int ndims, int bits, int ordering, const tt_ter
  * MPS arithmetic (a3, a4, a5)
  * ------------------------------------------------------------------------ */
 /* Exact MPO x MPS product (matrix-vector multiplication in MPS form,
- * "Computational complexity"): out core n = sum_s W[a,t,s,b] x[c,s,d] with
- * bond capacities c_n * D_n (new handle). */
-tt_status mps_apply_mpo(tt_ctx* ctx, const tt_tt* mpo, const tt_tt* x, tt_tt** out);
+ * section "Matrix product state algorithm"; its cost in "Computational
+ * complexity"): out core n = sum_s W[a,t,s,b] x[c,s,d] with bond capacities
+ * c_n * D_n (new handle).  dtype (a tt_dtype) is the precision of the
+ * products: TT_F64 exact, TT_F32 FP32-rounded operands, TT_BF16 operands
+ * split into BF16 high and low parts; the two terms of every output entry
+ * are summed in FP64 and stored FP64. */
+tt_status mps_apply_mpo(tt_ctx* ctx, const tt_tt* mpo, const tt_tt* x, int dtype, tt_tt** out);
 
 /* Exact linear combination sum_j coeffs[j] * xs[j] by block-diagonal core
  * concatenation (MPS addition); bond capacities add up (new handle). */
 tt_status mps_axpby(tt_ctx* ctx, int n_terms, const double* coeffs, const tt_tt* const* xs,
                     tt_tt** out);
 
-/* Deterministic rounding (bond truncation by SVD): an LQ sweep and a QR
+/* Outcome of a rounding (FP64).  max_bond: the most singular values kept at
+ * one bond; discarded_weight: the dropped squared singular values summed over
+ * the bonds (||x - out||^2 is at most this sum, the bonds being cut
+ * simultaneously); norm2: ||out||^2; per_bond: NULL, or n_sites + 1 doubles
+ * owned by the caller that receive the discarded weight of every bond (0 at
+ * the two ends). */
+typedef struct {
+  int32_t max_bond;
+  double discarded_weight;
+  double norm2;
+  double* per_bond;
+} tt_round_info;
+
+/* Deterministic rounding (bond truncation by SVD, sections "Matrix product
+ * state algorithm" and "Matrix product state encoding"): an LQ sweep and a QR
  * sweep (Householder, FP64) bring x to left-orthogonal form, then every bond
- * n is cut to min(chi, 2^n, 2^(N-n)) leading left singular vectors, obtained
- * from the eigen-decomposition of its right Gram matrix (FP64).  The result
- * satisfies ||x - out|| <= sum_n eps_n with eps_n the discarded singular
- * weight of bond n.  New handle. */
-tt_status mps_round(tt_ctx* ctx, const tt_tt* x, int chi, tt_tt** out);
+ * n is cut to at most min(chi, 2^n, 2^(N-n)) leading left singular vectors,
+ * obtained from the eigen-decomposition of its right Gram matrix (FP64);
+ * with rel_tol > 0 singular values at most rel_tol * sigma_1 of their bond
+ * are dropped as well (their vectors are zeroed; the bond capacity stays).
+ * info (nullable) receives the outcome and makes the call wait for it.  New
+ * handle with bond caps min(chi, 2^n, 2^(N-n)). */
+tt_status mps_round(tt_ctx* ctx, const tt_tt* x, int chi, double rel_tol, tt_round_info* info, tt_tt** out);
 
 /* Rounding of Y = sum_j coeffs[j] * W_j x_j (W_j an MPO or NULL = identity)
  * without forming Y: randomized range finding with the Gaussian sketch TT
@@ -350,8 +388,31 @@ tt_status tt_profile(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps, int k
 
 /* Per-bond discarded singular weight (sum of dropped sigma^2, n_sites + 1
  * entries) of the last rounding of the last step, and the squared norm of
- * its result.  Synchronises. */
+ * its result.  Synchronises.  Returns TT_ERR_NONFINITE (and clears the
+ * condition) if a NaN or Inf appeared in the result of any rounding of a
+ * step since the last such report: every step checks the output of each of
+ * its roundings on the device. */
 tt_status tt_step_info(tt_problem* prob, double* discarded, double* norm2);
+
+/* One record per step of tt_step_ex:
+ *   mass_dev          avg <1> - 1 after the step (the local norm <1>(x)
+ *                     should stay one, section "Validation of algorithm")
+ *   discarded_weight  sum over the bonds of the squared singular values the
+ *                     step's final rounding dropped
+ *   max_bond          the most singular values kept at one bond of f
+ *   nonfinite         1 if a NaN or Inf appeared in a rounding of the step */
+typedef struct {
+  double mass_dev;
+  double discarded_weight;
+  int32_t max_bond;
+  int32_t nonfinite;
+} tt_step_record;
+
+/* tt_step, one step at a time, with a record per step in records (n_steps
+ * host entries, nullable); synchronises after every step.  Returns
+ * TT_ERR_NONFINITE after the first step that produced a NaN or Inf (its
+ * record filled, f left as that step made it). */
+tt_status tt_step_ex(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps, tt_step_record* records);
 
 /* Scalar statistic of f (see tt_obs), FP64.  Synchronises. */
 tt_status tt_observable(tt_ctx* ctx, tt_problem* prob, const tt_tt* f, int which, double* out);

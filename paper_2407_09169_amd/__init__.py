@@ -29,12 +29,12 @@ LINEAR_OBS = ("mass", "mean1", "mean2", "mean12", "product")
 
 # every entry point of include/qttpdf.h
 EXPORTS = [
-    "tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_stream", "tt_ctx_synchronize", "tt_last_error",
+    "tt_set_allocator", "tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_stream", "tt_ctx_synchronize", "tt_last_error",
     "tt_alloc", "tt_free", "tt_info", "tt_set_cores", "tt_get_cores", "tt_from_separable",
     "mpo_build", "mps_apply_mpo", "mps_axpby", "mps_round", "mps_round_sketch",
     "mps_round_sketch_two_sided", "tt_l2_diff",
     "tt_inner", "tt_inner_noalloc", "tt_problem_create", "tt_problem_destroy", "tt_problem_info", "tt_problem_state",
-    "tt_step", "tt_profile", "tt_step_info", "tt_observable", "tt_mean_field",
+    "tt_step", "tt_step_ex", "tt_profile", "tt_step_info", "tt_observable", "tt_mean_field",
     "tt_linalg_qr", "tt_linalg_eigh", "tt_batch_create", "tt_step_batched", "tt_batch_destroy",
     "tt_step_tangent", "tt_moment_field", "tt_to_dense", "fd_smagorinsky", "fd_moment_steps",
     "fd_sq_diff_sum", "flow_error_measures", "tt_problem_create_flow", "tt_from_dense",
@@ -54,6 +54,16 @@ class TTParams(C.Structure):
 
 class TTTerm(C.Structure):
     _fields_ = [("coeff", C.c_double), ("op", C.c_int32 * 8), ("field", C.c_int32)]
+
+
+class TTRoundInfo(C.Structure):
+    _fields_ = [("max_bond", C.c_int32), ("discarded_weight", C.c_double), ("norm2", C.c_double),
+                ("per_bond", C.POINTER(C.c_double))]
+
+
+class TTStepRecord(C.Structure):
+    _fields_ = [("mass_dev", C.c_double), ("discarded_weight", C.c_double), ("max_bond", C.c_int32),
+                ("nonfinite", C.c_int32)]
 
 
 class QttError(RuntimeError):
@@ -78,6 +88,7 @@ def lib():
     vp, i32, dbl = C.c_void_p, C.c_int, C.c_double
     P = C.POINTER
     sig = {
+        "tt_set_allocator": [vp, vp, vp],
         "tt_ctx_create": [i32, vp, P(vp)],
         "tt_ctx_destroy": [vp],
         "tt_ctx_set_stream": [vp, vp],
@@ -89,9 +100,9 @@ def lib():
         "tt_get_cores": [vp, P(dbl)],
         "tt_from_separable": [vp, i32, i32, i32, i32, P(dbl), P(P(dbl)), i32, P(vp)],
         "mpo_build": [vp, i32, i32, i32, P(TTTerm), i32, P(vp), i32, i32, dbl, P(vp), P(i32)],
-        "mps_apply_mpo": [vp, vp, vp, P(vp)],
+        "mps_apply_mpo": [vp, vp, vp, i32, P(vp)],
         "mps_axpby": [vp, i32, P(dbl), P(vp), P(vp)],
-        "mps_round": [vp, vp, i32, P(vp)],
+        "mps_round": [vp, vp, i32, dbl, P(TTRoundInfo), P(vp)],
         "mps_round_sketch": [vp, i32, P(dbl), P(vp), P(vp), vp, i32, i32, P(vp)],
         "mps_round_sketch_two_sided": [vp, i32, P(dbl), P(vp), P(vp), vp, vp, i32, i32, P(vp)],
         "tt_l2_diff": [vp, vp, vp, P(dbl)],
@@ -102,6 +113,7 @@ def lib():
         "tt_problem_info": [vp, P(i32), P(C.c_int32), P(i32)],
         "tt_problem_state": [vp, P(vp)],
         "tt_step": [vp, vp, vp, i32],
+        "tt_step_ex": [vp, vp, vp, i32, P(TTStepRecord)],
         "tt_step_info": [vp, P(dbl), P(dbl)],
         "tt_profile": [vp, vp, vp, i32, i32, P(dbl), P(C.c_int64), P(dbl), P(dbl)],
         "tt_observable": [vp, vp, vp, i32, P(dbl)],
@@ -145,6 +157,37 @@ def _torch_stream():
     except Exception:  # noqa: BLE001 - torch is optional plumbing
         pass
     return C.c_void_p(None)
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p, C.c_void_p)
+_ALLOCATOR = None  # the registered callbacks (kept alive while registered)
+
+
+def use_torch_allocator(enable: bool = True):
+    """Routes the library's device allocations through PyTorch's caching
+    allocator (tt_set_allocator), so that torch owns and accounts for the
+    memory; enable=False restores hipMalloc.  Memory already allocated keeps
+    its allocator."""
+    global _ALLOCATOR
+    if not enable:
+        _check(lib().tt_set_allocator(None, None, None))
+        _ALLOCATOR = None
+        return
+    import torch
+
+    def _alloc(nbytes, device, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=int(device))
+        except Exception:  # noqa: BLE001 - reported by the library as TT_ERR_OOM
+            return None
+
+    def _free(ptr, nbytes, device, stream, user):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    cbs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _check(lib().tt_set_allocator(C.cast(cbs[0], C.c_void_p), C.cast(cbs[1], C.c_void_p), None))
+    _ALLOCATOR = cbs
 
 
 class Context:
@@ -286,9 +329,9 @@ def mpo_build(ctx, ndims, bits, ordering, terms, fields=(), field_ndims=0, rel_t
     return TT(ctx, h), mb.value
 
 
-def apply_mpo(ctx, W, x):
+def apply_mpo(ctx, W, x, dtype="f64"):
     h = C.c_void_p()
-    _check(lib().mps_apply_mpo(ctx.h, W.h, x.h, C.byref(h)))
+    _check(lib().mps_apply_mpo(ctx.h, W.h, x.h, DTYPES[dtype], C.byref(h)))
     return TT(ctx, h)
 
 
@@ -299,10 +342,19 @@ def axpby(ctx, coeffs, xs):
     return TT(ctx, h)
 
 
-def round_det(ctx, x, chi):
+def round_det(ctx, x, chi, rel_tol=0.0, with_info=False):
+    """mps_round; with_info also returns {"max_bond", "discarded_weight",
+    "norm2", "per_bond"}."""
     h = C.c_void_p()
-    _check(lib().mps_round(ctx.h, x.h, chi, C.byref(h)))
-    return TT(ctx, h)
+    if not with_info:
+        _check(lib().mps_round(ctx.h, x.h, chi, rel_tol, None, C.byref(h)))
+        return TT(ctx, h)
+    n = x.info()[1]
+    per = (C.c_double * (n + 1))()
+    info = TTRoundInfo(0, 0.0, 0.0, per)
+    _check(lib().mps_round(ctx.h, x.h, chi, rel_tol, C.byref(info), C.byref(h)))
+    return TT(ctx, h), {"max_bond": info.max_bond, "discarded_weight": info.discarded_weight,
+                        "norm2": info.norm2, "per_bond": list(per)}
 
 
 def round_sketch(ctx, coeffs, mpos, xs, sketch, chi, dtype="f64", sketch_left=None):
@@ -400,6 +452,21 @@ class Problem:
 
     def step(self, f, n_steps=1):
         _check(lib().tt_step(self.ctx.h, self.h, f.h, n_steps))
+
+    def step_ex(self, f, n_steps=1):
+        """tt_step_ex: steps with one record per step, [{"mass_dev",
+        "discarded_weight", "max_bond", "nonfinite"}]; raises QttError on a
+        NaN or Inf (the records up to that step in its .records)."""
+        recs = (TTStepRecord * max(1, n_steps))()
+        st = lib().tt_step_ex(self.ctx.h, self.h, f.h, n_steps, recs)
+        out = [{"mass_dev": r.mass_dev, "discarded_weight": r.discarded_weight, "max_bond": r.max_bond,
+                "nonfinite": r.nonfinite} for r in recs[:n_steps]]
+        if st != 0:
+            err = QttError(f"qttpdf status {st}: {lib().tt_last_error().decode(errors='replace')}")
+            err.status = st
+            err.records = out
+            raise err
+        return out
 
     def profile(self, f, n_steps, kernel):
         """(ms, launches, flops, bytes) of one kernel class over n_steps eager steps."""

@@ -214,6 +214,7 @@ struct tt_problem {
   RoundTarget last;              // final rounding of the recording that ran last
   RoundTarget last_plain, last_tan;  // ... of the plain and of the tangent recording
   std::unique_ptr<Plan> obs_plan;
+  DevBuf nonfinite;  // device int: set when a rounding of a step produced a NaN or Inf
   // host copy of the mean-field chain over the phi sites (unscaled) and the
   // mean-field bonds, for assembling further stage-shaped operators
   host::TT MFh;
@@ -405,6 +406,13 @@ static void plan_stage_operator(Plan& plan, tt_problem* P, const tt_tt* f, const
   plan_mf_blocks(plan, P, P->A.get(), P->Dfix, mt);
 }
 
+// flags a NaN or Inf in the cores of x (after a rounding wrote them)
+static void plan_check_finite(Plan& plan, const tt_tt* x, int* flag) {
+  const double* p = x->buf.d();
+  const int64_t n = x->total();
+  plan.add([=](hipStream_t s) { check_finite(p, n, flag, s); });
+}
+
 // forward-mode derivative carried along a step: parameter q and its tangent df
 struct Tangent {
   int q;
@@ -456,6 +464,7 @@ static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vec
       if (kp) terms.push_back(sterm(cg, &Av, kp));
       RoundTarget tg = target(P->k[i].get());
       plan_round_sketch_two_sided(*plan, terms, Z, Zl, tg, prec);
+      plan_check_finite(*plan, P->k[i].get(), P->nonfinite.as<int>());
     }
     for (size_t j = 0; j < tan.size(); ++j) {
       const int q = tan[j].q;
@@ -479,6 +488,7 @@ static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vec
       }
       RoundTarget tg = target(P->dk[q][i].get());
       plan_round_sketch_two_sided(*plan, terms, Z, Zl, tg, prec);
+      plan_check_finite(*plan, P->dk[q][i].get(), P->nonfinite.as<int>());
     }
   }
   const double b4[4] = {dt / 6, dt / 3, dt / 3, dt / 6}, b2[2] = {0.5 * dt, 0.5 * dt};
@@ -492,6 +502,7 @@ static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vec
     for (int i = 0; i < S; ++i) comb.push_back(sterm(b[i], nullptr, ks[i].get()));
     RoundTarget tg = target(x);
     plan_round_sketch_two_sided(*plan, comb, Z, Zl, tg, data_prec(prec));
+    plan_check_finite(*plan, x, P->nonfinite.as<int>());
     return tg;
   };
   P->last = combine(f, P->k);
@@ -556,6 +567,13 @@ static bool use_graph() {
 extern "C" {
 
 const char* tt_last_error(void) { return get_error(); }
+
+tt_status tt_set_allocator(tt_alloc_fn alloc, tt_free_fn free, void* user) {
+  return guard([&] {
+    QTT_REQUIRE((alloc == nullptr) == (free == nullptr), "give both allocator functions or neither");
+    rt::set_allocator(alloc, free, user);
+  });
+}
 
 tt_status tt_ctx_create(int device, void* hip_stream, tt_ctx** out) {
   return guard([&] {
@@ -707,8 +725,9 @@ tt_status mpo_build(tt_ctx* ctx, int ndims, int bits, int ordering, const tt_ter
   });
 }
 
-tt_status mps_apply_mpo(tt_ctx* ctx, const tt_tt* mpo, const tt_tt* x, tt_tt** out) {
+tt_status mps_apply_mpo(tt_ctx* ctx, const tt_tt* mpo, const tt_tt* x, int dtype, tt_tt** out) {
   return guard([&] {
+    const Prec prec = prec_of(dtype);
     check_tt(mpo, ctx);
     check_tt(x, ctx);
     QTT_REQUIRE(out, "out is null");
@@ -729,7 +748,7 @@ tt_status mps_apply_mpo(tt_ctx* ctx, const tt_tt* mpo, const tt_tt* x, tt_tt** o
     for (const ApplyJob& j : jobs) validate(j);
     DevBuf dj(jobs.size() * sizeof(ApplyJob));
     rt::copy(dj.p, jobs.data(), jobs.size() * sizeof(ApplyJob));
-    apply_jobs(dj.as<ApplyJob>(), N, maxe, ctx->stream);
+    apply_jobs(dj.as<ApplyJob>(), N, maxe, ctx->stream, prec);
     rt::sync(ctx->stream);
     *out = y.release();
   });
@@ -759,19 +778,30 @@ tt_status mps_axpby(tt_ctx* ctx, int n_terms, const double* coeffs, const tt_tt*
   });
 }
 
-tt_status mps_round(tt_ctx* ctx, const tt_tt* x, int chi, tt_tt** out) {
+tt_status mps_round(tt_ctx* ctx, const tt_tt* x, int chi, double rel_tol, tt_round_info* info, tt_tt** out) {
   return guard([&] {
     check_tt(x, ctx);
     QTT_REQUIRE(out && chi >= 1 && x->kind == TT_MPS, "bad argument");
+    QTT_REQUIRE(rel_tol >= 0.0 && rel_tol < 1.0, "rel_tol %g outside [0, 1)", rel_tol);
     auto y = make_tt(ctx, TT_MPS, x->N, chain_caps(x->N, chi));
     Plan plan;
     RoundTarget tg;
     for (int n = 0; n < x->N; ++n) tg.core.push_back(y->core(n));
     tg.caps = y->caps;
+    tg.rel_tol = rel_tol;
     plan_round_det(plan, view(x), tg);
     StreamScope sc(ctx);
     plan.run(ctx->stream);
     rt::sync(ctx->stream);
+    if (info) {
+      const RoundOutcome o = round_outcome(tg, ctx->stream);
+      info->max_bond = *std::max_element(o.kept.begin(), o.kept.end());
+      info->discarded_weight = 0.0;
+      for (double d : o.discarded) info->discarded_weight += d;
+      info->norm2 = o.norm2;
+      if (info->per_bond)
+        for (int n = 0; n <= x->N; ++n) info->per_bond[n] = o.discarded[n];
+    }
     *out = y.release();
   });
 }
@@ -1153,6 +1183,11 @@ tt_status tt_problem_create_flow(tt_ctx* ctx, const tt_params* pp, const tt_tt* 
     P->mff.alloc(sizeof(double) * 2 * 2 * P->cphi1);
     P->mfk.alloc(sizeof(double) * 2 * 2 * P->cphi1);
     P->scal.alloc(sizeof(double) * 4);
+    P->nonfinite.alloc(sizeof(int));
+    {
+      const int zero = 0;
+      rt::copy(P->nonfinite.p, &zero, sizeof(int));
+    }
     if (P->nx > 0)
       for (int a = 0; a < 2; ++a) P->mt[a] = make_tt(ctx, TT_MPS, P->nx, P->mcaps);
     rt::sync(ctx->stream);
@@ -1210,6 +1245,35 @@ static void ensure_step_graph(tt_problem* prob, tt_tt* f) {
   QTT_HIP(hipGraphInstantiate(&prob->exec, prob->graph, nullptr, nullptr, 0));
 }
 
+// reads and clears the problem's non-finite flag (synchronous); throws
+// TT_ERR_NONFINITE if it was set
+static void take_nonfinite(tt_problem* P, const char* where) {
+  int h = 0;
+  rt::sync(P->ctx->stream);
+  rt::copy(&h, P->nonfinite.p, sizeof(int));
+  if (h) {
+    const int zero = 0;
+    rt::copy(P->nonfinite.p, &zero, sizeof(int));
+    QTT_THROW(TT_ERR_NONFINITE, "NaN or Inf in the result of %s", where);
+  }
+}
+
+// weight chain of h^d sum_x,phi w1(phi1) w2(phi2) f (NULL: all ones)
+static host::TT weight_chain(const tt_params& p, const std::vector<double>* w1, const std::vector<double>* w2) {
+  const int M = 1 << p.bits;
+  const double h = 1.0 / M;
+  auto order = host::site_order(p.ndims, p.bits, p.ordering);
+  std::vector<double> one(M, h);
+  std::vector<host::TT> q(p.ndims);
+  std::vector<const host::TT*> pp(p.ndims);
+  for (int d = 0; d < p.ndims; ++d) {
+    const std::vector<double>* v = (d == 0 && w1) ? w1 : (d == 1 && w2) ? w2 : &one;
+    q[d] = host::vector_qtt(v->data(), p.bits);
+    pp[d] = &q[d];
+  }
+  return host::kron_dims(pp, order, p.ndims, 2);
+}
+
 // one step of a problem whose plan (and graph) exist, on stream s
 static void launch_step(tt_problem* prob, hipStream_t s) {
   prob->last = prob->last_plain;
@@ -1229,6 +1293,41 @@ tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps) {
     ensure_step_graph(prob, f);
     StreamScope sc(ctx);
     for (int i = 0; i < n_steps; ++i) launch_step(prob, ctx->stream);
+  });
+}
+
+tt_status tt_step_ex(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps, tt_step_record* records) {
+  return guard([&] {
+    QTT_REQUIRE(prob && f && n_steps >= 0, "bad argument");
+    check_tt(f, ctx);
+    QTT_REQUIRE(prob->ctx == ctx, "problem belongs to another context");
+    QTT_REQUIRE(f->caps == prob->fcaps, "state caps differ from the problem's");
+    if (n_steps == 0) return;
+    ensure_step_graph(prob, f);
+    host::TT w = weight_chain(prob->p, nullptr, nullptr);
+    auto wt = upload(ctx, TT_MPS, w, exact_caps(w));
+    Plan mp;
+    double* mass = mp.alloc(1);
+    plan_inner(mp, view(wt.get()), view(f), mass);
+    StreamScope sc(ctx);
+    for (int i = 0; i < n_steps; ++i) {
+      launch_step(prob, ctx->stream);
+      mp.run(ctx->stream);
+      const RoundOutcome o = round_outcome(prob->last, ctx->stream);
+      double m = 0.0;
+      int bad = 0;
+      rt::copy(&m, mass, sizeof(double));
+      rt::copy(&bad, prob->nonfinite.p, sizeof(int));
+      if (records) {
+        tt_step_record& r = records[i];
+        r.mass_dev = m - 1.0;
+        r.discarded_weight = 0.0;
+        for (double d : o.discarded) r.discarded_weight += d;
+        r.max_bond = *std::max_element(o.kept.begin(), o.kept.end());
+        r.nonfinite = bad ? 1 : 0;
+      }
+      if (bad) take_nonfinite(prob, "a rounding of this step");
+    }
   });
 }
 
@@ -1436,6 +1535,7 @@ tt_status tt_step_info(tt_problem* prob, double* discarded, double* norm2) {
         for (int i = 0; i < ell[1]; ++i) s += std::max(0.0, lam[(size_t)ld + i]);
       *norm2 = s;
     }
+    take_nonfinite(prob, "a rounding of a step");
   });
 }
 

@@ -72,6 +72,8 @@ tt_status guard(F&& body) {
 // ---------------------------------------------------------------------------
 namespace rt {
 bool dry();
+// routes dev_alloc / dev_free through the caller's allocator (null: hipMalloc)
+void set_allocator(tt_alloc_fn a, tt_free_fn f, void* user);
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
 // throws unless [p + lo*esize, p + (hi+1)*esize) lies inside one allocation

@@ -36,6 +36,16 @@ void scalar_comb(double* out, const double* a, const double* b, double cb, doubl
 void validate(const CopyJob& j);
 void validate(const ApplyJob& j);
 void copy_jobs(const CopyJob* d_jobs, int njobs, int64_t max_elems, hipStream_t s);
-void apply_jobs(const ApplyJob* d_jobs, int njobs, int64_t max_elems, hipStream_t s);
+// the products of the explicit MPO x MPS application in precision prec
+// (FP64; FP32 inputs; BF16 high + low parts), summed in FP64
+void apply_jobs(const ApplyJob* d_jobs, int njobs, int64_t max_elems, hipStream_t s, Prec prec = Prec::F64);
+// zeroes the eigenvector columns of a batch of truncations (matrix i: dims[i]
+// rows, keep[i] kept columns, eigenvalues descending) whose eigenvalue is at
+// most tol2 times the largest; device and host copies of dims and keep
+void rank_cut(double* P, int64_t strideP, int ldp, const double* lam, int64_t strideL, const int* d_dims,
+              const int* d_keep, const std::vector<int>& dims, const std::vector<int>& keep, double tol2,
+              hipStream_t s);
+// *flag = 1 if any of the n values at p is NaN or infinite (flag untouched otherwise)
+void check_finite(const double* p, int64_t n, int* flag, hipStream_t s);
 
 }  // namespace qtt

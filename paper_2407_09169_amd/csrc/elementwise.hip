@@ -3,6 +3,8 @@
 // Each launch processes a table of per-site jobs (blockIdx.y = job) so that a
 // whole chain is one launch; threads stream the elements of a core in order,
 // so global reads and writes are coalesced along the right bond.
+#include <cmath>
+
 #include "elementwise.h"
 
 namespace qtt {
@@ -31,6 +33,23 @@ __global__ void copy_jobs_kernel(const CopyJob* jobs) {
   }
 }
 
+// product of two operands at contraction precision PR: FP64, FP32 inputs, or
+// BF16 high + low parts (three products, the low-low one dropped)
+template <int PR>
+__device__ inline double prec_mul(double w, double x) {
+  if constexpr (PR == 0) {
+    return w * x;
+  } else if constexpr (PR == 1) {
+    return (double)((float)w * (float)x);
+  } else {
+    const float wf = (float)w, xf = (float)x;
+    const float wh = (float)(__bf16)wf, xh = (float)(__bf16)xf;
+    const float wl = (float)(__bf16)(wf - wh), xl = (float)(__bf16)(xf - xh);
+    return (double)(wh * xh + (wh * xl + wl * xh));
+  }
+}
+
+template <int PR>
 __global__ void apply_jobs_kernel(const ApplyJob* jobs) {
   const ApplyJob j = jobs[blockIdx.y];
   // out[(a,alpha), t, (b,beta)] = sum_s W[alpha,t,s,beta] x[a,s,b]
@@ -47,9 +66,37 @@ __global__ void apply_jobs_kernel(const ApplyJob* jobs) {
     double v = 0.0;
 #pragma unroll
     for (int s = 0; s < 2; ++s)
-      v += j.W[(((int64_t)al * 2 + t) * 2 + s) * j.Dr + be] * j.x[((int64_t)a * 2 + s) * j.xr + b];
+      v += prec_mul<PR>(j.W[(((int64_t)al * 2 + t) * 2 + s) * j.Dr + be], j.x[((int64_t)a * 2 + s) * j.xr + b]);
     j.out[e] = v;
   }
+}
+
+// Rank cut of a batch of truncations: matrix i keeps its first keep[i]
+// eigenvector columns; those whose eigenvalue is at most tol2 * lam[0] (all but
+// the first) are zeroed, so the rounding keeps only singular values above
+// sqrt(tol2) sigma_1.
+__global__ void rank_cut_kernel(double* P, int64_t strideP, int ldp, const double* lam, int64_t strideL,
+                                const int* dims, const int* keep, double tol2) {
+  const int i = blockIdx.x;
+  const double* l = lam + i * strideL;
+  const int kp = keep[i], rows = dims[i];
+  const double cut = tol2 * l[0];
+  int k = 1;
+  while (k < kp && l[k] > cut) ++k;
+  double* Pi = P + i * strideP;
+  const int64_t n = (int64_t)rows * (kp - k);
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const int r = (int)(e / (kp - k)), c = k + (int)(e % (kp - k));
+    Pi[(int64_t)r * ldp + c] = 0.0;
+  }
+}
+
+// Sets *flag to 1 if any of the n values is NaN or infinite.
+__global__ void nonfinite_kernel(const double* p, int64_t n, int* flag) {
+  bool bad = false;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(p[e]);
+  if (bad) *flag = 1;
 }
 
 __global__ void transpose_kernel(const double* src, int rows, int cols, double* dst) {
@@ -142,13 +189,49 @@ void copy_jobs(const CopyJob* d_jobs, int njobs, int64_t max_elems, hipStream_t 
   QTT_HIP(hipGetLastError());
 }
 
-void apply_jobs(const ApplyJob* d_jobs, int njobs, int64_t max_elems, hipStream_t s) {
+void rank_cut(double* P, int64_t strideP, int ldp, const double* lam, int64_t strideL, const int* d_dims,
+              const int* d_keep, const std::vector<int>& dims, const std::vector<int>& keep, double tol2,
+              hipStream_t s) {
+  const int count = (int)dims.size();
+  if (count == 0) return;
+  for (int i = 0; i < count; ++i) {
+    QTT_REQUIRE(keep[i] >= 1 && keep[i] <= ldp && keep[i] <= dims[i], "rank cut: keep %d of %d", keep[i], dims[i]);
+    rt::check_range(P, i * strideP, i * strideP + (int64_t)(dims[i] - 1) * ldp + keep[i] - 1, sizeof(double),
+                    "rank cut vectors");
+    rt::check_range(lam, i * strideL, i * strideL + keep[i] - 1, sizeof(double), "rank cut values");
+  }
+  rt::check_range(d_dims, 0, count - 1, sizeof(int), "rank cut dims");
+  rt::check_range(d_keep, 0, count - 1, sizeof(int), "rank cut keep");
+  if (rt::dry()) return;
+  hipLaunchKernelGGL(rank_cut_kernel, dim3(count), dim3(256), 0, s, P, strideP, ldp, lam, strideL, d_dims, d_keep,
+                     tol2);
+  QTT_HIP(hipGetLastError());
+}
+
+void check_finite(const double* p, int64_t n, int* flag, hipStream_t s) {
+  if (n <= 0) return;
+  rt::check_range(p, 0, n - 1, sizeof(double), "finite check");
+  rt::check_range(flag, 0, 0, sizeof(int), "finite check flag");
+  if (rt::dry()) {  // host memory stands in for device memory: scan it here
+    for (int64_t e = 0; e < n; ++e)
+      if (!std::isfinite(p[e])) *flag = 1;
+    return;
+  }
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, flag);
+  QTT_HIP(hipGetLastError());
+}
+
+void apply_jobs(const ApplyJob* d_jobs, int njobs, int64_t max_elems, hipStream_t s, Prec prec) {
   if (njobs <= 0) return;
   rt::check_range(d_jobs, 0, njobs - 1, sizeof(ApplyJob), "apply job table");
   if (rt::dry()) return;
   int64_t bx = std::min<int64_t>((max_elems + 255) / 256, 1024);
   if (bx < 1) bx = 1;
-  hipLaunchKernelGGL(apply_jobs_kernel, dim3((unsigned)bx, njobs), dim3(256), 0, s, d_jobs);
+  const dim3 grid((unsigned)bx, njobs);
+  if (prec == Prec::F64) hipLaunchKernelGGL(apply_jobs_kernel<0>, grid, dim3(256), 0, s, d_jobs);
+  else if (prec == Prec::F32) hipLaunchKernelGGL(apply_jobs_kernel<1>, grid, dim3(256), 0, s, d_jobs);
+  else hipLaunchKernelGGL(apply_jobs_kernel<2>, grid, dim3(256), 0, s, d_jobs);
   QTT_HIP(hipGetLastError());
 }
 

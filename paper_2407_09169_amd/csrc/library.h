@@ -184,7 +184,21 @@ struct RoundTarget {
   std::vector<int> caps;
   double* lam = nullptr;  // (N+1) x ldl eigenvalues (optional, filled by the planner)
   int ldl = 0;
+  // > 0: at every bond also drop the singular values at most rel_tol sigma_1
+  double rel_tol = 0.0;
+  std::vector<int> in_caps;  // bonds of the chain that is truncated (filled by the planner)
 };
+
+// Outcome of a recorded rounding, read back on the host after it ran:
+// per-bond discarded weight (sum of the dropped squared singular values),
+// kept directions per bond, and the squared norm of the result.
+struct RoundOutcome {
+  std::vector<double> discarded;  // N + 1
+  std::vector<int> kept;          // N + 1
+  double norm2 = 0.0;
+};
+// synchronises `s` and reads the eigenvalues the rounding left in tg.lam
+RoundOutcome round_outcome(const RoundTarget& tg, hipStream_t s);
 
 // randomized range finding (right sketches + QR sweep) into an ell-rank
 // left-orthogonal chain, then simultaneous SVD truncation to target.caps

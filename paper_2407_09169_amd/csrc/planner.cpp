@@ -263,6 +263,7 @@ static void plan_trunc_gram(Plan& plan, const std::vector<double*>& X, const std
   int* d_keep = plan.upload(keep);
   tg.lam = lam;
   tg.ldl = ldg;
+  tg.in_caps = ell;
   const size_t psz = (size_t)(N + 1) * ldg * ldp;
   plan.add([P, psz, lam, N, ldg](hipStream_t s) {
     fill(P, (int64_t)psz, 0.0, s);
@@ -311,6 +312,12 @@ static void plan_trunc_gram(Plan& plan, const std::vector<double*>& X, const std
       eig_launch(cnt, d_dims, d_keep, g1, (int64_t)ldg * ldg, ldg, p1, (int64_t)ldg * ldp, ldp, l1,
                  ldg, ework, lmax, unoise, s, pre);
     }, oi);
+    if (tg.rel_tol > 0.0) {
+      const double tol2 = tg.rel_tol * tg.rel_tol;
+      plan.add([=](hipStream_t s) {
+        rank_cut(p1, (int64_t)ldg * ldp, ldp, l1, ldg, d_dims, d_keep, dims, keep, tol2, s);
+      });
+    }
   }
   // new cores P_n^T X_n P_{n+1}
   for (int n = 0; n < N; ++n) {
@@ -695,6 +702,41 @@ void plan_round_det(Plan& plan, const ChainView& x, RoundTarget& tg) {
   for (int n = 0; n < N; ++n) rv.core.push_back(rc[n]);
   LeftOrth lo = plan_left_orth(plan, rv);
   plan_trunc_gram(plan, lo.core, lo.caps, tg, Prec::F64);
+}
+
+RoundOutcome round_outcome(const RoundTarget& tg, hipStream_t s) {
+  const int N = (int)tg.core.size();
+  RoundOutcome o;
+  o.discarded.assign(N + 1, 0.0);
+  o.kept.assign(N + 1, 1);
+  rt::sync(s);
+  if (N < 2 || !tg.lam) {
+    if (N == 1) {
+      double v[2];
+      rt::copy(v, tg.core[0], sizeof(v));
+      o.norm2 = v[0] * v[0] + v[1] * v[1];
+    }
+    return o;
+  }
+  QTT_REQUIRE((int)tg.in_caps.size() == N + 1, "rounding outcome: bonds of the input unknown");
+  std::vector<double> lam((size_t)(N + 1) * tg.ldl);
+  rt::copy(lam.data(), tg.lam, lam.size() * sizeof(double));
+  const double tol2 = tg.rel_tol * tg.rel_tol;
+  for (int n = 1; n < N; ++n) {
+    const double* l = &lam[(size_t)n * tg.ldl];
+    const int e = tg.in_caps[n], keep = std::min(e, tg.caps[n]);
+    int k = keep;
+    if (tol2 > 0.0) {
+      k = 1;
+      while (k < keep && l[k] > tol2 * l[0]) ++k;
+    }
+    double d = 0.0;
+    for (int i = k; i < e; ++i) d += std::max(0.0, l[i]);
+    o.discarded[n] = d;
+    o.kept[n] = k;
+  }
+  for (int i = 0; i < tg.in_caps[1]; ++i) o.norm2 += std::max(0.0, lam[(size_t)tg.ldl + i]);
+  return o;
 }
 
 // ---------------------------------------------------------------------------

@@ -352,6 +352,7 @@ struct TwoSided {
   double *Gam = nullptr, *P = nullptr, *lam = nullptr, *ework = nullptr, *TgL = nullptr, *TgR = nullptr;
   int ldg = 1, ldp = 1, lmax = 1;
   int *d_dims = nullptr, *d_keep = nullptr;
+  std::vector<int> dims_h, keep_h;
   size_t vsz = 1;
   double* G(int n) const { return Gam + (size_t)n * ldg * ldg; }
   double* Pn(int n) const { return P + (size_t)n * ldg * ldp; }
@@ -478,8 +479,11 @@ void ts_setup(Plan& plan, TwoSided& r, const std::vector<SketchTerm>& terms, Rou
   }
   r.d_dims = plan.upload(dims);
   r.d_keep = plan.upload(keep);
+  r.dims_h = dims;
+  r.keep_h = keep;
   tg.lam = r.lam;
   tg.ldl = r.ldg;
+  tg.in_caps = ell;
 }
 
 // partial sketch chain q of a rounding: right sketches of term group q/2
@@ -735,6 +739,11 @@ void ts_eig(Plan& plan, TwoSided& r, const std::vector<int>& ell, Prec prec) {
     eig_launch(cnt, d_dims, d_keep, g1, (int64_t)ldg * ldg, ldg, p1, (int64_t)ldg * ldp, ldp, l1, ldg, ework,
                lmax, unoise, s, pre);
   }, oi);
+  if (r.tg->rel_tol > 0.0) {
+    const double tol2 = r.tg->rel_tol * r.tg->rel_tol;
+    const std::vector<int> dims = r.dims_h, keep = r.keep_h;
+    plan.add([=](hipStream_t s) { rank_cut(p1, (int64_t)ldg * ldp, ldp, l1, ldg, d_dims, d_keep, dims, keep, tol2, s); });
+  }
 }
 
 // new core n: P_n^T A_n P_(n+1) (V1: scratch of r.vsz doubles)

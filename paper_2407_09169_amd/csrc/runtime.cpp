@@ -10,9 +10,27 @@ namespace qtt {
 namespace rt {
 
 static std::mutex g_mu;
-static std::map<uintptr_t, size_t>& registry() {
-  static std::map<uintptr_t, size_t> m;
+// every device range the library may touch: bytes, and whether it came from
+// the caller's allocator (returned to it on free)
+struct Range {
+  size_t bytes = 0;
+  bool hooked = false;
+};
+static std::map<uintptr_t, Range>& registry() {
+  static std::map<uintptr_t, Range> m;
   return m;
+}
+
+// the caller's allocator (tt_set_allocator); null: hipMalloc / hipFree
+static tt_alloc_fn g_alloc = nullptr;
+static tt_free_fn g_free = nullptr;
+static void* g_user = nullptr;
+
+void set_allocator(tt_alloc_fn a, tt_free_fn f, void* user) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_alloc = a;
+  g_free = f;
+  g_user = user;
 }
 
 bool dry() {
@@ -26,31 +44,66 @@ bool dry() {
 
 void* dev_alloc(size_t bytes) {
   void* p = nullptr;
+  bool hooked = false;
   if (dry()) {
     p = std::calloc(1, bytes);
     if (!p) QTT_THROW(TT_ERR_OOM, "host allocation of %zu bytes failed", bytes);
   } else {
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) QTT_THROW(TT_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    tt_alloc_fn a;
+    void* user;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      a = g_alloc;
+      user = g_user;
+    }
+    if (a) {
+      int dev = 0;
+      QTT_HIP(hipGetDevice(&dev));
+      p = a(bytes, dev, nullptr, user);
+      if (!p) QTT_THROW(TT_ERR_OOM, "the registered allocator returned no memory for %zu bytes", bytes);
+      hooked = true;
+    } else {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) QTT_THROW(TT_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
   }
   std::lock_guard<std::mutex> lk(g_mu);
-  registry()[(uintptr_t)p] = bytes;
+  registry()[(uintptr_t)p] = Range{bytes, hooked};
   return p;
 }
 
 void dev_free(void* p) {
   if (!p) return;
+  Range r;
+  tt_free_fn f;
+  void* user;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    registry().erase((uintptr_t)p);
+    auto it = registry().find((uintptr_t)p);
+    if (it != registry().end()) {
+      r = it->second;
+      registry().erase(it);
+    }
+    f = g_free;
+    user = g_user;
   }
-  if (dry()) std::free(p);
-  else (void)hipFree(p);
+  if (dry()) {
+    std::free(p);
+  } else if (r.hooked) {
+    // the caller's allocator may hand the block to other streams at once:
+    // no kernel of the library may still use it
+    (void)hipDeviceSynchronize();
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (f) f(p, r.bytes, dev, nullptr, user);
+  } else {
+    (void)hipFree(p);
+  }
 }
 
 void register_range(const void* p, size_t bytes) {
   std::lock_guard<std::mutex> lk(g_mu);
-  registry()[(uintptr_t)p] = bytes;
+  registry()[(uintptr_t)p] = Range{bytes, false};
 }
 
 void unregister_range(const void* p) {
@@ -67,9 +120,9 @@ void check_range(const void* p, int64_t lo, int64_t hi, size_t esize, const char
   auto it = m.upper_bound(a);
   if (it == m.begin()) QTT_THROW(TT_ERR_INVALID_ARG, "%s: pointer outside every allocation", what);
   --it;
-  if (a < it->first || b > it->first + it->second)
+  if (a < it->first || b > it->first + it->second.bytes)
     QTT_THROW(TT_ERR_INVALID_ARG, "%s: access [%ld, %ld] x %zu B overruns its allocation of %zu B",
-              what, (long)lo, (long)hi, esize, it->second);
+              what, (long)lo, (long)hi, esize, it->second.bytes);
 }
 
 void copy(void* dst, const void* src, size_t bytes) {

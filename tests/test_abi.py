@@ -250,3 +250,38 @@ print("ok")
 """ % ROOT
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
+
+
+def test_dry_run_nonfinite_reported():
+    """A NaN put into a state through tt_set_cores is found by the checks that
+    every step runs after its roundings (in a dry run on the host buffers that
+    stand in for device memory): tt_step_ex returns TT_ERR_NONFINITE and the
+    record says so; tt_step_info reports it after a plain tt_step."""
+    code = r"""
+import os, sys
+os.environ["QTTPDF_DRYRUN"] = "1"
+sys.path.insert(0, %r)
+import numpy as np
+import paper_2407_09169_amd as q, workloads
+ctx = q.Context(0, stream=0)
+w = workloads.get_workload("t_5d_M8_chi16")
+p, f = q.setup_workload(ctx, w, "f64")
+assert p.step_ex(f, 1)[0]["nonfinite"] == 0
+c = f.cores(); c[3][0, 0, 0] = np.inf; f.set_cores(c)
+try:
+    p.step_ex(f, 1)
+    raise SystemExit("no error")
+except q.QttError as e:
+    assert e.status == 4 and e.records[0]["nonfinite"] == 1, e
+p.step(f, 1)
+try:
+    p.step_info()
+    raise SystemExit("no error")
+except q.QttError as e:
+    assert "NaN or Inf" in str(e)
+x, info = q.round_det(ctx, f, 4, 1e-3, with_info=True)
+assert len(info["per_bond"]) == w.n_sites + 1
+print("ok")
+""" % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
