@@ -1,5 +1,6 @@
 // Allocation registry, dry-run switch and copy wrappers (see common.h).
 #include <cstdlib>
+#include <malloc.h>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -38,6 +39,11 @@ bool dry() {
   if (v < 0) {
     const char* e = std::getenv("QTTPDF_DRYRUN");
     v = (e && e[0] == '1') ? 1 : 0;
+    // Dry runs stand host memory in for thousands of workspaces of up to
+    // gigabytes: a fixed mmap threshold gives each large one its own fresh
+    // zero pages, instead of heap chunks that glibc would search and clear
+    // (its adaptive threshold otherwise grows after the first large frees).
+    if (v == 1) mallopt(M_MMAP_THRESHOLD, 256 * 1024);
   }
   return v == 1;
 }
