@@ -467,6 +467,38 @@ def _accuracy_series(q, ctx, w, runs, n):
     return series
 
 
+def _bench_chi_mean(args, log):
+    """What the bond cap chi_mean of the mean compositions <Phi_a>(x) costs
+    and changes: FP64 runs of the 128^5 chi = 64 and 1024^5 chi = 128
+    workloads from the same initial state with chi_mean in {8, 16, 32, chi}
+    (chi: the raw mean is kept whole), steps/s of each and the relative L2
+    distance of each final state to the chi_mean = chi run."""
+    import torch
+    import paper_2407_09169_amd as q
+    import workloads
+    ctx = q.Context(0)
+    out = {"metric": "chi_mean study: steps/s and L2 distance to the uncapped mean field", "runs": []}
+    for name, n in (("c2_5d_M128_chi64", args.steps), ("c3_5d_M1024_chi128", max(2, args.steps // 2))):
+        w0 = workloads.get_workload(name)
+        states = {}
+        for cm in (w0.chi, 8, 16, 32):
+            w = w0.replace(chi_mean=cm, oversample_mean=8)
+            prob, f = q.setup_workload(ctx, w, "f64")
+            _, mb = prob.info()
+            prob.step(f, 1)  # records the graph
+            ms = _time_steps(torch, prob, f, n)
+            states[cm] = (prob, f)
+            d = 0.0 if cm == w0.chi else q.l2_diff(ctx, f, states[w0.chi][1])
+            row = {"workload": name, "chi_mean": cm, "steps": n + 1, "steps_per_s": n / (ms / 1e3),
+                   "l2_vs_uncapped": d, "stage_mpo_bond_x_sites": mb + 2 * cm}
+            log(str(row))
+            out["runs"].append(row)
+        for prob, f in states.values():
+            f.free()
+            prob.close()
+    print(json.dumps(out))
+
+
 def _bench_drift(args, log):
     """Precision drift over a long run: the 128^5 chi = 64 workload (200 RK4
     steps) in FP32 and BF16 next to FP64 from the same initial state, the
@@ -511,6 +543,9 @@ def main():
                     help="also write the per-launch event times of one eager step to this file")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--chi-mean-study", action="store_true",
+                    help="FP64 steps/s and L2 distance to the uncapped mean field for chi_mean in "
+                         "{8, 16, 32, chi} on the 128^5 and 1024^5 workloads")
     ap.add_argument("--drift", action="store_true",
                     help="precision drift: FP32 and BF16 against FP64 after every step of the 128^5 "
                          "chi = 64 workload (--steps steps, 200 for the stated target)")
@@ -548,6 +583,9 @@ def main():
         return
     if args.drift:
         _bench_drift(args, log)
+        return
+    if args.chi_mean_study:
+        _bench_chi_mean(args, log)
         return
     if args.workload.startswith("fpmoms_M"):
         _bench_moments(args, log)

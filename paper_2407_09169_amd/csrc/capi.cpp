@@ -204,6 +204,13 @@ struct tt_problem {
   int mf_first_ld = 1;
   std::unique_ptr<tt_tt> k[4];
   std::unique_ptr<tt_tt> mt[2];
+  // Hadamard form of the mean-field term (5-D): the fixed operator F and, per
+  // composition a, the term -Omega D1g^(phi_a) diag(<Phi_a>) as an MPO of its
+  // own whose x-site cores are diagonal (written every stage), rounded as
+  // separate terms instead of the block sum A when that is cheaper
+  bool split_mf = false;
+  std::unique_ptr<tt_tt> F, MF[2];
+  ChainView Fv, MFv[2];
   DevBuf Ef, Ek, mff, mfk, scal;
   int cphi = 1, cphi1 = 1;  // caps of f at the phi|x cut and after the first x site
   // recorded step
@@ -362,10 +369,40 @@ static void plan_mf_blocks(Plan& plan, tt_problem* P, tt_tt* mpo, const std::vec
   plan.add([=](hipStream_t s) { copy_jobs(dj, nj, maxe, s); });
 }
 
-// writes the mean-field blocks of the stage operator A for the state
-// g = f + cg * kprev (kprev may be null)
+// writes diag(mt[a]) into the x-site cores of the Hadamard-form term MF[a]
+static void plan_mf_diag(Plan& plan, tt_problem* P, tt_tt* const mt[2]) {
+  std::vector<CopyJob> jobs;
+  int64_t maxe = 1;
+  for (int a = 0; a < 2; ++a)
+    for (int j = 0; j < P->nx; ++j) {
+      const int n = P->nphi + j;
+      CopyJob c{};
+      c.src = mt[a]->core(j);
+      c.dst = P->MF[a]->core(n);
+      c.rl = mt[a]->caps[j];
+      c.sp = 2;
+      c.rr = mt[a]->caps[j + 1];
+      c.dp = 4;
+      c.drr = P->MF[a]->caps[n + 1];
+      c.ro = 0;
+      c.co = 0;
+      c.diag = 1;
+      c.scale = 1.0;
+      c.dscale = nullptr;
+      jobs.push_back(c);
+      maxe = std::max<int64_t>(maxe, (int64_t)c.rl * 2 * c.rr);
+    }
+  for (const CopyJob& j : jobs) validate(j);
+  CopyJob* dj = plan.upload(jobs);
+  const int nj = (int)jobs.size();
+  plan.add([=](hipStream_t s) { copy_jobs(dj, nj, maxe, s); });
+}
+
+// writes the mean-field part of the stage operator for the state
+// g = f + cg * kprev (kprev may be null): the blocks of A, or with split the
+// diagonal cores of MF[0], MF[1]
 static void plan_stage_operator(Plan& plan, tt_problem* P, const tt_tt* f, const tt_tt* kprev,
-                                double cg) {
+                                double cg, bool split = false) {
   const tt_params& p = P->p;
   if (P->nx == 0) {
     // 2-D: scalars s_a = -Omega (m_a(f) + cg m_a(k)); first-core blocks scaled
@@ -403,7 +440,8 @@ static void plan_stage_operator(Plan& plan, tt_problem* P, const tt_tt* f, const
   if (kprev) terms.push_back({cg, kprev, P->mfk.d()});
   tt_tt* mt[2] = {P->mt[0].get(), P->mt[1].get()};
   plan_mean_round(plan, P, terms, mt);
-  plan_mf_blocks(plan, P, P->A.get(), P->Dfix, mt);
+  if (split) plan_mf_diag(plan, P, mt);
+  else plan_mf_blocks(plan, P, P->A.get(), P->Dfix, mt);
 }
 
 // flags a NaN or Inf in the cores of x (after a rounding wrote them)
@@ -458,10 +496,25 @@ static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vec
     const tt_tt* kp = (i == 0) ? nullptr : P->k[i - 1].get();
     const double cg = cst[i];
     if (kp) plan_mean_raw(*plan, P, kp, P->Ek.d(), P->mfk.d());
-    plan_stage_operator(*plan, P, f, kp, cg);
+    const bool split = P->split_mf && tan.empty();
+    plan_stage_operator(*plan, P, f, kp, cg, split);
     {
-      std::vector<SketchTerm> terms{sterm(1.0, &Av, f)};
-      if (kp) terms.push_back(sterm(cg, &Av, kp));
+      std::vector<SketchTerm> terms;
+      if (split) {
+        // F g + sum_a MF_a g, g = f + cg kp: the mean-field terms' x sites are diagonal
+        for (const ChainView* W : {&P->Fv, &P->MFv[0], &P->MFv[1]}) {
+          const int df = (W == &P->Fv) ? -1 : P->nphi;
+          terms.push_back(sterm(1.0, W, f));
+          terms.back().diag_from = df;
+          if (kp) {
+            terms.push_back(sterm(cg, W, kp));
+            terms.back().diag_from = df;
+          }
+        }
+      } else {
+        terms.push_back(sterm(1.0, &Av, f));
+        if (kp) terms.push_back(sterm(cg, &Av, kp));
+      }
       RoundTarget tg = target(P->k[i].get());
       plan_round_sketch_two_sided(*plan, terms, Z, Zl, tg, prec);
       plan_check_finite(*plan, P->k[i].get(), P->nonfinite.as<int>());
@@ -1113,6 +1166,39 @@ tt_status tt_problem_create_flow(tt_ctx* ctx, const tt_params* pp, const tt_tt* 
     // 5-D: the mean-field block carries -Omega in its first core; 2-D: the
     // first-core blocks are rescaled by -Omega <Phi_a> at every stage
     P->A = assemble_stage_mpo(P.get(), Fx, P->nx > 0 ? (P->has_Om ? -1.0 : -p.omega) : 1.0, P->Dfix);
+    if (P->nx > 0) {
+      // Hadamard form when the time its sketch contractions save over those
+      // of the block sum (flops per x site of a sketch chain: dense MPO of
+      // bond D, or diagonal cores of bond chi_mean; at the ~20 TFLOP/s these
+      // launches reach) exceeds what its six extra launches per x site cost
+      // (~10 us each).  Measured: the 1024^5 chi = 128 step with chi_mean =
+      // 128 gains 1.4x; the 128^5 chi = 64 step with chi_mean <= 64 loses.
+      const double r = p.chi, l = p.ell;
+      auto dense = [&](double D) { return D * 2 * r * l * l + 4 * D * D * r * l + 2 * D * r * r * l; };
+      auto diag = [&](double D) { return D * 2 * r * l * l + 2 * D * D * r * l + 2 * D * r * r * l; };
+      int dfx = 1;
+      for (int n = P->nphi; n <= N; ++n) dfx = std::max(dfx, P->Dfix[n]);
+      const double cm = p.chi_mean;
+      const char* e = std::getenv("QTTPDF_MEAN_FORM");
+      if (e && std::strcmp(e, "split") == 0) P->split_mf = true;
+      else if (e && std::strcmp(e, "block") == 0) P->split_mf = false;
+      else P->split_mf = (dense(dfx + 2 * cm) - dense(dfx) - 2 * diag(cm)) / 2e13 > 6 * 1e-5;
+      if (P->split_mf) {
+        P->F = upload(ctx, TT_MPO, Fx, exact_caps(Fx));
+        P->Fv = view(P->F.get());
+        const double sc = P->has_Om ? -1.0 : -p.omega;
+        for (int a = 0; a < 2; ++a) {
+          host::TT W = T[a];
+          for (double& v : W[0].v) v *= sc;
+          std::vector<int> caps(N + 1, 1);
+          for (int n = 0; n < P->nphi; ++n) caps[n + 1] = W[n].rr;
+          for (int j = 1; j < P->nx; ++j) caps[P->nphi + j] = P->mcaps[j];
+          for (int j = 0; j < P->nx; ++j) W.push_back(host::Core(caps[P->nphi + j], 4, caps[P->nphi + j + 1]));
+          P->MF[a] = upload(ctx, TT_MPO, W, caps);
+          P->MFv[a] = view(P->MF[a].get());
+        }
+      }
+    }
     if (P->nx == 0) {
       // first-core blocks of the two mean-field terms, kept unscaled
       P->mf_first_cols = {T[0][0].rr, T[1][0].rr};

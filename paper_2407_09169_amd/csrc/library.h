@@ -175,6 +175,12 @@ struct SketchTerm {
   double coef = 1.0;
   const ChainView* mpo = nullptr;  // nullptr: identity
   ChainView x;
+  // sites >= diag_from (if >= 0) have MPO cores that are diagonal in the
+  // physical index (W[A,t,s,B] = 0 for t != s), such as diag(field) on the x
+  // sites of a Hadamard-product term: their contractions skip the zeros
+  // (two-sided rounding only)
+  int diag_from = -1;
+  bool diag_at(int n) const { return mpo != nullptr && diag_from >= 0 && n >= diag_from; }
 };
 
 // Output of a rounding: destination cores (caps chi_n) and, for reporting,

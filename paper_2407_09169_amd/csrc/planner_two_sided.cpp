@@ -63,7 +63,29 @@ std::vector<TcDesc> rsketch_descs(const SketchTerm& t, const Shape& sh, const Ch
     d.ab = d.bb = d.cb = M1(0);
     out.push_back(d);
   }
-  if (t.mpo) {
+  if (t.diag_at(n)) {
+    {  // T2[(A,s), b, z] = sum_B W[A,s,s,B] T1[(b,B),(s,z)], batch (b, s)
+      TcDesc d;
+      d.batch = 2 * rp;
+      d.M = Dn;
+      d.K = Dp;
+      d.N = l;
+      d.A = t.mpo->core[n];
+      d.am = M1(4 * Dp);
+      d.ak = M1(1);
+      d.ab = M2(2, 0, 3 * Dp);
+      d.B = T1;
+      d.bk = M1(2 * l);
+      d.bn = M1(1);
+      d.bb = M2(2, (int64_t)Dp * 2 * l, l);
+      d.C = T2;
+      d.cm = M1((int64_t)2 * rp * l);
+      d.cn = M1(1);
+      d.cb = M2(2, l, (int64_t)rp * l);
+      out.push_back(d);
+    }
+  }
+  if (t.mpo && !t.diag_at(n)) {
     {  // T2[(A,s), b, z] = sum_(B,t) W[A,t,s,B] T1[(b,B),(t,z)], batch b
       TcDesc d;
       d.batch = rp;
@@ -84,6 +106,8 @@ std::vector<TcDesc> rsketch_descs(const SketchTerm& t, const Shape& sh, const Ch
       d.cb = M1(l);
       out.push_back(d);
     }
+  }
+  if (t.mpo) {
     {  // R_out[(a,A),z] = sum_(s,b) x[a,s,b] T2[A,s,b,z], batch A
       TcDesc d;
       d.batch = Dn;
@@ -148,7 +172,29 @@ std::vector<TcDesc> lsketch_descs(const SketchTerm& t, const Shape& sh, const Ch
     d.ab = d.bb = d.cb = M1(0);
     out.push_back(d);
   }
-  if (t.mpo) {
+  if (t.diag_at(n)) {
+    {  // T2[a,(s,B),z] = sum_A W[A,s,s,B] T1[(a,A),(s,z)], batch (a, s)
+      TcDesc d;
+      d.batch = 2 * rn;
+      d.M = Dp;
+      d.K = Dn;
+      d.N = lp;
+      d.A = t.mpo->core[n];
+      d.am = M1(1);
+      d.ak = M1(4 * Dp);
+      d.ab = M2(2, 0, 3 * Dp);
+      d.B = T1;
+      d.bk = M1(2 * lp);
+      d.bn = M1(1);
+      d.bb = M2(2, (int64_t)Dn * 2 * lp, lp);
+      d.C = T2;
+      d.cm = M1(lp);
+      d.cn = M1(1);
+      d.cb = M2(2, (int64_t)2 * Dp * lp, (int64_t)Dp * lp);
+      out.push_back(d);
+    }
+  }
+  if (t.mpo && !t.diag_at(n)) {
     {  // T2[a,(s,B),z] = sum_(A,t) W[A,t,s,B] T1[(a,A),(t,z)], batch a
       TcDesc d;
       d.batch = rn;
@@ -169,6 +215,8 @@ std::vector<TcDesc> lsketch_descs(const SketchTerm& t, const Shape& sh, const Ch
       d.cb = M1((int64_t)2 * Dp * lp);
       out.push_back(d);
     }
+  }
+  if (t.mpo) {
     {  // L_out[z,(b,B)] = sum_(a,s) T2[a,(s,B),z] x[a,s,b], batch B
       TcDesc d;
       d.batch = Dp;
@@ -236,6 +284,28 @@ std::vector<TcDesc> lcore_descs(const SketchTerm& t, const Shape& sh, int n, int
     d.cn = M1(1);
     d.cb = M1(2 * rp);
   }
+  if (t.diag_at(n)) {  // C[k,s,b,B] = sum_A U1[k,A,s,b] W[A,s,s,B], batch s
+    TcDesc& d = out[1];
+    d.batch = 2;
+    d.M = l * rp;
+    d.K = Dn;
+    d.N = Dp;
+    d.A = U1;
+    d.am = M2(rp, (int64_t)2 * Dn * rp, 1);
+    d.ak = M1(2 * rp);
+    d.ab = M1(rp);
+    d.B = t.mpo->core[n];
+    d.bk = M1(4 * Dp);
+    d.bn = M1(1);
+    d.bb = M1(3 * Dp);
+    d.C = Cdst;
+    d.cm = M2(rp, (int64_t)2 * rp * Dp, Dp);
+    d.cn = M1(1);
+    d.cb = M1((int64_t)rp * Dp);
+    d.alpha = alpha;
+    d.beta = beta;
+    return out;
+  }
   {  // C[k,t,b,B] = sum_(A,s) U1[k,A,s,b] W[A,t,s,B]
     TcDesc& d = out[1];
     d.M = l * rp;
@@ -283,6 +353,26 @@ std::vector<TcDesc> rcore_descs(const SketchTerm& t, const Shape& sh, int n, int
     d.cm = M1((int64_t)Dp * lp);
     d.cn = M1(1);
     d.cb = M1(lp);
+  }
+  if (t.diag_at(n)) {  // Cr[(a,A),(s,z)] = sum_B W[A,s,s,B] U1[(a,s),B,z], batch s
+    TcDesc& d = out[1];
+    d.batch = 2;
+    d.M = Dn;
+    d.N = rn * lp;
+    d.K = Dp;
+    d.A = t.mpo->core[n];
+    d.am = M1(4 * Dp);
+    d.ak = M1(1);
+    d.ab = M1(3 * Dp);
+    d.B = U1;
+    d.bk = M1(lp);
+    d.bn = M2(lp, (int64_t)2 * Dp * lp, 1);
+    d.bb = M1((int64_t)Dp * lp);
+    d.C = Cdst;
+    d.cm = M1(2 * lp);
+    d.cn = M2(lp, (int64_t)Dn * 2 * lp, 1);
+    d.cb = M1(lp);
+    return out;
   }
   {  // Cr[(a,A),(t,z)] = sum_(s,B) W[(A,t),(s,B)] U1[(a,s),B,z]: rows (A,t), columns (a,z)
     TcDesc& d = out[1];

@@ -118,3 +118,13 @@ def c4_instances():
     import workloads
     ws = workloads.batch_workloads()
     return [ws[i] for i in C4_INSTANCES]
+
+
+# workloads with the mean compositions kept whole (chi_mean at the bond cap of
+# their x chains): (name, chi_mean, steps)
+UNCAPPED_MEAN_CASES = [("t_5d_M8_chi16", 16, 3), ("t_5d_M16_chi32", 32, 2)]
+
+
+def uncapped(name, chi_mean):
+    import workloads
+    return workloads.get_workload(name).replace(chi_mean=chi_mean, oversample_mean=8)

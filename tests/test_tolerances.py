@@ -110,3 +110,13 @@ def test_gram_floor_of_full_size_steps(name, integrator, fields):
         st2 = make(w)
         emu, _ = st2.step(st2.initial_state())
     assert mps_rel(emu, ref) < TRUNC_TOL_F64 / 3
+
+
+@pytest.mark.parametrize("name,chi_mean,steps", cases.UNCAPPED_MEAN_CASES)
+def test_gram_floor_of_uncapped_mean_cases(name, chi_mean, steps):
+    w = cases.uncapped(name, chi_mean)
+    ref = _run(stepper.MPSStepper(w), steps)
+    with gram_truncation():
+        emu = _run(stepper.MPSStepper(w), steps)
+    worst = max(rel(a, b) for a, b in zip(emu, ref))
+    assert worst < TRUNC_TOL_F64 / 3, (name, worst)
