@@ -14,8 +14,10 @@ two states after the run.
 
 Other workloads print their own line: batch64 (64 uneven problems stepped
 together), --gradient (steps carrying parameter derivatives), fpmoms_M<M>
-(the moment equation on an M^3 grid) and flow_c2_5d_M128_chi64 (the flow
-case's accuracy protocol on the 128^5 grid).
+(the moment equation on an M^3 grid), flow_c2_5d_M128_chi64 (the flow
+case's accuracy protocol on the 128^5 grid), prolong_smag_M1024 (the closure
+field on 1024^3 by prolongation against the direct TT-SVD), --drift
+(precision over 200 steps) and --chi-mean-study.
 
 Prints ONE JSON line.
 """
@@ -298,6 +300,63 @@ def _bench_moments(args, log):
                      "timing": "events around the timed steps, divided by the launches"},
         "finite": bool(torch.isfinite(m).all()),
     }
+    print(json.dumps(out))
+
+
+def _bench_prolong(args, log):
+    """The flow case's Smagorinsky diffusivity as a bond-16 x-MPS on the 1024^3
+    grid, prepared two ways: directly (the velocity of eq. velField and the
+    closure evaluated on the 1024^3 grid, 2^30 values, then the truncated
+    TT-SVD of tt_from_dense) and by prolongation (the same on the 256^3 grid,
+    then two tt_prolong refinements).  Wall time of each path (the closure
+    field's set-up, not part of a step) and the relative L2 distance between
+    the two fields, both with the filter width Delta = 3 / 1024."""
+    import torch
+    import paper_2407_09169_amd as q
+    import workloads
+    ctx = q.Context(0)
+    dev = torch.device("cuda", 0)
+    delta, chi = 3.0 / 1024, 16
+
+    def closure(bits):
+        M = 1 << bits
+        w = workloads.get_workload("t_5d_M8_chi16", bits=bits, ic="paper")
+        U = torch.zeros((3, M, M, M), dtype=torch.float64, device=dev)
+        one = torch.ones(M, dtype=torch.float64, device=dev)
+        for i, comp in enumerate(workloads.velocity_terms(w)):
+            for c, vecs in comp:
+                v = [one if x is None else torch.as_tensor(x, device=dev) for x in vecs]
+                U[i] += c * v[0][:, None, None] * v[1][None, :, None] * v[2][None, None, :]
+        G = torch.empty(M ** 3, dtype=torch.float64, device=dev)
+        q.smagorinsky(ctx, bits, U.view(-1), G, 0.11, delta, 1e-3)
+        del U
+        return G
+
+    for rep in range(2):  # the first pass pages in the kernels
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G = closure(10)
+        direct, d_direct = q.from_dense(ctx, G, chi)
+        torch.cuda.synchronize()
+        t_direct = time.perf_counter() - t0
+        del G
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        G = closure(8)
+        coarse, d_coarse = q.from_dense(ctx, G, chi)
+        y1, d1 = q.prolong(ctx, coarse, 3, 8, chi)
+        y2, d2 = q.prolong(ctx, y1, 3, 9, chi)
+        torch.cuda.synchronize()
+        t_prolong = time.perf_counter() - t0
+        del G
+    diff = q.l2_diff(ctx, y2, direct)
+    log(f"direct {t_direct:.3f} s, prolonged {t_prolong:.3f} s, L2 between them {diff:.3e}")
+    out = {"metric": "set-up time of the 1024^3 Smagorinsky x-MPS (bond 16): direct vs prolongation from 256^3",
+           "value": t_direct / t_prolong, "unit": "speedup", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "prolong_smag_M1024", "chi": chi, "delta": delta, "coarse": "256^3"},
+           "direct_s": t_direct, "prolonged_s": t_prolong, "l2_prolonged_vs_direct": diff,
+           "discarded": {"direct": d_direct, "coarse": d_coarse, "prolong": d1 + d2}}
     print(json.dumps(out))
 
 
@@ -592,6 +651,9 @@ def main():
         return
     if args.workload == "flow_c2_5d_M128_chi64":
         _bench_flow(args, log)
+        return
+    if args.workload == "prolong_smag_M1024":
+        _bench_prolong(args, log)
         return
     w = workloads.get_workload(args.workload)
     ctx = q.Context(0)

@@ -454,6 +454,20 @@ tt_status tt_to_dense(tt_ctx* ctx, const tt_tt* x, double* out);
  * bonds, the squared 2-norm of the approximation error.  Synchronises. */
 tt_status tt_from_dense(tt_ctx* ctx, int n_sites, const double* values, int chi, tt_tt** out,
                         double* discarded);
+/* Prolongation of a field to the grid of twice the resolution in every
+ * dimension (section "Computational complexity": the input fields prepared
+ * at O(chi^3 d log M) by prolongation rather than from dense values): x is an
+ * MPS of ndims dimensions of `bits` sites each in serial order (a periodic
+ * x-field, x_j = j / M); the result (new handle) has bits + 1 sites per
+ * dimension and holds the periodic linear interpolation of x,
+ * x'_(2j) = x_j and x'_(2j+1) = (x_j + x_(j+1 mod M)) / 2 along every
+ * dimension.  Dimension by dimension, the chain is lifted by a site that
+ * copies the coarse value, the interpolation MPO is applied exactly, and the
+ * result is rounded to bond chi by mps_round (FP64); *discarded (nullable)
+ * receives the sum of the discarded weights of these roundings.
+ * Synchronises. */
+tt_status tt_prolong(tt_ctx* ctx, const tt_tt* x, int ndims, int bits, int chi, tt_tt** out,
+                     double* discarded);
 /* Total diffusivity G = gamma + gamma_SGS with the Smagorinsky closure of
  * the paragraph after eq. FP0: gamma_SGS = c_s delta^2 / 2 times the square
  * root of sum_ij (dU_i/dx_j + dU_j/dx_i)^2, the derivatives taken as

@@ -37,7 +37,7 @@ EXPORTS = [
     "tt_step", "tt_step_ex", "tt_profile", "tt_step_info", "tt_observable", "tt_mean_field",
     "tt_linalg_qr", "tt_linalg_eigh", "tt_batch_create", "tt_step_batched", "tt_batch_destroy",
     "tt_step_tangent", "tt_moment_field", "tt_to_dense", "fd_smagorinsky", "fd_moment_steps",
-    "fd_sq_diff_sum", "flow_error_measures", "tt_problem_create_flow", "tt_from_dense",
+    "fd_sq_diff_sum", "flow_error_measures", "tt_problem_create_flow", "tt_from_dense", "tt_prolong",
 ]
 KERNELS = {"contract": 0, "qr": 1, "eig": 2, "stream": 3, "all": 4}
 
@@ -132,6 +132,7 @@ def lib():
         "flow_error_measures": [i32, P(dbl), P(dbl), P(dbl), P(dbl)],
         "tt_problem_create_flow": [vp, P(TTParams), P(vp), vp, vp, vp, vp, vp, vp, P(vp)],
         "tt_from_dense": [vp, i32, vp, i32, P(vp), P(dbl)],
+        "tt_prolong": [vp, vp, i32, i32, i32, P(vp), P(dbl)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -647,6 +648,15 @@ def from_dense(ctx, values, chi):
     _check(lib().tt_from_dense(ctx.h, N, _dense_arg(values, n, "values"), chi, C.byref(h),
                                C.byref(disc)))
     return TT(ctx, h), disc.value
+
+
+def prolong(ctx, x, ndims, bits, chi):
+    """tt_prolong: (the field on the grid of twice the resolution, rounded to
+    chi; the discarded weight of the roundings)."""
+    h = C.c_void_p()
+    d = C.c_double()
+    _check(lib().tt_prolong(ctx.h, x.h, ndims, bits, chi, C.byref(h), C.byref(d)))
+    return TT(ctx, h), d.value
 
 
 def smagorinsky(ctx, bits, U, G, c_s, delta, gamma):

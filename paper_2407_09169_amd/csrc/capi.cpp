@@ -1908,6 +1908,77 @@ tt_status flow_error_measures(int n_samples, const double* mean_bar, const doubl
 
 extern "C" {
 
+tt_status tt_prolong(tt_ctx* ctx, const tt_tt* x, int ndims, int bits, int chi, tt_tt** out,
+                     double* discarded) {
+  return guard([&] {
+    check_tt(x, ctx);
+    QTT_REQUIRE(out && x->kind == TT_MPS, "bad argument");
+    QTT_REQUIRE(ndims >= 1 && ndims <= 8 && bits >= 1 && bits <= 20 && x->N == ndims * bits,
+                "tt_prolong: %d sites are not %d dimensions of %d bits", x->N, ndims, bits);
+    QTT_REQUIRE(chi >= 1, "bad chi");
+    StreamScope sc(ctx);
+    hipStream_t s = ctx->stream;
+    const host::TT Q = host::prolong_block(bits);
+    std::unique_ptr<tt_tt> cur;  // the chain after the dimensions refined so far
+    const tt_tt* y = x;
+    double disc = 0.0;
+    for (int d = 0; d < ndims; ++d) {
+      // lift: a new site after the last digit of dimension d whose core is the
+      // identity on its bond, so the lifted value does not depend on the new digit
+      const int N = y->N, p = (d + 1) * bits + d;  // index of the new site
+      std::vector<int> lc(N + 2);
+      for (int n = 0; n <= p; ++n) lc[n] = y->caps[n];
+      lc[p + 1] = y->caps[p];
+      for (int n = p + 1; n <= N; ++n) lc[n + 1] = y->caps[n];
+      auto z = make_tt(ctx, TT_MPS, N + 1, lc);
+      for (int n = 0; n < N; ++n) {
+        const int m = n < p ? n : n + 1;
+        rt::copy_async(z->core(m), y->core(n), (size_t)(y->off[n + 1] - y->off[n]) * sizeof(double), s);
+      }
+      {
+        const int r = y->caps[p];
+        std::vector<double> id((size_t)r * 2 * r, 0.0);
+        for (int a = 0; a < r; ++a) id[(size_t)a * 2 * r + a] = id[((size_t)a * 2 + 1) * r + a] = 1.0;
+        rt::copy(z->core(p), id.data(), id.size() * sizeof(double));
+      }
+      // interpolation MPO on the lifted chain: identity outside dimension d's block
+      host::TT W;
+      for (int n = 0; n < d * bits + d; ++n) W.push_back(host::mpo_identity(1)[0]);
+      W.insert(W.end(), Q.begin(), Q.end());
+      while ((int)W.size() < N + 1) W.push_back(host::mpo_identity(1)[0]);
+      auto Wd = upload(ctx, TT_MPO, W, exact_caps(W));
+      // exact product, then deterministic rounding to chi
+      std::vector<int> pc(N + 2);
+      for (int n = 0; n <= N + 1; ++n) pc[n] = z->caps[n] * Wd->caps[n];
+      auto yz = make_tt(ctx, TT_MPS, N + 1, pc);
+      std::vector<ApplyJob> jobs;
+      int64_t maxe = 1;
+      for (int n = 0; n <= N; ++n) {
+        jobs.push_back({Wd->core(n), z->core(n), yz->core(n), z->caps[n], z->caps[n + 1], Wd->caps[n],
+                        Wd->caps[n + 1]});
+        maxe = std::max<int64_t>(maxe, (int64_t)pc[n] * 2 * pc[n + 1]);
+      }
+      for (const ApplyJob& j : jobs) validate(j);
+      DevBuf dj(jobs.size() * sizeof(ApplyJob));
+      rt::copy(dj.p, jobs.data(), jobs.size() * sizeof(ApplyJob));
+      apply_jobs(dj.as<ApplyJob>(), N + 1, maxe, s);
+      auto r = make_tt(ctx, TT_MPS, N + 1, chain_caps(N + 1, chi));
+      Plan plan;
+      RoundTarget tg;
+      for (int n = 0; n <= N; ++n) tg.core.push_back(r->core(n));
+      tg.caps = r->caps;
+      plan_round_det(plan, view(yz.get()), tg);
+      plan.run(s);
+      const RoundOutcome o = round_outcome(tg, s);  // synchronises before the temporaries go
+      for (double v : o.discarded) disc += v;
+      cur = std::move(r);
+      y = cur.get();
+    }
+    if (discarded) *discarded = disc;
+    *out = cur.release();
+  });
+}
+
 tt_status tt_from_dense(tt_ctx* ctx, int n_sites, const double* values, int chi, tt_tt** out,
                         double* discarded) {
   return guard([&] {

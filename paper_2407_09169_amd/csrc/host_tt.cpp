@@ -311,6 +311,17 @@ TT op1d(int op, int bits) {
   return round_svd(out, 1e-15, 1 << 30);
 }
 
+TT prolong_block(int bits) {
+  Core E11(1, 4, 1);
+  E11.at(0, 3, 0) = 1.0;  // t = s = 1
+  TT I = mpo_identity(bits + 1);
+  TT S = shift_plus(bits, true);
+  S.push_back(E11);
+  TT D = mpo_identity(bits);
+  D.push_back(E11);
+  return round_svd(tt_sum({{1.0, &I}, {0.5, &S}, {-0.5, &D}}), 1e-15, 1 << 30);
+}
+
 std::vector<std::pair<int, int>> site_order(int ndims, int bits, int ordering) {
   std::vector<std::pair<int, int>> o;
   if (ordering == TT_SERIAL) {

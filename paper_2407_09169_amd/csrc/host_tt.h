@@ -51,6 +51,12 @@ TT mpo_diag(const TT& x);
 TT mpo_apply(const TT& W, const TT& x);
 // identity MPO over n sites
 TT mpo_identity(int n);
+// Periodic linear interpolation onto the grid of twice the resolution, on the
+// bits sites of one dimension followed by a new least significant site that
+// holds a copy of the coarse value (an identity core on the bond): the MPO
+// I + (S+ - I) (x) diag(0, 1/2), so that a lifted value f(j) at digit b
+// becomes f(j) + b (f(j+1 mod M) - f(j)) / 2 (bits + 1 sites, compressed)
+TT prolong_block(int bits);
 
 // textbook rounding (QR sweep + right-to-left truncated SVDs) with a
 // relative tolerance per bond -- used to compress operators

@@ -285,3 +285,23 @@ print("ok")
 """ % ROOT
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
+
+
+def test_dry_run_prolong_planning():
+    """tt_prolong at 256^3 -> 512^3 -> 1024^3 plans every launch in bounds
+    (dry run) and gives 27 and 30 sites."""
+    code = r"""
+import os, sys
+os.environ["QTTPDF_DRYRUN"] = "1"
+sys.path.insert(0, %r)
+import paper_2407_09169_amd as q, workloads
+ctx = q.Context(0, stream=0)
+w = workloads.get_workload("t_5d_M8_chi16", bits=8)
+x = q.from_separable(ctx, 3, 8, q.TT_SERIAL, workloads.flow_field_terms(w)["G"], 16)
+y, _ = q.prolong(ctx, x, 3, 8, 16)
+z, _ = q.prolong(ctx, y, 3, 9, 16)
+assert y.info()[1] == 27 and z.info()[1] == 30
+print("ok")
+""" % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
