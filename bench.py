@@ -661,7 +661,9 @@ def main():
 
     prob, f = q.setup_workload(ctx, w, args.dtype)
     log(f"{w.name} {args.dtype}: set up; warmup {W}")
+    t_rec = time.perf_counter()
     prob.step(f, W)
+    t_rec = time.perf_counter() - t_rec
     ms = _time_steps(torch, prob, f, K)
     value = K / (ms / 1e3)
     log(f"{args.dtype}: {K} steps in {ms:.1f} ms ({value:.2f} steps/s)")
@@ -730,6 +732,9 @@ def main():
         "discarded_weight_last_rounding": float(sum(disc)),
         **extra,
         "per_step_accuracy": accuracy,
+        "autotune": {"shapes_measured": q.autotune_info()[0], "seconds": q.autotune_info()[1],
+                     "enabled": os.environ.get("QTTPDF_AUTOTUNE", "1") != "0",
+                     "first_steps_with_recording_s": t_rec},
         "roofline": roof,
         "kernel_classes": rows,
         "cpu_baseline": cpu,

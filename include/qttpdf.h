@@ -386,6 +386,15 @@ tt_status tt_step_tangent(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_params,
 tt_status tt_profile(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps, int kernel, double* ms,
                      int64_t* launches, double* flops, double* bytes);
 
+/* Launch configuration of the contraction kernels: when a plan is recorded
+ * (problem steps, roundings, products), every distinct contraction shape is
+ * timed once on the device with each candidate FP64 tile (64x64, 64x32,
+ * 32x64, 32x32) and K split (1, 2, 4, ... 64 chunks), on scratch outputs,
+ * and the fastest is kept for the process (the environment variable
+ * QTTPDF_AUTOTUNE=0 keeps a fixed rule instead).  Reports the number of
+ * shapes measured so far and the seconds spent measuring. */
+tt_status tt_autotune_info(int* shapes, double* seconds);
+
 /* Per-bond discarded singular weight (sum of dropped sigma^2, n_sites + 1
  * entries) of the last rounding of the last step, and the squared norm of
  * its result.  Synchronises.  Returns TT_ERR_NONFINITE (and clears the

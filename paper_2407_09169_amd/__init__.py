@@ -29,7 +29,7 @@ LINEAR_OBS = ("mass", "mean1", "mean2", "mean12", "product")
 
 # every entry point of include/qttpdf.h
 EXPORTS = [
-    "tt_set_allocator", "tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_stream", "tt_ctx_synchronize", "tt_last_error",
+    "tt_set_allocator", "tt_autotune_info", "tt_ctx_create", "tt_ctx_destroy", "tt_ctx_set_stream", "tt_ctx_synchronize", "tt_last_error",
     "tt_alloc", "tt_free", "tt_info", "tt_set_cores", "tt_get_cores", "tt_from_separable",
     "mpo_build", "mps_apply_mpo", "mps_axpby", "mps_round", "mps_round_sketch",
     "mps_round_sketch_two_sided", "tt_l2_diff",
@@ -89,6 +89,7 @@ def lib():
     P = C.POINTER
     sig = {
         "tt_set_allocator": [vp, vp, vp],
+        "tt_autotune_info": [P(i32), P(dbl)],
         "tt_ctx_create": [i32, vp, P(vp)],
         "tt_ctx_destroy": [vp],
         "tt_ctx_set_stream": [vp, vp],
@@ -158,6 +159,13 @@ def _torch_stream():
     except Exception:  # noqa: BLE001 - torch is optional plumbing
         pass
     return C.c_void_p(None)
+
+
+def autotune_info():
+    """(launch shapes measured by the contraction autotuner, seconds spent)."""
+    n, t = C.c_int(), C.c_double()
+    _check(lib().tt_autotune_info(C.byref(n), C.byref(t)))
+    return n.value, t.value
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_int, C.c_void_p, C.c_void_p)

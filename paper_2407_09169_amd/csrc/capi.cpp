@@ -621,6 +621,10 @@ extern "C" {
 
 const char* tt_last_error(void) { return get_error(); }
 
+tt_status tt_autotune_info(int* shapes, double* seconds) {
+  return guard([&] { tc_autotune_stats(shapes, seconds); });
+}
+
 tt_status tt_set_allocator(tt_alloc_fn alloc, tt_free_fn free, void* user) {
   return guard([&] {
     QTT_REQUIRE((alloc == nullptr) == (free == nullptr), "give both allocator functions or neither");

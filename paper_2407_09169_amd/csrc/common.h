@@ -212,6 +212,7 @@ struct TcDesc {
   int32_t ksplit = 1;
   double* part = nullptr;
   int32_t ng = 1, gsum = 0;
+  int32_t tile = 0;  // FP64 tile: 0 by size, 1 64x64, 2 64x32, 3 32x64, 4 32x32
   const double* gA[TC_MAXG] = {};
   const double* gB[TC_MAXG] = {};
   double* gC[TC_MAXG] = {};
@@ -227,6 +228,15 @@ void tc_launch(const TcDesc& d, Prec p, hipStream_t s);
 // caller provides the partial-sum buffer of tc_part_size(d) doubles when
 // tc_uses_part(d) (set d.ksplit first)
 int tc_choose_ksplit(const TcDesc& d, Prec p);
+// Sets d.ksplit (and for FP64 d.tile) for a launch: with measure, the fastest
+// of the candidate tiles and K splits timed on the device with scratch
+// outputs (the operands are only read), cached per shape for the process;
+// without, a cached choice for the shape or the rule of tc_choose_ksplit.
+// QTTPDF_AUTOTUNE=0 keeps the rule everywhere.  Returns whether the choice
+// came from a measurement.
+bool tc_configure(TcDesc& d, Prec p, bool measure);
+// number of launch shapes measured so far and the time spent measuring (s)
+void tc_autotune_stats(int* shapes, double* seconds);
 inline bool tc_uses_part(const TcDesc& d) { return d.ksplit > 1 || (d.ng > 1 && d.gsum); }
 inline int64_t tc_part_size(const TcDesc& d) { return (int64_t)d.batch * d.ng * d.ksplit * d.M * d.N; }
 // name of the kernel (template instantiation) a launch uses

@@ -67,7 +67,9 @@ static Mode2 M1(int64_t s) { return mode1(s); }
 static Mode2 M2(int n2, int64_t s1, int64_t s2) { return mode2(n2, s1, s2); }
 
 void add_tc(Plan& plan, TcDesc d, Prec p) {
-  d.ksplit = tc_choose_ksplit(d, p);
+  // measured tile and K split (no measurement into a fixed scratch buffer:
+  // it would allocate; a cached choice or the rule then)
+  tc_configure(d, p, plan.arena == nullptr);
   if (tc_uses_part(d)) d.part = plan.alloc_transient((size_t)tc_part_size(d));
   if (d.ng > 1) {
     std::vector<const double*> table;

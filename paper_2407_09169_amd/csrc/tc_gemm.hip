@@ -15,7 +15,13 @@
 // next K tile into registers while the current one is being multiplied.
 // Contractions with few output tiles and a long K are split along K
 // (TcDesc::ksplit); their partial sums are added by tc_splitk_reduce.
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 
 #include "common.h"
 
@@ -378,6 +384,12 @@ struct Tile {
 };
 inline Tile tile_of(const TcDesc& d, Prec p) {
   if (p != Prec::F64) return {64, 64};
+  switch (d.tile) {
+    case 1: return {64, 64};
+    case 2: return {64, 32};
+    case 3: return {32, 64};
+    case 4: return {32, 32};
+  }
   return {d.M >= 48 ? 64 : 32, d.N >= 48 ? 64 : 32};
 }
 
@@ -470,6 +482,133 @@ void tc_launch(const TcDesc& d, Prec p, hipStream_t s) {
     hipLaunchKernelGGL(tc_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, d);
     QTT_HIP(hipGetLastError());
   }
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning of the FP64 tile and the K split, per launch shape
+// ---------------------------------------------------------------------------
+namespace {
+
+struct TuneKey {
+  int p, M, N, K, batch, ng, gsum, beta, akf, bnf;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(p, M, N, K, batch, ng, gsum, beta, akf, bnf) <
+           std::tie(o.p, o.M, o.N, o.K, o.batch, o.ng, o.gsum, o.beta, o.akf, o.bnf);
+  }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tuned;  // (tile, ksplit)
+hipStream_t g_tune_stream = nullptr;
+int g_tune_shapes = 0;
+double g_tune_seconds = 0.0;
+
+bool autotune_on() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("QTTPDF_AUTOTUNE");
+    v = (e && e[0] == '0') ? 0 : 1;
+  }
+  return v == 1 && !rt::dry();
+}
+
+TuneKey key_of(const TcDesc& d, Prec p) {
+  return {(int)p, d.M, d.N, d.K, d.batch, d.ng, d.gsum, d.beta != 0.0 ? 1 : 0, unit(d.ak) ? 1 : 0,
+          unit(d.bn) ? 1 : 0};
+}
+
+// times the launch shape of d with every candidate (scratch outputs); returns (tile, ksplit)
+std::pair<int, int> measure(const TcDesc& d, Prec p) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!g_tune_stream) QTT_HIP(hipStreamCreateWithFlags(&g_tune_stream, hipStreamNonBlocking));
+  hipStream_t s = g_tune_stream;
+  std::vector<int> tiles{0};
+  if (p == Prec::F64) {
+    tiles = {4};
+    if (d.N > 32) tiles.push_back(3);
+    if (d.M > 32) tiles.push_back(2);
+    if (d.M > 32 && d.N > 32) tiles.push_back(1);
+  }
+  const int minchunk = (p == Prec::F64) ? 16 : 32;
+  std::vector<int> splits;
+  for (int ks = 1; ks <= 64; ks *= 2)
+    if ((ks == 1 || d.K >= 2 * minchunk * ks / 2) && (int64_t)d.batch * d.ng * ks <= 65535) splits.push_back(ks);
+  const int rule = tc_choose_ksplit(d, p);
+  if (std::find(splits.begin(), splits.end(), rule) == splits.end()) splits.push_back(rule);
+  // scratch output (every group writes into it), partial sums for the largest split, group table
+  const int64_t cext = mode_max(d.cb, d.batch) + mode_max(d.cm, d.M) + mode_max(d.cn, d.N) + 1;
+  DevBuf C(sizeof(double) * (size_t)cext);
+  const int kmax = *std::max_element(splits.begin(), splits.end());
+  TcDesc probe = d;
+  probe.ksplit = kmax;
+  DevBuf part(sizeof(double) * (size_t)std::max<int64_t>(1, tc_part_size(probe)));
+  DevBuf table;
+  if (d.ng > 1) {
+    std::vector<const double*> t;
+    for (int g = 0; g < d.ng; ++g) t.push_back(d.gA[g]);
+    for (int g = 0; g < d.ng; ++g) t.push_back(d.gB[g]);
+    for (int g = 0; g < d.ng; ++g) t.push_back(C.d());
+    table.alloc(t.size() * sizeof(double*));
+    rt::copy(table.p, t.data(), t.size() * sizeof(double*));
+  }
+  hipEvent_t e0, e1;
+  QTT_HIP(hipEventCreate(&e0));
+  QTT_HIP(hipEventCreate(&e1));
+  std::pair<int, int> best{tiles[0], 1};
+  float best_ms = 1e30f;
+  for (int t : tiles)
+    for (int ks : splits) {
+      TcDesc e = d;
+      e.tile = t;
+      e.ksplit = ks;
+      e.C = C.d();
+      e.part = part.d();
+      if (d.ng > 1) {
+        for (int g = 0; g < d.ng; ++g) e.gC[g] = C.d();
+        e.gdev = table.as<const double*>();
+      }
+      tc_launch(e, p, s);  // warm-up
+      QTT_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) tc_launch(e, p, s);
+      QTT_HIP(hipEventRecord(e1, s));
+      QTT_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      QTT_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = {t, ks};
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  QTT_HIP(hipStreamSynchronize(s));
+  g_tune_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  ++g_tune_shapes;
+  return best;
+}
+
+}  // namespace
+
+bool tc_configure(TcDesc& d, Prec p, bool measure_ok) {
+  d.tile = 0;
+  d.ksplit = tc_choose_ksplit(d, p);
+  if (!autotune_on() || d.M <= 0 || d.N <= 0 || d.batch <= 0 || d.K <= 0) return false;
+  const TuneKey k = key_of(d, p);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(k);
+  if (it == g_tuned.end()) {
+    if (!measure_ok) return false;
+    it = g_tuned.emplace(k, measure(d, p)).first;
+  }
+  d.tile = it->second.first;
+  d.ksplit = it->second.second;
+  return true;
+}
+
+void tc_autotune_stats(int* shapes, double* seconds) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (shapes) *shapes = g_tune_shapes;
+  if (seconds) *seconds = g_tune_seconds;
 }
 
 TcDesc gemm_desc(int M, int N, int K, const double* A, int64_t lda, bool transA, const double* B,

@@ -305,3 +305,26 @@ print("ok")
 """ % ROOT
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
+
+
+def test_plan_lane_rules(tmp_path):
+    """The launch-plan rules that keep HIP graph capture on the forms that
+    work on this runtime (every fork from lane 0, every join onto it; one
+    lane on a fixed scratch buffer), exercised by a host program linked
+    against the library (dry run), and no batched step captures a graph of
+    its own: the batch launches the instances' recorded graphs on branch
+    streams (the four-branch captured form crashed the host process)."""
+    exe = tmp_path / "plan_rules"
+    src = os.path.join(ROOT, "tests", "cpp", "test_plan_rules.cpp")
+    lib_dir = os.path.dirname(LIB)
+    cmd = ["/opt/rocm/bin/hipcc", "-std=c++17", "-O1", "--offload-arch=gfx950", "-x", "hip", src,
+           "-I", os.path.join(lib_dir, "csrc"), "-L", lib_dir, "-lqttpdf", "-Wl,-rpath," + lib_dir, "-o", str(exe)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60,
+                       env={**os.environ, "QTTPDF_DRYRUN": "1"})
+    assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
+    src = open(os.path.join(lib_dir, "csrc", "capi.cpp")).read()
+    body = src[src.index("tt_status tt_step_batched("):]
+    body = body[:body.index("\n}\n")]
+    assert "hipStreamBeginCapture" not in body and "hipGraphInstantiate" not in body

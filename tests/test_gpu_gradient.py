@@ -74,3 +74,30 @@ def test_autograd_function(ctx):
     J2, g = q.statistic_and_gradient(ctx, w, 2, "product", "f64")
     assert float(J) == J2
     assert float(om.grad) == g["omega"] and float(kr.grad) == g["k_react"]
+
+
+def test_truncated_gradient_against_oracle_central_differences(ctx):
+    """16^5 grid at chi = 64 with truncation active: the GPU's forward-mode
+    dJ/dOmega and dJ/dk of the product mean after three steps against
+    central differences (h = 1e-4 relative) of the oracle stepper's J, to
+    1e-3 relative, the bound stated for gradients at chi = 64 before any run
+    (the tangent stands in for the derivative of the rounding; the gap
+    shrinks with the discarded weight)."""
+    w = workloads.get_workload("t_5d_M16_chi32").replace(chi=64)
+    n = 3
+    J, g = q.statistic_and_gradient(ctx, w, n, "product", "f64")
+
+    def J_oracle(wp):
+        st = stepper.MPSStepper(wp)
+        f = st.initial_state()
+        for _ in range(n):
+            f, _ = st.step(f)
+        return st.observables(f)["product"]
+
+    assert abs(J - J_oracle(w)) <= 1e-7 * max(1.0, abs(J))
+    for p in ("omega", "k_react"):
+        th = getattr(w, p)
+        h = 1e-4 * max(1.0, abs(th))
+        fd = (J_oracle(w.replace(**{p: th + h})) - J_oracle(w.replace(**{p: th - h}))) / (2 * h)
+        print(f"d J / d {p}: tangent {g[p]:.10e}, oracle central difference {fd:.10e}", flush=True)
+        assert abs(g[p] - fd) <= 1e-3 * abs(fd), (p, g[p], fd)
