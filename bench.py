@@ -372,6 +372,8 @@ def _bench_flow(args, log):
     from paper_2407_09169_amd import flow
     import workloads
     w = workloads.get_workload("c2_5d_M128_chi64", k_react=0.0, integrator="rk2", ic="paper")
+    if args.chi_mean:
+        w = w.replace(chi_mean=args.chi_mean, oversample_mean=8)
     ctx = q.Context(0)
     k = max(1, args.steps // 16)
     torch.cuda.synchronize()
@@ -389,7 +391,7 @@ def _bench_flow(args, log):
         "ms_per_step": 1e3 * sec / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": "flow_c2_5d_M128_chi64", "grid": "128^5", "chi": w.chi,
-                   "integrator": "rk2", "k_react": 0.0, "dt": w.dt, "samples": 17,
+                   "integrator": "rk2", "k_react": 0.0, "dt": w.dt, "samples": 17, "chi_mean": w.chi_mean,
                    "steps_per_sample": k,
                    "fields": "Smagorinsky G(x) (C_s 0.11, Delta 3/M, bond 16), Omega = G / Delta^2",
                    "initial_state": "eq. initPDF, eq. velField"},
@@ -602,6 +604,8 @@ def main():
                     help="also write the per-launch event times of one eager step to this file")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--chi-mean", type=int, default=0,
+                    help="bond cap of the mean compositions in the flow protocol (default: the workload's)")
     ap.add_argument("--chi-mean-study", action="store_true",
                     help="FP64 steps/s and L2 distance to the uncapped mean field for chi_mean in "
                          "{8, 16, 32, chi} on the 128^5 and 1024^5 workloads")

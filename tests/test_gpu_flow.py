@@ -163,13 +163,37 @@ def test_error_measures_match_oracle():
                                             [want[0], want[2], want[3]], rtol=1e-13)
 
 
-def _oracle_flow(w, T, k):
-    st = stepper.MPSStepper(w)
+def _oracle_fields(w, fields, chi_field, c_omega=1.0):
+    """The oracle stepper and the dense diffusivity of the moment equation for
+    the protocol's three settings: constant coefficients (fields None), the
+    seeded x-fields G(x), Omega(x) (fields True), or the paper's closure
+    (fields "smagorinsky": gamma + gamma_SGS from the velocity on the grid,
+    Delta = 3 / M, cut to chi_field by the oracle's TT-SVD, and Omega_mix =
+    c_omega G / Delta^2 of the cut field)."""
+    M = w.M
+    if not fields:
+        return stepper.MPSStepper(w), np.full((M, M, M), w.gamma)
+    if fields is True:
+        st = _field_stepper(w)
+        return st, st.dense_problem().G
+    assert fields == "smagorinsky"
+    st0 = stepper.MPSStepper(w)
+    xo = st0._x_order()
+    delta = 3.0 / M
+    Gd = moments.gamma_total(st0.velocity_dense(), w.gamma, 0.11, delta)
+    g = tt.tt_svd(tt.dense_to_sites(Gd, xo, w.bits), rel_tol=0.0, chi=chi_field)
+    om = [G.copy() for G in g]
+    om[0] = om[0] * (c_omega / (delta * delta))
+    st = stepper.MPSStepper(w, {"G": g, "Omega": om})
+    return st, tt.sites_to_dense(tt.tt_full(g), xo, w.bits, 3)
+
+
+def _oracle_flow(w, T, k, fields=None, chi_field=None):
+    st, G = _oracle_fields(w, fields, chi_field)
     f = st.initial_state()
     M, h = w.M, 1.0 / w.M
     phi = odense.phi_nodes(M)
     U = st.velocity_dense()
-    G = np.full((M, M, M), w.gamma)
     F = st.to_dense(f)
     m = [h * h * np.einsum("i,iabc->abc", phi, F.sum(axis=1)),
          h * h * np.einsum("j,jabc->abc", phi, F.sum(axis=0))]
@@ -246,9 +270,31 @@ def test_field_step_truncated_matches_oracle(ctx, name, integrator, steps):
     prob.close()
 
 
+@pytest.mark.parametrize("fields,chi_field", [(True, None), ("smagorinsky", 8)])
+def test_flow_protocol_with_fields_matches_oracle(ctx, fields, chi_field):
+    """The protocol with G(x) and Omega(x), the seeded fields or the paper's
+    closure (Smagorinsky field cut to a bond cap of 8, Omega = G / Delta^2),
+    against the oracle's run of the same protocol (field stepper and the
+    moment equation with the same dense G), to the tolerance of the
+    constant-coefficient run."""
+    from paper_2407_09169_amd import flow
+    w = workloads.get_workload("t_5d_M8_chi16", k_react=0.0, integrator="rk2", ic="paper")
+    T, k = 5, 2
+    want = _oracle_flow(w, T, k, fields, chi_field)
+    got = flow.run(ctx, w, n_samples=T, steps_per_sample=k, fields=fields,
+                   chi_field=chi_field if chi_field else 16)
+    vals = [got["E2b_up"], got["E2b_down"], got["E2c_up"], got["E2c_down"]]
+    assert all(np.isfinite(vals)), vals
+    assert vals[1] > 0.0
+    if fields == "smagorinsky":
+        assert got["field_discarded"] > 0.0  # the cap truncates the closure field
+    assert np.allclose(vals, want, rtol=1e-6, atol=1e-8), (vals, want)
+
+
 def test_flow_protocol_with_fields_runs(ctx):
-    """The protocol with G(x) and Omega(x): finite measures, the mass-norm
-    error at the truncation level, and the exact-mean error above zero."""
+    """The protocol with G(x) and Omega(x) on the 16^5 grid: finite measures,
+    the mass-norm error at the truncation level, and the exact-mean error
+    above zero."""
     from paper_2407_09169_amd import flow
     w = workloads.get_workload("t_5d_M16_chi32", k_react=0.0, integrator="rk2")
     got = flow.run(ctx, w, n_samples=5, steps_per_sample=2, fields=True)
