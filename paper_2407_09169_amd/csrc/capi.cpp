@@ -3,6 +3,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <thread>
 
 #include "library.h"
 #include "moments.h"
@@ -1502,6 +1503,13 @@ tt_status tt_step_batched(tt_batch* b, int n_steps) {
     QTT_REQUIRE(b && n_steps >= 0, "bad argument");
     StreamScope sc(b->ctx);
     hipStream_t s0 = b->ctx->stream;
+    // Submitting a recorded step graph costs host time per node; with
+    // QTTPDF_BATCH_THREADS=1 every branch is submitted by a host thread of
+    // its own, so the branches' submissions overlap.
+    static const bool threaded = [] {
+      const char* e = std::getenv("QTTPDF_BATCH_THREADS");
+      return e && e[0] == '1';
+    }();
     for (int step = 0; step < n_steps; ++step) {
       if (rt::dry()) {
         for (auto& ch : b->chain)
@@ -1510,12 +1518,32 @@ tt_status tt_step_batched(tt_batch* b, int n_steps) {
       }
       // fork from the context's stream, one chain per branch, join back
       QTT_HIP(hipEventRecord(b->events[0], s0));
-      for (size_t k = 0; k < b->chain.size(); ++k) {
+      const int nb = (int)b->chain.size();
+      auto branch = [&](int k) {
         QTT_HIP(hipStreamWaitEvent(b->streams[k], b->events[0], 0));
         for (int i : b->chain[k]) launch_step(b->probs[i], b->streams[k]);
         QTT_HIP(hipEventRecord(b->events[k + 1], b->streams[k]));
-        QTT_HIP(hipStreamWaitEvent(s0, b->events[k + 1], 0));
+      };
+      if (threaded && nb > 1) {
+        std::vector<std::thread> th;
+        std::vector<std::string> errs(nb);
+        const int dev = b->ctx->device;
+        for (int k = 0; k < nb; ++k)
+          th.emplace_back([&, k] {
+            try {
+              QTT_HIP(hipSetDevice(dev));
+              branch(k);
+            } catch (const Error& e) {
+              errs[k] = e.msg;
+            }
+          });
+        for (auto& t : th) t.join();
+        for (const auto& e : errs)
+          if (!e.empty()) QTT_THROW(TT_ERR_HIP, "%s", e.c_str());
+      } else {
+        for (int k = 0; k < nb; ++k) branch(k);
       }
+      for (int k = 0; k < nb; ++k) QTT_HIP(hipStreamWaitEvent(s0, b->events[k + 1], 0));
     }
   });
 }

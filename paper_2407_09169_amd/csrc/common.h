@@ -212,7 +212,8 @@ struct TcDesc {
   int32_t ksplit = 1;
   double* part = nullptr;
   int32_t ng = 1, gsum = 0;
-  int32_t tile = 0;  // FP64 tile: 0 by size, 1 64x64, 2 64x32, 3 32x64, 4 32x32
+  int32_t tile = 0;  // FP64 tile: 0 by size, 1 64x64, 2 64x32, 3 32x64, 4 32x32; MFMA pipeline: 0 K tile 32,
+                     // 1 K tile 32 double-buffered, 2 K tile 64 double-buffered
   const double* gA[TC_MAXG] = {};
   const double* gB[TC_MAXG] = {};
   double* gC[TC_MAXG] = {};
@@ -228,7 +229,7 @@ void tc_launch(const TcDesc& d, Prec p, hipStream_t s);
 // caller provides the partial-sum buffer of tc_part_size(d) doubles when
 // tc_uses_part(d) (set d.ksplit first)
 int tc_choose_ksplit(const TcDesc& d, Prec p);
-// Sets d.ksplit (and for FP64 d.tile) for a launch: with measure, the fastest
+// Sets d.ksplit and d.tile (FP64 tile, MFMA pipeline) for a launch: with measure, the fastest
 // of the candidate tiles and K splits timed on the device with scratch
 // outputs (the operands are only read), cached per shape for the process;
 // without, a cached choice for the shape or the rule of tc_choose_ksplit.

@@ -12,7 +12,9 @@
 //     operand split into a BF16 high and low part (three MFMAs per product).
 // The MFMA kernels read the FP64 operands, round them to FP32 / split them
 // into BF16 pairs while staging the tiles in LDS, and write FP64 results.  All kernels load the
-// next K tile into registers while the current one is being multiplied.
+// next K tile into registers while the current one is being multiplied; the
+// MFMA kernels come with three pipelines (K tile 32 or 64, one or two LDS
+// buffers), chosen per launch shape by measurement.
 // Contractions with few output tiles and a long K are split along K
 // (TcDesc::ksplit); their partial sums are added by tc_splitk_reduce.
 #include <algorithm>
@@ -178,15 +180,23 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // lo*hi on v_mfma_f32_16x16x32_bf16 (the dropped lo*lo term and the rounding
 // of lo leave a relative error of about 2^-16 per product instead of the
 // 2^-8 of a single BF16 operand).
-template <bool BF16, bool AKF, bool BNF>
+//
+// Two pipelines: DB = false stages one K tile of BK in LDS (two barriers per
+// step; the next tile is loaded into registers during the MFMAs); DB = true
+// double-buffers the LDS tiles (one barrier per step: the MFMAs read one
+// buffer while the next tile is stored into the other) and, for FP32, gives
+// MFMA t of a 16-wide K block the k values 4 lq + t of lane group lq, so each
+// lane reads its four operands of a block with one 16-byte LDS load.
+template <bool BF16, bool AKF, bool BNF, int BK, bool DB>
 __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
-  constexpr int BM = 64, BN = 64, BK = 32;
+  constexpr int BM = 64, BN = 64;
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
   using TIn = typename std::conditional<BF16, __bf16, float>::type;
   constexpr int PAD = BF16 ? 8 : 4;
   constexpr int NH = BF16 ? 2 : 1;  // hi (and lo) parts of each staged operand
-  __shared__ TIn As[NH][BM][BK + PAD];
-  __shared__ TIn Bs[NH][BN][BK + PAD];
+  constexpr int NBUF = DB ? 2 : 1;
+  __shared__ __align__(16) TIn As[NBUF][NH][BM][BK + PAD];
+  __shared__ __align__(16) TIn Bs[NBUF][NH][BN][BK + PAD];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -249,58 +259,78 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
       for (int q = 0; q < NB; ++q) rb[q] = (bok[q] && kok) ? B[ko + boff[q]] : 0.0;
     }
   };
-  if (kr.beg < kr.end) load(kr.beg);
-  for (int k0 = kr.beg; k0 < kr.end; k0 += BK) {
+  // registers -> LDS buffer `buf` (rounded to FP32 or split into BF16 pairs)
+  auto stage = [&](int buf) {
     if constexpr (BF16) {
 #pragma unroll
       for (int q = 0; q < NA; ++q) {
         const float x = (float)ra[q];
         const __bf16 hi = (__bf16)x;
-        As[0][a_row(q)][a_col(q)] = hi;
-        As[1][a_row(q)][a_col(q)] = (__bf16)(x - (float)hi);
+        As[buf][0][a_row(q)][a_col(q)] = hi;
+        As[buf][1][a_row(q)][a_col(q)] = (__bf16)(x - (float)hi);
       }
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
         const float x = (float)rb[q];
         const __bf16 hi = (__bf16)x;
-        Bs[0][b_col(q)][b_row(q)] = hi;
-        Bs[1][b_col(q)][b_row(q)] = (__bf16)(x - (float)hi);
+        Bs[buf][0][b_col(q)][b_row(q)] = hi;
+        Bs[buf][1][b_col(q)][b_row(q)] = (__bf16)(x - (float)hi);
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < NA; ++q) As[0][a_row(q)][a_col(q)] = (float)ra[q];
+      for (int q = 0; q < NA; ++q) As[buf][0][a_row(q)][a_col(q)] = (float)ra[q];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) Bs[0][b_col(q)][b_row(q)] = (float)rb[q];
+      for (int q = 0; q < NB; ++q) Bs[buf][0][b_col(q)][b_row(q)] = (float)rb[q];
     }
-    __syncthreads();
-    if (k0 + BK < kr.end) load(k0 + BK);
+  };
+  // MFMAs over the tile in LDS buffer `buf`
+  auto compute = [&](int buf) {
     if constexpr (BF16) {
-      bf16x8 a[2][2], b[2][2];  // [hi/lo][block]
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int kc = 0; kc < BK; kc += 32) {
+        bf16x8 a[2][2], b[2][2];  // [hi/lo][block]
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              a[h][i][t] = As[buf][h][wm + 16 * i + li][kc + 8 * lq + t];
+              b[h][i][t] = Bs[buf][h][wn + 16 * i + li][kc + 8 * lq + t];
+            }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            a[h][i][t] = As[h][wm + 16 * i + li][8 * lq + t];
-            b[h][i][t] = Bs[h][wn + 16 * i + li][8 * lq + t];
+          for (int j = 0; j < 2; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
           }
+      }
+    } else if constexpr (DB) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int kb = 0; kb < BK; kb += 16) {
+        f32x4 a[2], b[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
-        }
+        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const f32x4*>(&As[buf][0][wm + 16 * i + li][kb + 4 * lq]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const f32x4*>(&Bs[buf][0][wn + 16 * j + li][kb + 4 * lq]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
+      }
     } else {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
         float a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = As[0][wm + 16 * i + li][kk + lq];
+        for (int i = 0; i < 2; ++i) a[i] = As[buf][0][wm + 16 * i + li][kk + lq];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = Bs[0][wn + 16 * j + li][kk + lq];
+        for (int j = 0; j < 2; ++j) b[j] = Bs[buf][0][wn + 16 * j + li][kk + lq];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -308,7 +338,31 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
       }
     }
+  };
+  if constexpr (DB) {
+    if (kr.beg < kr.end) {
+      load(kr.beg);
+      stage(0);
+    }
     __syncthreads();
+    int buf = 0;
+    for (int k0 = kr.beg; k0 < kr.end; k0 += BK) {  // block-uniform trip count
+      const bool more = k0 + BK < kr.end;
+      if (more) load(k0 + BK);
+      compute(buf);
+      if (more) stage(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  } else {
+    if (kr.beg < kr.end) load(kr.beg);
+    for (int k0 = kr.beg; k0 < kr.end; k0 += BK) {
+      stage(0);
+      __syncthreads();
+      if (k0 + BK < kr.end) load(k0 + BK);
+      compute(0);
+      __syncthreads();
+    }
   }
   // accumulator layout: lane holds rows 4*(lane/16)+r, column lane%16 of each block
   if (to_part(d)) {
@@ -399,7 +453,8 @@ std::string tc_kernel_name(const TcDesc& d, Prec p) {
   if (p != Prec::F64) {
     const char* ak = unit(d.ak) ? "true" : "false";
     const char* bn = unit(d.bn) ? "true" : "false";
-    return std::string("tc_mfma_kernel<") + (p == Prec::BF16 ? "true" : "false") + ", " + ak + ", " + bn + ">";
+    const char* var = d.tile == 2 ? ", 64, true>" : d.tile == 1 ? ", 32, true>" : ", 32, false>";
+    return std::string("tc_mfma_kernel<") + (p == Prec::BF16 ? "true" : "false") + ", " + ak + ", " + bn + var;
   }
   const Tile t = tile_of(d, p);
   return "tc_f64_kernel<" + std::to_string(t.bm) + ", " + std::to_string(t.bn) + ">";
@@ -463,9 +518,16 @@ void tc_launch(const TcDesc& d, Prec p, hipStream_t s) {
     else
       hipLaunchKernelGGL((tc_f64_kernel<32, 32>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
   } else {
+    const int v = d.tile;  // MFMA pipeline: 0 one LDS tile of 32, 1 double-buffered 32, 2 double-buffered 64
 #define QTT_TC_MFMA(BF, AK, BN)                                                          \
-  if ((p == Prec::BF16) == BF && (a_kfast != 0) == AK && (b_nfast != 0) == BN)            \
-    hipLaunchKernelGGL((tc_mfma_kernel<BF, AK, BN>), grid, dim3(256), 0, s, d);
+  if ((p == Prec::BF16) == BF && (a_kfast != 0) == AK && (b_nfast != 0) == BN) {          \
+    if (v == 2)                                                                           \
+      hipLaunchKernelGGL((tc_mfma_kernel<BF, AK, BN, 64, true>), grid, dim3(256), 0, s, d); \
+    else if (v == 1)                                                                      \
+      hipLaunchKernelGGL((tc_mfma_kernel<BF, AK, BN, 32, true>), grid, dim3(256), 0, s, d); \
+    else                                                                                  \
+      hipLaunchKernelGGL((tc_mfma_kernel<BF, AK, BN, 32, false>), grid, dim3(256), 0, s, d); \
+  }
     QTT_TC_MFMA(true, true, true)
     QTT_TC_MFMA(true, true, false)
     QTT_TC_MFMA(true, false, true)
@@ -522,7 +584,7 @@ std::pair<int, int> measure(const TcDesc& d, Prec p) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!g_tune_stream) QTT_HIP(hipStreamCreateWithFlags(&g_tune_stream, hipStreamNonBlocking));
   hipStream_t s = g_tune_stream;
-  std::vector<int> tiles{0};
+  std::vector<int> tiles{0, 1, 2};  // MFMA pipelines
   if (p == Prec::F64) {
     tiles = {4};
     if (d.N > 32) tiles.push_back(3);
@@ -589,20 +651,34 @@ std::pair<int, int> measure(const TcDesc& d, Prec p) {
 
 }  // namespace
 
+namespace {
+// QTTPDF_MFMA_PIPELINE=0|1|2 forces one MFMA pipeline for every launch
+// recorded from then on (read at each call, so tests can cover each one)
+int forced_pipeline() {
+  const char* e = std::getenv("QTTPDF_MFMA_PIPELINE");
+  if (!e || e[0] < '0' || e[0] > '2' || e[1] != 0) return -1;
+  return e[0] - '0';
+}
+}  // namespace
+
 bool tc_configure(TcDesc& d, Prec p, bool measure_ok) {
   d.tile = 0;
   d.ksplit = tc_choose_ksplit(d, p);
-  if (!autotune_on() || d.M <= 0 || d.N <= 0 || d.batch <= 0 || d.K <= 0) return false;
-  const TuneKey k = key_of(d, p);
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tuned.find(k);
-  if (it == g_tuned.end()) {
-    if (!measure_ok) return false;
-    it = g_tuned.emplace(k, measure(d, p)).first;
+  const int fp = p == Prec::F64 ? -1 : forced_pipeline();
+  bool measured = false;
+  if (autotune_on() && d.M > 0 && d.N > 0 && d.batch > 0 && d.K > 0) {
+    const TuneKey k = key_of(d, p);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(k);
+    if (it == g_tuned.end() && measure_ok) it = g_tuned.emplace(k, measure(d, p)).first;
+    if (it != g_tuned.end()) {
+      d.tile = it->second.first;
+      d.ksplit = it->second.second;
+      measured = true;
+    }
   }
-  d.tile = it->second.first;
-  d.ksplit = it->second.second;
-  return true;
+  if (fp >= 0) d.tile = fp;
+  return measured;
 }
 
 void tc_autotune_stats(int* shapes, double* seconds) {

@@ -49,13 +49,17 @@ def test_round_rel_tol_and_info_match_oracle(ctx, chi, rel_tol):
     assert abs(info["discarded_weight"] - sum(info_o["discarded"])) <= 1e-12 * s1
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", 1e-14), ("f32", 2e-7), ("bf16", 1e-4)])
-def test_apply_mpo_precision(ctx, dtype, tol):
+@pytest.mark.parametrize("dtype,tol,pipeline", [("f64", 1e-14, None)] + [
+    (d, t, pl) for d, t in (("f32", 2e-7), ("bf16", 1e-4)) for pl in (None, "0", "1", "2")])
+def test_apply_mpo_precision(ctx, monkeypatch, dtype, tol, pipeline):
     """Explicit MPO x MPS product with FP64 products, FP32-rounded operands
     (relative 2^-24 per operand: a product errs by at most 2^-23 of its size,
     and the two products of an entry add at most that again), or BF16 high
     and low parts (2^-16 per product): entries against the FP64 dense
-    product, relative to the largest entry."""
+    product, relative to the largest entry.  pipeline: every MFMA launch
+    forced onto one of the three pipelines (None: the measured choice)."""
+    if pipeline is not None:
+        monkeypatch.setenv("QTTPDF_MFMA_PIPELINE", pipeline)
     Wc = cases.random_mpo(8, 3, 91)
     xc = random_tt([1, 2, 4, 8, 8, 8, 4, 2, 1], 92)
     W = q.TT.from_cores(ctx, Wc, kind=q.TT_MPO)

@@ -55,20 +55,34 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", TRUNC_TOL_F64), ("f32", 3e-5), ("bf16", 1e-2)])
-def test_full_size_step_matches_oracle(ctx, oracle_step, dtype, tol):
+def _check_step(ctx, oracle_step, dtype, tol, label=""):
     w, fo, obs_o = oracle_step
     prob, f = q.setup_workload(ctx, w, dtype)
     prob.step(f, 1)
     fg = [np.asarray(G, dtype=np.float64) for G in f.cores()]
     assert len(fg) == len(fo) == w.n_sites
     err = _diff_norm(fg, fo) / _norm(fo)
-    print(f"{NAME} {dtype}: relative L2 difference {err:.3e} (tol {tol:.1e})", flush=True)
+    print(f"{NAME} {dtype}{label}: relative L2 difference {err:.3e} (tol {tol:.1e})", flush=True)
     assert err < tol, (dtype, err, tol)
     for k, v in obs_o.items():
         g = prob.observable(f, k)
         assert abs(g - v) <= tol * max(1.0, abs(v)), (k, g, v)
     prob.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", TRUNC_TOL_F64), ("f32", 3e-5), ("bf16", 1e-2)])
+def test_full_size_step_matches_oracle(ctx, oracle_step, dtype, tol):
+    _check_step(ctx, oracle_step, dtype, tol)
+
+
+@pytest.mark.parametrize("pipeline", ["0", "1", "2"])
+@pytest.mark.parametrize("dtype,tol", [("f32", 3e-5), ("bf16", 1e-2)])
+def test_full_size_step_each_mfma_pipeline(ctx, oracle_step, monkeypatch, pipeline, dtype, tol):
+    """The same step with every MFMA launch forced onto one pipeline (K tile
+    32 with one LDS buffer; K tile 32 or 64 with two), at the tolerances
+    above: the measured choice per shape may take any of them."""
+    monkeypatch.setenv("QTTPDF_MFMA_PIPELINE", pipeline)
+    _check_step(ctx, oracle_step, dtype, tol, f" pipeline {pipeline}")
 
 
 @pytest.fixture(scope="module")
