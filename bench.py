@@ -187,9 +187,10 @@ def _kernel_probe(spec):
 
 def _bench_batched(args, log):
     """The batched ensemble (64 uneven 5-D problems, FP32-MFMA contractions):
-    instance-steps/s of the instances stepped together (one call per step,
-    their step graphs on parallel branches), next to the same instances
-    stepped one after another."""
+    instance-steps/s of the instances stepped together (one call per step;
+    instances of equal structure fused into shared launches, the units on
+    parallel branches), next to the same instances stepped one after
+    another."""
     import torch
     import paper_2407_09169_amd as q
     import workloads
@@ -198,7 +199,8 @@ def _bench_batched(args, log):
     t0 = time.perf_counter()
     inst = [q.setup_workload(ctx, w, args.dtype) for w in ws]
     b = q.Batch(ctx, [p for p, _ in inst], [f for _, f in inst])
-    log(f"batch of {len(ws)} set up in {time.perf_counter() - t0:.1f} s; warmup {args.warmup}")
+    binfo = b.info()
+    log(f"batch of {len(ws)} set up in {time.perf_counter() - t0:.1f} s ({binfo}); warmup {args.warmup}")
     b.step(args.warmup)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -235,6 +237,7 @@ def _bench_batched(args, log):
                    "total_cores": sum(w.n_sites for w in ws), "integrator": "rk4"},
         "sequential_instance_steps_per_s": seq,
         "batching_speedup": value / seq,
+        "batch": binfo,
         "mass_range": [min(masses), max(masses)],
     }
     print(json.dumps(out))

@@ -334,19 +334,38 @@ tt_status tt_step(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps);
  * ------------------------------------------------------------------------ */
 /* Prepares `count` problems, each with its own state (states[i] from
  * tt_problem_state(probs[i]); problems and states must be distinct), to be
- * stepped together.  Every instance keeps its own step graph, recorded as
- * tt_step records it.  The instances are spread over a few parallel branches
- * (streams; 8, or the environment variable QTTPDF_BATCH_BRANCHES), each a
- * chain of whole instance steps: an instance joins the branch with the least
- * estimated work (sum of cap^3 over its bonds), largest first.  The handles
- * stay owned by the caller and must outlive the batch; an instance must not
- * be stepped by other calls while the batch is in use.  Results are bitwise
- * those of tt_step on each instance alone. */
+ * stepped together.
+ *
+ * 5-D instances of equal structure (grid, bond caps, operator bonds, form of
+ * the mean-field product, precision and scheme; the coefficients Omega, k,
+ * dt and the seeded data may differ) form a fused class: the library copies
+ * each one's operator, sketches and workspaces into a slab of device memory
+ * of its own (slabs equally spaced, instance buffers at equal offsets),
+ * records the step once and captures it as one HIP graph whose every launch
+ * runs for all the instances of the class.  Other instances (and classes of
+ * one) keep their own step graphs, recorded as tt_step records them.  The
+ * units (classes and single instances) are spread over a few parallel
+ * branches (streams; 8, or the environment variable QTTPDF_BATCH_BRANCHES),
+ * each a chain of whole steps: a unit joins the branch with the least
+ * estimated work, largest first.  QTTPDF_BATCH_FUSE=0 forms no classes.
+ *
+ * The handles stay owned by the caller and must outlive the batch; an
+ * instance must not be stepped by other calls while the batch is in use.
+ * The slabs hold a second copy of every fused instance's step buffers (the
+ * batch frees them).  Results are bitwise those of tt_step on each instance
+ * alone; tt_step_info of a problem does not cover batched steps. */
 tt_status tt_batch_create(tt_ctx* ctx, int count, tt_problem* const* probs, tt_tt* const* states,
                           tt_batch** out);
-/* Advances every instance of the batch by n_steps steps: per step, the
- * branches fork from the context's stream, launch their instances' step
- * graphs in order, and join back (asynchronous to the host). */
+/* Composition of a batch: units of work (fused classes plus single
+ * instances), fused classes, instances in fused classes, and the device
+ * bytes of the slabs.  Any output pointer may be NULL. */
+tt_status tt_batch_info(const tt_batch* batch, int* n_units, int* n_fused_classes, int* n_fused_instances,
+                        int64_t* slab_bytes);
+/* Advances every instance of the batch by n_steps steps: the fused
+ * instances' states are copied into their slabs, then per step the branches
+ * fork from the context's stream, launch their units' step graphs in order,
+ * and join back; at the end the states are copied back (all asynchronous to
+ * the host, on the context's stream). */
 tt_status tt_step_batched(tt_batch* batch, int n_steps);
 tt_status tt_batch_destroy(tt_batch* batch);
 

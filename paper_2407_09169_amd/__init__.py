@@ -35,7 +35,7 @@ EXPORTS = [
     "mps_round_sketch_two_sided", "tt_l2_diff",
     "tt_inner", "tt_inner_noalloc", "tt_problem_create", "tt_problem_destroy", "tt_problem_info", "tt_problem_state",
     "tt_step", "tt_step_ex", "tt_profile", "tt_step_info", "tt_observable", "tt_mean_field",
-    "tt_linalg_qr", "tt_linalg_eigh", "tt_batch_create", "tt_step_batched", "tt_batch_destroy",
+    "tt_linalg_qr", "tt_linalg_eigh", "tt_batch_create", "tt_batch_info", "tt_step_batched", "tt_batch_destroy",
     "tt_step_tangent", "tt_moment_field", "tt_to_dense", "fd_smagorinsky", "fd_moment_steps",
     "fd_sq_diff_sum", "flow_error_measures", "tt_problem_create_flow", "tt_from_dense", "tt_prolong",
 ]
@@ -122,6 +122,7 @@ def lib():
         "tt_linalg_qr": [vp, i32, i32, i32, P(dbl), P(dbl), P(dbl)],
         "tt_linalg_eigh": [vp, i32, i32, i32, P(dbl), P(dbl), P(dbl)],
         "tt_batch_create": [vp, i32, P(vp), P(vp), P(vp)],
+        "tt_batch_info": [vp, P(i32), P(i32), P(i32), P(C.c_int64)],
         "tt_step_batched": [vp, i32],
         "tt_batch_destroy": [vp],
         "tt_step_tangent": [vp, vp, vp, i32, P(i32), P(vp), i32],
@@ -544,8 +545,9 @@ class Problem:
 
 
 class Batch:
-    """Many (problem, state) instances advanced together by one graph launch
-    per step (tt_batch_create / tt_step_batched)."""
+    """Many (problem, state) instances advanced together (tt_batch_create /
+    tt_step_batched): instances of equal structure share every launch of
+    their step (fused classes), the others step with their own graphs."""
 
     def __init__(self, ctx, problems, states):
         self.ctx = ctx
@@ -559,6 +561,14 @@ class Batch:
 
     def step(self, n_steps=1):
         _check(lib().tt_step_batched(self.h, n_steps))
+
+    def info(self):
+        """{"units", "fused_classes", "fused_instances", "slab_bytes"} (tt_batch_info)."""
+        u, c, fi = C.c_int32(), C.c_int32(), C.c_int32()
+        sb = C.c_int64()
+        _check(lib().tt_batch_info(self.h, C.byref(u), C.byref(c), C.byref(fi), C.byref(sb)))
+        return {"units": u.value, "fused_classes": c.value, "fused_instances": fi.value,
+                "slab_bytes": sb.value}
 
     def close(self):
         if getattr(self, "h", None):

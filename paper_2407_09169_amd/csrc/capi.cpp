@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <thread>
 
@@ -251,7 +252,10 @@ namespace qtt {
 
 // A stage-shaped MPO: the fixed part F stacked with the mean-field chain over
 // the phi sites (its first core scaled by mf_scale) whose x-site blocks,
-// diag(<Phi_a>) of a rounded mean field, are written when a step runs.
+// diag(<Phi_a>) of a rounded mean field, are written when a step runs.  The
+// time step dt is folded into the first core: the recorded step computes the
+// stage increments dt k_i, so no launch of it depends on dt (problems that
+// differ only in their coefficients record the same launches).
 static std::unique_ptr<tt_tt> assemble_stage_mpo(tt_problem* P, const host::TT& F, double mf_scale,
                                                  std::vector<int>& Dfix) {
   const int N = P->N;
@@ -266,12 +270,13 @@ static std::unique_ptr<tt_tt> assemble_stage_mpo(tt_problem* P, const host::TT& 
         for (int j = 0; j < B.rr; ++j)
           h[A->off[n] + ((int64_t)(ro + i) * 4 + s) * Dc[n + 1] + co + j] = sc * B.at(i, s, j);
   };
+  const double dt = P->p.dt;
   for (int n = 0; n < N; ++n) {
-    put(n, F[n], 0, 0, 1.0);
+    put(n, F[n], 0, 0, n == 0 ? dt : 1.0);
     if (n < P->nphi) {
       const int ro = (n == 0) ? 0 : Dfix[n];
       const int co = (n == N - 1) ? 0 : Dfix[n + 1];
-      put(n, P->MFh[n], ro, co, n == 0 ? mf_scale : 1.0);
+      put(n, P->MFh[n], ro, co, n == 0 ? mf_scale * dt : 1.0);
     }
   }
   rt::copy(A->buf.p, h.data(), h.size() * sizeof(double));
@@ -367,7 +372,10 @@ static void plan_mf_blocks(Plan& plan, tt_problem* P, tt_tt* mpo, const std::vec
   for (const CopyJob& j : jobs) validate(j);
   CopyJob* dj = plan.upload(jobs);
   const int nj = (int)jobs.size();
-  plan.add([=](hipStream_t s) { copy_jobs(dj, nj, maxe, s); });
+  plan.add([=](hipStream_t s) {
+    fuse_check(jobs);
+    copy_jobs(dj, nj, maxe, s);
+  });
 }
 
 // writes diag(mt[a]) into the x-site cores of the Hadamard-form term MF[a]
@@ -396,7 +404,10 @@ static void plan_mf_diag(Plan& plan, tt_problem* P, tt_tt* const mt[2]) {
   for (const CopyJob& j : jobs) validate(j);
   CopyJob* dj = plan.upload(jobs);
   const int nj = (int)jobs.size();
-  plan.add([=](hipStream_t s) { copy_jobs(dj, nj, maxe, s); });
+  plan.add([=](hipStream_t s) {
+    fuse_check(jobs);
+    copy_jobs(dj, nj, maxe, s);
+  });
 }
 
 // writes the mean-field part of the stage operator for the state
@@ -406,11 +417,11 @@ static void plan_stage_operator(Plan& plan, tt_problem* P, const tt_tt* f, const
                                 double cg, bool split = false) {
   const tt_params& p = P->p;
   if (P->nx == 0) {
-    // 2-D: scalars s_a = -Omega (m_a(f) + cg m_a(k)); first-core blocks scaled
+    // 2-D: scalars s_a = -Omega dt (m_a(f) + cg m_a(k)); first-core blocks scaled
     double* sc = P->scal.d();
     const double* ef = P->Ef.d();
     const double* ek = kprev ? P->Ek.d() : nullptr;
-    double om = p.omega;
+    const double om = p.omega * p.dt;
     plan.add([=](hipStream_t s) { scalar_comb(sc, ef, ek, cg, -om, 2, s); });
     std::vector<CopyJob> jobs;
     int64_t maxe = 1;
@@ -433,7 +444,10 @@ static void plan_stage_operator(Plan& plan, tt_problem* P, const tt_tt* f, const
     }
     for (const CopyJob& j : jobs) validate(j);
     CopyJob* dj = plan.upload(jobs);
-    plan.add([=](hipStream_t s) { copy_jobs(dj, 2, maxe, s); });
+    plan.add([=](hipStream_t s) {
+      fuse_check(jobs);
+      copy_jobs(dj, 2, maxe, s);
+    });
     return;
   }
   // 5-D: round the raw mean fields of g over the x sites, write diag blocks
@@ -465,6 +479,8 @@ struct Tangent {
 //   B_q = dA_fix/dq - sum_a D1g^(phi_a) diag(alpha_q <Phi_a>(g_i) + Omega <Phi_a>(dg_i)),
 // alpha_Omega = 1, alpha_k = 0 (the mean field enters A through -Omega m_a(g)),
 // and df+ = Round(df + sum_i b_i dk_i) beside f+ = Round(f + sum_i b_i k_i).
+// A and B_q carry dt, so k_i and dk_i are increments (dt times the slopes)
+// and c_i, b_i are the tableau's plain numbers.
 static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vector<Tangent>& tan) {
   auto plan = std::make_unique<Plan>();
   const tt_params& p = P->p;
@@ -474,8 +490,9 @@ static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vec
   ChainView Av = view(P->A.get());
   const bool rk4 = (p.integrator == TT_RK4);
   const int S = rk4 ? 4 : 2;
-  const double dt = p.dt;
-  const double cst[4] = {0.0, rk4 ? 0.5 * dt : dt, 0.5 * dt, dt};
+  // the stage operators carry dt (assemble_stage_mpo): k_i below is the stage
+  // increment dt times the slope, g_i = f + c_i k_(i-1), f+ = f + sum_i b_i k_i
+  const double cst[4] = {0.0, rk4 ? 0.5 : 1.0, 0.5, 1.0};
   std::vector<ChainView> Bv;
   for (const Tangent& t : tan) Bv.push_back(view(P->Bt[t.q].get()));
   auto sterm = [](double c, const ChainView* W, const tt_tt* x) {
@@ -545,7 +562,7 @@ static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vec
       plan_check_finite(*plan, P->dk[q][i].get(), P->nonfinite.as<int>());
     }
   }
-  const double b4[4] = {dt / 6, dt / 3, dt / 3, dt / 6}, b2[2] = {0.5 * dt, 0.5 * dt};
+  const double b4[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6}, b2[2] = {0.5, 0.5};
   const double* b = rk4 ? b4 : b2;
   // The final combination is dominated by f itself, whose every digit the
   // next step inherits: its sketches run in the data precision (FP32 when
@@ -1189,9 +1206,11 @@ tt_status tt_problem_create_flow(tt_ctx* ctx, const tt_params* pp, const tt_tt* 
       else if (e && std::strcmp(e, "block") == 0) P->split_mf = false;
       else P->split_mf = (dense(dfx + 2 * cm) - dense(dfx) - 2 * diag(cm)) / 2e13 > 6 * 1e-5;
       if (P->split_mf) {
-        P->F = upload(ctx, TT_MPO, Fx, exact_caps(Fx));
+        host::TT Fdt = Fx;
+        for (double& v : Fdt[0].v) v *= p.dt;
+        P->F = upload(ctx, TT_MPO, Fdt, exact_caps(Fdt));
         P->Fv = view(P->F.get());
-        const double sc = P->has_Om ? -1.0 : -p.omega;
+        const double sc = (P->has_Om ? -1.0 : -p.omega) * p.dt;
         for (int a = 0; a < 2; ++a) {
           host::TT W = T[a];
           for (double& v : W[0].v) v *= sc;
@@ -1434,11 +1453,165 @@ static int batch_branches() {
   return v >= 1 ? v : 8;
 }
 
+// fusing instances of the same structure into shared launches:
+// QTTPDF_BATCH_FUSE=0 turns it off
+static bool batch_fuse() {
+  const char* e = std::getenv("QTTPDF_BATCH_FUSE");
+  return !(e && e[0] == '0');
+}
+
+namespace qtt {
+
+// device buffers of a problem that its plain step reads or writes, in a
+// fixed order: (pointer, bytes); absent members are (null, 0)
+static std::vector<std::pair<void*, size_t>> step_buffers(const tt_problem* P) {
+  std::vector<std::pair<void*, size_t>> v;
+  auto t = [&](const std::unique_ptr<tt_tt>& x) {
+    v.push_back(x ? std::make_pair(x->buf.p, x->buf.bytes) : std::make_pair((void*)nullptr, (size_t)0));
+  };
+  auto d = [&](const DevBuf& b) { v.push_back({b.p, b.bytes}); };
+  t(P->Z), t(P->Zl), t(P->Zm), t(P->Zml), t(P->A), t(P->Wm), t(P->Wom), t(P->F), t(P->MF[0]), t(P->MF[1]);
+  for (int i = 0; i < 4; ++i) t(P->k[i]);
+  t(P->mt[0]), t(P->mt[1]);
+  d(P->mf_first), d(P->Ef), d(P->Ek), d(P->mff), d(P->mfk), d(P->scal), d(P->nonfinite);
+  return v;
+}
+
+// a chain with the shape of t and fresh (uninitialised) storage
+static std::unique_ptr<tt_tt> clone_shape(const tt_tt* t) {
+  if (!t) return nullptr;
+  auto c = std::make_unique<tt_tt>();
+  c->ctx = t->ctx;
+  c->kind = t->kind;
+  c->N = t->N;
+  c->p = t->p;
+  c->caps = t->caps;
+  c->off = t->off;
+  c->buf.alloc(t->buf.bytes);
+  return c;
+}
+
+// a problem with P's structure and fresh buffers for its plain step (the
+// contents are copied in afterwards), allocated in a fixed order
+static std::unique_ptr<tt_problem> clone_problem(const tt_problem* P) {
+  auto C = std::make_unique<tt_problem>();
+  C->ctx = P->ctx;
+  C->p = P->p;
+  C->N = P->N;
+  C->nphi = P->nphi;
+  C->nx = P->nx;
+  C->fcaps = P->fcaps;
+  C->mcaps = P->mcaps;
+  C->Dfix = P->Dfix;
+  C->has_G = P->has_G;
+  C->has_Om = P->has_Om;
+  C->mf_first_off = P->mf_first_off;
+  C->mf_first_cols = P->mf_first_cols;
+  C->mf_first_ld = P->mf_first_ld;
+  C->split_mf = P->split_mf;
+  C->cphi = P->cphi;
+  C->cphi1 = P->cphi1;
+  C->MFh = P->MFh;
+  C->Dmf = P->Dmf;
+  C->Z = clone_shape(P->Z.get());
+  C->Zl = clone_shape(P->Zl.get());
+  C->Zm = clone_shape(P->Zm.get());
+  C->Zml = clone_shape(P->Zml.get());
+  C->A = clone_shape(P->A.get());
+  C->Wm = clone_shape(P->Wm.get());
+  C->Wom = clone_shape(P->Wom.get());
+  C->F = clone_shape(P->F.get());
+  for (int a = 0; a < 2; ++a) C->MF[a] = clone_shape(P->MF[a].get());
+  for (int i = 0; i < 4; ++i) C->k[i] = clone_shape(P->k[i].get());
+  for (int a = 0; a < 2; ++a) C->mt[a] = clone_shape(P->mt[a].get());
+  auto cl = [](DevBuf& dst, const DevBuf& src) {
+    if (src.p) dst.alloc(src.bytes);
+  };
+  cl(C->mf_first, P->mf_first), cl(C->Ef, P->Ef), cl(C->Ek, P->Ek), cl(C->mff, P->mff), cl(C->mfk, P->mfk);
+  cl(C->scal, P->scal), cl(C->nonfinite, P->nonfinite);
+  if (C->Wom) C->Womv = view(C->Wom.get());
+  if (C->F) C->Fv = view(C->F.get());
+  for (int a = 0; a < 2; ++a)
+    if (C->MF[a]) C->MFv[a] = view(C->MF[a].get());
+  return C;
+}
+
+// Instances whose recorded steps are the same launches on different data:
+// equal structure (grid, caps, operator bonds, forms, precision, scheme).
+// The coefficients live in the data (the stage operators carry dt), so
+// problems that differ in them share a key.
+static std::string structure_key(const tt_problem* P) {
+  std::string k;
+  auto add = [&](long v) { k += std::to_string(v) + ","; };
+  auto vec = [&](const std::vector<int>& v) {
+    add((long)v.size());
+    for (int x : v) add(x);
+    k += ";";
+  };
+  const tt_params& p = P->p;
+  add(p.ndims), add(p.bits), add(p.ordering), add(p.chi), add(p.ell), add(p.chi_mean), add(p.ell_mean);
+  add(p.integrator), add(p.dtype), add(P->split_mf), add(P->has_G), add(P->has_Om);
+  vec(P->fcaps), vec(P->mcaps), vec(P->Dfix);
+  for (const auto& [ptr, bytes] : step_buffers(P)) add(ptr ? (long)bytes : -1L);
+  for (const tt_tt* t : {P->A.get(), P->F.get(), P->MF[0].get(), P->MF[1].get(), P->Wom.get(), P->Wm.get()})
+    if (t) vec(t->caps);
+  return k;
+}
+
+}  // namespace qtt
+
+// Instances of one structure stepped by shared launches: every instance's
+// buffers lie at the same offsets in its slab (slab i at slab + i * stride);
+// the step is recorded once, for slab 0, and every launch of it runs for all
+// the instances (rt::Fuse).
+struct FusedClass {
+  std::vector<int> members;  // instance indices
+  DevBuf slab;
+  char* base = nullptr;      // slab 0, 256-byte aligned
+  int64_t stride = 0;        // bytes
+  std::unique_ptr<tt_problem> P0;
+  std::unique_ptr<tt_tt> f0;
+  std::unique_ptr<Plan> plan;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  FusedClass() = default;
+  FusedClass(const FusedClass&) = delete;
+  FusedClass& operator=(const FusedClass&) = delete;
+  ~FusedClass() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    plan.reset();  // before the slab they live in
+    f0.reset();
+    P0.reset();
+  }
+  rt::Fuse fuse() const {
+    rt::Fuse f;
+    f.n = (int)members.size();
+    f.stride = stride;
+    f.lo = (uintptr_t)base;
+    f.hi = (uintptr_t)base + (uintptr_t)stride;
+    return f;
+  }
+};
+
+// sets this thread's fused-launch setting for a scope
+struct FuseScope {
+  explicit FuseScope(const rt::Fuse& f) { rt::fuse() = f; }
+  ~FuseScope() { rt::fuse() = rt::Fuse{}; }
+};
+
 struct tt_batch {
   tt_ctx* ctx = nullptr;
   std::vector<tt_problem*> probs;
   std::vector<tt_tt*> states;
-  std::vector<std::vector<int>> chain;  // instances of each branch, in order
+  // units of work: a single instance (its own step graph) or a fused class
+  struct Unit {
+    int inst = -1;
+    int cls = -1;
+  };
+  std::vector<Unit> units;
+  std::vector<std::unique_ptr<FusedClass>> classes;
+  std::vector<std::vector<int>> chain;  // units of each branch, in order
   std::vector<hipStream_t> streams;     // one per branch
   std::vector<hipEvent_t> events;       // fork + one join per branch
   ~tt_batch() {
@@ -1446,6 +1619,107 @@ struct tt_batch {
     for (auto st : streams) (void)hipStreamDestroy(st);
   }
 };
+
+namespace qtt {
+
+// Records and captures the fused step of the instances `members` (equal
+// structure keys): the slab stride is measured by recording once with
+// ordinary allocations, then the clone of the first instance is built in
+// slab 0 and recorded again (the contraction shapes are tuned by then, so
+// the second recording allocates the same sequence), and every instance's
+// inputs are copied to its slab.
+static std::unique_ptr<FusedClass> build_fused_class(tt_batch* b, const std::vector<int>& members) {
+  auto C = std::make_unique<FusedClass>();
+  C->members = members;
+  const tt_problem* P = b->probs[members[0]];
+  const tt_tt* f = b->states[members[0]];
+  size_t bytes = 0;
+  {
+    rt::alloc_count_reset();
+    auto Pc = clone_problem(P);
+    auto fc = clone_shape(f);
+    auto plan = record_step(Pc.get(), fc.get(), {});
+    bytes = rt::alloc_count();
+  }
+  const size_t align = size_t(1) << 16;
+  C->stride = (int64_t)((bytes + align - 1) / align * align);
+  C->slab.alloc((size_t)C->stride * members.size() + 256);
+  C->base = reinterpret_cast<char*>(((uintptr_t)C->slab.p + 255) & ~uintptr_t(255));
+  {
+    rt::SlabScope scope(C->base, (size_t)C->stride);
+    C->P0 = clone_problem(P);
+    C->f0 = clone_shape(f);
+    C->plan = record_step(C->P0.get(), C->f0.get(), {});
+  }
+  // what the recording wrote into slab 0 (tables, and constants such as the
+  // ones of the mean-field chains, which fused launches read per instance)
+  for (const auto& [ptr, n] : C->plan->uploads)
+    for (size_t i = 1; i < members.size(); ++i) rt::copy(ishift(ptr, (int64_t)i * C->stride), ptr, n);
+  const auto dst0 = step_buffers(C->P0.get());
+  for (size_t i = 0; i < members.size(); ++i) {
+    const auto src = step_buffers(b->probs[members[i]]);
+    QTT_REQUIRE(src.size() == dst0.size(), "fused batch: buffer lists differ");
+    for (size_t j = 0; j < src.size(); ++j) {
+      QTT_REQUIRE(src[j].second == dst0[j].second, "fused batch: instance %d buffer %zu differs in size",
+                  members[i], j);
+      if (src[j].first) rt::copy(ishift(dst0[j].first, (int64_t)i * C->stride), src[j].first, src[j].second);
+    }
+  }
+  if (rt::dry() || !use_graph()) return C;
+  StreamScope sc(b->ctx);
+  hipStream_t s = b->ctx->stream;
+  FuseScope fs(C->fuse());
+  QTT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  try {
+    C->plan->run(s);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(s, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  QTT_HIP(hipStreamEndCapture(s, &C->graph));
+  QTT_HIP(hipGraphInstantiate(&C->exec, C->graph, nullptr, nullptr, 0));
+  return C;
+}
+
+// drops a problem's recorded plain step (plan, graph and their buffers)
+static void release_step_plan(tt_problem* P) {
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  P->exec = nullptr;
+  P->graph = nullptr;
+  if (P->plan) rt::sync(P->ctx->stream);
+  P->plan.reset();
+  P->plan_f = nullptr;
+  P->last_plain = RoundTarget{};
+  P->last = P->tplan ? P->last_tan : RoundTarget{};
+}
+
+// one step of a fused class on stream s
+static void launch_fused(FusedClass& C, hipStream_t s) {
+  if (C.exec) {
+    QTT_HIP(hipGraphLaunch(C.exec, s));
+  } else {
+    FuseScope fs(C.fuse());
+    C.plan->run(s);
+  }
+}
+
+// the instances' states into (in) or out of their slabs
+static void fused_states(tt_batch* b, bool in, hipStream_t s) {
+  for (auto& C : b->classes) {
+    const size_t bytes = (size_t)C->f0->total() * sizeof(double);
+    for (size_t i = 0; i < C->members.size(); ++i) {
+      double* slab_f = ishift(C->f0->buf.d(), (int64_t)i * C->stride);
+      double* user_f = b->states[C->members[i]]->buf.d();
+      if (in) rt::copy_async(slab_f, user_f, bytes, s);
+      else rt::copy_async(user_f, slab_f, bytes, s);
+    }
+  }
+}
+
+}  // namespace qtt
 
 extern "C" {
 
@@ -1467,19 +1741,47 @@ tt_status tt_batch_create(tt_ctx* ctx, int count, tt_problem* const* probs, tt_t
       b->probs.push_back(P);
       b->states.push_back(f);
     }
-    // every instance keeps its own step graph (with its lanes), as tt_step
-    // records it
-    for (int i = 0; i < count; ++i) ensure_step_graph(b->probs[i], b->states[i]);
-    // Instances run on a few parallel branches (streams), each a chain of
-    // whole instance steps; an instance joins the branch with the least
-    // estimated work so far, largest first (work ~ sum of cap^3 over the
-    // bonds).
-    const int nb = std::min(count, batch_branches());
-    std::vector<double> cost(count, 0.0);
-    for (int i = 0; i < count; ++i)
-      for (int c : b->probs[i]->fcaps) cost[i] += (double)c * c * c;
-    std::vector<int> order(count);
-    for (int i = 0; i < count; ++i) order[i] = i;
+    // 5-D instances of equal structure form fused classes; the rest (and
+    // classes of one) step with their own graphs, as tt_step records them
+    std::map<std::string, std::vector<int>> groups;
+    std::vector<std::string> key_order;
+    for (int i = 0; i < count; ++i) {
+      const bool fusable = batch_fuse() && b->probs[i]->nx > 0;
+      const std::string k = fusable ? structure_key(b->probs[i]) : "single" + std::to_string(i);
+      if (!groups.count(k)) key_order.push_back(k);
+      groups[k].push_back(i);
+    }
+    std::vector<double> cost;
+    auto inst_cost = [&](int i) {
+      double c = 0.0;
+      for (int x : b->probs[i]->fcaps) c += (double)x * x * x;
+      return c;
+    };
+    for (const std::string& k : key_order) {
+      const std::vector<int>& m = groups[k];
+      tt_batch::Unit u;
+      if (m.size() == 1) {
+        u.inst = m[0];
+        ensure_step_graph(b->probs[m[0]], b->states[m[0]]);
+        cost.push_back(inst_cost(m[0]));
+      } else {
+        u.cls = (int)b->classes.size();
+        b->classes.push_back(build_fused_class(b.get(), m));
+        // the members' own step plans are not needed by the batch: their
+        // memory goes back (tt_step records them again when called)
+        for (int i : m) release_step_plan(b->probs[i]);
+        // a fused launch runs the instances side by side: about one instance's time
+        cost.push_back(inst_cost(m[0]) * (1.0 + 0.25 * (m.size() - 1)));
+      }
+      b->units.push_back(u);
+    }
+    // Units run on a few parallel branches (streams), each a chain of whole
+    // steps; a unit joins the branch with the least estimated work so far,
+    // largest first (work ~ sum of cap^3 over the bonds).
+    const int nu = (int)b->units.size();
+    const int nb = std::min(nu, batch_branches());
+    std::vector<int> order(nu);
+    for (int i = 0; i < nu; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
     b->chain.assign(nb, {});
     std::vector<double> load(nb, 0.0);
@@ -1498,6 +1800,23 @@ tt_status tt_batch_create(tt_ctx* ctx, int count, tt_problem* const* probs, tt_t
   });
 }
 
+tt_status tt_batch_info(const tt_batch* b, int* n_units, int* n_fused_classes, int* n_fused_instances,
+                        int64_t* slab_bytes) {
+  return guard([&] {
+    QTT_REQUIRE(b, "null batch");
+    int fi = 0;
+    int64_t sb = 0;
+    for (const auto& C : b->classes) {
+      fi += (int)C->members.size();
+      sb += C->stride * (int64_t)C->members.size();
+    }
+    if (n_units) *n_units = (int)b->units.size();
+    if (n_fused_classes) *n_fused_classes = (int)b->classes.size();
+    if (n_fused_instances) *n_fused_instances = fi;
+    if (slab_bytes) *slab_bytes = sb;
+  });
+}
+
 tt_status tt_step_batched(tt_batch* b, int n_steps) {
   return guard([&] {
     QTT_REQUIRE(b && n_steps >= 0, "bad argument");
@@ -1510,10 +1829,16 @@ tt_status tt_step_batched(tt_batch* b, int n_steps) {
       const char* e = std::getenv("QTTPDF_BATCH_THREADS");
       return e && e[0] == '1';
     }();
+    auto run_unit = [&](int u, hipStream_t s) {
+      const tt_batch::Unit& un = b->units[u];
+      if (un.cls >= 0) launch_fused(*b->classes[un.cls], s);
+      else launch_step(b->probs[un.inst], s);
+    };
+    if (n_steps > 0) fused_states(b, true, s0);
     for (int step = 0; step < n_steps; ++step) {
       if (rt::dry()) {
         for (auto& ch : b->chain)
-          for (int i : ch) launch_step(b->probs[i], s0);
+          for (int u : ch) run_unit(u, s0);
         continue;
       }
       // fork from the context's stream, one chain per branch, join back
@@ -1521,7 +1846,7 @@ tt_status tt_step_batched(tt_batch* b, int n_steps) {
       const int nb = (int)b->chain.size();
       auto branch = [&](int k) {
         QTT_HIP(hipStreamWaitEvent(b->streams[k], b->events[0], 0));
-        for (int i : b->chain[k]) launch_step(b->probs[i], b->streams[k]);
+        for (int u : b->chain[k]) run_unit(u, b->streams[k]);
         QTT_HIP(hipEventRecord(b->events[k + 1], b->streams[k]));
       };
       if (threaded && nb > 1) {
@@ -1545,6 +1870,7 @@ tt_status tt_step_batched(tt_batch* b, int n_steps) {
       }
       for (int k = 0; k < nb; ++k) QTT_HIP(hipStreamWaitEvent(s0, b->events[k + 1], 0));
     }
+    if (n_steps > 0) fused_states(b, false, s0);
   });
 }
 

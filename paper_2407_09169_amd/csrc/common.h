@@ -83,9 +83,46 @@ void check_range(const void* p, int64_t lo, int64_t hi, size_t esize, const char
 void register_range(const void* p, size_t bytes);
 void unregister_range(const void* p);
 void copy(void* dst, const void* src, size_t bytes);  // synchronous, any direction
+// asynchronous copy; while launches are fused (below), one copy per instance
 void copy_async(void* dst, const void* src, size_t bytes, hipStream_t s);
 void sync(hipStream_t s);
+
+// Fused launches over identically laid-out instances (batched stepping).
+// Every buffer of instance i lies at the same offset in slab i as instance
+// 0's in slab 0; the slabs are `stride` bytes apart and slab 0 is [lo, hi).
+// While n > 1 on the calling thread, the launch wrappers that support it run
+// each launch for the n instances at once (the kernels shift every data
+// pointer, given or read from a device table, by instance * stride; device
+// tables of sizes and pointers are read unshifted, from slab 0), and the
+// others refuse.
+struct Fuse {
+  int n = 1;
+  int64_t stride = 0;
+  uintptr_t lo = 0, hi = 0;
+};
+Fuse& fuse();  // this thread's setting
+// with fusing on: throws unless [p, p + bytes) lies inside slab 0
+void fuse_check(const void* p, size_t bytes, const char* what);
+// throws when fusing is on (launches without instance support)
+void fuse_refuse(const char* what);
+// allocation from a slab instead of the device allocator while a slab scope
+// is active on this thread: bump allocation, 256-byte aligned, no free
+struct SlabScope {
+  SlabScope(void* base, size_t cap);
+  ~SlabScope();
+  size_t used() const;
+};
+// bytes handed out by dev_alloc on this thread since the last reset (with
+// the 256-byte rounding a slab applies)
+void alloc_count_reset();
+size_t alloc_count();
 }  // namespace rt
+
+// pointer shifted by a byte offset (null stays null)
+template <class T>
+__host__ __device__ inline T* ishift(T* p, int64_t bytes) {
+  return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)bytes) : p;
+}
 
 // ---------------------------------------------------------------------------
 // device buffers
@@ -212,6 +249,8 @@ struct TcDesc {
   int32_t ksplit = 1;
   double* part = nullptr;
   int32_t ng = 1, gsum = 0;
+  int32_t ninst = 1;    // fused instances (grid z = batch * groups * K chunks * ninst)
+  int64_t istride = 0;  // bytes between the instances' data
   int32_t tile = 0;  // FP64 tile: 0 by size, 1 64x64, 2 64x32, 3 32x64, 4 32x32; MFMA pipeline: 0 K tile 32,
                      // 1 K tile 32 double-buffered, 2 K tile 64 double-buffered
   const double* gA[TC_MAXG] = {};

@@ -36,6 +36,9 @@ void scalar_comb(double* out, const double* a, const double* b, double cb, doubl
 void validate(const CopyJob& j);
 void validate(const ApplyJob& j);
 void copy_jobs(const CopyJob* d_jobs, int njobs, int64_t max_elems, hipStream_t s);
+// with fused launches on: throws unless every block of the jobs (host copy of
+// the table) lies in the instance slab
+void fuse_check(const std::vector<CopyJob>& jobs);
 // the products of the explicit MPO x MPS application in precision prec
 // (FP64; FP32 inputs; BF16 high + low parts), summed in FP64
 void apply_jobs(const ApplyJob* d_jobs, int njobs, int64_t max_elems, hipStream_t s, Prec prec = Prec::F64);

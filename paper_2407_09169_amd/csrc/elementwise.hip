@@ -11,14 +11,22 @@ namespace qtt {
 
 namespace {
 
-__global__ void fill_kernel(double* p, int64_t n, double v) {
+// Fused launches (batched instances): grid y or z is the instance, whose data
+// lie istride bytes after the previous one's; job tables and size tables are
+// shared, the pointers they hold are shifted.
+__global__ void fill_kernel(double* p, int64_t n, double v, int64_t istride) {
+  p = ishift(p, (int64_t)blockIdx.y * istride);
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (; i < n; i += stride) p[i] = v;
 }
 
-__global__ void copy_jobs_kernel(const CopyJob* jobs) {
-  const CopyJob j = jobs[blockIdx.y];
+__global__ void copy_jobs_kernel(const CopyJob* jobs, int64_t istride) {
+  CopyJob j = jobs[blockIdx.y];
+  const int64_t io = (int64_t)blockIdx.z * istride;
+  j.src = ishift(j.src, io);
+  j.dst = ishift(j.dst, io);
+  j.dscale = ishift(j.dscale, io);
   const int64_t n = (int64_t)j.rl * j.sp * j.rr;
   double sc = j.scale;
   if (j.dscale) sc *= *j.dscale;
@@ -76,8 +84,10 @@ __global__ void apply_jobs_kernel(const ApplyJob* jobs) {
 // the first) are zeroed, so the rounding keeps only singular values above
 // sqrt(tol2) sigma_1.
 __global__ void rank_cut_kernel(double* P, int64_t strideP, int ldp, const double* lam, int64_t strideL,
-                                const int* dims, const int* keep, double tol2) {
+                                const int* dims, const int* keep, double tol2, int64_t istride) {
   const int i = blockIdx.x;
+  P = ishift(P, (int64_t)blockIdx.y * istride);
+  lam = ishift(lam, (int64_t)blockIdx.y * istride);
   const double* l = lam + i * strideL;
   const int kp = keep[i], rows = dims[i];
   const double cut = tol2 * l[0];
@@ -92,7 +102,9 @@ __global__ void rank_cut_kernel(double* P, int64_t strideP, int ldp, const doubl
 }
 
 // Sets *flag to 1 if any of the n values is NaN or infinite.
-__global__ void nonfinite_kernel(const double* p, int64_t n, int* flag) {
+__global__ void nonfinite_kernel(const double* p, int64_t n, int* flag, int64_t istride) {
+  p = ishift(p, (int64_t)blockIdx.y * istride);
+  flag = ishift(flag, (int64_t)blockIdx.y * istride);
   bool bad = false;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     bad |= !isfinite(p[e]);
@@ -128,6 +140,7 @@ void transpose(const double* src, int rows, int cols, double* dst, hipStream_t s
   if (n <= 0) return;
   rt::check_range(src, 0, n - 1, sizeof(double), "transpose src");
   rt::check_range(dst, 0, n - 1, sizeof(double), "transpose dst");
+  rt::fuse_refuse("transpose");
   if (rt::dry()) return;
   int64_t blocks = std::min<int64_t>((n + 255) / 256, 2048);
   hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, rows, cols, dst);
@@ -137,6 +150,7 @@ void transpose(const double* src, int rows, int cols, double* dst, hipStream_t s
 void eye(double* dst, int m, hipStream_t s) {
   int64_t n = (int64_t)m * m;
   rt::check_range(dst, 0, n - 1, sizeof(double), "eye dst");
+  rt::fuse_refuse("eye");
   if (rt::dry()) return;
   int64_t blocks = std::min<int64_t>((n + 255) / 256, 2048);
   hipLaunchKernelGGL(eye_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, m);
@@ -149,6 +163,7 @@ void scalar_comb(double* out, const double* a, const double* b, double cb, doubl
   rt::check_range(out, 0, n - 1, sizeof(double), "scalar out");
   rt::check_range(a, 0, n - 1, sizeof(double), "scalar a");
   if (b) rt::check_range(b, 0, n - 1, sizeof(double), "scalar b");
+  rt::fuse_refuse("scalar_comb");
   if (rt::dry()) return;
   hipLaunchKernelGGL(scalar_comb_kernel, dim3(1), dim3(64), 0, s, out, a, b, cb, scale, n);
   QTT_HIP(hipGetLastError());
@@ -157,9 +172,11 @@ void scalar_comb(double* out, const double* a, const double* b, double cb, doubl
 void fill(double* p, int64_t n, double v, hipStream_t s) {
   if (n <= 0) return;
   rt::check_range(p, 0, n - 1, sizeof(double), "fill");
+  rt::fuse_check(p, 8 * n, "fill");
   if (rt::dry()) return;
+  const rt::Fuse& fu = rt::fuse();
   int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks, fu.n), dim3(256), 0, s, p, n, v, fu.stride);
   QTT_HIP(hipGetLastError());
 }
 
@@ -179,13 +196,24 @@ void validate(const ApplyJob& j) {
   rt::check_range(j.out, 0, (int64_t)j.xl * j.Dl * 2 * j.xr * j.Dr - 1, sizeof(double), "apply out");
 }
 
+void fuse_check(const std::vector<CopyJob>& jobs) {
+  if (rt::fuse().n <= 1) return;
+  for (const CopyJob& j : jobs) {
+    rt::fuse_check(j.src, 8 * (int64_t)j.rl * j.sp * j.rr, "copy job source");
+    const int64_t hi = ((int64_t)(j.ro + j.rl - 1) * j.dp + (j.dp - 1)) * j.drr + j.co + j.rr - 1;
+    rt::fuse_check(j.dst, 8 * (hi + 1), "copy job destination");
+    if (j.dscale) rt::fuse_check(j.dscale, 8, "copy job scale");
+  }
+}
+
 void copy_jobs(const CopyJob* d_jobs, int njobs, int64_t max_elems, hipStream_t s) {
   if (njobs <= 0) return;
   rt::check_range(d_jobs, 0, njobs - 1, sizeof(CopyJob), "copy job table");
   if (rt::dry()) return;
+  const rt::Fuse& fu = rt::fuse();
   int64_t bx = std::min<int64_t>((max_elems + 255) / 256, 1024);
   if (bx < 1) bx = 1;
-  hipLaunchKernelGGL(copy_jobs_kernel, dim3((unsigned)bx, njobs), dim3(256), 0, s, d_jobs);
+  hipLaunchKernelGGL(copy_jobs_kernel, dim3((unsigned)bx, njobs, fu.n), dim3(256), 0, s, d_jobs, fu.stride);
   QTT_HIP(hipGetLastError());
 }
 
@@ -202,9 +230,16 @@ void rank_cut(double* P, int64_t strideP, int ldp, const double* lam, int64_t st
   }
   rt::check_range(d_dims, 0, count - 1, sizeof(int), "rank cut dims");
   rt::check_range(d_keep, 0, count - 1, sizeof(int), "rank cut keep");
+  const rt::Fuse& fu = rt::fuse();
+  if (fu.n > 1) {
+    for (int i = 0; i < count; ++i) {
+      rt::fuse_check(P + i * strideP, 8 * ((int64_t)(dims[i] - 1) * ldp + keep[i]), "rank cut vectors");
+      rt::fuse_check(lam + i * strideL, 8 * (int64_t)keep[i], "rank cut values");
+    }
+  }
   if (rt::dry()) return;
-  hipLaunchKernelGGL(rank_cut_kernel, dim3(count), dim3(256), 0, s, P, strideP, ldp, lam, strideL, d_dims, d_keep,
-                     tol2);
+  hipLaunchKernelGGL(rank_cut_kernel, dim3(count, fu.n), dim3(256), 0, s, P, strideP, ldp, lam, strideL, d_dims,
+                     d_keep, tol2, fu.stride);
   QTT_HIP(hipGetLastError());
 }
 
@@ -212,19 +247,23 @@ void check_finite(const double* p, int64_t n, int* flag, hipStream_t s) {
   if (n <= 0) return;
   rt::check_range(p, 0, n - 1, sizeof(double), "finite check");
   rt::check_range(flag, 0, 0, sizeof(int), "finite check flag");
+  rt::fuse_check(p, 8 * n, "finite check");
+  rt::fuse_check(flag, sizeof(int), "finite check flag");
   if (rt::dry()) {  // host memory stands in for device memory: scan it here
     for (int64_t e = 0; e < n; ++e)
       if (!std::isfinite(p[e])) *flag = 1;
     return;
   }
+  const rt::Fuse& fu = rt::fuse();
   const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
-  hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, flag);
+  hipLaunchKernelGGL(nonfinite_kernel, dim3((unsigned)blocks, fu.n), dim3(256), 0, s, p, n, flag, fu.stride);
   QTT_HIP(hipGetLastError());
 }
 
 void apply_jobs(const ApplyJob* d_jobs, int njobs, int64_t max_elems, hipStream_t s, Prec prec) {
   if (njobs <= 0) return;
   rt::check_range(d_jobs, 0, njobs - 1, sizeof(ApplyJob), "apply job table");
+  rt::fuse_refuse("the explicit MPO x MPS product");
   if (rt::dry()) return;
   int64_t bx = std::min<int64_t>((max_elems + 255) / 256, 1024);
   if (bx < 1) bx = 1;

@@ -140,12 +140,19 @@ __global__ __launch_bounds__(QFT) void qr_kernel(int m, int n, const double* __r
                                                  double* __restrict__ Q0, int64_t strideQ,
                                                  double* __restrict__ R0, int64_t strideR,
                                                  double* __restrict__ work, const int* __restrict__ sq,
-                                                 int ldq) {
+                                                 int ldq, int64_t istride) {
   __shared__ double red[QFW];
   __shared__ double taus[1024];
   __shared__ double betas[1024];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t b = blockIdx.x;
+  {  // instance of a fused launch (grid y): shift the data, not the size table
+    const int64_t io = (int64_t)blockIdx.y * istride;
+    A0 = ishift(A0, io);
+    Q0 = ishift(Q0, io);
+    R0 = ishift(R0, io);
+    work = ishift(work, io);
+  }
   const double* A = A0 + b * strideA;
   double* W = work + b * (int64_t)m * n;  // column-major, W[c*m + r]
   const int ldo = ldq > 0 ? ldq : n;  // leading dimension of Q and R (launch n by default)
@@ -267,13 +274,19 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
                                                       int64_t strideA, int64_t rs, int64_t cs,
                                                       double* __restrict__ Q0, int64_t strideQ,
                                                       double* __restrict__ R0, int64_t strideR,
-                                                      const int* __restrict__ sq, int ldq) {
+                                                      const int* __restrict__ sq, int ldq, int64_t istride) {
   __shared__ double vbuf[2][64 * RS];
   __shared__ double taus[QW * CPW];
   __shared__ double betas[QW * CPW];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t bi = blockIdx.x;
+  {  // instance of a fused launch (grid y): shift the data, not the size table
+    const int64_t io = (int64_t)blockIdx.y * istride;
+    A0 = ishift(A0, io);
+    Q0 = ishift(Q0, io);
+    R0 = ishift(R0, io);
+  }
   const double* A = A0 + bi * strideA;
   const int ldo = ldq > 0 ? ldq : n;  // leading dimension of Q and R (launch n by default)
   if (sq != nullptr) {  // per-matrix square size
@@ -526,7 +539,8 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
                                                        double* __restrict__ Q0, int64_t strideQ,
                                                        double* __restrict__ R0, int64_t strideR,
                                                        const int* __restrict__ sq, int ldq,
-                                                       double* __restrict__ Vout, double* __restrict__ tout) {
+                                                       double* __restrict__ Vout, double* __restrict__ tout,
+                                                       int64_t istride) {
   constexpr int CL = 4 * NW;
   __shared__ double vbuf[2][16 * RPL];
   __shared__ double vall[CL][16 * RPL];
@@ -536,6 +550,14 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int g = lane >> 4, li = lane & 15;
   const int64_t bi = blockIdx.x;
+  {  // instance of a fused launch (grid y): shift the data, not the size table
+    const int64_t io = (int64_t)blockIdx.y * istride;
+    A0 = ishift(A0, io);
+    Q0 = ishift(Q0, io);
+    R0 = ishift(R0, io);
+    Vout = ishift(Vout, io);
+    tout = ishift(tout, io);
+  }
   const double* A = A0 + bi * strideA;
   const int ldo = ldq > 0 ? ldq : n;  // leading dimension of Q and R (launch n by default)
   if (sq != nullptr) {  // per-matrix square size
@@ -689,12 +711,23 @@ __global__ __launch_bounds__(EFT) void eig_kernel(const int* dims, const int* ke
                                                   int ldp, double* __restrict__ L0, int64_t strideL,
                                                   double* __restrict__ work, double unoise,
                                                   const double* __restrict__ Qp, double* __restrict__ R1p,
-                                                  double* __restrict__ R2p, int64_t strideQR, int ldqr) {
+                                                  double* __restrict__ R2p, int64_t strideQR, int ldqr,
+                                                  int64_t istride) {
   __shared__ int changed;
   __shared__ double gmax;
   __shared__ double nrm[1024];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t b = blockIdx.x;
+  {  // instance of a fused launch (grid y): shift the data, not the size tables
+    const int64_t io = (int64_t)blockIdx.y * istride;
+    G0 = ishift(G0, io);
+    P0 = ishift(P0, io);
+    L0 = ishift(L0, io);
+    work = ishift(work, io);
+    Qp = ishift(Qp, io);
+    R1p = ishift(R1p, io);
+    R2p = ishift(R2p, io);
+  }
   const int n = dims[b];
   const int k = keep[b];
   if (n <= 0) return;
@@ -828,7 +861,7 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
                                                           int64_t strideL, double unoise,
                                                           const double* __restrict__ Q0,
                                                           const double* __restrict__ R0,
-                                                          int64_t strideQR, int ldqr) {
+                                                          int64_t strideQR, int ldqr, int64_t istride) {
   __shared__ double xT[2][NW][2][64 * RS];  // outgoing last top column (W, V) per wave
   __shared__ double xB[2][NW][2][64 * RS];  // outgoing first bottom column (W, V) per wave
   __shared__ int xTid[2][NW], xBid[2][NW];
@@ -837,6 +870,14 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t bi = blockIdx.x;
+  {  // instance of a fused launch (grid y): shift the data, not the size tables
+    const int64_t io = (int64_t)blockIdx.y * istride;
+    G0 = ishift(G0, io);
+    P0 = ishift(P0, io);
+    L0 = ishift(L0, io);
+    Q0 = ishift(Q0, io);
+    R0 = ishift(R0, io);
+  }
   const int n = dims[bi];
   const int kk = keep[bi];
   if (n <= 0) return;
@@ -1274,7 +1315,7 @@ void qr_blocked(int m, int n, const double* A, int64_t rs, int64_t cs, double* Q
     if (run) {
       hipLaunchKernelGGL((qr_grp_kernel<36, 1, 8>), dim3(1), dim3(512), 0, s, mr, w, (const double*)Wp, (int64_t)0,
                          (int64_t)n, (int64_t)1, (double*)nullptr, (int64_t)0, W2, (int64_t)0, (const int*)nullptr,
-                         n, Vp, taus + p0);
+                         n, Vp, taus + p0, (int64_t)0);
       QTT_HIP(hipGetLastError());
       hipLaunchKernelGGL(qrb_copy_kernel, grid((int64_t)w * w), dim3(256), 0, s, Wp, n, (const double*)W2,
                          (int64_t)n, (int64_t)1, w, w);
@@ -1338,14 +1379,25 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
   if (generic) rt::check_range(work, 0, (int64_t)count * m * n - 1, sizeof(double), "qr workspace");
   if (generic && count == 1 && sq == nullptr && m <= QB_MAXM && work_size >= qr_work_size(1, m, n)) {
     rt::check_range(work, 0, qr_work_size(1, m, n) - 1, sizeof(double), "qr workspace");
+    rt::fuse_refuse("the blocked QR");
     qr_blocked(m, n, A, rs, cs, Q, lq, R, work, s);
     return;
   }
+  const rt::Fuse& fu = rt::fuse();
+  if (fu.n > 1) {
+    rt::fuse_check(A, 8 * ((int64_t)(count - 1) * strideA + (int64_t)(m - 1) * rs + (int64_t)(n - 1) * cs + 1),
+                   "qr input");
+    rt::fuse_check(Q, 8 * ((int64_t)(count - 1) * strideQ + (int64_t)(m - 1) * lq + n), "qr Q");
+    if (R) rt::fuse_check(R, 8 * ((int64_t)(count - 1) * strideR + (int64_t)(n - 1) * lq + n), "qr R");
+    if (generic) rt::fuse_check(work, 8 * ((int64_t)count * m * n), "qr workspace");
+  }
+  const dim3 grid(count, fu.n);
+  const int64_t is = fu.stride;
   if (rt::dry()) return;
 #define QTT_QR_REG(RS_, CPW_, NW_, CH_)                                                           \
   if (m <= 64 * RS_ && n <= NW_ * CPW_) {                                                         \
-    hipLaunchKernelGGL((qr_reg_kernel<RS_, CPW_, NW_, CH_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
-                       strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq);                             \
+    hipLaunchKernelGGL((qr_reg_kernel<RS_, CPW_, NW_, CH_>), grid, dim3(NW_ * 64), 0, s, m, n, A,       \
+                       strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq, is);                         \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }
@@ -1353,8 +1405,8 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
 #undef QTT_QR_REG
 #define QTT_QR_GRP(RPL_, CS_, NW_)                                                                \
   if (m <= 16 * RPL_ && n <= 4 * NW_ * CS_) {                                                     \
-    hipLaunchKernelGGL((qr_grp_kernel<RPL_, CS_, NW_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
-                       strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq, nullptr, nullptr);         \
+    hipLaunchKernelGGL((qr_grp_kernel<RPL_, CS_, NW_>), grid, dim3(NW_ * 64), 0, s, m, n, A,          \
+                       strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq, nullptr, nullptr, is);     \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }
@@ -1362,15 +1414,15 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
 #undef QTT_QR_GRP
 #define QTT_QR_REG(RS_, CPW_, NW_, CH_)                                                           \
   if (m <= 64 * RS_ && n <= NW_ * CPW_) {                                                         \
-    hipLaunchKernelGGL((qr_reg_kernel<RS_, CPW_, NW_, CH_>), dim3(count), dim3(NW_ * 64), 0, s, m, n, A, \
-                       strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq);                             \
+    hipLaunchKernelGGL((qr_reg_kernel<RS_, CPW_, NW_, CH_>), grid, dim3(NW_ * 64), 0, s, m, n, A,       \
+                       strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq, is);                         \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }
   QTT_QR_CONFIGS_LARGE(QTT_QR_REG)
 #undef QTT_QR_REG
-  hipLaunchKernelGGL(qr_kernel, dim3(count), dim3(QFT), 0, s, m, n, A, strideA, rs, cs, Q, strideQ,
-                     R, strideR, work, sq, ldq);
+  hipLaunchKernelGGL(qr_kernel, grid, dim3(QFT), 0, s, m, n, A, strideA, rs, cs, Q, strideQ,
+                     R, strideR, work, sq, ldq, is);
   QTT_HIP(hipGetLastError());
 }
 
@@ -1408,23 +1460,32 @@ void eig_launch(int count, const int* dims, const int* keep, const double* G, in
   rt::check_range(lam, 0, (int64_t)(count - 1) * strideL + max_n - 1, sizeof(double), "eig values");
   rt::check_range(work, 0, eig_work_size(count, ldg) - 1, sizeof(double), "eig workspace");
   QTT_REQUIRE(!preconditioned || eig_uses_precondition(max_n), "eig: no preconditioned configuration");
+  const rt::Fuse& fu = rt::fuse();
+  if (fu.n > 1) {
+    rt::fuse_check(G, 8 * ((int64_t)(count - 1) * strideG + (int64_t)(max_n - 1) * ldg + max_n), "eig input");
+    rt::fuse_check(P, 8 * ((int64_t)(count - 1) * strideP + (int64_t)max_n * ldp), "eig vectors");
+    rt::fuse_check(lam, 8 * ((int64_t)(count - 1) * strideL + max_n), "eig values");
+    rt::fuse_check(work, 8 * eig_work_size(count, ldg), "eig workspace");
+  }
+  const dim3 grid(count, fu.n);
+  const int64_t is = fu.stride;
   if (rt::dry()) return;
   const int64_t st = (int64_t)ldg * ldg;
   const double* Qf = preconditioned ? work : nullptr;
   const double* Rf = preconditioned ? work + 2 * count * st : nullptr;
 #define QTT_EIG_REG(RS_, PPW_, NW_, CH_)                                                          \
   if (max_n <= 64 * RS_ && max_n <= 2 * NW_ * PPW_) {                                            \
-    hipLaunchKernelGGL((eig_reg_kernel<RS_, PPW_, NW_, CH_>), dim3(count), dim3(NW_ * 64), 0, s,  \
+    hipLaunchKernelGGL((eig_reg_kernel<RS_, PPW_, NW_, CH_>), grid, dim3(NW_ * 64), 0, s,        \
                        dims, keep, G, strideG, ldg, P, strideP, ldp, lam, strideL, unoise, Qf, Rf, \
-                       st, max_n);                                                               \
+                       st, max_n, is);                                                           \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }
   QTT_EIG_CONFIGS(QTT_EIG_REG)
 #undef QTT_EIG_REG
-  hipLaunchKernelGGL(eig_kernel, dim3(count), dim3(EFT), 0, s, dims, keep, G, strideG, ldg, P,
+  hipLaunchKernelGGL(eig_kernel, grid, dim3(EFT), 0, s, dims, keep, G, strideG, ldg, P,
                      strideP, ldp, lam, strideL, work, unoise, Qf, preconditioned ? work + count * st : nullptr,
-                     preconditioned ? work + 2 * count * st : nullptr, st, max_n);
+                     preconditioned ? work + 2 * count * st : nullptr, st, max_n, is);
   QTT_HIP(hipGetLastError());
 }
 

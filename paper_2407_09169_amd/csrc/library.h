@@ -117,8 +117,12 @@ struct Plan {
     QTT_REQUIRE(arena == nullptr, "a plan on a fixed scratch buffer cannot upload tables");
     bufs.emplace_back(new DevBuf(std::max<size_t>(host.size(), 1) * sizeof(T)));
     if (!host.empty()) rt::copy(bufs.back()->p, host.data(), host.size() * sizeof(T));
+    uploads.push_back({bufs.back()->p, host.size() * sizeof(T)});
     return static_cast<T*>(bufs.back()->p);
   }
+  // device memory written when the plan was recorded (uploaded tables and
+  // constants): (pointer, bytes)
+  std::vector<std::pair<void*, size_t>> uploads;
   void add(std::function<void(hipStream_t)> f, OpInfo oi = OpInfo{}) {
     ops.push_back(std::move(f));
     info.push_back(oi);

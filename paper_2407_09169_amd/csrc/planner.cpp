@@ -782,6 +782,7 @@ void plan_axpby(Plan& plan, const std::vector<std::pair<double, ChainView>>& ter
   for (const CopyJob& j : jobs) oi.bytes += 16.0 * j.rl * j.sp * j.rr;
   oi.bytes += 8.0 * tot;
   plan.add([=](hipStream_t s) {
+    fuse_check(jobs);
     fill(base, tot, 0.0, s);
     copy_jobs(dj, nj, maxe, s);
   }, oi);

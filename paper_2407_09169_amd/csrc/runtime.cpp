@@ -16,6 +16,7 @@ static std::mutex g_mu;
 struct Range {
   size_t bytes = 0;
   bool hooked = false;
+  bool slab = false;  // carved from a slab: nothing to free
 };
 static std::map<uintptr_t, Range>& registry() {
   static std::map<uintptr_t, Range> m;
@@ -48,9 +49,61 @@ bool dry() {
   return v == 1;
 }
 
+namespace {
+struct Slab {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+};
+thread_local Slab* t_slab = nullptr;
+thread_local size_t t_count = 0;
+thread_local Fuse t_fuse;
+constexpr size_t kSlabAlign = 256;
+size_t slab_round(size_t b) { return (std::max<size_t>(b, 1) + kSlabAlign - 1) & ~(kSlabAlign - 1); }
+}  // namespace
+
+SlabScope::SlabScope(void* base, size_t cap) {
+  QTT_REQUIRE(t_slab == nullptr, "slab scopes do not nest");
+  QTT_REQUIRE(((uintptr_t)base & (kSlabAlign - 1)) == 0, "slab base not aligned");
+  t_slab = new Slab{static_cast<char*>(base), cap, 0};
+}
+SlabScope::~SlabScope() {
+  delete t_slab;
+  t_slab = nullptr;
+}
+size_t SlabScope::used() const { return t_slab ? t_slab->used : 0; }
+
+void alloc_count_reset() { t_count = 0; }
+size_t alloc_count() { return t_count; }
+
+Fuse& fuse() { return t_fuse; }
+
+void fuse_check(const void* p, size_t bytes, const char* what) {
+  const Fuse& f = t_fuse;
+  if (f.n <= 1 || bytes == 0) return;
+  const uintptr_t a = (uintptr_t)p;
+  if (!(a >= f.lo && a + bytes <= f.hi))
+    QTT_THROW(TT_ERR_INVALID_ARG, "%s: a fused launch needs its data inside the instance slab", what);
+}
+
+void fuse_refuse(const char* what) {
+  if (t_fuse.n > 1) QTT_THROW(TT_ERR_INVALID_ARG, "%s has no fused form for batched instances", what);
+}
+
 void* dev_alloc(size_t bytes) {
   void* p = nullptr;
   bool hooked = false;
+  t_count += slab_round(bytes);
+  if (t_slab) {
+    Slab& sl = *t_slab;
+    const size_t n = slab_round(bytes);
+    if (sl.used + n > sl.cap)
+      QTT_THROW(TT_ERR_OOM, "slab of %zu bytes exhausted (%zu more needed)", sl.cap, sl.used + n - sl.cap);
+    p = sl.base + sl.used;
+    sl.used += n;
+    std::lock_guard<std::mutex> lk(g_mu);
+    registry()[(uintptr_t)p] = Range{bytes, false, true};
+    return p;
+  }
   if (dry()) {
     p = std::calloc(1, bytes);
     if (!p) QTT_THROW(TT_ERR_OOM, "host allocation of %zu bytes failed", bytes);
@@ -93,7 +146,9 @@ void dev_free(void* p) {
     f = g_free;
     user = g_user;
   }
-  if (dry()) {
+  if (r.slab) {
+    return;  // the slab's owner frees it as a whole
+  } else if (dry()) {
     std::free(p);
   } else if (r.hooked) {
     // the caller's allocator may hand the block to other streams at once:
@@ -142,11 +197,17 @@ void copy(void* dst, const void* src, size_t bytes) {
 
 void copy_async(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (bytes == 0) return;
+  const Fuse& f = t_fuse;
+  if (f.n > 1) {
+    fuse_check(dst, bytes, "copy destination");
+    fuse_check(src, bytes, "copy source");
+  }
   if (dry()) {
     std::memcpy(dst, src, bytes);
     return;
   }
-  QTT_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, s));
+  for (int i = 0; i < f.n; ++i)
+    QTT_HIP(hipMemcpyAsync(ishift(dst, i * f.stride), ishift(src, i * f.stride), bytes, hipMemcpyDefault, s));
 }
 
 void sync(hipStream_t s) {

@@ -33,33 +33,47 @@ namespace {
 
 constexpr int BK64 = 16;
 
-// blockIdx.z = (batch index * ng + group) * ksplit + K chunk
+// blockIdx.z = ((instance * batch + batch index) * ng + group) * ksplit + K chunk
 struct KRange {
   int z, g, beg, end;
+  int zz;      // blockIdx.z within the instance
+  int64_t io;  // byte offset of the instance's data
 };
 
 template <int BK>
 __device__ inline KRange k_range(const TcDesc& d) {
-  if (d.ksplit == 1 && d.ng == 1) return {(int)blockIdx.z, 0, 0, d.K};  // no split, no groups
-  const int ks = (int)(blockIdx.z % (unsigned)d.ksplit);
-  const int zg = (int)(blockIdx.z / (unsigned)d.ksplit);
+  int zz = (int)blockIdx.z;
+  int64_t io = 0;
+  if (d.ninst > 1) {
+    const int per = d.batch * d.ng * d.ksplit;
+    const int inst = zz / per;
+    zz -= inst * per;
+    io = (int64_t)inst * d.istride;
+  }
+  if (d.ksplit == 1 && d.ng == 1) return {zz, 0, 0, d.K, zz, io};  // no split, no groups
+  const int ks = zz % d.ksplit;
+  const int zg = zz / d.ksplit;
   const int g = zg % d.ng;
   const int z = zg / d.ng;
   const int chunk = ((d.K + d.ksplit - 1) / d.ksplit + BK - 1) / BK * BK;
   const int beg = ks * chunk;
   const int end = min(d.K, beg + chunk);
-  return {z, g, beg, end};
+  return {z, g, beg, end, zz, io};
 }
 
-// group base pointers from the device table (one scalar load each)
+// group base pointers from the device table (one scalar load each), shifted
+// to the launch's instance
 __device__ inline const double* base_a(const TcDesc& d, const KRange& kr) {
-  return (d.ng > 1 ? d.gdev[kr.g] : d.A) + d.ab.off(kr.z);
+  return ishift(d.ng > 1 ? d.gdev[kr.g] : d.A, kr.io) + d.ab.off(kr.z);
 }
 __device__ inline const double* base_b(const TcDesc& d, const KRange& kr) {
-  return (d.ng > 1 ? d.gdev[d.ng + kr.g] : d.B) + d.bb.off(kr.z);
+  return ishift(d.ng > 1 ? d.gdev[d.ng + kr.g] : d.B, kr.io) + d.bb.off(kr.z);
 }
 __device__ inline double* base_c(const TcDesc& d, const KRange& kr) {
-  return (d.ng > 1 ? const_cast<double*>(d.gdev[2 * d.ng + kr.g]) : d.C) + d.cb.off(kr.z);
+  return ishift(d.ng > 1 ? const_cast<double*>(d.gdev[2 * d.ng + kr.g]) : d.C, kr.io) + d.cb.off(kr.z);
+}
+__device__ inline double* base_part(const TcDesc& d, const KRange& kr) {
+  return ishift(d.part, kr.io) + (int64_t)kr.zz * d.M * d.N;
 }
 __device__ inline bool to_part(const TcDesc& d) { return d.ksplit > 1 || (d.ng > 1 && d.gsum); }
 
@@ -128,7 +142,7 @@ __global__ __launch_bounds__(256) void tc_f64_kernel(TcDesc d, int a_kfast, int 
     __syncthreads();
   }
   if (to_part(d)) {
-    double* Pp = d.part + (int64_t)blockIdx.z * d.M * d.N;
+    double* Pp = base_part(d, kr);
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
       const int m = m0 + ty + 16 * i;
@@ -366,7 +380,7 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
   }
   // accumulator layout: lane holds rows 4*(lane/16)+r, column lane%16 of each block
   if (to_part(d)) {
-    double* Pp = d.part + (int64_t)blockIdx.z * d.M * d.N;
+    double* Pp = base_part(d, kr);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -417,14 +431,15 @@ __global__ __launch_bounds__(256) void tc_splitk_reduce(TcDesc d) {
   const int nparts = (d.gsum ? d.ng : 1) * d.ksplit;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= mn * d.batch * gout) return;
+  const int64_t io = (int64_t)blockIdx.y * d.istride;  // instance (grid y)
   const int zo = (int)(idx / mn);
   const int64_t rem = idx - (int64_t)zo * mn;
   const int m = (int)(rem / d.N), n = (int)(rem - (int64_t)m * d.N);
   const int z = zo / gout, g = zo - z * gout;
-  const double* Pp = d.part + ((int64_t)z * d.ng + g) * d.ksplit * mn + rem;
+  const double* Pp = ishift(d.part, io) + ((int64_t)z * d.ng + g) * d.ksplit * mn + rem;
   double s = 0.0;
   for (int k = 0; k < nparts; ++k) s += Pp[(int64_t)k * mn];
-  double* base = (d.ng > 1 && !d.gsum) ? const_cast<double*>(d.gdev[2 * d.ng + g]) : d.C;
+  double* base = ishift((d.ng > 1 && !d.gsum) ? const_cast<double*>(d.gdev[2 * d.ng + g]) : d.C, io);
   double* p = base + d.cb.off(z) + d.cm.off(m) + d.cn.off(n);
   double v = d.alpha * s;
   if (d.beta != 0.0) v += d.beta * *p;
@@ -491,23 +506,38 @@ void tc_validate(const TcDesc& d) {
       rt::check_range(B, 0, mode_max(d.bb, d.batch) + mode_max(d.bk, d.K) + mode_max(d.bn, d.N),
                       sizeof(double), "contraction operand B");
     }
-    rt::check_range(C, 0, mode_max(d.cb, d.batch) + mode_max(d.cm, d.M) + mode_max(d.cn, d.N),
-                    sizeof(double), "contraction result C");
+    const int64_t ce = mode_max(d.cb, d.batch) + mode_max(d.cm, d.M) + mode_max(d.cn, d.N);
+    rt::check_range(C, 0, ce, sizeof(double), "contraction result C");
+    if (rt::fuse().n > 1) {
+      if (d.K > 0) {
+        rt::fuse_check(A, 8 * (mode_max(d.ab, d.batch) + mode_max(d.am, d.M) + mode_max(d.ak, d.K) + 1),
+                       "contraction operand A");
+        rt::fuse_check(B, 8 * (mode_max(d.bb, d.batch) + mode_max(d.bk, d.K) + mode_max(d.bn, d.N) + 1),
+                       "contraction operand B");
+      }
+      rt::fuse_check(C, 8 * (ce + 1), "contraction result C");
+    }
   }
-  if (tc_uses_part(d))
+  if (tc_uses_part(d)) {
     rt::check_range(d.part, 0, tc_part_size(d) - 1, sizeof(double), "contraction partial sums");
+    rt::fuse_check(d.part, 8 * tc_part_size(d), "contraction partial sums");
+  }
 }
 
-void tc_launch(const TcDesc& d, Prec p, hipStream_t s) {
-  if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return;
+void tc_launch(const TcDesc& d0, Prec p, hipStream_t s) {
+  if (d0.M <= 0 || d0.N <= 0 || d0.batch <= 0) return;
+  TcDesc d = d0;
+  d.ninst = rt::fuse().n;
+  d.istride = rt::fuse().stride;
   tc_validate(d);
   if (rt::dry()) return;
-  QTT_REQUIRE((int64_t)d.batch * d.ng * d.ksplit <= 65535 && (d.M + 31) / 32 <= 65535,
-              "contraction too large (M=%d batch=%d groups=%d split=%d)", d.M, d.batch, d.ng, d.ksplit);
+  QTT_REQUIRE((int64_t)d.batch * d.ng * d.ksplit * d.ninst <= 65535 && (d.M + 31) / 32 <= 65535,
+              "contraction too large (M=%d batch=%d groups=%d split=%d instances=%d)", d.M, d.batch, d.ng,
+              d.ksplit, d.ninst);
   const int a_kfast = unit(d.ak) ? 1 : 0;
   const int b_nfast = unit(d.bn) ? 1 : 0;
   const Tile t = tile_of(d, p);
-  const dim3 grid((d.N + t.bn - 1) / t.bn, (d.M + t.bm - 1) / t.bm, d.batch * d.ng * d.ksplit);
+  const dim3 grid((d.N + t.bn - 1) / t.bn, (d.M + t.bm - 1) / t.bm, d.batch * d.ng * d.ksplit * d.ninst);
   if (p == Prec::F64) {
     if (t.bm == 64 && t.bn == 64)
       hipLaunchKernelGGL((tc_f64_kernel<64, 64>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
@@ -541,7 +571,7 @@ void tc_launch(const TcDesc& d, Prec p, hipStream_t s) {
   QTT_HIP(hipGetLastError());
   if (tc_uses_part(d)) {
     const int64_t tot = (int64_t)d.M * d.N * d.batch * (d.gsum ? 1 : d.ng);
-    hipLaunchKernelGGL(tc_splitk_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, d);
+    hipLaunchKernelGGL(tc_splitk_reduce, dim3((unsigned)((tot + 255) / 256), d.ninst), dim3(256), 0, s, d);
     QTT_HIP(hipGetLastError());
   }
 }

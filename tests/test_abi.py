@@ -68,8 +68,9 @@ print("ok")
 
 
 def test_dry_run_batch_planning_is_in_bounds():
-    """The batched step over uneven problems plans every launch in bounds, and
-    a batch that repeats a problem is refused."""
+    """The batched step over uneven problems plans every launch in bounds
+    (fused classes included), and a batch that repeats a problem is
+    refused."""
     code = r"""
 import os, sys
 os.environ["QTTPDF_DRYRUN"] = "1"
@@ -80,6 +81,17 @@ ws = workloads.batch_workloads(count=4, seed=7, bits=(3, 4, 6), chis=(8, 16, 64)
 inst = [q.setup_workload(ctx, w, "f32") for w in ws]
 b = q.Batch(ctx, [p for p, _ in inst], [f for _, f in inst])
 b.step(1)
+# two 64^5 chi = 64 instances of equal structure share their launches: every
+# fused launch checks that each instance's data stay inside its slab
+info = b.info()
+assert info["fused_classes"] == 1 and info["fused_instances"] == 2 and info["units"] == 3, info
+ws6 = workloads.batch_workloads(count=6, seed=7, bits=(3, 4), chis=(8, 16, 32))
+inst6 = [q.setup_workload(ctx, w, "f64") for w in ws6]
+b6 = q.Batch(ctx, [p for p, _ in inst6], [f for _, f in inst6])
+b6.step(2)
+assert b6.info()["fused_classes"] == 2, b6.info()
+os.environ["QTTPDF_BATCH_FUSE"] = "0"
+assert q.Batch(ctx, [p for p, _ in inst6], [f for _, f in inst6]).info()["fused_classes"] == 0
 try:
     q.Batch(ctx, [inst[0][0], inst[0][0]], [inst[0][1], inst[0][1]])
 except q.QttError as e:
@@ -311,9 +323,10 @@ def test_plan_lane_rules(tmp_path):
     """The launch-plan rules that keep HIP graph capture on the forms that
     work on this runtime (every fork from lane 0, every join onto it; one
     lane on a fixed scratch buffer), exercised by a host program linked
-    against the library (dry run), and no batched step captures a graph of
-    its own: the batch launches the instances' recorded graphs on branch
-    streams (the four-branch captured form crashed the host process)."""
+    against the library (dry run), and no batched step captures a graph
+    across its units: the batch launches recorded graphs on branch streams
+    (the four-branch captured form crashed the host process), each fused
+    class's graph captured from one plan as a single step's is."""
     exe = tmp_path / "plan_rules"
     src = os.path.join(ROOT, "tests", "cpp", "test_plan_rules.cpp")
     lib_dir = os.path.dirname(LIB)
@@ -328,3 +341,7 @@ def test_plan_lane_rules(tmp_path):
     body = src[src.index("tt_status tt_step_batched("):]
     body = body[:body.index("\n}\n")]
     assert "hipStreamBeginCapture" not in body and "hipGraphInstantiate" not in body
+    fused = src[src.index("static std::unique_ptr<FusedClass> build_fused_class("):]
+    fused = fused[:fused.index("\n}\n")]
+    cap = fused[fused.index("hipStreamBeginCapture"):fused.index("hipStreamEndCapture")]
+    assert cap.count("->run(") == 1 and "hipStreamWaitEvent" not in cap
