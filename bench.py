@@ -213,6 +213,11 @@ def _bench_batched(args, log):
     log(f"batched: {args.steps} steps of {len(ws)} instances in {ms:.1f} ms ({value:.1f} instance-steps/s)")
     masses = [p.observable(f, "mass") for p, f in inst]
     b.close()  # releases the batch plan before the instances record their own
+    if args.no_plain:  # the batch alone
+        print(json.dumps({"metric": "instance-steps/s, 64 uneven 5-D QTT PDF problems stepped together",
+                          "value": value, "unit": "instance-steps/s", "ms_per_step": ms / args.steps,
+                          "batch": binfo}))
+        return
     # one after another: each instance records its own graph, is timed over
     # one step, and releases its plan (all 64 step plans at once would not fit)
     ms1 = 0.0
@@ -595,8 +600,8 @@ def _bench_drift(args, log):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--dtype", default="f32", choices=["bf16", "f32", "f64"])
     ap.add_argument("--workload", default="c3_5d_M1024_chi128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
