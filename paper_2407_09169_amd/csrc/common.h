@@ -311,6 +311,15 @@ TcDesc gemm_desc(int M, int N, int K, const double* A, int64_t lda, bool transA,
 void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_t rs, int64_t cs,
                double* Q, int64_t strideQ, double* R, int64_t strideR, double* work,
                hipStream_t s, const int* sq = nullptr, int ldq = 0, int64_t work_size = -1);
+// One m x n matrix, thin Q only, in two launches: the factorising workgroup
+// leaves the reflectors (V, row-major with unit diagonal, then tau: m n + n
+// doubles of work), and workgroups of 16 columns form Q from them.  Whether
+// a shape and workspace take this path (qr_launch takes it by itself when
+// they do; QTTPDF_QR_SPLIT=0 turns it off):
+bool qr_split(int m, int n, int64_t work_size);
+void qr_reflectors_launch(int m, int n, const double* A, int64_t rs, int64_t cs, double* work, hipStream_t s);
+void qr_form_q_launch(int m, int n, const double* work, double* Q, int ldq, hipStream_t s);
+std::string qr_q_kernel_name(int m, int n);
 
 // workspace that lets a single matrix beyond the register kernels (m <= 576)
 // take the blocked Householder QR (pass it as work_size); otherwise

@@ -6,6 +6,7 @@
 // reflector or Jacobi rotation touches contiguous columns.  Reductions over
 // a column use wavefront shuffles, then one LDS slot per wavefront.
 #include <cstdio>
+#include <cstdlib>
 #include <string>
 
 #include "common.h"
@@ -691,6 +692,96 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
 }
 
 // ---------------------------------------------------------------------------
+// Thin Q of a factorisation left as reflectors (V: m x n, row-major, unit
+// diagonal, zeros above; tau: n), Q = H_0 H_1 ... H_(n-1) [I; 0], spread over
+// workgroups of 16 columns (the columns of Q are independent given the
+// reflectors).  Layout of qr_grp_kernel: column c = 16 blockIdx.x + 4 w + g
+// on the 16 lanes of group g of wavefront w, rows li + 16 r (r < RPL).
+// Column c starts as e_c and takes the reflectors from the last to the first
+// (those past c leave it unchanged: v_k vanishes above row k).  The
+// reflectors pass through LDS in chunks of KC, double-buffered: the next
+// chunk's global loads are in flight while the current chunk is applied.
+// ---------------------------------------------------------------------------
+template <int RPL>
+__global__ __launch_bounds__(256) void qr_q_kernel(int m, int n, const double* __restrict__ V,
+                                                   const double* __restrict__ tau, double* __restrict__ Q, int ldq,
+                                                   int64_t istride) {
+  constexpr int KC = RPL > 18 ? 8 : 16;
+  constexpr int MR = 16 * RPL;
+  constexpr int NPRE = KC * MR / 256;
+  static_assert(NPRE * 256 == KC * MR, "chunk must split evenly over the workgroup");
+  __shared__ double Vs[2][KC][MR];  // reflectors of a chunk, one row of Vs per reflector
+  __shared__ double ts[2][KC];
+  {  // instance of a fused launch (grid y)
+    const int64_t io = (int64_t)blockIdx.y * istride;
+    V = ishift(V, io);
+    tau = ishift(tau, io);
+    Q = ishift(Q, io);
+  }
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, li = lane & 15;
+  const int c = (int)blockIdx.x * 16 + 4 * w + g;
+  double q[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) q[r] = (li + 16 * r == c) ? 1.0 : 0.0;
+  // chunk with top reflector khi: reflectors khi, khi - 1, ..., khi - KC + 1
+  // (those below 0 are zero); element e: reflector khi - e % KC, row e / KC
+  // (a row's KC values are contiguous in V)
+  double pre[NPRE];
+  auto load = [&](int khi) {
+#pragma unroll
+    for (int i = 0; i < NPRE; ++i) {
+      const int e = tid + 256 * i;
+      const int k = khi - e % KC, row = e / KC;
+      pre[i] = (k >= 0 && row < m) ? V[(int64_t)row * n + k] : 0.0;
+    }
+  };
+  auto store = [&](int buf, int khi) {
+#pragma unroll
+    for (int i = 0; i < NPRE; ++i) {
+      const int e = tid + 256 * i;
+      Vs[buf][e % KC][e / KC] = pre[i];
+    }
+    if (tid < KC) ts[buf][tid] = (khi - tid >= 0) ? tau[khi - tid] : 0.0;
+  };
+  int khi = min(n - 1, (int)blockIdx.x * 16 + 15);
+  load(khi);
+  store(0, khi);
+  __syncthreads();
+  int buf = 0;
+  while (khi >= 0) {  // block-uniform
+    const int knext = khi - KC;
+    if (knext >= 0) load(knext);
+    const int kn = min(KC, khi + 1);
+    for (int kk = 0; kk < kn; ++kk) {
+      const double t = ts[buf][kk];
+      double v[RPL];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) v[r] = Vs[buf][kk][li + 16 * r];
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc[r & 3] = fma(v[r], q[r], acc[r & 3]);
+      const double wgt = t * row_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) q[r] = fma(-wgt, v[r], q[r]);
+    }
+    if (knext >= 0) store(buf ^ 1, knext);
+    __syncthreads();
+    buf ^= 1;
+    khi = knext;
+  }
+  if (c < n) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int row = li + 16 * r;
+      if (row < m) Q[(int64_t)row * ldq + c] = q[r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Symmetric PSD eigen-decomposition by one-sided (Hestenes) Jacobi, general
 // sizes, columns in global memory (L2), 16 wavefronts.  Either from W = G,
 // V = I, or (preconditioned) from W = R^T, V = Q where G = Q1 R^T Q^T comes
@@ -1356,6 +1447,79 @@ void qr_blocked(int m, int n, const double* A, int64_t rs, int64_t cs, double* Q
 
 }  // namespace
 
+namespace {
+bool qr_split_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("QTTPDF_QR_SPLIT");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+// the group configuration a shape takes (RPL of it), or 0
+int qr_grp_rpl(int m, int n) {
+  if (qr_kernel_name(m, n).rfind("qr_grp_kernel", 0) != 0) return 0;
+#define QTT_QRG_RPL(RPL_, CS_, NW_) \
+  if (m <= 16 * RPL_ && n <= 4 * NW_ * CS_) return RPL_;
+  QTT_QRG_CONFIGS(QTT_QRG_RPL)
+#undef QTT_QRG_RPL
+  return 0;
+}
+}  // namespace
+
+bool qr_split(int m, int n, int64_t work_size) {
+  return qr_split_on() && qr_grp_rpl(m, n) > 0 && work_size >= (int64_t)m * n + n;
+}
+
+std::string qr_q_kernel_name(int m, int n) { return "qr_q_kernel<" + std::to_string(qr_grp_rpl(m, n)) + ">"; }
+
+void qr_reflectors_launch(int m, int n, const double* A, int64_t rs, int64_t cs, double* work, hipStream_t s) {
+  QTT_REQUIRE(qr_grp_rpl(m, n) > 0, "qr: no reflector kernel for %d x %d", m, n);
+  rt::check_range(A, 0, (int64_t)(m - 1) * rs + (int64_t)(n - 1) * cs, sizeof(double), "qr input");
+  rt::check_range(work, 0, (int64_t)m * n + n - 1, sizeof(double), "qr reflectors");
+  const rt::Fuse& fu = rt::fuse();
+  if (fu.n > 1) {
+    rt::fuse_check(A, 8 * ((int64_t)(m - 1) * rs + (int64_t)(n - 1) * cs + 1), "qr input");
+    rt::fuse_check(work, 8 * ((int64_t)m * n + n), "qr reflectors");
+  }
+  if (rt::dry()) return;
+  const dim3 grid(1, fu.n);
+  const int64_t is = fu.stride;
+#define QTT_QR_REFL(RPL_, CS_, NW_)                                                                   \
+  if (m <= 16 * RPL_ && n <= 4 * NW_ * CS_) {                                                         \
+    hipLaunchKernelGGL((qr_grp_kernel<RPL_, CS_, NW_>), grid, dim3(NW_ * 64), 0, s, m, n, A, (int64_t)0, rs, cs, \
+                       (double*)nullptr, (int64_t)0, (double*)nullptr, (int64_t)0, (const int*)nullptr, n, work, \
+                       work + (int64_t)m * n, is);                                                    \
+    QTT_HIP(hipGetLastError());                                                                      \
+    return;                                                                                          \
+  }
+  QTT_QRG_CONFIGS(QTT_QR_REFL)
+#undef QTT_QR_REFL
+}
+
+void qr_form_q_launch(int m, int n, const double* work, double* Q, int ldq, hipStream_t s) {
+  const int rpl = qr_grp_rpl(m, n);
+  QTT_REQUIRE(rpl > 0 && ldq >= n, "qr: no Q kernel for %d x %d", m, n);
+  rt::check_range(work, 0, (int64_t)m * n + n - 1, sizeof(double), "qr reflectors");
+  rt::check_range(Q, 0, (int64_t)(m - 1) * ldq + n - 1, sizeof(double), "qr Q");
+  const rt::Fuse& fu = rt::fuse();
+  if (fu.n > 1) {
+    rt::fuse_check(work, 8 * ((int64_t)m * n + n), "qr reflectors");
+    rt::fuse_check(Q, 8 * ((int64_t)(m - 1) * ldq + n), "qr Q");
+  }
+  if (rt::dry()) return;
+  const dim3 grid((n + 15) / 16, fu.n);
+  const int64_t is = fu.stride;
+  const double* tau = work + (int64_t)m * n;
+#define QTT_QR_FORM(RPL_, CS_, NW_)                                                                   \
+  if (rpl == RPL_) {                                                                                  \
+    hipLaunchKernelGGL((qr_q_kernel<RPL_>), grid, dim3(256), 0, s, m, n, work, tau, Q, ldq, is);         \
+    QTT_HIP(hipGetLastError());                                                                      \
+    return;                                                                                          \
+  }
+  QTT_QRG_CONFIGS(QTT_QR_FORM)
+#undef QTT_QR_FORM
+}
+
 std::string qr_path_name(int m, int n) {
   const std::string k = qr_kernel_name(m, n);
   return (k == "qr_kernel" && m <= QB_MAXM) ? std::string("qr_blocked") : k;
@@ -1381,6 +1545,14 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
     rt::check_range(work, 0, qr_work_size(1, m, n) - 1, sizeof(double), "qr workspace");
     rt::fuse_refuse("the blocked QR");
     qr_blocked(m, n, A, rs, cs, Q, lq, R, work, s);
+    return;
+  }
+  // One matrix, Q only, with a workspace for the reflectors: the group
+  // kernels leave the reflectors and qr_q_kernel forms Q across workgroups
+  // (QTTPDF_QR_SPLIT=0 keeps Q in the factorising workgroup).
+  if (count == 1 && sq == nullptr && R == nullptr && work != nullptr && qr_split(m, n, work_size)) {
+    qr_reflectors_launch(m, n, A, rs, cs, work, s);
+    qr_form_q_launch(m, n, work, Q, lq, s);
     return;
   }
   const rt::Fuse& fu = rt::fuse();

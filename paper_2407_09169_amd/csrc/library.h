@@ -234,6 +234,10 @@ void add_tc(Plan& plan, TcDesc d, Prec p);
 void add_gemm(Plan& plan, int M, int N, int K, const double* A, int64_t lda, bool ta, const double* B,
               int64_t ldb, bool tb, double* C, int64_t ldc, double alpha, double beta, Prec p);
 OpInfo qr_info(int m, int n);
+// thin Q of one m x n matrix (A at rows rs, columns cs apart; Q with ld n):
+// one launch, or the reflector and Q launches of qr_split as two ops
+void add_qr_q(Plan& plan, int m, int n, const double* A, int64_t rs, int64_t cs, double* Q, double* work,
+              int64_t work_size);
 // LQ sweep + QR sweep + simultaneous truncation of an explicit chain
 void plan_round_det(Plan& plan, const ChainView& x, RoundTarget& target);
 // QR sweep only: left-orthogonal copy (returns caps of the result); used for norms

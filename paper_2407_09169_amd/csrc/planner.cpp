@@ -106,6 +106,25 @@ OpInfo qr_info(int m, int n) {
   return oi;
 }
 
+void add_qr_q(Plan& plan, int m, int n, const double* A, int64_t rs, int64_t cs, double* Q, double* work,
+              int64_t work_size) {
+  if (!qr_split(m, n, work_size)) {
+    plan.add([=](hipStream_t s) { qr_launch(1, m, n, A, 0, rs, cs, Q, 0, nullptr, 0, work, s, nullptr, 0, work_size); },
+             qr_info(m, n));
+    return;
+  }
+  const std::string shape = "|m" + std::to_string(m) + " n" + std::to_string(n);
+  OpInfo f;  // the factorisation: read A, write the reflectors
+  f.kind = OP_QR;
+  f.flops = 2.0 * m * (double)n * n - 2.0 * n * (double)n * n / 3.0;
+  f.bytes = 8.0 * (2.0 * m * (double)n + n);
+  f.what = qr_kernel_name(m, n) + shape;
+  plan.add([=](hipStream_t s) { qr_reflectors_launch(m, n, A, rs, cs, work, s); }, f);
+  OpInfo q = f;  // thin Q from the reflectors: as many flops, read the reflectors, write Q
+  q.what = qr_q_kernel_name(m, n) + shape;
+  plan.add([=](hipStream_t s) { qr_form_q_launch(m, n, work, Q, n, s); }, q);
+}
+
 Plan::~Plan() {
   for (auto e : events)
     if (e) (void)hipEventDestroy(e);
@@ -574,8 +593,7 @@ void plan_round_sketch(Plan& plan, const std::vector<SketchTerm>& terms, const C
     {
       double* Xn = X[n];
       const int m = 2 * l, nc = lp;
-      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, S, 0, nc, 1, Xn, 0, nullptr, 0, qrw, s, nullptr, 0, qrws); },
-               qr_info(m, nc));
+      add_qr_q(plan, m, nc, S, nc, 1, Xn, qrw, qrws);
     }
     plan.fork(L);
     for (int j = 0; j < J; ++j) {

@@ -638,8 +638,7 @@ void ts_left_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double*
       double* qw = r.qwL;
       const int64_t qws = r.qwsz;
       const int m = 2 * l, nc = lp;
-      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, SL, 0, nc, 1, Xn, 0, nullptr, 0, qw, s, nullptr, 0, qws); },
-               qr_info(m, nc));
+      add_qr_q(plan, m, nc, SL, nc, 1, Xn, qw, qws);
     }
     for (const auto& g : r.groups) {  // M'_j = X_n^T C_j
       std::vector<TcDesc> ds;
@@ -692,8 +691,7 @@ void ts_right_sweep(Plan& plan, TwoSided& r, const std::vector<int>& ell, double
       double* qw = r.qwR;
       const int64_t qws = r.qwsz;
       const int m = 2 * lp, nc = l;
-      plan.add([=](hipStream_t s) { qr_launch(1, m, nc, SR, 0, 1, m, Vn, 0, nullptr, 0, qw, s, nullptr, 0, qws); },
-               qr_info(m, nc));
+      add_qr_q(plan, m, nc, SR, 1, m, Vn, qw, qws);
     }
     for (const auto& g : r.groups) {  // Mr_j[(a,A),y] = sum_(t,z) Cr_j[(a,A),(t,z)] Vt[(t,z),y]
       std::vector<TcDesc> ds;

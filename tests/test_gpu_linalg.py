@@ -29,6 +29,26 @@ def test_qr(ctx, m, n):
         assert np.max(np.abs(np.tril(R[b], -1))) == 0.0
 
 
+@pytest.mark.parametrize("m,n", [(288, 144), (256, 128), (192, 96), (144, 144), (160, 80), (100, 37), (576, 32)])
+def test_qr_q_only_split(ctx, m, n):
+    """One matrix, Q only (the sweeps' call): the factorising workgroup leaves
+    the reflectors and Q is formed across workgroups of 16 columns.  Same Q
+    as the factorisation that forms Q itself (with R), to rounding, for
+    random, exactly rank-deficient and graded matrices."""
+    rng = np.random.default_rng(m * 13 + n)
+    for kind in ("random", "rank deficient", "graded"):
+        A = rng.standard_normal((1, m, n))
+        if kind == "rank deficient":
+            A[0, :, n // 2:] = 0.0
+        if kind == "graded":
+            A[0] *= np.logspace(0, -12, n)[None, :]
+        Qs, _ = q.linalg_qr(ctx, A, with_r=False)
+        Qf, R = q.linalg_qr(ctx, A)
+        assert np.max(np.abs(Qs[0].T @ Qs[0] - np.eye(n))) < 50 * n * 2.2e-16, kind
+        assert np.max(np.abs(Qs[0] @ R[0] - A[0])) <= 50 * n * 2.2e-16 * np.abs(A[0]).max(), kind
+        assert np.max(np.abs(Qs[0] - Qf[0])) < 1e-12, kind
+
+
 @pytest.mark.parametrize("m,n", [(576, 288), (576, 100), (500, 250), (400, 33), (333, 257)])
 def test_qr_single_blocked(ctx, m, n):
     """One matrix beyond the register kernels: blocked Householder (register
