@@ -17,10 +17,12 @@ in front.
 Schedule of one RK4 step (RK2 is the Heun analogue):
 
     L(g)  = Round_chi( A(g) g ),   A(g) = A_fixed - Omega sum_a D1g^(phi_a) diag(m~_a(g))
-    k1 = L(f); k2 = L(f + dt/2 k1); k3 = L(f + dt/2 k2); k4 = L(f + dt k3)
-    f+ = Round_chi( f + dt/6 k1 + dt/3 k2 + dt/3 k3 + dt/6 k4 )
+    k1 = L(f); k2 = L(f + dt/2 k1); k3 = L(f + dt/2 k2)
+    f+ = Round_chi( f + dt/6 k1 + dt/3 k2 + dt/3 k3 + dt/6 A(g4) g4 ),   g4 = f + dt k3
 
-where the stage inputs f + c k are exact (block-diagonal) sums, m~_a(g) is
+where the stage inputs f + c k are exact (block-diagonal) sums, the last
+stage's product A(g4) g4 is never rounded by itself (its terms join the
+final rounding: f is rounded once per step, each earlier slope once), m~_a(g) is
 the raw mean composition of g rounded to chi_mean, and Round is the
 randomized range finder followed by simultaneous SVD truncation
 (``oracle.tt.round_sketch_two_sided``: the chain is orthogonalised from both
@@ -279,18 +281,28 @@ class MPSStepper:
             return g
 
         if w.integrator == "rk4":
+            c_last, b = dt, [dt / 6, dt / 3, dt / 3, dt / 6]
             k1 = L(f)
             k2 = L(stage_input(0.5 * dt, k1))
             k3 = L(stage_input(0.5 * dt, k2))
-            k4 = L(stage_input(dt, k3))
-            comb = [(1.0, f), (dt / 6, k1), (dt / 3, k2), (dt / 3, k3), (dt / 6, k4)]
+            ks = [k1, k2, k3]
         elif w.integrator == "rk2":
-            k1 = L(f)
-            k2 = L(stage_input(dt, k1))
-            comb = [(1.0, f), (0.5 * dt, k1), (0.5 * dt, k2)]
+            c_last, b = dt, [0.5 * dt, 0.5 * dt]
+            ks = [L(f)]
         else:
             raise ValueError(w.integrator)
-        fn, info = self._combine(comb)
+        g_last = stage_input(c_last, ks[-1])
+        comb = [(1.0, f)] + [(bi, k) for bi, k in zip(b, ks)]
+        if self.rounding == "svd":
+            # the paper's plain schedule: the last product rounded, then the sum
+            comb.append((b[-1], L(g_last)))
+            fn, info = self._combine(comb)
+        else:
+            # the last stage's product A(g) g is not rounded by itself: its
+            # terms, weighted by b_S, join the rounding of the combination
+            terms = [(c, None, x) for c, x in comb]
+            terms += [(b[-1] * c, W, g_last) for c, W in self.operator_terms(g_last)]
+            fn, info = tt.round_sketch_two_sided(terms, self.Z, self.Zl, w.chi, w.rel_tol)
         infos.append(info)
         return fn, infos
 

@@ -478,9 +478,11 @@ struct Tangent {
 //   dk_i = Round( A(g_i) dg_i + B_q(g_i, dg_i) g_i ),
 //   B_q = dA_fix/dq - sum_a D1g^(phi_a) diag(alpha_q <Phi_a>(g_i) + Omega <Phi_a>(dg_i)),
 // alpha_Omega = 1, alpha_k = 0 (the mean field enters A through -Omega m_a(g)),
-// and df+ = Round(df + sum_i b_i dk_i) beside f+ = Round(f + sum_i b_i k_i).
-// A and B_q carry dt, so k_i and dk_i are increments (dt times the slopes)
-// and c_i, b_i are the tableau's plain numbers.
+// and df+ = Round(df + sum_i b_i dk_i) beside f+ = Round(f + sum_i b_i k_i),
+// where the last stage's k_S = A(g_S) g_S (and dk_S) enters the final
+// rounding unrounded, as its MPO x MPS terms.  A and B_q carry dt, so k_i
+// and dk_i are increments (dt times the slopes) and c_i, b_i are the
+// tableau's plain numbers.
 static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vector<Tangent>& tan) {
   auto plan = std::make_unique<Plan>();
   const tt_params& p = P->p;
@@ -508,11 +510,20 @@ static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vec
     tg.caps = P->fcaps;
     return tg;
   };
+  const double b4[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6}, b2[2] = {0.5, 0.5};
+  const double* b = rk4 ? b4 : b2;
+  // The last stage's product is never rounded by itself: its terms, weighted
+  // by b_S, join the final combination's rounding (f is rounded once per
+  // step, the slopes k_1 .. k_(S-1) once each).
+  std::vector<SketchTerm> last;
+  std::vector<std::vector<SketchTerm>> last_t(tan.size());
   plan_mean_raw(*plan, P, f, P->Ef.d(), P->mff.d());
   for (const Tangent& t : tan) plan_mean_raw(*plan, P, t.df, P->Edf[t.q].d(), P->mfdf[t.q].d());
   for (int i = 0; i < S; ++i) {
     const tt_tt* kp = (i == 0) ? nullptr : P->k[i - 1].get();
     const double cg = cst[i];
+    const bool final_stage = (i == S - 1);
+    const double w = final_stage ? b[i] : 1.0;
     if (kp) plan_mean_raw(*plan, P, kp, P->Ek.d(), P->mfk.d());
     const bool split = P->split_mf && tan.empty();
     plan_stage_operator(*plan, P, f, kp, cg, split);
@@ -522,20 +533,24 @@ static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vec
         // F g + sum_a MF_a g, g = f + cg kp: the mean-field terms' x sites are diagonal
         for (const ChainView* W : {&P->Fv, &P->MFv[0], &P->MFv[1]}) {
           const int df = (W == &P->Fv) ? -1 : P->nphi;
-          terms.push_back(sterm(1.0, W, f));
+          terms.push_back(sterm(w, W, f));
           terms.back().diag_from = df;
           if (kp) {
-            terms.push_back(sterm(cg, W, kp));
+            terms.push_back(sterm(w * cg, W, kp));
             terms.back().diag_from = df;
           }
         }
       } else {
-        terms.push_back(sterm(1.0, &Av, f));
-        if (kp) terms.push_back(sterm(cg, &Av, kp));
+        terms.push_back(sterm(w, &Av, f));
+        if (kp) terms.push_back(sterm(w * cg, &Av, kp));
       }
-      RoundTarget tg = target(P->k[i].get());
-      plan_round_sketch_two_sided(*plan, terms, Z, Zl, tg, prec);
-      plan_check_finite(*plan, P->k[i].get(), P->nonfinite.as<int>());
+      if (final_stage) {
+        last = terms;
+      } else {
+        RoundTarget tg = target(P->k[i].get());
+        plan_round_sketch_two_sided(*plan, terms, Z, Zl, tg, prec);
+        plan_check_finite(*plan, P->k[i].get(), P->nonfinite.as<int>());
+      }
     }
     for (size_t j = 0; j < tan.size(); ++j) {
       const int q = tan[j].q;
@@ -552,32 +567,36 @@ static std::unique_ptr<Plan> record_step(tt_problem* P, tt_tt* f, const std::vec
       tt_tt* mt[2] = {P->mtt[q][0].get(), P->mtt[q][1].get()};
       plan_mean_round(*plan, P, mterms, mt);
       plan_mf_blocks(*plan, P, P->Bt[q].get(), P->Dfix_t[q], mt);
-      std::vector<SketchTerm> terms{sterm(1.0, &Av, df), sterm(1.0, &Bv[j], f)};
+      std::vector<SketchTerm> terms{sterm(w, &Av, df), sterm(w, &Bv[j], f)};
       if (kp) {
-        terms.push_back(sterm(cg, &Av, dkp));
-        terms.push_back(sterm(cg, &Bv[j], kp));
+        terms.push_back(sterm(w * cg, &Av, dkp));
+        terms.push_back(sterm(w * cg, &Bv[j], kp));
       }
-      RoundTarget tg = target(P->dk[q][i].get());
-      plan_round_sketch_two_sided(*plan, terms, Z, Zl, tg, prec);
-      plan_check_finite(*plan, P->dk[q][i].get(), P->nonfinite.as<int>());
+      if (final_stage) {
+        last_t[j] = terms;
+      } else {
+        RoundTarget tg = target(P->dk[q][i].get());
+        plan_round_sketch_two_sided(*plan, terms, Z, Zl, tg, prec);
+        plan_check_finite(*plan, P->dk[q][i].get(), P->nonfinite.as<int>());
+      }
     }
   }
-  const double b4[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6}, b2[2] = {0.5, 0.5};
-  const double* b = rk4 ? b4 : b2;
   // The final combination is dominated by f itself, whose every digit the
   // next step inherits: its sketches run in the data precision (FP32 when
   // BF16 is requested), while BF16 serves the sketches of the stage slopes,
   // whose errors enter f+ weighted by dt.
-  auto combine = [&](tt_tt* x, std::unique_ptr<tt_tt>* ks) {
+  auto combine = [&](tt_tt* x, std::unique_ptr<tt_tt>* ks, const std::vector<SketchTerm>& tail) {
     std::vector<SketchTerm> comb{sterm(1.0, nullptr, x)};
-    for (int i = 0; i < S; ++i) comb.push_back(sterm(b[i], nullptr, ks[i].get()));
+    for (int i = 0; i + 1 < S; ++i) comb.push_back(sterm(b[i], nullptr, ks[i].get()));
+    comb.insert(comb.end(), tail.begin(), tail.end());
     RoundTarget tg = target(x);
     plan_round_sketch_two_sided(*plan, comb, Z, Zl, tg, data_prec(prec));
     plan_check_finite(*plan, x, P->nonfinite.as<int>());
     return tg;
   };
-  P->last = combine(f, P->k);
-  for (const Tangent& t : tan) combine(t.df, P->dk[t.q]);
+  // the tangents' final terms read f (B_q f): their roundings go before f's own
+  for (size_t j = 0; j < tan.size(); ++j) combine(tan[j].df, P->dk[tan[j].q], last_t[j]);
+  P->last = combine(f, P->k, last);
   return plan;
 }
 
