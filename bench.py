@@ -382,6 +382,10 @@ def _bench_flow(args, log):
     from paper_2407_09169_amd import flow
     import workloads
     w = workloads.get_workload("c2_5d_M128_chi64", k_react=0.0, integrator="rk2", ic="paper")
+    if args.chi:
+        w = w.replace(chi=args.chi)
+    if args.dt:
+        w = w.replace(dt=args.dt)
     if args.chi_mean:
         w = w.replace(chi_mean=args.chi_mean, oversample_mean=8)
     ctx = q.Context(0)
@@ -389,11 +393,13 @@ def _bench_flow(args, log):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = flow.run(ctx, w, n_samples=17, steps_per_sample=k, dtype=args.dtype, fields="smagorinsky",
-                 chi_field=16, c_omega=1.0)
+                 chi_field=16, c_omega=1.0,
+                 on_sample=lambda t, T: log(f"flow sample {t + 1}/{T} at step {t * k}"),
+                 sketch_seed=args.sketch_seed)
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
     steps = 16 * k
-    log(f"flow protocol 128^5 chi=64: {steps} steps and 17 samples in {sec:.2f} s; "
+    log(f"flow protocol 128^5 chi={w.chi} chi_mean={w.chi_mean}: {steps} steps and 17 samples in {sec:.2f} s; "
         f"E2b up {r['E2b_up']:.3e} down {r['E2b_down']:.3e}, E2c up {r['E2c_up']:.3e} down {r['E2c_down']:.3e}")
     out = {
         "metric": "flow-protocol steps/s (MPS step + moment equation + 17 samples of the error measures)",
@@ -402,7 +408,8 @@ def _bench_flow(args, log):
         "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": "flow_c2_5d_M128_chi64", "grid": "128^5", "chi": w.chi,
                    "integrator": "rk2", "k_react": 0.0, "dt": w.dt, "samples": 17, "chi_mean": w.chi_mean,
-                   "steps_per_sample": k,
+                   "steps_per_sample": k, "sketch_seed": w.seed if args.sketch_seed is None else args.sketch_seed,
+                   "autotune": os.environ.get("QTTPDF_AUTOTUNE", "1")[:1] != "0",
                    "fields": "Smagorinsky G(x) (C_s 0.11, Delta 3/M, bond 16), Omega = G / Delta^2",
                    "initial_state": "eq. initPDF, eq. velField"},
         "errors": {"E2b_up": r["E2b_up"], "E2b_down": r["E2b_down"], "E2c_up": r["E2c_up"],
@@ -616,6 +623,12 @@ def main():
                     help="only run a plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--chi-mean", type=int, default=0,
                     help="bond cap of the mean compositions in the flow protocol (default: the workload's)")
+    ap.add_argument("--chi", type=int, default=0,
+                    help="bond cap chi of the PDF in the flow protocol (default: the workload's, 64)")
+    ap.add_argument("--dt", type=float, default=0.0,
+                    help="time step of the flow protocol (default: the workload's, 1e-3)")
+    ap.add_argument("--sketch-seed", type=int, default=None,
+                    help="seed of the Gaussian sketches in the flow protocol (default: the workload's)")
     ap.add_argument("--chi-mean-study", action="store_true",
                     help="FP64 steps/s and L2 distance to the uncapped mean field for chi_mean in "
                          "{8, 16, 32, chi} on the 128^5 and 1024^5 workloads")

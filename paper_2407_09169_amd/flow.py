@@ -51,7 +51,7 @@ def smagorinsky_fields(ctx, w, chi_field, c_omega=1.0):
 
 
 def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None, fields=False,
-        chi_field=16, c_omega=1.0):
+        chi_field=16, c_omega=1.0, on_sample=None, sketch_seed=None):
     """Advances workload w (5-D) for (n_samples - 1) * steps_per_sample steps,
     sampling at every steps_per_sample steps from t = 0.
 
@@ -62,7 +62,9 @@ def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None, field
     or False (skip it).  fields=True runs the problem with the seeded x-fields
     G(x) and Omega(x) (setup_workload), fields="smagorinsky" with the paper's
     closure (smagorinsky_fields, G cut to chi_field, Omega = c_omega G /
-    Delta^2); the moment equation then uses the same G(x)."""
+    Delta^2); the moment equation then uses the same G(x).  on_sample(t, T),
+    if given, is called after sample t of T has been taken; sketch_seed draws
+    the Gaussian sketches from another seed (setup_workload)."""
     import torch
     import workloads
 
@@ -77,9 +79,9 @@ def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None, field
     fdisc = None
     if fields == "smagorinsky":
         fx, fdisc, G_closure = smagorinsky_fields(ctx, w, chi_field, c_omega)
-        prob, f = setup_workload(ctx, w, dtype, fields=fx)
+        prob, f = setup_workload(ctx, w, dtype, fields=fx, sketch_seed=sketch_seed)
     else:
-        prob, f = setup_workload(ctx, w, dtype, fields=fields)
+        prob, f = setup_workload(ctx, w, dtype, fields=fields, sketch_seed=sketch_seed)
     phi = (np.arange(M) + 0.5) / M
     dense = torch.empty(n, dtype=torch.float64, device=dev)
     m = work = U = G = None
@@ -123,6 +125,8 @@ def run(ctx, w, n_samples=17, steps_per_sample=1, dtype="f64", exact=None, field
                 to_dense(ctx, x, dense)
                 x.free()
                 sq_mean_x[a, t] = sq_diff_sum(ctx, dense, m[a * n:(a + 1) * n]) / n
+        if on_sample is not None:
+            on_sample(t, T)
     e = error_measures(mean_bar, sq_mean_x if exact else None, sq_norm_x)
     _, max_bond = prob.info()
     f.free()
