@@ -139,8 +139,8 @@ def _roofline(rows):
         # CUs such a launch occupies (the blocked QR spreads over the chip)
         m = re.match(r"b(\d+) ", shape)
         cus = int(m.group(1)) if m else 1
-        if kernel.startswith("qr_q_kernel"):  # workgroups of 16 columns of Q
-            cus = -(-int(re.search(r"n(\d+)", shape).group(1)) // 16)
+        if kernel.startswith("qr_q_kernel"):  # workgroups of 4 columns of Q
+            cus = -(-int(re.search(r"n(\d+)", shape).group(1)) // 4)
         roof["cus_per_launch"] = cus
         roof["frac_of_cus_used"] = roof["achieved"] / (roof["peak"] * cus / N_CU)
     return roof

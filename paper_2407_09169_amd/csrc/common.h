@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -118,10 +119,26 @@ void alloc_count_reset();
 size_t alloc_count();
 }  // namespace rt
 
-// pointer shifted by a byte offset (null stays null)
+// pointer shifted by a byte offset (null stays null).  The offset is added to
+// a byte pointer, not to an integer: in device code the result then keeps the
+// global address space the compiler infers for a kernel argument, so the
+// accesses through it stay global loads and stores (a round trip through an
+// integer would turn them into flat accesses, which also wait on LDS traffic)
 template <class T>
 __host__ __device__ inline T* ishift(T* p, int64_t bytes) {
-  return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)bytes) : p;
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return p ? reinterpret_cast<T*>(reinterpret_cast<B*>(p) + bytes) : p;
+}
+
+// p taken as a pointer into device (global) memory, which every buffer a
+// kernel here receives is.  For pointers the compiler cannot trace to a
+// kernel argument (fields of a descriptor passed by value, pointer tables in
+// device memory) accesses through the result are global instead of flat ones
+// (a flat load also holds up every later wait for LDS traffic).
+typedef __attribute__((address_space(1))) double gdouble;
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* as_global(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
 }
 
 // ---------------------------------------------------------------------------

@@ -693,24 +693,52 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
 
 // ---------------------------------------------------------------------------
 // Thin Q of a factorisation left as reflectors (V: m x n, row-major, unit
-// diagonal, zeros above; tau: n), Q = H_0 H_1 ... H_(n-1) [I; 0], spread over
-// workgroups of 16 columns (the columns of Q are independent given the
-// reflectors).  Layout of qr_grp_kernel: column c = 16 blockIdx.x + 4 w + g
-// on the 16 lanes of group g of wavefront w, rows li + 16 r (r < RPL).
+// diagonal, zeros above; tau: n), Q = H_0 H_1 ... H_(n-1) [I; 0], one column
+// per wavefront: column c = QQ_NW blockIdx.x + w, rows lane + 64 r (r < RW).
 // Column c starts as e_c and takes the reflectors from the last to the first
-// (those past c leave it unchanged: v_k vanishes above row k).  The
-// reflectors pass through LDS in chunks of KC, double-buffered: the next
-// chunk's global loads are in flight while the current chunk is applied.
+// (those past c leave it unchanged: v_k vanishes above row k).  Reflectors
+// pass through LDS in double-buffered chunks of KC.  A column takes them in
+// pairs: with a = v_k, b = v_(k-1) and q the column, the dot products a.q
+// and b.q and the product a.b go through one wavefront sum, and then
+//   d_a = a.q,  d_b = b.q - tau_k d_a (a.b),  q -= tau_k d_a a + tau_(k-1) d_b b,
+// which is H_(k-1) H_k q.  That halves the chain of sums a column waits on;
+// the next pair's vectors are read from LDS while the current sums run.
 // ---------------------------------------------------------------------------
-template <int RPL>
-__global__ __launch_bounds__(256) void qr_q_kernel(int m, int n, const double* __restrict__ V,
-                                                   const double* __restrict__ tau, double* __restrict__ Q, int ldq,
-                                                   int64_t istride) {
-  constexpr int KC = RPL > 18 ? 8 : 16;
-  constexpr int MR = 16 * RPL;
-  constexpr int NPRE = KC * MR / 256;
-  static_assert(NPRE * 256 == KC * MR, "chunk must split evenly over the workgroup");
-  __shared__ double Vs[2][KC][MR];  // reflectors of a chunk, one row of Vs per reflector
+constexpr int QQ_NW = 4;  // columns (wavefronts) per workgroup
+
+// sums of K values over the wavefront at once (the K chains interleave), in
+// every lane: the four in-row steps take no old value (every lane of a row is
+// valid), the two row broadcasts add into the masked rows only, and lane 63,
+// which then holds the total, is read into scalar registers
+template <int K>
+__device__ inline void wave_sum_k(double (&x)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += dpp_row<0xB1>(x[k]);   // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += dpp_row<0x4E>(x[k]);   // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += dpp_row<0x141>(x[k]);  // row_half_mirror
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += dpp_row<0x140>(x[k]);  // row_mirror
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += dpp_move<0x142, 0xA>(x[k]);  // row_bcast:15 into rows 1, 3
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] += dpp_move<0x143, 0xC>(x[k]);  // row_bcast:31 into rows 2, 3
+#pragma unroll
+  for (int k = 0; k < K; ++k) x[k] = read_lane(x[k], 63);
+}
+
+template <int RW>
+__global__ __launch_bounds__(QQ_NW * 64) void qr_q_kernel(int m, int n, const double* __restrict__ V,
+                                                        const double* __restrict__ tau, double* __restrict__ Q,
+                                                        int ldq, int64_t istride) {
+  constexpr int NWQ = QQ_NW;
+  constexpr int NT = NWQ * 64;
+  constexpr int KC = RW > 5 ? 8 : 16;
+  constexpr int MR = 64 * RW;
+  constexpr int NPRE = KC * MR / NT;
+  static_assert(NPRE * NT == KC * MR, "chunk must split evenly over the workgroup");
+  __shared__ double Vs[2][KC][MR + 1];  // odd row stride: a row's KC stores land on distinct banks
   __shared__ double ts[2][KC];
   {  // instance of a fused launch (grid y)
     const int64_t io = (int64_t)blockIdx.y * istride;
@@ -721,19 +749,17 @@ __global__ __launch_bounds__(256) void qr_q_kernel(int m, int n, const double* _
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int g = lane >> 4, li = lane & 15;
-  const int c = (int)blockIdx.x * 16 + 4 * w + g;
-  double q[RPL];
+  const int c = (int)blockIdx.x * NWQ + w;  // wave-uniform
+  double q[RW];
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) q[r] = (li + 16 * r == c) ? 1.0 : 0.0;
-  // chunk with top reflector khi: reflectors khi, khi - 1, ..., khi - KC + 1
-  // (those below 0 are zero); element e: reflector khi - e % KC, row e / KC
-  // (a row's KC values are contiguous in V)
+  for (int r = 0; r < RW; ++r) q[r] = (lane + 64 * r == c) ? 1.0 : 0.0;
+  // chunk with top reflector khi: element e is reflector khi - e % KC, row e / KC
+  // (every element of a chunk is written: zero past row m and below k = 0)
   double pre[NPRE];
   auto load = [&](int khi) {
 #pragma unroll
     for (int i = 0; i < NPRE; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       const int k = khi - e % KC, row = e / KC;
       pre[i] = (k >= 0 && row < m) ? V[(int64_t)row * n + k] : 0.0;
     }
@@ -741,12 +767,16 @@ __global__ __launch_bounds__(256) void qr_q_kernel(int m, int n, const double* _
   auto store = [&](int buf, int khi) {
 #pragma unroll
     for (int i = 0; i < NPRE; ++i) {
-      const int e = tid + 256 * i;
+      const int e = tid + NT * i;
       Vs[buf][e % KC][e / KC] = pre[i];
     }
     if (tid < KC) ts[buf][tid] = (khi - tid >= 0) ? tau[khi - tid] : 0.0;
   };
-  int khi = min(n - 1, (int)blockIdx.x * 16 + 15);
+  auto vec = [&](double (&x)[RW], int buf, int kk) {
+#pragma unroll
+    for (int r = 0; r < RW; ++r) x[r] = Vs[buf][kk][lane + 64 * r];
+  };
+  int khi = min(n - 1, (int)blockIdx.x * NWQ + NWQ - 1);
   load(khi);
   store(0, khi);
   __syncthreads();
@@ -755,17 +785,53 @@ __global__ __launch_bounds__(256) void qr_q_kernel(int m, int n, const double* _
     const int knext = khi - KC;
     if (knext >= 0) load(knext);
     const int kn = min(KC, khi + 1);
-    for (int kk = 0; kk < kn; ++kk) {
-      const double t = ts[buf][kk];
-      double v[RPL];
+    int kk = max(0, khi - c);  // H_k with k > c leaves column c unchanged
+    // pair step on (a, b) = (v_k, v_(k-1)) of this chunk, reading the next
+    // pair into (na, nb) meanwhile (indices clamped into the chunk)
+    auto pair = [&](const double (&a)[RW], const double (&b)[RW], double (&na)[RW], double (&nb)[RW])
+        __attribute__((always_inline)) {
+      const double ta = ts[buf][kk], tb = ts[buf][kk + 1];
+      double x[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) v[r] = Vs[buf][kk][li + 16 * r];
-      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int r = 0; r < RW; ++r) {
+        x[0] = fma(a[r], q[r], x[0]);
+        x[1] = fma(b[r], q[r], x[1]);
+        x[2] = fma(a[r], b[r], x[2]);
+      }
+      vec(na, buf, min(kk + 2, KC - 1));
+      vec(nb, buf, min(kk + 3, KC - 1));
+      wave_sum_k<3>(x);
+      const double wa = ta * x[0];
+      const double wb = tb * (x[1] - wa * x[2]);
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) acc[r & 3] = fma(v[r], q[r], acc[r & 3]);
-      const double wgt = t * row_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
+      for (int r = 0; r < RW; ++r) q[r] = fma(-wb, b[r], fma(-wa, a[r], q[r]));
+      kk += 2;
+    };
+    auto single = [&](const double (&a)[RW]) __attribute__((always_inline)) {
+      double x[1] = {0.0};
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) q[r] = fma(-wgt, v[r], q[r]);
+      for (int r = 0; r < RW; ++r) x[0] = fma(a[r], q[r], x[0]);
+      wave_sum_k<1>(x);
+      const double wa = ts[buf][kk] * x[0];
+#pragma unroll
+      for (int r = 0; r < RW; ++r) q[r] = fma(-wa, a[r], q[r]);
+    };
+    if (kk < kn) {  // wave-uniform
+      double a[RW], b[RW], na[RW], nb[RW];
+      vec(a, buf, kk);
+      vec(b, buf, min(kk + 1, KC - 1));
+      for (;;) {  // pairs, alternating between the two register sets
+        if (kk + 1 >= kn) {
+          if (kk < kn) single(a);
+          break;
+        }
+        pair(a, b, na, nb);
+        if (kk + 1 >= kn) {
+          if (kk < kn) single(na);
+          break;
+        }
+        pair(na, nb, a, b);
+      }
     }
     if (knext >= 0) store(buf ^ 1, knext);
     __syncthreads();
@@ -774,8 +840,8 @@ __global__ __launch_bounds__(256) void qr_q_kernel(int m, int n, const double* _
   }
   if (c < n) {
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int row = li + 16 * r;
+    for (int r = 0; r < RW; ++r) {
+      const int row = lane + 64 * r;
       if (row < m) Q[(int64_t)row * ldq + c] = q[r];
     }
   }
@@ -1470,7 +1536,11 @@ bool qr_split(int m, int n, int64_t work_size) {
   return qr_split_on() && qr_grp_rpl(m, n) > 0 && work_size >= (int64_t)m * n + n;
 }
 
-std::string qr_q_kernel_name(int m, int n) { return "qr_q_kernel<" + std::to_string(qr_grp_rpl(m, n)) + ">"; }
+// rows per lane of qr_q_kernel for the reflectors of an m x n factorisation
+// (the row count the reflector kernel covers, over 64 lanes)
+int qr_q_rows(int m, int n) { return (16 * qr_grp_rpl(m, n) + 63) / 64; }
+
+std::string qr_q_kernel_name(int m, int n) { return "qr_q_kernel<" + std::to_string(qr_q_rows(m, n)) + ">"; }
 
 void qr_reflectors_launch(int m, int n, const double* A, int64_t rs, int64_t cs, double* work, hipStream_t s) {
   QTT_REQUIRE(qr_grp_rpl(m, n) > 0, "qr: no reflector kernel for %d x %d", m, n);
@@ -1507,17 +1577,19 @@ void qr_form_q_launch(int m, int n, const double* work, double* Q, int ldq, hipS
     rt::fuse_check(Q, 8 * ((int64_t)(m - 1) * ldq + n), "qr Q");
   }
   if (rt::dry()) return;
-  const dim3 grid((n + 15) / 16, fu.n);
   const int64_t is = fu.stride;
   const double* tau = work + (int64_t)m * n;
-#define QTT_QR_FORM(RPL_, CS_, NW_)                                                                   \
-  if (rpl == RPL_) {                                                                                  \
-    hipLaunchKernelGGL((qr_q_kernel<RPL_>), grid, dim3(256), 0, s, m, n, work, tau, Q, ldq, is);         \
-    QTT_HIP(hipGetLastError());                                                                      \
-    return;                                                                                          \
+  const dim3 grid((n + QQ_NW - 1) / QQ_NW, fu.n);
+  const int rw = qr_q_rows(m, n);
+#define QTT_QR_FORM(RW_)                                                                                 \
+  if (rw == RW_) {                                                                                       \
+    hipLaunchKernelGGL((qr_q_kernel<RW_>), grid, dim3(QQ_NW * 64), 0, s, m, n, work, tau, Q, ldq, is);   \
+    QTT_HIP(hipGetLastError());                                                                          \
+    return;                                                                                              \
   }
-  QTT_QRG_CONFIGS(QTT_QR_FORM)
+  QTT_QR_FORM(3) QTT_QR_FORM(4) QTT_QR_FORM(5) QTT_QR_FORM(9)
 #undef QTT_QR_FORM
+  QTT_REQUIRE(false, "qr: no Q kernel for %d rows per lane (%d x %d)", rw, m, n);
 }
 
 std::string qr_path_name(int m, int n) {

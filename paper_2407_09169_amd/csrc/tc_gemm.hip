@@ -63,17 +63,17 @@ __device__ inline KRange k_range(const TcDesc& d) {
 
 // group base pointers from the device table (one scalar load each), shifted
 // to the launch's instance
-__device__ inline const double* base_a(const TcDesc& d, const KRange& kr) {
-  return ishift(d.ng > 1 ? d.gdev[kr.g] : d.A, kr.io) + d.ab.off(kr.z);
+__device__ inline const gdouble* base_a(const TcDesc& d, const KRange& kr) {
+  return as_global(ishift(d.ng > 1 ? d.gdev[kr.g] : d.A, kr.io) + d.ab.off(kr.z));
 }
-__device__ inline const double* base_b(const TcDesc& d, const KRange& kr) {
-  return ishift(d.ng > 1 ? d.gdev[d.ng + kr.g] : d.B, kr.io) + d.bb.off(kr.z);
+__device__ inline const gdouble* base_b(const TcDesc& d, const KRange& kr) {
+  return as_global(ishift(d.ng > 1 ? d.gdev[d.ng + kr.g] : d.B, kr.io) + d.bb.off(kr.z));
 }
-__device__ inline double* base_c(const TcDesc& d, const KRange& kr) {
-  return ishift(d.ng > 1 ? const_cast<double*>(d.gdev[2 * d.ng + kr.g]) : d.C, kr.io) + d.cb.off(kr.z);
+__device__ inline gdouble* base_c(const TcDesc& d, const KRange& kr) {
+  return as_global(ishift(d.ng > 1 ? const_cast<double*>(d.gdev[2 * d.ng + kr.g]) : d.C, kr.io) + d.cb.off(kr.z));
 }
-__device__ inline double* base_part(const TcDesc& d, const KRange& kr) {
-  return ishift(d.part, kr.io) + (int64_t)kr.zz * d.M * d.N;
+__device__ inline gdouble* base_part(const TcDesc& d, const KRange& kr) {
+  return as_global(ishift(d.part, kr.io) + (int64_t)kr.zz * d.M * d.N);
 }
 __device__ inline bool to_part(const TcDesc& d) { return d.ksplit > 1 || (d.ng > 1 && d.gsum); }
 
@@ -87,8 +87,8 @@ __global__ __launch_bounds__(256) void tc_f64_kernel(TcDesc d, int a_kfast, int 
   const int tx = tid & 15, ty = tid >> 4;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const KRange kr = k_range<BK64>(d);
-  const double* A = base_a(d, kr);
-  const double* B = base_b(d, kr);
+  const gdouble* A = base_a(d, kr);
+  const gdouble* B = base_b(d, kr);
   double acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void tc_f64_kernel(TcDesc d, int a_kfast, int 
     __syncthreads();
   }
   if (to_part(d)) {
-    double* Pp = base_part(d, kr);
+    gdouble* Pp = base_part(d, kr);
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
       const int m = m0 + ty + 16 * i;
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void tc_f64_kernel(TcDesc d, int a_kfast, int 
     }
     return;
   }
-  double* C = base_c(d, kr);
+  gdouble* C = base_c(d, kr);
   int64_t coff[TN];
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void tc_f64_kernel(TcDesc d, int a_kfast, int 
     for (int j = 0; j < TN; ++j) {
       const int n = n0 + tx + 16 * j;
       if (n >= d.N) continue;
-      double* p = C + rowoff + coff[j];
+      gdouble* p = C + rowoff + coff[j];
       double v = d.alpha * acc[i][j];
       if (d.beta != 0.0) v += d.beta * *p;
       *p = v;
@@ -216,8 +216,8 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const KRange kr = k_range<BK>(d);
-  const double* A = base_a(d, kr);
-  const double* B = base_b(d, kr);
+  const gdouble* A = base_a(d, kr);
+  const gdouble* B = base_b(d, kr);
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
   }
   // accumulator layout: lane holds rows 4*(lane/16)+r, column lane%16 of each block
   if (to_part(d)) {
-    double* Pp = base_part(d, kr);
+    gdouble* Pp = base_part(d, kr);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
         }
     return;
   }
-  double* C = base_c(d, kr);
+  gdouble* C = base_c(d, kr);
   // output offsets: 8 distinct rows and 2 distinct columns per thread
   int64_t coff[2];
   bool cok[2];
@@ -413,7 +413,7 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         if (!cok[j]) continue;
-        double* p = C + ro + coff[j];
+        gdouble* p = C + ro + coff[j];
         double v = d.alpha * (double)acc[i][j][r];
         if (d.beta != 0.0) v += d.beta * *p;
         *p = v;
@@ -436,11 +436,11 @@ __global__ __launch_bounds__(256) void tc_splitk_reduce(TcDesc d) {
   const int64_t rem = idx - (int64_t)zo * mn;
   const int m = (int)(rem / d.N), n = (int)(rem - (int64_t)m * d.N);
   const int z = zo / gout, g = zo - z * gout;
-  const double* Pp = ishift(d.part, io) + ((int64_t)z * d.ng + g) * d.ksplit * mn + rem;
+  const gdouble* Pp = as_global(ishift(d.part, io) + ((int64_t)z * d.ng + g) * d.ksplit * mn + rem);
   double s = 0.0;
   for (int k = 0; k < nparts; ++k) s += Pp[(int64_t)k * mn];
-  double* base = ishift((d.ng > 1 && !d.gsum) ? const_cast<double*>(d.gdev[2 * d.ng + g]) : d.C, io);
-  double* p = base + d.cb.off(z) + d.cm.off(m) + d.cn.off(n);
+  gdouble* base = as_global(ishift((d.ng > 1 && !d.gsum) ? const_cast<double*>(d.gdev[2 * d.ng + g]) : d.C, io));
+  gdouble* p = base + d.cb.off(z) + d.cm.off(m) + d.cn.off(n);
   double v = d.alpha * s;
   if (d.beta != 0.0) v += d.beta * *p;
   *p = v;
