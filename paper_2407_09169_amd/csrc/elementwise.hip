@@ -29,7 +29,9 @@ __global__ void copy_jobs_kernel(const CopyJob* jobs, int64_t istride) {
   j.dscale = ishift(j.dscale, io);
   const int64_t n = (int64_t)j.rl * j.sp * j.rr;
   double sc = j.scale;
-  if (j.dscale) sc *= *j.dscale;
+  if (j.dscale) sc *= *as_global(j.dscale);
+  const gdouble* src = as_global(j.src);  // table pointers: global accesses
+  gdouble* dst = as_global(j.dst);
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
     int b = (int)(e % j.rr);
@@ -37,7 +39,7 @@ __global__ void copy_jobs_kernel(const CopyJob* jobs, int64_t istride) {
     int s = (int)(q % j.sp);
     int a = (int)(q / j.sp);
     int ds = j.diag ? (s * 2 + s) : s;  // MPS digit s -> MPO entry (t = s, s)
-    j.dst[((int64_t)(j.ro + a) * j.dp + ds) * j.drr + j.co + b] = sc * j.src[e];
+    dst[((int64_t)(j.ro + a) * j.dp + ds) * j.drr + j.co + b] = sc * src[e];
   }
 }
 
@@ -63,6 +65,9 @@ __global__ void apply_jobs_kernel(const ApplyJob* jobs) {
   // out[(a,alpha), t, (b,beta)] = sum_s W[alpha,t,s,beta] x[a,s,b]
   const int OL = j.xl * j.Dl, OR = j.xr * j.Dr;
   const int64_t n = (int64_t)OL * 2 * OR;
+  const gdouble* W = as_global(j.W);  // table pointers: global accesses
+  const gdouble* x = as_global(j.x);
+  gdouble* out = as_global(j.out);
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x) {
     int col = (int)(e % OR);
@@ -74,8 +79,8 @@ __global__ void apply_jobs_kernel(const ApplyJob* jobs) {
     double v = 0.0;
 #pragma unroll
     for (int s = 0; s < 2; ++s)
-      v += prec_mul<PR>(j.W[(((int64_t)al * 2 + t) * 2 + s) * j.Dr + be], j.x[((int64_t)a * 2 + s) * j.xr + b]);
-    j.out[e] = v;
+      v += prec_mul<PR>(W[(((int64_t)al * 2 + t) * 2 + s) * j.Dr + be], x[((int64_t)a * 2 + s) * j.xr + b]);
+    out[e] = v;
   }
 }
 

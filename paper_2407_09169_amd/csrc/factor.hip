@@ -32,6 +32,15 @@ __device__ inline double dpp_move(double x) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// a DPP move within rows whose every lane has a valid source: no old value
+template <int CTRL>
+__device__ inline double dpp_row(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(b & 0xffffffffull), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 __device__ inline double read_lane(double x, int l) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(x);
   const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
@@ -49,13 +58,13 @@ struct OpMax {
 template <class Op, int K>
 __device__ inline void wave_reduce_n(double (&v)[K]) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = Op::f(v[k], dpp_move<0xB1, 0xF>(v[k]));  // quad_perm [1,0,3,2]
+  for (int k = 0; k < K; ++k) v[k] = Op::f(v[k], dpp_row<0xB1>(v[k]));  // quad_perm [1,0,3,2]
 #pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = Op::f(v[k], dpp_move<0x4E, 0xF>(v[k]));  // quad_perm [2,3,0,1]
+  for (int k = 0; k < K; ++k) v[k] = Op::f(v[k], dpp_row<0x4E>(v[k]));  // quad_perm [2,3,0,1]
 #pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = Op::f(v[k], dpp_move<0x141, 0xF>(v[k]));  // row_half_mirror
+  for (int k = 0; k < K; ++k) v[k] = Op::f(v[k], dpp_row<0x141>(v[k]));  // row_half_mirror
 #pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = Op::f(v[k], dpp_move<0x140, 0xF>(v[k]));  // row_mirror
+  for (int k = 0; k < K; ++k) v[k] = Op::f(v[k], dpp_row<0x140>(v[k]));  // row_mirror
   // rows outside the row mask receive 0, the identity of both operations here
   // (the max is only taken over non-negative values)
 #pragma unroll
@@ -428,13 +437,6 @@ __global__ __launch_bounds__(QW * 64) void qr_reg_kernel(int m, int n, const dou
 // Q by backward accumulation, phase by phase: the phase's stored reflectors
 // are published at once and applied with no barrier in between.
 // ---------------------------------------------------------------------------
-template <int CTRL>
-__device__ inline double dpp_row(double x) {  // every row lane valid: no old value
-  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(b & 0xffffffffull), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, true);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
 
 // sum over the 16 lanes of every row, left in every lane of the row
 __device__ inline double row_sum(double v) {

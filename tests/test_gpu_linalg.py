@@ -32,9 +32,11 @@ def test_qr(ctx, m, n):
 @pytest.mark.parametrize("m,n", [(288, 144), (256, 128), (192, 96), (144, 144), (160, 80), (100, 37), (576, 32)])
 def test_qr_q_only_split(ctx, m, n):
     """One matrix, Q only (the sweeps' call): the factorising workgroup leaves
-    the reflectors and Q is formed across workgroups of 16 columns.  Same Q
-    as the factorisation that forms Q itself (with R), to rounding, for
-    random, exactly rank-deficient and graded matrices."""
+    the reflectors and Q is formed with one column per wavefront, reflectors
+    taken in pairs (odd n leaves a single one per chunk; n = 37 leaves idle
+    wavefronts in the last workgroup; m = 576 takes chunks of 8).  Same Q as
+    the factorisation that forms Q itself (with R), to rounding, for random,
+    exactly rank-deficient and graded matrices."""
     rng = np.random.default_rng(m * 13 + n)
     for kind in ("random", "rank deficient", "graded"):
         A = rng.standard_normal((1, m, n))
