@@ -1011,6 +1011,48 @@ __global__ __launch_bounds__(EFT) void eig_kernel(const int* dims, const int* ke
 // a sweep in which every pair of columns meets once; sweeps repeat until no
 // pair needs a rotation.
 // ---------------------------------------------------------------------------
+// Sums over the wavefront of 8 values at once, in transposed form.  Each
+// step exchanges half of the values still in flight with the partner lanes
+// and adds, so the count halves: the permlane swaps of gfx950 trade the
+// upper half (S = 32) or the odd rows (S = 16) of one register for the lower
+// half or even rows of another (one instruction per 32 bits for two
+// values), then a rotation by 8 within each row; the one value left is
+// summed over its 8-lane group by three in-row DPP steps.  On return lane l
+// holds the total of value j = l5 + 2 l4 + 4 l3 (bits of l), identical in
+// the 8 lanes of its group.
+template <int S>
+__device__ inline double swap_sum(double a, double b) {  // lanes of the lower half / even rows: a, others: b
+  const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+  const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+  const unsigned alo = (unsigned)(ua & 0xffffffffull), ahi = (unsigned)(ua >> 32);
+  const unsigned blo = (unsigned)(ub & 0xffffffffull), bhi = (unsigned)(ub >> 32);
+  auto sw = [](unsigned u, unsigned v) {
+    if constexpr (S == 32) return __builtin_amdgcn_permlane32_swap(u, v, false, false);
+    else return __builtin_amdgcn_permlane16_swap(u, v, false, false);
+  };
+  const auto l = sw(alo, blo), h = sw(ahi, bhi);
+  const double p = __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | l[0]));
+  const double q = __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | l[1]));
+  return p + q;
+}
+
+__device__ inline double transposed_sum8(const double (&x)[8]) {
+  const double y0 = swap_sum<32>(x[0], x[1]), y1 = swap_sum<32>(x[2], x[3]);
+  const double y2 = swap_sum<32>(x[4], x[5]), y3 = swap_sum<32>(x[6], x[7]);
+  const double z0 = swap_sum<16>(y0, y1), z1 = swap_sum<16>(y2, y3);
+  // lanes with bit 3 set keep z1 and send z0, the others the reverse; row_ror:8
+  // reads the register of the lane 8 apart in the row
+  const bool hi8 = (threadIdx.x & 8) != 0;
+  double w = (hi8 ? z1 : z0) + dpp_row<0x128>(hi8 ? z0 : z1);
+  w += dpp_row<0xB1>(w);                      // quad_perm [1,0,3,2]
+  w += dpp_row<0x4E>(w);                      // quad_perm [2,3,0,1]
+  w += dpp_row<0x141>(w);                     // row_half_mirror
+  return w;
+}
+
+// first lane of the group holding value j after transposed_sum8
+constexpr int eig_lane_of(int j) { return 32 * (j & 1) + 16 * ((j >> 1) & 1) + 8 * ((j >> 2) & 1); }
+
 template <int RS, int PPW, int NW, int CH>
 __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const int* keep,
                                                           const double* __restrict__ G0,
@@ -1122,38 +1164,62 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
     }
     int rotated = 0;
     for (int rd = 0; rd < rounds; ++rd) {
-      // ---- cross products of every pair of this wavefront (wave-uniform)
-      double g[PPW];
-#pragma unroll
-      for (int j0 = 0; j0 < PPW; j0 += CH) {
-        double gc[CH];
-#pragma unroll
-        for (int jj = 0; jj < CH; ++jj) {
-          const int j = (j0 + jj < PPW) ? j0 + jj : PPW - 1;
-          double x = 0.0;
-#pragma unroll
-          for (int i = 0; i < RS; ++i) x += wt[j][i] * wb[j][i];
-          gc[jj] = x;
-        }
-        wave_sum_n<CH>(gc);
-#pragma unroll
-        for (int jj = 0; jj < CH; ++jj)
-          if (j0 + jj < PPW) g[j0 + jj] = gc[jj];
-      }
-      // ---- rotation of pair j computed by lane j (t = tan of the angle that
-      // makes the pair orthogonal, the root of smaller modulus), then broadcast
+      // ---- cross products of every pair of this wavefront, and the rotation
+      // of pair j (t = tan of the angle that makes the pair orthogonal, the
+      // root of smaller modulus) computed by one lane holding its sum
       double rc = 1.0, rs = 0.0;
-      {
-        int idt = 0, idb = 0;
-        double gg = 0.0;
+      int jl = 0;     // pair whose rotation this lane computes
+      bool rl = false;
+      double gg = 0.0;
+      if constexpr (PPW >= 4) {
+        // sums in transposed form: value j ends in the 8 lanes whose bits
+        // 5, 4, 3 spell j (eig_lane_of), each sum through fewer steps
+        double x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          double d = 0.0;
+          if (j < PPW) {
+#pragma unroll
+            for (int i = 0; i < RS; ++i) d += wt[j][i] * wb[j][i];
+          }
+          x[j] = d;
+        }
+        gg = transposed_sum8(x);
+        jl = ((lane >> 5) & 1) | (((lane >> 4) & 1) << 1) | (((lane >> 3) & 1) << 2);
+        rl = (lane & 7) == 0 && jl < PPW;
+      } else {
+        double g[PPW];
+#pragma unroll
+        for (int j0 = 0; j0 < PPW; j0 += CH) {
+          double gc[CH];
+#pragma unroll
+          for (int jj = 0; jj < CH; ++jj) {
+            const int j = (j0 + jj < PPW) ? j0 + jj : PPW - 1;
+            double x = 0.0;
+#pragma unroll
+            for (int i = 0; i < RS; ++i) x += wt[j][i] * wb[j][i];
+            gc[jj] = x;
+          }
+          wave_sum_n<CH>(gc);
+#pragma unroll
+          for (int jj = 0; jj < CH; ++jj)
+            if (j0 + jj < PPW) g[j0 + jj] = gc[jj];
+        }
 #pragma unroll
         for (int j = 0; j < PPW; ++j)
-          if (lane == j) {
+          if (lane == j) gg = g[j];
+        jl = lane;
+        rl = lane < PPW;
+      }
+      {
+        int idt = 0, idb = 0;
+#pragma unroll
+        for (int j = 0; j < PPW; ++j)
+          if (jl == j) {
             idt = it[j];
             idb = ib[j];
-            gg = g[j];
           }
-        if (lane < PPW && p0 + lane < NP) {
+        if (rl && p0 + jl < NP) {
           const double a = cn[idt], b = cn[idb];
           const double g2 = gg * gg;
           if (g2 > 1e-30 * a * b && g2 > gf2 * fmax(a, b)) {
@@ -1169,7 +1235,8 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
       }
 #pragma unroll
       for (int j = 0; j < PPW; ++j) {
-        const double c = read_lane(rc, j), s = read_lane(rs, j);
+        const int lj = PPW >= 4 ? eig_lane_of(j) : j;
+        const double c = read_lane(rc, lj), s = read_lane(rs, lj);
         if (s == 0.0) continue;
 #pragma unroll
         for (int i = 0; i < RS; ++i) {
