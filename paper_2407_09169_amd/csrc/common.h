@@ -285,7 +285,7 @@ void tc_launch(const TcDesc& d, Prec p, hipStream_t s);
 // caller provides the partial-sum buffer of tc_part_size(d) doubles when
 // tc_uses_part(d) (set d.ksplit first)
 int tc_choose_ksplit(const TcDesc& d, Prec p);
-// Sets d.ksplit and d.tile (FP64 tile, MFMA pipeline) for a launch: with measure, the fastest
+// Sets d.ksplit and d.tile (FP64 tile; MFMA pipeline and tile) for a launch: with measure, the fastest
 // of the candidate tiles and K splits timed on the device with scratch
 // outputs (the operands are only read), cached per shape for the process;
 // without, a cached choice for the shape or the rule of tc_choose_ksplit.

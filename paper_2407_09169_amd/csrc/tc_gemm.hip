@@ -182,8 +182,10 @@ __global__ __launch_bounds__(256) void tc_f64_kernel(TcDesc d, int a_kfast, int 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// 64x64 output tile per workgroup, 4 waves each owning a 32x32 quadrant made
-// of 2x2 16x16 MFMA blocks.  LDS holds A as [m][k] and B as [n][k] so that a
+// BMN x BMN output tile per workgroup (64 or 32), 4 waves each owning a
+// quadrant made of MI x MI 16x16 MFMA blocks (MI = BMN / 32): the 32-wide
+// tile gives four times as many workgroups to shapes that a 64-wide tile
+// leaves short of the chip's CUs, without splitting K.  LDS holds A as [m][k] and B as [n][k] so that a
 // lane's MFMA operand is contiguous in k.  AKF / BNF: A is read along k
 // (row-major operand) / B along n; each thread's tile elements keep their row
 // (column) offsets for the whole K loop, so a K step costs one or NA mode
@@ -201,9 +203,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // buffer while the next tile is stored into the other) and, for FP32, gives
 // MFMA t of a 16-wide K block the k values 4 lq + t of lane group lq, so each
 // lane reads its four operands of a block with one 16-byte LDS load.
-template <bool BF16, bool AKF, bool BNF, int BK, bool DB>
+template <bool BF16, bool AKF, bool BNF, int BK, bool DB, int BMN>
 __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
-  constexpr int BM = 64, BN = 64;
+  constexpr int BM = BMN, BN = BMN;
+  constexpr int MI = BMN / 32;  // 16x16 blocks per wave along m and along n
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
   using TIn = typename std::conditional<BF16, __bf16, float>::type;
   constexpr int PAD = BF16 ? 8 : 4;
@@ -213,16 +216,16 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
   __shared__ __align__(16) TIn Bs[NBUF][NH][BN][BK + PAD];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * (BMN / 2), wn = (wave & 1) * (BMN / 2);
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const KRange kr = k_range<BK>(d);
   const gdouble* A = base_a(d, kr);
   const gdouble* B = base_b(d, kr);
-  f32x4 acc[2][2];
+  f32x4 acc[MI][MI];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < MI; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int li = lane & 15, lq = lane >> 4;
   // element q of this thread: A at (row am_q, column ak_q), B at (ak_q', bn_q)
   auto a_row = [&](int q) { return AKF ? tid / BK + q * (256 / BK) : tid % BM; };
@@ -302,20 +305,20 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
     if constexpr (BF16) {
 #pragma unroll
       for (int kc = 0; kc < BK; kc += 32) {
-        bf16x8 a[2][2], b[2][2];  // [hi/lo][block]
+        bf16x8 a[2][MI], b[2][MI];  // [hi/lo][block]
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < MI; ++i)
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
               a[h][i][t] = As[buf][h][wm + 16 * i + li][kc + 8 * lq + t];
               b[h][i][t] = Bs[buf][h][wn + 16 * i + li][kc + 8 * lq + t];
             }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < MI; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
+          for (int j = 0; j < MI; ++j) {
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
@@ -324,31 +327,31 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
     } else if constexpr (DB) {
 #pragma unroll
       for (int kb = 0; kb < BK; kb += 16) {
-        f32x4 a[2], b[2];
+        f32x4 a[MI], b[MI];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const f32x4*>(&As[buf][0][wm + 16 * i + li][kb + 4 * lq]);
+        for (int i = 0; i < MI; ++i) a[i] = *reinterpret_cast<const f32x4*>(&As[buf][0][wm + 16 * i + li][kb + 4 * lq]);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const f32x4*>(&Bs[buf][0][wn + 16 * j + li][kb + 4 * lq]);
+        for (int j = 0; j < MI; ++j) b[j] = *reinterpret_cast<const f32x4*>(&Bs[buf][0][wn + 16 * j + li][kb + 4 * lq]);
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < MI; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < MI; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
       }
     } else {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        float a[2], b[2];
+        float a[MI], b[MI];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = As[buf][0][wm + 16 * i + li][kk + lq];
+        for (int i = 0; i < MI; ++i) a[i] = As[buf][0][wm + 16 * i + li][kk + lq];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = Bs[buf][0][wn + 16 * j + li][kk + lq];
+        for (int j = 0; j < MI; ++j) b[j] = Bs[buf][0][wn + 16 * j + li][kk + lq];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < MI; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
+          for (int j = 0; j < MI; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
       }
     }
@@ -382,9 +385,9 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
   if (to_part(d)) {
     gdouble* Pp = base_part(d, kr);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < MI; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int m = m0 + wm + 16 * i + 4 * lq + r;
@@ -394,24 +397,24 @@ __global__ __launch_bounds__(256) void tc_mfma_kernel(TcDesc d) {
     return;
   }
   gdouble* C = base_c(d, kr);
-  // output offsets: 8 distinct rows and 2 distinct columns per thread
-  int64_t coff[2];
-  bool cok[2];
+  // output offsets: 4 MI distinct rows and MI distinct columns per thread
+  int64_t coff[MI];
+  bool cok[MI];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < MI; ++j) {
     const int n = n0 + wn + 16 * j + li;
     cok[j] = n < d.N;
     coff[j] = cok[j] ? d.cn.off(n) : 0;
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int m = m0 + wm + 16 * i + 4 * lq + r;
       if (m >= d.M) continue;
       const int64_t ro = d.cm.off(m);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < MI; ++j) {
         if (!cok[j]) continue;
         gdouble* p = C + ro + coff[j];
         double v = d.alpha * (double)acc[i][j][r];
@@ -452,7 +455,7 @@ struct Tile {
   int bm, bn;
 };
 inline Tile tile_of(const TcDesc& d, Prec p) {
-  if (p != Prec::F64) return {64, 64};
+  if (p != Prec::F64) return d.tile >= 3 ? Tile{32, 32} : Tile{64, 64};
   switch (d.tile) {
     case 1: return {64, 64};
     case 2: return {64, 32};
@@ -468,8 +471,10 @@ std::string tc_kernel_name(const TcDesc& d, Prec p) {
   if (p != Prec::F64) {
     const char* ak = unit(d.ak) ? "true" : "false";
     const char* bn = unit(d.bn) ? "true" : "false";
-    const char* var = d.tile == 2 ? ", 64, true>" : d.tile == 1 ? ", 32, true>" : ", 32, false>";
-    return std::string("tc_mfma_kernel<") + (p == Prec::BF16 ? "true" : "false") + ", " + ak + ", " + bn + var;
+    const int pl = d.tile % 3;
+    const char* var = pl == 2 ? ", 64, true" : pl == 1 ? ", 32, true" : ", 32, false";
+    const char* tsz = d.tile >= 3 ? ", 32>" : ", 64>";
+    return std::string("tc_mfma_kernel<") + (p == Prec::BF16 ? "true" : "false") + ", " + ak + ", " + bn + var + tsz;
   }
   const Tile t = tile_of(d, p);
   return "tc_f64_kernel<" + std::to_string(t.bm) + ", " + std::to_string(t.bn) + ">";
@@ -548,15 +553,20 @@ void tc_launch(const TcDesc& d0, Prec p, hipStream_t s) {
     else
       hipLaunchKernelGGL((tc_f64_kernel<32, 32>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
   } else {
-    const int v = d.tile;  // MFMA pipeline: 0 one LDS tile of 32, 1 double-buffered 32, 2 double-buffered 64
+    // MFMA pipeline v % 3: 0 one LDS tile of 32, 1 double-buffered 32, 2
+    // double-buffered 64; tile 64 x 64 for v < 3, 32 x 32 from 3 on
+    const int v = d.tile;
+#define QTT_TC_MFMA_T(BF, AK, BN, T)                                                              \
+  if (v == (T == 64 ? 2 : 5))                                                                     \
+    hipLaunchKernelGGL((tc_mfma_kernel<BF, AK, BN, 64, true, T>), grid, dim3(256), 0, s, d);      \
+  else if (v == (T == 64 ? 1 : 4))                                                                \
+    hipLaunchKernelGGL((tc_mfma_kernel<BF, AK, BN, 32, true, T>), grid, dim3(256), 0, s, d);      \
+  else if (v == (T == 64 ? 0 : 3))                                                                \
+    hipLaunchKernelGGL((tc_mfma_kernel<BF, AK, BN, 32, false, T>), grid, dim3(256), 0, s, d);
 #define QTT_TC_MFMA(BF, AK, BN)                                                          \
   if ((p == Prec::BF16) == BF && (a_kfast != 0) == AK && (b_nfast != 0) == BN) {          \
-    if (v == 2)                                                                           \
-      hipLaunchKernelGGL((tc_mfma_kernel<BF, AK, BN, 64, true>), grid, dim3(256), 0, s, d); \
-    else if (v == 1)                                                                      \
-      hipLaunchKernelGGL((tc_mfma_kernel<BF, AK, BN, 32, true>), grid, dim3(256), 0, s, d); \
-    else                                                                                  \
-      hipLaunchKernelGGL((tc_mfma_kernel<BF, AK, BN, 32, false>), grid, dim3(256), 0, s, d); \
+    QTT_TC_MFMA_T(BF, AK, BN, 64)                                                         \
+    QTT_TC_MFMA_T(BF, AK, BN, 32)                                                         \
   }
     QTT_TC_MFMA(true, true, true)
     QTT_TC_MFMA(true, true, false)
@@ -567,6 +577,7 @@ void tc_launch(const TcDesc& d0, Prec p, hipStream_t s) {
     QTT_TC_MFMA(false, false, true)
     QTT_TC_MFMA(false, false, false)
 #undef QTT_TC_MFMA
+#undef QTT_TC_MFMA_T
   }
   QTT_HIP(hipGetLastError());
   if (tc_uses_part(d)) {
@@ -614,7 +625,12 @@ std::pair<int, int> measure(const TcDesc& d, Prec p) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!g_tune_stream) QTT_HIP(hipStreamCreateWithFlags(&g_tune_stream, hipStreamNonBlocking));
   hipStream_t s = g_tune_stream;
-  std::vector<int> tiles{0, 1, 2};  // MFMA pipelines
+  std::vector<int> tiles{0, 1, 2};  // MFMA pipelines with 64 x 64 tiles
+  if (p != Prec::F64) {
+    // the 32 x 32 tiles where 64 x 64 ones leave the chip short of workgroups
+    const int64_t t64 = (int64_t)((d.M + 63) / 64) * ((d.N + 63) / 64) * d.batch * d.ng;
+    if (t64 < 512) tiles.insert(tiles.end(), {3, 4, 5});
+  }
   if (p == Prec::F64) {
     tiles = {4};
     if (d.N > 32) tiles.push_back(3);
@@ -682,11 +698,12 @@ std::pair<int, int> measure(const TcDesc& d, Prec p) {
 }  // namespace
 
 namespace {
-// QTTPDF_MFMA_PIPELINE=0|1|2 forces one MFMA pipeline for every launch
-// recorded from then on (read at each call, so tests can cover each one)
+// QTTPDF_MFMA_PIPELINE=0..5 forces one MFMA variant (pipeline v % 3, tile
+// 64 x 64 below 3, 32 x 32 from 3 on) for every launch recorded from then on
+// (read at each call, so tests can cover each one)
 int forced_pipeline() {
   const char* e = std::getenv("QTTPDF_MFMA_PIPELINE");
-  if (!e || e[0] < '0' || e[0] > '2' || e[1] != 0) return -1;
+  if (!e || e[0] < '0' || e[0] > '5' || e[1] != 0) return -1;
   return e[0] - '0';
 }
 }  // namespace

@@ -50,14 +50,15 @@ def test_round_rel_tol_and_info_match_oracle(ctx, chi, rel_tol):
 
 
 @pytest.mark.parametrize("dtype,tol,pipeline", [("f64", 1e-14, None)] + [
-    (d, t, pl) for d, t in (("f32", 2e-7), ("bf16", 1e-4)) for pl in (None, "0", "1", "2")])
+    (d, t, pl) for d, t in (("f32", 2e-7), ("bf16", 1e-4)) for pl in (None, "0", "1", "2", "3", "4", "5")])
 def test_apply_mpo_precision(ctx, monkeypatch, dtype, tol, pipeline):
     """Explicit MPO x MPS product with FP64 products, FP32-rounded operands
     (relative 2^-24 per operand: a product errs by at most 2^-23 of its size,
     and the two products of an entry add at most that again), or BF16 high
     and low parts (2^-16 per product): entries against the FP64 dense
     product, relative to the largest entry.  pipeline: every MFMA launch
-    forced onto one of the three pipelines (None: the measured choice)."""
+    forced onto one of the three pipelines with 64 x 64 tiles (0-2) or with
+    32 x 32 tiles (3-5) (None: the measured choice)."""
     if pipeline is not None:
         monkeypatch.setenv("QTTPDF_MFMA_PIPELINE", pipeline)
     Wc = cases.random_mpo(8, 3, 91)

@@ -75,12 +75,13 @@ def test_full_size_step_matches_oracle(ctx, oracle_step, dtype, tol):
     _check_step(ctx, oracle_step, dtype, tol)
 
 
-@pytest.mark.parametrize("pipeline", ["0", "1", "2"])
+@pytest.mark.parametrize("pipeline", ["0", "1", "2", "3", "4", "5"])
 @pytest.mark.parametrize("dtype,tol", [("f32", 3e-5), ("bf16", 1e-2)])
 def test_full_size_step_each_mfma_pipeline(ctx, oracle_step, monkeypatch, pipeline, dtype, tol):
     """The same step with every MFMA launch forced onto one pipeline (K tile
-    32 with one LDS buffer; K tile 32 or 64 with two), at the tolerances
-    above: the measured choice per shape may take any of them."""
+    32 with one LDS buffer; K tile 32 or 64 with two) and one output tile
+    (64 x 64 for 0-2, 32 x 32 for 3-5), at the tolerances above: the measured
+    choice per shape may take any of them."""
     monkeypatch.setenv("QTTPDF_MFMA_PIPELINE", pipeline)
     _check_step(ctx, oracle_step, dtype, tol, f" pipeline {pipeline}")
 
