@@ -441,7 +441,13 @@ __global__ __launch_bounds__(256) void tc_splitk_reduce(TcDesc d) {
   const int z = zo / gout, g = zo - z * gout;
   const gdouble* Pp = as_global(ishift(d.part, io) + ((int64_t)z * d.ng + g) * d.ksplit * mn + rem);
   double s = 0.0;
-  for (int k = 0; k < nparts; ++k) s += Pp[(int64_t)k * mn];
+  int k = 0;
+  for (; k + 4 <= nparts; k += 4) {  // four loads in flight, added in order
+    const double p0 = Pp[(int64_t)k * mn], p1 = Pp[(int64_t)(k + 1) * mn];
+    const double p2 = Pp[(int64_t)(k + 2) * mn], p3 = Pp[(int64_t)(k + 3) * mn];
+    s = (((s + p0) + p1) + p2) + p3;
+  }
+  for (; k < nparts; ++k) s += Pp[(int64_t)k * mn];
   gdouble* base = as_global(ishift((d.ng > 1 && !d.gsum) ? const_cast<double*>(d.gdev[2 * d.ng + g]) : d.C, io));
   gdouble* p = base + d.cb.off(z) + d.cm.off(m) + d.cn.off(n);
   double v = d.alpha * s;
