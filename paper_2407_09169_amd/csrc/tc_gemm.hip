@@ -467,6 +467,9 @@ inline Tile tile_of(const TcDesc& d, Prec p) {
     case 2: return {64, 32};
     case 3: return {32, 64};
     case 4: return {32, 32};
+    case 5: return {16, 16};  // the 16-wide tiles for shapes with M or N of at most 16
+    case 6: return {16, 64};
+    case 7: return {64, 16};
   }
   return {d.M >= 48 ? 64 : 32, d.N >= 48 ? 64 : 32};
 }
@@ -542,22 +545,28 @@ void tc_launch(const TcDesc& d0, Prec p, hipStream_t s) {
   d.istride = rt::fuse().stride;
   tc_validate(d);
   if (rt::dry()) return;
-  QTT_REQUIRE((int64_t)d.batch * d.ng * d.ksplit * d.ninst <= 65535 && (d.M + 31) / 32 <= 65535,
+  const Tile t = tile_of(d, p);
+  QTT_REQUIRE((int64_t)d.batch * d.ng * d.ksplit * d.ninst <= 65535 && (d.M + t.bm - 1) / t.bm <= 65535,
               "contraction too large (M=%d batch=%d groups=%d split=%d instances=%d)", d.M, d.batch, d.ng,
               d.ksplit, d.ninst);
   const int a_kfast = unit(d.ak) ? 1 : 0;
   const int b_nfast = unit(d.bn) ? 1 : 0;
-  const Tile t = tile_of(d, p);
   const dim3 grid((d.N + t.bn - 1) / t.bn, (d.M + t.bm - 1) / t.bm, d.batch * d.ng * d.ksplit * d.ninst);
   if (p == Prec::F64) {
     if (t.bm == 64 && t.bn == 64)
       hipLaunchKernelGGL((tc_f64_kernel<64, 64>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
-    else if (t.bm == 64)
+    else if (t.bm == 64 && t.bn == 32)
       hipLaunchKernelGGL((tc_f64_kernel<64, 32>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
-    else if (t.bn == 64)
+    else if (t.bm == 32 && t.bn == 64)
       hipLaunchKernelGGL((tc_f64_kernel<32, 64>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
-    else
+    else if (t.bm == 32 && t.bn == 32)
       hipLaunchKernelGGL((tc_f64_kernel<32, 32>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
+    else if (t.bm == 16 && t.bn == 16)
+      hipLaunchKernelGGL((tc_f64_kernel<16, 16>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
+    else if (t.bm == 16)
+      hipLaunchKernelGGL((tc_f64_kernel<16, 64>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
+    else
+      hipLaunchKernelGGL((tc_f64_kernel<64, 16>), grid, dim3(256), 0, s, d, a_kfast, b_nfast);
   } else {
     // MFMA pipeline v % 3: 0 one LDS tile of 32, 1 double-buffered 32, 2
     // double-buffered 64; tile 64 x 64 for v < 3, 32 x 32 from 3 on
@@ -642,6 +651,9 @@ std::pair<int, int> measure(const TcDesc& d, Prec p) {
     if (d.N > 32) tiles.push_back(3);
     if (d.M > 32) tiles.push_back(2);
     if (d.M > 32 && d.N > 32) tiles.push_back(1);
+    if (d.M <= 16 || d.N <= 16) tiles.push_back(5);
+    if (d.M <= 16 && d.N > 32) tiles.push_back(6);
+    if (d.N <= 16 && d.M > 32) tiles.push_back(7);
   }
   const int minchunk = (p == Prec::F64) ? 16 : 32;
   std::vector<int> splits;
@@ -705,11 +717,17 @@ std::pair<int, int> measure(const TcDesc& d, Prec p) {
 
 namespace {
 // QTTPDF_MFMA_PIPELINE=0..5 forces one MFMA variant (pipeline v % 3, tile
-// 64 x 64 below 3, 32 x 32 from 3 on) for every launch recorded from then on
-// (read at each call, so tests can cover each one)
+// 64 x 64 below 3, 32 x 32 from 3 on) for every launch recorded from then on,
+// QTTPDF_F64_TILE=1..7 one tile of the FP64 kernel (read at each call, so
+// tests can cover each one)
 int forced_pipeline() {
   const char* e = std::getenv("QTTPDF_MFMA_PIPELINE");
   if (!e || e[0] < '0' || e[0] > '5' || e[1] != 0) return -1;
+  return e[0] - '0';
+}
+int forced_f64_tile() {
+  const char* e = std::getenv("QTTPDF_F64_TILE");
+  if (!e || e[0] < '1' || e[0] > '7' || e[1] != 0) return -1;
   return e[0] - '0';
 }
 }  // namespace
@@ -717,7 +735,7 @@ int forced_pipeline() {
 bool tc_configure(TcDesc& d, Prec p, bool measure_ok) {
   d.tile = 0;
   d.ksplit = tc_choose_ksplit(d, p);
-  const int fp = p == Prec::F64 ? -1 : forced_pipeline();
+  const int fp = p == Prec::F64 ? forced_f64_tile() : forced_pipeline();
   bool measured = false;
   if (autotune_on() && d.M > 0 && d.N > 0 && d.batch > 0 && d.K > 0) {
     const TuneKey k = key_of(d, p);

@@ -50,6 +50,7 @@ def test_round_rel_tol_and_info_match_oracle(ctx, chi, rel_tol):
 
 
 @pytest.mark.parametrize("dtype,tol,pipeline", [("f64", 1e-14, None)] + [
+    ("f64", 1e-14, f"f64 tile {t}") for t in range(1, 8)] + [
     (d, t, pl) for d, t in (("f32", 2e-7), ("bf16", 1e-4)) for pl in (None, "0", "1", "2", "3", "4", "5")])
 def test_apply_mpo_precision(ctx, monkeypatch, dtype, tol, pipeline):
     """Explicit MPO x MPS product with FP64 products, FP32-rounded operands
@@ -58,8 +59,11 @@ def test_apply_mpo_precision(ctx, monkeypatch, dtype, tol, pipeline):
     and low parts (2^-16 per product): entries against the FP64 dense
     product, relative to the largest entry.  pipeline: every MFMA launch
     forced onto one of the three pipelines with 64 x 64 tiles (0-2) or with
-    32 x 32 tiles (3-5) (None: the measured choice)."""
-    if pipeline is not None:
+    32 x 32 tiles (3-5), every FP64 launch onto one of its seven tiles (64 or
+    32 wide, and the 16-wide ones) (None: the measured choice)."""
+    if pipeline is not None and pipeline.startswith("f64 tile"):
+        monkeypatch.setenv("QTTPDF_F64_TILE", pipeline.split()[-1])
+    elif pipeline is not None:
         monkeypatch.setenv("QTTPDF_MFMA_PIPELINE", pipeline)
     Wc = cases.random_mpo(8, 3, 91)
     xc = random_tt([1, 2, 4, 8, 8, 8, 4, 2, 1], 92)

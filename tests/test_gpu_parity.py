@@ -190,6 +190,25 @@ def test_step_untruncated_equals_dense(ctx, name, integrator):
         assert err < 1e-11, (name, err)
 
 
+@pytest.mark.parametrize("tile", [str(t) for t in range(1, 8)])
+def test_step_untruncated_each_f64_tile(ctx, monkeypatch, tile):
+    """The untruncated FP64 step with every FP64 contraction forced onto one
+    tile of the SIMT kernel (64 and 32 wide, and the 16-wide ones the
+    autotuner tries on shapes with M or N of at most 16): the dense solver's
+    result to 1e-11, as with the measured choice."""
+    monkeypatch.setenv("QTTPDF_F64_TILE", tile)
+    w = workloads.get_workload("t_5d_M8_exact", integrator="rk4")
+    st = stepper.MPSStepper(w)
+    prob, f = q.setup_workload(ctx, w, "f64")
+    P = st.dense_problem()
+    fd = dense.dense_from_terms(workloads.ic_terms(w), w.ndims, w.M)
+    for _ in range(2):
+        prob.step(f, 1)
+        fd = P.step(fd, w.dt, "rk4")
+        err = rel(_dense_of(st, f.cores()), fd)
+        assert err < 1e-11, (tile, err)
+
+
 @pytest.mark.parametrize("name,integrator,steps", [(n, i, k) for n, i, k, fl in cases.STEP_CASES if not fl])
 def test_step_truncated_matches_oracle(ctx, name, integrator, steps):
     """Truncated FP64 steps agree with the oracle (the same randomized schedule
