@@ -644,6 +644,7 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
     for (int c = threadIdx.x; c < n; c += NW * 64) tout[c] = taus[c];
     return;
   }
+  if (Q0 == nullptr) return;  // R only: no Q wanted
   // ---- thin Q by backward accumulation, one slot phase at a time (in
   // reverse): the reflectors of the phase's CL columns are published together,
   // then every wavefront applies them, last to first, to its own columns with
@@ -1676,7 +1677,10 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
   const int lq = ldq > 0 ? ldq : n;
   rt::check_range(A, 0, (int64_t)(count - 1) * strideA + (int64_t)(m - 1) * rs + (int64_t)(n - 1) * cs,
                   sizeof(double), "qr input");
-  rt::check_range(Q, 0, (int64_t)(count - 1) * strideQ + (int64_t)(m - 1) * lq + n - 1, sizeof(double), "qr Q");
+  // Q may be left out (R only) where the group kernel factorises
+  QTT_REQUIRE(Q != nullptr || (R != nullptr && qr_kernel_name(m, n).rfind("qr_grp_kernel", 0) == 0),
+              "qr: R without Q needs the group kernel (m=%d n=%d)", m, n);
+  if (Q) rt::check_range(Q, 0, (int64_t)(count - 1) * strideQ + (int64_t)(m - 1) * lq + n - 1, sizeof(double), "qr Q");
   if (R) rt::check_range(R, 0, (int64_t)(count - 1) * strideR + (int64_t)(n - 1) * lq + n - 1, sizeof(double),
                          "qr R");
   if (sq) rt::check_range(sq, 0, count - 1, sizeof(int), "qr sizes");
@@ -1700,7 +1704,7 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
   if (fu.n > 1) {
     rt::fuse_check(A, 8 * ((int64_t)(count - 1) * strideA + (int64_t)(m - 1) * rs + (int64_t)(n - 1) * cs + 1),
                    "qr input");
-    rt::fuse_check(Q, 8 * ((int64_t)(count - 1) * strideQ + (int64_t)(m - 1) * lq + n), "qr Q");
+    if (Q) rt::fuse_check(Q, 8 * ((int64_t)(count - 1) * strideQ + (int64_t)(m - 1) * lq + n), "qr Q");
     if (R) rt::fuse_check(R, 8 * ((int64_t)(count - 1) * strideR + (int64_t)(n - 1) * lq + n), "qr R");
     if (generic) rt::fuse_check(work, 8 * ((int64_t)count * m * n), "qr workspace");
   }
@@ -1753,9 +1757,10 @@ void eig_precondition_launch(int count, const int* dims, const double* G, int64_
   double* R2 = work + 2 * count * st;
   double* qw = work + 3 * count * st;  // global-memory QR workspace (count * max_n^2 <= count * st)
   // G = Q1 R1 and R1^T = Q2 R2 give G = Q1 R2^T Q2^T: the sweeps run on
-  // W = R2^T from V = Q2 (Q2 overwrites Q1, which is not needed).  Two
-  // factorisations leave the columns closer to orthogonal than one.
-  qr_launch(count, max_n, max_n, G, strideG, ldg, 1, Q, st, R1, st, qw, s, dims);
+  // W = R2^T from V = Q2; Q1 is not needed (the group kernel skips forming
+  // it).  Two factorisations leave the columns closer to orthogonal than one.
+  const bool r_only = qr_kernel_name(max_n, max_n).rfind("qr_grp_kernel", 0) == 0;
+  qr_launch(count, max_n, max_n, G, strideG, ldg, 1, r_only ? nullptr : Q, st, R1, st, qw, s, dims);
   qr_launch(count, max_n, max_n, R1, st, 1, max_n, Q, st, R2, st, qw, s, dims);
 }
 
