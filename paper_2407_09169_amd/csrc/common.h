@@ -330,7 +330,7 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
                hipStream_t s, const int* sq = nullptr, int ldq = 0, int64_t work_size = -1);
 // One m x n matrix, thin Q only, in two launches: the factorising workgroup
 // leaves the reflectors (V, row-major with unit diagonal, then tau: m n + n
-// doubles of work), and workgroups of 16 columns form Q from them.  Whether
+// doubles of work), and one wavefront per column forms Q from them.  Whether
 // a shape and workspace take this path (qr_launch takes it by itself when
 // they do; QTTPDF_QR_SPLIT=0 turns it off):
 bool qr_split(int m, int n, int64_t work_size);

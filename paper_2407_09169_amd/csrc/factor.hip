@@ -1390,18 +1390,24 @@ __global__ __launch_bounds__(NW * 64) void eig_reg_kernel(const int* dims, const
 // register-resident configurations, tried in order: (rows per lane, columns
 // per wave, waves, reduction chunk) and (rows per lane, pairs per wave,
 // waves, reduction chunk); larger problems use the global-memory kernels
-#define QTT_QR_CONFIGS(X) X(1, 1, 16, 1) X(1, 2, 16, 2) X(2, 2, 16, 2) X(2, 4, 16, 4)
+#define QTT_QR_CONFIGS(X) X(1, 1, 16, 1) X(2, 2, 16, 2)
 // one column per 16-lane group: (rows per lane, column slots, waves)
-#define QTT_QRG_CONFIGS(X) X(12, 3, 8) X(16, 4, 8) X(9, 5, 8) X(18, 5, 8) X(36, 1, 8)
+#define QTT_QRG_CONFIGS(X) \
+  X(2, 1, 8) X(4, 2, 8) X(8, 4, 8) X(9, 5, 8) X(12, 3, 8) X(16, 4, 8) X(16, 5, 8) X(18, 5, 8) X(36, 1, 8)
 // larger than the group configurations
 #define QTT_QR_CONFIGS_LARGE(X) X(5, 10, 16, 2)
 #define QTT_EIG_CONFIGS(X) \
   X(1, 1, 4, 1) X(1, 2, 8, 2) X(1, 4, 8, 4) X(2, 4, 8, 4) X(2, 8, 8, 4) X(3, 6, 12, 2)
 
+// the register kernels take matrices of at most this many columns; wider
+// ones go to the group kernel, whose reflector and thin-Q launches are faster
+// from 32 columns on (32 x 32: 25 against 40 us; 64 x 64: 53 against 142 us)
+constexpr int QR_REG_MAXN = 16;
+
 std::string qr_kernel_name(int m, int n) {
   char b[64];
 #define QTT_QR_NAME(RS_, CPW_, NW_, CH_)                                              \
-  if (m <= 64 * RS_ && n <= NW_ * CPW_) {                                             \
+  if (m <= 64 * RS_ && n <= NW_ * CPW_ && n <= QR_REG_MAXN) {                        \
     snprintf(b, sizeof b, "qr_reg_kernel<%d, %d, %d, %d>", RS_, CPW_, NW_, CH_); \
     return b;                                                                         \
   }
@@ -1657,7 +1663,7 @@ void qr_form_q_launch(int m, int n, const double* work, double* Q, int ldq, hipS
     QTT_HIP(hipGetLastError());                                                                          \
     return;                                                                                              \
   }
-  QTT_QR_FORM(3) QTT_QR_FORM(4) QTT_QR_FORM(5) QTT_QR_FORM(9)
+  QTT_QR_FORM(1) QTT_QR_FORM(2) QTT_QR_FORM(3) QTT_QR_FORM(4) QTT_QR_FORM(5) QTT_QR_FORM(9)
 #undef QTT_QR_FORM
   QTT_REQUIRE(false, "qr: no Q kernel for %d rows per lane (%d x %d)", rw, m, n);
 }
@@ -1712,7 +1718,7 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
   const int64_t is = fu.stride;
   if (rt::dry()) return;
 #define QTT_QR_REG(RS_, CPW_, NW_, CH_)                                                           \
-  if (m <= 64 * RS_ && n <= NW_ * CPW_) {                                                         \
+  if (m <= 64 * RS_ && n <= NW_ * CPW_ && n <= QR_REG_MAXN) {                                    \
     hipLaunchKernelGGL((qr_reg_kernel<RS_, CPW_, NW_, CH_>), grid, dim3(NW_ * 64), 0, s, m, n, A,       \
                        strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq, is);                         \
     QTT_HIP(hipGetLastError());                                                                  \

@@ -29,7 +29,8 @@ def test_qr(ctx, m, n):
         assert np.max(np.abs(np.tril(R[b], -1))) == 0.0
 
 
-@pytest.mark.parametrize("m,n", [(288, 144), (256, 128), (192, 96), (144, 144), (160, 80), (100, 37), (576, 32)])
+@pytest.mark.parametrize("m,n", [(288, 144), (256, 144), (256, 128), (192, 96), (144, 144), (160, 80), (128, 128),
+                                 (100, 37), (64, 64), (48, 24), (32, 32), (576, 32)])
 def test_qr_q_only_split(ctx, m, n):
     """One matrix, Q only (the sweeps' call): the factorising workgroup leaves
     the reflectors and Q is formed with one column per wavefront, reflectors
