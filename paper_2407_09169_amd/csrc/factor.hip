@@ -536,7 +536,11 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-template <int RPL, int CS, int NW>
+// QF: the workgroup may form Q itself (needs the phase buffer vall, CL x 16
+// RPL doubles of LDS); launches that leave reflectors (Vout) or write R only
+// take QF = false and keep their LDS to the factorisation's few kilobytes,
+// so the workgroup finds room on a CU that other launches keep busy.
+template <int RPL, int CS, int NW, bool QF>
 __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const double* __restrict__ A0,
                                                        int64_t strideA, int64_t rs, int64_t cs,
                                                        double* __restrict__ Q0, int64_t strideQ,
@@ -546,7 +550,7 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
                                                        int64_t istride) {
   constexpr int CL = 4 * NW;
   __shared__ double vbuf[2][16 * RPL];
-  __shared__ double vall[CL][16 * RPL];
+  __shared__ double vall[QF ? CL : 1][QF ? 16 * RPL : 1];
   __shared__ double taus[CL * CS];
   __shared__ double betas[CL * CS];
   const int lane = threadIdx.x & 63;
@@ -645,6 +649,9 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
     return;
   }
   if (Q0 == nullptr) return;  // R only: no Q wanted
+  if constexpr (!QF) {
+    return;  // never reached: launches without Q space always pass Vout or no Q
+  } else {
   // ---- thin Q by backward accumulation, one slot phase at a time (in
   // reverse): the reflectors of the phase's CL columns are published together,
   // then every wavefront applies them, last to first, to its own columns with
@@ -691,6 +698,7 @@ __global__ __launch_bounds__(NW * 64) void qr_grp_kernel(int m, int n, const dou
       const int row = li + 16 * r;
       if (row < m) Q[(int64_t)row * ldo + c] = a[j][r];
     }
+  }
   }
 }
 
@@ -1546,7 +1554,7 @@ void qr_blocked(int m, int n, const double* A, int64_t rs, int64_t cs, double* Q
     double* Wp = W + (int64_t)p0 * n + p0;
     // panel: reflectors to Vp, taus, its R block (w x w, ld n) to W2, then into W
     if (run) {
-      hipLaunchKernelGGL((qr_grp_kernel<36, 1, 8>), dim3(1), dim3(512), 0, s, mr, w, (const double*)Wp, (int64_t)0,
+      hipLaunchKernelGGL((qr_grp_kernel<36, 1, 8, false>), dim3(1), dim3(512), 0, s, mr, w, (const double*)Wp, (int64_t)0,
                          (int64_t)n, (int64_t)1, (double*)nullptr, (int64_t)0, W2, (int64_t)0, (const int*)nullptr,
                          n, Vp, taus + p0, (int64_t)0);
       QTT_HIP(hipGetLastError());
@@ -1632,7 +1640,7 @@ void qr_reflectors_launch(int m, int n, const double* A, int64_t rs, int64_t cs,
   const int64_t is = fu.stride;
 #define QTT_QR_REFL(RPL_, CS_, NW_)                                                                   \
   if (m <= 16 * RPL_ && n <= 4 * NW_ * CS_) {                                                         \
-    hipLaunchKernelGGL((qr_grp_kernel<RPL_, CS_, NW_>), grid, dim3(NW_ * 64), 0, s, m, n, A, (int64_t)0, rs, cs, \
+    hipLaunchKernelGGL((qr_grp_kernel<RPL_, CS_, NW_, false>), grid, dim3(NW_ * 64), 0, s, m, n, A, (int64_t)0, rs, cs, \
                        (double*)nullptr, (int64_t)0, (double*)nullptr, (int64_t)0, (const int*)nullptr, n, work, \
                        work + (int64_t)m * n, is);                                                    \
     QTT_HIP(hipGetLastError());                                                                      \
@@ -1728,8 +1736,12 @@ void qr_launch(int count, int m, int n, const double* A, int64_t strideA, int64_
 #undef QTT_QR_REG
 #define QTT_QR_GRP(RPL_, CS_, NW_)                                                                \
   if (m <= 16 * RPL_ && n <= 4 * NW_ * CS_) {                                                     \
-    hipLaunchKernelGGL((qr_grp_kernel<RPL_, CS_, NW_>), grid, dim3(NW_ * 64), 0, s, m, n, A,          \
-                       strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq, nullptr, nullptr, is);     \
+    if (Q != nullptr)                                                                             \
+      hipLaunchKernelGGL((qr_grp_kernel<RPL_, CS_, NW_, true>), grid, dim3(NW_ * 64), 0, s, m, n, A,  \
+                         strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq, nullptr, nullptr, is);   \
+    else                                                                                          \
+      hipLaunchKernelGGL((qr_grp_kernel<RPL_, CS_, NW_, false>), grid, dim3(NW_ * 64), 0, s, m, n, A, \
+                         strideA, rs, cs, Q, strideQ, R, strideR, sq, ldq, nullptr, nullptr, is);   \
     QTT_HIP(hipGetLastError());                                                                  \
     return;                                                                                      \
   }
