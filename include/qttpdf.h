@@ -407,11 +407,14 @@ tt_status tt_profile(tt_ctx* ctx, tt_problem* prob, tt_tt* f, int n_steps, int k
 
 /* Launch configuration of the contraction kernels: when a plan is recorded
  * (problem steps, roundings, products), every distinct contraction shape is
- * timed once on the device with each candidate FP64 tile (64x64, 64x32,
- * 32x64, 32x32) and K split (1, 2, 4, ... 64 chunks), on scratch outputs,
- * and the fastest is kept for the process (the environment variable
- * QTTPDF_AUTOTUNE=0 keeps a fixed rule instead).  Reports the number of
- * shapes measured so far and the seconds spent measuring. */
+ * timed once on the device with each candidate variant (FP64: tiles 64x64,
+ * 64x32, 32x64, 32x32, and 16x16, 16x64, 64x16 where M or N is at most 16;
+ * MFMA: three pipelines on 64x64 tiles, and on 32x32 tiles where 64x64 ones
+ * give fewer than 512 workgroups) and K split (1, 2, 4, ... 64 chunks), on
+ * scratch outputs, and the fastest is kept for the process (the environment
+ * variable QTTPDF_AUTOTUNE=0 keeps a fixed rule instead; QTTPDF_F64_TILE=1..7
+ * and QTTPDF_MFMA_PIPELINE=0..5 force one variant, for tests).  Reports the
+ * number of shapes measured so far and the seconds spent measuring. */
 tt_status tt_autotune_info(int* shapes, double* seconds);
 
 /* Per-bond discarded singular weight (sum of dropped sigma^2, n_sites + 1
