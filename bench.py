@@ -650,7 +650,7 @@ def main():
         _kernel_probe(args.kernel_probe)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for {args.gpus}); "
+        print(f"bench.py measures one GPU: there is no multi-GPU path (asked for {args.gpus}); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
