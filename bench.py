@@ -10,7 +10,10 @@ inputs (workloads.c3_5d_M1024_chi128).  Inputs are resident in HBM before the
 timed region.  The MFMA path (FP32 by default) and the plain FP64 path run the
 same schedule from the same initial state; the line reports the MFMA path's
 steps/s as `value`, the FP64 path's steps/s and the L2 distance between the
-two states after the run.
+two states after the run.  Four more timed regions of K steps continue the
+same trajectory afterwards (`repeats_steps_per_s`, `median_steps_per_s`): the
+Jacobi sweeps of the truncations, and with them the step time, grow as the
+state evolves.
 
 Other workloads print their own line: batch64 (64 uneven problems stepped
 together), --gradient (steps carrying parameter derivatives), fpmoms_M<M>
@@ -27,6 +30,7 @@ import argparse
 import json
 import os
 import re
+import statistics
 import sys
 import time
 
@@ -732,6 +736,10 @@ def main():
     rows = _classes(oplog)
     log(f"kernel classes: {rows}")
     log(f"dominant kernel: {roof}")
+    # four more timed regions of K steps continuing the same trajectory: the
+    # median of the five rates is reported beside value (which is the first)
+    reps = [value] + [K / (_time_steps(torch, prob, f, K) / 1e3) for _ in range(4)]
+    log(f"repeats (steps/s): {[round(r, 2) for r in reps]}")
     cpu = None if args.no_cpu_baseline else _cpu_baseline(w)
     if cpu:
         log(f"cpu baseline: {cpu}")
@@ -757,6 +765,8 @@ def main():
         "l2_err_vs_f64": l2,
         "mass_after": mass,
         "discarded_weight_last_rounding": float(sum(disc)),
+        "repeats_steps_per_s": reps,
+        "median_steps_per_s": statistics.median(reps),
         **extra,
         "per_step_accuracy": accuracy,
         "autotune": {"shapes_measured": q.autotune_info()[0], "seconds": q.autotune_info()[1],
