@@ -88,3 +88,42 @@ def test_eigh(ctx, n, keep):
         assert np.max(np.abs(P[b].T @ P[b] - np.eye(keep))) < 100 * n * 2.2e-16, b
         resid = G[b] @ P[b] - P[b] * lam[b][:keep][None, :]
         assert np.max(np.abs(resid)) < 100 * n * 2.2e-16 * l1, b
+
+
+@pytest.mark.parametrize("m,n", [(8, 5), (64, 64), (288, 144), (576, 32)])
+def test_qr_degenerate(ctx, m, n):
+    """Exactly degenerate inputs: the zero matrix (every reflector is the
+    identity: Q = [I; 0], R = 0) and a single nonzero column (R = Q^T A has
+    one nonzero column); Q stays orthonormal and Q R = A, with and without R."""
+    A = np.zeros((2, m, n))
+    A[1, :, n // 2] = np.random.default_rng(m + n).standard_normal(m)
+    Q, R = q.linalg_qr(ctx, A)
+    Qs, _ = q.linalg_qr(ctx, A, with_r=False)
+    assert np.array_equal(Q[0], np.eye(m, n)) and np.array_equal(R[0], np.zeros((n, n)))
+    for b in range(2):
+        assert np.max(np.abs(Q[b].T @ Q[b] - np.eye(n))) < 50 * n * 2.2e-16, b
+        assert np.max(np.abs(Q[b] @ R[b] - A[b])) <= 50 * n * 2.2e-16 * max(1.0, np.abs(A[b]).max()), b
+        assert np.max(np.abs(np.tril(R[b], -1))) == 0.0, b
+        assert np.max(np.abs(Qs[b] - Q[b])) < 1e-12, b
+    assert np.count_nonzero(np.abs(R[1]).max(axis=0) > 0) == 1
+
+
+@pytest.mark.parametrize("n,keep", [(16, 8), (33, 20), (144, 128)])
+def test_eigh_degenerate(ctx, n, keep):
+    """Exactly repeated eigenvalues, with the cut inside a multiplet (only the
+    eigenspace is unique there: the kept vectors must be orthonormal
+    eigenvectors, the eigenvalues exact), the matrix 2 I, and the zero
+    matrix (eigenvalues 0, orthonormal vectors)."""
+    rng = np.random.default_rng(n * 31 + keep)
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.repeat([4.0, 2.0, 1.0, 0.5], (n + 3) // 4)[:n].copy()
+    lam[keep:keep + 2] = lam[keep - 1]  # the multiplet of lam[keep-1] reaches past the cut
+    G = np.stack([(U * lam) @ U.T, 2.0 * np.eye(n), np.zeros((n, n))])
+    refs = [lam, np.full(n, 2.0), np.zeros(n)]
+    P, got = q.linalg_eigh(ctx, G, keep)
+    for b in range(3):
+        l1 = max(1.0, refs[b][0])
+        assert np.max(np.abs(got[b] - refs[b])) < 100 * n * 2.2e-16 * l1, b
+        assert np.max(np.abs(P[b].T @ P[b] - np.eye(keep))) < 100 * n * 2.2e-16, b
+        resid = G[b] @ P[b] - P[b] * got[b][:keep][None, :]
+        assert np.max(np.abs(resid)) < 100 * n * 2.2e-16 * l1, b
