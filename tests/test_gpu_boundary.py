@@ -140,3 +140,28 @@ def test_torch_allocator(ctx):
     finally:
         q.use_torch_allocator(False)
     assert torch.cuda.memory_allocated() >= before
+
+
+@pytest.mark.parametrize("N,cap,ell,chi", [(10, 24, 20, 12), (16, 160, 144, 128)])
+def test_round_zero_chain(ctx, N, cap, ell, chi):
+    """The degenerate input of a rounding: a chain of zero cores.  Every
+    sketch, Gram matrix and eigenvalue is zero; the deterministic and the
+    two-sided sketched roundings return the zero tensor with finite cores,
+    and the outcome record reports zero norm and zero discarded weight."""
+    from tests.helpers import gaussian_sketch
+    caps = [min(2 ** n, 2 ** (N - n), cap) for n in range(N + 1)]
+    zc = [np.zeros((caps[n], 2, caps[n + 1])) for n in range(N)]
+    x = q.TT.from_cores(ctx, zc)
+    out, info = q.round_det(ctx, x, chi, 1e-3, with_info=True)
+    cores = out.cores()
+    assert all(np.all(np.isfinite(c)) for c in cores)
+    assert np.abs(full(cores)).max() == 0.0
+    assert info["norm2"] == 0.0 and info["discarded_weight"] == 0.0
+    assert all(v == 0.0 for v in info["per_bond"])
+    Z, _ = gaussian_sketch(N, ell, 91)
+    Zl, _ = gaussian_sketch(N, ell, 92)
+    out2 = q.round_sketch(ctx, [1.0], [None], [x], q.TT.from_cores(ctx, Z), chi,
+                          sketch_left=q.TT.from_cores(ctx, Zl))
+    cores2 = out2.cores()
+    assert all(np.all(np.isfinite(c)) for c in cores2)
+    assert np.abs(full(cores2)).max() == 0.0
